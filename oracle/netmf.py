@@ -1,0 +1,374 @@
+"""ORACLE -- test infrastructure, not part of the product.
+
+FP64 reference of every step of the sparsified-NetMF hot path.  Each function
+names the passage of arXiv 2302.07084 it follows.  Sampling, aggregation and
+the truncated logarithm are in ``sampler.c`` (plain C, called through
+ctypes); the linear algebra uses numpy/scipy library routines as its steps
+(matrix products, LAPACK symmetric eigensolver) with no blocking or fusion.
+
+Readings of points the paper leaves open are stated where they are used; the
+full list is in the design notes of the repository.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.special
+
+from . import build as _build
+
+F_BITS = 16                 # fixed-point fraction bits of sample weights
+TAG_OMEGA = 3 << 24         # Philox counter tag of the Gaussian test matrix
+
+_LIB = None
+
+
+def lib():
+    """ctypes handle of liboracle.so (built on first use if absent)."""
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64, u64, i32, f64 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_double
+        L.ora_philox.argtypes = [u64, P, i64, P]
+        L.ora_plan.argtypes = [i32, P, u64, i64, P, P, P]
+        L.ora_sample_slots.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64,
+                                       P, P, P, P, P, P, P]
+        L.ora_sample_slots.restype = i64
+        L.ora_count_rows.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i32,
+                                     P, P, P, P, P, P]
+        L.ora_count_rows.restype = i32
+        L.ora_free.argtypes = [P]
+        L.ora_trunc_log.argtypes = [i64, i64, P, P, P, P, u64, u64, u64, P, P]
+        _LIB = L
+    return _LIB
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _graph_arrays(g):
+    return (np.ascontiguousarray(g.rowptr, dtype=np.int64),
+            np.ascontiguousarray(g.col, dtype=np.int32))
+
+
+def _s_array(params):
+    s = np.ascontiguousarray(np.asarray(params["s"], dtype=np.float64))
+    assert len(s) == params["T"]
+    return s
+
+
+def _coin_args(params):
+    C = params.get("C")
+    no_ds = 1 if (C is None or (isinstance(C, float) and math.isinf(C))) else 0
+    return (0.0 if no_ds else float(C)), no_ds
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def philox(seed: int, ctr: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 blocks for counters ``ctr`` (N x 4 uint32), key = seed."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().ora_philox(ctypes.c_uint64(seed), _p(ctr), ctr.shape[0], _p(out))
+    return out
+
+
+def plan(T: int, s, M: int, m: int):
+    """Integer constants of the sampler: floor(M/m), the Bernoulli threshold of
+    frac(M/m) and the length thresholds of Multinomial(s) (Algorithm
+    "Downsampled Per-Edge PathSampling", the n_e and r draws)."""
+    s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
+    base = np.zeros(1, np.uint64)
+    thr = np.zeros(1, np.uint64)
+    theta = np.zeros(T, np.uint64)
+    lib().ora_plan(T, _p(s), M, m, _p(base), _p(thr), _p(theta))
+    return int(base[0]), int(thr[0]), theta
+
+
+# --------------------------------------------------------------------------
+# Sparsifier (section 5.2)
+# --------------------------------------------------------------------------
+def sample_slots(g, params, e_begin: int = 0, e_end: int | None = None):
+    """Every sample slot (e, j) of edges [e_begin, e_end): accepted flag, r,
+    endpoints (u', v') and fixed-point weight (0 if rejected)."""
+    rp, col = _graph_arrays(g)
+    m = g.m
+    if e_end is None:
+        e_end = m
+    s = _s_array(params)
+    C, no_ds = _coin_args(params)
+    cap = 1 << 16
+    while True:
+        out = dict(e=np.empty(cap, np.int64), j=np.empty(cap, np.uint32),
+                   acc=np.empty(cap, np.uint8), r=np.empty(cap, np.uint8),
+                   a=np.empty(cap, np.int32), b=np.empty(cap, np.int32),
+                   w=np.empty(cap, np.uint64))
+        k = lib().ora_sample_slots(g.n, _p(rp), _p(col), params["T"], _p(s),
+                                   int(params["M"]), C, no_ds, int(params["seed"]),
+                                   e_begin, e_end, cap, _p(out["e"]), _p(out["j"]),
+                                   _p(out["acc"]), _p(out["r"]), _p(out["a"]),
+                                   _p(out["b"]), _p(out["w"]))
+        if k >= 0:
+            return {key: v[:k] for key, v in out.items()}
+        cap = -k
+
+
+def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
+              nthreads: int | None = None):
+    """Aggregated count matrix W (fixed point, 2^-16 units) restricted to rows
+    [row_lo, row_hi): returns (rowptr, col, W, attempted, accepted).  Equal
+    pairs are summed exactly in uint64 (section 5.2, sparse parallel hashing;
+    here a sort of the sample triples)."""
+    rp, col = _graph_arrays(g)
+    if row_hi is None:
+        row_hi = g.n
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    s = _s_array(params)
+    C, no_ds = _coin_args(params)
+    prp = ctypes.c_void_p()
+    pcol = ctypes.c_void_p()
+    pw = ctypes.c_void_p()
+    nnz = ctypes.c_int64()
+    att = ctypes.c_uint64()
+    acc = ctypes.c_uint64()
+    rc = lib().ora_count_rows(g.n, _p(rp), _p(col), params["T"], _p(s), int(params["M"]),
+                              C, no_ds, int(params["seed"]), row_lo, row_hi, nthreads,
+                              ctypes.byref(prp), ctypes.byref(pcol), ctypes.byref(pw),
+                              ctypes.byref(nnz), ctypes.byref(att), ctypes.byref(acc))
+    if rc == -1:
+        raise MemoryError("oracle aggregation ran out of memory")
+    if rc == -2:
+        raise OverflowError("weight sum exceeds uint64")
+    rows = row_hi - row_lo
+    k = nnz.value
+    R = np.ctypeslib.as_array(ctypes.cast(prp, ctypes.POINTER(ctypes.c_int64)), (rows + 1,)).copy()
+    Cc = (np.ctypeslib.as_array(ctypes.cast(pcol, ctypes.POINTER(ctypes.c_int32)), (k,)).copy()
+          if k else np.zeros(0, np.int32))
+    W = (np.ctypeslib.as_array(ctypes.cast(pw, ctypes.POINTER(ctypes.c_uint64)), (k,)).copy()
+         if k else np.zeros(0, np.uint64))
+    for ptr in (prp, pcol, pw):
+        lib().ora_free(ptr)
+    return R, Cc, W, att.value, acc.value
+
+
+def trunc_log(g, params, rowptr, col, W, row_lo: int = 0):
+    """Eq. (1): x = vol^2/(2bM) * (W/2^F) / (d_a d_b); keep x > 1 (exact
+    integer test), value log x.  Returns (keep mask, values)."""
+    deg = np.ascontiguousarray(g.degrees(), dtype=np.int64)
+    rows = len(rowptr) - 1
+    keep = np.zeros(len(col), np.uint8)
+    val = np.zeros(len(col), np.float64)
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    W = np.ascontiguousarray(W, dtype=np.uint64)
+    lib().ora_trunc_log(rows, row_lo, _p(deg), _p(rowptr), _p(col), _p(W),
+                        g.n_arcs, int(params["b"]), int(params["M"]), _p(keep), _p(val))
+    return keep.astype(bool), val
+
+
+def compact(rowptr, col, keep, val):
+    """Drop the entries trunc_log removed; returns (rowptr, col, val)."""
+    rows = len(rowptr) - 1
+    row_of = np.repeat(np.arange(rows), np.diff(rowptr))
+    kept_rows = row_of[keep]
+    rp = np.zeros(rows + 1, np.int64)
+    np.add.at(rp, kept_rows + 1, 1)
+    return np.cumsum(rp), col[keep], val[keep]
+
+
+def netmf_sparse(g, params, nthreads=None):
+    """The sparsified NetMF matrix (FP64 CSR) of the whole graph."""
+    R, Cc, W, _, _ = count_csr(g, params, nthreads=nthreads)
+    keep, val = trunc_log(g, params, R, Cc, W)
+    rp, c2, v2 = compact(R, Cc, keep, val)
+    return sp.csr_matrix((v2, c2, rp), shape=(g.n, g.n))
+
+
+# --------------------------------------------------------------------------
+# Randomized SVD (section 4.2)
+# --------------------------------------------------------------------------
+def gaussian_omega(n: int, k: int, seed: int) -> np.ndarray:
+    """Omega = randn(n, k) (Algorithm "Fast Randomized SVD", first step).
+    Entry (i, c) is Box-Muller on the first two words of
+    Philox(counter = (i_lo, i_hi, c // 2, TAG_OMEGA)): with u1 = (z0+.5)/2^32,
+    u2 = (z1+.5)/2^32, radius sqrt(-2 ln u1), even c takes the cosine and odd c
+    the sine of 2 pi u2."""
+    half = (k + 1) // 2
+    i = np.repeat(np.arange(n, dtype=np.uint64), half)
+    c = np.tile(np.arange(half, dtype=np.uint64), n)
+    ctr = np.stack([(i & 0xFFFFFFFF).astype(np.uint32), (i >> 32).astype(np.uint32),
+                    c.astype(np.uint32), np.full(n * half, TAG_OMEGA, np.uint32)], axis=1)
+    z = philox(seed, ctr).astype(np.float64)
+    u1 = (z[:, 0] + 0.5) * 2.0 ** -32
+    u2 = (z[:, 1] + 0.5) * 2.0 ** -32
+    rad = np.sqrt(-2.0 * np.log(u1))
+    out = np.empty((n, 2 * half))
+    out[:, 0::2] = (rad * np.cos(2.0 * np.pi * u2)).reshape(n, half)
+    out[:, 1::2] = (rad * np.sin(2.0 * np.pi * u2)).reshape(n, half)
+    return out[:, :k]
+
+
+def eigsvd(Y: np.ndarray):
+    """Algorithm "eigSVD": C = Y^T Y, [V, D] = eig(C), S = sqrt(diag D),
+    U = Y V S^-1.  Eigenpairs are sorted by decreasing eigenvalue (the paper's
+    LAPACK routine returns them ascending while the top-d columns are used).
+    Eigenvalues at or below k * eps * lambda_max are treated as zero and
+    their columns of U set to zero."""
+    C = Y.T @ Y
+    lam, V = np.linalg.eigh(C)
+    order = np.argsort(lam)[::-1]
+    lam = lam[order]
+    V = V[:, order]
+    lam = np.where(lam > Y.shape[1] * np.finfo(float).eps * max(lam[0], 0.0), lam, 0.0)
+    S = np.sqrt(lam)
+    inv = np.where(S > 0, 1.0 / np.where(S > 0, S, 1.0), 0.0)
+    U = (Y @ V) * inv
+    return U, S, V
+
+
+def orth_householder(Y: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of range(Y) by Householder QR (LAPACK)."""
+    Q, _ = np.linalg.qr(Y)
+    return Q
+
+
+def fast_rsvd(M, d: int, oversample: int, q: int, omega: np.ndarray,
+              orth: str = "eigsvd"):
+    """Algorithm "Fast Randomized SVD" for a symmetric M:
+    Y = M Omega; Q = eigSVD(Y).U; q times { Y = M Q; T = Q; [Q, S, V] =
+    eigSVD(Y) }; return Q[:, :d], S[:d], T V[:, :d].  ``orth`` replaces the
+    orthonormalisation of the power iterations ("householder") for cross
+    checks; the final eigSVD is always taken."""
+    if q < 1:
+        raise ValueError("q >= 1 required (q = 0 leaves S and V undefined)")
+    assert omega.shape[1] == d + oversample
+    Y = M @ omega
+    Q = eigsvd(Y)[0] if orth == "eigsvd" else orth_householder(Y)
+    for it in range(q):
+        Y = M @ Q
+        T = Q
+        if it < q - 1 and orth != "eigsvd":
+            Q = orth_householder(Y)
+            continue
+        Q, S, V = eigsvd(Y)
+    return Q[:, :d], S[:d], T @ V[:, :d]
+
+
+# --------------------------------------------------------------------------
+# Spectral propagation (section 4.3)
+# --------------------------------------------------------------------------
+def cheb_coeffs(theta: float, k: int) -> np.ndarray:
+    """Coefficients c_0..c_k of the band-pass filter
+    g(lambda) = exp(-theta/2 ((lambda - mu)^2 - 1)) written in Chebyshev
+    polynomials T_n(x), x = (lambda - mu)^2 / 2 - 1 (Jacobi-Anger expansion):
+    c_0 = e^{-theta/2} I_0(theta), c_n = 2 (-1)^n e^{-theta/2} I_n(theta)."""
+    n = np.arange(k + 1)
+    c = 2.0 * (-1.0) ** n * scipy.special.iv(n, theta) * math.exp(-theta / 2)
+    c[0] /= 2.0
+    return c
+
+
+def _walk_matrix(g):
+    deg = g.degrees().astype(np.float64)
+    A = sp.csr_matrix((np.ones(g.n_arcs), g.col, g.rowptr), shape=(g.n, g.n))
+    inv = np.where(deg > 0, 1.0 / np.where(deg > 0, deg, 1.0), 0.0)
+    return sp.diags(inv) @ A
+
+
+def propagate(g, X0: np.ndarray, k: int, theta: float, mu: float) -> np.ndarray:
+    """Spectral propagation on the input graph: L = I - D^-1 A, the filter
+    g_k(L) = sum_n c_n T_n(L_mu), L_mu = (L - mu I)^2 / 2 - I, applied by the
+    Chebyshev three-term recurrence; output D^-1 A (X0 - g_k(L) X0).
+    Returns X0 unchanged when k = 0 or theta < 1e-12 (propagation off)."""
+    if k == 0 or theta < 1e-12:
+        return X0.copy()
+    P = _walk_matrix(g)
+    c = cheb_coeffs(theta, k)
+
+    def B(Z):
+        return (1.0 - mu) * Z - P @ Z      # (L - mu I) Z
+
+    T0 = X0
+    T1 = 0.5 * B(B(T0)) - T0
+    conv = c[0] * T0 + c[1] * T1
+    for nn in range(2, k + 1):
+        T2 = B(B(T1)) - 2.0 * T1 - T0
+        conv = conv + c[nn] * T2
+        T0, T1 = T1, T2
+    return P @ (X0 - conv)
+
+
+def propagate_dense(g, X0: np.ndarray, k: int, theta: float, mu: float,
+                    exact: bool = False) -> np.ndarray:
+    """Closed form of ``propagate`` through the eigendecomposition of the
+    symmetric N = D^-1/2 A D^-1/2: L = D^-1/2 (I - N) D^1/2, so a polynomial
+    p(L) = D^-1/2 V p(1 - Lambda) V^T D^1/2.  ``exact`` uses the filter
+    g itself instead of its degree-k expansion.  Small graphs only."""
+    deg = g.degrees().astype(np.float64)
+    A = sp.csr_matrix((np.ones(g.n_arcs), g.col, g.rowptr), shape=(g.n, g.n)).toarray()
+    dm = np.where(deg > 0, deg ** -0.5, 0.0)
+    N = dm[:, None] * A * dm[None, :]
+    lam_n, V = np.linalg.eigh(N)
+    lam = 1.0 - lam_n
+    x = 0.5 * (lam - mu) ** 2 - 1.0
+    if exact:
+        gv = np.exp(-0.5 * theta * ((lam - mu) ** 2 - 1.0))
+    else:
+        c = cheb_coeffs(theta, k)
+        gv = np.polynomial.chebyshev.chebval(x, c)
+    Dh = np.where(deg > 0, deg ** 0.5, 0.0)
+    G = (dm[:, None] * (V * gv) @ V.T) * Dh[None, :]
+    P = np.where(deg[:, None] > 0, A / np.where(deg > 0, deg, 1.0)[:, None], 0.0)
+    return P @ (X0 - G @ X0)
+
+
+def bessel_tail_bound(theta: float, k: int) -> float:
+    """Sup-norm truncation error of the degree-k expansion on |x| <= 1:
+    e^{-theta/2} * 2 * sum_{n > k} I_n(theta)."""
+    n = np.arange(k + 1, k + 60)
+    return float(math.exp(-theta / 2) * 2.0 * np.sum(scipy.special.iv(n, theta)))
+
+
+# --------------------------------------------------------------------------
+# Whole path
+# --------------------------------------------------------------------------
+def embedding(U: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """X = U S^{1/2} (section 4.2, the embedding from the factorisation)."""
+    return U * np.sqrt(S)[None, :]
+
+
+def final_embedding(Xsp: np.ndarray) -> np.ndarray:
+    """eigSVD of the propagated matrix, scaled as X = U_p S_p^{1/2}
+    (the last stage of spectral propagation, section 6 time breakdown)."""
+    U, S, _ = eigsvd(Xsp)
+    return embedding(U, S)
+
+
+def embed(g, params, nthreads=None, return_stages=False):
+    """Sparsified NetMF embedding of graph g (FP64 throughout)."""
+    Mmat = netmf_sparse(g, params, nthreads=nthreads)
+    d, ov = params["d"], params["oversample"]
+    omega = gaussian_omega(g.n, d + ov, params["seed"])
+    U, S, V = fast_rsvd(Mmat, d, ov, params["q"], omega)
+    X0 = embedding(U, S)
+    k, theta, mu = params["cheb_k"], params["theta"], params["mu"]
+    if k == 0 or theta < 1e-12:
+        X = X0
+        Xsp = None
+    else:
+        Xsp = propagate(g, X0, k, theta, mu)
+        X = final_embedding(Xsp)
+    if return_stages:
+        return dict(M=Mmat, omega=omega, U=U, S=S, V=V, X0=X0, Xsp=Xsp, X=X)
+    return X
