@@ -1,0 +1,253 @@
+/*
+ * lne.h -- C ABI of the MI355X (gfx950) sparsified-NetMF embedding library.
+ *
+ * The library computes the network embedding of arXiv 2302.07084 (LightNE 2.0)
+ * on one GPU:
+ *   sparsifier  downsampled per-edge PathSampling (section 5.2, Algorithms
+ *               "PathSampling" and "Downsampled Per-Edge PathSampling",
+ *               degree sampling of section 4.1) aggregated into a CSR matrix
+ *   trunc_log   the entry-wise truncated logarithm of Eq. (1)
+ *   rSVD        the fast randomized SVD (section 4.2, Algorithms "eigSVD" and
+ *               "Fast Randomized SVD"), embedding X0 = U S^(1/2)
+ *   propagate   Chebyshev spectral propagation on the input graph (section
+ *               4.3) followed by a final eigSVD
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are marked "host".  Dense matrices are row-major with a leading
+ *     dimension (elements between consecutive rows) >= their width.
+ *   - All work is enqueued on the context's HIP stream.  An entry point that
+ *     must learn a data-dependent size (nnz) synchronises that stream and says
+ *     so.  Outputs are valid once the stream has been synchronised.
+ *   - The caller owns every buffer it passes in.  Buffers the library returns
+ *     (lne_csr) are allocated through the context's allocator and released
+ *     with lne_csr_free.  Scratch memory comes from the same allocator and is
+ *     released before the call returns.
+ *   - Every function returns an lne_status; nothing throws across the ABI.
+ *     Arguments are validated on the host before any GPU work is enqueued; on
+ *     an error no output is written and lne_last_error() describes it.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef LNE_H
+#define LNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lne_status;
+#define LNE_OK 0
+#define LNE_EINVAL (-1)        /* invalid argument or malformed input            */
+#define LNE_ENOMEM (-2)        /* the allocator returned NULL                    */
+#define LNE_EHIP (-3)          /* a HIP runtime call failed                      */
+#define LNE_ENUMERIC (-4)      /* breakdown of a factorisation                   */
+#define LNE_EUNSUPPORTED (-5)  /* valid request outside the supported range      */
+
+/* element types of dense matrices and of CSR values */
+#define LNE_F64 0
+#define LNE_F32 1
+#define LNE_BF16 2
+#define LNE_U64 3
+
+/* params.flags */
+#define LNE_FLAG_NO_FINAL_EIGSVD 1u  /* lne_propagate: return the filtered matrix */
+
+typedef void *(*lne_alloc_fn)(size_t bytes, void *user);
+typedef void (*lne_free_fn)(void *ptr, void *user);
+
+typedef struct lne_ctx lne_ctx;
+
+/* Undirected, unweighted, simple input graph in symmetric CSR form: row i
+ * lists the neighbours of vertex i in ascending order, no self-loops, no
+ * duplicates, and j is in row i iff i is in row j (checked only where cheap).
+ * Isolated vertices are allowed. */
+typedef struct {
+    int64_t n;                 /* vertices                                   */
+    int64_t n_arcs;            /* 2m = vol(G), must be < 2^32                */
+    const int64_t *row_ptr;    /* device, n + 1 entries, row_ptr[0] = 0      */
+    const int32_t *col;        /* device, n_arcs entries                     */
+} lne_graph;
+
+/* Hyperparameters (notation table of the paper; s_r of Eq. (1)). */
+typedef struct {
+    int32_t T;            /* window size, 1..16                                 */
+    double s[16];         /* s_1..s_T >= 0, positive sum (normalised inside)    */
+    uint64_t M;           /* number of edge samples                              */
+    uint32_t b;           /* negative samples, >= 1; 2 b M < 2^40               */
+    double C;             /* degree-sampling constant; <= 0: ln n; +inf: off    */
+    int32_t d;            /* embedding dimension                                 */
+    int32_t oversample;   /* rSVD oversampling s; d + oversample <= n, <= 288   */
+    int32_t q;            /* power iterations, >= 1                              */
+    int32_t cheb_k;       /* propagation order k; 0 switches propagation off     */
+    double theta, mu;     /* propagation filter parameters; theta < 1e-12: off   */
+    uint64_t seed;        /* Philox key                                          */
+    int32_t precision;    /* LNE_F64, LNE_F32 or LNE_BF16 (see lne_rsvd)         */
+    uint32_t flags;       /* LNE_FLAG_*                                          */
+} lne_params;
+
+/* CSR matrix owned by the library (release with lne_csr_free). */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    int64_t *row_ptr;     /* device, n_rows + 1                                  */
+    int32_t *col;         /* device, nnz, ascending inside each row              */
+    void *val;            /* device, nnz values of type val_type                 */
+    int32_t val_type;     /* LNE_U64 (count matrix), LNE_F64 or LNE_F32          */
+} lne_csr;
+
+typedef struct {
+    uint64_t attempted;   /* sample slots drawn: sum over edges of n_e           */
+    uint64_t accepted;    /* samples whose downsampling coin came up heads       */
+    uint64_t nnz_counts;  /* nnz of the symmetric count matrix                   */
+    uint64_t nnz_log;     /* nnz after the truncated logarithm                   */
+    uint32_t shifted;     /* number of shifted Cholesky fallbacks taken          */
+    uint32_t reserved;
+} lne_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context bound to `stream` (a hipStream_t; NULL = default stream).
+ * alloc/free may be NULL together, in which case hipMalloc/hipFree are used.
+ * Makes no HIP call.  Errors: EINVAL (out NULL, or only one of alloc/free). */
+lne_status lne_ctx_create(lne_ctx **out, void *stream, lne_alloc_fn alloc,
+                          lne_free_fn free_fn, void *user);
+void lne_ctx_destroy(lne_ctx *ctx);
+/* Message of the last failed call on ctx (static storage inside ctx). */
+const char *lne_last_error(const lne_ctx *ctx);
+/* Library version string. */
+const char *lne_version(void);
+
+/* Per-kernel timing with HIP events on the context stream.  While enabled,
+ * every launch is bracketed by two events; lne_prof_get synchronises and
+ * returns the summed duration and launch count of kernels named `name`. */
+lne_status lne_prof_enable(lne_ctx *ctx, int32_t on);
+lne_status lne_prof_get(lne_ctx *ctx, const char *name, double *total_ms,
+                        int64_t *launches);
+lne_status lne_prof_reset(lne_ctx *ctx);
+
+/* ---- random numbers ----------------------------------------------------- */
+
+/* Philox4x32-10 (Salmon et al., SC'11): out[4i..4i+3] = block of counter
+ * ctr[4i..4i+3] under key (seed low word, seed high word).  ctr, out: device,
+ * 4 * count uint32.  Errors: EINVAL (count < 0, NULL with count > 0). */
+lne_status lne_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr,
+                      int64_t count, uint32_t *out);
+
+/* Gaussian test matrix Omega = randn(n, k) of the fast randomized SVD (first
+ * step of Algorithm "Fast Randomized SVD").  Entry (i, c) is the Box-Muller
+ * transform of the first two words of Philox(counter = (i_lo, i_hi, c / 2,
+ * 3 << 24)): even c takes the cosine, odd c the sine.  out: device, n x k,
+ * leading dimension ld, element type dtype (values computed in double and
+ * rounded).  Errors: EINVAL. */
+lne_status lne_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld,
+                        uint64_t seed, int32_t dtype, void *out);
+
+/* ---- sparsifier ----------------------------------------------------------- */
+
+/* Sample slots per edge: floor(M/m) + (frac(M/m) > 0), m = n_arcs / 2.
+ * Host only, no GPU work.  Returns 0 on invalid input. */
+int64_t lne_slots_per_edge(const lne_params *p, int64_t n_arcs);
+
+/* Host-side constants of the sampler (for inspection): floor(M/m), the
+ * Bernoulli threshold floor(frac(M/m) 2^32) and the length thresholds
+ * theta_t = floor(2^32 cumsum(s)_t / sum(s)), theta_T = 2^32.  All host. */
+lne_status lne_sampler_plan(const lne_params *p, int64_t n_arcs, uint64_t *base,
+                            uint64_t *frac_thr, uint64_t *theta);
+
+/* Every sample slot (e, j), e in [e_begin, e_end), j < slots per edge, of
+ * Algorithm "Downsampled Per-Edge PathSampling"; edges are the arcs (u, v),
+ * u < v, in CSR order.  Slot (e, j) is written at (e - e_begin) * S + j:
+ *   r[.]  = 0 if j >= n_e (empty slot), else the drawn length r in 1..T
+ *   w[.]  = fixed-point weight rint(2^16 / p_e) if accepted, 0 otherwise
+ *   a[.], b[.] = (u', v') of PathSampling if accepted, -1 otherwise.
+ * a, b: device int32; w: device uint64; r: device uint8.
+ * Errors: EINVAL (bad graph/params/range). */
+lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            int64_t e_begin, int64_t e_end, int32_t *a, int32_t *b,
+                            uint64_t *w, uint8_t *r);
+
+/* Sparsifier construction (section 5.2): runs every sample of every edge and
+ * sums the fixed-point weights of equal pairs, each sample counted in both
+ * orientations.  out receives the symmetric count CSR (val_type LNE_U64, units
+ * of 2^-16).  Synchronises the stream (twice: to size the pair buffer and the
+ * CSR).  st may be NULL.  Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED (a
+ * per-sample weight above 2^32 - 1 or more than 2^31 vertices). */
+lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                        lne_csr *out, lne_stats *st);
+
+/* Truncated logarithm of Eq. (1) on the count matrix:
+ *   x_ab = vol^2 / (2 b M) * (W_ab / 2^16) / (d_a d_b)
+ * kept iff x_ab > 1 (decided exactly in 128-bit integers), value ln x_ab as
+ * double (precision LNE_F64) or float (otherwise).  out is compacted.
+ * Synchronises the stream once (nnz).  Errors: EINVAL, ENOMEM, EHIP. */
+lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                         const lne_csr *counts, lne_csr *out);
+
+/* Copies a library CSR into caller device buffers (row_ptr: n_rows + 1,
+ * col: nnz, val: nnz elements of val_type).  Errors: EINVAL. */
+lne_status lne_csr_copy(lne_ctx *ctx, const lne_csr *m, int64_t *row_ptr,
+                        int32_t *col, void *val);
+void lne_csr_free(lne_ctx *ctx, lne_csr *m);
+
+/* ---- linear algebra -------------------------------------------------------- */
+
+/* Y = A X for a library CSR A (values F64 or F32) and a dense X of width k.
+ * dtype is the element type of X and Y: F64 needs F64 values; F32 or BF16
+ * need F32 values (BF16 operands are accumulated in FP32).
+ * Errors: EINVAL. */
+lne_status lne_spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx,
+                    void *Y, int64_t ldy, int32_t k, int32_t dtype);
+
+/* eigSVD (Algorithm "eigSVD") of a dense Y (n x k, dtype): C = Y^T Y in FP64
+ * (BF16 inputs: FP32 accumulation), C = V D V^T by two-sided parallel-order Jacobi in
+ * FP64 on the device, S = sqrt(D) sorted descending, U = Y V S^-1 (columns with
+ * S <= k eps S_1 are zero).  U: device n x k (ldu, dtype; BF16 input gives F32
+ * U), S: device k doubles, V: device k x k doubles.  Any output may be NULL.
+ * Errors: EINVAL, ENOMEM, EUNSUPPORTED (k > 288). */
+lne_status lne_eigsvd(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t ld,
+                      int32_t dtype, void *U, int64_t ldu, double *S, double *V);
+
+/* Orthonormal basis of range(Y) by CholeskyQR2 with a shifted first pass on
+ * breakdown (Fukaya et al.), in place; the Cholesky factorisations are FP64.
+ * This replaces eigSVD as the orthonormaliser of the power iteration: both
+ * span range(Y), and the fast randomized SVD depends on the basis only
+ * through that span.  Errors: EINVAL, ENOMEM, ENUMERIC. */
+lne_status lne_orthonormalize(lne_ctx *ctx, void *Y, int64_t n, int32_t k, int64_t ld,
+                              int32_t dtype);
+
+/* Fast randomized SVD (Algorithm "Fast Randomized SVD") of the symmetric
+ * sparsifier matrix M (values F64 for precision LNE_F64, F32 otherwise):
+ * Omega (lne_gaussian, p->seed) -> Y = M Omega -> orthonormalise -> q times
+ * {Y = M Q; T = Q; eigSVD(Y) or orthonormalise} -> U = Q[:, :d],
+ * Sigma = S[:d], V = T V[:, :d], X0 = U Sigma^(1/2).
+ * Dense n x (d + oversample) matrices are F64 (LNE_F64), F32 (LNE_F32) or
+ * BF16 (LNE_BF16: the Gram products and projections run on BF16 MFMA with
+ * FP32 accumulation, the Cholesky and the final eigen-solve stay FP64).
+ * Outputs (any may be NULL): U, V, X0 device n x d (F64 for LNE_F64, else F32),
+ * sigma device d doubles.  Errors: EINVAL, ENOMEM, EHIP, ENUMERIC. */
+lne_status lne_rsvd(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U,
+                    double *sigma, void *V, void *X0);
+
+/* Spectral propagation (section 4.3) on the input graph with L = I - D^-1 A:
+ *   X_sp = D^-1 A (X0 - g_k(L) X0),  g_k = sum_{n<=k} c_n T_n((L - mu I)^2/2 - I),
+ *   c_0 = e^(-theta/2) I_0(theta), c_n = 2 (-1)^n e^(-theta/2) I_n(theta),
+ * the degree-k Chebyshev (Jacobi-Anger) expansion of the band-pass filter
+ * exp(-theta/2 ((lambda - mu)^2 - 1)); then X = U_p S_p^(1/2) from eigSVD(X_sp)
+ * unless LNE_FLAG_NO_FINAL_EIGSVD.  With k = 0 or theta < 1e-12 X = X0.
+ * X0, X: device n x d, F64 if p->precision == LNE_F64 else F32.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                         const void *X0, void *X);
+
+/* Whole path: sparsify -> trunc_log -> rSVD -> propagate.  X: device n x d
+ * (F64 for LNE_F64, else F32).  Synchronises the stream (sizes).  st may be
+ * NULL.  Errors: those of the stages. */
+lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void *X,
+                     lne_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LNE_H */

@@ -1,0 +1,412 @@
+"""Python binding of liblne.so (include/lne.h): argument marshalling only.
+
+Every step of the embedding runs in the library's HIP kernels; this module
+turns torch tensors into device pointers, forwards torch's caching allocator
+and current stream to the library, and raises on a non-zero status.  It
+never falls back to a CPU path: if the library is missing, ``load`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblne.so")
+
+F64, F32, BF16, U64 = 0, 1, 2, 3
+FLAG_NO_FINAL_EIGSVD = 1
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16}
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
+
+
+class LneError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("s", ctypes.c_double * 16), ("M", ctypes.c_uint64),
+                ("b", ctypes.c_uint32), ("C", ctypes.c_double), ("d", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("cheb_k", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class CsrStruct(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("val_type", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("attempted", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
+                ("nnz_counts", ctypes.c_uint64), ("nnz_log", ctypes.c_uint64),
+                ("shifted", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+
+
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+# (name, restype, argtypes) of every exported function
+_P, _I32, _I64, _U64, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                            ctypes.c_double)
+SIGNATURES = [
+    ("lne_ctx_create", _I32, [_P, _P, _ALLOC_T, _FREE_T, _P]),
+    ("lne_ctx_destroy", None, [_P]),
+    ("lne_last_error", ctypes.c_char_p, [_P]),
+    ("lne_version", ctypes.c_char_p, []),
+    ("lne_prof_enable", _I32, [_P, _I32]),
+    ("lne_prof_get", _I32, [_P, ctypes.c_char_p, _P, _P]),
+    ("lne_prof_reset", _I32, [_P]),
+    ("lne_philox", _I32, [_P, _U64, _P, _I64, _P]),
+    ("lne_gaussian", _I32, [_P, _I64, _I32, _I64, _U64, _I32, _P]),
+    ("lne_slots_per_edge", _I64, [_P, _I64]),
+    ("lne_sampler_plan", _I32, [_P, _I64, _P, _P, _P]),
+    ("lne_sample_slots", _I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P]),
+    ("lne_sparsify", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_trunc_log", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_csr_copy", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_csr_free", None, [_P, _P]),
+    ("lne_spmm", _I32, [_P, _P, _P, _I64, _P, _I64, _I32, _I32]),
+    ("lne_eigsvd", _I32, [_P, _P, _I64, _I32, _I64, _I32, _P, _I64, _P, _P]),
+    ("lne_orthonormalize", _I32, [_P, _P, _I64, _I32, _I64, _I32]),
+    ("lne_rsvd", _I32, [_P, _P, _P, _P, _P, _P, _P]),
+    ("lne_propagate", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_embed", _I32, [_P, _P, _P, _P, _P]),
+]
+
+_lib = None
+
+
+def _hip_runtime():
+    """Makes one HIP runtime globally visible before liblne binds to it.
+
+    torch carries its own libamdhip64; a second runtime from /opt/rocm in the
+    same process would not share torch's device state.  liblne leaves the HIP
+    symbols undefined and binds to whichever runtime is promoted here."""
+    try:
+        import torch  # noqa: F401  (loads torch's HIP runtime)
+        from .build import hip_runtime_dir
+        path = os.path.join(hip_runtime_dir(), "libamdhip64.so")
+        if not os.path.exists(path):
+            path = "/opt/rocm/lib/libamdhip64.so"
+    except ImportError:
+        path = "/opt/rocm/lib/libamdhip64.so"
+    ctypes.CDLL(path, mode=os.RTLD_GLOBAL | os.RTLD_NOW)
+
+
+def load(path: str = LIB_PATH):
+    """Loads liblne.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
+                              "`python -m paper_2302_07084_amd.build` (gfx950 hipcc)")
+        _hip_runtime()
+        L = ctypes.CDLL(path, mode=os.RTLD_NOW)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return load().lne_version().decode()
+
+
+def make_params(p: dict, **override) -> Params:
+    p = dict(p)
+    p.update(override)
+    out = Params()
+    T = int(p["T"])
+    s = np.asarray(p["s"], dtype=np.float64)
+    out.T = T
+    for i in range(T):
+        out.s[i] = float(s[i])
+    out.M = int(p["M"])
+    out.b = int(p.get("b", 1))
+    C = p.get("C")
+    out.C = math.inf if C is None else float(C)
+    out.d = int(p.get("d", 1))
+    out.oversample = int(p.get("oversample", 0))
+    out.q = int(p.get("q", 1))
+    out.cheb_k = int(p.get("cheb_k", 0))
+    out.theta = float(p.get("theta", 0.0))
+    out.mu = float(p.get("mu", 0.0))
+    out.seed = int(p.get("seed", 0))
+    prec = p.get("precision", "f64")
+    out.precision = _PREC[prec] if isinstance(prec, str) else int(prec)
+    out.flags = int(p.get("flags", 0))
+    return out
+
+
+def _torch_dtype(code):
+    import torch
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, U64: torch.int64}[code]
+
+
+def _code_of(t):
+    import torch
+    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
+
+
+class Context:
+    """A library context bound to torch's current stream and caching allocator."""
+
+    def __init__(self, device=None, use_torch_allocator: bool = True):
+        import torch
+        self.L = load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.current_stream(self.device)
+        dev_index = self.device.index
+        stream = self.stream
+
+        def _alloc(size, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(size), dev_index, stream)
+            except Exception:
+                return None
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        if use_torch_allocator:
+            self._alloc = _ALLOC_T(_alloc)
+            self._free = _FREE_T(_free)
+        else:
+            self._alloc = ctypes.cast(None, _ALLOC_T)
+            self._free = ctypes.cast(None, _FREE_T)
+        h = ctypes.c_void_p()
+        rc = self.L.lne_ctx_create(ctypes.byref(h), ctypes.c_void_p(stream.cuda_stream),
+                                   self._alloc, self._free, None)
+        if rc != 0:
+            raise LneError(rc, "lne_ctx_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lne_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc, what):
+        if rc != 0:
+            raise LneError(rc, f"{what}: {self.L.lne_last_error(self.h).decode()}")
+
+    # ---- profiling ------------------------------------------------------
+    def prof_enable(self, on=True):
+        self.check(self.L.lne_prof_enable(self.h, 1 if on else 0), "prof_enable")
+
+    def prof_get(self, name):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self.check(self.L.lne_prof_get(self.h, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+                   "prof_get")
+        return ms.value, cnt.value
+
+    def prof_reset(self):
+        self.check(self.L.lne_prof_reset(self.h), "prof_reset")
+
+
+def graph_struct(rowptr, col):
+    """lne_graph over device tensors (int64 row offsets, int32 columns)."""
+    import torch
+    assert rowptr.is_cuda and col.is_cuda
+    assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
+    assert rowptr.is_contiguous() and col.is_contiguous()
+    g = Graph()
+    g.n = rowptr.numel() - 1
+    g.n_arcs = col.numel()
+    g.row_ptr = rowptr.data_ptr()
+    g.col = col.data_ptr() if col.numel() else None
+    return g
+
+
+class Csr:
+    """A CSR matrix owned by the library (freed with the object)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        self.s = CsrStruct()
+
+    @property
+    def nnz(self):
+        return int(self.s.nnz)
+
+    def to_torch(self):
+        import torch
+        n = self.s.n_rows
+        rp = torch.empty(n + 1, dtype=torch.int64, device=self.ctx.device)
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.ctx.device)
+        val = torch.empty(max(self.nnz, 1), dtype=_torch_dtype(self.s.val_type), device=self.ctx.device)
+        self.ctx.check(self.ctx.L.lne_csr_copy(self.ctx.h, ctypes.byref(self.s), rp.data_ptr(),
+                                               col.data_ptr(), val.data_ptr()), "csr_copy")
+        return rp, col[:self.nnz], val[:self.nnz]
+
+    def free(self):
+        if self.s.row_ptr:
+            self.ctx.L.lne_csr_free(self.ctx.h, ctypes.byref(self.s))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---- entry points (same names as the C ABI, without the prefix) ----------
+def philox(ctx: Context, seed: int, ctr):
+    import torch
+    out = torch.empty_like(ctr)
+    ctx.check(ctx.L.lne_philox(ctx.h, seed, ctr.data_ptr(), ctr.numel() // 4, out.data_ptr()),
+              "philox")
+    return out
+
+
+def gaussian(ctx: Context, n: int, k: int, seed: int, dtype=None, ld=None):
+    import torch
+    dtype = dtype or torch.float64
+    ld = ld or k
+    out = torch.empty((n, ld), dtype=dtype, device=ctx.device)
+    ctx.check(ctx.L.lne_gaussian(ctx.h, n, k, ld, seed, _code_of(out), out.data_ptr()), "gaussian")
+    return out[:, :k]
+
+
+def slots_per_edge(params: dict, n_arcs: int) -> int:
+    p = make_params(params)
+    return int(load().lne_slots_per_edge(ctypes.byref(p), n_arcs))
+
+
+def sampler_plan(params: dict, n_arcs: int):
+    p = make_params(params)
+    base = ctypes.c_uint64()
+    thr = ctypes.c_uint64()
+    theta = (ctypes.c_uint64 * 16)()
+    rc = load().lne_sampler_plan(ctypes.byref(p), n_arcs, ctypes.byref(base), ctypes.byref(thr),
+                                 theta)
+    if rc != 0:
+        raise LneError(rc, "sampler_plan")
+    return int(base.value), int(thr.value), np.array(theta[:p.T], dtype=np.uint64)
+
+
+def sample_slots(ctx: Context, rowptr, col, params: dict, e_begin: int, e_end: int):
+    import torch
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    S = int(ctx.L.lne_slots_per_edge(ctypes.byref(p), g.n_arcs))
+    cnt = max((e_end - e_begin) * S, 1)
+    dev = ctx.device
+    a = torch.empty(cnt, dtype=torch.int32, device=dev)
+    b = torch.empty(cnt, dtype=torch.int32, device=dev)
+    w = torch.empty(cnt, dtype=torch.int64, device=dev)
+    r = torch.empty(cnt, dtype=torch.uint8, device=dev)
+    ctx.check(ctx.L.lne_sample_slots(ctx.h, ctypes.byref(g), ctypes.byref(p), e_begin, e_end,
+                                     a.data_ptr(), b.data_ptr(), w.data_ptr(), r.data_ptr()),
+              "sample_slots")
+    k = (e_end - e_begin) * S
+    return dict(S=S, a=a[:k], b=b[:k], w=w[:k], r=r[:k])
+
+
+def sparsify(ctx: Context, rowptr, col, params: dict):
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    out = Csr(ctx)
+    st = Stats()
+    ctx.check(ctx.L.lne_sparsify(ctx.h, ctypes.byref(g), ctypes.byref(p), ctypes.byref(out.s),
+                                 ctypes.byref(st)), "sparsify")
+    return out, st.as_dict()
+
+
+def trunc_log(ctx: Context, rowptr, col, params: dict, counts: Csr):
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    out = Csr(ctx)
+    ctx.check(ctx.L.lne_trunc_log(ctx.h, ctypes.byref(g), ctypes.byref(p), ctypes.byref(counts.s),
+                                  ctypes.byref(out.s)), "trunc_log")
+    return out
+
+
+def spmm(ctx: Context, A: Csr, X):
+    import torch
+    n, k = X.shape
+    Y = torch.empty((A.s.n_rows, k), dtype=X.dtype, device=X.device)
+    ctx.check(ctx.L.lne_spmm(ctx.h, ctypes.byref(A.s), X.data_ptr(), X.stride(0), Y.data_ptr(),
+                             Y.stride(0), k, _code_of(X)), "spmm")
+    return Y
+
+
+def eigsvd(ctx: Context, Y):
+    import torch
+    n, k = Y.shape
+    ut = torch.float32 if Y.dtype == torch.bfloat16 else Y.dtype
+    U = torch.empty((n, k), dtype=ut, device=Y.device)
+    S = torch.empty(k, dtype=torch.float64, device=Y.device)
+    V = torch.empty((k, k), dtype=torch.float64, device=Y.device)
+    ctx.check(ctx.L.lne_eigsvd(ctx.h, Y.data_ptr(), n, k, Y.stride(0), _code_of(Y), U.data_ptr(),
+                               U.stride(0), S.data_ptr(), V.data_ptr()), "eigsvd")
+    return U, S, V
+
+
+def orthonormalize(ctx: Context, Y):
+    n, k = Y.shape
+    ctx.check(ctx.L.lne_orthonormalize(ctx.h, Y.data_ptr(), n, k, Y.stride(0), _code_of(Y)),
+              "orthonormalize")
+    return Y
+
+
+def rsvd(ctx: Context, M: Csr, params: dict):
+    import torch
+    p = make_params(params)
+    n, d = M.s.n_rows, p.d
+    dt = torch.float64 if p.precision == F64 else torch.float32
+    dev = ctx.device
+    U = torch.empty((n, d), dtype=dt, device=dev)
+    V = torch.empty((n, d), dtype=dt, device=dev)
+    X0 = torch.empty((n, d), dtype=dt, device=dev)
+    S = torch.empty(d, dtype=torch.float64, device=dev)
+    ctx.check(ctx.L.lne_rsvd(ctx.h, ctypes.byref(M.s), ctypes.byref(p), U.data_ptr(), S.data_ptr(),
+                             V.data_ptr(), X0.data_ptr()), "rsvd")
+    return U, S, V, X0
+
+
+def propagate(ctx: Context, rowptr, col, params: dict, X0):
+    import torch
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    X = torch.empty_like(X0)
+    ctx.check(ctx.L.lne_propagate(ctx.h, ctypes.byref(g), ctypes.byref(p), X0.data_ptr(),
+                                  X.data_ptr()), "propagate")
+    return X
+
+
+def embed(ctx: Context, rowptr, col, params: dict, out=None):
+    import torch
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    dt = torch.float64 if p.precision == F64 else torch.float32
+    X = out if out is not None else torch.empty((g.n, p.d), dtype=dt, device=ctx.device)
+    st = Stats()
+    ctx.check(ctx.L.lne_embed(ctx.h, ctypes.byref(g), ctypes.byref(p), X.data_ptr(),
+                              ctypes.byref(st)), "embed")
+    return X, st.as_dict()

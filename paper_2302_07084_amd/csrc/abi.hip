@@ -1,0 +1,686 @@
+// C ABI of the library: argument validation, the sampler's host constants,
+// context and scratch management, and the orchestration of the stages
+// (sparsify -> trunc_log -> fast randomized SVD -> spectral propagation).
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <limits>
+
+#include "common.hpp"
+
+namespace lne {
+
+lne_status fail(lne_ctx *ctx, lne_status code, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+void *dev_alloc(lne_ctx *ctx, size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    if (ctx->alloc) return ctx->alloc(bytes, ctx->user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(lne_ctx *ctx, void *p) {
+    if (!p) return;
+    if (ctx->free_fn) ctx->free_fn(p, ctx->user);
+    else (void)hipFree(p);
+}
+
+void Buf::release() {
+    if (p && ctx) dev_free(ctx, p);
+    p = nullptr;
+    bytes = 0;
+}
+
+lne_status alloc(lne_ctx *ctx, Buf &b, size_t bytes) {
+    b.release();
+    b.ctx = ctx;
+    b.p = dev_alloc(ctx, bytes);
+    if (!b.p) return fail(ctx, LNE_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    b.bytes = bytes;
+    return LNE_OK;
+}
+
+Launch::Launch(lne_ctx *c, const char *n) : ctx(c), name(n) {
+    if (ctx->prof) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, ctx->stream);
+    }
+}
+
+Launch::~Launch() {
+    if (ctx->prof && a && b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->marks.push_back({name, a, b});
+    }
+}
+
+lne_status check_launch(lne_ctx *ctx, const char *name) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(ctx, LNE_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e));
+    return LNE_OK;
+}
+
+size_t dtype_size(int32_t t) {
+    switch (t) {
+        case LNE_F64: return 8;
+        case LNE_F32: return 4;
+        case LNE_BF16: return 2;
+        case LNE_U64: return 8;
+        default: return 0;
+    }
+}
+
+lne_status validate_graph(lne_ctx *ctx, const lne_graph *g) {
+    if (!g) return fail(ctx, LNE_EINVAL, "graph is NULL");
+    if (g->n < 1 || g->n >= (int64_t)1 << 31)
+        return fail(ctx, LNE_EINVAL, "graph: n = %lld outside [1, 2^31)", (long long)g->n);
+    if (g->n_arcs < 0 || (g->n_arcs & 1) || g->n_arcs >= (int64_t)1 << 32)
+        return fail(ctx, LNE_EINVAL, "graph: n_arcs = %lld must be even and below 2^32",
+                    (long long)g->n_arcs);
+    if (!g->row_ptr || (g->n_arcs > 0 && !g->col))
+        return fail(ctx, LNE_EINVAL, "graph: NULL row_ptr or col");
+    return LNE_OK;
+}
+
+lne_status validate_params(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
+                           bool need_linalg) {
+    if (!p) return fail(ctx, LNE_EINVAL, "params is NULL");
+    if (p->T < 1 || p->T > 16) return fail(ctx, LNE_EINVAL, "T = %d outside 1..16", p->T);
+    double tot = 0.0;
+    for (int t = 0; t < p->T; ++t) {
+        if (!(p->s[t] >= 0.0) || !std::isfinite(p->s[t]))
+            return fail(ctx, LNE_EINVAL, "s[%d] must be finite and >= 0", t);
+        tot += p->s[t];
+    }
+    if (!(tot > 0.0)) return fail(ctx, LNE_EINVAL, "s must have a positive sum");
+    if (p->b < 1) return fail(ctx, LNE_EINVAL, "b must be >= 1");
+    const unsigned __int128 bm = (unsigned __int128)2 * p->b * p->M;
+    if (bm >= ((unsigned __int128)1 << 40)) return fail(ctx, LNE_EINVAL, "2 b M must be below 2^40");
+    if (std::isnan(p->C)) return fail(ctx, LNE_EINVAL, "C is NaN");
+    if (!need_linalg) return LNE_OK;
+    if (p->d < 1 || p->oversample < 0) return fail(ctx, LNE_EINVAL, "d >= 1, oversample >= 0");
+    const int64_t kp = (int64_t)p->d + p->oversample;
+    if (kp > n) return fail(ctx, LNE_EINVAL, "d + oversample = %lld exceeds n", (long long)kp);
+    if (kp > 288) return fail(ctx, LNE_EUNSUPPORTED, "d + oversample = %lld above 288", (long long)kp);
+    if (p->q < 1) return fail(ctx, LNE_EINVAL, "q must be >= 1");
+    if (p->cheb_k < 0 || p->cheb_k > 64) return fail(ctx, LNE_EINVAL, "cheb_k outside 0..64");
+    if (!std::isfinite(p->theta) || p->theta < 0.0 || !std::isfinite(p->mu))
+        return fail(ctx, LNE_EINVAL, "theta must be finite and >= 0, mu finite");
+    if (p->precision < LNE_F64 || p->precision > LNE_BF16)
+        return fail(ctx, LNE_EINVAL, "precision must be LNE_F64, LNE_F32 or LNE_BF16");
+    (void)n_arcs;
+    return LNE_OK;
+}
+
+static void host_plan(const lne_params *p, int64_t n, int64_t n_arcs, SamplePlan &pl) {
+    std::memset(&pl, 0, sizeof(pl));
+    const int64_t m = n_arcs / 2;
+    pl.seed = p->seed;
+    pl.T = p->T;
+    if (m > 0) {
+        pl.base = p->M / (uint64_t)m;
+        const uint64_t rem = p->M % (uint64_t)m;
+        pl.frac_thr = (uint64_t)(((unsigned __int128)rem << 32) / (uint64_t)m);
+        pl.S = (int64_t)pl.base + (rem > 0 ? 1 : 0);
+    }
+    double total = 0.0;
+    for (int t = 0; t < p->T; ++t) total += p->s[t];
+    double cum = 0.0;
+    for (int t = 0; t < p->T; ++t) {
+        cum += p->s[t];
+        uint64_t th = (uint64_t)std::floor(cum / total * 4294967296.0);
+        if (th > 4294967296ull) th = 4294967296ull;
+        pl.theta[t] = th;
+    }
+    pl.theta[p->T - 1] = 4294967296ull;
+    for (int t = p->T; t < 16; ++t) pl.theta[t] = 4294967296ull;
+    if (std::isinf(p->C) && p->C > 0) {
+        pl.no_ds = 1;
+        pl.C = 0.0;
+    } else {
+        pl.no_ds = 0;
+        pl.C = p->C > 0.0 ? p->C : std::log((double)n);
+    }
+    // one thread per chunk of J slots of one edge, about 2^20 threads overall
+    const int64_t slots = m * (pl.S > 0 ? pl.S : 1);
+    int64_t J = (slots + (1 << 20) - 1) >> 20;
+    if (J < 1) J = 1;
+    if (J > pl.S) J = pl.S > 0 ? pl.S : 1;
+    pl.J = J;
+    pl.chunks = pl.S > 0 ? (pl.S + J - 1) / J : 1;
+    int cb = 1;
+    while (((int64_t)1 << cb) < n) ++cb;
+    pl.colbits = cb;
+}
+
+lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
+                     SamplePlan &pl) {
+    (void)ctx;
+    host_plan(p, n, n_arcs, pl);
+    return LNE_OK;
+}
+
+// Modified Bessel function of the first kind, integer order, by its power
+// series sum_j (x/2)^(2j+n) / (j! (j+n)!).
+static double bessel_i(int n, double x) {
+    double term = 1.0;
+    for (int i = 1; i <= n; ++i) term *= (x / 2.0) / i;
+    double sum = term;
+    for (int j = 1; j < 500; ++j) {
+        term *= (x / 2.0) * (x / 2.0) / ((double)j * (double)(j + n));
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+// ------------------------------------------------------------------- stages
+static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                                lne_csr *out, lne_stats *st) {
+    SamplePlan pl;
+    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, pl));
+    const int64_t m = g->n_arcs / 2;
+    uint64_t accepted = 0;
+    unsigned long long attempted = 0;
+    uint32_t max_w = 0;
+    Buf k0(ctx), v0(ctx), k1(ctx), v1(ctx);
+    if (m > 0 && pl.S > 0) {
+        Buf eu(ctx), ev(ctx);
+        LNE_TRY(build_edges(ctx, g, eu, ev, m));
+        const int64_t threads = sample_threads(pl, m);
+        const int64_t nw = threads / 64;
+        Buf wc(ctx), wo(ctx), scal(ctx);
+        LNE_TRY(alloc(ctx, wc, sizeof(uint32_t) * (size_t)nw));
+        LNE_TRY(alloc(ctx, wo, sizeof(uint64_t) * (size_t)(nw + 1)));
+        LNE_TRY(alloc(ctx, scal, 16));
+        LNE_HIP(ctx, hipMemsetAsync(scal.p, 0, 16, ctx->stream));
+        unsigned long long *att_d = scal.as<unsigned long long>();
+        uint32_t *maxw_d = reinterpret_cast<uint32_t *>(scal.as<char>() + 8);
+        LNE_TRY(launch_sample_count(ctx, g, pl, eu.as<int32_t>(), ev.as<int32_t>(), m,
+                                    wc.as<uint32_t>(), nw, att_d, maxw_d));
+        LNE_TRY(scan_u32(ctx, wc.as<uint32_t>(), wo.as<uint64_t>(), nw));
+        LNE_HIP(ctx, hipMemcpyAsync(&accepted, wo.as<uint64_t>() + nw, 8, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        LNE_HIP(ctx, hipMemcpyAsync(&attempted, att_d, 8, hipMemcpyDeviceToHost, ctx->stream));
+        LNE_HIP(ctx, hipMemcpyAsync(&max_w, maxw_d, 4, hipMemcpyDeviceToHost, ctx->stream));
+        LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (max_w == 0xFFFFFFFFu)
+            return fail(ctx, LNE_EUNSUPPORTED, "a per-sample weight exceeds 2^32 - 1");
+        const int64_t P = 2 * (int64_t)accepted;
+        LNE_TRY(alloc(ctx, k0, sizeof(uint64_t) * (size_t)(P > 0 ? P : 1)));
+        LNE_TRY(alloc(ctx, v0, sizeof(uint32_t) * (size_t)(P > 0 ? P : 1)));
+        if (P > 0)
+            LNE_TRY(launch_sample_emit(ctx, g, pl, eu.as<int32_t>(), ev.as<int32_t>(), m,
+                                       wo.as<uint64_t>(), k0.as<uint64_t>(), v0.as<uint32_t>()));
+    }
+    const int64_t P = 2 * (int64_t)accepted;
+    int which = 0;
+    if (P > 1) {
+        LNE_TRY(alloc(ctx, k1, sizeof(uint64_t) * (size_t)P));
+        LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)P));
+        LNE_TRY(radix_sort(ctx, k0.as<uint64_t>(), v0.as<uint32_t>(), k1.as<uint64_t>(),
+                           v1.as<uint32_t>(), P, 2 * pl.colbits, &which));
+    }
+    const uint64_t *keys = which ? k1.as<uint64_t>() : k0.as<uint64_t>();
+    const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
+    LNE_TRY(reduce_to_csr(ctx, keys, vals, P, g->n, pl.colbits, out));
+    if (st) {
+        st->attempted = attempted;
+        st->accepted = accepted;
+        st->nnz_counts = (uint64_t)out->nnz;
+    }
+    return LNE_OK;
+}
+
+struct Flags {
+    Buf b;
+    int32_t *status() const { return b.as<int32_t>(); }
+    int32_t *shifted() const { return b.as<int32_t>() + 1; }
+    int32_t *run3() const { return b.as<int32_t>() + 2; }
+};
+
+static lne_status make_flags(lne_ctx *ctx, Flags &f) {
+    f.b.ctx = ctx;
+    LNE_TRY(alloc(ctx, f.b, 16));
+    LNE_HIP(ctx, hipMemsetAsync(f.b.p, 0, 16, ctx->stream));
+    return LNE_OK;
+}
+
+static lne_status read_flags(lne_ctx *ctx, const Flags &f, lne_stats *st) {
+    int32_t h[4] = {0, 0, 0, 0};
+    LNE_HIP(ctx, hipMemcpyAsync(h, f.b.p, 16, hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (st) st->shifted += (uint32_t)h[1];
+    if (h[0]) return fail(ctx, LNE_ENUMERIC, "Cholesky breakdown even after a shift");
+    return LNE_OK;
+}
+
+// CholeskyQR2 in place; a shifted first pass triggers a third pass (flag on
+// the device, so no host round trip).
+static lne_status orth_impl(lne_ctx *ctx, void *Y, int64_t n, int32_t k, int64_t ld,
+                            int32_t dtype, const Flags &f) {
+    Buf G(ctx), W(ctx);
+    LNE_TRY(alloc(ctx, G, sizeof(double) * (size_t)k * k));
+    LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)k * k));
+    for (int pass = 0; pass < 3; ++pass) {
+        const int32_t *skip = pass == 2 ? f.run3() : nullptr;
+        int32_t *next = pass == 0 ? f.run3() : nullptr;
+        LNE_TRY(gram(ctx, Y, dtype, n, k, ld, G.as<double>(), skip));
+        LNE_TRY(chol_inv(ctx, G.as<double>(), k, W.as<double>(), f.status(), f.shifted(), n,
+                         skip, next));
+        LNE_TRY(project(ctx, Y, dtype, ld, n, k, W.as<double>(), k, Y, dtype, ld, skip));
+    }
+    return LNE_OK;
+}
+
+// C = Y^T Y, eigenpairs sorted descending into V (k x k), lam (k).
+static lne_status eig_of_gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n,
+                              int32_t k, int64_t ld, Buf &V, Buf &lam) {
+    Buf G(ctx);
+    LNE_TRY(alloc(ctx, G, sizeof(double) * (size_t)k * k));
+    LNE_TRY(alloc(ctx, V, sizeof(double) * (size_t)k * k));
+    LNE_TRY(alloc(ctx, lam, sizeof(double) * (size_t)k));
+    LNE_TRY(gram(ctx, Y, dtype, n, k, ld, G.as<double>(), nullptr));
+    return sym_eig(ctx, G.as<double>(), k, V.as<double>(), lam.as<double>());
+}
+
+static int64_t round8(int64_t x) { return (x + 7) / 8 * 8; }
+
+static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U,
+                            double *sigma, void *V, void *X0, lne_stats *st) {
+    const int64_t n = M->n_rows;
+    const int32_t kp = p->d + p->oversample, d = p->d;
+    const int32_t dt = p->precision;
+    const int32_t out_t = dt == LNE_F64 ? LNE_F64 : LNE_F32;
+    const int64_t ld = round8(kp);
+    const size_t es = dtype_size(dt);
+    Buf A(ctx), B(ctx);
+    LNE_TRY(alloc(ctx, A, es * (size_t)n * ld));
+    LNE_TRY(alloc(ctx, B, es * (size_t)n * ld));
+    Flags f;
+    LNE_TRY(make_flags(ctx, f));
+    void *Q = A.p, *Y = B.p;
+    LNE_TRY(launch_gaussian(ctx, n, kp, ld, p->seed, dt, Q));
+    LNE_TRY(spmm(ctx, M, Q, ld, Y, ld, kp, dt));
+    LNE_TRY(orth_impl(ctx, Y, n, kp, ld, dt, f));
+    std::swap(Q, Y);
+    Buf Vk(ctx), lam(ctx);
+    for (int it = 1; it <= p->q; ++it) {
+        LNE_TRY(spmm(ctx, M, Q, ld, Y, ld, kp, dt));
+        if (it < p->q) {
+            LNE_TRY(orth_impl(ctx, Y, n, kp, ld, dt, f));
+            std::swap(Q, Y);
+        } else {
+            LNE_TRY(eig_of_gram(ctx, Y, dt, n, kp, ld, Vk, lam));
+        }
+    }
+    // Q holds T (the basis of the last power step), Y holds M T.
+    Buf W(ctx), S(ctx);
+    LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)kp * d));
+    LNE_TRY(alloc(ctx, S, sizeof(double) * (size_t)d));
+    if (U) {
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, -0.5, W.as<double>(),
+                            nullptr));
+        LNE_TRY(project(ctx, Y, dt, ld, n, kp, W.as<double>(), d, U, out_t, d, nullptr));
+    }
+    if (V) {
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, 0.0, W.as<double>(),
+                            nullptr));
+        LNE_TRY(project(ctx, Q, dt, ld, n, kp, W.as<double>(), d, V, out_t, d, nullptr));
+    }
+    if (X0) {
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, -0.25,
+                            W.as<double>(), nullptr));
+        LNE_TRY(project(ctx, Y, dt, ld, n, kp, W.as<double>(), d, X0, out_t, d, nullptr));
+    }
+    LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, 0.0, nullptr,
+                        S.as<double>()));
+    if (sigma)
+        LNE_HIP(ctx, hipMemcpyAsync(sigma, S.p, sizeof(double) * d, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    return read_flags(ctx, f, st);
+}
+
+lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,
+                 int64_t ld, int32_t dt, double a, double b);
+
+static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                                 const void *X0, void *X) {
+    const int64_t n = g->n;
+    const int32_t d = p->d;
+    const int32_t dt = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    const size_t es = dtype_size(dt);
+    if (p->cheb_k == 0 || p->theta < 1e-12) {
+        LNE_HIP(ctx, hipMemcpyAsync(X, X0, es * (size_t)n * d, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+        return LNE_OK;
+    }
+    const int64_t ld = round8(d);
+    const int K = p->cheb_k;
+    const double th = p->theta, mu = p->mu;
+    std::vector<double> c(K + 1);
+    for (int i = 0; i <= K; ++i)
+        c[i] = (i == 0 ? 1.0 : 2.0 * ((i & 1) ? -1.0 : 1.0)) * std::exp(-th / 2.0) * bessel_i(i, th);
+    Buf b0(ctx), b1(ctx), b2(ctx), bz(ctx), bc(ctx);
+    for (Buf *b : {&b0, &b1, &b2, &bz, &bc}) LNE_TRY(alloc(ctx, *b, es * (size_t)n * ld));
+    void *T0 = b0.p, *T1 = b1.p, *T2 = b2.p, *Z = bz.p, *conv = bc.p;
+    LNE_TRY(dense_scale(ctx, X0, dt, d, T0, dt, ld, n, d, 1.0));
+    LNE_TRY(dense_scale(ctx, T0, dt, ld, conv, dt, ld, n, d, c[0]));
+    // T1 = (B^2 / 2 - I) T0 with B = L - mu I = (1 - mu) I - D^-1 A
+    LNE_TRY(graph_spmm(ctx, g, T0, Z, ld, d, dt, 1.0 - mu, -1.0, nullptr, 0, nullptr, 0,
+                       nullptr, 0));
+    LNE_TRY(graph_spmm(ctx, g, Z, T1, ld, d, dt, 0.5 * (1.0 - mu), -0.5, T0, -1.0, nullptr, 0,
+                       conv, c[1]));
+    for (int i = 2; i <= K; ++i) {
+        // T_i = B^2 T_{i-1} - 2 T_{i-1} - T_{i-2}
+        LNE_TRY(graph_spmm(ctx, g, T1, Z, ld, d, dt, 1.0 - mu, -1.0, nullptr, 0, nullptr, 0,
+                           nullptr, 0));
+        LNE_TRY(graph_spmm(ctx, g, Z, T2, ld, d, dt, 1.0 - mu, -1.0, T1, -2.0, T0, -1.0, conv,
+                           c[i]));
+        void *t = T0;
+        T0 = T1;
+        T1 = T2;
+        T2 = t;
+    }
+    // X_sp = D^-1 A (X0 - conv)
+    void *tmp = T2;   // holds neither of the last two terms
+    LNE_TRY(dense_scale(ctx, X0, dt, d, tmp, dt, ld, n, d, 1.0));
+    LNE_TRY(axpby(ctx, tmp, conv, conv, n, d, ld, dt, 1.0, -1.0));
+    LNE_TRY(graph_spmm(ctx, g, conv, Z, ld, d, dt, 0.0, 1.0, nullptr, 0, nullptr, 0, nullptr, 0));
+    if (p->flags & LNE_FLAG_NO_FINAL_EIGSVD)
+        return dense_scale(ctx, Z, dt, ld, X, dt, d, n, d, 1.0);
+    // X = U_p S_p^(1/2) = X_sp V S^(-1/2)
+    Buf V(ctx), lam(ctx), W(ctx);
+    LNE_TRY(eig_of_gram(ctx, Z, dt, n, d, ld, V, lam));
+    LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)d * d));
+    LNE_TRY(eig_weights(ctx, V.as<double>(), lam.as<double>(), d, d, -0.25, W.as<double>(),
+                        nullptr));
+    return project(ctx, Z, dt, ld, n, d, W.as<double>(), d, X, dt, d, nullptr);
+}
+
+}  // namespace lne
+
+using namespace lne;
+
+// ===================================================================== ABI
+extern "C" {
+
+lne_status lne_ctx_create(lne_ctx **out, void *stream, lne_alloc_fn alloc_fn,
+                          lne_free_fn free_fn, void *user) {
+    if (!out) return LNE_EINVAL;
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return LNE_EINVAL;
+    lne_ctx *c = new (std::nothrow) lne_ctx();
+    if (!c) return LNE_ENOMEM;
+    c->stream = (hipStream_t)stream;
+    c->alloc = alloc_fn;
+    c->free_fn = free_fn;
+    c->user = user;
+    *out = c;
+    return LNE_OK;
+}
+
+void lne_ctx_destroy(lne_ctx *ctx) {
+    if (!ctx) return;
+    for (auto &m : ctx->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    delete ctx;
+}
+
+const char *lne_last_error(const lne_ctx *ctx) { return ctx ? ctx->err : "NULL context"; }
+
+const char *lne_version(void) { return "lne 0.1 (gfx950)"; }
+
+lne_status lne_prof_enable(lne_ctx *ctx, int32_t on) {
+    if (!ctx) return LNE_EINVAL;
+    ctx->prof = on != 0;
+    return LNE_OK;
+}
+
+static lne_status prof_collect(lne_ctx *ctx) {
+    if (ctx->marks.empty()) return LNE_OK;
+    LNE_HIP(ctx, hipEventSynchronize(ctx->marks.back().b));
+    for (auto &m : ctx->marks) {
+        float ms = 0.f;
+        LNE_HIP(ctx, hipEventElapsedTime(&ms, m.a, m.b));
+        auto &acc = ctx->prof_acc[m.name];
+        acc.first += ms;
+        acc.second += 1;
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    ctx->marks.clear();
+    return LNE_OK;
+}
+
+lne_status lne_prof_get(lne_ctx *ctx, const char *name, double *total_ms, int64_t *launches) {
+    if (!ctx || !name) return LNE_EINVAL;
+    LNE_TRY(prof_collect(ctx));
+    auto it = ctx->prof_acc.find(name);
+    if (total_ms) *total_ms = it == ctx->prof_acc.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == ctx->prof_acc.end() ? 0 : it->second.second;
+    return LNE_OK;
+}
+
+lne_status lne_prof_reset(lne_ctx *ctx) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(prof_collect(ctx));
+    ctx->prof_acc.clear();
+    return LNE_OK;
+}
+
+lne_status lne_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr, int64_t count,
+                      uint32_t *out) {
+    if (!ctx) return LNE_EINVAL;
+    if (count < 0 || (count > 0 && (!ctr || !out)))
+        return fail(ctx, LNE_EINVAL, "philox: bad arguments");
+    return launch_philox(ctx, seed, ctr, count, out);
+}
+
+lne_status lne_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld, uint64_t seed,
+                        int32_t dtype, void *out) {
+    if (!ctx) return LNE_EINVAL;
+    if (n < 0 || k < 0 || ld < k || (n * k > 0 && !out) || dtype < LNE_F64 || dtype > LNE_BF16)
+        return fail(ctx, LNE_EINVAL, "gaussian: bad arguments");
+    return launch_gaussian(ctx, n, k, ld, seed, dtype, out);
+}
+
+int64_t lne_slots_per_edge(const lne_params *p, int64_t n_arcs) {
+    if (!p || n_arcs < 2) return 0;
+    const uint64_t m = (uint64_t)(n_arcs / 2);
+    return (int64_t)(p->M / m + (p->M % m ? 1 : 0));
+}
+
+lne_status lne_sampler_plan(const lne_params *p, int64_t n_arcs, uint64_t *base,
+                            uint64_t *frac_thr, uint64_t *theta) {
+    if (!p || p->T < 1 || p->T > 16 || n_arcs < 2 || !base || !frac_thr || !theta)
+        return LNE_EINVAL;
+    SamplePlan pl;
+    {
+        lne_ctx tmp;
+        LNE_TRY(validate_params(&tmp, p, 1, n_arcs, false));
+        make_plan(&tmp, p, 2, n_arcs, pl);
+    }
+    *base = pl.base;
+    *frac_thr = pl.frac_thr;
+    for (int t = 0; t < p->T; ++t) theta[t] = pl.theta[t];
+    return LNE_OK;
+}
+
+lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            int64_t e_begin, int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
+                            uint8_t *r) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    const int64_t m = g->n_arcs / 2;
+    if (e_begin < 0 || e_end < e_begin || e_end > m)
+        return fail(ctx, LNE_EINVAL, "sample_slots: edge range [%lld, %lld) outside [0, %lld)",
+                    (long long)e_begin, (long long)e_end, (long long)m);
+    if (e_end > e_begin && (!a || !b || !w || !r))
+        return fail(ctx, LNE_EINVAL, "sample_slots: NULL output");
+    if (e_end == e_begin) return LNE_OK;
+    LNE_TRY(validate_graph_device(ctx, g));
+    SamplePlan pl;
+    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, pl));
+    Buf eu(ctx), ev(ctx);
+    LNE_TRY(build_edges(ctx, g, eu, ev, m));
+    return launch_sample_slots(ctx, g, pl, eu.as<int32_t>(), ev.as<int32_t>(), e_begin, e_end,
+                               a, b, w, r);
+}
+
+lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
+                        lne_stats *st) {
+    if (!ctx) return LNE_EINVAL;
+    if (!out) return fail(ctx, LNE_EINVAL, "sparsify: out is NULL");
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    std::memset(out, 0, sizeof(*out));
+    LNE_TRY(validate_graph_device(ctx, g));
+    return sparsify_impl(ctx, g, p, out, st);
+}
+
+lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                         const lne_csr *counts, lne_csr *out) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    if (!counts || !out || counts->val_type != LNE_U64 || counts->n_rows != g->n)
+        return fail(ctx, LNE_EINVAL, "trunc_log: counts must be the U64 count matrix of g");
+    if (p->precision < LNE_F64 || p->precision > LNE_BF16)
+        return fail(ctx, LNE_EINVAL, "trunc_log: bad precision");
+    std::memset(out, 0, sizeof(*out));
+    return trunc_log_csr(ctx, g, p, counts, p->precision == LNE_F64 ? LNE_F64 : LNE_F32, out);
+}
+
+lne_status lne_csr_copy(lne_ctx *ctx, const lne_csr *m, int64_t *row_ptr, int32_t *col,
+                        void *val) {
+    if (!ctx) return LNE_EINVAL;
+    if (!m || !row_ptr || (m->nnz > 0 && (!col || !val)))
+        return fail(ctx, LNE_EINVAL, "csr_copy: NULL argument");
+    LNE_HIP(ctx, hipMemcpyAsync(row_ptr, m->row_ptr, sizeof(int64_t) * (size_t)(m->n_rows + 1),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    if (m->nnz > 0) {
+        LNE_HIP(ctx, hipMemcpyAsync(col, m->col, sizeof(int32_t) * (size_t)m->nnz,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        LNE_HIP(ctx, hipMemcpyAsync(val, m->val, dtype_size(m->val_type) * (size_t)m->nnz,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return LNE_OK;
+}
+
+void lne_csr_free(lne_ctx *ctx, lne_csr *m) {
+    if (!ctx || !m) return;
+    dev_free(ctx, m->row_ptr);
+    dev_free(ctx, m->col);
+    dev_free(ctx, m->val);
+    std::memset(m, 0, sizeof(*m));
+}
+
+lne_status lne_spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void *Y,
+                    int64_t ldy, int32_t k, int32_t dtype) {
+    if (!ctx) return LNE_EINVAL;
+    if (!A || k < 1 || ldx < k || ldy < k || !X || !Y)
+        return fail(ctx, LNE_EINVAL, "spmm: bad arguments");
+    return spmm(ctx, A, X, ldx, Y, ldy, k, dtype);
+}
+
+lne_status lne_eigsvd(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t ld,
+                      int32_t dtype, void *U, int64_t ldu, double *S, double *V) {
+    if (!ctx) return LNE_EINVAL;
+    if (!Y || n < 1 || k < 1 || ld < k || (U && ldu < k) || dtype < LNE_F64 || dtype > LNE_BF16)
+        return fail(ctx, LNE_EINVAL, "eigsvd: bad arguments");
+    if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "eigsvd: k above 288");
+    Buf Vk(ctx), lam(ctx), W(ctx);
+    LNE_TRY(eig_of_gram(ctx, Y, dtype, n, k, ld, Vk, lam));
+    LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)k * k));
+    if (U) {
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), k, k, -0.5, W.as<double>(),
+                            nullptr));
+        const int32_t ut = dtype == LNE_BF16 ? LNE_F32 : dtype;
+        LNE_TRY(project(ctx, Y, dtype, ld, n, k, W.as<double>(), k, U, ut, ldu, nullptr));
+    }
+    if (S) LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), k, k, 0.0, nullptr, S));
+    if (V)
+        LNE_HIP(ctx, hipMemcpyAsync(V, Vk.p, sizeof(double) * (size_t)k * k,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    return LNE_OK;
+}
+
+lne_status lne_orthonormalize(lne_ctx *ctx, void *Y, int64_t n, int32_t k, int64_t ld,
+                              int32_t dtype) {
+    if (!ctx) return LNE_EINVAL;
+    if (!Y || n < 1 || k < 1 || k > n || ld < k || dtype < LNE_F64 || dtype > LNE_BF16)
+        return fail(ctx, LNE_EINVAL, "orthonormalize: bad arguments");
+    if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "orthonormalize: k above 288");
+    Flags f;
+    LNE_TRY(make_flags(ctx, f));
+    LNE_TRY(orth_impl(ctx, Y, n, k, ld, dtype, f));
+    return read_flags(ctx, f, nullptr);
+}
+
+lne_status lne_rsvd(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U,
+                    double *sigma, void *V, void *X0) {
+    if (!ctx) return LNE_EINVAL;
+    if (!M || M->n_rows != M->n_cols || M->n_rows < 1)
+        return fail(ctx, LNE_EINVAL, "rsvd: M must be square");
+    LNE_TRY(validate_params(ctx, p, M->n_rows, 0, true));
+    const int32_t need = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    if (M->val_type != need)
+        return fail(ctx, LNE_EINVAL, "rsvd: values must be %s for this precision",
+                    need == LNE_F64 ? "F64" : "F32");
+    return rsvd_impl(ctx, M, p, U, sigma, V, X0, nullptr);
+}
+
+lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p, const void *X0,
+                         void *X) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
+    if (!X0 || !X) return fail(ctx, LNE_EINVAL, "propagate: NULL matrix");
+    LNE_TRY(validate_graph_device(ctx, g));
+    return propagate_impl(ctx, g, p, X0, X);
+}
+
+lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void *X,
+                     lne_stats *st) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
+    if (!X) return fail(ctx, LNE_EINVAL, "embed: X is NULL");
+    if (st) std::memset(st, 0, sizeof(*st));
+    lne_csr counts, M;
+    std::memset(&counts, 0, sizeof(counts));
+    std::memset(&M, 0, sizeof(M));
+    LNE_TRY(validate_graph_device(ctx, g));
+    lne_status s = sparsify_impl(ctx, g, p, &counts, st);
+    if (s == LNE_OK)
+        s = trunc_log_csr(ctx, g, p, &counts, p->precision == LNE_F64 ? LNE_F64 : LNE_F32, &M);
+    lne_csr_free(ctx, &counts);
+    if (s != LNE_OK) {
+        lne_csr_free(ctx, &M);
+        return s;
+    }
+    if (st) st->nnz_log = (uint64_t)M.nnz;
+    const int32_t out_t = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    Buf X0(ctx);
+    s = alloc(ctx, X0, dtype_size(out_t) * (size_t)g->n * p->d);
+    if (s == LNE_OK) s = rsvd_impl(ctx, &M, p, nullptr, nullptr, nullptr, X0.p, st);
+    lne_csr_free(ctx, &M);
+    if (s != LNE_OK) return s;
+    return propagate_impl(ctx, g, p, X0.p, X);
+}
+
+}  // extern "C"

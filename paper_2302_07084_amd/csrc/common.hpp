@@ -1,0 +1,183 @@
+// Internal declarations shared by the library's translation units: the
+// context, scratch buffers, launch bookkeeping, error propagation and the
+// host-side entry points of every kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lne.h"
+
+struct lne_ctx {
+    hipStream_t stream = nullptr;
+    lne_alloc_fn alloc = nullptr;
+    lne_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    char err[512] = {0};
+    bool prof = false;
+    struct Mark { std::string name; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    std::map<std::string, std::pair<double, int64_t>> prof_acc;
+};
+
+namespace lne {
+
+lne_status fail(lne_ctx *ctx, lne_status code, const char *fmt, ...);
+
+#define LNE_TRY(expr)                         \
+    do {                                      \
+        lne_status _s = (expr);               \
+        if (_s != LNE_OK) return _s;          \
+    } while (0)
+
+#define LNE_HIP(ctx, expr)                                                            \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess)                                                         \
+            return ::lne::fail((ctx), LNE_EHIP, "%s failed: %s (%s:%d)", #expr,       \
+                               hipGetErrorString(_e), __FILE__, __LINE__);            \
+    } while (0)
+
+// Device scratch from the context allocator, released at scope exit.
+struct Buf {
+    lne_ctx *ctx = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    explicit Buf(lne_ctx *c) : ctx(c) {}
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+    Buf(Buf &&o) noexcept : ctx(o.ctx), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+    ~Buf() { release(); }
+    void release();
+    void *detach() { void *q = p; p = nullptr; return q; }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+lne_status alloc(lne_ctx *ctx, Buf &b, size_t bytes);
+void dev_free(lne_ctx *ctx, void *p);
+void *dev_alloc(lne_ctx *ctx, size_t bytes);
+
+// Launch bookkeeping: when profiling is on, brackets the launch with events.
+struct Launch {
+    lne_ctx *ctx;
+    const char *name;
+    hipEvent_t a = nullptr, b = nullptr;
+    Launch(lne_ctx *c, const char *n);
+    ~Launch();
+};
+lne_status check_launch(lne_ctx *ctx, const char *name);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline unsigned grid_of(int64_t work, int block) {
+    int64_t g = ceil_div(work, block);
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---- scan (k_scan.hip) ---------------------------------------------------
+// Exclusive prefix sum of n values (uint32 or uint64 input) into uint64
+// out[0..n]; out[n] holds the total.  Synchronous only with respect to the
+// stream.
+lne_status scan_u32(lne_ctx *ctx, const uint32_t *in, uint64_t *out, int64_t n);
+lne_status scan_u64(lne_ctx *ctx, const uint64_t *in, uint64_t *out, int64_t n);
+
+// ---- sampler (k_sample.hip) -----------------------------------------------
+struct SamplePlan {
+    uint64_t seed;
+    uint64_t base;        // floor(M/m)
+    uint64_t frac_thr;    // Bernoulli threshold of frac(M/m)
+    uint64_t theta[16];   // length thresholds
+    int32_t T;
+    int32_t no_ds;        // downsampling off
+    double C;
+    int64_t S;            // slots per edge
+    int64_t J;            // slots per thread chunk
+    int64_t chunks;       // chunks per edge
+    int32_t colbits;      // bits of a column id in the packed key
+};
+
+lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
+                     SamplePlan &pl);
+
+// Device-side structural check of the input CSR; synchronises the stream.
+lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g);
+// Edge list (u < v arcs in CSR order): eu, ev of m entries.
+lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m);
+lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+                               const int32_t *eu, const int32_t *ev, int64_t e_begin,
+                               int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
+                               uint8_t *r);
+// Per-wave accepted counts (count pass) and pair emission (scatter pass).
+lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+                               const int32_t *eu, const int32_t *ev, int64_t m,
+                               uint32_t *wave_cnt, int64_t n_waves,
+                               unsigned long long *attempted, uint32_t *max_w);
+lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+                              const int32_t *eu, const int32_t *ev, int64_t m,
+                              const uint64_t *wave_off, uint64_t *keys, uint32_t *vals);
+int64_t sample_threads(const SamplePlan &pl, int64_t m);
+lne_status launch_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr, int64_t count,
+                         uint32_t *out);
+lne_status launch_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld, uint64_t seed,
+                           int32_t dtype, void *out);
+
+// ---- aggregation (k_sort.hip) ----------------------------------------------
+// Sorts (key, val) by the low `bits` bits of key (stable LSD radix), ping-pong
+// between the two buffer pairs; returns in *which (0 or 1) the sorted copy.
+lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1,
+                      uint32_t *v1, int64_t n, int bits, int *which);
+// Sorted (key, val) -> count CSR (rows, cols from the packed key).
+lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
+                         int64_t n_items, int64_t n_rows, int colbits, lne_csr *out);
+
+// ---- trunc_log (k_trunclog.hip) ---------------------------------------------
+lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                         const lne_csr *counts, int32_t val_type, lne_csr *out);
+
+// ---- SpMM (k_spmm.hip) -------------------------------------------------------
+lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void *Y,
+                int64_t ldy, int32_t k, int32_t dtype);
+// out = a Z + b D^-1 A Z + c1 E1 + c2 E2 ; if acc: acc += cacc * out
+// (graph adjacency without values; E1/E2/acc may be null).
+lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out,
+                      int64_t ld, int32_t k, int32_t dtype, double a, double b,
+                      const void *E1, double c1, const void *E2, double c2, void *acc,
+                      double cacc);
+// Dense elementwise: y = alpha x (conversion between dtypes allowed).
+lne_status dense_scale(lne_ctx *ctx, const void *x, int32_t xt, int64_t ldx, void *y,
+                       int32_t yt, int64_t ldy, int64_t n, int32_t k, double alpha);
+
+// ---- dense (k_dense.hip) -------------------------------------------------------
+// G (k x k, FP64, leading dimension k) = Y^T Y.
+lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k,
+                int64_t ld, double *G, const int32_t *skip);
+// out (n x kout, out_t) = Y (n x kin, y_t) W (kin x kout, FP64 device, ld kout).
+lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_t n,
+                   int32_t kin, const double *W, int32_t kout, void *out, int32_t out_t,
+                   int64_t ldo, const int32_t *skip);
+// Upper Cholesky G = R^T R in place (R in upper triangle, lower zeroed) and
+// W = R^-1; on breakdown retries with a shift and sets *shifted.  mode 0:
+// plain; mode 1: the shift is always allowed.  status: 0 ok, 1 failed.
+lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *status,
+                    int32_t *shifted, int64_t n_rows, const int32_t *skip,
+                    int32_t *skip_next);
+// Symmetric eigen-decomposition of C (k x k, FP64): V (k x k, columns = vectors),
+// lam (k), sorted by decreasing eigenvalue.  C is overwritten.
+lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam);
+// W (k x kout) = V[:, :kout] diag(f(lam)) with f = lam^pow (0 for
+// lam <= k eps lam_max); S (kout) = sqrt(lam) (optional).
+lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t k,
+                       int32_t kout, double power, double *W, double *S);
+
+// ---- pipeline (pipeline.cpp) ---------------------------------------------------
+lne_status validate_graph(lne_ctx *ctx, const lne_graph *g);
+lne_status validate_params(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
+                           bool need_linalg);
+size_t dtype_size(int32_t t);
+
+}  // namespace lne

@@ -1,0 +1,604 @@
+// Dense steps of the fast randomized SVD (section 4.2): tall-skinny Gram
+// products C = Y^T Y and projections Y W on MFMA, and the small FP64 solves
+// (Cholesky with inverse, symmetric eigen-decomposition) of eigSVD and
+// CholeskyQR2, each in one workgroup so the whole chain stays on the device.
+//
+// MFMA use (gfx950, 64-lane waves, 16 x 16 output tiles):
+//   FP64 / FP32 data: v_mfma_f64_16x16x4f64 (FP32 inputs widened to FP64)
+//   BF16 data:        v_mfma_f32_16x16x32_bf16 with FP32 accumulation
+// Operand lane layout of a 16 x 16 x K step: lane l supplies A[l % 16][k-block
+// l / 16] and B[k-block l / 16][l % 16].  Accumulator value i of lane l is
+// column l % 16 of the output tile, row 4 (l / 16) + i for the FP32/BF16
+// forms but row l / 16 + 4 i for the FP64 form (checked by a lane probe).
+#include "common.hpp"
+
+namespace lne {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <class T> __device__ __forceinline__ double to_d(T x) { return (double)x; }
+template <> __device__ __forceinline__ double to_d<__bf16>(__bf16 x) { return (double)(float)x; }
+
+__device__ __forceinline__ void upper_tile(int t, int nt, int &I, int &J) {
+    I = 0;
+    while (t >= nt - I) { t -= nt - I; ++I; }
+    J = I + t;
+}
+
+// ---------------------------------------------------------------- Gram FP64
+constexpr int kGramRows = 32;
+constexpr int kGramThreads = 512;
+
+template <class YT, int MAXT>
+__global__ void __launch_bounds__(kGramThreads)
+k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t rows_per_wg,
+         double *__restrict__ part, const int32_t *__restrict__ skip) {
+    if (skip && *skip == 0) return;
+    __shared__ double tile[kGramRows * 288];       // kGramRows x KP
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
+    int TI[MAXT], TJ[MAXT];
+    v4d acc[MAXT];
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+        acc[s] = (v4d){0, 0, 0, 0};
+        const int t = w + 8 * s;
+        if (t < ntu) upper_tile(t, nt, TI[s], TJ[s]); else { TI[s] = TJ[s] = -1; }
+    }
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r_end = min(n, r_begin + rows_per_wg);
+    const int kr = lane >> 4, kc = lane & 15;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows) {
+        for (int idx = tid; idx < kGramRows * KP; idx += kGramThreads) {
+            const int rr = idx / KP, c = idx - rr * KP;
+            const int64_t row = r0 + rr;
+            tile[idx] = (row < r_end && c < k) ? to_d(Y[row * ld + c]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGramRows; kk += 4) {
+            const double *trow = tile + (kk + kr) * KP + kc;
+#pragma unroll
+            for (int s = 0; s < MAXT; ++s) {
+                if (TI[s] >= 0) {
+                    const double a = trow[16 * TI[s]];
+                    const double b = trow[16 * TJ[s]];
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double *P = part + (int64_t)blockIdx.x * KP * KP;
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+        if (TI[s] < 0) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            P[(int64_t)(16 * TI[s] + kr + 4 * i) * KP + 16 * TJ[s] + kc] = acc[s][i];
+    }
+}
+
+// ---------------------------------------------------------------- Gram BF16
+constexpr int kTS = 40;   // LDS row stride (bf16) of the transposed tile: 80 B
+
+template <int MAXT>
+__global__ void __launch_bounds__(kGramThreads)
+k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
+            int64_t rows_per_wg, double *__restrict__ part, const int32_t *__restrict__ skip) {
+    if (skip && *skip == 0) return;
+    __shared__ __attribute__((aligned(16))) __bf16 tt[288 * kTS];   // KP x kTS, transposed
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
+    int TI[MAXT], TJ[MAXT];
+    v4f acc[MAXT];
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+        acc[s] = (v4f){0, 0, 0, 0};
+        const int t = w + 8 * s;
+        if (t < ntu) upper_tile(t, nt, TI[s], TJ[s]); else { TI[s] = TJ[s] = -1; }
+    }
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r_end = min(n, r_begin + rows_per_wg);
+    const int kr = lane >> 4, kc = lane & 15;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 32) {
+        for (int idx = tid; idx < 32 * KP; idx += kGramThreads) {
+            const int rr = idx / KP, c = idx - rr * KP;
+            const int64_t row = r0 + rr;
+            tt[c * kTS + rr] = (row < r_end && c < k) ? Y[row * ld + c] : (__bf16)0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < MAXT; ++s) {
+            if (TI[s] >= 0) {
+                const v8bf a = *reinterpret_cast<const v8bf *>(tt + (16 * TI[s] + kc) * kTS + 8 * kr);
+                const v8bf b = *reinterpret_cast<const v8bf *>(tt + (16 * TJ[s] + kc) * kTS + 8 * kr);
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double *P = part + (int64_t)blockIdx.x * KP * KP;
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+        if (TI[s] < 0) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            P[(int64_t)(16 * TI[s] + 4 * kr + i) * KP + 16 * TJ[s] + kc] = (double)acc[s][i];
+    }
+}
+
+__global__ void k_gram_reduce(const double *__restrict__ part, int nwg, int KP, int k,
+                              double *__restrict__ G, const int32_t *__restrict__ skip) {
+    if (skip && *skip == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)k * k) return;
+    const int i = (int)(t / k), j = (int)(t % k);
+    const int a = min(i, j), b = max(i, j);
+    double s = 0.0;
+    for (int w = 0; w < nwg; ++w) s += part[((int64_t)w * KP + a) * KP + b];
+    G[(int64_t)i * k + j] = s;
+}
+
+// ---------------------------------------------------------------- projection
+constexpr int kProjRows = 128;
+constexpr int kProjThreads = 512;
+constexpr int kKC = 16;           // K chunk (FP64 path)
+constexpr int kAS = kKC + 1;      // padded LDS row stride (doubles)
+
+template <class YT, class OT, int MAXJ>
+__global__ void __launch_bounds__(kProjThreads)
+k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
+         const double *__restrict__ W, int kout, OT *__restrict__ out, int64_t ldo,
+         const int32_t *__restrict__ skip) {
+    if (skip && *skip == 0) return;
+    __shared__ double As[kProjRows * kAS];
+    __shared__ double Ws[kKC * 16 * MAXJ];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int KPo = 16 * MAXJ;
+    const int ntout = (kout + 15) / 16;
+    const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
+    const int kr = lane >> 4, kc = lane & 15;
+    v4d acc[MAXJ];
+#pragma unroll
+    for (int J = 0; J < MAXJ; ++J) acc[J] = (v4d){0, 0, 0, 0};
+    for (int k0 = 0; k0 < kin; k0 += kKC) {
+        for (int idx = tid; idx < kProjRows * kKC; idx += kProjThreads) {
+            const int rr = idx / kKC, cc = idx - rr * kKC;
+            const int64_t row = r0 + rr;
+            const int kcol = k0 + cc;
+            As[rr * kAS + cc] = (row < n && kcol < kin) ? to_d(Y[row * ldy + kcol]) : 0.0;
+        }
+        for (int idx = tid; idx < kKC * KPo; idx += kProjThreads) {
+            const int rr = idx / KPo, c = idx - rr * KPo;
+            const int krow = k0 + rr;
+            Ws[idx] = (krow < kin && c < kout) ? W[(int64_t)krow * kout + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kKC; kk += 4) {
+            const double a = As[(16 * w + kc) * kAS + kk + kr];
+#pragma unroll
+            for (int J = 0; J < MAXJ; ++J) {
+                if (J < ntout) {
+                    const double b = Ws[(kk + kr) * KPo + 16 * J + kc];
+                    acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[J], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int J = 0; J < MAXJ; ++J) {
+        if (J >= ntout) continue;
+        const int c = 16 * J + kc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + 16 * w + kr + 4 * i;
+            if (row < n && c < kout) out[row * ldo + c] = (OT)acc[J][i];
+        }
+    }
+}
+
+template <class OT, int MAXJ>
+__global__ void __launch_bounds__(kProjThreads)
+k_proj_bf16(const __bf16 *__restrict__ Y, int64_t ldy, int64_t n, int kin,
+            const __bf16 *__restrict__ Wt, int ldw, int kout, OT *__restrict__ out,
+            int64_t ldo, const int32_t *__restrict__ skip) {
+    if (skip && *skip == 0) return;
+    __shared__ __attribute__((aligned(16))) __bf16 As[kProjRows * kTS];
+    __shared__ __attribute__((aligned(16))) __bf16 Ws[16 * MAXJ * kTS];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ntout = (kout + 15) / 16;
+    const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
+    const int kr = lane >> 4, kc = lane & 15;
+    v4f acc[MAXJ];
+#pragma unroll
+    for (int J = 0; J < MAXJ; ++J) acc[J] = (v4f){0, 0, 0, 0};
+    for (int k0 = 0; k0 < kin; k0 += 32) {
+        for (int idx = tid; idx < kProjRows * 32; idx += kProjThreads) {
+            const int rr = idx >> 5, cc = idx & 31;
+            const int64_t row = r0 + rr;
+            const int kcol = k0 + cc;
+            As[rr * kTS + cc] = (row < n && kcol < kin) ? Y[row * ldy + kcol] : (__bf16)0.0f;
+        }
+        for (int idx = tid; idx < 16 * MAXJ * 32; idx += kProjThreads) {
+            const int c = idx >> 5, cc = idx & 31;
+            const int kcol = k0 + cc;
+            Ws[c * kTS + cc] = (c < kout && kcol < kin) ? Wt[(int64_t)c * ldw + kcol] : (__bf16)0.0f;
+        }
+        __syncthreads();
+        const v8bf a = *reinterpret_cast<const v8bf *>(As + (16 * w + kc) * kTS + 8 * kr);
+#pragma unroll
+        for (int J = 0; J < MAXJ; ++J) {
+            if (J < ntout) {
+                const v8bf b = *reinterpret_cast<const v8bf *>(Ws + (16 * J + kc) * kTS + 8 * kr);
+                acc[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[J], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int J = 0; J < MAXJ; ++J) {
+        if (J >= ntout) continue;
+        const int c = 16 * J + kc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + 16 * w + 4 * kr + i;
+            if (row < n && c < kout) out[row * ldo + c] = (OT)acc[J][i];
+        }
+    }
+}
+
+__global__ void k_w_to_bf16t(const double *__restrict__ W, int kin, int kout,
+                             __bf16 *__restrict__ Wt, int ldw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)kin * kout) return;
+    const int i = (int)(t / kout), c = (int)(t % kout);
+    Wt[(int64_t)c * ldw + i] = (__bf16)(float)W[t];
+}
+
+// ---------------------------------------------------------------- Cholesky
+constexpr int kSolveThreads = 1024;
+
+// Right-looking upper Cholesky of A (k x k, in place).  Returns false on a
+// pivot that is not positive relative to the original diagonal.
+__device__ bool chol_upper(double *A, int k, const double *diag0) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        const double piv = A[(int64_t)j * k + j];
+        const bool ok = piv > 1e-14 * diag0[j] && piv > 0.0 && isfinite(piv);
+        if (!ok) {
+            if (threadIdx.x == 0) bad = 1;
+            __syncthreads();
+            return false;
+        }
+        const double r = sqrt(piv);
+        __syncthreads();
+        for (int c = j + 1 + threadIdx.x; c < k; c += kSolveThreads) A[(int64_t)j * k + c] /= r;
+        if (threadIdx.x == 0) A[(int64_t)j * k + j] = r;
+        __syncthreads();
+        const int m = k - j - 1;
+        for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += kSolveThreads) {
+            const int i = j + 1 + (int)(idx / m), c = j + 1 + (int)(idx % m);
+            if (c >= i) A[(int64_t)i * k + c] -= A[(int64_t)j * k + i] * A[(int64_t)j * k + c];
+        }
+        __syncthreads();
+    }
+    return bad == 0;
+}
+
+__global__ void __launch_bounds__(kSolveThreads)
+k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__restrict__ diag0,
+           int32_t *__restrict__ status, int32_t *__restrict__ shifted, int64_t n_rows,
+           const int32_t *__restrict__ skip, int32_t *__restrict__ run_next) {
+    if (skip && *skip == 0) {
+        if (run_next && threadIdx.x == 0) *run_next = 0;
+        return;
+    }
+    const int64_t kk = (int64_t)k * k;
+    __shared__ double trace;
+    for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads) W[i] = G[i];
+    for (int i = threadIdx.x; i < k; i += kSolveThreads) diag0[i] = G[(int64_t)i * k + i];
+    __syncthreads();
+    bool ok = chol_upper(G, k, diag0);
+    bool sh = false;
+    if (!ok) {
+        // shifted retry: G + sigma I, sigma = 11 (n k + k (k + 1)) u trace(G)
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < k; ++i) t += diag0[i];
+            trace = t;
+        }
+        __syncthreads();
+        const double sigma = 11.0 * ((double)n_rows * k + (double)k * (k + 1)) *
+                             1.1102230246251565e-16 * trace;
+        for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads)
+            G[i] = W[i] + ((i / k == i % k) ? sigma : 0.0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < k; i += kSolveThreads) diag0[i] = 0.0;
+        __syncthreads();
+        ok = chol_upper(G, k, diag0);
+        sh = true;
+    }
+    if (threadIdx.x == 0) {
+        if (!ok) *status = 1;
+        if (sh) atomicAdd(shifted, 1);
+        if (run_next) *run_next = sh ? 1 : 0;
+    }
+    // lower triangle of R is zero; W = R^-1 (upper), one thread per column
+    for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads)
+        if (i / k > i % k) G[i] = 0.0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += kSolveThreads) {
+        for (int i = c + 1; i < k; ++i) W[(int64_t)i * k + c] = 0.0;
+        W[(int64_t)c * k + c] = ok ? 1.0 / G[(int64_t)c * k + c] : 0.0;
+        for (int i = c - 1; i >= 0; --i) {
+            double s = 0.0;
+            for (int j = i + 1; j <= c; ++j) s += G[(int64_t)i * k + j] * W[(int64_t)j * k + c];
+            W[(int64_t)i * k + c] = ok ? -s / G[(int64_t)i * k + i] : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Jacobi eig
+// Two-sided cyclic Jacobi with the round-robin (circle) ordering: every round
+// rotates kk/2 disjoint pairs at once, so a sweep is kk - 1 rounds.
+__global__ void __launch_bounds__(kSolveThreads)
+k_sym_eig(double *__restrict__ A, int k, double *__restrict__ Vw, double *__restrict__ V,
+          double *__restrict__ lam) {
+    __shared__ double cs[160], sn[160];
+    __shared__ int pp[160], qq[160];
+    __shared__ double red[kSolveThreads / 64][2];
+    __shared__ int done;
+    const int tid = threadIdx.x;
+    const int kk = k + (k & 1);
+    const int half = kk / 2, m = kk - 1;
+    const int64_t k2 = (int64_t)k * k;
+    for (int64_t i = tid; i < k2; i += kSolveThreads) Vw[i] = (i / k == i % k) ? 1.0 : 0.0;
+    if (tid == 0) done = 0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        for (int r = 0; r < m; ++r) {
+            if (tid < half) {
+                int p, q;
+                if (tid == 0) { p = m; q = r; }
+                else { p = (r + tid) % m; q = (r - tid + m) % m; }
+                if (p > q) { const int x = p; p = q; q = x; }
+                double c = 1.0, s = 0.0;
+                if (q < k) {
+                    const double apq = A[(int64_t)p * k + q];
+                    if (apq != 0.0) {
+                        const double app = A[(int64_t)p * k + p], aqq = A[(int64_t)q * k + q];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int64_t idx = tid; idx < (int64_t)half * k; idx += kSolveThreads) {
+                const int pr = (int)(idx / k), j = (int)(idx % k);
+                const int p = pp[pr], q = qq[pr];
+                if (q >= k || sn[pr] == 0.0) continue;
+                const double c = cs[pr], s = sn[pr];
+                const double ap = A[(int64_t)p * k + j], aq = A[(int64_t)q * k + j];
+                A[(int64_t)p * k + j] = c * ap - s * aq;
+                A[(int64_t)q * k + j] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int64_t idx = tid; idx < (int64_t)half * k; idx += kSolveThreads) {
+                const int pr = (int)(idx / k), i = (int)(idx % k);
+                const int p = pp[pr], q = qq[pr];
+                if (q >= k || sn[pr] == 0.0) continue;
+                const double c = cs[pr], s = sn[pr];
+                const double ap = A[(int64_t)i * k + p], aq = A[(int64_t)i * k + q];
+                A[(int64_t)i * k + p] = c * ap - s * aq;
+                A[(int64_t)i * k + q] = s * ap + c * aq;
+                const double vp = Vw[(int64_t)i * k + p], vq = Vw[(int64_t)i * k + q];
+                Vw[(int64_t)i * k + p] = c * vp - s * vq;
+                Vw[(int64_t)i * k + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+        // convergence: off-diagonal mass relative to the diagonal
+        double off = 0.0, dia = 0.0;
+        for (int64_t i = tid; i < k2; i += kSolveThreads) {
+            const double x = A[i];
+            if (i / k == i % k) dia += x * x; else off += x * x;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o, 64);
+            dia += __shfl_xor(dia, o, 64);
+        }
+        if ((tid & 63) == 0) { red[tid >> 6][0] = off; red[tid >> 6][1] = dia; }
+        __syncthreads();
+        if (tid == 0) {
+            double o = 0.0, d = 0.0;
+            for (int i = 0; i < kSolveThreads / 64; ++i) { o += red[i][0]; d += red[i][1]; }
+            done = (o <= 1e-30 * d) ? 1 : 0;
+        }
+        __syncthreads();
+        if (done) break;
+    }
+    // sort by decreasing eigenvalue (rank by counting, ties by index)
+    for (int i = tid; i < k; i += kSolveThreads) {
+        const double li = A[(int64_t)i * k + i];
+        int rank = 0;
+        for (int j = 0; j < k; ++j) {
+            const double lj = A[(int64_t)j * k + j];
+            rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
+        }
+        lam[rank] = li;
+        for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vw[(int64_t)row * k + i];
+    }
+}
+
+__global__ void k_eig_weights(const double *__restrict__ V, const double *__restrict__ lam,
+                              int k, int kout, double power, double *__restrict__ W,
+                              double *__restrict__ S) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double lmax = lam[0] > 0.0 ? lam[0] : 0.0;
+    const double floor_ = (double)k * 2.220446049250313e-16 * lmax;
+    if (S && t < kout) {
+        const double l = lam[t];
+        S[t] = l > floor_ ? sqrt(l) : 0.0;
+    }
+    if (W && t < (int64_t)k * kout) {
+        const int i = (int)(t / kout), c = (int)(t % kout);
+        const double l = lam[c];
+        W[t] = l > floor_ ? V[(int64_t)i * k + c] * pow(l, power) : 0.0;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k, int64_t ld,
+                double *G, const int32_t *skip) {
+    const int KP = ((k + 15) / 16) * 16;
+    const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
+    const int per_wave = (ntu + 7) / 8;
+    if (per_wave > 22) return fail(ctx, LNE_EUNSUPPORTED, "gram: k = %d above 288", k);
+    const int64_t blocks_rows = ceil_div(n > 0 ? n : 1, kGramRows);
+    const int nwg = (int)std::min<int64_t>(blocks_rows, KP > 160 ? 256 : 512);
+    const int64_t rows_per_wg = ceil_div(blocks_rows, nwg) * kGramRows;
+    Buf part(ctx);
+    LNE_TRY(alloc(ctx, part, sizeof(double) * (size_t)nwg * KP * KP));
+    {
+        Launch L(ctx, "gram");
+        if (dtype == LNE_BF16) {
+#define LNE_GB(MT)                                                                       \
+    k_gram_bf16<MT><<<nwg, kGramThreads, 0, ctx->stream>>>(                            \
+        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip)
+            if (per_wave <= 1) LNE_GB(1);
+            else if (per_wave <= 6) LNE_GB(6);
+            else if (per_wave <= 12) LNE_GB(12);
+            else LNE_GB(22);
+#undef LNE_GB
+        } else {
+#define LNE_G64(T, MT)                                                                   \
+    k_gram64<T, MT><<<nwg, kGramThreads, 0, ctx->stream>>>(                            \
+        (const T *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip)
+            if (dtype == LNE_F64) {
+                if (per_wave <= 1) LNE_G64(double, 1);
+                else if (per_wave <= 6) LNE_G64(double, 6);
+                else if (per_wave <= 12) LNE_G64(double, 12);
+                else LNE_G64(double, 22);
+            } else {
+                if (per_wave <= 1) LNE_G64(float, 1);
+                else if (per_wave <= 6) LNE_G64(float, 6);
+                else if (per_wave <= 12) LNE_G64(float, 12);
+                else LNE_G64(float, 22);
+            }
+#undef LNE_G64
+        }
+    }
+    LNE_TRY(check_launch(ctx, "gram"));
+    {
+        Launch L(ctx, "gram_reduce");
+        k_gram_reduce<<<grid_of((int64_t)k * k, 256), 256, 0, ctx->stream>>>(
+            part.as<double>(), nwg, KP, k, G, skip);
+    }
+    return check_launch(ctx, "gram_reduce");
+}
+
+lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_t n,
+                   int32_t kin, const double *W, int32_t kout, void *out, int32_t out_t,
+                   int64_t ldo, const int32_t *skip) {
+    if (kout > 288 || kin > 288) return fail(ctx, LNE_EUNSUPPORTED, "project: width above 288");
+    const unsigned grid = grid_of(n > 0 ? n : 1, kProjRows);
+    const int ntout = (kout + 15) / 16;
+    if (y_t == LNE_BF16) {
+        const int ldw = ((kin + 31) / 32) * 32;
+        Buf wt(ctx);
+        LNE_TRY(alloc(ctx, wt, sizeof(__bf16) * (size_t)kout * ldw));
+        {
+            Launch L(ctx, "w_to_bf16");
+            k_w_to_bf16t<<<grid_of((int64_t)kin * kout, 256), 256, 0, ctx->stream>>>(
+                W, kin, kout, wt.as<__bf16>(), ldw);
+        }
+        LNE_TRY(check_launch(ctx, "w_to_bf16"));
+        Launch L(ctx, "project");
+#define LNE_PB(OT, MJ)                                                                     \
+    k_proj_bf16<OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                           \
+        (const __bf16 *)Y, ldy, n, kin, wt.as<__bf16>(), ldw, kout, (OT *)out, ldo, skip)
+        if (out_t == LNE_BF16) {
+            if (ntout <= 3) LNE_PB(__bf16, 3);
+            else if (ntout <= 9) LNE_PB(__bf16, 9);
+            else LNE_PB(__bf16, 18);
+        } else if (out_t == LNE_F32) {
+            if (ntout <= 3) LNE_PB(float, 3);
+            else if (ntout <= 9) LNE_PB(float, 9);
+            else LNE_PB(float, 18);
+        } else {
+            return fail(ctx, LNE_EINVAL, "project: bf16 input needs bf16/f32 output");
+        }
+#undef LNE_PB
+    } else {
+        Launch L(ctx, "project");
+#define LNE_P64(YT, OT, MJ)                                                                \
+    k_proj64<YT, OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                          \
+        (const YT *)Y, ldy, n, kin, W, kout, (OT *)out, ldo, skip)
+#define LNE_P64J(YT, OT)                                                                   \
+    do {                                                                                   \
+        if (ntout <= 3) LNE_P64(YT, OT, 3);                                                \
+        else if (ntout <= 9) LNE_P64(YT, OT, 9);                                           \
+        else LNE_P64(YT, OT, 18);                                                          \
+    } while (0)
+        if (y_t == LNE_F64 && out_t == LNE_F64) LNE_P64J(double, double);
+        else if (y_t == LNE_F32 && out_t == LNE_F32) LNE_P64J(float, float);
+        else if (y_t == LNE_F32 && out_t == LNE_F64) LNE_P64J(float, double);
+        else if (y_t == LNE_F64 && out_t == LNE_F32) LNE_P64J(double, float);
+        else return fail(ctx, LNE_EINVAL, "project: unsupported types");
+#undef LNE_P64J
+#undef LNE_P64
+    }
+    return check_launch(ctx, "project");
+}
+
+lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *status,
+                    int32_t *shifted, int64_t n_rows, const int32_t *skip, int32_t *skip_next) {
+    Buf diag(ctx);
+    LNE_TRY(alloc(ctx, diag, sizeof(double) * (size_t)k));
+    {
+        Launch L(ctx, "chol_inv");
+        k_chol_inv<<<1, kSolveThreads, 0, ctx->stream>>>(G, k, W, diag.as<double>(), status,
+                                                         shifted, n_rows, skip, skip_next);
+    }
+    return check_launch(ctx, "chol_inv");
+}
+
+lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam) {
+    if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above 288", k);
+    Buf vw(ctx);
+    LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)k * k));
+    {
+        Launch L(ctx, "sym_eig");
+        k_sym_eig<<<1, kSolveThreads, 0, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
+    }
+    return check_launch(ctx, "sym_eig");
+}
+
+lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t k,
+                       int32_t kout, double power, double *W, double *S) {
+    {
+        Launch L(ctx, "eig_weights");
+        k_eig_weights<<<grid_of((int64_t)k * kout, 256), 256, 0, ctx->stream>>>(
+            V, lam, k, kout, power, W, S);
+    }
+    return check_launch(ctx, "eig_weights");
+}
+
+}  // namespace lne

@@ -1,0 +1,421 @@
+// Sparsifier sampling on gfx950: the edge list, the per-edge downsampled
+// PathSampling walkers, the Philox and Gaussian generators.
+//
+// Method (section 5.2 and its two sampling algorithms; degree sampling of
+// section 4.1): every undirected edge e = (u, v), u < v, draws
+// n_e = floor(M/m) + Bernoulli(frac(M/m)) sample slots; slot j flips a coin of
+// probability p_e = min(1, C (1/d_u + 1/d_v)), draws a length r from
+// Multinomial(s), a split uniform in {0..r-1}, walks u for split steps and v
+// for r-1-split steps, and adds the pair with weight 1/p_e.
+//
+// GPU design.  One thread owns a chunk of J consecutive slots of one edge, so
+// the edge's endpoints, degrees and coin threshold are loaded once per chunk
+// and every random decision is an integer compare on a Philox word of a
+// counter that names (edge, slot, block): results do not depend on the launch
+// shape.  Pairs are emitted in two passes over the same streams: a count pass
+// that only flips the coins (one Philox block per slot, no memory traffic
+// besides the edge list) and an emit pass that walks and writes each wave's
+// accepted pairs contiguously at an offset from the scanned per-wave counts,
+// so the pair array is compact and in a fixed order without global atomics.
+// Compiled with -ffp-contract=off: the coin thresholds and fixed-point
+// weights are IEEE double operations taken one at a time.
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace lne {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Coin {
+    bool all;        // p_e >= 1 (or downsampling off): every slot accepted
+    uint64_t tau;    // accept iff word < tau
+    uint64_t w;      // fixed-point weight rint(2^16 / p_e)
+};
+
+__device__ __forceinline__ Coin edge_coin(const SamplePlan &pl, int64_t du, int64_t dv) {
+    Coin c;
+    if (pl.no_ds) { c.all = true; c.tau = 0; c.w = 65536ull; return c; }
+    const double p = pl.C * (1.0 / (double)du + 1.0 / (double)dv);
+    if (p >= 1.0) { c.all = true; c.tau = 0; c.w = 65536ull; return c; }
+    c.all = false;
+    c.tau = (uint64_t)floor(p * 4294967296.0);
+    c.w = (uint64_t)rint(65536.0 / p);
+    return c;
+}
+
+__device__ __forceinline__ uint64_t draw_ne(const SamplePlan &pl, int64_t e) {
+    const uint4 o = philox4x32_10(
+        make_uint4((uint32_t)e, (uint32_t)((uint64_t)e >> 32), 0xFFFFFFFFu, kTagEdgeCount),
+        (uint32_t)pl.seed, (uint32_t)(pl.seed >> 32));
+    return pl.base + ((uint64_t)o.x < pl.frac_thr ? 1u : 0u);
+}
+
+__device__ __forceinline__ uint4 slot_block(const SamplePlan &pl, int64_t e, uint32_t j,
+                                            uint32_t blk) {
+    return philox4x32_10(
+        make_uint4((uint32_t)e, (uint32_t)((uint64_t)e >> 32), j, kTagWalk | blk),
+        (uint32_t)pl.seed, (uint32_t)(pl.seed >> 32));
+}
+
+// r = min{t : z < theta_t}; theta is nondecreasing so this is one plus the
+// number of thresholds at or below z.
+__device__ __forceinline__ int draw_r(const SamplePlan &pl, uint32_t z) {
+    int r = 1;
+#pragma unroll
+    for (int t = 0; t < 15; ++t)
+        r += (t < pl.T - 1 && (uint64_t)z >= pl.theta[t]) ? 1 : 0;
+    return r;
+}
+
+__device__ __forceinline__ int32_t walk_step(const int64_t *__restrict__ rp,
+                                             const int32_t *__restrict__ col, int32_t x,
+                                             uint32_t z) {
+    const int64_t beg = rp[x];
+    const uint32_t deg = (uint32_t)(rp[x + 1] - beg);
+    return deg ? col[beg + (int64_t)(z % deg)] : x;   // a sink (asymmetric input) holds
+}
+
+// Walks of an accepted slot whose first Philox block is `blk0`.
+__device__ __forceinline__ void walk_pair(const SamplePlan &pl, const int64_t *__restrict__ rp,
+                                          const int32_t *__restrict__ col, int64_t e,
+                                          uint32_t j, uint4 blk0, int32_t u, int32_t v,
+                                          int32_t &a, int32_t &b) {
+    const int r = draw_r(pl, blk0.y);
+    const int split = (int)(blk0.z % (uint32_t)r);
+    uint4 buf = make_uint4(blk0.w, 0, 0, 0);
+    int left = 1;
+    uint32_t blk = 0;
+    int32_t x = u, y = v;
+    // words after the first three: split steps from u, then r-1-split from v
+    for (int i = 0; i < r - 1; ++i) {
+        if (left == 0) {
+            buf = slot_block(pl, e, j, ++blk);
+            left = 4;
+        }
+        const uint32_t z = buf.x;
+        buf = make_uint4(buf.y, buf.z, buf.w, 0);
+        --left;
+        if (i < split) x = walk_step(rp, col, x, z);
+        else y = walk_step(rp, col, y, z);
+    }
+    a = x;
+    b = y;
+}
+
+// Structural check of the input CSR (bit 1: offsets, 2: column range,
+// 4: self-loop, 8: unsorted or duplicate column).
+__global__ void k_validate(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           int64_t n, int64_t n_arcs, uint32_t *__restrict__ flags) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    uint32_t f = 0;
+    if (u == 0 && rp[0] != 0) f |= 1;
+    if (u == n - 1 && rp[n] != n_arcs) f |= 1;
+    const int64_t b = rp[u], e = rp[u + 1];
+    if (b < 0 || e < b || e > n_arcs) {
+        atomicOr(flags, f | 1u);
+        return;
+    }
+    for (int64_t k = b; k < e; ++k) {
+        const int32_t c = col[k];
+        if (c < 0 || (int64_t)c >= n) f |= 2;
+        if ((int64_t)c == u) f |= 4;
+        if (k > b && c <= col[k - 1]) f |= 8;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_row_up(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                         int64_t n, uint32_t *__restrict__ nup, int64_t *__restrict__ first) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int64_t lo = rp[u], hi = rp[u + 1];
+    const int64_t end = hi;
+    while (lo < hi) {                    // first arc with col > u
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] > (int32_t)u) hi = mid; else lo = mid + 1;
+    }
+    first[u] = lo;
+    nup[u] = (uint32_t)(end - lo);
+}
+
+__global__ void k_fill_edges(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             int64_t n, const int64_t *__restrict__ first,
+                             const uint64_t *__restrict__ eoff, int32_t *__restrict__ eu,
+                             int32_t *__restrict__ ev) {
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (u >= n) return;
+    const int64_t f = first[u], end = rp[u + 1];
+    const int64_t base = (int64_t)eoff[u];
+    for (int64_t k = f + lane; k < end; k += 64) {
+        eu[base + (k - f)] = (int32_t)u;
+        ev[base + (k - f)] = col[k];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ eu,
+               const int32_t *__restrict__ ev, int64_t m, uint32_t *__restrict__ wave_cnt,
+               unsigned long long *__restrict__ attempted, uint32_t *__restrict__ max_w) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t e = t / pl.chunks;
+    const int64_t c = t - e * pl.chunks;
+    uint32_t cnt = 0;
+    uint64_t att = 0;
+    uint64_t wmax = 0;
+    if (e < m) {
+        const int32_t u = eu[e], v = ev[e];
+        const Coin cn = edge_coin(pl, rp[u + 1] - rp[u], rp[v + 1] - rp[v]);
+        const uint64_t ne = draw_ne(pl, e);
+        const uint64_t j0 = (uint64_t)c * pl.J;
+        const uint64_t j1 = min(j0 + (uint64_t)pl.J, ne);
+        for (uint64_t j = j0; j < j1; ++j) {
+            const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
+            cnt += (cn.all || (uint64_t)b0.x < cn.tau) ? 1u : 0u;
+        }
+        att = j1 > j0 ? j1 - j0 : 0;
+        wmax = cnt ? cn.w : 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off, 64);
+        att += __shfl_xor(att, off, 64);
+        const uint64_t o = __shfl_xor(wmax, off, 64);
+        wmax = o > wmax ? o : wmax;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wave_cnt[t >> 6] = cnt;
+        if (att) atomicAdd(attempted, (unsigned long long)att);
+        if (wmax) atomicMax(max_w, wmax > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wmax);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+              const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
+              const uint64_t *__restrict__ wave_off, uint64_t *__restrict__ keys,
+              uint32_t *__restrict__ vals) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t e = t / pl.chunks;
+    const int64_t c = t - e * pl.chunks;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t pos = wave_off[t >> 6];
+    int32_t u = 0, v = 0;
+    Coin cn{true, 0, 0};
+    uint64_t ne = 0;
+    const uint64_t j0 = (uint64_t)c * pl.J;
+    if (e < m) {
+        u = eu[e];
+        v = ev[e];
+        cn = edge_coin(pl, rp[u + 1] - rp[u], rp[v + 1] - rp[v]);
+        ne = draw_ne(pl, e);
+    }
+    const uint32_t w = (uint32_t)cn.w;
+    for (int64_t jj = 0; jj < pl.J; ++jj) {
+        const uint64_t j = j0 + (uint64_t)jj;
+        bool acc = false;
+        int32_t a = u, b = v;
+        if (e < m && j < ne) {
+            const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
+            acc = cn.all || (uint64_t)b0.x < cn.tau;
+            if (acc) walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+        }
+        const uint64_t mask = __ballot(acc);
+        if (acc) {
+            const uint64_t idx = pos + (uint64_t)__popcll(mask & lt);
+            keys[2 * idx] = ((uint64_t)(uint32_t)a << pl.colbits) | (uint32_t)b;
+            keys[2 * idx + 1] = ((uint64_t)(uint32_t)b << pl.colbits) | (uint32_t)a;
+            vals[2 * idx] = w;
+            vals[2 * idx + 1] = w;
+        }
+        pos += (uint64_t)__popcll(mask);
+    }
+}
+
+__global__ void k_sample_slots(SamplePlan pl, const int64_t *__restrict__ rp,
+                               const int32_t *__restrict__ col, const int32_t *__restrict__ eu,
+                               const int32_t *__restrict__ ev, int64_t e_begin, int64_t count,
+                               int32_t *__restrict__ oa, int32_t *__restrict__ ob,
+                               uint64_t *__restrict__ ow, uint8_t *__restrict__ orr) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const int64_t e = e_begin + s / pl.S;
+    const uint64_t j = (uint64_t)(s % pl.S);
+    const int32_t u = eu[e], v = ev[e];
+    int32_t a = -1, b = -1;
+    uint64_t w = 0;
+    uint8_t r = 0;
+    if (j < draw_ne(pl, e)) {
+        const Coin cn = edge_coin(pl, rp[u + 1] - rp[u], rp[v + 1] - rp[v]);
+        const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
+        if (cn.all || (uint64_t)b0.x < cn.tau) {
+            a = u;
+            b = v;
+            walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+            r = (uint8_t)draw_r(pl, b0.y);
+            w = cn.w;
+        }
+    }
+    oa[s] = a;
+    ob[s] = b;
+    ow[s] = w;
+    orr[s] = r;
+}
+
+__global__ void k_philox(uint64_t seed, const uint4 *__restrict__ ctr, int64_t count,
+                         uint4 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[i] = philox4x32_10(ctr[i], (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+template <class T> __device__ __forceinline__ T from_double(double x);
+template <> __device__ __forceinline__ double from_double<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_double<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ __bf16 from_double<__bf16>(double x) {
+    return (__bf16)(float)x;
+}
+
+template <class T>
+__global__ void k_gaussian(int64_t n, int32_t k, int64_t ld, uint64_t seed, T *__restrict__ out) {
+    const int32_t half = (k + 1) >> 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * half) return;
+    const int64_t i = t / half;
+    const uint32_t h = (uint32_t)(t - i * half);
+    const uint4 z = philox4x32_10(
+        make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), h, kTagOmega),
+        (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = ((double)z.x + 0.5) * 2.3283064365386963e-10;   // 2^-32
+    const double u2 = ((double)z.y + 0.5) * 2.3283064365386963e-10;
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 2.0 * 3.141592653589793 * u2;
+    const int64_t c = 2 * (int64_t)h;
+    out[i * ld + c] = from_double<T>(rad * cos(ang));
+    if (c + 1 < k) out[i * ld + c + 1] = from_double<T>(rad * sin(ang));
+}
+
+}  // namespace
+
+int64_t sample_threads(const SamplePlan &pl, int64_t m) {
+    return ceil_div(m * pl.chunks, kBlock) * kBlock;
+}
+
+lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g) {
+    Buf fl(ctx);
+    LNE_TRY(alloc(ctx, fl, sizeof(uint32_t)));
+    LNE_HIP(ctx, hipMemsetAsync(fl.p, 0, sizeof(uint32_t), ctx->stream));
+    {
+        Launch L(ctx, "validate_graph");
+        k_validate<<<grid_of(g->n, 256), 256, 0, ctx->stream>>>(g->row_ptr, g->col, g->n,
+                                                                g->n_arcs, fl.as<uint32_t>());
+    }
+    LNE_TRY(check_launch(ctx, "validate_graph"));
+    uint32_t f = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(&f, fl.p, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (f)
+        return fail(ctx, LNE_EINVAL,
+                    "graph CSR is malformed (%s%s%s%s)", (f & 1) ? "offsets " : "",
+                    (f & 2) ? "column-range " : "", (f & 4) ? "self-loop " : "",
+                    (f & 8) ? "unsorted-or-duplicate" : "");
+    return LNE_OK;
+}
+
+lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m) {
+    Buf nup(ctx), first(ctx), eoff(ctx);
+    LNE_TRY(alloc(ctx, nup, sizeof(uint32_t) * (size_t)(g->n + 1)));
+    LNE_TRY(alloc(ctx, first, sizeof(int64_t) * (size_t)(g->n + 1)));
+    LNE_TRY(alloc(ctx, eoff, sizeof(uint64_t) * (size_t)(g->n + 1)));
+    LNE_TRY(alloc(ctx, eu, sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+    LNE_TRY(alloc(ctx, ev, sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+    {
+        Launch L(ctx, "row_up");
+        k_row_up<<<grid_of(g->n, 256), 256, 0, ctx->stream>>>(g->row_ptr, g->col, g->n,
+                                                              nup.as<uint32_t>(),
+                                                              first.as<int64_t>());
+    }
+    LNE_TRY(check_launch(ctx, "row_up"));
+    LNE_TRY(scan_u32(ctx, nup.as<uint32_t>(), eoff.as<uint64_t>(), g->n));
+    {
+        Launch L(ctx, "fill_edges");
+        k_fill_edges<<<grid_of(g->n * 64, 256), 256, 0, ctx->stream>>>(
+            g->row_ptr, g->col, g->n, first.as<int64_t>(), eoff.as<uint64_t>(),
+            eu.as<int32_t>(), ev.as<int32_t>());
+    }
+    return check_launch(ctx, "fill_edges");
+}
+
+lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+                               const int32_t *eu, const int32_t *ev, int64_t e_begin,
+                               int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
+                               uint8_t *r) {
+    const int64_t count = (e_end - e_begin) * pl.S;
+    if (count <= 0) return LNE_OK;
+    {
+        Launch L(ctx, "sample_slots");
+        k_sample_slots<<<grid_of(count, 256), 256, 0, ctx->stream>>>(
+            pl, g->row_ptr, g->col, eu, ev, e_begin, count, a, b, w, r);
+    }
+    return check_launch(ctx, "sample_slots");
+}
+
+lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+                               const int32_t *eu, const int32_t *ev, int64_t m,
+                               uint32_t *wave_cnt, int64_t n_waves,
+                               unsigned long long *attempted, uint32_t *max_w) {
+    const int64_t threads = sample_threads(pl, m);
+    if (threads / 64 != n_waves) return fail(ctx, LNE_EINVAL, "sampler wave count mismatch");
+    {
+        Launch L(ctx, "sample_count");
+        k_sample_count<<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
+            pl, g->row_ptr, eu, ev, m, wave_cnt, attempted, max_w);
+    }
+    return check_launch(ctx, "sample_count");
+}
+
+lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+                              const int32_t *eu, const int32_t *ev, int64_t m,
+                              const uint64_t *wave_off, uint64_t *keys, uint32_t *vals) {
+    const int64_t threads = sample_threads(pl, m);
+    {
+        Launch L(ctx, "sample_emit");
+        k_sample_emit<<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
+            pl, g->row_ptr, g->col, eu, ev, m, wave_off, keys, vals);
+    }
+    return check_launch(ctx, "sample_emit");
+}
+
+lne_status launch_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr, int64_t count,
+                         uint32_t *out) {
+    if (count <= 0) return LNE_OK;
+    {
+        Launch L(ctx, "philox");
+        k_philox<<<grid_of(count, 256), 256, 0, ctx->stream>>>(
+            seed, reinterpret_cast<const uint4 *>(ctr), count, reinterpret_cast<uint4 *>(out));
+    }
+    return check_launch(ctx, "philox");
+}
+
+lne_status launch_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld, uint64_t seed,
+                           int32_t dtype, void *out) {
+    const int64_t work = n * ((k + 1) / 2);
+    if (work <= 0) return LNE_OK;
+    {
+        Launch L(ctx, "gaussian");
+        const unsigned gr = grid_of(work, 256);
+        if (dtype == LNE_F64)
+            k_gaussian<double><<<gr, 256, 0, ctx->stream>>>(n, k, ld, seed, (double *)out);
+        else if (dtype == LNE_F32)
+            k_gaussian<float><<<gr, 256, 0, ctx->stream>>>(n, k, ld, seed, (float *)out);
+        else
+            k_gaussian<__bf16><<<gr, 256, 0, ctx->stream>>>(n, k, ld, seed, (__bf16 *)out);
+    }
+    return check_launch(ctx, "gaussian");
+}
+
+}  // namespace lne

@@ -1,0 +1,309 @@
+// Pair aggregation: stable LSD radix sort of packed (row, col) keys with
+// their fixed-point weights, then a segmented sum of equal keys that writes
+// the count CSR directly (section 5.2: each distinct sampled pair with the
+// exact sum of its weights; here order-independent integer sums instead of a
+// lock-free hash, so the result is bit-identical for any launch shape).
+//
+// Radix pass (8-bit digit): per-tile digit histograms (digit-major table),
+// one device-wide scan of the table, then a scatter in which every tile ranks
+// its items stably (wave ballots per digit bit + per-wave digit counts in LDS),
+// stages them in LDS in digit order and writes each digit run contiguously.
+#include "common.hpp"
+
+namespace lne {
+
+namespace {
+
+constexpr int kT = 256;              // threads per block
+constexpr int kIt = 16;              // items per thread
+constexpr int kTile = kT * kIt;      // items per tile
+constexpr int kWaves = kT / 64;
+
+__global__ void __launch_bounds__(kT) k_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                             int shift, int64_t ntiles,
+                                             uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = base + it * kT + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kT) k_scatter(const uint64_t *__restrict__ kin,
+                                                const uint32_t *__restrict__ vin, int64_t n,
+                                                int shift, int64_t ntiles,
+                                                const uint32_t *__restrict__ hist,
+                                                const uint64_t *__restrict__ offs,
+                                                uint64_t *__restrict__ kout,
+                                                uint32_t *__restrict__ vout) {
+    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t sval[kTile];
+    __shared__ uint32_t whist[kWaves][256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t tpre[256];
+    __shared__ uint64_t gbase[256];
+    __shared__ uint32_t wtot[kWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kTile;
+
+    // exclusive prefix of this tile's digit counts
+    {
+        const uint32_t c = hist[(int64_t)tid * ntiles + tile];
+        uint32_t inc = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        if (lane == 63) wtot[wv] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int i = 0; i < wv; ++i) before += wtot[i];
+        tpre[tid] = before + inc - c;
+        gbase[tid] = offs[(int64_t)tid * ntiles + tile];
+        run[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) whist[w][tid] = 0;
+    }
+    __syncthreads();
+
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = base + it * kT + tid;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        uint32_t d = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            d = (uint32_t)(key >> shift) & 255u;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) whist[wv][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wv; ++w) pos += whist[w][d];
+            const uint32_t lp = tpre[d] + pos;
+            skey[lp] = key;
+            sval[lp] = val;
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                add += whist[w][tid];
+                whist[w][tid] = 0;
+            }
+            run[tid] += add;
+        }
+        __syncthreads();
+    }
+
+    const int64_t cnt = min((int64_t)kTile, n - base);
+    for (int64_t p = tid; p < cnt; p += kT) {
+        const uint64_t key = skey[p];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint64_t g = gbase[d] + (uint64_t)(p - tpre[d]);
+        kout[g] = key;
+        vout[g] = sval[p];
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_heads(const uint64_t *__restrict__ keys, int64_t n,
+                                              uint32_t *__restrict__ tile_heads) {
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t c = 0;
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = base + it * kT + threadIdx.x;
+        if (i < n && (i == 0 || keys[i] != keys[i - 1])) ++c;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    __shared__ uint32_t ws[kWaves];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < kWaves; ++i) t += ws[i];
+        tile_heads[blockIdx.x] = t;
+    }
+}
+
+// Segmented sums of equal keys.  Items are visited 256 at a time in order, so
+// a wave holds 64 consecutive items.  Segments strictly inside a wave are
+// stored; the first and last segment of a wave may continue into a
+// neighbour and are added atomically (integer, so order-independent).
+__global__ void __launch_bounds__(kT) k_reduce(const uint64_t *__restrict__ keys,
+                                               const uint32_t *__restrict__ vals, int64_t n,
+                                               const uint64_t *__restrict__ head_off,
+                                               int colbits, int32_t *__restrict__ col,
+                                               unsigned long long *__restrict__ W,
+                                               int64_t *__restrict__ rowptr) {
+    __shared__ uint32_t wh[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const uint64_t colmask = (1ull << colbits) - 1;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint64_t running = head_off[blockIdx.x];   // heads before this iteration
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = base + it * kT + tid;
+        const bool valid = i < n;
+        uint64_t key = 0, prev = 0;
+        uint64_t v = 0;
+        bool head = false;
+        if (valid) {
+            key = keys[i];
+            v = vals[i];
+            prev = i > 0 ? keys[i - 1] : ~0ull;
+            head = (i == 0) || key != prev;
+        }
+        const uint64_t hm = __ballot(head);
+        if (lane == 0) wh[wv] = (uint32_t)__popcll(hm);
+        __syncthreads();
+        uint64_t before = running;
+        uint64_t itot = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wv) before += wh[w];
+            itot += wh[w];
+        }
+        __syncthreads();
+        running += itot;
+        // unique index: heads up to and including this item, minus one
+        const uint64_t u = before + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
+        // inclusive segmented sum within the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t ov = __shfl_up(v, off, 64);
+            const uint64_t ou = __shfl_up(u, off, 64);
+            if (lane >= off && ou == u) v += ov;
+        }
+        const uint64_t nu = __shfl_down(u, 1, 64);
+        const bool next_valid = i + 1 < n;
+        if (!valid) continue;
+        if (head) {
+            col[u] = (int32_t)(key & colmask);
+            const int64_t row = (int64_t)(key >> colbits);
+            const int64_t prow = i == 0 ? -1 : (int64_t)(prev >> colbits);
+            for (int64_t r = prow + 1; r <= row; ++r) rowptr[r] = (int64_t)u;
+        }
+        const bool last_in_wave = lane == 63 || !next_valid || nu != u;
+        if (last_in_wave) {
+            // A head at or below this lane means the segment started in this
+            // wave; below lane 63 it also ends here.  Only such segments are
+            // touched by one wave alone.
+            const bool started_here = (hm & (lt | (1ull << lane))) != 0;
+            if (started_here && lane < 63)
+                W[u] = v;
+            else
+                atomicAdd(&W[u], (unsigned long long)v);
+        }
+    }
+}
+
+__global__ void k_rowptr_tail(const uint64_t *__restrict__ keys, int64_t n_items,
+                              int colbits, const uint64_t *__restrict__ nnz_p,
+                              int64_t n_rows, int64_t *__restrict__ rowptr) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n_rows) return;
+    const int64_t last = n_items > 0 ? (int64_t)(keys[n_items - 1] >> colbits) : -1;
+    if (r > last) rowptr[r] = (int64_t)*nnz_p;
+}
+
+}  // namespace
+
+lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                      int64_t n, int bits, int *which) {
+    *which = 0;
+    if (n <= 1) return LNE_OK;
+    const int64_t ntiles = ceil_div(n, kTile);
+    Buf hist(ctx), offs(ctx);
+    LNE_TRY(alloc(ctx, hist, sizeof(uint32_t) * (size_t)(256 * ntiles)));
+    LNE_TRY(alloc(ctx, offs, sizeof(uint64_t) * (size_t)(256 * ntiles + 1)));
+    uint64_t *ks[2] = {k0, k1};
+    uint32_t *vs[2] = {v0, v1};
+    int cur = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        {
+            Launch L(ctx, "radix_hist");
+            k_hist<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(ks[cur], n, shift, ntiles,
+                                                             hist.as<uint32_t>());
+        }
+        LNE_TRY(check_launch(ctx, "radix_hist"));
+        LNE_TRY(scan_u32(ctx, hist.as<uint32_t>(), offs.as<uint64_t>(), 256 * ntiles));
+        {
+            Launch L(ctx, "radix_scatter");
+            k_scatter<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
+                ks[cur], vs[cur], n, shift, ntiles, hist.as<uint32_t>(), offs.as<uint64_t>(),
+                ks[cur ^ 1], vs[cur ^ 1]);
+        }
+        LNE_TRY(check_launch(ctx, "radix_scatter"));
+        cur ^= 1;
+    }
+    *which = cur;
+    return LNE_OK;
+}
+
+lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
+                         int64_t n_items, int64_t n_rows, int colbits, lne_csr *out) {
+    const int64_t ntiles = ceil_div(n_items > 0 ? n_items : 1, kTile);
+    Buf th(ctx), hoff(ctx);
+    LNE_TRY(alloc(ctx, th, sizeof(uint32_t) * (size_t)ntiles));
+    LNE_TRY(alloc(ctx, hoff, sizeof(uint64_t) * (size_t)(ntiles + 1)));
+    {
+        Launch L(ctx, "heads");
+        k_heads<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(keys, n_items, th.as<uint32_t>());
+    }
+    LNE_TRY(check_launch(ctx, "heads"));
+    LNE_TRY(scan_u32(ctx, th.as<uint32_t>(), hoff.as<uint64_t>(), ntiles));
+    uint64_t nnz = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(&nnz, hoff.as<uint64_t>() + ntiles, sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+
+    Buf rp(ctx), cc(ctx), ww(ctx);
+    LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)(n_rows + 1)));
+    LNE_TRY(alloc(ctx, cc, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+    LNE_TRY(alloc(ctx, ww, sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1)));
+    LNE_HIP(ctx, hipMemsetAsync(ww.p, 0, sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1),
+                                ctx->stream));
+    if (n_items > 0) {
+        Launch L(ctx, "reduce");
+        k_reduce<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
+            keys, vals, n_items, hoff.as<uint64_t>(), colbits, cc.as<int32_t>(),
+            ww.as<unsigned long long>(), rp.as<int64_t>());
+    }
+    LNE_TRY(check_launch(ctx, "reduce"));
+    {
+        Launch L(ctx, "rowptr_tail");
+        k_rowptr_tail<<<grid_of(n_rows + 1, 256), 256, 0, ctx->stream>>>(
+            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>());
+    }
+    LNE_TRY(check_launch(ctx, "rowptr_tail"));
+    out->n_rows = n_rows;
+    out->n_cols = n_rows;
+    out->nnz = (int64_t)nnz;
+    out->row_ptr = (int64_t *)rp.detach();
+    out->col = (int32_t *)cc.detach();
+    out->val = ww.detach();
+    out->val_type = LNE_U64;
+    return LNE_OK;
+}
+
+}  // namespace lne

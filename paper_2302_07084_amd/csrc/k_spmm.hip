@@ -1,0 +1,340 @@
+// Sparse x dense products on gfx950.
+//
+// spmm: Y = A X with A a CSR matrix with values (the sparsified NetMF matrix
+// of the randomized SVD, Algorithm "Fast Randomized SVD") and X a row-major
+// n x k dense block.  graph_spmm: out = a Z + b D^-1 A Z + c1 E1 + c2 E2
+// (+ acc += cacc out) with A the value-free graph adjacency, the building
+// block of the Chebyshev recurrence of section 4.3.
+//
+// Both are gather-bound: every nonzero pulls one k-wide row of the dense
+// operand.  One wave owns one output row.  Its 64 lanes read the row's column
+// ids and values in coalesced batches of 64 and broadcast them lane to lane;
+// the wave is split into G = 64 / L lane groups of L lanes, each lane moving
+// 16 bytes per gathered row (float4 / double2 / 8 x bf16), so a 16-byte
+// aligned gathered row of up to L * 16 bytes is one vector load per lane and G
+// nonzeros are in flight per instruction.  Groups are combined by a butterfly
+// over lane offsets L, 2L, ... before the epilogue writes the row.
+#include "common.hpp"
+
+namespace lne {
+
+namespace {
+
+template <class T> struct Vec;
+template <> struct Vec<double> { static constexpr int N = 2; using A = double; };
+template <> struct Vec<float> { static constexpr int N = 4; using A = float; };
+template <> struct Vec<__bf16> { static constexpr int N = 8; using A = float; };
+
+template <class T> __device__ __forceinline__ float to_f(T x) { return (float)x; }
+
+template <class XT, class AT, int N>
+__device__ __forceinline__ void load_row(const XT *__restrict__ p, int c0, int k, AT v[N]) {
+    if (c0 + N <= k) {
+        if constexpr (sizeof(XT) * N == 16) {
+            const uint4 raw = *reinterpret_cast<const uint4 *>(p);
+            const XT *e = reinterpret_cast<const XT *>(&raw);
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = (AT)e[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = (AT)p[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = (c0 + i < k) ? (AT)p[i] : (AT)0;
+    }
+}
+
+template <class OT, class AT, int N>
+__device__ __forceinline__ void store_row(OT *__restrict__ p, int c0, int k, const AT v[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (c0 + i < k) p[i] = (OT)v[i];
+}
+
+// L = lanes per gathered row (power of two, <= 64); VT value type (void for
+// the graph kernel); XT operand type; OT output type.
+template <int L, class VT, class XT, class OT>
+__global__ void __launch_bounds__(256)
+k_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+       const VT *__restrict__ val, int64_t n_rows, const XT *__restrict__ X, int64_t ldx,
+       OT *__restrict__ Y, int64_t ldy, int k) {
+    constexpr int N = Vec<XT>::N;
+    using AT = typename Vec<XT>::A;
+    constexpr int G = 64 / L;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n_rows) return;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / L, lc = lane % L;
+    const int64_t beg = rp[row], end = rp[row + 1];
+    for (int cb = 0; cb < k; cb += L * N) {
+        const int c0 = cb + lc * N;
+        AT acc[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = 0;
+        for (int64_t b0 = beg; b0 < end; b0 += 64) {
+            const int64_t idx = b0 + lane;
+            const int32_t cj = idx < end ? col[idx] : 0;
+            const AT vj = idx < end ? (AT)val[idx] : (AT)0;
+            const int cnt = (int)min((int64_t)64, end - b0);
+            // the trip count is the same for every lane, so every shuffle
+            // reads from lanes that are active
+            for (int t0 = 0; t0 < cnt; t0 += 4 * G) {
+                const int t[4] = {t0 + grp, t0 + grp + G, t0 + grp + 2 * G, t0 + grp + 3 * G};
+                int32_t j[4];
+                AT v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    j[q] = __shfl(cj, t[q] & 63);
+                    v[q] = __shfl(vj, t[q] & 63);
+                }
+                AT x[4][N];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (t[q] < cnt && c0 < k)
+                        load_row<XT, AT, N>(X + (int64_t)j[q] * ldx + c0, c0, k, x[q]);
+                    else
+#pragma unroll
+                        for (int i = 0; i < N; ++i) x[q][i] = 0;
+                }
+#pragma unroll
+                for (int i = 0; i < N; ++i)
+                    acc[i] += (t[0] < cnt ? v[0] * x[0][i] : (AT)0) +
+                              (t[1] < cnt ? v[1] * x[1][i] : (AT)0) +
+                              (t[2] < cnt ? v[2] * x[2][i] : (AT)0) +
+                              (t[3] < cnt ? v[3] * x[3][i] : (AT)0);
+            }
+        }
+#pragma unroll
+        for (int off = L; off < 64; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+        if (grp == 0 && c0 < k) store_row<OT, AT, N>(Y + row * ldy + c0, c0, k, acc);
+    }
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(256)
+k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n_rows,
+             const T *__restrict__ Z, int64_t ld, int k, T *__restrict__ out, T a, T b,
+             const T *__restrict__ E1, T c1, const T *__restrict__ E2, T c2,
+             T *__restrict__ accum, T cacc) {
+    constexpr int N = Vec<T>::N;
+    constexpr int G = 64 / L;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n_rows) return;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / L, lc = lane % L;
+    const int64_t beg = rp[row], end = rp[row + 1];
+    const T inv = end > beg ? (T)1 / (T)(end - beg) : (T)0;
+    for (int cb = 0; cb < k; cb += L * N) {
+        const int c0 = cb + lc * N;
+        T acc[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = 0;
+        for (int64_t b0 = beg; b0 < end; b0 += 64) {
+            const int64_t idx = b0 + lane;
+            const int32_t cj = idx < end ? col[idx] : 0;
+            const int cnt = (int)min((int64_t)64, end - b0);
+            for (int t0 = 0; t0 < cnt; t0 += 4 * G) {
+                const int t[4] = {t0 + grp, t0 + grp + G, t0 + grp + 2 * G, t0 + grp + 3 * G};
+                int32_t j[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) j[q] = __shfl(cj, t[q] & 63);
+                T x[4][N];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (t[q] < cnt && c0 < k)
+                        load_row<T, T, N>(Z + (int64_t)j[q] * ld + c0, c0, k, x[q]);
+                    else
+#pragma unroll
+                        for (int i = 0; i < N; ++i) x[q][i] = 0;
+                }
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc[i] += (x[0][i] + x[1][i]) + (x[2][i] + x[3][i]);
+            }
+        }
+#pragma unroll
+        for (int off = L; off < 64; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+        if (grp == 0 && c0 < k) {
+            T z[N], e1[N], e2[N];
+            const int64_t o = row * ld + c0;
+            load_row<T, T, N>(Z + o, c0, k, z);
+            if (E1) load_row<T, T, N>(E1 + o, c0, k, e1);
+            if (E2) load_row<T, T, N>(E2 + o, c0, k, e2);
+            T r[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                r[i] = a * z[i] + b * (inv * acc[i]);
+                if (E1) r[i] += c1 * e1[i];
+                if (E2) r[i] += c2 * e2[i];
+            }
+            store_row<T, T, N>(out + o, c0, k, r);
+            if (accum) {
+                T s[N];
+                load_row<T, T, N>(accum + o, c0, k, s);
+#pragma unroll
+                for (int i = 0; i < N; ++i) s[i] += cacc * r[i];
+                store_row<T, T, N>(accum + o, c0, k, s);
+            }
+        }
+    }
+}
+
+template <class XT, class YT>
+__global__ void k_scale(const XT *__restrict__ x, int64_t ldx, YT *__restrict__ y, int64_t ldy,
+                        int64_t n, int k, double alpha) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t i = t / k;
+    const int c = (int)(t - i * k);
+    y[i * ldy + c] = (YT)(alpha * (double)x[i * ldx + c]);
+}
+
+template <class T>
+__global__ void k_axpby(const T *__restrict__ x, const T *__restrict__ y, T *__restrict__ out,
+                        int64_t n, int k, int64_t ld, T a, T b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t i = t / k;
+    const int64_t o = i * ld + (t - i * k);
+    out[o] = a * x[o] + b * y[o];
+}
+
+int lanes_for(int k, int N) {
+    const int need = (k + N - 1) / N;
+    int L = 1;
+    while (L < need && L < 64) L <<= 1;
+    return L;
+}
+
+template <class VT, class XT, class OT>
+lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y,
+                  int64_t ldy, int k) {
+    const int N = Vec<XT>::N;
+    const bool aligned = ((uintptr_t)X % 16 == 0) && (ldx % N == 0);
+    const unsigned grid = grid_of(A->n_rows * 64, 256);
+    const int L = lanes_for(k, N);
+    const VT *val = (const VT *)A->val;
+    if (!aligned) return fail(ctx, LNE_EINVAL, "spmm: X must be 16-byte aligned with ld %% %d == 0", N);
+    Launch Lc(ctx, "spmm");
+#define LNE_SPMM_CASE(LL)                                                                  \
+    case LL:                                                                               \
+        k_spmm<LL, VT, XT, OT><<<grid, 256, 0, ctx->stream>>>(A->row_ptr, A->col, val,    \
+                                                              A->n_rows, X, ldx, Y, ldy,   \
+                                                              k);                          \
+        break;
+    switch (L) {
+        LNE_SPMM_CASE(1) LNE_SPMM_CASE(2) LNE_SPMM_CASE(4) LNE_SPMM_CASE(8)
+        LNE_SPMM_CASE(16) LNE_SPMM_CASE(32) LNE_SPMM_CASE(64)
+        default: break;
+    }
+#undef LNE_SPMM_CASE
+    return LNE_OK;
+}
+
+template <class T>
+lne_status gspmm_t(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k,
+                   double a, double b, const T *E1, double c1, const T *E2, double c2,
+                   T *acc, double cacc) {
+    const int N = Vec<T>::N;
+    if ((uintptr_t)Z % 16 || (uintptr_t)out % 16 || ld % N)
+        return fail(ctx, LNE_EINVAL, "graph_spmm: operands must be 16-byte aligned");
+    const unsigned grid = grid_of(g->n * 64, 256);
+    const int L = lanes_for(k, N);
+    Launch Lc(ctx, "graph_spmm");
+#define LNE_GSPMM_CASE(LL)                                                                   \
+    case LL:                                                                                 \
+        k_graph_spmm<LL, T><<<grid, 256, 0, ctx->stream>>>(g->row_ptr, g->col, g->n, Z, ld, \
+                                                           k, out, (T)a, (T)b, E1, (T)c1,   \
+                                                           E2, (T)c2, acc, (T)cacc);        \
+        break;
+    switch (L) {
+        LNE_GSPMM_CASE(1) LNE_GSPMM_CASE(2) LNE_GSPMM_CASE(4) LNE_GSPMM_CASE(8)
+        LNE_GSPMM_CASE(16) LNE_GSPMM_CASE(32) LNE_GSPMM_CASE(64)
+        default: break;
+    }
+#undef LNE_GSPMM_CASE
+    return LNE_OK;
+}
+
+}  // namespace
+
+lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void *Y,
+                int64_t ldy, int32_t k, int32_t dtype) {
+    lne_status s;
+    if (dtype == LNE_F64) {
+        if (A->val_type != LNE_F64) return fail(ctx, LNE_EINVAL, "spmm: F64 needs F64 values");
+        s = spmm_t<double, double, double>(ctx, A, (const double *)X, ldx, (double *)Y, ldy, k);
+    } else if (dtype == LNE_F32) {
+        if (A->val_type != LNE_F32) return fail(ctx, LNE_EINVAL, "spmm: F32 needs F32 values");
+        s = spmm_t<float, float, float>(ctx, A, (const float *)X, ldx, (float *)Y, ldy, k);
+    } else if (dtype == LNE_BF16) {
+        if (A->val_type != LNE_F32) return fail(ctx, LNE_EINVAL, "spmm: BF16 needs F32 values");
+        s = spmm_t<float, __bf16, __bf16>(ctx, A, (const __bf16 *)X, ldx, (__bf16 *)Y, ldy, k);
+    } else {
+        return fail(ctx, LNE_EINVAL, "spmm: bad dtype");
+    }
+    LNE_TRY(s);
+    return check_launch(ctx, "spmm");
+}
+
+lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out, int64_t ld,
+                      int32_t k, int32_t dtype, double a, double b, const void *E1, double c1,
+                      const void *E2, double c2, void *acc, double cacc) {
+    lne_status s;
+    if (dtype == LNE_F64)
+        s = gspmm_t<double>(ctx, g, (const double *)Z, (double *)out, ld, k, a, b,
+                            (const double *)E1, c1, (const double *)E2, c2, (double *)acc, cacc);
+    else if (dtype == LNE_F32)
+        s = gspmm_t<float>(ctx, g, (const float *)Z, (float *)out, ld, k, a, b,
+                           (const float *)E1, c1, (const float *)E2, c2, (float *)acc, cacc);
+    else
+        return fail(ctx, LNE_EINVAL, "graph_spmm: bad dtype");
+    LNE_TRY(s);
+    return check_launch(ctx, "graph_spmm");
+}
+
+lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,
+                 int64_t ld, int32_t dt, double a, double b) {
+    if (n * k == 0) return LNE_OK;
+    {
+        Launch L(ctx, "axpby");
+        const unsigned grid = grid_of(n * k, 256);
+        if (dt == LNE_F64)
+            k_axpby<double><<<grid, 256, 0, ctx->stream>>>((const double *)x, (const double *)y,
+                                                           (double *)out, n, k, ld, a, b);
+        else if (dt == LNE_F32)
+            k_axpby<float><<<grid, 256, 0, ctx->stream>>>((const float *)x, (const float *)y,
+                                                          (float *)out, n, k, ld, (float)a,
+                                                          (float)b);
+        else
+            return fail(ctx, LNE_EINVAL, "axpby: bad dtype");
+    }
+    return check_launch(ctx, "axpby");
+}
+
+lne_status dense_scale(lne_ctx *ctx, const void *x, int32_t xt, int64_t ldx, void *y,
+                       int32_t yt, int64_t ldy, int64_t n, int32_t k, double alpha) {
+    if (n * k == 0) return LNE_OK;
+    const unsigned grid = grid_of(n * k, 256);
+    {
+        Launch L(ctx, "dense_scale");
+#define LNE_SC(XT, YT)                                                                    \
+    k_scale<XT, YT><<<grid, 256, 0, ctx->stream>>>((const XT *)x, ldx, (YT *)y, ldy, n, k, \
+                                                   alpha)
+        if (xt == LNE_F64 && yt == LNE_F64) LNE_SC(double, double);
+        else if (xt == LNE_F64 && yt == LNE_F32) LNE_SC(double, float);
+        else if (xt == LNE_F32 && yt == LNE_F32) LNE_SC(float, float);
+        else if (xt == LNE_F32 && yt == LNE_F64) LNE_SC(float, double);
+        else if (xt == LNE_F32 && yt == LNE_BF16) LNE_SC(float, __bf16);
+        else if (xt == LNE_BF16 && yt == LNE_F32) LNE_SC(__bf16, float);
+        else return fail(ctx, LNE_EINVAL, "dense_scale: unsupported conversion");
+#undef LNE_SC
+    }
+    return check_launch(ctx, "dense_scale");
+}
+
+}  // namespace lne

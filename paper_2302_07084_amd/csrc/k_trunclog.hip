@@ -1,0 +1,131 @@
+// Truncated logarithm of Eq. (1) on the count matrix, compacted in place of
+// the paper's in-hash logarithm (section 5.2, "memory tricks").
+//   x_ab = vol^2 / (2 b M) * (W_ab / 2^16) / (d_a d_b),  kept iff x_ab > 1.
+// The keep decision is exact: W vol^2 > (2 b M 2^16) d_a d_b compared as
+// 128-bit products (vol < 2^32 and 2 b M < 2^40 are validated on the host).
+// One wave per row; kept entries are compacted with a ballot prefix so the
+// output keeps the ascending column order.
+#include "common.hpp"
+
+namespace lne {
+
+namespace {
+
+struct TLConst {
+    uint64_t vol2;     // vol^2
+    uint64_t K;        // 2 b M 2^16
+    double scale;      // vol^2 / (2 b M) / 2^16
+};
+
+__device__ __forceinline__ bool keep_entry(const TLConst &c, uint64_t W, uint64_t da,
+                                           uint64_t db) {
+    const uint64_t dd = da * db;
+    const uint64_t lh = __umul64hi(W, c.vol2), ll = W * c.vol2;
+    const uint64_t rh = __umul64hi(c.K, dd), rl = c.K * dd;
+    return lh > rh || (lh == rh && ll > rl);
+}
+
+__global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t n,
+                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const uint64_t *__restrict__ W, uint32_t *__restrict__ kept) {
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    const uint64_t da = (uint64_t)(grp[a + 1] - grp[a]);
+    uint32_t cnt = 0;
+    for (int64_t i = rp[a] + lane; i < rp[a + 1]; i += 64) {
+        const int32_t b = col[i];
+        cnt += keep_entry(c, W[i], da, (uint64_t)(grp[b + 1] - grp[b])) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if (lane == 0) kept[a] = cnt;
+}
+
+template <class VT>
+__global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t n,
+                          const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                          const uint64_t *__restrict__ W, const int64_t *__restrict__ orp,
+                          int32_t *__restrict__ ocol, VT *__restrict__ oval) {
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t da = (uint64_t)(grp[a + 1] - grp[a]);
+    int64_t pos = orp[a];
+    const int64_t beg = rp[a], end = rp[a + 1];
+    for (int64_t i0 = beg; i0 < end; i0 += 64) {
+        const int64_t i = i0 + lane;
+        bool k = false;
+        int32_t b = 0;
+        uint64_t w = 0, db = 1;
+        if (i < end) {
+            b = col[i];
+            w = W[i];
+            db = (uint64_t)(grp[b + 1] - grp[b]);
+            k = keep_entry(c, w, da, db);
+        }
+        const uint64_t mask = __ballot(k);
+        if (k) {
+            const int64_t o = pos + __popcll(mask & lt);
+            const double x = (double)w * c.scale / ((double)da * (double)db);
+            ocol[o] = b;
+            oval[o] = (VT)log(x);
+        }
+        pos += __popcll(mask);
+    }
+}
+
+}  // namespace
+
+lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                         const lne_csr *counts, int32_t val_type, lne_csr *out) {
+    const int64_t n = counts->n_rows;
+    TLConst c;
+    const uint64_t vol = (uint64_t)g->n_arcs;
+    c.vol2 = vol * vol;
+    c.K = (2ull * (uint64_t)p->b * p->M) << 16;
+    c.scale = ((double)vol * (double)vol) / (2.0 * (double)p->b * (double)p->M) / 65536.0;
+
+    Buf kept(ctx), rp(ctx);
+    LNE_TRY(alloc(ctx, kept, sizeof(uint32_t) * (size_t)(n + 1)));
+    LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)(n + 1)));
+    const unsigned grid = grid_of(n * 64, 256);
+    if (n > 0) {
+        Launch L(ctx, "trunc_log_count");
+        k_tl_count<<<grid, 256, 0, ctx->stream>>>(c, g->row_ptr, n, counts->row_ptr,
+                                                  counts->col, (const uint64_t *)counts->val,
+                                                  kept.as<uint32_t>());
+    }
+    LNE_TRY(check_launch(ctx, "trunc_log_count"));
+    LNE_TRY(scan_u32(ctx, kept.as<uint32_t>(), rp.as<uint64_t>(), n));
+    uint64_t nnz = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(&nnz, rp.as<int64_t>() + n, sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    Buf cc(ctx), vv(ctx);
+    LNE_TRY(alloc(ctx, cc, sizeof(int32_t) * (size_t)(nnz ? nnz : 1)));
+    LNE_TRY(alloc(ctx, vv, dtype_size(val_type) * (size_t)(nnz ? nnz : 1)));
+    if (n > 0) {
+        Launch L(ctx, "trunc_log_fill");
+        if (val_type == LNE_F64)
+            k_tl_fill<double><<<grid, 256, 0, ctx->stream>>>(
+                c, g->row_ptr, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
+                rp.as<int64_t>(), cc.as<int32_t>(), vv.as<double>());
+        else
+            k_tl_fill<float><<<grid, 256, 0, ctx->stream>>>(
+                c, g->row_ptr, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
+                rp.as<int64_t>(), cc.as<int32_t>(), vv.as<float>());
+    }
+    LNE_TRY(check_launch(ctx, "trunc_log_fill"));
+    out->n_rows = n;
+    out->n_cols = counts->n_cols;
+    out->nnz = (int64_t)nnz;
+    out->row_ptr = (int64_t *)rp.detach();
+    out->col = (int32_t *)cc.detach();
+    out->val = vv.detach();
+    out->val_type = val_type;
+    return LNE_OK;
+}
+
+}  // namespace lne

@@ -19,3 +19,16 @@ def lne():
     import paper_2302_07084_amd as lne_mod
     lne_mod.load()
     return lne_mod
+
+
+@pytest.fixture(scope="session")
+def ctx(lne):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return lne.Context()
+
+
+def to_dev(g):
+    import torch
+    return (torch.from_numpy(g.rowptr.astype("int64")).cuda(),
+            torch.from_numpy(g.col.astype("int32")).cuda())

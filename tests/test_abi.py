@@ -1,0 +1,117 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/lne.h declares, and rejects bad arguments on the host before any
+GPU work (these calls never reach the HIP runtime)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import graphs_small as gs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lne.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:lne_status|void|const char\s*\*|int64_t)\s*(lne_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(lne):
+    L = lne.load()
+    names = declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    bound = {n for n, _, _ in lne.SIGNATURES}
+    assert bound == set(names)
+
+
+def test_version(lne):
+    assert "gfx950" in lne.version()
+
+
+def _ctx(lne):
+    L = lne.load()
+    h = ctypes.c_void_p()
+    null_a = ctypes.cast(None, lne._ALLOC_T)
+    null_f = ctypes.cast(None, lne._FREE_T)
+    assert L.lne_ctx_create(ctypes.byref(h), None, null_a, null_f, None) == 0
+    return L, h
+
+
+def test_ctx_create_rejects_half_allocator(lne):
+    L = lne.load()
+    h = ctypes.c_void_p()
+    a = lne._ALLOC_T(lambda n, u: None)
+    null_f = ctypes.cast(None, lne._FREE_T)
+    assert L.lne_ctx_create(ctypes.byref(h), None, a, null_f, None) == -1
+    assert L.lne_ctx_create(None, None, ctypes.cast(None, lne._ALLOC_T), null_f, None) == -1
+
+
+def _graph(n=10, n_arcs=20):
+    g = __import__("paper_2302_07084_amd").Graph()
+    g.n, g.n_arcs, g.row_ptr, g.col = n, n_arcs, 0x1000, 0x2000
+    return g
+
+
+@pytest.mark.parametrize("field,value", [("T", 0), ("T", 17), ("b", 0), ("M", 1 << 40)])
+def test_sparsify_rejects_bad_params(lne, field, value):
+    L, h = _ctx(lne)
+    p = lne.make_params(gs.params(T=3, m=10))
+    setattr(p, field, value)
+    out = lne.CsrStruct()
+    rc = L.lne_sparsify(h, ctypes.byref(_graph()), ctypes.byref(p), ctypes.byref(out), None)
+    assert rc == -1
+    assert L.lne_last_error(h)
+    L.lne_ctx_destroy(h)
+
+
+def test_sparsify_rejects_bad_s(lne):
+    L, h = _ctx(lne)
+    for s in ([0.0, 0.0, 0.0], [0.5, -0.1, 0.6], [math.nan, 1, 1]):
+        p = lne.make_params(gs.params(T=3, s=s, m=10))
+        rc = L.lne_sparsify(h, ctypes.byref(_graph()), ctypes.byref(p), ctypes.byref(lne.CsrStruct()), None)
+        assert rc == -1
+    L.lne_ctx_destroy(h)
+
+
+@pytest.mark.parametrize("n,n_arcs", [(0, 0), (5, 3), (5, -2), (5, 1 << 32), (1 << 31, 4)])
+def test_graph_validation(lne, n, n_arcs):
+    L, h = _ctx(lne)
+    p = lne.make_params(gs.params(T=2, m=10))
+    rc = L.lne_sparsify(h, ctypes.byref(_graph(n, n_arcs)), ctypes.byref(p),
+                        ctypes.byref(lne.CsrStruct()), None)
+    assert rc == -1
+    L.lne_ctx_destroy(h)
+
+
+def test_linalg_param_validation(lne):
+    L, h = _ctx(lne)
+    base = gs.params(T=2, m=10, d=4, oversample=2, q=1)
+    for bad in (dict(q=0), dict(d=0), dict(d=300), dict(d=8, oversample=4), dict(cheb_k=-1),
+                dict(theta=-1.0), dict(precision=7)):
+        p = lne.make_params(dict(base, **bad))
+        rc = L.lne_embed(h, ctypes.byref(_graph()), ctypes.byref(p), ctypes.c_void_p(0x3000), None)
+        assert rc in (-1, -5), bad
+    L.lne_ctx_destroy(h)
+
+
+def test_sampler_plan_matches_oracle(lne):
+    rng = np.random.default_rng(0)
+    for T in (1, 3, 10, 16):
+        for _ in range(5):
+            s = rng.dirichlet(np.ones(T))
+            s[rng.random(T) < 0.2] = 0.0
+            if s.sum() == 0:
+                s[0] = 1.0
+            m = int(rng.integers(1, 10 ** 7))
+            M = int(rng.integers(1, 10 ** 10))
+            p = dict(T=T, s=s, M=M, b=1, C=1.0, seed=0)
+            assert lne.sampler_plan(p, 2 * m)[0:2] == oracle.plan(T, s, M, m)[0:2]
+            np.testing.assert_array_equal(lne.sampler_plan(p, 2 * m)[2], oracle.plan(T, s, M, m)[2])
+            assert lne.slots_per_edge(p, 2 * m) == M // m + (1 if M % m else 0)

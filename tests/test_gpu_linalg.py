@@ -1,0 +1,171 @@
+"""GPU SpMM, eigSVD, CholeskyQR2 orthonormaliser, fast randomized SVD and
+spectral propagation vs the oracle and LAPACK."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from synth import workload
+from tests.conftest import to_dev
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+UBF = 2.0 ** -8
+
+
+def principal_angle(A, B):
+    """Largest principal angle between span(A) and span(B), as
+    arcsin ||(I - Qa Qa^T) Qb||_2 (accurate for small angles)."""
+    qa, _ = np.linalg.qr(A)
+    qb, _ = np.linalg.qr(B)
+    r = qb - qa @ (qa.T @ qb)
+    return float(np.arcsin(min(1.0, np.linalg.norm(r, 2))))
+
+
+def procrustes_err(X, Xref):
+    U, _, Vt = np.linalg.svd(X.T @ Xref)
+    return float(np.linalg.norm(X @ (U @ Vt) - Xref) / np.linalg.norm(Xref))
+
+
+@pytest.fixture(scope="module")
+def tiny(lne, ctx):
+    g, p = workload("tiny")
+    rp, col = to_dev(g)
+    st = oracle.embed(g, p, return_stages=True)
+    return g, p, rp, col, st
+
+
+def _rand_y(n, k, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    return (Q1 * np.logspace(0, -math.log10(cond), k)) @ Q2
+
+
+@pytest.mark.parametrize("k", [5, 42, 138, 272])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_eigsvd_vs_lapack(lne, ctx, k, dtype):
+    import torch
+    n = 3000
+    Y = _rand_y(n, k, seed=k, cond=10.0 if dtype == "bf16" else 1e3)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    ld = (k + 7) // 8 * 8
+    Yd = torch.zeros((n, ld), dtype=tdt, device="cuda")
+    Yd[:, :k] = torch.from_numpy(Y).to(tdt)
+    Yq = Yd[:, :k].double().cpu().numpy()         # the values the GPU sees
+    U, S, V = lne.eigsvd(ctx, Yd[:, :k])
+    S2 = np.linalg.svd(Yq, compute_uv=False)
+    tol = {"f64": 1e-11, "f32": 1e-10, "bf16": 4 * UBF}[dtype]
+    np.testing.assert_allclose(S.cpu().numpy(), S2, rtol=tol * 10, atol=tol * S2[0])
+    Un = U.double().cpu().numpy()
+    Vn = V.cpu().numpy()
+    recon = (Un * S.cpu().numpy()) @ Vn.T
+    rt = {"f64": 1e-12, "f32": 1e-6, "bf16": 2e-2}[dtype]
+    assert np.linalg.norm(recon - Yq) <= rt * np.linalg.norm(Yq)
+    np.testing.assert_allclose(Vn.T @ Vn, np.eye(k), atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("k", [42, 138])
+def test_orthonormalize(lne, ctx, dtype, k):
+    import torch
+    n = 5000
+    Y = _rand_y(n, k, seed=3, cond=1e4)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    ld = (k + 7) // 8 * 8
+    Yd = torch.zeros((n, ld), dtype=tdt, device="cuda")
+    Yd[:, :k] = torch.from_numpy(Y).to(tdt)
+    Yq = Yd[:, :k].double().cpu().numpy()
+    lne.orthonormalize(ctx, Yd[:, :k])
+    Q = Yd[:, :k].double().cpu().numpy()
+    tol = {"f64": 1e-13, "f32": 3e-6, "bf16": 6e-2}[dtype]
+    assert np.max(np.abs(Q.T @ Q - np.eye(k))) < tol * math.sqrt(k)
+    assert principal_angle(Q, Yq) < {"f64": 1e-8, "f32": 1e-2, "bf16": 0.5}[dtype]
+
+
+def test_orthonormalize_ill_conditioned_takes_shift(lne, ctx):
+    import torch
+    n, k = 4000, 40
+    Y = _rand_y(n, k, seed=9, cond=1e12)
+    Yd = torch.from_numpy(Y).cuda()
+    lne.orthonormalize(ctx, Yd)
+    Q = Yd.cpu().numpy()
+    assert np.max(np.abs(Q.T @ Q - np.eye(k))) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_spmm_vs_scipy(lne, ctx, tiny, prec):
+    import torch
+    g, p, rp, col, st = tiny
+    pp = dict(p, precision=prec)
+    counts, _ = lne.sparsify(ctx, rp, col, pp)
+    M = lne.trunc_log(ctx, rp, col, pp, counts)
+    R, C, V = (x.cpu() for x in M.to_torch())
+    A = sp.csr_matrix((V.double().numpy(), C.numpy(), R.numpy()), shape=(g.n, g.n))
+    for k in (1, 8, 42, 138):
+        rng = np.random.default_rng(k)
+        X = rng.standard_normal((g.n, k))
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
+        ld = (k + 7) // 8 * 8
+        Xd = torch.zeros((g.n, ld), dtype=tdt, device="cuda")
+        Xd[:, :k] = torch.from_numpy(X).to(tdt)
+        Y = lne.spmm(ctx, M, Xd[:, :k]).double().cpu().numpy()
+        ref = A @ Xd[:, :k].double().cpu().numpy()
+        scale = np.abs(A) @ np.abs(Xd[:, :k].double().cpu().numpy())
+        u = {"f64": U64, "f32": U32, "bf16": UBF}[prec]
+        assert np.all(np.abs(Y - ref) <= 4 * np.sqrt(A.getnnz(1).max()) * u * scale + 1e-300)
+
+
+def test_rsvd_matches_oracle_f64(lne, ctx, tiny):
+    g, p, rp, col, st = tiny
+    counts, _ = lne.sparsify(ctx, rp, col, p)
+    M = lne.trunc_log(ctx, rp, col, p, counts)
+    U, S, V, X0 = (x.cpu().numpy() for x in lne.rsvd(ctx, M, p))
+    Sref = st["S"]
+    kp = p["d"] + p["oversample"]
+    # full spectrum of the basis, for the gap at d
+    gap = (Sref[-2] - Sref[-1]) / Sref[0] if len(Sref) > 1 else 1.0
+    tol = 100 * math.sqrt(kp) * U64 / max(gap, 1e-3)
+    np.testing.assert_allclose(S, Sref, rtol=10 * math.sqrt(kp) * U64 * Sref[0] / Sref.min() + 1e-12)
+    assert principal_angle(U, st["U"]) < max(tol, 1e-9)
+    assert procrustes_err(X0, st["X0"]) < max(tol, 1e-9)
+    assert procrustes_err(V, st["V"]) < max(tol, 1e-9)
+
+
+@pytest.mark.parametrize("k,theta,mu", [(10, 0.5, 0.2), (3, 1.0, 0.4), (1, 0.3, 0.0)])
+def test_propagate_filter_matches_oracle(lne, ctx, tiny, k, theta, mu):
+    import torch
+    g, p, rp, col, st = tiny
+    X0 = st["X0"]
+    pp = dict(p, cheb_k=k, theta=theta, mu=mu, flags=lne.FLAG_NO_FINAL_EIGSVD)
+    Xsp = lne.propagate(ctx, rp, col, pp, torch.from_numpy(X0).cuda()).cpu().numpy()
+    ref = oracle.propagate(g, X0, k, theta, mu)
+    assert np.max(np.abs(Xsp - ref)) <= 1e-12 * np.max(np.abs(X0)) * (2 * k + 1)
+
+
+def test_propagate_final_embedding(lne, ctx, tiny):
+    import torch
+    g, p, rp, col, st = tiny
+    X = lne.propagate(ctx, rp, col, p, torch.from_numpy(st["X0"]).cuda()).cpu().numpy()
+    assert procrustes_err(X, st["X"]) < 1e-9
+
+
+def test_propagate_off_is_identity(lne, ctx, tiny):
+    import torch
+    g, p, rp, col, st = tiny
+    X0 = torch.from_numpy(st["X0"]).cuda()
+    for pp in (dict(p, cheb_k=0), dict(p, theta=0.0)):
+        assert bool((lne.propagate(ctx, rp, col, pp, X0) == X0).all())
+
+
+def test_embed_tiny_matches_oracle(lne, ctx, tiny):
+    g, p, rp, col, st = tiny
+    X, stats = lne.embed(ctx, rp, col, p)
+    X = X.cpu().numpy()
+    assert stats["nnz_log"] == st["M"].nnz
+    assert principal_angle(X, st["X"]) < 1e-8
+    assert procrustes_err(X, st["X"]) < 1e-8

@@ -14,10 +14,12 @@ from tests import graphs_small as gs
 
 
 def principal_angle(A, B):
+    """Largest principal angle between span(A) and span(B), as
+    arcsin ||(I - Qa Qa^T) Qb||_2 (accurate for small angles)."""
     qa, _ = np.linalg.qr(A)
     qb, _ = np.linalg.qr(B)
-    s = np.linalg.svd(qa.T @ qb, compute_uv=False)
-    return float(np.arccos(np.clip(s.min(), -1, 1)))
+    r = qb - qa @ (qa.T @ qb)
+    return float(np.arcsin(min(1.0, np.linalg.norm(r, 2))))
 
 
 def rand_sym(n, spectrum, seed):
