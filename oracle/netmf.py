@@ -42,8 +42,8 @@ def lib():
         L.ora_sample_slots.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64,
                                        P, P, P, P, P, P, P]
         L.ora_sample_slots.restype = i64
-        L.ora_count_rows.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i32,
-                                     P, P, P, P, P, P]
+        L.ora_count_rows.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64, i64,
+                                     i32, P, P, P, P, P, P]
         L.ora_count_rows.restype = i32
         L.ora_free.argtypes = [P]
         L.ora_trunc_log.argtypes = [i64, i64, P, P, P, P, u64, u64, u64, P, P]
@@ -124,9 +124,10 @@ def sample_slots(g, params, e_begin: int = 0, e_end: int | None = None):
 
 
 def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
-              nthreads: int | None = None):
+              nthreads: int | None = None, e_begin: int = 0, e_end: int = -1):
     """Aggregated count matrix W (fixed point, 2^-16 units) restricted to rows
-    [row_lo, row_hi): returns (rowptr, col, W, attempted, accepted).  Equal
+    [row_lo, row_hi), from the samples of edges [e_begin, e_end) (all edges
+    by default): returns (rowptr, col, W, attempted, accepted).  Equal
     pairs are summed exactly in uint64 (section 5.2, sparse parallel hashing;
     here a sort of the sample triples)."""
     rp, col = _graph_arrays(g)
@@ -143,7 +144,8 @@ def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
     att = ctypes.c_uint64()
     acc = ctypes.c_uint64()
     rc = lib().ora_count_rows(g.n, _p(rp), _p(col), params["T"], _p(s), int(params["M"]),
-                              C, no_ds, int(params["seed"]), row_lo, row_hi, nthreads,
+                              C, no_ds, int(params["seed"]), row_lo, row_hi, e_begin, e_end,
+                              nthreads,
                               ctypes.byref(prp), ctypes.byref(pcol), ctypes.byref(pw),
                               ctypes.byref(nnz), ctypes.byref(att), ctypes.byref(acc))
     if rc == -1:

@@ -308,15 +308,16 @@ static int trip_cmp(const void *x, const void *y)
 }
 
 /*
- * Count CSR of the rows [row_lo, row_hi): *o_rowptr has row_hi-row_lo+1
+ * Count CSR of the rows [row_lo, row_hi) from the samples of the edges
+ * [e_begin, e_end) (e_end < 0: all edges): *o_rowptr has row_hi-row_lo+1
  * entries starting at 0, *o_col / *o_w have *o_nnz entries.  Buffers are
  * malloc'ed here and released with ora_free.  Also reports the number of
- * attempted and accepted samples over all edges.  Returns 0, or -1 on
+ * attempted and accepted samples of those edges.  Returns 0, or -1 on
  * allocation failure, -2 on a weight-sum overflow.
  */
 int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
                    const double *s, uint64_t M, double C, int no_ds, uint64_t seed,
-                   int64_t row_lo, int64_t row_hi, int nthreads,
+                   int64_t row_lo, int64_t row_hi, int64_t e_begin, int64_t e_end, int nthreads,
                    int64_t **o_rowptr, int32_t **o_col, uint64_t **o_w, int64_t *o_nnz,
                    uint64_t *o_attempted, uint64_t *o_accepted)
 {
@@ -329,13 +330,17 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
     plan_t pl;
     make_plan(T, s, M, m, &pl);
     if (nthreads < 1) nthreads = 1;
+    if (e_end < 0 || e_end > m) e_end = m;
+    if (e_begin < 0) e_begin = 0;
+    if (e_begin > e_end) e_begin = e_end;
     job_t *jobs = calloc((size_t)nthreads, sizeof(job_t));
     pthread_t *th = calloc((size_t)nthreads, sizeof(pthread_t));
     for (int t = 0; t < nthreads; ++t) {
         job_t *jb = &jobs[t];
         jb->g = &g; jb->pl = &pl; jb->seed = seed; jb->C = C; jb->no_ds = no_ds;
         jb->eu = eu; jb->ev = ev;
-        jb->e0 = m * t / nthreads; jb->e1 = m * (t + 1) / nthreads;
+        jb->e0 = e_begin + (e_end - e_begin) * t / nthreads;
+        jb->e1 = e_begin + (e_end - e_begin) * (t + 1) / nthreads;
         jb->row_lo = row_lo; jb->row_hi = row_hi;
         pthread_create(&th[t], NULL, job_run, jb);
     }

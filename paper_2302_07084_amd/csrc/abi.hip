@@ -231,6 +231,8 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
         LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)P));
         LNE_TRY(radix_sort(ctx, k0.as<uint64_t>(), v0.as<uint32_t>(), k1.as<uint64_t>(),
                            v1.as<uint32_t>(), P, 2 * pl.colbits, &which));
+        // the other ping-pong pair is free before the CSR is allocated
+        if (which) { k0.release(); v0.release(); } else { k1.release(); v1.release(); }
     }
     const uint64_t *keys = which ? k1.as<uint64_t>() : k0.as<uint64_t>();
     const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
