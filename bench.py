@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--report", choices=["precision"], default=None,
+                    help="precision: the FP32 and BF16-MFMA paths against the FP64 path")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -71,6 +73,10 @@ def main():
 
     import paper_2302_07084_amd as lne
     from synth import workload
+
+    if args.report == "precision":
+        precision_report(args.workload if args.workload != "large" else "precision")
+        return
 
     if args.calib_copy_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
@@ -174,6 +180,85 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def _principal_angle(A, B):
+    import numpy as np
+    qa, _ = np.linalg.qr(A)
+    qb, _ = np.linalg.qr(B)
+    r = qb - qa @ (qa.T @ qb)
+    return float(np.arcsin(min(1.0, np.linalg.norm(r, 2))))
+
+
+def _procrustes(X, Xref):
+    import numpy as np
+    U, _, Vt = np.linalg.svd(X.T @ Xref)
+    return float(np.linalg.norm(X @ (U @ Vt) - Xref) / np.linalg.norm(Xref))
+
+
+def precision_report(name):
+    """Runs the workload's sparsifier, fast randomized SVD and propagation in
+    FP64, FP32 and BF16 (dense rSVD steps on BF16 MFMA, FP64 Cholesky and
+    eigen-solves) and reports each result's error against the FP64 run."""
+    import numpy as np
+    import torch
+
+    import paper_2302_07084_amd as lne
+    from synth import workload
+
+    g, p = workload(name, device="cuda")
+    log(f"precision report on '{name}': n={g.n} m={g.m} M={p['M']} d={p['d']} q={p['q']}")
+    rp = torch.from_numpy(g.rowptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    ctx = lne.Context()
+    res = {}
+    for prec in ("f64", "f32", "bf16"):
+        pp = dict(p, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        counts, st = lne.sparsify(ctx, rp, col, pp)
+        M = lne.trunc_log(ctx, rp, col, pp, counts)
+        counts.free()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        U, S, V, X0 = lne.rsvd(ctx, M, pp)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        nnz = M.nnz
+        M.free()
+        X = lne.propagate(ctx, rp, col, pp, X0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        res[prec] = dict(U=U.double().cpu().numpy(), S=S.cpu().numpy(), X0=X0.double().cpu().numpy(),
+                         X=X.double().cpu().numpy(), t_sparsify=t1 - t0, t_rsvd=t2 - t1,
+                         t_propagate=t3 - t2, nnz=nnz, stats=st)
+        log(f"{prec}: sparsify {t1 - t0:.2f}s rsvd {t2 - t1:.2f}s propagate {t3 - t2:.2f}s nnz={nnz}")
+        del U, S, V, X0, X
+        torch.cuda.empty_cache()
+    ref = res["f64"]
+    S = ref["S"]
+    gaps = (S[:-1] - S[1:]) / S[0]
+    dprime = int(max([i + 1 for i in range(len(gaps)) if gaps[i] >= 1e-3] or [1]))
+    kp = p["d"] + p["oversample"]
+    out = {"report": "precision", "workload": name, "n": g.n, "m": g.m, "M": p["M"], "d": p["d"],
+           "q": p["q"], "oversample": p["oversample"], "d_prime": dprime,
+           "gap_at_d_prime": float(gaps[dprime - 1]), "results": {}}
+    for prec, u in (("f32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
+        r = res[prec]
+        bar = 100 * math.sqrt(kp) * u / max(float(gaps[dprime - 1]), 1e-12)
+        out["results"][prec] = {
+            "sigma_max_rel_err": float(np.max(np.abs(r["S"] - S) / S)),
+            "U_principal_angle_top_dprime": _principal_angle(r["U"][:, :dprime], ref["U"][:, :dprime]),
+            "X0_procrustes_rel_err": _procrustes(r["X0"], ref["X0"]),
+            "X_procrustes_rel_err": _procrustes(r["X"], ref["X"]),
+            "angle_bar": bar,
+            "seconds": {"sparsify_trunc_log": r["t_sparsify"], "rsvd": r["t_rsvd"],
+                        "propagate": r["t_propagate"]},
+        }
+    out["results"]["f64"] = {"seconds": {"sparsify_trunc_log": ref["t_sparsify"],
+                                         "rsvd": ref["t_rsvd"], "propagate": ref["t_propagate"]},
+                             "nnz": ref["nnz"], "stats": ref["stats"]}
     print(json.dumps(out), flush=True)
 
 

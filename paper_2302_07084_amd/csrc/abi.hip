@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <algorithm>
+#include <cstdlib>
 #include <limits>
 
 #include "common.hpp"
@@ -186,61 +188,154 @@ static double bessel_i(int n, double x) {
 }
 
 // ------------------------------------------------------------------- stages
-static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                                lne_csr *out, lne_stats *st) {
+// Pair-buffer budget in bytes: LNE_HBM_BUDGET_GB if set, else 70% of HBM.
+static double pair_budget(lne_ctx *ctx) {
+    const char *env = getenv("LNE_HBM_BUDGET_GB");
+    if (env && *env) return atof(env) * 1e9;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return 64e9;
+    (void)ctx;
+    return 0.7 * (double)tot;
+}
+
+// Device bytes one row range needs while it is aggregated: two (key, weight)
+// ping-pong pairs and, at worst, a count CSR entry per pair entry.
+static double range_bytes(uint64_t entries) { return 36.0 * (double)entries; }
+
+struct Sampler {
     SamplePlan pl;
-    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, pl));
-    const int64_t m = g->n_arcs / 2;
-    uint64_t accepted = 0;
-    unsigned long long attempted = 0;
-    uint32_t max_w = 0;
-    Buf k0(ctx), v0(ctx), k1(ctx), v1(ctx);
-    if (m > 0 && pl.S > 0) {
-        Buf eu(ctx), ev(ctx);
-        LNE_TRY(build_edges(ctx, g, eu, ev, m));
-        const int64_t threads = sample_threads(pl, m);
-        const int64_t nw = threads / 64;
-        Buf wc(ctx), wo(ctx), scal(ctx);
-        LNE_TRY(alloc(ctx, wc, sizeof(uint32_t) * (size_t)nw));
-        LNE_TRY(alloc(ctx, wo, sizeof(uint64_t) * (size_t)(nw + 1)));
-        LNE_TRY(alloc(ctx, scal, 16));
-        LNE_HIP(ctx, hipMemsetAsync(scal.p, 0, 16, ctx->stream));
-        unsigned long long *att_d = scal.as<unsigned long long>();
-        uint32_t *maxw_d = reinterpret_cast<uint32_t *>(scal.as<char>() + 8);
-        LNE_TRY(launch_sample_count(ctx, g, pl, eu.as<int32_t>(), ev.as<int32_t>(), m,
-                                    wc.as<uint32_t>(), nw, att_d, maxw_d));
-        LNE_TRY(scan_u32(ctx, wc.as<uint32_t>(), wo.as<uint64_t>(), nw));
-        LNE_HIP(ctx, hipMemcpyAsync(&accepted, wo.as<uint64_t>() + nw, 8, hipMemcpyDeviceToHost,
-                                    ctx->stream));
-        LNE_HIP(ctx, hipMemcpyAsync(&attempted, att_d, 8, hipMemcpyDeviceToHost, ctx->stream));
-        LNE_HIP(ctx, hipMemcpyAsync(&max_w, maxw_d, 4, hipMemcpyDeviceToHost, ctx->stream));
-        LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    Buf eu, ev, wc, wo;
+    int64_t m = 0, nw = 0;
+    uint64_t attempted = 0, accepted = 0;
+};
+
+static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
+                              int64_t hi, uint64_t *entries, bool stats) {
+    Buf scal(ctx);
+    LNE_TRY(alloc(ctx, scal, 16));
+    LNE_HIP(ctx, hipMemsetAsync(scal.p, 0, 16, ctx->stream));
+    unsigned long long *att_d = stats ? scal.as<unsigned long long>() : nullptr;
+    uint32_t *maxw_d = stats ? reinterpret_cast<uint32_t *>(scal.as<char>() + 8) : nullptr;
+    LNE_TRY(launch_sample_count(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), S.m, lo, hi,
+                                S.wc.as<uint32_t>(), S.nw, att_d, maxw_d));
+    LNE_TRY(scan_u32(ctx, S.wc.as<uint32_t>(), S.wo.as<uint64_t>(), S.nw));
+    uint64_t host[3] = {0, 0, 0};
+    LNE_HIP(ctx, hipMemcpyAsync(&host[0], S.wo.as<uint64_t>() + S.nw, 8, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    if (stats)
+        LNE_HIP(ctx, hipMemcpyAsync(&host[1], scal.p, 16, hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *entries = host[0];
+    if (stats) {
+        S.attempted = host[1];
+        S.accepted = host[0] / 2;
+        const uint32_t max_w = (uint32_t)host[2];
         if (max_w == 0xFFFFFFFFu)
             return fail(ctx, LNE_EUNSUPPORTED, "a per-sample weight exceeds 2^32 - 1");
-        const int64_t P = 2 * (int64_t)accepted;
-        LNE_TRY(alloc(ctx, k0, sizeof(uint64_t) * (size_t)(P > 0 ? P : 1)));
-        LNE_TRY(alloc(ctx, v0, sizeof(uint32_t) * (size_t)(P > 0 ? P : 1)));
-        if (P > 0)
-            LNE_TRY(launch_sample_emit(ctx, g, pl, eu.as<int32_t>(), ev.as<int32_t>(), m,
-                                       wo.as<uint64_t>(), k0.as<uint64_t>(), v0.as<uint32_t>()));
     }
-    const int64_t P = 2 * (int64_t)accepted;
+    return LNE_OK;
+}
+
+// Aggregates the pair entries of rows [lo, hi) (already counted into S.wo)
+// into a count CSR block with hi - lo rows.
+static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
+                                  int64_t hi, uint64_t entries, lne_csr *out) {
+    const int64_t P = (int64_t)entries;
+    Buf k0(ctx), v0(ctx), k1(ctx), v1(ctx);
+    LNE_TRY(alloc(ctx, k0, sizeof(uint64_t) * (size_t)(P > 0 ? P : 1)));
+    LNE_TRY(alloc(ctx, v0, sizeof(uint32_t) * (size_t)(P > 0 ? P : 1)));
+    if (P > 0)
+        LNE_TRY(launch_sample_emit(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), S.m, lo,
+                                   hi, S.wo.as<uint64_t>(), k0.as<uint64_t>(), v0.as<uint32_t>()));
     int which = 0;
     if (P > 1) {
+        int rowbits = 0;
+        while (((int64_t)1 << rowbits) < hi - lo) ++rowbits;
         LNE_TRY(alloc(ctx, k1, sizeof(uint64_t) * (size_t)P));
         LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)P));
         LNE_TRY(radix_sort(ctx, k0.as<uint64_t>(), v0.as<uint32_t>(), k1.as<uint64_t>(),
-                           v1.as<uint32_t>(), P, 2 * pl.colbits, &which));
+                           v1.as<uint32_t>(), P, rowbits + S.pl.colbits, &which));
         // the other ping-pong pair is free before the CSR is allocated
         if (which) { k0.release(); v0.release(); } else { k1.release(); v1.release(); }
     }
     const uint64_t *keys = which ? k1.as<uint64_t>() : k0.as<uint64_t>();
     const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
-    LNE_TRY(reduce_to_csr(ctx, keys, vals, P, g->n, pl.colbits, out));
+    return reduce_to_csr(ctx, keys, vals, P, hi - lo, S.pl.colbits, out);
+}
+
+// Runs the sparsifier and hands each row block of the count matrix, in row
+// order, to `sink(block, row_lo)`, which takes ownership of the block.  One
+// block covers all rows unless the pair buffers would exceed the budget; then
+// the rows are split into ranges of about equal arc count (and halved again
+// while a range is still too large), each range walking every sample again
+// and keeping the entries whose row falls inside it.
+template <class Sink>
+static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                                lne_stats *st, Sink &&sink) {
+    Sampler S;
+    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
+    S.m = g->n_arcs / 2;
+    uint64_t total = 0;
+    if (S.m > 0 && S.pl.S > 0) {
+        LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m));
+        S.nw = sample_threads(S.pl, S.m) / 64;
+        LNE_TRY(alloc(ctx, S.wc, sizeof(uint32_t) * (size_t)S.nw));
+        LNE_TRY(alloc(ctx, S.wo, sizeof(uint64_t) * (size_t)(S.nw + 1)));
+        LNE_TRY(count_range(ctx, g, S, 0, g->n, &total, true));
+    }
     if (st) {
-        st->attempted = attempted;
-        st->accepted = accepted;
-        st->nnz_counts = (uint64_t)out->nnz;
+        st->attempted = S.attempted;
+        st->accepted = S.accepted;
+        st->nnz_counts = 0;
+    }
+    const double budget = pair_budget(ctx);
+    if (total == 0 || range_bytes(total) <= budget) {
+        lne_csr blk;
+        std::memset(&blk, 0, sizeof(blk));
+        if (total == 0) {
+            LNE_TRY(reduce_to_csr(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits, &blk));
+        } else {
+            LNE_TRY(aggregate_range(ctx, g, S, 0, g->n, total, &blk));
+        }
+        if (st) st->nnz_counts = (uint64_t)blk.nnz;
+        return sink(blk, (int64_t)0);
+    }
+    // equal-arc row ranges from the graph offsets
+    const int64_t K = (int64_t)std::ceil(range_bytes(total) / budget * 1.25);
+    std::vector<int64_t> rp(g->n + 1);
+    LNE_HIP(ctx, hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int64_t) * (size_t)(g->n + 1),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<std::pair<int64_t, int64_t>> todo;
+    int64_t lo = 0;
+    for (int64_t k = 1; k <= K; ++k) {
+        const int64_t target = g->n_arcs * k / K;
+        int64_t hi = (int64_t)(std::lower_bound(rp.begin(), rp.end(), target) - rp.begin());
+        if (k == K) hi = g->n;
+        hi = std::max(hi, lo + 1);
+        hi = std::min(hi, g->n);
+        if (hi > lo) todo.push_back({lo, hi});
+        lo = hi;
+        if (lo >= g->n) break;
+    }
+    if (lo < g->n) todo.push_back({lo, g->n});
+    std::reverse(todo.begin(), todo.end());   // used as a stack, lowest rows on top
+    while (!todo.empty()) {
+        const auto rg = todo.back();
+        todo.pop_back();
+        uint64_t entries = 0;
+        LNE_TRY(count_range(ctx, g, S, rg.first, rg.second, &entries, false));
+        if (range_bytes(entries) > budget && rg.second - rg.first > 1) {
+            const int64_t mid = rg.first + (rg.second - rg.first) / 2;
+            todo.push_back({mid, rg.second});
+            todo.push_back({rg.first, mid});
+            continue;
+        }
+        lne_csr blk;
+        std::memset(&blk, 0, sizeof(blk));
+        LNE_TRY(aggregate_range(ctx, g, S, rg.first, rg.second, entries, &blk));
+        if (st) st->nnz_counts += (uint64_t)blk.nnz;
+        LNE_TRY(sink(blk, rg.first));
     }
     return LNE_OK;
 }
@@ -551,7 +646,15 @@ lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p, l
     LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
     std::memset(out, 0, sizeof(*out));
     LNE_TRY(validate_graph_device(ctx, g));
-    return sparsify_impl(ctx, g, p, out, st);
+    std::vector<lne_csr> blocks;
+    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
+        blocks.push_back(blk);
+        return LNE_OK;
+    };
+    lne_status s = sparsify_impl(ctx, g, p, st, sink);
+    if (s == LNE_OK) s = concat_rows(ctx, blocks, g->n, out);
+    for (auto &b : blocks) lne_csr_free(ctx, &b);
+    return s;
 }
 
 lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
@@ -564,7 +667,7 @@ lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
     if (p->precision < LNE_F64 || p->precision > LNE_BF16)
         return fail(ctx, LNE_EINVAL, "trunc_log: bad precision");
     std::memset(out, 0, sizeof(*out));
-    return trunc_log_csr(ctx, g, p, counts, p->precision == LNE_F64 ? LNE_F64 : LNE_F32, out);
+    return trunc_log_csr(ctx, g, p, counts, 0, p->precision == LNE_F64 ? LNE_F64 : LNE_F32, out);
 }
 
 lne_status lne_csr_copy(lne_ctx *ctx, const lne_csr *m, int64_t *row_ptr, int32_t *col,
@@ -663,14 +766,24 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
     if (!X) return fail(ctx, LNE_EINVAL, "embed: X is NULL");
     if (st) std::memset(st, 0, sizeof(*st));
-    lne_csr counts, M;
-    std::memset(&counts, 0, sizeof(counts));
+    // each count block goes through trunc_log as soon as it exists, so only
+    // one block of counts is alive at a time
+    const int32_t vt = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    std::vector<lne_csr> mblocks;
+    auto sink = [&](lne_csr &blk, int64_t row_lo) -> lne_status {
+        lne_csr mb;
+        std::memset(&mb, 0, sizeof(mb));
+        lne_status r = trunc_log_csr(ctx, g, p, &blk, row_lo, vt, &mb);
+        lne_csr_free(ctx, &blk);
+        if (r == LNE_OK) mblocks.push_back(mb);
+        return r;
+    };
+    lne_csr M;
     std::memset(&M, 0, sizeof(M));
     LNE_TRY(validate_graph_device(ctx, g));
-    lne_status s = sparsify_impl(ctx, g, p, &counts, st);
-    if (s == LNE_OK)
-        s = trunc_log_csr(ctx, g, p, &counts, p->precision == LNE_F64 ? LNE_F64 : LNE_F32, &M);
-    lne_csr_free(ctx, &counts);
+    lne_status s = sparsify_impl(ctx, g, p, st, sink);
+    if (s == LNE_OK) s = concat_rows(ctx, mblocks, g->n, &M);
+    for (auto &b : mblocks) lne_csr_free(ctx, &b);
     if (s != LNE_OK) {
         lne_csr_free(ctx, &M);
         return s;

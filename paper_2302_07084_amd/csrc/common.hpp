@@ -112,14 +112,17 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
                                const int32_t *eu, const int32_t *ev, int64_t e_begin,
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
                                uint8_t *r);
-// Per-wave accepted counts (count pass) and pair emission (scatter pass).
+// Per-wave pair-entry counts (count pass) and pair emission (emit pass) for
+// the rows [row_lo, row_hi); keys are relative to row_lo.  attempted and
+// max_w may be NULL.
 lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
-                               const int32_t *eu, const int32_t *ev, int64_t m,
-                               uint32_t *wave_cnt, int64_t n_waves,
+                               const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
+                               int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,
                                unsigned long long *attempted, uint32_t *max_w);
 lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
-                              const int32_t *eu, const int32_t *ev, int64_t m,
-                              const uint64_t *wave_off, uint64_t *keys, uint32_t *vals);
+                              const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
+                              int64_t row_hi, const uint64_t *wave_off, uint64_t *keys,
+                              uint32_t *vals);
 int64_t sample_threads(const SamplePlan &pl, int64_t m);
 lne_status launch_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr, int64_t count,
                          uint32_t *out);
@@ -136,8 +139,13 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
                          int64_t n_items, int64_t n_rows, int colbits, lne_csr *out);
 
 // ---- trunc_log (k_trunclog.hip) ---------------------------------------------
+// counts covers the rows [row_lo, row_lo + counts->n_rows) of the graph.
 lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                         const lne_csr *counts, int32_t val_type, lne_csr *out);
+                         const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out);
+// Stacks row blocks (block b holds rows [lo_b, lo_b + n_rows_b), in order)
+// into one CSR of n_rows rows; the blocks are released.
+lne_status concat_rows(lne_ctx *ctx, std::vector<lne_csr> &blocks, int64_t n_rows,
+                       lne_csr *out);
 
 // ---- SpMM (k_spmm.hip) -------------------------------------------------------
 lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void *Y,

@@ -156,9 +156,14 @@ __global__ void k_fill_edges(const int64_t *__restrict__ rp, const int32_t *__re
     }
 }
 
+// Count pass: pair entries each wave will emit.  Without a row filter every
+// accepted sample gives two entries and no walk is needed; with a filter
+// [row_lo, row_hi) the walk decides which orientations fall inside.
+template <bool FILTER>
 __global__ void __launch_bounds__(kBlock)
-k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ eu,
-               const int32_t *__restrict__ ev, int64_t m, uint32_t *__restrict__ wave_cnt,
+k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+               const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
+               int64_t row_lo, int64_t row_hi, uint32_t *__restrict__ wave_cnt,
                unsigned long long *__restrict__ attempted, uint32_t *__restrict__ max_w) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t e = t / pl.chunks;
@@ -172,12 +177,23 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
         const uint64_t ne = draw_ne(pl, e);
         const uint64_t j0 = (uint64_t)c * pl.J;
         const uint64_t j1 = min(j0 + (uint64_t)pl.J, ne);
+        uint32_t acc = 0;
         for (uint64_t j = j0; j < j1; ++j) {
             const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
-            cnt += (cn.all || (uint64_t)b0.x < cn.tau) ? 1u : 0u;
+            const bool ok = cn.all || (uint64_t)b0.x < cn.tau;
+            if (!ok) continue;
+            ++acc;
+            if (FILTER) {
+                int32_t a = u, b = v;
+                walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+                cnt += (a >= row_lo && a < row_hi) ? 1u : 0u;
+                cnt += (b >= row_lo && b < row_hi) ? 1u : 0u;
+            } else {
+                cnt += 2;
+            }
         }
         att = j1 > j0 ? j1 - j0 : 0;
-        wmax = cnt ? cn.w : 0;
+        wmax = acc ? cn.w : 0;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -188,16 +204,19 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
     }
     if ((threadIdx.x & 63) == 0) {
         wave_cnt[t >> 6] = cnt;
-        if (att) atomicAdd(attempted, (unsigned long long)att);
-        if (wmax) atomicMax(max_w, wmax > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wmax);
+        if (attempted && att) atomicAdd(attempted, (unsigned long long)att);
+        if (max_w && wmax) atomicMax(max_w, wmax > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wmax);
     }
 }
 
+// Emit pass: every wave writes its entries contiguously from the scanned
+// per-wave count; the order inside a wave is (slot, lane, orientation).
+// Keys are ((row - row_lo) << colbits) | col.
 __global__ void __launch_bounds__(kBlock)
 k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
               const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
-              const uint64_t *__restrict__ wave_off, uint64_t *__restrict__ keys,
-              uint32_t *__restrict__ vals) {
+              int64_t row_lo, int64_t row_hi, const uint64_t *__restrict__ wave_off,
+              uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t e = t / pl.chunks;
     const int64_t c = t - e * pl.chunks;
@@ -217,22 +236,29 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
     const uint32_t w = (uint32_t)cn.w;
     for (int64_t jj = 0; jj < pl.J; ++jj) {
         const uint64_t j = j0 + (uint64_t)jj;
-        bool acc = false;
+        bool ina = false, inb = false;
         int32_t a = u, b = v;
         if (e < m && j < ne) {
             const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
-            acc = cn.all || (uint64_t)b0.x < cn.tau;
-            if (acc) walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+            if (cn.all || (uint64_t)b0.x < cn.tau) {
+                walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+                ina = a >= row_lo && a < row_hi;
+                inb = b >= row_lo && b < row_hi;
+            }
         }
-        const uint64_t mask = __ballot(acc);
-        if (acc) {
-            const uint64_t idx = pos + (uint64_t)__popcll(mask & lt);
-            keys[2 * idx] = ((uint64_t)(uint32_t)a << pl.colbits) | (uint32_t)b;
-            keys[2 * idx + 1] = ((uint64_t)(uint32_t)b << pl.colbits) | (uint32_t)a;
-            vals[2 * idx] = w;
-            vals[2 * idx + 1] = w;
+        const uint32_t cnt = (ina ? 1u : 0u) + (inb ? 1u : 0u);
+        const uint64_t m0 = __ballot(cnt & 1u), m1 = __ballot(cnt & 2u);
+        uint64_t idx = pos + (uint64_t)__popcll(m0 & lt) + 2ull * (uint64_t)__popcll(m1 & lt);
+        if (ina) {
+            keys[idx] = ((uint64_t)(uint32_t)(a - row_lo) << pl.colbits) | (uint32_t)b;
+            vals[idx] = w;
+            ++idx;
         }
-        pos += (uint64_t)__popcll(mask);
+        if (inb) {
+            keys[idx] = ((uint64_t)(uint32_t)(b - row_lo) << pl.colbits) | (uint32_t)a;
+            vals[idx] = w;
+        }
+        pos += (uint64_t)__popcll(m0) + 2ull * (uint64_t)__popcll(m1);
     }
 }
 
@@ -365,27 +391,33 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
 }
 
 lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
-                               const int32_t *eu, const int32_t *ev, int64_t m,
-                               uint32_t *wave_cnt, int64_t n_waves,
+                               const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
+                               int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,
                                unsigned long long *attempted, uint32_t *max_w) {
     const int64_t threads = sample_threads(pl, m);
     if (threads / 64 != n_waves) return fail(ctx, LNE_EINVAL, "sampler wave count mismatch");
+    const bool filter = !(row_lo <= 0 && row_hi >= g->n);
     {
-        Launch L(ctx, "sample_count");
-        k_sample_count<<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
-            pl, g->row_ptr, eu, ev, m, wave_cnt, attempted, max_w);
+        Launch L(ctx, filter ? "sample_count_range" : "sample_count");
+        if (filter)
+            k_sample_count<true><<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, attempted, max_w);
+        else
+            k_sample_count<false><<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, attempted, max_w);
     }
     return check_launch(ctx, "sample_count");
 }
 
 lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
-                              const int32_t *eu, const int32_t *ev, int64_t m,
-                              const uint64_t *wave_off, uint64_t *keys, uint32_t *vals) {
+                              const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
+                              int64_t row_hi, const uint64_t *wave_off, uint64_t *keys,
+                              uint32_t *vals) {
     const int64_t threads = sample_threads(pl, m);
     {
         Launch L(ctx, "sample_emit");
         k_sample_emit<<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
-            pl, g->row_ptr, g->col, eu, ev, m, wave_off, keys, vals);
+            pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_off, keys, vals);
     }
     return check_launch(ctx, "sample_emit");
 }

@@ -25,13 +25,13 @@ __device__ __forceinline__ bool keep_entry(const TLConst &c, uint64_t W, uint64_
     return lh > rh || (lh == rh && ll > rl);
 }
 
-__global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t n,
+__global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t row_lo, int64_t n,
                            const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const uint64_t *__restrict__ W, uint32_t *__restrict__ kept) {
     const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (a >= n) return;
-    const uint64_t da = (uint64_t)(grp[a + 1] - grp[a]);
+    const uint64_t da = (uint64_t)(grp[row_lo + a + 1] - grp[row_lo + a]);
     uint32_t cnt = 0;
     for (int64_t i = rp[a] + lane; i < rp[a + 1]; i += 64) {
         const int32_t b = col[i];
@@ -43,7 +43,7 @@ __global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t n
 }
 
 template <class VT>
-__global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t n,
+__global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t row_lo, int64_t n,
                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                           const uint64_t *__restrict__ W, const int64_t *__restrict__ orp,
                           int32_t *__restrict__ ocol, VT *__restrict__ oval) {
@@ -51,7 +51,7 @@ __global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t n,
     const int lane = threadIdx.x & 63;
     if (a >= n) return;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t da = (uint64_t)(grp[a + 1] - grp[a]);
+    const uint64_t da = (uint64_t)(grp[row_lo + a + 1] - grp[row_lo + a]);
     int64_t pos = orp[a];
     const int64_t beg = rp[a], end = rp[a + 1];
     for (int64_t i0 = beg; i0 < end; i0 += 64) {
@@ -76,10 +76,68 @@ __global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t n,
     }
 }
 
+__global__ void k_shift_rows(const int64_t *__restrict__ rp, int64_t rows, int64_t row_lo,
+                             int64_t off, int64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows) out[row_lo + i] = rp[i] + off;
+}
+
 }  // namespace
 
+lne_status concat_rows(lne_ctx *ctx, std::vector<lne_csr> &blocks, int64_t n_rows,
+                       lne_csr *out) {
+    if (blocks.size() == 1 && blocks[0].n_rows == n_rows) {
+        *out = blocks[0];
+        out->n_cols = n_rows;
+        blocks.clear();
+        return LNE_OK;
+    }
+    int64_t nnz = 0;
+    for (auto &b : blocks) nnz += b.nnz;
+    const int32_t vt = blocks.empty() ? LNE_U64 : blocks[0].val_type;
+    const size_t es = dtype_size(vt);
+    Buf rp(ctx), cc(ctx), vv(ctx);
+    LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)(n_rows + 1)));
+    LNE_TRY(alloc(ctx, cc, sizeof(int32_t) * (size_t)(nnz ? nnz : 1)));
+    LNE_TRY(alloc(ctx, vv, es * (size_t)(nnz ? nnz : 1)));
+    int64_t off = 0, lo = 0;
+    for (auto &b : blocks) {
+        if (b.n_rows > 0) {
+            Launch L(ctx, "concat_rows");
+            k_shift_rows<<<grid_of(b.n_rows, 256), 256, 0, ctx->stream>>>(b.row_ptr, b.n_rows, lo,
+                                                                          off, rp.as<int64_t>());
+        }
+        LNE_TRY(check_launch(ctx, "concat_rows"));
+        if (b.nnz > 0) {
+            LNE_HIP(ctx, hipMemcpyAsync(cc.as<int32_t>() + off, b.col, sizeof(int32_t) * b.nnz,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+            LNE_HIP(ctx, hipMemcpyAsync(vv.as<char>() + es * off, b.val, es * b.nnz,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        off += b.nnz;
+        lo += b.n_rows;
+        dev_free(ctx, b.row_ptr);
+        dev_free(ctx, b.col);
+        dev_free(ctx, b.val);
+    }
+    blocks.clear();
+    if (lo != n_rows) return fail(ctx, LNE_EINVAL, "concat_rows: blocks cover %lld of %lld rows",
+                                  (long long)lo, (long long)n_rows);
+    LNE_HIP(ctx, hipMemcpyAsync(rp.as<int64_t>() + n_rows, &off, sizeof(int64_t),
+                                hipMemcpyHostToDevice, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    out->n_rows = n_rows;
+    out->n_cols = n_rows;
+    out->nnz = nnz;
+    out->row_ptr = (int64_t *)rp.detach();
+    out->col = (int32_t *)cc.detach();
+    out->val = vv.detach();
+    out->val_type = vt;
+    return LNE_OK;
+}
+
 lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                         const lne_csr *counts, int32_t val_type, lne_csr *out) {
+                         const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out) {
     const int64_t n = counts->n_rows;
     TLConst c;
     const uint64_t vol = (uint64_t)g->n_arcs;
@@ -93,7 +151,7 @@ lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
     const unsigned grid = grid_of(n * 64, 256);
     if (n > 0) {
         Launch L(ctx, "trunc_log_count");
-        k_tl_count<<<grid, 256, 0, ctx->stream>>>(c, g->row_ptr, n, counts->row_ptr,
+        k_tl_count<<<grid, 256, 0, ctx->stream>>>(c, g->row_ptr, row_lo, n, counts->row_ptr,
                                                   counts->col, (const uint64_t *)counts->val,
                                                   kept.as<uint32_t>());
     }
@@ -110,11 +168,11 @@ lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
         Launch L(ctx, "trunc_log_fill");
         if (val_type == LNE_F64)
             k_tl_fill<double><<<grid, 256, 0, ctx->stream>>>(
-                c, g->row_ptr, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
+                c, g->row_ptr, row_lo, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
                 rp.as<int64_t>(), cc.as<int32_t>(), vv.as<double>());
         else
             k_tl_fill<float><<<grid, 256, 0, ctx->stream>>>(
-                c, g->row_ptr, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
+                c, g->row_ptr, row_lo, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
                 rp.as<int64_t>(), cc.as<int32_t>(), vv.as<float>());
     }
     LNE_TRY(check_launch(ctx, "trunc_log_fill"));

@@ -119,3 +119,22 @@ def test_trunc_log_strict_boundary(lne, ctx):
     counts, _ = lne.sparsify(ctx, rp, col, p)
     M = lne.trunc_log(ctx, rp, col, p, counts)
     assert counts.nnz == 32 and M.nnz == 0
+
+
+def test_row_range_passes_match_single_pass(lne, ctx, monkeypatch):
+    """A pair-buffer budget far below the need splits the rows into ranges
+    (each range re-walks every sample); the result is identical."""
+    g, p = workload("tiny")
+    rp, col = to_dev(g)
+    ref, st_ref = lne.sparsify(ctx, rp, col, p)
+    R0, C0, W0 = (x.cpu().numpy() for x in ref.to_torch())
+    Xref, _ = lne.embed(ctx, rp, col, p)
+    monkeypatch.setenv("LNE_HBM_BUDGET_GB", "0.05")
+    csr, st = lne.sparsify(ctx, rp, col, p)
+    R, C, W = (x.cpu().numpy() for x in csr.to_torch())
+    np.testing.assert_array_equal(R, R0)
+    np.testing.assert_array_equal(C, C0)
+    np.testing.assert_array_equal(W, W0)
+    assert st == st_ref
+    X, _ = lne.embed(ctx, rp, col, p)
+    assert bool((X == Xref).all())
