@@ -247,6 +247,52 @@ lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
 lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void *X,
                      lne_stats *st);
 
+/* ---- hyperparameter search: surrogate network and downstream scorer ------ */
+/* Section 4.4 searches s_r, M, q, k, theta and mu against the downstream
+ * score.  The surrogate is an MLP in_dim -> hidden -> hidden -> 1 with GELU
+ * activations in FP32 that learns (hyperparameters, graph statistics) ->
+ * score from trials of the plain method and ranks candidate trials; the plain
+ * method (lne_embed + lne_score_micro_f1) scores every proposal.
+ * Parameters are one flat FP32 device array: W1 (in_dim x hidden, row-major),
+ * b1 (hidden), W2 (hidden x hidden), b2 (hidden), W3 (hidden), b3 (1). */
+
+/* Number of parameters; 0 on invalid dimensions.  Host only. */
+int64_t lne_mlp_param_count(int32_t in_dim, int32_t hidden);
+
+/* Glorot-uniform weights (Philox words, key = seed), zero biases.
+ * Errors: EINVAL. */
+lne_status lne_mlp_init(lne_ctx *ctx, int32_t in_dim, int32_t hidden, uint64_t seed,
+                        float *params);
+
+/* y (batch) = MLP(X), X: device batch x in_dim row-major.  Errors: EINVAL, ENOMEM. */
+lne_status lne_mlp_forward(lne_ctx *ctx, int32_t in_dim, int32_t hidden, const float *params,
+                           const float *X, int64_t batch, float *y);
+
+/* Gradient of the mean squared error mean_b (MLP(X)_b - target_b)^2 with
+ * respect to every parameter (grad: device, same layout as params); loss:
+ * device scalar or NULL.  Errors: EINVAL, ENOMEM. */
+lne_status lne_mlp_grad(lne_ctx *ctx, int32_t in_dim, int32_t hidden, const float *params,
+                        const float *X, const float *target, int64_t batch, float *grad,
+                        float *loss);
+
+/* One Adam step (Kingma & Ba) on count parameters with bias correction for
+ * step >= 1: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  Errors: EINVAL. */
+lne_status lne_mlp_adam(lne_ctx *ctx, int64_t count, float *params, const float *grad, float *m,
+                        float *v, int64_t step, float lr, float beta1, float beta2, float eps);
+
+/* Downstream score of an embedding (the node-classification protocol of the
+ * evaluation section): one-vs-rest L2-regularised logistic regression on the
+ * standardised rows X[train] (full-batch Adam, `epochs` steps, rate lr, L2
+ * weight l2), then each test vertex predicts its top-k labels with k its true
+ * label count; *f1 (host) = micro-F1 over the test vertices.
+ * X: device n x d FP32; labels: device n x n_labels uint8 (0/1); train, test:
+ * device int32 row indices.  Synchronises the stream.  Errors: EINVAL, ENOMEM. */
+lne_status lne_score_micro_f1(lne_ctx *ctx, const float *X, int64_t n, int32_t d,
+                              const uint8_t *labels, int32_t n_labels, const int32_t *train,
+                              int64_t n_train, const int32_t *test, int64_t n_test,
+                              int32_t epochs, float lr, float l2, double *f1);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,14 @@ SIGNATURES = [
     ("lne_rsvd", _I32, [_P, _P, _P, _P, _P, _P, _P]),
     ("lne_propagate", _I32, [_P, _P, _P, _P, _P]),
     ("lne_embed", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_mlp_param_count", _I64, [_I32, _I32]),
+    ("lne_mlp_init", _I32, [_P, _I32, _I32, _U64, _P]),
+    ("lne_mlp_forward", _I32, [_P, _I32, _I32, _P, _P, _I64, _P]),
+    ("lne_mlp_grad", _I32, [_P, _I32, _I32, _P, _P, _P, _I64, _P, _P]),
+    ("lne_mlp_adam", _I32, [_P, _I64, _P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, ctypes.c_float]),
+    ("lne_score_micro_f1", _I32, [_P, _P, _I64, _I32, _P, _I32, _P, _I64, _P, _I64, _I32,
+                                  ctypes.c_float, ctypes.c_float, _P]),
 ]
 
 _lib = None
@@ -410,3 +418,58 @@ def embed(ctx: Context, rowptr, col, params: dict, out=None):
     ctx.check(ctx.L.lne_embed(ctx.h, ctypes.byref(g), ctypes.byref(p), X.data_ptr(),
                               ctypes.byref(st)), "embed")
     return X, st.as_dict()
+
+
+# ---- surrogate network and scorer ------------------------------------------
+def mlp_param_count(in_dim: int, hidden: int) -> int:
+    return int(load().lne_mlp_param_count(in_dim, hidden))
+
+
+def mlp_init(ctx: Context, in_dim: int, hidden: int, seed: int):
+    import torch
+    p = torch.empty(mlp_param_count(in_dim, hidden), dtype=torch.float32, device=ctx.device)
+    ctx.check(ctx.L.lne_mlp_init(ctx.h, in_dim, hidden, seed, p.data_ptr()), "mlp_init")
+    return p
+
+
+def mlp_forward(ctx: Context, in_dim: int, hidden: int, params, X):
+    import torch
+    X = X.contiguous()
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    ctx.check(ctx.L.lne_mlp_forward(ctx.h, in_dim, hidden, params.data_ptr(), X.data_ptr(),
+                                    X.shape[0], y.data_ptr()), "mlp_forward")
+    return y
+
+
+def mlp_grad(ctx: Context, in_dim: int, hidden: int, params, X, target):
+    import torch
+    X = X.contiguous()
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    ctx.check(ctx.L.lne_mlp_grad(ctx.h, in_dim, hidden, params.data_ptr(), X.data_ptr(),
+                                 target.contiguous().data_ptr(), X.shape[0], g.data_ptr(),
+                                 loss.data_ptr()), "mlp_grad")
+    return g, loss
+
+
+def mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999,
+             eps=1e-8):
+    ctx.check(ctx.L.lne_mlp_adam(ctx.h, params.numel(), params.data_ptr(), grad.data_ptr(),
+                                 m.data_ptr(), v.data_ptr(), step, lr, beta1, beta2, eps),
+              "mlp_adam")
+
+
+def score_micro_f1(ctx: Context, X, labels, train, test, epochs=300, lr=0.05, l2=None):
+    """micro-F1 of one-vs-rest logistic regression trained on rows `train`."""
+    import torch
+    X = X.float().contiguous()
+    n, d = X.shape
+    L = labels.shape[1]
+    l2 = (1.0 / len(train)) if l2 is None else l2
+    f1 = ctypes.c_double()
+    ctx.check(ctx.L.lne_score_micro_f1(ctx.h, X.data_ptr(), n, d,
+                                       labels.to(torch.uint8).contiguous().data_ptr(), L,
+                                       train.to(torch.int32).contiguous().data_ptr(), len(train),
+                                       test.to(torch.int32).contiguous().data_ptr(), len(test),
+                                       epochs, lr, l2, ctypes.byref(f1)), "score_micro_f1")
+    return f1.value

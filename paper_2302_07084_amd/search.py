@@ -1,0 +1,190 @@
+"""Hyperparameter search driven by a learned surrogate (section 4.4).
+
+The paper searches s_1..s_T, M, q and the propagation parameters (k, theta,
+mu) with FLAML against the downstream score.  Here a small MLP, trained on
+(hyperparameters, graph statistics) -> micro-F1 pairs produced by the plain
+method, ranks candidate trials; the plain method (lne_embed followed by
+lne_score_micro_f1, both on the GPU) scores every trial that is actually
+proposed, so the surrogate only decides the order in which trials are tried
+and the plain method stays the judge and the fallback (a random proposal
+stream).  This module only orchestrates: the embedding, the scorer and the
+network's forward, backward and Adam steps are library kernels.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import (Context, embed, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
+               score_micro_f1)
+
+T_MAX = 10
+N_STATS = 8
+IN_DIM = T_MAX + 3 + N_STATS      # s_1..s_10, k, theta, mu, graph statistics
+HIDDEN = 256
+
+
+@dataclasses.dataclass
+class Trial:
+    s: np.ndarray      # T weights, sum 1
+    k: int             # propagation order, 1..20
+    theta: float       # [0, 1]
+    mu: float          # [0, 0.5]
+
+    def vector(self) -> np.ndarray:
+        s = np.zeros(T_MAX)
+        s[:len(self.s)] = self.s
+        return np.concatenate([s, [self.k / 20.0, self.theta, 2.0 * self.mu]])
+
+
+def sample_trials(rng: np.random.Generator, count: int, T: int = T_MAX):
+    """The search space of the batched configuration: s ~ Dirichlet(1),
+    k ~ U{1..20}, theta ~ U[0, 1], mu ~ U[0, 0.5]."""
+    return [Trial(rng.dirichlet(np.ones(T)), int(rng.integers(1, 21)), float(rng.random()),
+                  float(0.5 * rng.random())) for _ in range(count)]
+
+
+def graph_stats(g, seed: int = 0) -> np.ndarray:
+    """Eight descriptors of a graph: log n, log m, log mean degree, degree
+    coefficient of variation, log max degree, tail exponent (Hill estimator
+    above the median degree), wedge-sampled clustering coefficient and the
+    spectral gap 1 - lambda_2 of D^-1/2 A D^-1/2."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    deg = np.diff(g.rowptr).astype(np.float64)
+    n, m = g.n, g.m
+    xmin = max(1.0, float(np.median(deg)))
+    tail = deg[deg >= xmin]
+    alpha = 1.0 + len(tail) / max(np.sum(np.log(tail / (xmin - 0.5))), 1e-9)
+    rng = np.random.default_rng(seed)
+    cand = np.flatnonzero(deg >= 2)
+    closed = 0
+    trials = 2000
+    for _ in range(trials):
+        v = cand[rng.integers(len(cand))]
+        nb = g.col[g.rowptr[v]:g.rowptr[v + 1]]
+        a, b = rng.choice(nb, 2, replace=False)
+        row = g.col[g.rowptr[a]:g.rowptr[a + 1]]
+        j = np.searchsorted(row, b)
+        closed += int(j < len(row) and row[j] == b)
+    A = sp.csr_matrix((np.ones(len(g.col)), g.col, g.rowptr), shape=(n, n))
+    dm = sp.diags(np.where(deg > 0, deg ** -0.5, 0.0))
+    N = dm @ A @ dm
+    lam = sla.eigsh(N, k=2, which="LA", return_eigenvectors=False, tol=1e-4,
+                    v0=np.ones(n) / math.sqrt(n))
+    gap = 1.0 - float(np.sort(lam)[0])
+    return np.array([math.log(n), math.log(max(m, 1)), math.log(deg.mean()),
+                     deg.std() / deg.mean(), math.log(deg.max()), alpha, closed / trials, gap])
+
+
+class Surrogate:
+    """Device-resident MLP surrogate: features -> predicted micro-F1."""
+
+    def __init__(self, ctx: Context, seed: int = 0, hidden: int = HIDDEN):
+        import torch
+        self.ctx, self.hidden = ctx, hidden
+        self.p = mlp_init(ctx, IN_DIM, hidden, seed)
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.step = 0
+        self.mu = np.zeros(IN_DIM)
+        self.sd = np.ones(IN_DIM)
+        self.F = np.zeros((0, IN_DIM))
+        self.y = np.zeros(0)
+
+    def add(self, F: np.ndarray, y):
+        """Appends observed (features, score) pairs to the training set."""
+        self.F = np.concatenate([self.F, F])
+        self.y = np.concatenate([self.y, np.asarray(y, np.float64)])
+
+    def set_scaler(self, F: np.ndarray):
+        self.mu = F.mean(0)
+        self.sd = np.where(F.std(0) > 1e-12, F.std(0), 1.0)
+
+    def _x(self, F):
+        import torch
+        return torch.from_numpy(((F - self.mu) / self.sd).astype(np.float32)).to(self.ctx.device)
+
+    def fit(self, epochs: int = 400, lr: float = 1e-3):
+        """Full-batch Adam on every pair seen so far (library kernels)."""
+        import torch
+        X = self._x(self.F)
+        t = torch.from_numpy(np.asarray(self.y, np.float32)).to(self.ctx.device)
+        losses = []
+        for _ in range(epochs):
+            g, loss = mlp_grad(self.ctx, IN_DIM, self.hidden, self.p, X, t)
+            self.step += 1
+            mlp_adam(self.ctx, self.p, g, self.m, self.v, self.step, lr)
+            losses.append(loss)
+        return float(losses[-1].item()), float(losses[0].item())
+
+    def predict(self, F: np.ndarray) -> np.ndarray:
+        return mlp_forward(self.ctx, IN_DIM, self.hidden, self.p, self._x(F)).cpu().numpy()
+
+
+@dataclasses.dataclass
+class Task:
+    """A labelled graph on the device with the fixed part of the parameters."""
+    g: object
+    rp: object
+    col: object
+    labels: object
+    base: dict
+    stats: np.ndarray
+    splits: list
+
+    @staticmethod
+    def make(g, base: dict, train_ratio: float = 0.1, n_splits: int = 1, seed: int = 0):
+        import torch
+        rng = np.random.default_rng(seed)
+        splits = []
+        for _ in range(n_splits):
+            perm = rng.permutation(g.n)
+            ntr = max(1, int(round(train_ratio * g.n)))
+            splits.append((torch.from_numpy(np.sort(perm[:ntr]).astype(np.int32)).cuda(),
+                           torch.from_numpy(np.sort(perm[ntr:]).astype(np.int32)).cuda()))
+        return Task(g, torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.col).cuda(),
+                    torch.from_numpy(g.labels.astype(np.uint8)).cuda(), dict(base),
+                    graph_stats(g, seed), splits)
+
+
+def evaluate(ctx: Context, task: Task, trial: Trial) -> float:
+    """The plain method on one trial: embedding, then micro-F1 averaged over
+    the task's splits."""
+    p = dict(task.base, s=trial.s, T=len(trial.s), cheb_k=trial.k, theta=trial.theta, mu=trial.mu)
+    X, _ = embed(ctx, task.rp, task.col, p)
+    return float(np.mean([score_micro_f1(ctx, X, task.labels, tr, te) for tr, te in task.splits]))
+
+
+def features(task: Task, trials) -> np.ndarray:
+    return np.stack([np.concatenate([t.vector(), task.stats]) for t in trials])
+
+
+def random_search(ctx, task, budget, rng):
+    trials = sample_trials(rng, budget)
+    return trials, [evaluate(ctx, task, t) for t in trials]
+
+
+def surrogate_search(ctx, task, sur: Surrogate, budget, rng, pool: int = 4096,
+                     explore: float = 0.25, rounds: int = 4):
+    """Proposes `budget` trials in `rounds` rounds: each round ranks a fresh
+    pool of random candidates by the surrogate's prediction and takes the best
+    (plus a random share for exploration); every proposal is scored by the
+    plain method and the surrogate is refitted on what it has seen."""
+    tried, scores = [], []
+    per = max(1, budget // rounds)
+    while len(tried) < budget:
+        n = min(per, budget - len(tried))
+        cand = sample_trials(rng, pool)
+        pred = sur.predict(features(task, cand))
+        n_exp = int(round(explore * n))
+        best = [cand[i] for i in np.argsort(-pred)[:n - n_exp]]
+        pick = best + sample_trials(rng, n_exp)
+        for t in pick:
+            tried.append(t)
+            scores.append(evaluate(ctx, task, t))
+        sur.add(features(task, pick), scores[-len(pick):])
+        sur.fit(epochs=100)
+    return tried, scores
