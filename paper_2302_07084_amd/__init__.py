@@ -444,11 +444,12 @@ def mlp_forward(ctx: Context, in_dim: int, hidden: int, params, X):
 def mlp_grad(ctx: Context, in_dim: int, hidden: int, params, X, target):
     import torch
     X = X.contiguous()
+    t = target.contiguous()
     g = torch.empty_like(params)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
     ctx.check(ctx.L.lne_mlp_grad(ctx.h, in_dim, hidden, params.data_ptr(), X.data_ptr(),
-                                 target.contiguous().data_ptr(), X.shape[0], g.data_ptr(),
-                                 loss.data_ptr()), "mlp_grad")
+                                 t.data_ptr(), X.shape[0], g.data_ptr(), loss.data_ptr()),
+              "mlp_grad")
     return g, loss
 
 
@@ -462,14 +463,18 @@ def mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float, beta1=0.9, 
 def score_micro_f1(ctx: Context, X, labels, train, test, epochs=300, lr=0.05, l2=None):
     """micro-F1 of one-vs-rest logistic regression trained on rows `train`."""
     import torch
-    X = X.float().contiguous()
-    n, d = X.shape
-    L = labels.shape[1]
-    l2 = (1.0 / len(train)) if l2 is None else l2
+    # every converted tensor stays referenced until the library call returns:
+    # a temporary would go back to torch's allocator, which the library's own
+    # scratch allocation may then reuse
+    Xf = X.float().contiguous()
+    lab = labels.to(torch.uint8).contiguous()
+    tr = train.to(torch.int32).contiguous()
+    te = test.to(torch.int32).contiguous()
+    n, d = Xf.shape
+    L = lab.shape[1]
+    l2 = (1.0 / len(tr)) if l2 is None else l2
     f1 = ctypes.c_double()
-    ctx.check(ctx.L.lne_score_micro_f1(ctx.h, X.data_ptr(), n, d,
-                                       labels.to(torch.uint8).contiguous().data_ptr(), L,
-                                       train.to(torch.int32).contiguous().data_ptr(), len(train),
-                                       test.to(torch.int32).contiguous().data_ptr(), len(test),
+    ctx.check(ctx.L.lne_score_micro_f1(ctx.h, Xf.data_ptr(), n, d, lab.data_ptr(), L,
+                                       tr.data_ptr(), len(tr), te.data_ptr(), len(te),
                                        epochs, lr, l2, ctypes.byref(f1)), "score_micro_f1")
     return f1.value

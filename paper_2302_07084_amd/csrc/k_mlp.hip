@@ -129,14 +129,23 @@ __global__ void k_mlp_init(float *__restrict__ p, int in, int h, uint64_t seed) 
 
 // ---- scorer ----------------------------------------------------------------
 // Rows idx of X into Xs (n_sel x d) and labels into Ys (n_sel x L, 0/1).
-__global__ void k_gather_rows(const float *__restrict__ X, int d, const uint8_t *__restrict__ lab,
-                             int L, const int32_t *__restrict__ idx, int64_t n_sel,
-                             float *__restrict__ Xs, float *__restrict__ Ys) {
+// An index outside [0, n) is counted in *bad and its row left zero.
+__global__ void k_gather_rows(const float *__restrict__ X, int64_t n, int d,
+                             const uint8_t *__restrict__ lab, int L,
+                             const int32_t *__restrict__ idx, int64_t n_sel,
+                             float *__restrict__ Xs, float *__restrict__ Ys,
+                             unsigned long long *__restrict__ bad) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_sel * (d + L)) return;
     const int64_t r = t / (d + L);
     const int c = (int)(t - r * (d + L));
     const int64_t src = idx[r];
+    if (src < 0 || src >= n) {
+        if (c == 0) atomicAdd(bad, 1ull);
+        if (c < d) Xs[r * d + c] = 0.0f;
+        else Ys[r * L + (c - d)] = 0.0f;
+        return;
+    }
     if (c < d) Xs[r * d + c] = X[src * d + c];
     else Ys[r * L + (c - d)] = (float)lab[src * L + (c - d)];
 }
@@ -327,7 +336,7 @@ lne_status lne_score_micro_f1(lne_ctx *ctx, const float *X, int64_t n, int32_t d
     const int64_t wsz = n_train * (d + L) + n_test * (d + L) + 2 * d + 4 * ((int64_t)d * L + L) +
                         2 * n_train * L + n_test * L;
     LNE_TRY(alloc(ctx, ws, sizeof(float) * (size_t)wsz));
-    LNE_TRY(alloc(ctx, cnt, 2 * sizeof(unsigned long long)));
+    LNE_TRY(alloc(ctx, cnt, 3 * sizeof(unsigned long long)));
     float *Xtr = ws.as<float>(), *Ytr = Xtr + n_train * d, *Xte = Ytr + n_train * L,
           *Yte = Xte + n_test * d, *mu = Yte + n_test * L, *isd = mu + d, *W = isd + d,
           *b = W + (int64_t)d * L, *gW = b + L, *gb = gW + (int64_t)d * L, *mW = gb + L,
@@ -337,13 +346,14 @@ lne_status lne_score_micro_f1(lne_ctx *ctx, const float *X, int64_t n, int32_t d
     LNE_HIP(ctx, hipMemsetAsync(W, 0, sizeof(float) * (size_t)((int64_t)d * L + L), ctx->stream));
     LNE_HIP(ctx, hipMemsetAsync(mW, 0, sizeof(float) * (size_t)(2 * ((int64_t)d * L + L)),
                                 ctx->stream));
-    LNE_HIP(ctx, hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), ctx->stream));
+    LNE_HIP(ctx, hipMemsetAsync(cnt.p, 0, 3 * sizeof(unsigned long long), ctx->stream));
     {
         Launch Lc(ctx, "score");
+        unsigned long long *bad = cnt.as<unsigned long long>() + 2;
         k_gather_rows<<<grid_of(n_train * (d + L), 256), 256, 0, ctx->stream>>>(
-            X, d, labels, L, train, n_train, Xtr, Ytr);
+            X, n, d, labels, L, train, n_train, Xtr, Ytr, bad);
         k_gather_rows<<<grid_of(n_test * (d + L), 256), 256, 0, ctx->stream>>>(
-            X, d, labels, L, test, n_test, Xte, Yte);
+            X, n, d, labels, L, test, n_test, Xte, Yte, bad);
         k_col_stats<<<grid_of(d, 64), 64, 0, ctx->stream>>>(Xtr, n_train, d, mu, isd);
         k_standardize<<<grid_of(n_train * d, 256), 256, 0, ctx->stream>>>(Xtr, n_train, d, mu, isd);
         k_standardize<<<grid_of(n_test * d, 256), 256, 0, ctx->stream>>>(Xte, n_test, d, mu, isd);
@@ -365,9 +375,10 @@ lne_status lne_score_micro_f1(lne_ctx *ctx, const float *X, int64_t n, int32_t d
                                                                  cnt.as<unsigned long long>());
     }
     LNE_TRY(check_launch(ctx, "score"));
-    unsigned long long h[2] = {0, 0};
+    unsigned long long h[3] = {0, 0, 0};
     LNE_HIP(ctx, hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h[2]) return fail(ctx, LNE_EINVAL, "score_micro_f1: %llu row indices outside [0, n)", h[2]);
     // top-k with k = true count: FP = FN = k - TP per row
     const double tp = (double)h[0], fp = (double)(h[1] - h[0]);
     *f1 = (2 * tp + 2 * fp) > 0 ? 2 * tp / (2 * tp + 2 * fp) : 0.0;

