@@ -247,6 +247,43 @@ lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
 lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void *X,
                      lne_stats *st);
 
+/* ---- batched trials sharing one sampling pass ------------------------------- */
+/* One trial of the search space of section 4.4 (s_1..s_T of Eq. (1) and the
+ * propagation parameters); M, q, d and the rest come from the base params. */
+typedef struct {
+    double s[16];       /* s_1..s_T >= 0, positive sum (normalised inside)    */
+    int32_t cheb_k;     /* propagation order; 0 switches propagation off      */
+    double theta, mu;   /* filter parameters; theta < 1e-12 switches it off   */
+} lne_trial;
+
+/* Sparsifier with per-length channels: like lne_sparsify but every sample
+ * draws its length r uniformly from 1..T (p->s is ignored) and r is kept:
+ * the count CSR has n x 16n columns, column (b << 4) | (r - 1) holding the
+ * weight of pairs (a, b) sampled at length r.  Synchronises the stream.
+ * Errors: as lne_sparsify; EUNSUPPORTED if n > 2^30. */
+lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                                 lne_csr *out, lne_stats *st);
+
+/* Sparsifier matrix of one trial from the channel counts: with pi_r = 1/T,
+ * the trial's weights are sum_r (s_r / pi_r) W_r (an unbiased estimate of its
+ * own sampler's counts) and the entries are ln x for x > 1 of Eq. (1), 0 for
+ * x <= 1 (the structure is the union over lengths; zeros are kept).
+ * out: F32 values.  Synchronises the stream.  Errors: EINVAL, ENOMEM. */
+lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            const lne_csr *channels, const lne_trial *trial, lne_csr *out);
+
+/* The whole path for n_trials trials at once (FP32): one channel sampling
+ * pass, every trial's matrix on the shared structure, the fast randomized SVD
+ * of all trials with one wide SpMM per power step (trial t's n x k' operand in
+ * columns [t k'', t k'' + k'), k'' = k' rounded up to 8) and per-trial FP64
+ * orthonormalisation and eigen-solves, then one wide graph SpMM per
+ * propagation step with per-trial coefficients and a per-trial final eigSVD.
+ * X: device n_trials x n x d FP32 (trial-major).  p->precision must be LNE_F32.
+ * Synchronises the stream.  Errors: EINVAL, ENOMEM, EHIP, ENUMERIC,
+ * EUNSUPPORTED (n_trials outside 1..256). */
+lne_status lne_embed_batch(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                           const lne_trial *trials, int32_t n_trials, float *X, lne_stats *st);
+
 /* ---- hyperparameter search: surrogate network and downstream scorer ------ */
 /* Section 4.4 searches s_r, M, q, k, theta and mu against the downstream
  * score.  The surrogate is an MLP in_dim -> hidden -> hidden -> 1 with GELU

@@ -43,7 +43,7 @@ def lib():
                                        P, P, P, P, P, P, P]
         L.ora_sample_slots.restype = i64
         L.ora_count_rows.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64, i64,
-                                     i32, P, P, P, P, P, P]
+                                     i32, i32, P, P, P, P, P, P]
         L.ora_count_rows.restype = i32
         L.ora_free.argtypes = [P]
         L.ora_trunc_log.argtypes = [i64, i64, P, P, P, P, u64, u64, u64, P, P]
@@ -124,10 +124,13 @@ def sample_slots(g, params, e_begin: int = 0, e_end: int | None = None):
 
 
 def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
-              nthreads: int | None = None, e_begin: int = 0, e_end: int = -1):
+              nthreads: int | None = None, e_begin: int = 0, e_end: int = -1,
+              channels: bool = False):
     """Aggregated count matrix W (fixed point, 2^-16 units) restricted to rows
     [row_lo, row_hi), from the samples of edges [e_begin, e_end) (all edges
-    by default): returns (rowptr, col, W, attempted, accepted).  Equal
+    by default): returns (rowptr, col, W, attempted, accepted).  With
+    ``channels`` the length r is drawn uniformly from 1..T and kept: column
+    (b << 4) | (r - 1).  Equal
     pairs are summed exactly in uint64 (section 5.2, sparse parallel hashing;
     here a sort of the sample triples)."""
     rp, col = _graph_arrays(g)
@@ -145,7 +148,7 @@ def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
     acc = ctypes.c_uint64()
     rc = lib().ora_count_rows(g.n, _p(rp), _p(col), params["T"], _p(s), int(params["M"]),
                               C, no_ds, int(params["seed"]), row_lo, row_hi, e_begin, e_end,
-                              nthreads,
+                              1 if channels else 0, nthreads,
                               ctypes.byref(prp), ctypes.byref(pcol), ctypes.byref(pw),
                               ctypes.byref(nnz), ctypes.byref(att), ctypes.byref(acc))
     if rc == -1:
@@ -187,6 +190,34 @@ def compact(rowptr, col, keep, val):
     rp = np.zeros(rows + 1, np.int64)
     np.add.at(rp, kept_rows + 1, 1)
     return np.cumsum(rp), col[keep], val[keep]
+
+
+def trial_matrix(g, params, R, Cext, W, s):
+    """Sparsifier matrix of one trial from per-length channel counts (the
+    batched search reading): with the length drawn uniformly (pi_r = 1/T),
+    sum_r (s_r / pi_r) W_r estimates the trial's own counts; then Eq. (1)'s
+    truncated logarithm.  Returns a dense-structure FP64 CSR over the union of
+    lengths with log x where x > 1 and explicit zeros elsewhere."""
+    T = params["T"]
+    s = np.asarray(s, np.float64)
+    s = s / s.sum()
+    rows = np.repeat(np.arange(g.n), np.diff(R))
+    base = Cext >> 4
+    r = Cext & 15
+    key = rows.astype(np.int64) * g.n + base
+    uniq, start = np.unique(key, return_index=True)
+    grp = np.searchsorted(uniq, key)
+    mixed = np.zeros(len(uniq))
+    np.add.at(mixed, grp, T * s[r] * W.astype(np.float64))
+    a = uniq // g.n
+    b = uniq % g.n
+    deg = g.degrees().astype(np.float64)
+    vol = float(g.n_arcs)
+    x = vol * vol / (2.0 * params["b"] * params["M"]) / 65536.0 * mixed / (deg[a] * deg[b])
+    val = np.where(x > 1.0, np.log(np.where(x > 1.0, x, 1.0)), 0.0)
+    rp = np.zeros(g.n + 1, np.int64)
+    np.add.at(rp, a + 1, 1)
+    return sp.csr_matrix((val, b, np.cumsum(rp)), shape=(g.n, g.n))
 
 
 def netmf_sparse(g, params, nthreads=None):

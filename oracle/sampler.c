@@ -255,7 +255,7 @@ int64_t ora_sample_slots(int64_t n, const int64_t *rowptr, const int32_t *col,
 typedef struct { int32_t a, b; uint64_t w; } trip_t;
 
 typedef struct {
-    const graph_t *g; const plan_t *pl; uint64_t seed; double C; int no_ds;
+    const graph_t *g; const plan_t *pl; uint64_t seed; double C; int no_ds; int channels;
     const int32_t *eu, *ev;
     int64_t e0, e1, row_lo, row_hi;
     trip_t *buf; int64_t len, cap;
@@ -292,8 +292,14 @@ static void *job_run(void *arg)
             if (!sample_slot(g, jb->pl, jb->seed, e, u, v, (uint32_t)j, all, tau, &a, &b, &r))
                 continue;
             jb->accepted++;
-            push(jb, a, b, w);
-            push(jb, b, a, w);
+            if (jb->channels) {
+                /* per-length channels: column (b << 4) | (r - 1) */
+                push(jb, a, (int32_t)(((uint32_t)b << 4) | (uint32_t)(r - 1)), w);
+                push(jb, b, (int32_t)(((uint32_t)a << 4) | (uint32_t)(r - 1)), w);
+            } else {
+                push(jb, a, b, w);
+                push(jb, b, a, w);
+            }
         }
     }
     return NULL;
@@ -312,12 +318,15 @@ static int trip_cmp(const void *x, const void *y)
  * [e_begin, e_end) (e_end < 0: all edges): *o_rowptr has row_hi-row_lo+1
  * entries starting at 0, *o_col / *o_w have *o_nnz entries.  Buffers are
  * malloc'ed here and released with ora_free.  Also reports the number of
- * attempted and accepted samples of those edges.  Returns 0, or -1 on
+ * attempted and accepted samples of those edges.  With channels != 0 the
+ * length r is drawn uniformly from 1..T (s is ignored) and kept in the column:
+ * entry (a, (b << 4) | (r - 1)).  Returns 0, or -1 on
  * allocation failure, -2 on a weight-sum overflow.
  */
 int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
                    const double *s, uint64_t M, double C, int no_ds, uint64_t seed,
-                   int64_t row_lo, int64_t row_hi, int64_t e_begin, int64_t e_end, int nthreads,
+                   int64_t row_lo, int64_t row_hi, int64_t e_begin, int64_t e_end, int channels,
+                   int nthreads,
                    int64_t **o_rowptr, int32_t **o_col, uint64_t **o_w, int64_t *o_nnz,
                    uint64_t *o_attempted, uint64_t *o_accepted)
 {
@@ -328,7 +337,9 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
     if (!eu || !ev) return -1;
     edge_list(&g, eu, ev);
     plan_t pl;
-    make_plan(T, s, M, m, &pl);
+    double uni[16];
+    for (int t = 0; t < T; ++t) uni[t] = 1.0;
+    make_plan(T, channels ? uni : s, M, m, &pl);
     if (nthreads < 1) nthreads = 1;
     if (e_end < 0 || e_end > m) e_end = m;
     if (e_begin < 0) e_begin = 0;
@@ -338,6 +349,7 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
     for (int t = 0; t < nthreads; ++t) {
         job_t *jb = &jobs[t];
         jb->g = &g; jb->pl = &pl; jb->seed = seed; jb->C = C; jb->no_ds = no_ds;
+        jb->channels = channels;
         jb->eu = eu; jb->ev = ev;
         jb->e0 = e_begin + (e_end - e_begin) * t / nthreads;
         jb->e1 = e_begin + (e_end - e_begin) * (t + 1) / nthreads;

@@ -49,6 +49,19 @@ class CsrStruct(ctypes.Structure):
                 ("val_type", ctypes.c_int32)]
 
 
+class TrialStruct(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_double * 16), ("cheb_k", ctypes.c_int32),
+                ("theta", ctypes.c_double), ("mu", ctypes.c_double)]
+
+
+def make_trial(s, k, theta, mu) -> TrialStruct:
+    t = TrialStruct()
+    for i, x in enumerate(np.asarray(s, np.float64)):
+        t.s[i] = float(x)
+    t.cheb_k, t.theta, t.mu = int(k), float(theta), float(mu)
+    return t
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("attempted", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
                 ("nnz_counts", ctypes.c_uint64), ("nnz_log", ctypes.c_uint64),
@@ -87,6 +100,9 @@ SIGNATURES = [
     ("lne_rsvd", _I32, [_P, _P, _P, _P, _P, _P, _P]),
     ("lne_propagate", _I32, [_P, _P, _P, _P, _P]),
     ("lne_embed", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_sparsify_channels", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_trial_matrix", _I32, [_P, _P, _P, _P, _P, _P]),
+    ("lne_embed_batch", _I32, [_P, _P, _P, _P, _I32, _P, _P]),
     ("lne_mlp_param_count", _I64, [_I32, _I32]),
     ("lne_mlp_init", _I32, [_P, _I32, _I32, _U64, _P]),
     ("lne_mlp_forward", _I32, [_P, _I32, _I32, _P, _P, _I64, _P]),
@@ -417,6 +433,44 @@ def embed(ctx: Context, rowptr, col, params: dict, out=None):
     st = Stats()
     ctx.check(ctx.L.lne_embed(ctx.h, ctypes.byref(g), ctypes.byref(p), X.data_ptr(),
                               ctypes.byref(st)), "embed")
+    return X, st.as_dict()
+
+
+# ---- batched trials ----------------------------------------------------------
+def sparsify_channels(ctx: Context, rowptr, col, params: dict):
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    out = Csr(ctx)
+    st = Stats()
+    ctx.check(ctx.L.lne_sparsify_channels(ctx.h, ctypes.byref(g), ctypes.byref(p),
+                                          ctypes.byref(out.s), ctypes.byref(st)),
+              "sparsify_channels")
+    return out, st.as_dict()
+
+
+def trial_matrix(ctx: Context, rowptr, col, params: dict, channels: Csr, trial: dict):
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    t = make_trial(trial["s"], trial.get("k", 0), trial.get("theta", 0.0), trial.get("mu", 0.0))
+    out = Csr(ctx)
+    ctx.check(ctx.L.lne_trial_matrix(ctx.h, ctypes.byref(g), ctypes.byref(p),
+                                     ctypes.byref(channels.s), ctypes.byref(t),
+                                     ctypes.byref(out.s)), "trial_matrix")
+    return out
+
+
+def embed_batch(ctx: Context, rowptr, col, params: dict, trials):
+    """Embeddings of several trials (dicts with s, k, theta, mu) from one
+    shared sampling pass; returns (n_trials x n x d FP32, stats)."""
+    import torch
+    g = graph_struct(rowptr, col)
+    p = make_params(params, precision="f32")
+    arr = (TrialStruct * len(trials))(*[make_trial(t["s"], t["k"], t["theta"], t["mu"])
+                                        for t in trials])
+    X = torch.empty((len(trials), g.n, p.d), dtype=torch.float32, device=ctx.device)
+    st = Stats()
+    ctx.check(ctx.L.lne_embed_batch(ctx.h, ctypes.byref(g), ctypes.byref(p), arr, len(trials),
+                                    X.data_ptr(), ctypes.byref(st)), "embed_batch")
     return X, st.as_dict()
 
 

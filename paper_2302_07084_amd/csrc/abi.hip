@@ -254,13 +254,15 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
         LNE_TRY(alloc(ctx, k1, sizeof(uint64_t) * (size_t)P));
         LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)P));
         LNE_TRY(radix_sort(ctx, k0.as<uint64_t>(), v0.as<uint32_t>(), k1.as<uint64_t>(),
-                           v1.as<uint32_t>(), P, rowbits + S.pl.colbits, &which));
+                           v1.as<uint32_t>(), P, rowbits + S.pl.colbits + S.pl.cbits, &which));
         // the other ping-pong pair is free before the CSR is allocated
         if (which) { k0.release(); v0.release(); } else { k1.release(); v1.release(); }
     }
     const uint64_t *keys = which ? k1.as<uint64_t>() : k0.as<uint64_t>();
     const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
-    return reduce_to_csr(ctx, keys, vals, P, hi - lo, S.pl.colbits, out);
+    LNE_TRY(reduce_to_csr(ctx, keys, vals, P, hi - lo, S.pl.colbits + S.pl.cbits, out));
+    out->n_cols = g->n << S.pl.cbits;
+    return LNE_OK;
 }
 
 // Runs the sparsifier and hands each row block of the count matrix, in row
@@ -271,9 +273,18 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
 // and keeping the entries whose row falls inside it.
 template <class Sink>
 static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                                lne_stats *st, Sink &&sink) {
+                                lne_stats *st, Sink &&sink, bool channels = false) {
     Sampler S;
-    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
+    if (channels) {
+        // one pass shared by trials with different s: the length is drawn
+        // uniformly from 1..T and kept in the key (section 4.4 search space)
+        lne_params pu = *p;
+        for (int t = 0; t < p->T; ++t) pu.s[t] = 1.0;
+        LNE_TRY(make_plan(ctx, &pu, g->n, g->n_arcs, S.pl));
+        S.pl.cbits = 4;
+    } else {
+        LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
+    }
     S.m = g->n_arcs / 2;
     uint64_t total = 0;
     if (S.m > 0 && S.pl.S > 0) {
@@ -293,7 +304,8 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
         lne_csr blk;
         std::memset(&blk, 0, sizeof(blk));
         if (total == 0) {
-            LNE_TRY(reduce_to_csr(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits, &blk));
+            LNE_TRY(reduce_to_csr(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits + S.pl.cbits, &blk));
+            blk.n_cols = g->n << S.pl.cbits;
         } else {
             LNE_TRY(aggregate_range(ctx, g, S, 0, g->n, total, &blk));
         }
@@ -796,6 +808,257 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     lne_csr_free(ctx, &M);
     if (s != LNE_OK) return s;
     return propagate_impl(ctx, g, p, X0.p, X);
+}
+
+static lne_status check_trial(lne_ctx *ctx, const lne_trial *t, int T) {
+    double tot = 0.0;
+    for (int r = 0; r < T; ++r) {
+        if (!(t->s[r] >= 0.0) || !std::isfinite(t->s[r]))
+            return fail(ctx, LNE_EINVAL, "trial: s must be finite and >= 0");
+        tot += t->s[r];
+    }
+    if (!(tot > 0.0)) return fail(ctx, LNE_EINVAL, "trial: s must have a positive sum");
+    if (t->cheb_k < 0 || t->cheb_k > 64 || !std::isfinite(t->theta) || t->theta < 0.0 ||
+        !std::isfinite(t->mu))
+        return fail(ctx, LNE_EINVAL, "trial: cheb_k in 0..64, theta >= 0, mu finite");
+    return LNE_OK;
+}
+
+// normalised s of each trial, 16 doubles per trial (zeros beyond T)
+static std::vector<double> trial_s(const lne_trial *trials, int ntr, int T) {
+    std::vector<double> s(16 * (size_t)ntr, 0.0);
+    for (int t = 0; t < ntr; ++t) {
+        double tot = 0.0;
+        for (int r = 0; r < T; ++r) tot += trials[t].s[r];
+        for (int r = 0; r < T; ++r) s[16 * t + r] = trials[t].s[r] / tot;
+    }
+    return s;
+}
+
+static double tl_scale(const lne_graph *g, const lne_params *p) {
+    const double vol = (double)g->n_arcs;
+    return vol * vol / (2.0 * (double)p->b * (double)p->M) / 65536.0;
+}
+
+static lne_status channels_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                                lne_csr *out, lne_stats *st) {
+    if (g->n > ((int64_t)1 << 30))
+        return fail(ctx, LNE_EUNSUPPORTED, "channel sparsifier: n above 2^30");
+    std::vector<lne_csr> blocks;
+    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
+        blocks.push_back(blk);
+        return LNE_OK;
+    };
+    lne_status s = sparsify_impl(ctx, g, p, st, sink, true);
+    if (s == LNE_OK) s = concat_rows(ctx, blocks, g->n, out);
+    for (auto &b : blocks) lne_csr_free(ctx, &b);
+    return s;
+}
+
+lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                                 lne_csr *out, lne_stats *st) {
+    if (!ctx) return LNE_EINVAL;
+    if (!out) return fail(ctx, LNE_EINVAL, "sparsify_channels: out is NULL");
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    std::memset(out, 0, sizeof(*out));
+    LNE_TRY(validate_graph_device(ctx, g));
+    return channels_impl(ctx, g, p, out, st);
+}
+
+lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            const lne_csr *channels, const lne_trial *trial, lne_csr *out) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    if (!channels || !trial || !out || channels->val_type != LNE_U64 ||
+        channels->n_rows != g->n || channels->n_cols != (g->n << 4))
+        return fail(ctx, LNE_EINVAL, "trial_matrix: channels must come from lne_sparsify_channels");
+    LNE_TRY(check_trial(ctx, trial, p->T));
+    std::memset(out, 0, sizeof(*out));
+    lne_csr st;
+    std::memset(&st, 0, sizeof(st));
+    Buf chan(ctx), sdev(ctx), vals(ctx);
+    LNE_TRY(split_channels(ctx, channels, p->T, &st, chan));
+    const std::vector<double> sh = trial_s(trial, 1, p->T);
+    lne_status s = alloc(ctx, sdev, sizeof(double) * 16);
+    if (s == LNE_OK) s = alloc(ctx, vals, sizeof(float) * (size_t)(st.nnz ? st.nnz : 1));
+    if (s == LNE_OK && hipMemcpyAsync(sdev.p, sh.data(), sizeof(double) * 16,
+                                      hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+        s = fail(ctx, LNE_EHIP, "trial_matrix: copy of s failed");
+    if (s == LNE_OK)
+        s = trial_values(ctx, g, &st, chan.as<uint64_t>(), p->T, sdev.as<double>(), 1,
+                         tl_scale(g, p), vals.as<float>());
+    if (s == LNE_OK) s = hipStreamSynchronize(ctx->stream) == hipSuccess ? LNE_OK : LNE_EHIP;
+    if (s != LNE_OK) {
+        lne_csr_free(ctx, &st);
+        return s;
+    }
+    st.val = vals.detach();
+    st.val_type = LNE_F32;
+    *out = st;
+    return LNE_OK;
+}
+
+lne_status lne_embed_batch(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                           const lne_trial *trials, int32_t n_trials, float *X, lne_stats *st) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
+    if (!trials || !X) return fail(ctx, LNE_EINVAL, "embed_batch: NULL trials or X");
+    if (n_trials < 1 || n_trials > 256)
+        return fail(ctx, LNE_EUNSUPPORTED, "embed_batch: n_trials = %d outside 1..256", n_trials);
+    if (p->precision != LNE_F32)
+        return fail(ctx, LNE_EINVAL, "embed_batch: precision must be LNE_F32");
+    for (int t = 0; t < n_trials; ++t) LNE_TRY(check_trial(ctx, &trials[t], p->T));
+    if (st) std::memset(st, 0, sizeof(*st));
+    LNE_TRY(validate_graph_device(ctx, g));
+    const int ntr = n_trials, T = p->T;
+    const int64_t n = g->n;
+
+    // 1. one channel sampling pass, split into structure + channels
+    lne_csr ext, S;
+    std::memset(&ext, 0, sizeof(ext));
+    std::memset(&S, 0, sizeof(S));
+    LNE_TRY(channels_impl(ctx, g, p, &ext, st));
+    Buf chan(ctx);
+    lne_status s = split_channels(ctx, &ext, T, &S, chan);
+    lne_csr_free(ctx, &ext);
+    LNE_TRY(s);
+    struct Guard { lne_ctx *c; lne_csr *m; ~Guard() { lne_csr_free(c, m); } } guard{ctx, &S};
+
+    // 2. every trial's matrix values on the shared structure
+    Buf sdev(ctx), vals(ctx);
+    const std::vector<double> sh = trial_s(trials, ntr, T);
+    LNE_TRY(alloc(ctx, sdev, sizeof(double) * sh.size()));
+    LNE_TRY(alloc(ctx, vals, sizeof(float) * (size_t)(S.nnz ? S.nnz : 1) * ntr));
+    LNE_HIP(ctx, hipMemcpyAsync(sdev.p, sh.data(), sizeof(double) * sh.size(),
+                                hipMemcpyHostToDevice, ctx->stream));
+    LNE_TRY(trial_values(ctx, g, &S, chan.as<uint64_t>(), T, sdev.as<double>(), ntr,
+                         tl_scale(g, p), vals.as<float>()));
+    chan.release();
+    if (st) st->nnz_log = (uint64_t)S.nnz;
+
+    // 3. fast randomized SVD of all trials
+    const int32_t kp = p->d + p->oversample, d = p->d;
+    const int dp = (int)round8(kp), d8 = (int)round8(d);
+    const int64_t ld = (int64_t)ntr * dp, ldx = (int64_t)ntr * d8;
+    Buf A(ctx), B(ctx), X0(ctx);
+    LNE_TRY(alloc(ctx, A, sizeof(float) * (size_t)n * ld));
+    LNE_TRY(alloc(ctx, B, sizeof(float) * (size_t)n * ld));
+    LNE_TRY(alloc(ctx, X0, sizeof(float) * (size_t)n * ldx));
+    LNE_HIP(ctx, hipMemsetAsync(A.p, 0, sizeof(float) * (size_t)n * ld, ctx->stream));
+    Flags f;
+    LNE_TRY(make_flags(ctx, f));
+    float *Q = A.as<float>(), *Y = B.as<float>();
+    for (int t = 0; t < ntr; ++t)
+        LNE_TRY(launch_gaussian(ctx, n, kp, ld, p->seed, LNE_F32, Q + (int64_t)t * dp));
+    LNE_TRY(spmm_multi(ctx, &S, vals.as<float>(), ntr, Q, ld, Y, dp));
+    for (int t = 0; t < ntr; ++t) LNE_TRY(orth_impl(ctx, Y + (int64_t)t * dp, n, kp, ld, LNE_F32, f));
+    std::swap(Q, Y);
+    Buf W(ctx);
+    LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)kp * d));
+    for (int it = 1; it <= p->q; ++it) {
+        LNE_TRY(spmm_multi(ctx, &S, vals.as<float>(), ntr, Q, ld, Y, dp));
+        if (it < p->q) {
+            for (int t = 0; t < ntr; ++t)
+                LNE_TRY(orth_impl(ctx, Y + (int64_t)t * dp, n, kp, ld, LNE_F32, f));
+            std::swap(Q, Y);
+        } else {
+            for (int t = 0; t < ntr; ++t) {
+                Buf Vk(ctx), lam(ctx);
+                LNE_TRY(eig_of_gram(ctx, Y + (int64_t)t * dp, LNE_F32, n, kp, ld, Vk, lam));
+                LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, -0.25,
+                                    W.as<double>(), nullptr));
+                LNE_TRY(project(ctx, Y + (int64_t)t * dp, LNE_F32, ld, n, kp, W.as<double>(), d,
+                                X0.as<float>() + (int64_t)t * d8, LNE_F32, ldx, nullptr));
+            }
+        }
+    }
+    vals.release();
+    A.release();
+    B.release();
+
+    // 4. propagation of all trials with one wide graph SpMM per step
+    int K = 0;
+    std::vector<bool> on(ntr);
+    for (int t = 0; t < ntr; ++t) {
+        on[t] = trials[t].cheb_k > 0 && trials[t].theta >= 1e-12;
+        if (on[t]) K = std::max(K, (int)trials[t].cheb_k);
+    }
+    const float *Xsp = X0.as<float>();
+    Buf b0(ctx), b1(ctx), b2(ctx), bz(ctx), bc(ctx), coefd(ctx);
+    if (K > 0) {
+        for (Buf *b : {&b0, &b1, &b2, &bz, &bc}) LNE_TRY(alloc(ctx, *b, sizeof(float) * (size_t)n * ldx));
+        // coefficient table: 2K calls of the recurrence + the final D^-1 A
+        const int calls = 2 * K + 1;
+        std::vector<float> cf((size_t)calls * ntr * 5, 0.0f);
+        std::vector<std::vector<double>> cheb(ntr, std::vector<double>(K + 1, 0.0));
+        for (int t = 0; t < ntr; ++t) {
+            if (!on[t]) continue;
+            const double th = trials[t].theta;
+            for (int i = 0; i <= trials[t].cheb_k; ++i)
+                cheb[t][i] = (i == 0 ? 1.0 : 2.0 * ((i & 1) ? -1.0 : 1.0)) * std::exp(-th / 2.0) *
+                             bessel_i(i, th);
+        }
+        auto set = [&](int call, int t, float a, float b, float c1, float c2, float e) {
+            float *q = &cf[((size_t)call * ntr + t) * 5];
+            q[0] = a; q[1] = b; q[2] = c1; q[3] = c2; q[4] = e;
+        };
+        for (int t = 0; t < ntr; ++t) {
+            const float am = (float)(1.0 - trials[t].mu);
+            set(0, t, am, -1.f, 0.f, 0.f, 0.f);
+            set(1, t, 0.5f * am, -0.5f, -1.f, 0.f, (float)cheb[t][1]);
+            for (int i = 2; i <= K; ++i) {
+                set(2 * i - 2, t, am, -1.f, 0.f, 0.f, 0.f);
+                set(2 * i - 1, t, am, -1.f, -2.f, -1.f, (float)cheb[t][i]);
+            }
+            set(2 * K, t, 0.f, 1.f, 0.f, 0.f, 0.f);
+        }
+        LNE_TRY(alloc(ctx, coefd, sizeof(float) * cf.size()));
+        LNE_HIP(ctx, hipMemcpyAsync(coefd.p, cf.data(), sizeof(float) * cf.size(),
+                                    hipMemcpyHostToDevice, ctx->stream));
+        const float *C = coefd.as<float>();
+        auto cc = [&](int call) { return C + (size_t)call * ntr * 5; };
+        float *T0 = b0.as<float>(), *T1 = b1.as<float>(), *T2 = b2.as<float>(), *Z = bz.as<float>(),
+              *conv = bc.as<float>();
+        LNE_HIP(ctx, hipMemcpyAsync(T0, X0.p, sizeof(float) * (size_t)n * ldx,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        for (int t = 0; t < ntr; ++t)
+            LNE_TRY(dense_scale(ctx, T0 + (int64_t)t * d8, LNE_F32, ldx, conv + (int64_t)t * d8,
+                                LNE_F32, ldx, n, d8, cheb[t][0]));
+        LNE_TRY(gspmm_multi(ctx, g, T0, ldx, ntr, d8, Z, nullptr, nullptr, nullptr, cc(0)));
+        LNE_TRY(gspmm_multi(ctx, g, Z, ldx, ntr, d8, T1, T0, nullptr, conv, cc(1)));
+        for (int i = 2; i <= K; ++i) {
+            LNE_TRY(gspmm_multi(ctx, g, T1, ldx, ntr, d8, Z, nullptr, nullptr, nullptr, cc(2 * i - 2)));
+            LNE_TRY(gspmm_multi(ctx, g, Z, ldx, ntr, d8, T2, T1, T0, conv, cc(2 * i - 1)));
+            float *tmp = T0;
+            T0 = T1;
+            T1 = T2;
+            T2 = tmp;
+        }
+        LNE_TRY(axpby(ctx, X0.p, conv, conv, n, (int32_t)ldx, ldx, LNE_F32, 1.0, -1.0));
+        LNE_TRY(gspmm_multi(ctx, g, conv, ldx, ntr, d8, Z, nullptr, nullptr, nullptr, cc(2 * K)));
+        Xsp = Z;
+    }
+    // 5. final eigSVD per trial (or X0 for trials with propagation off)
+    Buf Wd(ctx);
+    LNE_TRY(alloc(ctx, Wd, sizeof(double) * (size_t)d * d));
+    for (int t = 0; t < ntr; ++t) {
+        float *Xt = X + (int64_t)t * n * d;
+        if (!on[t]) {
+            LNE_TRY(dense_scale(ctx, X0.as<float>() + (int64_t)t * d8, LNE_F32, ldx, Xt, LNE_F32, d,
+                                n, d, 1.0));
+            continue;
+        }
+        Buf Vk(ctx), lam(ctx);
+        LNE_TRY(eig_of_gram(ctx, Xsp + (int64_t)t * d8, LNE_F32, n, d, ldx, Vk, lam));
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), d, d, -0.25, Wd.as<double>(),
+                            nullptr));
+        LNE_TRY(project(ctx, Xsp + (int64_t)t * d8, LNE_F32, ldx, n, d, Wd.as<double>(), d, Xt,
+                        LNE_F32, d, nullptr));
+    }
+    return read_flags(ctx, f, st);
 }
 
 }  // extern "C"

@@ -99,6 +99,8 @@ struct SamplePlan {
     int64_t J;            // slots per thread chunk
     int64_t chunks;       // chunks per edge
     int32_t colbits;      // bits of a column id in the packed key
+    int32_t cbits;        // channel bits below the column (0, or 4 when the
+                          // length r is kept: key column = col << 4 | r - 1)
 };
 
 lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
@@ -181,6 +183,21 @@ lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam);
 // lam <= k eps lam_max); S (kout) = sqrt(lam) (optional).
 lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t k,
                        int32_t kout, double power, double *W, double *S);
+
+// ---- batched trials (k_batch.hip) ------------------------------------------------
+// Extended count CSR (columns col << 4 | r - 1) -> structure (val NULL) plus
+// channels chan[entry * T + r - 1] (uint64).
+lne_status split_channels(lne_ctx *ctx, const lne_csr *ext, int T, lne_csr *st, Buf &chan);
+// vals[entry * ntr + t]: truncated log of trial t's mixed counts (0 if dropped).
+lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, const uint64_t *chan,
+                        int T, const double *s_dev, int ntr, double scale, float *vals);
+// Y = M_t X_t for every trial t, slices of width dp in n x ld matrices.
+lne_status spmm_multi(lne_ctx *ctx, const lne_csr *st, const float *vals, int ntr, const float *X,
+                      int64_t ld, float *Y, int dp);
+// Wide graph SpMM with per-trial epilogue coefficients coef[5 t + {a, b, c1, c2, e}].
+lne_status gspmm_multi(lne_ctx *ctx, const lne_graph *g, const float *Z, int64_t ld, int ntr,
+                       int dp, float *out, const float *E1, const float *E2, float *acc,
+                       const float *coef);
 
 // ---- pipeline (pipeline.cpp) ---------------------------------------------------
 lne_status validate_graph(lne_ctx *ctx, const lne_graph *g);

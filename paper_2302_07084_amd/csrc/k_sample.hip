@@ -78,10 +78,10 @@ __device__ __forceinline__ int32_t walk_step(const int64_t *__restrict__ rp,
 }
 
 // Walks of an accepted slot whose first Philox block is `blk0`.
-__device__ __forceinline__ void walk_pair(const SamplePlan &pl, const int64_t *__restrict__ rp,
-                                          const int32_t *__restrict__ col, int64_t e,
-                                          uint32_t j, uint4 blk0, int32_t u, int32_t v,
-                                          int32_t &a, int32_t &b) {
+__device__ __forceinline__ int walk_pair(const SamplePlan &pl, const int64_t *__restrict__ rp,
+                                         const int32_t *__restrict__ col, int64_t e,
+                                         uint32_t j, uint4 blk0, int32_t u, int32_t v,
+                                         int32_t &a, int32_t &b) {
     const int r = draw_r(pl, blk0.y);
     const int split = (int)(blk0.z % (uint32_t)r);
     uint4 buf = make_uint4(blk0.w, 0, 0, 0);
@@ -102,6 +102,7 @@ __device__ __forceinline__ void walk_pair(const SamplePlan &pl, const int64_t *_
     }
     a = x;
     b = y;
+    return r;
 }
 
 // Structural check of the input CSR (bit 1: offsets, 2: column range,
@@ -234,28 +235,33 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
         ne = draw_ne(pl, e);
     }
     const uint32_t w = (uint32_t)cn.w;
+    const int kb = pl.colbits + pl.cbits;
     for (int64_t jj = 0; jj < pl.J; ++jj) {
         const uint64_t j = j0 + (uint64_t)jj;
         bool ina = false, inb = false;
         int32_t a = u, b = v;
+        uint64_t ch = 0;
         if (e < m && j < ne) {
             const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
             if (cn.all || (uint64_t)b0.x < cn.tau) {
-                walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+                const int r = walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
                 ina = a >= row_lo && a < row_hi;
                 inb = b >= row_lo && b < row_hi;
+                ch = pl.cbits ? (uint64_t)(r - 1) : 0;
             }
         }
         const uint32_t cnt = (ina ? 1u : 0u) + (inb ? 1u : 0u);
         const uint64_t m0 = __ballot(cnt & 1u), m1 = __ballot(cnt & 2u);
         uint64_t idx = pos + (uint64_t)__popcll(m0 & lt) + 2ull * (uint64_t)__popcll(m1 & lt);
         if (ina) {
-            keys[idx] = ((uint64_t)(uint32_t)(a - row_lo) << pl.colbits) | (uint32_t)b;
+            keys[idx] = ((uint64_t)(uint32_t)(a - row_lo) << kb) |
+                        ((uint64_t)(uint32_t)b << pl.cbits) | ch;
             vals[idx] = w;
             ++idx;
         }
         if (inb) {
-            keys[idx] = ((uint64_t)(uint32_t)(b - row_lo) << pl.colbits) | (uint32_t)a;
+            keys[idx] = ((uint64_t)(uint32_t)(b - row_lo) << kb) |
+                        ((uint64_t)(uint32_t)a << pl.cbits) | ch;
             vals[idx] = w;
         }
         pos += (uint64_t)__popcll(m0) + 2ull * (uint64_t)__popcll(m1);

@@ -88,10 +88,10 @@ lne_status concat_rows(lne_ctx *ctx, std::vector<lne_csr> &blocks, int64_t n_row
                        lne_csr *out) {
     if (blocks.size() == 1 && blocks[0].n_rows == n_rows) {
         *out = blocks[0];
-        out->n_cols = n_rows;
         blocks.clear();
         return LNE_OK;
     }
+    const int64_t n_cols = blocks.empty() ? n_rows : blocks[0].n_cols;
     int64_t nnz = 0;
     for (auto &b : blocks) nnz += b.nnz;
     const int32_t vt = blocks.empty() ? LNE_U64 : blocks[0].val_type;
@@ -127,7 +127,7 @@ lne_status concat_rows(lne_ctx *ctx, std::vector<lne_csr> &blocks, int64_t n_row
                                 hipMemcpyHostToDevice, ctx->stream));
     LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     out->n_rows = n_rows;
-    out->n_cols = n_rows;
+    out->n_cols = n_cols;
     out->nnz = nnz;
     out->row_ptr = (int64_t *)rp.detach();
     out->col = (int32_t *)cc.detach();
