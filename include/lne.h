@@ -272,15 +272,60 @@ lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_par
 lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                             const lne_csr *channels, const lne_trial *trial, lne_csr *out);
 
-/* The whole path for n_trials trials at once (FP32): one channel sampling
- * pass, every trial's matrix on the shared structure, the fast randomized SVD
- * of all trials with one wide SpMM per power step (trial t's n x k' operand in
- * columns [t k'', t k'' + k'), k'' = k' rounded up to 8) and per-trial FP64
- * orthonormalisation and eigen-solves, then one wide graph SpMM per
- * propagation step with per-trial coefficients and a per-trial final eigSVD.
- * X: device n_trials x n x d FP32 (trial-major).  p->precision must be LNE_F32.
- * Synchronises the stream.  Errors: EINVAL, ENOMEM, EHIP, ENUMERIC,
- * EUNSUPPORTED (n_trials outside 1..256). */
+/* A batch: the state that every trial on one graph shares.  Creating it runs
+ * the channel sampling pass once (as lne_sparsify_channels), draws the
+ * Gaussian test matrix of Algorithm "Fast Randomized SVD" (the same matrix
+ * the single-trial path draws from p->seed) and allocates a trial-major FP32
+ * workspace for max_trials trials (about (2 k'' + 7 d'') n 4 bytes per trial,
+ * k'' and d'' = d + oversample and d rounded up to 8, plus the channel CSR).
+ * It also picks the launch shapes of the batched SpMM kernels by timing each
+ * shape on this matrix (with env LNE_TUNE_CACHE naming a JSON-lines file, the
+ * choice is read from / appended to it).  The graph's device arrays must stay
+ * valid until lne_batch_destroy.  p->s is not used (each trial brings its
+ * own); p->precision must be LNE_F32 and d + oversample <= 256.
+ * Synchronises the stream.  st (may be NULL): attempted, accepted, nnz_counts
+ * of the channel pass.  Errors: those of lne_sparsify_channels, EINVAL,
+ * ENOMEM, EUNSUPPORTED (max_trials outside 1..256). */
+typedef struct lne_batch lne_batch;
+lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            int32_t max_trials, lne_batch **out, lne_stats *st);
+
+#define LNE_BATCH_EAGER 0   /* enqueue the launches of the run one by one          */
+#define LNE_BATCH_GRAPH 1   /* replay them as one captured HIP graph               */
+/* Embeddings of n_trials <= max_trials trials.  For every trial t, M_t (the
+ * lne_trial_matrix of trial t) is regenerated on the fly inside each SpMM
+ * from the channel CSR; the fast randomized SVD (CholeskyQR2 and eigSVD in
+ * FP64 on MFMA, one launch per step for all trials), Chebyshev propagation
+ * (one graph SpMM per recurrence step for all trials, per-trial k, theta, mu)
+ * and the final eigSVD follow the single-trial path.  X: device n_trials x n x
+ * d FP32 (trial-major).  The first run, and the first with more trials than
+ * any run before, runs eagerly to size the scratch arena of the dense steps;
+ * in mode LNE_BATCH_GRAPH later runs capture the launch sequence once per
+ * (n_trials, largest k) and replay it.  Synchronises the stream.  st (may be
+ * NULL): shifted Cholesky count, nnz_counts.  Errors: EINVAL, ENOMEM, EHIP,
+ * ENUMERIC. */
+lne_status lne_batch_run(lne_batch *b, const lne_trial *trials, int32_t n_trials, int32_t mode,
+                         float *X, lne_stats *st);
+/* Stage entry of the batched SpMM: Y_t = M_t X_t for t < n_trials with M_t
+ * the trial matrix of trials[t] (as lne_trial_matrix), generated on the fly.
+ * X_t = X + t xs (xs = 0: one operand for all trials), n x k with rows ldx
+ * apart; Y_t = Y + t ys, rows ldy apart.  k % 4 == 0, k <= 256, X, Y,
+ * ldx, ldy, xs, ys 16-byte aligned; columns of X beyond k are not read.
+ * Synchronises the stream.  Errors: EINVAL. */
+lne_status lne_batch_spmm(lne_batch *b, const lne_trial *trials, int32_t n_trials,
+                          const float *X, int64_t ldx, int64_t xs, float *Y, int64_t ldy,
+                          int64_t ys, int32_t k);
+/* Launch shapes chosen by the tuner (0-based variant ids), nnz of the channel
+ * CSR and the number of graph captures so far; any pointer may be NULL.
+ * Host only.  Errors: EINVAL (b NULL). */
+lne_status lne_batch_info(const lne_batch *b, int32_t *spmm_variant, int32_t *gspmm_variant,
+                          int64_t *channel_nnz, int32_t *captures);
+/* Waits for the context's stream and releases the batch. */
+void lne_batch_destroy(lne_batch *b);
+
+/* One-shot batch: lne_batch_create, one eager lne_batch_run, lne_batch_destroy.
+ * st: attempted and accepted of the sampling pass, nnz_counts, shifted.
+ * Errors: those of the two calls; EUNSUPPORTED (n_trials outside 1..256). */
 lne_status lne_embed_batch(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                            const lne_trial *trials, int32_t n_trials, float *X, lne_stats *st);
 

@@ -103,6 +103,11 @@ SIGNATURES = [
     ("lne_sparsify_channels", _I32, [_P, _P, _P, _P, _P]),
     ("lne_trial_matrix", _I32, [_P, _P, _P, _P, _P, _P]),
     ("lne_embed_batch", _I32, [_P, _P, _P, _P, _I32, _P, _P]),
+    ("lne_batch_create", _I32, [_P, _P, _P, _I32, _P, _P]),
+    ("lne_batch_run", _I32, [_P, _P, _I32, _I32, _P, _P]),
+    ("lne_batch_info", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_batch_spmm", _I32, [_P, _P, _I32, _P, _I64, _I64, _P, _I64, _I64, _I32]),
+    ("lne_batch_destroy", None, [_P]),
     ("lne_mlp_param_count", _I64, [_I32, _I32]),
     ("lne_mlp_init", _I32, [_P, _I32, _I32, _U64, _P]),
     ("lne_mlp_forward", _I32, [_P, _I32, _I32, _P, _P, _I64, _P]),
@@ -207,8 +212,13 @@ class Context:
             except Exception:
                 return None
 
+        _delete = torch.cuda.caching_allocator_delete
+
         def _free(ptr, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                _delete(ptr)
+            except Exception:   # interpreter shutdown: torch is already torn down
+                pass
 
         if use_torch_allocator:
             self._alloc = _ALLOC_T(_alloc)
@@ -459,19 +469,91 @@ def trial_matrix(ctx: Context, rowptr, col, params: dict, channels: Csr, trial: 
     return out
 
 
+def _trial_array(trials):
+    return (TrialStruct * len(trials))(*[make_trial(t["s"], t["k"], t["theta"], t["mu"])
+                                         for t in trials])
+
+
 def embed_batch(ctx: Context, rowptr, col, params: dict, trials):
     """Embeddings of several trials (dicts with s, k, theta, mu) from one
     shared sampling pass; returns (n_trials x n x d FP32, stats)."""
     import torch
     g = graph_struct(rowptr, col)
     p = make_params(params, precision="f32")
-    arr = (TrialStruct * len(trials))(*[make_trial(t["s"], t["k"], t["theta"], t["mu"])
-                                        for t in trials])
+    arr = _trial_array(trials)
     X = torch.empty((len(trials), g.n, p.d), dtype=torch.float32, device=ctx.device)
     st = Stats()
     ctx.check(ctx.L.lne_embed_batch(ctx.h, ctypes.byref(g), ctypes.byref(p), arr, len(trials),
                                     X.data_ptr(), ctypes.byref(st)), "embed_batch")
     return X, st.as_dict()
+
+
+BATCH_EAGER, BATCH_GRAPH = 0, 1
+
+
+class Batch:
+    """Persistent per-graph state of the batched trials (lne_batch_*): one
+    channel sampling pass at construction, then any number of runs of up to
+    `max_trials` trials.  Holds references to the graph tensors, which the
+    library reads on every run."""
+
+    def __init__(self, ctx: Context, rowptr, col, params: dict, max_trials: int):
+        self.ctx = ctx
+        self._rp, self._col = rowptr, col
+        self._g = graph_struct(rowptr, col)
+        self._p = make_params(params, precision="f32")
+        self.max_trials = max_trials
+        self.h = ctypes.c_void_p()
+        st = Stats()
+        ctx.check(ctx.L.lne_batch_create(ctx.h, ctypes.byref(self._g), ctypes.byref(self._p),
+                                         max_trials, ctypes.byref(self.h), ctypes.byref(st)),
+                  "batch_create")
+        self.stats = st.as_dict()
+
+    def run(self, trials, graph: bool = False, out=None):
+        import torch
+        n, d = self._g.n, self._p.d
+        X = out if out is not None else torch.empty((len(trials), n, d), dtype=torch.float32,
+                                                    device=self.ctx.device)
+        arr = _trial_array(trials)
+        st = Stats()
+        self.ctx.check(self.ctx.L.lne_batch_run(self.h, arr, len(trials),
+                                                BATCH_GRAPH if graph else BATCH_EAGER,
+                                                X.data_ptr(), ctypes.byref(st)), "batch_run")
+        return X, st.as_dict()
+
+    def spmm(self, trials, X):
+        """Y[t] = M_t X[t] (X: n_trials x n x k, or n x k shared by all trials)."""
+        import torch
+        X = X.contiguous()
+        k = X.shape[-1]
+        n = self._g.n
+        xs = 0 if X.dim() == 2 else n * k
+        Y = torch.empty((len(trials), n, k), dtype=torch.float32, device=X.device)
+        arr = _trial_array(trials)
+        self.ctx.check(self.ctx.L.lne_batch_spmm(self.h, arr, len(trials), X.data_ptr(), k, xs,
+                                                 Y.data_ptr(), k, n * k, k), "batch_spmm")
+        return Y
+
+    def info(self):
+        sv, gv, cap = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        self.ctx.check(self.ctx.L.lne_batch_info(self.h, ctypes.byref(sv), ctypes.byref(gv),
+                                                 ctypes.byref(nnz), ctypes.byref(cap)),
+                       "batch_info")
+        return {"spmm_variant": sv.value, "graph_spmm_variant": gv.value,
+                "channel_nnz": nnz.value, "graph_captures": cap.value}
+
+    def close(self):
+        if self.h:
+            self.ctx.L.lne_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- surrogate network and scorer ------------------------------------------

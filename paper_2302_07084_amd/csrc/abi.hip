@@ -24,6 +24,14 @@ lne_status fail(lne_ctx *ctx, lne_status code, const char *fmt, ...) {
 
 void *dev_alloc(lne_ctx *ctx, size_t bytes) {
     if (bytes == 0) bytes = 1;
+    const size_t rounded = (bytes + 255) / 256 * 256;
+    if (ctx->arena_on) {
+        if (ctx->arena_used + rounded > ctx->arena_cap) return nullptr;
+        void *p = ctx->arena + ctx->arena_used;
+        ctx->arena_used += rounded;
+        return p;
+    }
+    if (ctx->arena_measure) ctx->arena_need += rounded;
     if (ctx->alloc) return ctx->alloc(bytes, ctx->user);
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
@@ -32,6 +40,7 @@ void *dev_alloc(lne_ctx *ctx, size_t bytes) {
 
 void dev_free(lne_ctx *ctx, void *p) {
     if (!p) return;
+    if (ctx->arena && (char *)p >= ctx->arena && (char *)p < ctx->arena + ctx->arena_cap) return;
     if (ctx->free_fn) ctx->free_fn(p, ctx->user);
     else (void)hipFree(p);
 }
@@ -52,7 +61,7 @@ lne_status alloc(lne_ctx *ctx, Buf &b, size_t bytes) {
 }
 
 Launch::Launch(lne_ctx *c, const char *n) : ctx(c), name(n) {
-    if (ctx->prof) {
+    if (ctx->prof && !ctx->capturing) {
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
         (void)hipEventRecord(a, ctx->stream);
@@ -175,7 +184,7 @@ lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arc
 
 // Modified Bessel function of the first kind, integer order, by its power
 // series sum_j (x/2)^(2j+n) / (j! (j+n)!).
-static double bessel_i(int n, double x) {
+double bessel_i(int n, double x) {
     double term = 1.0;
     for (int i = 1; i <= n; ++i) term *= (x / 2.0) / i;
     double sum = term;
@@ -461,9 +470,6 @@ static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p,
     return read_flags(ctx, f, st);
 }
 
-lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,
-                 int64_t ld, int32_t dt, double a, double b);
-
 static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                                  const void *X0, void *X) {
     const int64_t n = g->n;
@@ -516,6 +522,23 @@ static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_par
     LNE_TRY(eig_weights(ctx, V.as<double>(), lam.as<double>(), d, d, -0.25, W.as<double>(),
                         nullptr));
     return project(ctx, Z, dt, ld, n, d, W.as<double>(), d, X, dt, d, nullptr);
+}
+
+// The channel sampling pass of the batched trials: the sparsifier with the
+// walk length r kept in the key (column b << 4 | r - 1), as one CSR.
+lne_status channels_pass(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
+                         lne_stats *st) {
+    if (g->n > ((int64_t)1 << 30))
+        return fail(ctx, LNE_EUNSUPPORTED, "channel sparsifier: n above 2^30");
+    std::vector<lne_csr> blocks;
+    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
+        blocks.push_back(blk);
+        return LNE_OK;
+    };
+    lne_status s = sparsify_impl(ctx, g, p, st, sink, true);
+    if (s == LNE_OK) s = concat_rows(ctx, blocks, g->n, out);
+    for (auto &b : blocks) lne_csr_free(ctx, &b);
+    return s;
 }
 
 }  // namespace lne
@@ -808,257 +831,6 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     lne_csr_free(ctx, &M);
     if (s != LNE_OK) return s;
     return propagate_impl(ctx, g, p, X0.p, X);
-}
-
-static lne_status check_trial(lne_ctx *ctx, const lne_trial *t, int T) {
-    double tot = 0.0;
-    for (int r = 0; r < T; ++r) {
-        if (!(t->s[r] >= 0.0) || !std::isfinite(t->s[r]))
-            return fail(ctx, LNE_EINVAL, "trial: s must be finite and >= 0");
-        tot += t->s[r];
-    }
-    if (!(tot > 0.0)) return fail(ctx, LNE_EINVAL, "trial: s must have a positive sum");
-    if (t->cheb_k < 0 || t->cheb_k > 64 || !std::isfinite(t->theta) || t->theta < 0.0 ||
-        !std::isfinite(t->mu))
-        return fail(ctx, LNE_EINVAL, "trial: cheb_k in 0..64, theta >= 0, mu finite");
-    return LNE_OK;
-}
-
-// normalised s of each trial, 16 doubles per trial (zeros beyond T)
-static std::vector<double> trial_s(const lne_trial *trials, int ntr, int T) {
-    std::vector<double> s(16 * (size_t)ntr, 0.0);
-    for (int t = 0; t < ntr; ++t) {
-        double tot = 0.0;
-        for (int r = 0; r < T; ++r) tot += trials[t].s[r];
-        for (int r = 0; r < T; ++r) s[16 * t + r] = trials[t].s[r] / tot;
-    }
-    return s;
-}
-
-static double tl_scale(const lne_graph *g, const lne_params *p) {
-    const double vol = (double)g->n_arcs;
-    return vol * vol / (2.0 * (double)p->b * (double)p->M) / 65536.0;
-}
-
-static lne_status channels_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                                lne_csr *out, lne_stats *st) {
-    if (g->n > ((int64_t)1 << 30))
-        return fail(ctx, LNE_EUNSUPPORTED, "channel sparsifier: n above 2^30");
-    std::vector<lne_csr> blocks;
-    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
-        blocks.push_back(blk);
-        return LNE_OK;
-    };
-    lne_status s = sparsify_impl(ctx, g, p, st, sink, true);
-    if (s == LNE_OK) s = concat_rows(ctx, blocks, g->n, out);
-    for (auto &b : blocks) lne_csr_free(ctx, &b);
-    return s;
-}
-
-lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                                 lne_csr *out, lne_stats *st) {
-    if (!ctx) return LNE_EINVAL;
-    if (!out) return fail(ctx, LNE_EINVAL, "sparsify_channels: out is NULL");
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
-    std::memset(out, 0, sizeof(*out));
-    LNE_TRY(validate_graph_device(ctx, g));
-    return channels_impl(ctx, g, p, out, st);
-}
-
-lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                            const lne_csr *channels, const lne_trial *trial, lne_csr *out) {
-    if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
-    if (!channels || !trial || !out || channels->val_type != LNE_U64 ||
-        channels->n_rows != g->n || channels->n_cols != (g->n << 4))
-        return fail(ctx, LNE_EINVAL, "trial_matrix: channels must come from lne_sparsify_channels");
-    LNE_TRY(check_trial(ctx, trial, p->T));
-    std::memset(out, 0, sizeof(*out));
-    lne_csr st;
-    std::memset(&st, 0, sizeof(st));
-    Buf chan(ctx), sdev(ctx), vals(ctx);
-    LNE_TRY(split_channels(ctx, channels, p->T, &st, chan));
-    const std::vector<double> sh = trial_s(trial, 1, p->T);
-    lne_status s = alloc(ctx, sdev, sizeof(double) * 16);
-    if (s == LNE_OK) s = alloc(ctx, vals, sizeof(float) * (size_t)(st.nnz ? st.nnz : 1));
-    if (s == LNE_OK && hipMemcpyAsync(sdev.p, sh.data(), sizeof(double) * 16,
-                                      hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-        s = fail(ctx, LNE_EHIP, "trial_matrix: copy of s failed");
-    if (s == LNE_OK)
-        s = trial_values(ctx, g, &st, chan.as<uint64_t>(), p->T, sdev.as<double>(), 1,
-                         tl_scale(g, p), vals.as<float>());
-    if (s == LNE_OK) s = hipStreamSynchronize(ctx->stream) == hipSuccess ? LNE_OK : LNE_EHIP;
-    if (s != LNE_OK) {
-        lne_csr_free(ctx, &st);
-        return s;
-    }
-    st.val = vals.detach();
-    st.val_type = LNE_F32;
-    *out = st;
-    return LNE_OK;
-}
-
-lne_status lne_embed_batch(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                           const lne_trial *trials, int32_t n_trials, float *X, lne_stats *st) {
-    if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
-    if (!trials || !X) return fail(ctx, LNE_EINVAL, "embed_batch: NULL trials or X");
-    if (n_trials < 1 || n_trials > 256)
-        return fail(ctx, LNE_EUNSUPPORTED, "embed_batch: n_trials = %d outside 1..256", n_trials);
-    if (p->precision != LNE_F32)
-        return fail(ctx, LNE_EINVAL, "embed_batch: precision must be LNE_F32");
-    for (int t = 0; t < n_trials; ++t) LNE_TRY(check_trial(ctx, &trials[t], p->T));
-    if (st) std::memset(st, 0, sizeof(*st));
-    LNE_TRY(validate_graph_device(ctx, g));
-    const int ntr = n_trials, T = p->T;
-    const int64_t n = g->n;
-
-    // 1. one channel sampling pass, split into structure + channels
-    lne_csr ext, S;
-    std::memset(&ext, 0, sizeof(ext));
-    std::memset(&S, 0, sizeof(S));
-    LNE_TRY(channels_impl(ctx, g, p, &ext, st));
-    Buf chan(ctx);
-    lne_status s = split_channels(ctx, &ext, T, &S, chan);
-    lne_csr_free(ctx, &ext);
-    LNE_TRY(s);
-    struct Guard { lne_ctx *c; lne_csr *m; ~Guard() { lne_csr_free(c, m); } } guard{ctx, &S};
-
-    // 2. every trial's matrix values on the shared structure
-    Buf sdev(ctx), vals(ctx);
-    const std::vector<double> sh = trial_s(trials, ntr, T);
-    LNE_TRY(alloc(ctx, sdev, sizeof(double) * sh.size()));
-    LNE_TRY(alloc(ctx, vals, sizeof(float) * (size_t)(S.nnz ? S.nnz : 1) * ntr));
-    LNE_HIP(ctx, hipMemcpyAsync(sdev.p, sh.data(), sizeof(double) * sh.size(),
-                                hipMemcpyHostToDevice, ctx->stream));
-    LNE_TRY(trial_values(ctx, g, &S, chan.as<uint64_t>(), T, sdev.as<double>(), ntr,
-                         tl_scale(g, p), vals.as<float>()));
-    chan.release();
-    if (st) st->nnz_log = (uint64_t)S.nnz;
-
-    // 3. fast randomized SVD of all trials
-    const int32_t kp = p->d + p->oversample, d = p->d;
-    const int dp = (int)round8(kp), d8 = (int)round8(d);
-    const int64_t ld = (int64_t)ntr * dp, ldx = (int64_t)ntr * d8;
-    Buf A(ctx), B(ctx), X0(ctx);
-    LNE_TRY(alloc(ctx, A, sizeof(float) * (size_t)n * ld));
-    LNE_TRY(alloc(ctx, B, sizeof(float) * (size_t)n * ld));
-    LNE_TRY(alloc(ctx, X0, sizeof(float) * (size_t)n * ldx));
-    LNE_HIP(ctx, hipMemsetAsync(A.p, 0, sizeof(float) * (size_t)n * ld, ctx->stream));
-    Flags f;
-    LNE_TRY(make_flags(ctx, f));
-    float *Q = A.as<float>(), *Y = B.as<float>();
-    for (int t = 0; t < ntr; ++t)
-        LNE_TRY(launch_gaussian(ctx, n, kp, ld, p->seed, LNE_F32, Q + (int64_t)t * dp));
-    LNE_TRY(spmm_multi(ctx, &S, vals.as<float>(), ntr, Q, ld, Y, dp));
-    for (int t = 0; t < ntr; ++t) LNE_TRY(orth_impl(ctx, Y + (int64_t)t * dp, n, kp, ld, LNE_F32, f));
-    std::swap(Q, Y);
-    Buf W(ctx);
-    LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)kp * d));
-    for (int it = 1; it <= p->q; ++it) {
-        LNE_TRY(spmm_multi(ctx, &S, vals.as<float>(), ntr, Q, ld, Y, dp));
-        if (it < p->q) {
-            for (int t = 0; t < ntr; ++t)
-                LNE_TRY(orth_impl(ctx, Y + (int64_t)t * dp, n, kp, ld, LNE_F32, f));
-            std::swap(Q, Y);
-        } else {
-            for (int t = 0; t < ntr; ++t) {
-                Buf Vk(ctx), lam(ctx);
-                LNE_TRY(eig_of_gram(ctx, Y + (int64_t)t * dp, LNE_F32, n, kp, ld, Vk, lam));
-                LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, -0.25,
-                                    W.as<double>(), nullptr));
-                LNE_TRY(project(ctx, Y + (int64_t)t * dp, LNE_F32, ld, n, kp, W.as<double>(), d,
-                                X0.as<float>() + (int64_t)t * d8, LNE_F32, ldx, nullptr));
-            }
-        }
-    }
-    vals.release();
-    A.release();
-    B.release();
-
-    // 4. propagation of all trials with one wide graph SpMM per step
-    int K = 0;
-    std::vector<bool> on(ntr);
-    for (int t = 0; t < ntr; ++t) {
-        on[t] = trials[t].cheb_k > 0 && trials[t].theta >= 1e-12;
-        if (on[t]) K = std::max(K, (int)trials[t].cheb_k);
-    }
-    const float *Xsp = X0.as<float>();
-    Buf b0(ctx), b1(ctx), b2(ctx), bz(ctx), bc(ctx), coefd(ctx);
-    if (K > 0) {
-        for (Buf *b : {&b0, &b1, &b2, &bz, &bc}) LNE_TRY(alloc(ctx, *b, sizeof(float) * (size_t)n * ldx));
-        // coefficient table: 2K calls of the recurrence + the final D^-1 A
-        const int calls = 2 * K + 1;
-        std::vector<float> cf((size_t)calls * ntr * 5, 0.0f);
-        std::vector<std::vector<double>> cheb(ntr, std::vector<double>(K + 1, 0.0));
-        for (int t = 0; t < ntr; ++t) {
-            if (!on[t]) continue;
-            const double th = trials[t].theta;
-            for (int i = 0; i <= trials[t].cheb_k; ++i)
-                cheb[t][i] = (i == 0 ? 1.0 : 2.0 * ((i & 1) ? -1.0 : 1.0)) * std::exp(-th / 2.0) *
-                             bessel_i(i, th);
-        }
-        auto set = [&](int call, int t, float a, float b, float c1, float c2, float e) {
-            float *q = &cf[((size_t)call * ntr + t) * 5];
-            q[0] = a; q[1] = b; q[2] = c1; q[3] = c2; q[4] = e;
-        };
-        for (int t = 0; t < ntr; ++t) {
-            const float am = (float)(1.0 - trials[t].mu);
-            set(0, t, am, -1.f, 0.f, 0.f, 0.f);
-            set(1, t, 0.5f * am, -0.5f, -1.f, 0.f, (float)cheb[t][1]);
-            for (int i = 2; i <= K; ++i) {
-                set(2 * i - 2, t, am, -1.f, 0.f, 0.f, 0.f);
-                set(2 * i - 1, t, am, -1.f, -2.f, -1.f, (float)cheb[t][i]);
-            }
-            set(2 * K, t, 0.f, 1.f, 0.f, 0.f, 0.f);
-        }
-        LNE_TRY(alloc(ctx, coefd, sizeof(float) * cf.size()));
-        LNE_HIP(ctx, hipMemcpyAsync(coefd.p, cf.data(), sizeof(float) * cf.size(),
-                                    hipMemcpyHostToDevice, ctx->stream));
-        const float *C = coefd.as<float>();
-        auto cc = [&](int call) { return C + (size_t)call * ntr * 5; };
-        float *T0 = b0.as<float>(), *T1 = b1.as<float>(), *T2 = b2.as<float>(), *Z = bz.as<float>(),
-              *conv = bc.as<float>();
-        LNE_HIP(ctx, hipMemcpyAsync(T0, X0.p, sizeof(float) * (size_t)n * ldx,
-                                    hipMemcpyDeviceToDevice, ctx->stream));
-        for (int t = 0; t < ntr; ++t)
-            LNE_TRY(dense_scale(ctx, T0 + (int64_t)t * d8, LNE_F32, ldx, conv + (int64_t)t * d8,
-                                LNE_F32, ldx, n, d8, cheb[t][0]));
-        LNE_TRY(gspmm_multi(ctx, g, T0, ldx, ntr, d8, Z, nullptr, nullptr, nullptr, cc(0)));
-        LNE_TRY(gspmm_multi(ctx, g, Z, ldx, ntr, d8, T1, T0, nullptr, conv, cc(1)));
-        for (int i = 2; i <= K; ++i) {
-            LNE_TRY(gspmm_multi(ctx, g, T1, ldx, ntr, d8, Z, nullptr, nullptr, nullptr, cc(2 * i - 2)));
-            LNE_TRY(gspmm_multi(ctx, g, Z, ldx, ntr, d8, T2, T1, T0, conv, cc(2 * i - 1)));
-            float *tmp = T0;
-            T0 = T1;
-            T1 = T2;
-            T2 = tmp;
-        }
-        LNE_TRY(axpby(ctx, X0.p, conv, conv, n, (int32_t)ldx, ldx, LNE_F32, 1.0, -1.0));
-        LNE_TRY(gspmm_multi(ctx, g, conv, ldx, ntr, d8, Z, nullptr, nullptr, nullptr, cc(2 * K)));
-        Xsp = Z;
-    }
-    // 5. final eigSVD per trial (or X0 for trials with propagation off)
-    Buf Wd(ctx);
-    LNE_TRY(alloc(ctx, Wd, sizeof(double) * (size_t)d * d));
-    for (int t = 0; t < ntr; ++t) {
-        float *Xt = X + (int64_t)t * n * d;
-        if (!on[t]) {
-            LNE_TRY(dense_scale(ctx, X0.as<float>() + (int64_t)t * d8, LNE_F32, ldx, Xt, LNE_F32, d,
-                                n, d, 1.0));
-            continue;
-        }
-        Buf Vk(ctx), lam(ctx);
-        LNE_TRY(eig_of_gram(ctx, Xsp + (int64_t)t * d8, LNE_F32, n, d, ldx, Vk, lam));
-        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), d, d, -0.25, Wd.as<double>(),
-                            nullptr));
-        LNE_TRY(project(ctx, Xsp + (int64_t)t * d8, LNE_F32, ldx, n, d, Wd.as<double>(), d, Xt,
-                        LNE_F32, d, nullptr));
-    }
-    return read_flags(ctx, f, st);
 }
 
 }  // extern "C"

@@ -23,6 +23,14 @@ struct lne_ctx {
     struct Mark { std::string name; hipEvent_t a, b; };
     std::vector<Mark> marks;
     std::map<std::string, std::pair<double, int64_t>> prof_acc;
+    // Bump arena: while arena_on, scratch comes from [arena, arena + arena_cap)
+    // and is never returned, so a sequence of launches can be captured into a
+    // graph and replayed with the same addresses; while arena_measure, every
+    // request's rounded size is added to arena_need (the memory is real).
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0, arena_need = 0;
+    bool arena_on = false, arena_measure = false;
+    bool capturing = false;   // no event bracketing while a graph is captured
 };
 
 namespace lne {
@@ -158,31 +166,42 @@ lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out
                       int64_t ld, int32_t k, int32_t dtype, double a, double b,
                       const void *E1, double c1, const void *E2, double c2, void *acc,
                       double cacc);
+// out = a x + b y over n rows of k columns (rows ld apart), dt F64 or F32.
+lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,
+                 int64_t ld, int32_t dt, double a, double b);
 // Dense elementwise: y = alpha x (conversion between dtypes allowed).
 lne_status dense_scale(lne_ctx *ctx, const void *x, int32_t xt, int64_t ldx, void *y,
                        int32_t yt, int64_t ldy, int64_t n, int32_t k, double alpha);
 
 // ---- dense (k_dense.hip) -------------------------------------------------------
+// Every dense step also runs on a batch of nb independent problems in one
+// launch: operand b starts at its base pointer + b * (its stride), the k x k
+// results of entry b at + b k k, and entry b's flags (skip, status, shifted,
+// run_next) at + kFlagStride b.
+constexpr int kFlagStride = 4;
 // G (k x k, FP64, leading dimension k) = Y^T Y.
 lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k,
-                int64_t ld, double *G, const int32_t *skip);
+                int64_t ld, double *G, const int32_t *skip, int32_t nb = 1, int64_t ys = 0);
 // out (n x kout, out_t) = Y (n x kin, y_t) W (kin x kout, FP64 device, ld kout).
 lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_t n,
                    int32_t kin, const double *W, int32_t kout, void *out, int32_t out_t,
-                   int64_t ldo, const int32_t *skip);
+                   int64_t ldo, const int32_t *skip, int32_t nb = 1, int64_t ys = 0,
+                   int64_t ws = 0, int64_t os = 0);
 // Upper Cholesky G = R^T R in place (R in upper triangle, lower zeroed) and
 // W = R^-1; on breakdown retries with a shift and sets *shifted.  mode 0:
 // plain; mode 1: the shift is always allowed.  status: 0 ok, 1 failed.
 lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *status,
                     int32_t *shifted, int64_t n_rows, const int32_t *skip,
-                    int32_t *skip_next);
+                    int32_t *skip_next, int32_t nb = 1);
 // Symmetric eigen-decomposition of C (k x k, FP64): V (k x k, columns = vectors),
 // lam (k), sorted by decreasing eigenvalue.  C is overwritten.
-lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam);
+lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb = 1);
 // W (k x kout) = V[:, :kout] diag(f(lam)) with f = lam^pow (0 for
-// lam <= k eps lam_max); S (kout) = sqrt(lam) (optional).
+// lam <= k eps lam_max); S (kout) = sqrt(lam) (optional).  Entries b with
+// on[b] == 0 (on may be NULL) get W = I and S = 1 instead (k == kout).
 lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t k,
-                       int32_t kout, double power, double *W, double *S);
+                       int32_t kout, double power, double *W, double *S, int32_t nb = 1,
+                       const int32_t *on = nullptr);
 
 // ---- batched trials (k_batch.hip) ------------------------------------------------
 // Extended count CSR (columns col << 4 | r - 1) -> structure (val NULL) plus
@@ -191,15 +210,32 @@ lne_status split_channels(lne_ctx *ctx, const lne_csr *ext, int T, lne_csr *st, 
 // vals[entry * ntr + t]: truncated log of trial t's mixed counts (0 if dropped).
 lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, const uint64_t *chan,
                         int T, const double *s_dev, int ntr, double scale, float *vals);
-// Y = M_t X_t for every trial t, slices of width dp in n x ld matrices.
-lne_status spmm_multi(lne_ctx *ctx, const lne_csr *st, const float *vals, int ntr, const float *X,
-                      int64_t ld, float *Y, int dp);
-// Wide graph SpMM with per-trial epilogue coefficients coef[5 t + {a, b, c1, c2, e}].
-lne_status gspmm_multi(lne_ctx *ctx, const lne_graph *g, const float *Z, int64_t ld, int ntr,
-                       int dp, float *out, const float *E1, const float *E2, float *acc,
-                       const float *coef);
+// Y_t (rows ldy apart, trials ys apart) = M_t X_t (ldx, xs; xs = 0 shares one
+// operand) for ntr trials, M_t generated from the channel CSR `ext` with
+// coef[16 t + r - 1] = T s_t[r] and scale = vol^2 / (2 b M 2^16); k <= 256,
+// k % 4 == 0, X's columns up to k zero-padded.  variant: launch shape 0..5.
+lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, const lne_graph *g, int ntr,
+                     const double *coef, double scale, const float *X, int64_t ldx, int64_t xs,
+                     float *Y, int64_t ldy, int64_t ys, int k, int variant);
+constexpr int kSpmmChanVariants = 6;
+// Propagation step for ntr trials (blocks zs apart, rows ld apart, k columns):
+// out = a Z + b D^-1 A Z + c1 E1 + c2 E2, acc += e out, coef[5 t + {a, b, c1,
+// c2, e}]; E1, E2, acc may be NULL.  variant: launch shape 0..3.
+lne_status gspmm_batch(lne_ctx *ctx, const lne_graph *g, int ntr, int k, int64_t ld, int64_t zs,
+                       const float *Z, float *out, const float *E1, const float *E2, float *acc,
+                       const float *coef, int variant);
+constexpr int kGspmmBatchVariants = 4;
+// y[i] = alpha[i / per] x[i], i < count.
+lne_status scale_blocks(lne_ctx *ctx, const float *x, float *y, int64_t count, int64_t per,
+                        const float *alpha);
+// p[0..count) = v (32-bit words), a kernel so that it can sit in a captured graph.
+lne_status fill_u32(lne_ctx *ctx, void *p, int64_t count, uint32_t v);
+double bessel_i(int n, double x);
+// The channel sampling pass (lengths kept in the columns) into one CSR.
+lne_status channels_pass(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
+                         lne_stats *st);
 
-// ---- pipeline (pipeline.cpp) ---------------------------------------------------
+// ---- validation (abi.hip) -------------------------------------------------------
 lne_status validate_graph(lne_ctx *ctx, const lne_graph *g);
 lne_status validate_params(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
                            bool need_linalg);

@@ -7,12 +7,12 @@
 // expectation of its own sampler; the truncated logarithm is applied per
 // trial on the shared structure (dropped entries keep an explicit zero).
 //
-// The rSVD products of all trials run as one "wide" SpMM: the dense operand
-// of trial t is columns [t dp, t dp + k') of an n x (trials dp) matrix, so
-// every gathered row serves every trial, each multiplied by its own value.
-// Propagation likewise runs one wide graph SpMM per step, with the epilogue
-// coefficients (1 - mu_t, Chebyshev weights of trial t) looked up per column
-// block.
+// Nothing per trial is materialised at the size of the matrix: each SpMM of
+// trial t regenerates M_t's values from the channel CSR while it streams it,
+// and the dense blocks of all trials (n x k' each, trial-major) go through
+// one launch per step (batched Gram, Cholesky, eigen-solves and projections,
+// one channel SpMM over every (trial, row) pair, one graph SpMM per
+// propagation step with per-trial epilogue coefficients).
 #include "common.hpp"
 
 namespace lne {
@@ -90,94 +90,163 @@ __global__ void k_trial_values(const int64_t *__restrict__ grp, const int64_t *_
     }
 }
 
-// Y[row, c] = sum_i vals[i ntr + c / dp] X[col_i, c] over the row's entries,
-// one wave per (row, 256-column block), float4 per lane.
+// Y_t = M_t X_t for trials t = 0..ntr-1 with M_t generated on the fly from
+// the channel CSR: for every (row a, column b) structure entry -- a run of
+// channel entries with the same b, ascending r -- the head lane of the run
+// sums coef_t[r] W_r (coef_t[r] = T s_t[r]), forms x = scale sum / (d_a d_b)
+// and the truncated logarithm ln x (0 if x <= 1).  The nonzero values of a
+// 64-entry chunk are compacted to the low lanes with one ds_permute, then the
+// wave gathers the X rows of those entries, U rows in flight per lane, lane l
+// holding columns 4l..4l+3 (k <= 256, k % 4 == 0, padding columns of X zero).
+// TM: waves enumerate (trial, row) trial-major (consecutive waves share a
+// trial's operand) or row-major (consecutive waves share a row's entries).
+template <int U, bool TM>
 __global__ void __launch_bounds__(256)
-k_spmm_multi(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-             const float *__restrict__ vals, int ntr, int64_t n_rows, const float *__restrict__ X,
-             int64_t ld, float *__restrict__ Y, int dp, int ncb) {
+k_spmm_chan(const int64_t *__restrict__ rp, const int32_t *__restrict__ ecol,
+            const uint64_t *__restrict__ W, const int64_t *__restrict__ grp, int64_t n, int ntr,
+            const double *__restrict__ coef, double scale, const float *__restrict__ X,
+            int64_t ldx, int64_t xs, float *__restrict__ Y, int64_t ldy, int64_t ys, int k) {
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w >= n_rows * ncb) return;
-    const int64_t row = w / ncb;
-    const int cb = (int)(w - row * ncb);
+    if (w >= n * ntr) return;
+    int64_t row;
+    int t;
+    if (TM) {
+        t = (int)(w / n);
+        row = w - (int64_t)t * n;
+    } else {
+        row = w / ntr;
+        t = (int)(w - row * ntr);
+    }
     const int lane = threadIdx.x & 63;
-    const int c0 = cb * 256 + lane * 4;
-    const bool active = c0 < ntr * dp;
-    const int trial = active ? c0 / dp : 0;
+    const int c0 = lane * 4;
+    const bool act = c0 < k;
+    X += (int64_t)t * xs;
+    Y += (int64_t)t * ys;
+    coef += 16 * t;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t beg = rp[row], end = rp[row + 1];
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const double da = (double)(grp[row + 1] - grp[row]);
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t b0 = beg; b0 < end; b0 += 64) {
-        const int64_t idx = b0 + lane;
-        const int32_t cj = idx < end ? col[idx] : 0;
-        const int cnt = (int)min((int64_t)64, end - b0);
-        for (int t0 = 0; t0 < cnt; t0 += 4) {
-            int32_t j[4];
-            float v[4];
-            float4 x[4];
+        const int64_t i = b0 + lane;
+        const bool valid = i < end;
+        const int32_t ec = valid ? ecol[i] : -16;
+        int32_t pe = __shfl_up(ec, 1, 64);
+        if (lane == 0) pe = b0 > beg ? ecol[b0 - 1] : -16;
+        const int32_t jb = ec >> 4;
+        const bool head = valid && (pe >> 4) != jb;
+        float v = 0.f;
+        if (head) {
+            double sum = 0.0;
+            for (int64_t j = i; j < end; ++j) {
+                const int32_t e = ecol[j];
+                if ((e >> 4) != jb) break;
+                sum += coef[e & 15] * (double)W[j];
+            }
+            const double x = scale * sum / (da * (double)(grp[jb + 1] - grp[jb]));
+            v = x > 1.0 ? (float)log(x) : 0.f;
+        }
+        const bool take = v != 0.f;
+        const uint64_t mask = __ballot(take);
+        const int cnt = __popcll(mask);
+        // a permutation of the 64 lanes: kept entries first, in order
+        const int dst = take ? __popcll(mask & lt) : cnt + __popcll(~mask & lt);
+        const int jc = __builtin_amdgcn_ds_permute(dst << 2, jb);
+        const float vc = __int_as_float(__builtin_amdgcn_ds_permute(dst << 2, __float_as_int(v)));
+        for (int t0 = 0; t0 < cnt; t0 += U) {
+            int32_t j[U];
+            float vv[U];
+            float4 x[U];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) j[q] = __shfl(cj, (t0 + q) & 63);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const bool ok = active && t0 + q < cnt;
-                v[q] = ok ? vals[(b0 + t0 + q) * ntr + trial] : 0.f;
-                x[q] = ok ? *reinterpret_cast<const float4 *>(X + (int64_t)j[q] * ld + c0)
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int q = 0; q < U; ++q) {
+                j[q] = __shfl(jc, (t0 + q) & 63, 64);
+                vv[q] = __shfl(vc, (t0 + q) & 63, 64);
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc[0] += v[q] * x[q].x;
-                acc[1] += v[q] * x[q].y;
-                acc[2] += v[q] * x[q].z;
-                acc[3] += v[q] * x[q].w;
+            for (int q = 0; q < U; ++q)
+                x[q] = (act && t0 + q < cnt)
+                           ? *reinterpret_cast<const float4 *>(X + (int64_t)j[q] * ldx + c0)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const float f = t0 + q < cnt ? vv[q] : 0.f;
+                acc.x += f * x[q].x;
+                acc.y += f * x[q].y;
+                acc.z += f * x[q].z;
+                acc.w += f * x[q].w;
             }
         }
     }
-    if (active)
-        *reinterpret_cast<float4 *>(Y + row * ld + c0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    if (act) *reinterpret_cast<float4 *>(Y + row * ldy + c0) = acc;
 }
 
-// out = a_t Z + b_t D^-1 A Z + c1_t E1 + c2_t E2; acc += e_t out; coefficients
-// coef[5 t + {0..4}] of the trial owning the column.
+// Propagation step of every trial: out_t = a_t Z_t + b_t D^-1 A Z_t + c1_t E1_t
+// + c2_t E2_t and accum_t += e_t out_t, coefficients coef[5 t + {0..4}].  The
+// trials' n x ld blocks are zs apart.  L lanes (float4 each) per gathered row,
+// 64 / L gathered rows per step of the wave, U steps in flight.
+template <int L, int U, bool TM>
 __global__ void __launch_bounds__(256)
-k_gspmm_multi(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n_rows,
-              const float *__restrict__ Z, int64_t ld, int ntr, int dp, int ncb,
+k_gspmm_batch(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
+              int ntr, int k, int64_t ld, int64_t zs, const float *__restrict__ Z,
               float *__restrict__ out, const float *__restrict__ E1, const float *__restrict__ E2,
               float *__restrict__ accum, const float *__restrict__ coef) {
+    constexpr int G = 64 / L;
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w >= n_rows * ncb) return;
-    const int64_t row = w / ncb;
-    const int cb = (int)(w - row * ncb);
+    if (w >= n * ntr) return;
+    int64_t row;
+    int t;
+    if (TM) {
+        t = (int)(w / n);
+        row = w - (int64_t)t * n;
+    } else {
+        row = w / ntr;
+        t = (int)(w - row * ntr);
+    }
     const int lane = threadIdx.x & 63;
-    const int c0 = cb * 256 + lane * 4;
-    const bool active = c0 < ntr * dp;
+    const int gi = lane / L, c0 = (lane % L) * 4;
+    const bool act = c0 < k;
+    const int64_t off = (int64_t)t * zs;
+    Z += off;
     const int64_t beg = rp[row], end = rp[row + 1];
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t b0 = beg; b0 < end; b0 += 64) {
         const int64_t idx = b0 + lane;
         const int32_t cj = idx < end ? col[idx] : 0;
         const int cnt = (int)min((int64_t)64, end - b0);
-        for (int t0 = 0; t0 < cnt; t0 += 4) {
-            int32_t j[4];
+        for (int t0 = 0; t0 < cnt; t0 += U * G) {
+            int32_t j[U];
+            float4 x[U];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) j[q] = __shfl(cj, (t0 + q) & 63);
+            for (int q = 0; q < U; ++q) j[q] = __shfl(cj, (t0 + gi + q * G) & 63, 64);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (active && t0 + q < cnt) {
-                    const float4 x = *reinterpret_cast<const float4 *>(Z + (int64_t)j[q] * ld + c0);
-                    s.x += x.x; s.y += x.y; s.z += x.z; s.w += x.w;
-                }
+            for (int q = 0; q < U; ++q)
+                x[q] = (act && t0 + gi + q * G < cnt)
+                           ? *reinterpret_cast<const float4 *>(Z + (int64_t)j[q] * ld + c0)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                s.x += x[q].x;
+                s.y += x[q].y;
+                s.z += x[q].z;
+                s.w += x[q].w;
             }
         }
     }
-    if (!active) return;
-    const int t = c0 / dp;
-    const float a = coef[5 * t], b = coef[5 * t + 1], c1 = coef[5 * t + 2], c2 = coef[5 * t + 3],
-                e = coef[5 * t + 4];
+#pragma unroll
+    for (int o = L; o < 64; o <<= 1) {
+        s.x += __shfl_xor(s.x, o, 64);
+        s.y += __shfl_xor(s.y, o, 64);
+        s.z += __shfl_xor(s.z, o, 64);
+        s.w += __shfl_xor(s.w, o, 64);
+    }
+    if (gi != 0 || !act) return;
+    const float *cf = coef + 5 * t;
+    const float a = cf[0], b = cf[1], c1 = cf[2], c2 = cf[3], e = cf[4];
     const float inv = end > beg ? 1.0f / (float)(end - beg) : 0.0f;
-    const int64_t o = row * ld + c0;
-    const float4 z = *reinterpret_cast<const float4 *>(Z + o);
-    float4 r = make_float4(a * z.x + b * inv * s.x, a * z.y + b * inv * s.y,
-                           a * z.z + b * inv * s.z, a * z.w + b * inv * s.w);
+    const int64_t o = off + row * ld + c0;
+    const float4 z = *reinterpret_cast<const float4 *>(Z + row * ld + c0);
+    float4 r = make_float4(a * z.x + b * (inv * s.x), a * z.y + b * (inv * s.y),
+                           a * z.z + b * (inv * s.z), a * z.w + b * (inv * s.w));
     if (E1) {
         const float4 q = *reinterpret_cast<const float4 *>(E1 + o);
         r.x += c1 * q.x; r.y += c1 * q.y; r.z += c1 * q.z; r.w += c1 * q.w;
@@ -192,6 +261,18 @@ k_gspmm_multi(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, i
         q.x += e * r.x; q.y += e * r.y; q.z += e * r.z; q.w += e * r.w;
         *reinterpret_cast<float4 *>(accum + o) = q;
     }
+}
+
+// y = alpha[i / per] x over `count` floats (alpha per trial block of `per`)
+__global__ void k_scale_blocks(const float *__restrict__ x, float *__restrict__ y, int64_t count,
+                               int64_t per, const float *__restrict__ alpha) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) y[i] = alpha[i / per] * x[i];
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t count, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
 }
 
 }  // namespace
@@ -244,30 +325,84 @@ lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, con
     return check_launch(ctx, "trial_values");
 }
 
-lne_status spmm_multi(lne_ctx *ctx, const lne_csr *st, const float *vals, int ntr, const float *X,
-                      int64_t ld, float *Y, int dp) {
-    if (dp % 4 || ld % 4 || (uintptr_t)X % 16 || (uintptr_t)Y % 16)
-        return fail(ctx, LNE_EINVAL, "spmm_multi: 16-byte aligned slices required");
-    const int ncb = (ntr * dp + 255) / 256;
+lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, const lne_graph *g, int ntr,
+                     const double *coef, double scale, const float *X, int64_t ldx, int64_t xs,
+                     float *Y, int64_t ldy, int64_t ys, int k, int variant) {
+    if (k % 4 || k > 256 || ldx % 4 || ldy % 4 || xs % 4 || ys % 4 || (uintptr_t)X % 16 ||
+        (uintptr_t)Y % 16)
+        return fail(ctx, LNE_EINVAL, "spmm_chan: k <= 256, k %% 4 == 0 and 16-byte aligned rows");
+    const int64_t n = ext->n_rows;
+    if (n == 0 || ntr == 0) return LNE_OK;
+    const unsigned grid = grid_of(n * ntr * 64, 256);
     {
-        Launch L(ctx, "spmm_multi");
-        k_spmm_multi<<<grid_of(st->n_rows * ncb * 64, 256), 256, 0, ctx->stream>>>(
-            st->row_ptr, st->col, vals, ntr, st->n_rows, X, ld, Y, dp, ncb);
+        Launch L(ctx, "spmm_chan");
+#define LNE_SC(UU, TMM)                                                                   \
+    k_spmm_chan<UU, TMM><<<grid, 256, 0, ctx->stream>>>(ext->row_ptr, ext->col,           \
+                                                        (const uint64_t *)ext->val,       \
+                                                        g->row_ptr, n, ntr, coef, scale,  \
+                                                        X, ldx, xs, Y, ldy, ys, k)
+        switch (variant) {
+            case 0: LNE_SC(4, true); break;
+            case 1: LNE_SC(2, true); break;
+            case 2: LNE_SC(8, true); break;
+            case 3: LNE_SC(4, false); break;
+            case 4: LNE_SC(2, false); break;
+            case 5: LNE_SC(8, false); break;
+            default: return fail(ctx, LNE_EINVAL, "spmm_chan: variant %d", variant);
+        }
+#undef LNE_SC
     }
-    return check_launch(ctx, "spmm_multi");
+    return check_launch(ctx, "spmm_chan");
 }
 
-lne_status gspmm_multi(lne_ctx *ctx, const lne_graph *g, const float *Z, int64_t ld, int ntr,
-                       int dp, float *out, const float *E1, const float *E2, float *acc,
-                       const float *coef) {
-    if (dp % 4 || ld % 4) return fail(ctx, LNE_EINVAL, "gspmm_multi: aligned slices required");
-    const int ncb = (ntr * dp + 255) / 256;
+lne_status gspmm_batch(lne_ctx *ctx, const lne_graph *g, int ntr, int k, int64_t ld, int64_t zs,
+                       const float *Z, float *out, const float *E1, const float *E2, float *acc,
+                       const float *coef, int variant) {
+    if (k % 4 || k > 256 || ld % 4 || zs % 4 || (uintptr_t)Z % 16 || (uintptr_t)out % 16)
+        return fail(ctx, LNE_EINVAL, "gspmm_batch: k <= 256, k %% 4 == 0 and aligned rows");
+    const int64_t n = g->n;
+    if (n == 0 || ntr == 0) return LNE_OK;
+    const unsigned grid = grid_of(n * ntr * 64, 256);
+    const bool wide = k > 128;
     {
-        Launch L(ctx, "graph_spmm_multi");
-        k_gspmm_multi<<<grid_of(g->n * ncb * 64, 256), 256, 0, ctx->stream>>>(
-            g->row_ptr, g->col, g->n, Z, ld, ntr, dp, ncb, out, E1, E2, acc, coef);
+        Launch L(ctx, "graph_spmm_batch");
+#define LNE_GB(LL, UU, TMM)                                                                  \
+    k_gspmm_batch<LL, UU, TMM><<<grid, 256, 0, ctx->stream>>>(g->row_ptr, g->col, n, ntr, k, \
+                                                             ld, zs, Z, out, E1, E2, acc,   \
+                                                             coef)
+        switch (variant * 2 + (wide ? 1 : 0)) {
+            case 0: LNE_GB(32, 4, true); break;
+            case 1: LNE_GB(64, 4, true); break;
+            case 2: LNE_GB(32, 2, true); break;
+            case 3: LNE_GB(64, 2, true); break;
+            case 4: LNE_GB(32, 4, false); break;
+            case 5: LNE_GB(64, 4, false); break;
+            case 6: LNE_GB(32, 2, false); break;
+            case 7: LNE_GB(64, 2, false); break;
+            default: return fail(ctx, LNE_EINVAL, "gspmm_batch: variant %d", variant);
+        }
+#undef LNE_GB
     }
-    return check_launch(ctx, "graph_spmm_multi");
+    return check_launch(ctx, "graph_spmm_batch");
+}
+
+lne_status scale_blocks(lne_ctx *ctx, const float *x, float *y, int64_t count, int64_t per,
+                        const float *alpha) {
+    if (count == 0) return LNE_OK;
+    {
+        Launch L(ctx, "scale_blocks");
+        k_scale_blocks<<<grid_of(count, 256), 256, 0, ctx->stream>>>(x, y, count, per, alpha);
+    }
+    return check_launch(ctx, "scale_blocks");
+}
+
+lne_status fill_u32(lne_ctx *ctx, void *p, int64_t count, uint32_t v) {
+    if (count == 0) return LNE_OK;
+    {
+        Launch L(ctx, "fill");
+        k_fill_u32<<<grid_of(count, 256), 256, 0, ctx->stream>>>((uint32_t *)p, count, v);
+    }
+    return check_launch(ctx, "fill");
 }
 
 }  // namespace lne

@@ -36,7 +36,10 @@ constexpr int kGramThreads = 512;
 template <class YT, int MAXT>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t rows_per_wg,
-         double *__restrict__ part, const int32_t *__restrict__ skip) {
+         double *__restrict__ part, const int32_t *__restrict__ skip, int64_t ys) {
+    Y += (int64_t)blockIdx.y * ys;
+    part += (int64_t)blockIdx.y * gridDim.x * KP * KP;
+    if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
     __shared__ double tile[kGramRows * 288];       // kGramRows x KP
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -89,7 +92,11 @@ constexpr int kTS = 40;   // LDS row stride (bf16) of the transposed tile: 80 B
 template <int MAXT>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
-            int64_t rows_per_wg, double *__restrict__ part, const int32_t *__restrict__ skip) {
+            int64_t rows_per_wg, double *__restrict__ part, const int32_t *__restrict__ skip,
+            int64_t ys) {
+    Y += (int64_t)blockIdx.y * ys;
+    part += (int64_t)blockIdx.y * gridDim.x * KP * KP;
+    if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
     __shared__ __attribute__((aligned(16))) __bf16 tt[288 * kTS];   // KP x kTS, transposed
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -134,6 +141,9 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
 
 __global__ void k_gram_reduce(const double *__restrict__ part, int nwg, int KP, int k,
                               double *__restrict__ G, const int32_t *__restrict__ skip) {
+    part += (int64_t)blockIdx.y * nwg * KP * KP;
+    G += (int64_t)blockIdx.y * k * k;
+    if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)k * k) return;
@@ -154,7 +164,11 @@ template <class YT, class OT, int MAXJ>
 __global__ void __launch_bounds__(kProjThreads)
 k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
          const double *__restrict__ W, int kout, OT *__restrict__ out, int64_t ldo,
-         const int32_t *__restrict__ skip) {
+         const int32_t *__restrict__ skip, int64_t ys, int64_t ws, int64_t os) {
+    Y += (int64_t)blockIdx.y * ys;
+    W += (int64_t)blockIdx.y * ws;
+    out += (int64_t)blockIdx.y * os;
+    if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
     __shared__ double As[kProjRows * kAS];
     __shared__ double Ws[kKC * 16 * MAXJ];
@@ -208,7 +222,11 @@ template <class OT, int MAXJ>
 __global__ void __launch_bounds__(kProjThreads)
 k_proj_bf16(const __bf16 *__restrict__ Y, int64_t ldy, int64_t n, int kin,
             const __bf16 *__restrict__ Wt, int ldw, int kout, OT *__restrict__ out,
-            int64_t ldo, const int32_t *__restrict__ skip) {
+            int64_t ldo, const int32_t *__restrict__ skip, int64_t ys, int64_t os) {
+    Y += (int64_t)blockIdx.y * ys;
+    Wt += (int64_t)blockIdx.y * kout * ldw;
+    out += (int64_t)blockIdx.y * os;
+    if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
     __shared__ __attribute__((aligned(16))) __bf16 As[kProjRows * kTS];
     __shared__ __attribute__((aligned(16))) __bf16 Ws[16 * MAXJ * kTS];
@@ -255,7 +273,9 @@ k_proj_bf16(const __bf16 *__restrict__ Y, int64_t ldy, int64_t n, int kin,
 }
 
 __global__ void k_w_to_bf16t(const double *__restrict__ W, int kin, int kout,
-                             __bf16 *__restrict__ Wt, int ldw) {
+                             __bf16 *__restrict__ Wt, int ldw, int64_t ws) {
+    W += (int64_t)blockIdx.y * ws;
+    Wt += (int64_t)blockIdx.y * kout * ldw;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)kin * kout) return;
     const int i = (int)(t / kout), c = (int)(t % kout);
@@ -298,6 +318,16 @@ __global__ void __launch_bounds__(kSolveThreads)
 k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__restrict__ diag0,
            int32_t *__restrict__ status, int32_t *__restrict__ shifted, int64_t n_rows,
            const int32_t *__restrict__ skip, int32_t *__restrict__ run_next) {
+    {
+        const int64_t b = blockIdx.x;
+        G += b * k * k;
+        W += b * k * k;
+        diag0 += b * k;
+        status += kFlagStride * b;
+        shifted += kFlagStride * b;
+        if (skip) skip += kFlagStride * b;
+        if (run_next) run_next += kFlagStride * b;
+    }
     if (skip && *skip == 0) {
         if (run_next && threadIdx.x == 0) *run_next = 0;
         return;
@@ -353,6 +383,13 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
 __global__ void __launch_bounds__(kSolveThreads)
 k_sym_eig(double *__restrict__ A, int k, double *__restrict__ Vw, double *__restrict__ V,
           double *__restrict__ lam) {
+    {
+        const int64_t b = blockIdx.x;
+        A += b * k * k;
+        Vw += b * k * k;
+        V += b * k * k;
+        lam += b * k;
+    }
     __shared__ double cs[160], sn[160];
     __shared__ int pp[160], qq[160];
     __shared__ double red[kSolveThreads / 64][2];
@@ -447,8 +484,19 @@ k_sym_eig(double *__restrict__ A, int k, double *__restrict__ Vw, double *__rest
 
 __global__ void k_eig_weights(const double *__restrict__ V, const double *__restrict__ lam,
                               int k, int kout, double power, double *__restrict__ W,
-                              double *__restrict__ S) {
+                              double *__restrict__ S, const int32_t *__restrict__ on) {
+    const int64_t b = blockIdx.y;
+    V += b * k * k;
+    lam += b * k;
+    if (W) W += b * k * kout;
+    if (S) S += b * kout;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (on && on[b] == 0) {
+        // pass-through entry: identity weights
+        if (W && t < (int64_t)k * kout) W[t] = (t / kout == t % kout) ? 1.0 : 0.0;
+        if (S && t < kout) S[t] = 1.0;
+        return;
+    }
     const double lmax = lam[0] > 0.0 ? lam[0] : 0.0;
     const double floor_ = (double)k * 2.220446049250313e-16 * lmax;
     if (S && t < kout) {
@@ -466,22 +514,26 @@ __global__ void k_eig_weights(const double *__restrict__ V, const double *__rest
 
 // ---------------------------------------------------------------- host side
 lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k, int64_t ld,
-                double *G, const int32_t *skip) {
+                double *G, const int32_t *skip, int32_t nb, int64_t ys) {
     const int KP = ((k + 15) / 16) * 16;
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
     const int per_wave = (ntu + 7) / 8;
     if (per_wave > 22) return fail(ctx, LNE_EUNSUPPORTED, "gram: k = %d above 288", k);
+    if (nb < 1 || nb > 65535) return fail(ctx, LNE_EINVAL, "gram: batch of %d", nb);
     const int64_t blocks_rows = ceil_div(n > 0 ? n : 1, kGramRows);
-    const int nwg = (int)std::min<int64_t>(blocks_rows, KP > 160 ? 256 : 512);
+    // about 512 (256 for wide k) workgroups over the whole batch
+    const int64_t target = std::max<int64_t>(1, (KP > 160 ? 256 : 512) / nb);
+    const int nwg = (int)std::min<int64_t>(blocks_rows, target);
     const int64_t rows_per_wg = ceil_div(blocks_rows, nwg) * kGramRows;
     Buf part(ctx);
-    LNE_TRY(alloc(ctx, part, sizeof(double) * (size_t)nwg * KP * KP));
+    LNE_TRY(alloc(ctx, part, sizeof(double) * (size_t)nb * nwg * KP * KP));
+    const dim3 grid((unsigned)nwg, (unsigned)nb);
     {
         Launch L(ctx, "gram");
         if (dtype == LNE_BF16) {
 #define LNE_GB(MT)                                                                       \
-    k_gram_bf16<MT><<<nwg, kGramThreads, 0, ctx->stream>>>(                            \
-        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip)
+    k_gram_bf16<MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
+        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys)
             if (per_wave <= 1) LNE_GB(1);
             else if (per_wave <= 6) LNE_GB(6);
             else if (per_wave <= 12) LNE_GB(12);
@@ -489,8 +541,8 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
 #undef LNE_GB
         } else {
 #define LNE_G64(T, MT)                                                                   \
-    k_gram64<T, MT><<<nwg, kGramThreads, 0, ctx->stream>>>(                            \
-        (const T *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip)
+    k_gram64<T, MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
+        (const T *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys)
             if (dtype == LNE_F64) {
                 if (per_wave <= 1) LNE_G64(double, 1);
                 else if (per_wave <= 6) LNE_G64(double, 6);
@@ -508,7 +560,7 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     LNE_TRY(check_launch(ctx, "gram"));
     {
         Launch L(ctx, "gram_reduce");
-        k_gram_reduce<<<grid_of((int64_t)k * k, 256), 256, 0, ctx->stream>>>(
+        k_gram_reduce<<<dim3(grid_of((int64_t)k * k, 256), (unsigned)nb), 256, 0, ctx->stream>>>(
             part.as<double>(), nwg, KP, k, G, skip);
     }
     return check_launch(ctx, "gram_reduce");
@@ -516,24 +568,26 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
 
 lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_t n,
                    int32_t kin, const double *W, int32_t kout, void *out, int32_t out_t,
-                   int64_t ldo, const int32_t *skip) {
+                   int64_t ldo, const int32_t *skip, int32_t nb, int64_t ys, int64_t ws,
+                   int64_t os) {
     if (kout > 288 || kin > 288) return fail(ctx, LNE_EUNSUPPORTED, "project: width above 288");
-    const unsigned grid = grid_of(n > 0 ? n : 1, kProjRows);
+    if (nb < 1 || nb > 65535) return fail(ctx, LNE_EINVAL, "project: batch of %d", nb);
+    const dim3 grid(grid_of(n > 0 ? n : 1, kProjRows), (unsigned)nb);
     const int ntout = (kout + 15) / 16;
     if (y_t == LNE_BF16) {
         const int ldw = ((kin + 31) / 32) * 32;
         Buf wt(ctx);
-        LNE_TRY(alloc(ctx, wt, sizeof(__bf16) * (size_t)kout * ldw));
+        LNE_TRY(alloc(ctx, wt, sizeof(__bf16) * (size_t)nb * kout * ldw));
         {
             Launch L(ctx, "w_to_bf16");
-            k_w_to_bf16t<<<grid_of((int64_t)kin * kout, 256), 256, 0, ctx->stream>>>(
-                W, kin, kout, wt.as<__bf16>(), ldw);
+            k_w_to_bf16t<<<dim3(grid_of((int64_t)kin * kout, 256), (unsigned)nb), 256, 0,
+                           ctx->stream>>>(W, kin, kout, wt.as<__bf16>(), ldw, ws);
         }
         LNE_TRY(check_launch(ctx, "w_to_bf16"));
         Launch L(ctx, "project");
 #define LNE_PB(OT, MJ)                                                                     \
     k_proj_bf16<OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                           \
-        (const __bf16 *)Y, ldy, n, kin, wt.as<__bf16>(), ldw, kout, (OT *)out, ldo, skip)
+        (const __bf16 *)Y, ldy, n, kin, wt.as<__bf16>(), ldw, kout, (OT *)out, ldo, skip, ys, os)
         if (out_t == LNE_BF16) {
             if (ntout <= 3) LNE_PB(__bf16, 3);
             else if (ntout <= 9) LNE_PB(__bf16, 9);
@@ -550,7 +604,7 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
         Launch L(ctx, "project");
 #define LNE_P64(YT, OT, MJ)                                                                \
     k_proj64<YT, OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                          \
-        (const YT *)Y, ldy, n, kin, W, kout, (OT *)out, ldo, skip)
+        (const YT *)Y, ldy, n, kin, W, kout, (OT *)out, ldo, skip, ys, ws, os)
 #define LNE_P64J(YT, OT)                                                                   \
     do {                                                                                   \
         if (ntout <= 3) LNE_P64(YT, OT, 3);                                                \
@@ -569,34 +623,37 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
 }
 
 lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *status,
-                    int32_t *shifted, int64_t n_rows, const int32_t *skip, int32_t *skip_next) {
+                    int32_t *shifted, int64_t n_rows, const int32_t *skip, int32_t *skip_next,
+                    int32_t nb) {
     Buf diag(ctx);
-    LNE_TRY(alloc(ctx, diag, sizeof(double) * (size_t)k));
+    LNE_TRY(alloc(ctx, diag, sizeof(double) * (size_t)nb * k));
     {
         Launch L(ctx, "chol_inv");
-        k_chol_inv<<<1, kSolveThreads, 0, ctx->stream>>>(G, k, W, diag.as<double>(), status,
+        k_chol_inv<<<nb, kSolveThreads, 0, ctx->stream>>>(G, k, W, diag.as<double>(), status,
                                                          shifted, n_rows, skip, skip_next);
     }
     return check_launch(ctx, "chol_inv");
 }
 
-lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam) {
+lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb) {
     if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above 288", k);
     Buf vw(ctx);
-    LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)k * k));
+    LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)nb * k * k));
     {
         Launch L(ctx, "sym_eig");
-        k_sym_eig<<<1, kSolveThreads, 0, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
+        k_sym_eig<<<nb, kSolveThreads, 0, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
     }
     return check_launch(ctx, "sym_eig");
 }
 
 lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t k,
-                       int32_t kout, double power, double *W, double *S) {
+                       int32_t kout, double power, double *W, double *S, int32_t nb,
+                       const int32_t *on) {
+    if (on && k != kout) return fail(ctx, LNE_EINVAL, "eig_weights: pass-through needs k == kout");
     {
         Launch L(ctx, "eig_weights");
-        k_eig_weights<<<grid_of((int64_t)k * kout, 256), 256, 0, ctx->stream>>>(
-            V, lam, k, kout, power, W, S);
+        k_eig_weights<<<dim3(grid_of((int64_t)k * kout, 256), (unsigned)nb), 256, 0,
+                        ctx->stream>>>(V, lam, k, kout, power, W, S, on);
     }
     return check_launch(ctx, "eig_weights");
 }

@@ -1,7 +1,10 @@
 """Batched trials sharing one sampling pass: the channel sparsifier is
 bit-exact with the oracle, each trial's matrix matches the oracle's mixing of
-the channels, and the batched pipeline equals the single-trial pipeline run
-on the same trial matrices."""
+the channels, the batched SpMM (values generated on the fly) matches the
+oracle's trial matrix times the operand, and the batched pipeline -- eager or
+replayed from a captured HIP graph -- equals the single-trial pipeline run on
+the same trial matrices."""
+import json
 import math
 
 import numpy as np
@@ -51,6 +54,51 @@ def test_trial_matrix_matches_oracle_mixing(lne, ctx):
         np.testing.assert_allclose(V, ref.data.astype(np.float32), rtol=2e-6, atol=1e-6)
 
 
+def _spmm_bar(M, X):
+    """FP32 accumulation bound: |M| |X| per entry times a few ulps per term."""
+    absmx = abs(M) @ np.abs(X)
+    nnz_row = np.diff(M.indptr).max()
+    return 4 * max(nnz_row, 1) * 2.0 ** -24 * absmx + 1e-30
+
+
+def test_batch_spmm_matches_oracle(lne, ctx):
+    """Values generated inside the SpMM equal the oracle's trial matrices:
+    per-trial and shared operands, widths that leave lanes idle and fill the
+    wave, rows longer than one 64-entry chunk (channel runs straddle chunks)."""
+    import torch
+    g = sbm([150] * 4, 0.3, 0.02, seed=8)
+    p = gs.params(T=8, M_per_m=60, C=math.log(g.n), m=g.m, seed=3, d=16, oversample=8,
+                  precision="f32")
+    rp, col = to_dev(g)
+    R0, C0, W0, _, _ = oracle.count_csr(g, p, channels=True)
+    assert np.diff(R0).max() > 200
+    trials = trial_vectors(3, seed=4, T=8)
+    trials[2]["s"] = np.array([0, 0, 1.0, 0, 0, 0, 0, 0])     # one length only
+    B = lne.Batch(ctx, rp, col, p, max_trials=3)
+    Ms = [oracle.trial_matrix(g, p, R0, C0, W0, tr["s"]) for tr in trials]
+    rng = np.random.default_rng(0)
+    for k in (4, 36, 144, 256):
+        X = rng.standard_normal((3, g.n, k)).astype(np.float32)
+        Y = B.spmm(trials, torch.from_numpy(X).cuda()).cpu().numpy()
+        for t in range(3):
+            ref = Ms[t] @ X[t].astype(np.float64)
+            bar = _spmm_bar(Ms[t], X[t].astype(np.float64))
+            assert np.all(np.abs(Y[t] - ref) <= bar), (k, t, np.max(np.abs(Y[t] - ref) / bar))
+    Xs = rng.standard_normal((g.n, 32)).astype(np.float32)
+    Y = B.spmm(trials, torch.from_numpy(Xs).cuda()).cpu().numpy()
+    for t in range(3):
+        ref = Ms[t] @ Xs.astype(np.float64)
+        assert np.all(np.abs(Y[t] - ref) <= _spmm_bar(Ms[t], Xs.astype(np.float64)))
+    B.close()
+
+
+def _single_trial_reference(lne, ctx, rp, col, p, ch, tr):
+    M = lne.trial_matrix(ctx, rp, col, p, ch, tr)
+    pt = dict(p, s=tr["s"], cheb_k=tr["k"], theta=tr["theta"], mu=tr["mu"])
+    U, S, V, X0 = lne.rsvd(ctx, M, pt)
+    return lne.propagate(ctx, rp, col, pt, X0).cpu().numpy()
+
+
 def test_batched_pipeline_equals_single_trial_runs(lne, ctx):
     g = sbm([100] * 8, 0.12, 0.01, seed=3)
     p = dict(T=10, s=np.full(10, 0.1), M=30 * 10 * g.m, b=1, C=math.log(g.n), d=16,
@@ -58,12 +106,83 @@ def test_batched_pipeline_equals_single_trial_runs(lne, ctx):
     rp, col = to_dev(g)
     trials = trial_vectors(5, seed=7)
     trials[1]["k"] = 0                      # propagation off for one trial
+    trials[3]["theta"] = 0.0                # and off through theta for another
     Xb, st = lne.embed_batch(ctx, rp, col, p, trials)
     ch, _ = lne.sparsify_channels(ctx, rp, col, p)
     for t, tr in enumerate(trials):
-        M = lne.trial_matrix(ctx, rp, col, p, ch, tr)
-        pt = dict(p, s=tr["s"], cheb_k=tr["k"], theta=tr["theta"], mu=tr["mu"])
-        U, S, V, X0 = lne.rsvd(ctx, M, pt)
-        X = lne.propagate(ctx, rp, col, pt, X0).cpu().numpy()
+        X = _single_trial_reference(lne, ctx, rp, col, p, ch, tr)
         err = procrustes_err(Xb[t].cpu().numpy(), X)
         assert err < 2e-3, (t, err)
+
+
+def test_graph_replays_equal_eager_runs(lne, ctx):
+    """A captured launch sequence replayed several times, with other eager
+    work and host synchronisations in between, gives every replay the eager
+    result of the same trials; a batch of other trials (and of another size
+    and largest order) triggers a new capture and matches its eager run."""
+    import torch
+    g = sbm([80] * 6, 0.15, 0.01, seed=11)
+    p = dict(T=10, s=np.full(10, 0.1), M=20 * 10 * g.m, b=1, C=math.log(g.n), d=16,
+             oversample=8, q=1, cheb_k=5, theta=0.5, mu=0.2, seed=2, precision="f32")
+    rp, col = to_dev(g)
+    B = lne.Batch(ctx, rp, col, p, max_trials=6)
+    set_a = trial_vectors(6, seed=21)
+    set_b = trial_vectors(4, seed=22)
+    set_b[0]["k"] = 0
+    first, _ = B.run(set_a)                       # sizes the scratch arena
+    eager_a, _ = B.run(set_a)
+    eager_b, _ = B.run(set_b)
+    np.testing.assert_array_equal(first.cpu().numpy(), eager_a.cpu().numpy())
+    for rep in range(3):
+        Xa, _ = B.run(set_a, graph=True)
+        junk = torch.randn(1 << 20, device="cuda").sum()      # other eager work
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(Xa.cpu().numpy(), eager_a.cpu().numpy(), rtol=1e-6, atol=1e-7)
+        del junk
+    for rep in range(2):
+        Xb, _ = B.run(set_b, graph=True)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(Xb.cpu().numpy(), eager_b.cpu().numpy(), rtol=1e-6, atol=1e-7)
+    assert B.info()["graph_captures"] == 2
+    ch, _ = lne.sparsify_channels(ctx, rp, col, p)
+    for t in (0, 3):
+        X = _single_trial_reference(lne, ctx, rp, col, p, ch, set_a[t])
+        assert procrustes_err(eager_a[t].cpu().numpy(), X) < 2e-3
+    B.close()
+
+
+def test_all_trials_off_is_the_rsvd_embedding(lne, ctx):
+    g = sbm([60] * 5, 0.2, 0.01, seed=5)
+    p = dict(T=10, s=np.full(10, 0.1), M=20 * 10 * g.m, b=1, C=math.log(g.n), d=8,
+             oversample=8, q=1, cheb_k=5, theta=0.5, mu=0.2, seed=4, precision="f32")
+    rp, col = to_dev(g)
+    trials = trial_vectors(3, seed=9)
+    for tr in trials:
+        tr["k"] = 0
+    Xb, _ = lne.embed_batch(ctx, rp, col, p, trials)
+    ch, _ = lne.sparsify_channels(ctx, rp, col, p)
+    for t, tr in enumerate(trials):
+        M = lne.trial_matrix(ctx, rp, col, p, ch, tr)
+        _, _, _, X0 = lne.rsvd(ctx, M, dict(p, s=tr["s"]))
+        assert procrustes_err(Xb[t].cpu().numpy(), X0.cpu().numpy()) < 2e-3
+
+
+def test_tuner_cache_round_trip(lne, ctx, tmp_path, monkeypatch):
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("LNE_TUNE_CACHE", str(path))
+    g = sbm([60] * 4, 0.2, 0.02, seed=6)
+    p = dict(T=6, s=np.full(6, 1 / 6), M=10 * 6 * g.m, b=1, C=math.log(g.n), d=8,
+             oversample=8, q=1, cheb_k=3, theta=0.5, mu=0.2, seed=4, precision="f32")
+    rp, col = to_dev(g)
+    B1 = lne.Batch(ctx, rp, col, p, max_trials=2)
+    i1 = B1.info()
+    B1.close()
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert {x["op"] for x in lines} == {"spmm_chan", "graph_spmm_batch"}
+    sp = [x for x in lines if x["op"] == "spmm_chan"][0]
+    assert sp["variant"] == i1["spmm_variant"] and len(sp["ms"]) == 6
+    assert sp["nnz"] == i1["channel_nnz"]
+    B2 = lne.Batch(ctx, rp, col, p, max_trials=2)
+    assert B2.info()["spmm_variant"] == i1["spmm_variant"]
+    assert len(path.read_text().splitlines()) == 2          # read, not re-tuned
+    B2.close()
