@@ -58,8 +58,13 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--report", choices=["precision"], default=None,
-                    help="precision: the FP32 and BF16-MFMA paths against the FP64 path")
+    ap.add_argument("--report", choices=["precision", "automl"], default=None,
+                    help="precision: the FP32 and BF16-MFMA paths against the FP64 path; "
+                         "automl: trials/s and time to an equal score of the plain "
+                         "sequential search and the batched surrogate search")
+    ap.add_argument("--automl-trials", type=int, default=64)
+    ap.add_argument("--pretrain-trials", type=int, default=64,
+                    help="surrogate pretraining trials per family graph (8 graphs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -76,6 +81,10 @@ def main():
 
     if args.report == "precision":
         precision_report(args.workload if args.workload != "large" else "precision")
+        return
+    if args.report == "automl":
+        automl_report(args.workload if args.workload != "large" else "batched",
+                      args.automl_trials, args.pretrain_trials)
         return
 
     if args.calib_copy_mib:
@@ -259,6 +268,103 @@ def precision_report(name):
     out["results"]["f64"] = {"seconds": {"sparsify_trunc_log": ref["t_sparsify"],
                                          "rsvd": ref["t_rsvd"], "propagate": ref["t_propagate"]},
                              "nnz": ref["nnz"], "stats": ref["stats"]}
+    print(json.dumps(out), flush=True)
+
+
+def automl_report(name, budget, pretrain_per_graph):
+    """Hyperparameter search on the batched-trials workload, two arms on the
+    same GPU, the same search space, scorer and splits:
+      plain      one trial after another, each with its own sampling pass
+                 (random proposals, as a plain sequential search)
+      batched    one shared sampling pass, rounds of 16 trials run as one
+                 batch (HIP graph replay) and scored in one call, proposed by
+                 the surrogate (pretrained on a family of smaller graphs,
+                 refitted after each round)
+    Reports trials/s with and without scoring and the wall time each arm
+    needs to reach the better arm's best score minus its 95% interval over
+    the scoring splits."""
+    import numpy as np
+    import torch
+
+    import paper_2302_07084_amd as lne
+    from paper_2302_07084_amd import search
+    from synth import workload
+
+    ctx = lne.Context()
+    t0 = time.perf_counter()
+    family = []
+    for i, (blocks, size, intra) in enumerate([(20, 1000, 0.30), (20, 1000, 0.36), (40, 500, 0.32),
+                                                (40, 500, 0.40), (25, 1600, 0.28), (25, 1600, 0.34),
+                                                (50, 800, 0.31), (50, 800, 0.37)]):
+        g, p = workload(name, sizes=[size] * blocks, intra=intra, seed=100 + i)
+        family.append(search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=100 + i))
+    t_fam = time.perf_counter() - t0
+    log(f"automl: {len(family)} family graphs in {t_fam:.1f}s")
+    t0 = time.perf_counter()
+    F, y = search.pretrain_pairs(ctx, family, pretrain_per_graph, np.random.default_rng(0))
+    t_pairs = time.perf_counter() - t0
+    sur = search.Surrogate(ctx, seed=0)
+    sur.set_scaler(F)
+    sur.add(F, y)
+    t0 = time.perf_counter()
+    loss = sur.fit(epochs=800)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    log(f"automl: surrogate pretrained on {len(y)} trials ({t_pairs:.1f}s batched runs, "
+        f"{t_fit:.1f}s fit, loss {loss})")
+    del family
+
+    g, p = workload(name, device="cuda")
+    task = search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=0)
+    log(f"automl: target graph n={g.n} m={g.m}, budget {budget} trials per arm")
+    # warm both paths once so that neither arm pays first-launch costs
+    w = search.sample_trials(np.random.default_rng(9), 1)
+    search.plain_sequential_search(ctx, task, w)
+    torch.cuda.synchronize()
+
+    trials_a = search.sample_trials(np.random.default_rng(1), budget)
+    sa, ta, ea = search.plain_sequential_search(ctx, task, trials_a)
+    log(f"automl: plain arm {ta[-1]:.1f}s, best {sa.mean(axis=1).max():.4f}")
+    tb, sb, stb, eb, setup = search.batched_surrogate_search(ctx, task, sur, budget,
+                                                             np.random.default_rng(2))
+    log(f"automl: batched arm {stb[-1]:.1f}s (set-up {setup:.1f}s), best {sb.mean(axis=1).max():.4f}")
+
+    def best_ci(sc):
+        m = sc.mean(axis=1)
+        i = int(np.argmax(m))
+        half = 1.96 * sc[i].std(ddof=1) / math.sqrt(sc.shape[1]) if sc.shape[1] > 1 else 0.0
+        return float(m[i]), float(half)
+
+    ba, ca = best_ci(sa)
+    bb, cb = best_ci(sb)
+    target = (ba - ca) if ba >= bb else (bb - cb)
+
+    def time_to(sc, stamps):
+        run = np.maximum.accumulate(sc.mean(axis=1))
+        hit = np.flatnonzero(run >= target)
+        return float(stamps[hit[0]]) if len(hit) else None
+
+    def arm(sc, stamps, embed_s, extra):
+        return dict(extra, trials=len(stamps), seconds=float(stamps[-1]),
+                    trials_per_s=len(stamps) / float(stamps[-1]),
+                    trials_per_s_embedding_only=len(stamps) / embed_s,
+                    best_micro_f1=float(sc.mean(axis=1).max()),
+                    mean_micro_f1=float(sc.mean()), seconds_to_target=time_to(sc, stamps))
+
+    out = {"report": "automl", "workload": name, "n": g.n, "m": g.m, "T": p["T"], "M": p["M"],
+           "d": p["d"], "q": p["q"], "budget": budget, "scoring": "one-vs-rest logistic "
+           "regression on GPU, 10% training labels, 3 seeded splits, micro-F1",
+           "target_micro_f1": target,
+           "arms": {"plain_sequential": arm(sa, ta, ea, {"proposals": "random"}),
+                    "batched_surrogate": arm(sb, stb, eb, {"proposals": "surrogate, 25% random",
+                                                           "per_round": 16,
+                                                           "setup_seconds": setup})},
+           "surrogate_pretraining": {"graphs": 8, "trials": int(len(y)),
+                                     "batched_run_seconds": t_pairs, "fit_seconds": t_fit}}
+    a, b = out["arms"]["plain_sequential"], out["arms"]["batched_surrogate"]
+    out["speedup_trials_per_s"] = b["trials_per_s"] / a["trials_per_s"]
+    if a["seconds_to_target"] and b["seconds_to_target"]:
+        out["speedup_time_to_target"] = a["seconds_to_target"] / b["seconds_to_target"]
     print(json.dumps(out), flush=True)
 
 

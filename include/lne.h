@@ -256,19 +256,20 @@ typedef struct {
     double theta, mu;   /* filter parameters; theta < 1e-12 switches it off   */
 } lne_trial;
 
-/* Sparsifier with per-length channels: like lne_sparsify but every sample
- * draws its length r uniformly from 1..T (p->s is ignored) and r is kept:
+/* Sparsifier with per-length channels: lne_sparsify with the sampled length
+ * r kept (p->s plays the role of the channel pass's length distribution pi):
  * the count CSR has n x 16n columns, column (b << 4) | (r - 1) holding the
  * weight of pairs (a, b) sampled at length r.  Synchronises the stream.
  * Errors: as lne_sparsify; EUNSUPPORTED if n > 2^30. */
 lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                                  lne_csr *out, lne_stats *st);
 
-/* Sparsifier matrix of one trial from the channel counts: with pi_r = 1/T,
- * the trial's weights are sum_r (s_r / pi_r) W_r (an unbiased estimate of its
- * own sampler's counts) and the entries are ln x for x > 1 of Eq. (1), 0 for
- * x <= 1 (the structure is the union over lengths; zeros are kept).
- * out: F32 values.  Synchronises the stream.  Errors: EINVAL, ENOMEM. */
+/* Sparsifier matrix of one trial from the channel counts of a pass with
+ * length distribution pi = p->s (normalised): the trial's weights are
+ * sum_r (s_r / pi_r) W_r (an unbiased estimate of its own sampler's counts)
+ * and the entries are ln x for x > 1 of Eq. (1), 0 for x <= 1 (the structure
+ * is the union over lengths; zeros are kept).  out: F32 values.  Synchronises
+ * the stream.  Errors: EINVAL (also when s_r > 0 where pi_r = 0), ENOMEM. */
 lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                             const lne_csr *channels, const lne_trial *trial, lne_csr *out);
 
@@ -281,14 +282,23 @@ lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *
  * It also picks the launch shapes of the batched SpMM kernels by timing each
  * shape on this matrix (with env LNE_TUNE_CACHE naming a JSON-lines file, the
  * choice is read from / appended to it).  The graph's device arrays must stay
- * valid until lne_batch_destroy.  p->s is not used (each trial brings its
- * own); p->precision must be LNE_F32 and d + oversample <= 256.
+ * valid until lne_batch_destroy.  p->s is the length distribution pi of the
+ * channel pass (each trial brings its own s; a trial needs pi_r > 0 wherever
+ * its s_r > 0, and its estimate has the least variance when pi is close to
+ * its s); p->precision must be LNE_F32 and d + oversample <= 256.
  * Synchronises the stream.  st (may be NULL): attempted, accepted, nnz_counts
  * of the channel pass.  Errors: those of lne_sparsify_channels, EINVAL,
  * ENOMEM, EUNSUPPORTED (max_trials outside 1..256). */
 typedef struct lne_batch lne_batch;
 lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                             int32_t max_trials, lne_batch **out, lne_stats *st);
+
+/* Runs the channel sampling pass again with length distribution pi (T
+ * doubles, normalised inside) in place of the batch's current one; the
+ * workspace, tuned launch shapes and scratch arena are kept, a captured
+ * graph is dropped.  Synchronises the stream.  st (may be NULL): as
+ * lne_batch_create.  Errors: those of lne_batch_create. */
+lne_status lne_batch_resample(lne_batch *b, const double *pi, lne_stats *st);
 
 #define LNE_BATCH_EAGER 0   /* enqueue the launches of the run one by one          */
 #define LNE_BATCH_GRAPH 1   /* replay them as one captured HIP graph               */
@@ -374,6 +384,14 @@ lne_status lne_score_micro_f1(lne_ctx *ctx, const float *X, int64_t n, int32_t d
                               const uint8_t *labels, int32_t n_labels, const int32_t *train,
                               int64_t n_train, const int32_t *test, int64_t n_test,
                               int32_t epochs, float lr, float l2, double *f1);
+/* The same protocol for n_trials embeddings at once (X: device n_trials x n x
+ * d, trial-major; same labels and split): every epoch is one launch sequence
+ * over all trials.  f1: host array of n_trials.  Errors: as above. */
+lne_status lne_score_micro_f1_batch(lne_ctx *ctx, const float *X, int32_t n_trials, int64_t n,
+                                    int32_t d, const uint8_t *labels, int32_t n_labels,
+                                    const int32_t *train, int64_t n_train, const int32_t *test,
+                                    int64_t n_test, int32_t epochs, float lr, float l2,
+                                    double *f1);
 
 #ifdef __cplusplus
 }

@@ -129,7 +129,7 @@ def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
     """Aggregated count matrix W (fixed point, 2^-16 units) restricted to rows
     [row_lo, row_hi), from the samples of edges [e_begin, e_end) (all edges
     by default): returns (rowptr, col, W, attempted, accepted).  With
-    ``channels`` the length r is drawn uniformly from 1..T and kept: column
+    ``channels`` the length r (drawn from s as always) is kept: column
     (b << 4) | (r - 1).  Equal
     pairs are summed exactly in uint64 (section 5.2, sparse parallel hashing;
     here a sort of the sample triples)."""
@@ -194,13 +194,19 @@ def compact(rowptr, col, keep, val):
 
 def trial_matrix(g, params, R, Cext, W, s):
     """Sparsifier matrix of one trial from per-length channel counts (the
-    batched search reading): with the length drawn uniformly (pi_r = 1/T),
-    sum_r (s_r / pi_r) W_r estimates the trial's own counts; then Eq. (1)'s
-    truncated logarithm.  Returns a dense-structure FP64 CSR over the union of
-    lengths with log x where x > 1 and explicit zeros elsewhere."""
+    batched search reading): with the channel pass's lengths drawn from
+    pi = params["s"] (normalised), sum_r (s_r / pi_r) W_r estimates the
+    trial's own counts for any pi that is positive wherever s is; then
+    Eq. (1)'s truncated logarithm.  Returns a dense-structure FP64 CSR over
+    the union of lengths with log x where x > 1 and explicit zeros elsewhere."""
     T = params["T"]
     s = np.asarray(s, np.float64)
     s = s / s.sum()
+    pi = np.asarray(params["s"], np.float64)[:T]
+    pi = pi / pi.sum()
+    if np.any((pi == 0) & (s[:T] > 0)):
+        raise ValueError("trial uses a length the channel pass never draws")
+    coef = np.where(pi > 0, s[:T] / np.where(pi > 0, pi, 1.0), 0.0)
     rows = np.repeat(np.arange(g.n), np.diff(R))
     base = Cext >> 4
     r = Cext & 15
@@ -208,7 +214,7 @@ def trial_matrix(g, params, R, Cext, W, s):
     uniq, start = np.unique(key, return_index=True)
     grp = np.searchsorted(uniq, key)
     mixed = np.zeros(len(uniq))
-    np.add.at(mixed, grp, T * s[r] * W.astype(np.float64))
+    np.add.at(mixed, grp, coef[r] * W.astype(np.float64))
     a = uniq // g.n
     b = uniq % g.n
     deg = g.degrees().astype(np.float64)

@@ -319,8 +319,8 @@ static int trip_cmp(const void *x, const void *y)
  * entries starting at 0, *o_col / *o_w have *o_nnz entries.  Buffers are
  * malloc'ed here and released with ora_free.  Also reports the number of
  * attempted and accepted samples of those edges.  With channels != 0 the
- * length r is drawn uniformly from 1..T (s is ignored) and kept in the column:
- * entry (a, (b << 4) | (r - 1)).  Returns 0, or -1 on
+ * length r (drawn from s as always) is kept in the column: entry
+ * (a, (b << 4) | (r - 1)).  Returns 0, or -1 on
  * allocation failure, -2 on a weight-sum overflow.
  */
 int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
@@ -337,9 +337,7 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
     if (!eu || !ev) return -1;
     edge_list(&g, eu, ev);
     plan_t pl;
-    double uni[16];
-    for (int t = 0; t < T; ++t) uni[t] = 1.0;
-    make_plan(T, channels ? uni : s, M, m, &pl);
+    make_plan(T, s, M, m, &pl);
     if (nthreads < 1) nthreads = 1;
     if (e_end < 0 || e_end > m) e_end = m;
     if (e_begin < 0) e_begin = 0;

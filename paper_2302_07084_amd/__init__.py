@@ -106,6 +106,7 @@ SIGNATURES = [
     ("lne_batch_create", _I32, [_P, _P, _P, _I32, _P, _P]),
     ("lne_batch_run", _I32, [_P, _P, _I32, _I32, _P, _P]),
     ("lne_batch_info", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_batch_resample", _I32, [_P, _P, _P]),
     ("lne_batch_spmm", _I32, [_P, _P, _I32, _P, _I64, _I64, _P, _I64, _I64, _I32]),
     ("lne_batch_destroy", None, [_P]),
     ("lne_mlp_param_count", _I64, [_I32, _I32]),
@@ -116,6 +117,8 @@ SIGNATURES = [
                             ctypes.c_float, ctypes.c_float]),
     ("lne_score_micro_f1", _I32, [_P, _P, _I64, _I32, _P, _I32, _P, _I64, _P, _I64, _I32,
                                   ctypes.c_float, ctypes.c_float, _P]),
+    ("lne_score_micro_f1_batch", _I32, [_P, _P, _I32, _I64, _I32, _P, _I32, _P, _I64, _P, _I64,
+                                        _I32, ctypes.c_float, ctypes.c_float, _P]),
 ]
 
 _lib = None
@@ -164,7 +167,7 @@ def make_params(p: dict, **override) -> Params:
     p.update(override)
     out = Params()
     T = int(p["T"])
-    s = np.asarray(p["s"], dtype=np.float64)
+    s = np.asarray(p["s"] if p.get("s") is not None else np.full(T, 1.0 / T), dtype=np.float64)
     out.T = T
     for i in range(T):
         out.s[i] = float(s[i])
@@ -493,9 +496,9 @@ BATCH_EAGER, BATCH_GRAPH = 0, 1
 
 class Batch:
     """Persistent per-graph state of the batched trials (lne_batch_*): one
-    channel sampling pass at construction, then any number of runs of up to
-    `max_trials` trials.  Holds references to the graph tensors, which the
-    library reads on every run."""
+    channel sampling pass at construction (lengths drawn from params["s"]),
+    then any number of runs of up to `max_trials` trials.  Holds references
+    to the graph tensors, which the library reads on every run."""
 
     def __init__(self, ctx: Context, rowptr, col, params: dict, max_trials: int):
         self.ctx = ctx
@@ -521,6 +524,19 @@ class Batch:
                                                 BATCH_GRAPH if graph else BATCH_EAGER,
                                                 X.data_ptr(), ctypes.byref(st)), "batch_run")
         return X, st.as_dict()
+
+    def resample(self, pi):
+        """New channel pass with length distribution pi (the trials' s must
+        be covered by it)."""
+        T = self._p.T
+        arr = (ctypes.c_double * 16)(*[float(x) for x in np.asarray(pi, np.float64)[:T]])
+        st = Stats()
+        self.ctx.check(self.ctx.L.lne_batch_resample(self.h, arr, ctypes.byref(st)),
+                       "batch_resample")
+        for i in range(T):
+            self._p.s[i] = arr[i]
+        self.stats = st.as_dict()
+        return self.stats
 
     def spmm(self, trials, X):
         """Y[t] = M_t X[t] (X: n_trials x n x k, or n x k shared by all trials)."""
@@ -597,7 +613,8 @@ def mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float, beta1=0.9, 
 
 
 def score_micro_f1(ctx: Context, X, labels, train, test, epochs=300, lr=0.05, l2=None):
-    """micro-F1 of one-vs-rest logistic regression trained on rows `train`."""
+    """micro-F1 of one-vs-rest logistic regression trained on rows `train`.
+    X: n x d (one embedding, returns a float) or t x n x d (returns a list)."""
     import torch
     # every converted tensor stays referenced until the library call returns:
     # a temporary would go back to torch's allocator, which the library's own
@@ -606,11 +623,13 @@ def score_micro_f1(ctx: Context, X, labels, train, test, epochs=300, lr=0.05, l2
     lab = labels.to(torch.uint8).contiguous()
     tr = train.to(torch.int32).contiguous()
     te = test.to(torch.int32).contiguous()
-    n, d = Xf.shape
+    single = Xf.dim() == 2
+    ntr = 1 if single else Xf.shape[0]
+    n, d = Xf.shape[-2:]
     L = lab.shape[1]
     l2 = (1.0 / len(tr)) if l2 is None else l2
-    f1 = ctypes.c_double()
-    ctx.check(ctx.L.lne_score_micro_f1(ctx.h, Xf.data_ptr(), n, d, lab.data_ptr(), L,
-                                       tr.data_ptr(), len(tr), te.data_ptr(), len(te),
-                                       epochs, lr, l2, ctypes.byref(f1)), "score_micro_f1")
-    return f1.value
+    f1 = (ctypes.c_double * ntr)()
+    ctx.check(ctx.L.lne_score_micro_f1_batch(ctx.h, Xf.data_ptr(), ntr, n, d, lab.data_ptr(), L,
+                                             tr.data_ptr(), len(tr), te.data_ptr(), len(te),
+                                             epochs, lr, l2, f1), "score_micro_f1")
+    return f1[0] if single else list(f1)

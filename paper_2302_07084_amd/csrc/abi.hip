@@ -284,16 +284,10 @@ template <class Sink>
 static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                                 lne_stats *st, Sink &&sink, bool channels = false) {
     Sampler S;
-    if (channels) {
-        // one pass shared by trials with different s: the length is drawn
-        // uniformly from 1..T and kept in the key (section 4.4 search space)
-        lne_params pu = *p;
-        for (int t = 0; t < p->T; ++t) pu.s[t] = 1.0;
-        LNE_TRY(make_plan(ctx, &pu, g->n, g->n_arcs, S.pl));
-        S.pl.cbits = 4;
-    } else {
-        LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
-    }
+    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
+    // one pass shared by trials with different s: the length r is kept in
+    // the key (column b << 4 | r - 1)
+    if (channels) S.pl.cbits = 4;
     S.m = g->n_arcs / 2;
     uint64_t total = 0;
     if (S.m > 0 && S.pl.S > 0) {

@@ -42,15 +42,32 @@ lne_status check_trial(lne_ctx *ctx, const lne_trial *t, int T) {
     return LNE_OK;
 }
 
-// normalised s of each trial, 16 doubles per trial (zeros beyond T)
-std::vector<double> trial_s(const lne_trial *trials, int ntr, int T) {
-    std::vector<double> s(16 * (size_t)ntr, 0.0);
+// Channel weights of each trial, 16 doubles per trial (zeros beyond T):
+// s_t[r] / pi_r with s_t and the channel pass's length distribution pi
+// (p->s) both normalised.
+std::vector<double> trial_coef(const lne_trial *trials, int ntr, const lne_params *p) {
+    const int T = p->T;
+    double pt = 0.0;
+    for (int r = 0; r < T; ++r) pt += p->s[r];
+    std::vector<double> c(16 * (size_t)ntr, 0.0);
     for (int t = 0; t < ntr; ++t) {
         double tot = 0.0;
         for (int r = 0; r < T; ++r) tot += trials[t].s[r];
-        for (int r = 0; r < T; ++r) s[16 * t + r] = trials[t].s[r] / tot;
+        for (int r = 0; r < T; ++r) {
+            const double pi = p->s[r] / pt;
+            c[16 * t + r] = pi > 0.0 ? (trials[t].s[r] / tot) / pi : 0.0;
+        }
     }
-    return s;
+    return c;
+}
+
+// A trial is estimable from the channels iff pi_r > 0 wherever s_r > 0.
+lne_status check_support(lne_ctx *ctx, const lne_trial *t, const lne_params *p) {
+    for (int r = 0; r < p->T; ++r)
+        if (t->s[r] > 0.0 && !(p->s[r] > 0.0))
+            return fail(ctx, LNE_EINVAL,
+                        "trial: s_%d > 0 but the channel pass never draws length %d", r + 1, r + 1);
+    return LNE_OK;
 }
 
 // vol^2 / (2 b M) / 2^16: Eq. (1)'s constant on fixed-point counts
@@ -154,13 +171,12 @@ lne_status enqueue_trials(lne_batch *b, int ntr, int K) {
 
     // fast randomized SVD (Algorithm "Fast Randomized SVD") of every trial
     float *Q = b->A.as<float>(), *Y = b->B.as<float>();
-    LNE_TRY(spmm_chan(ctx, &b->ext, &b->g, ntr, b->chan(), b->scale, b->om.as<float>(), dp, 0, Y,
-                      dp, ys, dp, b->spmm_v));
+    LNE_TRY(spmm_chan(ctx, &b->ext, ntr, b->chan(), b->om.as<float>(), dp, 0, Y, dp, ys, dp,
+                      b->spmm_v));
     LNE_TRY(orth_batch(ctx, Y, n, kp, dp, ys, ntr, fl));
     std::swap(Q, Y);
     for (int it = 1; it <= b->p.q; ++it) {
-        LNE_TRY(spmm_chan(ctx, &b->ext, &b->g, ntr, b->chan(), b->scale, Q, dp, ys, Y, dp, ys, dp,
-                          b->spmm_v));
+        LNE_TRY(spmm_chan(ctx, &b->ext, ntr, b->chan(), Q, dp, ys, Y, dp, ys, dp, b->spmm_v));
         if (it < b->p.q) {
             LNE_TRY(orth_batch(ctx, Y, n, kp, dp, ys, ntr, fl));
             std::swap(Q, Y);
@@ -214,10 +230,10 @@ int fill_table(lne_batch *b, const lne_trial *tr, int ntr) {
     float *one = (float *)(h.data() + b->off_one);
     int32_t *on = (int32_t *)(h.data() + b->off_on);
     float *pc = (float *)(h.data() + b->off_pc);
-    const std::vector<double> s = trial_s(tr, ntr, T);
+    const std::vector<double> cf = trial_coef(tr, ntr, &b->p);
     int K = 0;
     for (int t = 0; t < ntr; ++t) {
-        for (int r = 0; r < T; ++r) chan[16 * t + r] = (double)T * s[16 * t + r];
+        for (int r = 0; r < T; ++r) chan[16 * t + r] = cf[16 * t + r];
         one[t] = 1.0f;
         on[t] = trial_on(tr[t]) ? 1 : 0;
         if (on[t]) K = std::max(K, (int)tr[t].cheb_k);
@@ -311,7 +327,7 @@ lne_status tune(lne_batch *b) {
     lne_ctx *ctx = b->ctx;
     const int nt = std::min(2, b->max_trials);
     const int64_t ys = b->n * b->dp, xs = b->n * b->d8;
-    // uniform s for timing: coef = T * (1 / T)
+    // the batch's own distribution for timing: coef = 1
     std::vector<double> ch(16 * (size_t)nt, 0.0);
     for (int t = 0; t < nt; ++t)
         for (int r = 0; r < b->p.T; ++r) ch[16 * t + r] = 1.0;
@@ -329,8 +345,8 @@ lne_status tune(lne_batch *b) {
     int v = cached_variant(ks);
     if (v < 0 || v >= kSpmmChanVariants) {
         LNE_TRY(time_variants(ctx, kSpmmChanVariants, [&](int var) {
-            return spmm_chan(ctx, &b->ext, &b->g, nt, b->chan(), b->scale, b->om.as<float>(), b->dp,
-                             0, b->B.as<float>(), b->dp, ys, b->dp, var);
+            return spmm_chan(ctx, &b->ext, nt, b->chan(), b->om.as<float>(), b->dp, 0,
+                             b->B.as<float>(), b->dp, ys, b->dp, var);
         }, &v, ms));
         store_variant(ks, v, ms);
     }
@@ -403,12 +419,13 @@ lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *
         channels->n_rows != g->n || channels->n_cols != (g->n << 4))
         return fail(ctx, LNE_EINVAL, "trial_matrix: channels must come from lne_sparsify_channels");
     LNE_TRY(check_trial(ctx, trial, p->T));
+    LNE_TRY(check_support(ctx, trial, p));
     std::memset(out, 0, sizeof(*out));
     lne_csr st;
     std::memset(&st, 0, sizeof(st));
     Buf chan(ctx), sdev(ctx), vals(ctx);
     LNE_TRY(split_channels(ctx, channels, p->T, &st, chan));
-    const std::vector<double> sh = trial_s(trial, 1, p->T);
+    const std::vector<double> sh = trial_coef(trial, 1, p);
     lne_status s = alloc(ctx, sdev, sizeof(double) * 16);
     if (s == LNE_OK) s = alloc(ctx, vals, sizeof(float) * (size_t)(st.nnz ? st.nnz : 1));
     if (s == LNE_OK && hipMemcpyAsync(sdev.p, sh.data(), sizeof(double) * 16,
@@ -466,6 +483,7 @@ lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *
 
     LNE_TRY(channels_pass(ctx, g, p, &b->ext, st));
     if (st) st->nnz_counts = (uint64_t)b->ext.nnz;
+    LNE_TRY(norm_channels(ctx, &b->ext, g, b->scale));
 
     const int64_t n = b->n, mt = max_trials;
     LNE_TRY(alloc(ctx, b->om, sizeof(float) * (size_t)n * b->dp));
@@ -506,7 +524,10 @@ lne_status lne_batch_run(lne_batch *b, const lne_trial *trials, int32_t n_trials
                     b->max_trials);
     if (mode != LNE_BATCH_EAGER && mode != LNE_BATCH_GRAPH)
         return fail(ctx, LNE_EINVAL, "batch_run: mode %d", mode);
-    for (int t = 0; t < n_trials; ++t) LNE_TRY(check_trial(ctx, &trials[t], b->p.T));
+    for (int t = 0; t < n_trials; ++t) {
+        LNE_TRY(check_trial(ctx, &trials[t], b->p.T));
+        LNE_TRY(check_support(ctx, &trials[t], &b->p));
+    }
     if (st) std::memset(st, 0, sizeof(*st));
     const int ntr = n_trials;
     const int K = fill_table(b, trials, ntr);
@@ -577,6 +598,26 @@ lne_status lne_batch_run(lne_batch *b, const lne_trial *trials, int32_t n_trials
     return read_batch_flags(b, ntr, st);
 }
 
+lne_status lne_batch_resample(lne_batch *b, const double *pi, lne_stats *st) {
+    if (!b) return LNE_EINVAL;
+    lne_ctx *ctx = b->ctx;
+    if (!pi) return fail(ctx, LNE_EINVAL, "batch_resample: pi is NULL");
+    lne_params p = b->p;
+    for (int r = 0; r < p.T; ++r) p.s[r] = pi[r];
+    LNE_TRY(validate_params(ctx, &p, b->g.n, b->g.n_arcs, true));
+    if (st) std::memset(st, 0, sizeof(*st));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    drop_graph(b);
+    lne_csr_free(ctx, &b->ext);
+    std::memset(&b->ext, 0, sizeof(b->ext));
+    b->p = p;
+    LNE_TRY(channels_pass(ctx, &b->g, &b->p, &b->ext, st));
+    if (st) st->nnz_counts = (uint64_t)b->ext.nnz;
+    LNE_TRY(norm_channels(ctx, &b->ext, &b->g, b->scale));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return LNE_OK;
+}
+
 lne_status lne_batch_spmm(lne_batch *b, const lne_trial *trials, int32_t n_trials,
                           const float *X, int64_t ldx, int64_t xs, float *Y, int64_t ldy,
                           int64_t ys, int32_t k) {
@@ -588,12 +629,14 @@ lne_status lne_batch_spmm(lne_batch *b, const lne_trial *trials, int32_t n_trial
                     b->max_trials);
     if (k < 4 || ldx < k || ldy < k || xs < 0 || ys < (int64_t)b->n * ldy)
         return fail(ctx, LNE_EINVAL, "batch_spmm: bad dimensions");
-    for (int t = 0; t < n_trials; ++t) LNE_TRY(check_trial(ctx, &trials[t], b->p.T));
+    for (int t = 0; t < n_trials; ++t) {
+        LNE_TRY(check_trial(ctx, &trials[t], b->p.T));
+        LNE_TRY(check_support(ctx, &trials[t], &b->p));
+    }
     (void)fill_table(b, trials, n_trials);
     LNE_HIP(ctx, hipMemcpyAsync(b->tab.p, b->host_tab.data(), b->tab_bytes, hipMemcpyHostToDevice,
                                 ctx->stream));
-    LNE_TRY(spmm_chan(ctx, &b->ext, &b->g, n_trials, b->chan(), b->scale, X, ldx, xs, Y, ldy, ys,
-                      k, b->spmm_v));
+    LNE_TRY(spmm_chan(ctx, &b->ext, n_trials, b->chan(), X, ldx, xs, Y, ldy, ys, k, b->spmm_v));
     LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return LNE_OK;
 }
@@ -626,7 +669,10 @@ lne_status lne_embed_batch(lne_ctx *ctx, const lne_graph *g, const lne_params *p
         return fail(ctx, LNE_EUNSUPPORTED, "embed_batch: n_trials = %d outside 1..256", n_trials);
     LNE_TRY(validate_graph(ctx, g));
     LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
-    for (int t = 0; t < n_trials; ++t) LNE_TRY(check_trial(ctx, &trials[t], p->T));
+    for (int t = 0; t < n_trials; ++t) {
+        LNE_TRY(check_trial(ctx, &trials[t], p->T));
+        LNE_TRY(check_support(ctx, &trials[t], p));
+    }
     lne_batch *b = nullptr;
     lne_stats s0;
     LNE_TRY(lne_batch_create(ctx, g, p, n_trials, &b, &s0));

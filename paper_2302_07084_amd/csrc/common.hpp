@@ -207,16 +207,20 @@ lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t
 // Extended count CSR (columns col << 4 | r - 1) -> structure (val NULL) plus
 // channels chan[entry * T + r - 1] (uint64).
 lne_status split_channels(lne_ctx *ctx, const lne_csr *ext, int T, lne_csr *st, Buf &chan);
-// vals[entry * ntr + t]: truncated log of trial t's mixed counts (0 if dropped).
+// vals[entry * ntr + t]: truncated log of trial t's mixed counts (0 if
+// dropped); s_dev[16 t + r - 1] = s_t[r] / pi_r.
 lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, const uint64_t *chan,
                         int T, const double *s_dev, int ntr, double scale, float *vals);
+// Channel CSR weights in place: counts W_r -> FP64 scale W_r / (d_a d_b)
+// (val_type becomes LNE_F64).
+lne_status norm_channels(lne_ctx *ctx, lne_csr *ext, const lne_graph *g, double scale);
 // Y_t (rows ldy apart, trials ys apart) = M_t X_t (ldx, xs; xs = 0 shares one
-// operand) for ntr trials, M_t generated from the channel CSR `ext` with
-// coef[16 t + r - 1] = T s_t[r] and scale = vol^2 / (2 b M 2^16); k <= 256,
-// k % 4 == 0, X's columns up to k zero-padded.  variant: launch shape 0..5.
-lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, const lne_graph *g, int ntr,
-                     const double *coef, double scale, const float *X, int64_t ldx, int64_t xs,
-                     float *Y, int64_t ldy, int64_t ys, int k, int variant);
+// operand) for ntr trials, M_t generated from the normalised channel CSR
+// `ext` with coef[16 t + r - 1] = s_t[r] / pi_r; k <= 256, k % 4 == 0, X's columns
+// up to k zero-padded.  variant: launch shape 0..5.
+lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, int ntr, const double *coef,
+                     const float *X, int64_t ldx, int64_t xs, float *Y, int64_t ldy, int64_t ys,
+                     int k, int variant);
 constexpr int kSpmmChanVariants = 6;
 // Propagation step for ntr trials (blocks zs apart, rows ld apart, k columns):
 // out = a Z + b D^-1 A Z + c1 E1 + c2 E2, acc += e out, coef[5 t + {a, b, c1,

@@ -1,11 +1,12 @@
 // Batched hyperparameter trials sharing one sampling pass (section 4.4: many
 // trials of s_1..s_T, k, theta, mu on one graph).
 //
-// The shared pass draws the walk length r uniformly from 1..T (pi_r = 1/T)
-// and keeps r in the count matrix, giving per-length channels W_r.  Trial t
-// then uses sum_r (s_r^(t) / pi_r) W_r in place of the counts, which has the
-// expectation of its own sampler; the truncated logarithm is applied per
-// trial on the shared structure (dropped entries keep an explicit zero).
+// The shared pass draws the walk length r from a sampling distribution pi
+// (chosen for the batch) and keeps r in the count matrix, giving per-length
+// channels W_r.  Trial t then uses sum_r (s_r^(t) / pi_r) W_r in place of the
+// counts, which has the expectation of its own sampler whenever pi_r > 0 for
+// every r with s_r^(t) > 0; the truncated logarithm is applied per trial on
+// the shared structure (dropped entries keep an explicit zero).
 //
 // Nothing per trial is materialised at the size of the matrix: each SpMM of
 // trial t regenerates M_t's values from the channel CSR while it streams it,
@@ -64,8 +65,8 @@ __global__ void k_split_fill(const int64_t *__restrict__ rp, const int32_t *__re
     }
 }
 
-// vals[i * ntr + t] = ln x if x > 1 else 0, x = scale * T * sum_r s_t[r] W_r /
-// (d_a d_b) with scale = vol^2 / (2 b M) / 2^16.
+// vals[i * ntr + t] = ln x if x > 1 else 0, x = scale * sum_r c_t[r] W_r /
+// (d_a d_b) with c_t[r] = s_t[r] / pi_r and scale = vol^2 / (2 b M) / 2^16.
 __global__ void k_trial_values(const int64_t *__restrict__ grp, const int64_t *__restrict__ srp,
                                const int32_t *__restrict__ scol, const uint64_t *__restrict__ chan,
                                int T, int64_t n, const double *__restrict__ s, int ntr,
@@ -84,17 +85,36 @@ __global__ void k_trial_values(const int64_t *__restrict__ grp, const int64_t *_
             double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc += s[t * 16 + r] * w[r];
-            const double x = (double)T * acc * scale / dd;
+            const double x = acc * scale / dd;
             vals[i * ntr + t] = x > 1.0 ? (float)log(x) : 0.0f;
         }
     }
 }
 
+// Channel weights in place: W_r (fixed-point counts) -> the FP64 number
+// scale W_r / (d_a d_b) (scale = vol^2 / (2 b M 2^16)), so that a trial's
+// Eq. (1) argument is x = sum_r coef_t[r] w_r with coef_t[r] = s_t[r] / pi_r.
+__global__ void k_norm_chan(const int64_t *__restrict__ rp, const int32_t *__restrict__ ecol,
+                            const int64_t *__restrict__ grp, int64_t n, double scale,
+                            uint64_t *__restrict__ W) {
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    const double da = (double)(grp[a + 1] - grp[a]);
+    double *out = reinterpret_cast<double *>(W);
+    for (int64_t i = rp[a] + lane; i < rp[a + 1]; i += 64) {
+        const int32_t b = ecol[i] >> 4;
+        const double db = (double)(grp[b + 1] - grp[b]);
+        out[i] = scale * (double)W[i] / (da * db);
+    }
+}
+
 // Y_t = M_t X_t for trials t = 0..ntr-1 with M_t generated on the fly from
-// the channel CSR: for every (row a, column b) structure entry -- a run of
-// channel entries with the same b, ascending r -- the head lane of the run
-// sums coef_t[r] W_r (coef_t[r] = T s_t[r]), forms x = scale sum / (d_a d_b)
-// and the truncated logarithm ln x (0 if x <= 1).  The nonzero values of a
+// the normalised channel CSR: for every (row a, column b) structure entry --
+// a run of channel entries with the same b, ascending r -- the head lane of
+// the run sums x = sum_r coef_t[r] w_r with coef_t[r] = s_t[r] / pi_r (FP64,
+// so the x > 1 decision is taken in FP64) and forms the truncated logarithm
+// ln x (FP32; 0 if x <= 1).  The nonzero values of a
 // 64-entry chunk are compacted to the low lanes with one ds_permute, then the
 // wave gathers the X rows of those entries, U rows in flight per lane, lane l
 // holding columns 4l..4l+3 (k <= 256, k % 4 == 0, padding columns of X zero).
@@ -103,8 +123,8 @@ __global__ void k_trial_values(const int64_t *__restrict__ grp, const int64_t *_
 template <int U, bool TM>
 __global__ void __launch_bounds__(256)
 k_spmm_chan(const int64_t *__restrict__ rp, const int32_t *__restrict__ ecol,
-            const uint64_t *__restrict__ W, const int64_t *__restrict__ grp, int64_t n, int ntr,
-            const double *__restrict__ coef, double scale, const float *__restrict__ X,
+            const double *__restrict__ wn, int64_t n, int ntr,
+            const double *__restrict__ coef, const float *__restrict__ X,
             int64_t ldx, int64_t xs, float *__restrict__ Y, int64_t ldy, int64_t ys, int k) {
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (w >= n * ntr) return;
@@ -125,7 +145,6 @@ k_spmm_chan(const int64_t *__restrict__ rp, const int32_t *__restrict__ ecol,
     coef += 16 * t;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t beg = rp[row], end = rp[row + 1];
-    const double da = (double)(grp[row + 1] - grp[row]);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t b0 = beg; b0 < end; b0 += 64) {
         const int64_t i = b0 + lane;
@@ -141,10 +160,9 @@ k_spmm_chan(const int64_t *__restrict__ rp, const int32_t *__restrict__ ecol,
             for (int64_t j = i; j < end; ++j) {
                 const int32_t e = ecol[j];
                 if ((e >> 4) != jb) break;
-                sum += coef[e & 15] * (double)W[j];
+                sum += coef[e & 15] * wn[j];
             }
-            const double x = scale * sum / (da * (double)(grp[jb + 1] - grp[jb]));
-            v = x > 1.0 ? (float)log(x) : 0.f;
+            v = sum > 1.0 ? logf((float)sum) : 0.f;
         }
         const bool take = v != 0.f;
         const uint64_t mask = __ballot(take);
@@ -325,9 +343,23 @@ lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, con
     return check_launch(ctx, "trial_values");
 }
 
-lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, const lne_graph *g, int ntr,
-                     const double *coef, double scale, const float *X, int64_t ldx, int64_t xs,
-                     float *Y, int64_t ldy, int64_t ys, int k, int variant) {
+lne_status norm_channels(lne_ctx *ctx, lne_csr *ext, const lne_graph *g, double scale) {
+    if (ext->val_type != LNE_U64) return fail(ctx, LNE_EINVAL, "norm_channels: counts expected");
+    if (ext->n_rows > 0) {
+        Launch L(ctx, "norm_channels");
+        k_norm_chan<<<grid_of(ext->n_rows * 64, 256), 256, 0, ctx->stream>>>(
+            ext->row_ptr, ext->col, g->row_ptr, ext->n_rows, scale, (uint64_t *)ext->val);
+    }
+    LNE_TRY(check_launch(ctx, "norm_channels"));
+    ext->val_type = LNE_F64;
+    return LNE_OK;
+}
+
+lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, int ntr, const double *coef,
+                     const float *X, int64_t ldx, int64_t xs, float *Y, int64_t ldy, int64_t ys,
+                     int k, int variant) {
+    if (ext->val_type != LNE_F64)
+        return fail(ctx, LNE_EINVAL, "spmm_chan: channel weights must be normalised");
     if (k % 4 || k > 256 || ldx % 4 || ldy % 4 || xs % 4 || ys % 4 || (uintptr_t)X % 16 ||
         (uintptr_t)Y % 16)
         return fail(ctx, LNE_EINVAL, "spmm_chan: k <= 256, k %% 4 == 0 and 16-byte aligned rows");
@@ -338,9 +370,8 @@ lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, const lne_graph *g, int n
         Launch L(ctx, "spmm_chan");
 #define LNE_SC(UU, TMM)                                                                   \
     k_spmm_chan<UU, TMM><<<grid, 256, 0, ctx->stream>>>(ext->row_ptr, ext->col,           \
-                                                        (const uint64_t *)ext->val,       \
-                                                        g->row_ptr, n, ntr, coef, scale,  \
-                                                        X, ldx, xs, Y, ldy, ys, k)
+                                                        (const double *)ext->val, n, ntr, \
+                                                        coef, X, ldx, xs, Y, ldy, ys, k)
         switch (variant) {
             case 0: LNE_SC(4, true); break;
             case 1: LNE_SC(2, true); break;

@@ -127,80 +127,213 @@ __global__ void k_mlp_init(float *__restrict__ p, int in, int h, uint64_t seed) 
     p[i] = a * (2.0f * u - 1.0f);
 }
 
-// ---- scorer ----------------------------------------------------------------
-// Rows idx of X into Xs (n_sel x d) and labels into Ys (n_sel x L, 0/1).
-// An index outside [0, n) is counted in *bad and its row left zero.
-__global__ void k_gather_rows(const float *__restrict__ X, int64_t n, int d,
-                             const uint8_t *__restrict__ lab, int L,
-                             const int32_t *__restrict__ idx, int64_t n_sel,
-                             float *__restrict__ Xs, float *__restrict__ Ys,
-                             unsigned long long *__restrict__ bad) {
+// ---- batched scorer ----------------------------------------------------------
+// ntr embeddings scored at once: X is ntr x n x d (trial-major); the training
+// rows of trial t are gathered into Xtr + t n_tr d and standardised with that
+// trial's statistics; labels are shared.  Parameters of trial t: W (d x L)
+// followed by b (L) at P + t (d + 1) L.
+
+// Xs[t][r][c] = X[t][idx[r]][c]; out-of-range indices are counted in *bad.
+__global__ void k_sc_gather(const float *__restrict__ X, int64_t n, int d, int ntr,
+                            const int32_t *__restrict__ idx, int64_t n_sel,
+                            float *__restrict__ Xs, unsigned long long *__restrict__ bad) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_sel * (d + L)) return;
-    const int64_t r = t / (d + L);
-    const int c = (int)(t - r * (d + L));
+    if (t >= (int64_t)ntr * n_sel * d) return;
+    const int64_t tr = t / (n_sel * d);
+    const int64_t rem = t - tr * n_sel * d;
+    const int64_t r = rem / d;
+    const int c = (int)(rem - r * d);
     const int64_t src = idx[r];
     if (src < 0 || src >= n) {
-        if (c == 0) atomicAdd(bad, 1ull);
-        if (c < d) Xs[r * d + c] = 0.0f;
-        else Ys[r * L + (c - d)] = 0.0f;
+        if (c == 0 && tr == 0) atomicAdd(bad, 1ull);
+        Xs[t] = 0.0f;
         return;
     }
-    if (c < d) Xs[r * d + c] = X[src * d + c];
-    else Ys[r * L + (c - d)] = (float)lab[src * L + (c - d)];
+    Xs[t] = X[(tr * n + src) * d + c];
 }
 
-// Column mean and inverse standard deviation over the training rows.
-__global__ void k_col_stats(const float *__restrict__ X, int64_t n, int d, float *__restrict__ mu,
-                            float *__restrict__ isd) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d) return;
+__global__ void k_sc_labels(const uint8_t *__restrict__ lab, int64_t n, int L,
+                            const int32_t *__restrict__ idx, int64_t n_sel,
+                            float *__restrict__ Ys) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_sel * L) return;
+    const int64_t r = t / L;
+    const int64_t src = idx[r];
+    Ys[t] = (src >= 0 && src < n) ? (float)lab[src * L + (t - r * L)] : 0.0f;
+}
+
+// Column mean and inverse standard deviation of each trial's training rows:
+// one 256-thread block per (trial, column), FP64 partial sums.
+__global__ void __launch_bounds__(256)
+k_sc_stats(const float *__restrict__ Xs, int64_t n_sel, int d, float *__restrict__ mu,
+           float *__restrict__ isd) {
+    const int c = blockIdx.x, tr = blockIdx.y;
+    const float *x = Xs + (int64_t)tr * n_sel * d + c;
     double s = 0.0, q = 0.0;
-    for (int64_t r = 0; r < n; ++r) {
-        const double x = X[r * d + c];
-        s += x;
-        q += x * x;
+    for (int64_t r = threadIdx.x; r < n_sel; r += 256) {
+        const double v = x[r * d];
+        s += v;
+        q += v * v;
     }
-    const double m = s / (double)n;
-    const double var = q / (double)n - m * m;
-    mu[c] = (float)m;
-    isd[c] = var > 1e-30 ? (float)(1.0 / sqrt(var)) : 0.0f;
+    __shared__ double S[256], Q[256];
+    S[threadIdx.x] = s;
+    Q[threadIdx.x] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            S[threadIdx.x] += S[threadIdx.x + o];
+            Q[threadIdx.x] += Q[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = S[0] / (double)n_sel;
+        const double var = Q[0] / (double)n_sel - m * m;
+        mu[(int64_t)tr * d + c] = (float)m;
+        isd[(int64_t)tr * d + c] = var > 1e-30 ? (float)(1.0 / sqrt(var)) : 0.0f;
+    }
 }
 
-__global__ void k_standardize(float *__restrict__ X, int64_t n, int d, const float *__restrict__ mu,
-                              const float *__restrict__ isd) {
+__global__ void k_sc_standardize(float *__restrict__ Xs, int64_t n_sel, int d, int ntr,
+                                 const float *__restrict__ mu, const float *__restrict__ isd) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * d) return;
+    if (t >= (int64_t)ntr * n_sel * d) return;
+    const int64_t tr = t / (n_sel * d);
     const int c = (int)(t % d);
-    X[t] = (X[t] - mu[c]) * isd[c];
+    Xs[t] = (Xs[t] - mu[tr * d + c]) * isd[tr * d + c];
 }
 
-// Gradient of the mean logistic loss: G = (sigmoid(Z) - Y) / n.
-__global__ void k_bce_grad(const float *__restrict__ Z, const float *__restrict__ Y, int64_t cnt,
-                           float inv_n, float *__restrict__ G) {
+// G[t][r][o] = (sigmoid(b_o + x_r . W[:, o]) - Y[r][o]) / n_sel
+__global__ void k_sc_fwd_grad(const float *__restrict__ Xs, int64_t n_sel, int d, int L, int ntr,
+                              const float *__restrict__ P, const float *__restrict__ Y,
+                              float inv_n, float *__restrict__ G) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    G[t] = (1.0f / (1.0f + expf(-Z[t])) - Y[t]) * inv_n;
+    if (t >= (int64_t)ntr * n_sel * L) return;
+    const int64_t tr = t / (n_sel * L);
+    const int64_t rem = t - tr * n_sel * L;
+    const int64_t r = rem / L;
+    const int o = (int)(rem - r * L);
+    const float *W = P + tr * (int64_t)(d + 1) * L;
+    const float *x = Xs + (tr * n_sel + r) * d;
+    float z = W[(int64_t)d * L + o];
+    for (int i = 0; i < d; ++i) z += x[i] * W[(int64_t)i * L + o];
+    G[t] = (1.0f / (1.0f + expf(-z)) - Y[rem]) * inv_n;
 }
 
-// Per test row: predict the top-k labels (k = true label count, ties by
-// label index) and accumulate true positives and the label count.
-__global__ void k_topk_f1(const float *__restrict__ Z, const float *__restrict__ Y, int64_t n,
-                          int L, unsigned long long *__restrict__ counts) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const float *z = Z + r * L;
-    const float *y = Y + r * L;
-    int k = 0;
-    for (int l = 0; l < L; ++l) k += y[l] > 0.5f ? 1 : 0;
-    int tp = 0;
-    for (int l = 0; l < L; ++l) {
-        int rank = 0;
-        for (int j = 0; j < L; ++j) rank += (z[j] > z[l] || (z[j] == z[l] && j < l)) ? 1 : 0;
-        if (rank < k && y[l] > 0.5f) ++tp;
+// part[t][p][i][o] = sum over rows r in chunk p of X[t][r][i] G[t][r][o]
+// (row i = d: the bias, X = 1).
+__global__ void k_sc_wgrad(const float *__restrict__ Xs, int64_t n_sel, int d, int L, int ntr,
+                           const float *__restrict__ G, int nchunk, float *__restrict__ part) {
+    const int64_t per = (int64_t)(d + 1) * L;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ntr * nchunk * per) return;
+    const int64_t tr = t / (nchunk * per);
+    const int64_t rem = t - tr * nchunk * per;
+    const int p = (int)(rem / per);
+    const int64_t j = rem - (int64_t)p * per;
+    const int i = (int)(j / L), o = (int)(j - (int64_t)i * L);
+    const int64_t rows = (n_sel + nchunk - 1) / nchunk;
+    const int64_t r0 = p * rows, r1 = min(n_sel, r0 + rows);
+    const float *x = Xs + tr * n_sel * d;
+    const float *g = G + tr * n_sel * L;
+    float s = 0.0f;
+    if (i < d)
+        for (int64_t r = r0; r < r1; ++r) s += x[r * d + i] * g[r * L + o];
+    else
+        for (int64_t r = r0; r < r1; ++r) s += g[r * L + o];
+    part[t] = s;
+}
+
+// Adam on every trial's (W, b): gradient = sum of the chunk partials + l2 W.
+__global__ void k_sc_adam(float *__restrict__ P, const float *__restrict__ part, int nchunk,
+                          int d, int L, int ntr, float l2, float *__restrict__ m,
+                          float *__restrict__ v, float lr, float b1, float b2, float eps,
+                          float c1, float c2) {
+    const int64_t per = (int64_t)(d + 1) * L;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ntr * per) return;
+    const int64_t tr = t / per, j = t - tr * per;
+    float g = 0.0f;
+    for (int p = 0; p < nchunk; ++p) g += part[(tr * nchunk + p) * per + j];
+    if (j < (int64_t)d * L) g += l2 * P[t];
+    const float mm = b1 * m[t] + (1.0f - b1) * g;
+    const float vv = b2 * v[t] + (1.0f - b2) * g * g;
+    m[t] = mm;
+    v[t] = vv;
+    P[t] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// Per (trial, test row): logits from the raw row X[t][idx[r]] standardised on
+// the fly, top-k prediction with k the true label count (ties by label index)
+// and the true positives; counts[2 t] += TP, counts[2 t + 1] += k.  LMAX > 0:
+// the logits live in registers (L <= LMAX); LMAX == 0: in Z (L floats per row).
+template <int LMAX>
+__global__ void k_sc_test(const float *__restrict__ X, int64_t n, int d, int L, int ntr,
+                          const int32_t *__restrict__ idx, int64_t n_sel,
+                          const uint8_t *__restrict__ lab, const float *__restrict__ mu,
+                          const float *__restrict__ isd, const float *__restrict__ P,
+                          float *__restrict__ Z, unsigned long long *__restrict__ counts) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ntr * n_sel) return;
+    const int64_t tr = t / n_sel, r = t - tr * n_sel;
+    const int64_t src = idx[r];
+    if (src < 0 || src >= n) return;
+    const float *x = X + (tr * n + src) * d;
+    const float *W = P + tr * (int64_t)(d + 1) * L;
+    const float *m = mu + tr * d, *s = isd + tr * d;
+    const uint8_t *y = lab + src * L;
+    int k = 0, tp = 0;
+    if constexpr (LMAX > 0) {
+        float z[LMAX];
+#pragma unroll
+        for (int o = 0; o < LMAX; ++o) z[o] = o < L ? W[(int64_t)d * L + o] : 0.0f;
+        for (int i = 0; i < d; ++i) {
+            const float xi = (x[i] - m[i]) * s[i];
+            const float *w = W + (int64_t)i * L;
+#pragma unroll
+            for (int o = 0; o < LMAX; ++o)
+                if (o < L) z[o] += xi * w[o];
+        }
+        bool pos[LMAX];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            pos[l] = l < L && y[l] != 0;
+            k += pos[l] ? 1 : 0;
+        }
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            if (!pos[l]) continue;
+            int rank = 0;
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j)
+                rank += (j < L && (z[j] > z[l] || (z[j] == z[l] && j < l))) ? 1 : 0;
+            if (rank < k) ++tp;
+        }
+    } else {
+        float *z = Z + t * L;
+        for (int o = 0; o < L; ++o) z[o] = W[(int64_t)d * L + o];
+        for (int i = 0; i < d; ++i) {
+            const float xi = (x[i] - m[i]) * s[i];
+            const float *w = W + (int64_t)i * L;
+            for (int o = 0; o < L; ++o) z[o] += xi * w[o];
+        }
+        for (int l = 0; l < L; ++l) k += y[l] ? 1 : 0;
+        for (int l = 0; l < L; ++l) {
+            if (!y[l]) continue;
+            int rank = 0;
+            for (int j = 0; j < L; ++j) rank += (z[j] > z[l] || (z[j] == z[l] && j < l)) ? 1 : 0;
+            if (rank < k) ++tp;
+        }
     }
-    atomicAdd(&counts[0], (unsigned long long)tp);
-    atomicAdd(&counts[1], (unsigned long long)k);
+    atomicAdd(&counts[2 * tr], (unsigned long long)tp);
+    atomicAdd(&counts[2 * tr + 1], (unsigned long long)k);
+}
+
+// *bad += number of indices outside [0, n)
+__global__ void k_sc_check(const int32_t *__restrict__ idx, int64_t n_sel, int64_t n,
+                           unsigned long long *__restrict__ bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_sel && (idx[t] < 0 || idx[t] >= n)) atomicAdd(bad, 1ull);
 }
 
 struct MlpLayout {
@@ -323,66 +456,91 @@ lne_status lne_mlp_adam(lne_ctx *ctx, int64_t count, float *params, const float 
     return check_launch(ctx, "mlp_adam");
 }
 
+lne_status lne_score_micro_f1_batch(lne_ctx *ctx, const float *X, int32_t n_trials, int64_t n,
+                                    int32_t d, const uint8_t *labels, int32_t n_labels,
+                                    const int32_t *train, int64_t n_train, const int32_t *test,
+                                    int64_t n_test, int32_t epochs, float lr, float l2,
+                                    double *f1) {
+    if (!ctx) return LNE_EINVAL;
+    if (!X || !labels || !train || !test || !f1 || n < 1 || d < 1 || d > 4096 || n_labels < 1 ||
+        n_labels > 1024 || n_train < 1 || n_test < 1 || epochs < 1 || n_trials < 1 ||
+        n_trials > 1024)
+        return fail(ctx, LNE_EINVAL, "score_micro_f1: bad arguments");
+    const int L = n_labels, ntr = n_trials;
+    const int64_t per = (int64_t)(d + 1) * L;
+    // row chunks of the weight gradient: enough threads to fill the device
+    int nchunk = 1;
+    while (nchunk < 64 && (int64_t)ntr * nchunk * per < (1 << 20) && n_train / (2 * nchunk) >= 64)
+        nchunk *= 2;
+    Buf xtr(ctx), ytr(ctx), st(ctx), prm(ctx), g(ctx), part(ctx), zte(ctx), cnt(ctx);
+    LNE_TRY(alloc(ctx, xtr, sizeof(float) * (size_t)ntr * n_train * d));
+    LNE_TRY(alloc(ctx, ytr, sizeof(float) * (size_t)n_train * L));
+    LNE_TRY(alloc(ctx, st, sizeof(float) * (size_t)2 * ntr * d));
+    LNE_TRY(alloc(ctx, prm, sizeof(float) * (size_t)3 * ntr * per));
+    LNE_TRY(alloc(ctx, g, sizeof(float) * (size_t)ntr * n_train * L));
+    LNE_TRY(alloc(ctx, part, sizeof(float) * (size_t)ntr * nchunk * per));
+    LNE_TRY(alloc(ctx, zte, sizeof(float) * (size_t)(L <= 64 ? 1 : ntr * n_test * L)));
+    LNE_TRY(alloc(ctx, cnt, sizeof(unsigned long long) * (size_t)(2 * ntr + 1)));
+    float *mu = st.as<float>(), *isd = mu + (int64_t)ntr * d;
+    float *P = prm.as<float>(), *m = P + (int64_t)ntr * per, *v = m + (int64_t)ntr * per;
+    unsigned long long *counts = cnt.as<unsigned long long>(), *bad = counts + 2 * ntr;
+    LNE_HIP(ctx, hipMemsetAsync(prm.p, 0, prm.bytes, ctx->stream));
+    LNE_HIP(ctx, hipMemsetAsync(cnt.p, 0, cnt.bytes, ctx->stream));
+    {
+        Launch Lc(ctx, "score");
+        const int64_t nx = (int64_t)ntr * n_train * d;
+        k_sc_gather<<<grid_of(nx, 256), 256, 0, ctx->stream>>>(X, n, d, ntr, train, n_train,
+                                                                xtr.as<float>(), bad);
+        k_sc_labels<<<grid_of(n_train * L, 256), 256, 0, ctx->stream>>>(labels, n, L, train,
+                                                                          n_train, ytr.as<float>());
+        k_sc_stats<<<dim3((unsigned)d, (unsigned)ntr), 256, 0, ctx->stream>>>(
+            xtr.as<float>(), n_train, d, mu, isd);
+        k_sc_standardize<<<grid_of(nx, 256), 256, 0, ctx->stream>>>(xtr.as<float>(), n_train, d,
+                                                                     ntr, mu, isd);
+        const float b1 = 0.9f, b2 = 0.999f;
+        const int64_t ng = (int64_t)ntr * n_train * L, nw = (int64_t)ntr * nchunk * per,
+                      np = (int64_t)ntr * per;
+        for (int e = 1; e <= epochs; ++e) {
+            k_sc_fwd_grad<<<grid_of(ng, 256), 256, 0, ctx->stream>>>(
+                xtr.as<float>(), n_train, d, L, ntr, P, ytr.as<float>(), 1.0f / (float)n_train,
+                g.as<float>());
+            k_sc_wgrad<<<grid_of(nw, 256), 256, 0, ctx->stream>>>(xtr.as<float>(), n_train, d, L,
+                                                                   ntr, g.as<float>(), nchunk,
+                                                                   part.as<float>());
+            k_sc_adam<<<grid_of(np, 256), 256, 0, ctx->stream>>>(
+                P, part.as<float>(), nchunk, d, L, ntr, l2, m, v, lr, b1, b2, 1e-8f,
+                1.0f - powf(b1, (float)e), 1.0f - powf(b2, (float)e));
+        }
+        const unsigned gt = grid_of((int64_t)ntr * n_test, 128);
+        if (L <= 64)
+            k_sc_test<64><<<gt, 128, 0, ctx->stream>>>(X, n, d, L, ntr, test, n_test, labels, mu,
+                                                       isd, P, nullptr, counts);
+        else
+            k_sc_test<0><<<gt, 128, 0, ctx->stream>>>(X, n, d, L, ntr, test, n_test, labels, mu,
+                                                      isd, P, zte.as<float>(), counts);
+        k_sc_check<<<grid_of(n_test, 256), 256, 0, ctx->stream>>>(test, n_test, n, bad);
+    }
+    LNE_TRY(check_launch(ctx, "score"));
+    std::vector<unsigned long long> h((size_t)(2 * ntr + 1));
+    LNE_HIP(ctx, hipMemcpyAsync(h.data(), cnt.p, sizeof(unsigned long long) * h.size(),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h[2 * ntr])
+        return fail(ctx, LNE_EINVAL, "score_micro_f1: %llu row indices outside [0, n)", h[2 * ntr]);
+    for (int t = 0; t < ntr; ++t) {
+        // top-k with k = true count: FP = FN = k - TP per row
+        const double tp = (double)h[2 * t], fp = (double)(h[2 * t + 1] - h[2 * t]);
+        f1[t] = (2 * tp + 2 * fp) > 0 ? 2 * tp / (2 * tp + 2 * fp) : 0.0;
+    }
+    return LNE_OK;
+}
+
 lne_status lne_score_micro_f1(lne_ctx *ctx, const float *X, int64_t n, int32_t d,
                               const uint8_t *labels, int32_t n_labels, const int32_t *train,
                               int64_t n_train, const int32_t *test, int64_t n_test,
                               int32_t epochs, float lr, float l2, double *f1) {
-    if (!ctx) return LNE_EINVAL;
-    if (!X || !labels || !train || !test || !f1 || n < 1 || d < 1 || n_labels < 1 ||
-        n_labels > 1024 || n_train < 1 || n_test < 1 || epochs < 1)
-        return fail(ctx, LNE_EINVAL, "score_micro_f1: bad arguments");
-    const int L = n_labels;
-    Buf ws(ctx), cnt(ctx);
-    const int64_t wsz = n_train * (d + L) + n_test * (d + L) + 2 * d + 4 * ((int64_t)d * L + L) +
-                        2 * n_train * L + n_test * L;
-    LNE_TRY(alloc(ctx, ws, sizeof(float) * (size_t)wsz));
-    LNE_TRY(alloc(ctx, cnt, 3 * sizeof(unsigned long long)));
-    float *Xtr = ws.as<float>(), *Ytr = Xtr + n_train * d, *Xte = Ytr + n_train * L,
-          *Yte = Xte + n_test * d, *mu = Yte + n_test * L, *isd = mu + d, *W = isd + d,
-          *b = W + (int64_t)d * L, *gW = b + L, *gb = gW + (int64_t)d * L, *mW = gb + L,
-          *vW = mW + ((int64_t)d * L + L), *Z = vW + ((int64_t)d * L + L), *G = Z + n_train * L,
-          *Zte = G + n_train * L;
-    // W and b are adjacent, as are their gradients: one Adam update covers both
-    LNE_HIP(ctx, hipMemsetAsync(W, 0, sizeof(float) * (size_t)((int64_t)d * L + L), ctx->stream));
-    LNE_HIP(ctx, hipMemsetAsync(mW, 0, sizeof(float) * (size_t)(2 * ((int64_t)d * L + L)),
-                                ctx->stream));
-    LNE_HIP(ctx, hipMemsetAsync(cnt.p, 0, 3 * sizeof(unsigned long long), ctx->stream));
-    {
-        Launch Lc(ctx, "score");
-        unsigned long long *bad = cnt.as<unsigned long long>() + 2;
-        k_gather_rows<<<grid_of(n_train * (d + L), 256), 256, 0, ctx->stream>>>(
-            X, n, d, labels, L, train, n_train, Xtr, Ytr, bad);
-        k_gather_rows<<<grid_of(n_test * (d + L), 256), 256, 0, ctx->stream>>>(
-            X, n, d, labels, L, test, n_test, Xte, Yte, bad);
-        k_col_stats<<<grid_of(d, 64), 64, 0, ctx->stream>>>(Xtr, n_train, d, mu, isd);
-        k_standardize<<<grid_of(n_train * d, 256), 256, 0, ctx->stream>>>(Xtr, n_train, d, mu, isd);
-        k_standardize<<<grid_of(n_test * d, 256), 256, 0, ctx->stream>>>(Xte, n_test, d, mu, isd);
-        const float b1 = 0.9f, b2 = 0.999f;
-        for (int e = 1; e <= epochs; ++e) {
-            k_lin_fwd<<<grid_of(n_train * L, 256), 256, 0, ctx->stream>>>(Xtr, d, W, b, L, n_train,
-                                                                          Z, nullptr);
-            k_bce_grad<<<grid_of(n_train * L, 256), 256, 0, ctx->stream>>>(
-                Z, Ytr, n_train * L, 1.0f / (float)n_train, G);
-            k_lin_wgrad<<<grid_of((int64_t)d * L + L, 256), 256, 0, ctx->stream>>>(
-                Xtr, d, G, L, n_train, W, l2, gW, gb);
-            k_adam<<<grid_of((int64_t)d * L + L, 256), 256, 0, ctx->stream>>>(
-                W, gW, mW, vW, (int64_t)d * L + L, lr, b1, b2, 1e-8f,
-                1.0f - powf(b1, (float)e), 1.0f - powf(b2, (float)e));
-        }
-        k_lin_fwd<<<grid_of(n_test * L, 256), 256, 0, ctx->stream>>>(Xte, d, W, b, L, n_test, Zte,
-                                                                     nullptr);
-        k_topk_f1<<<grid_of(n_test, 256), 256, 0, ctx->stream>>>(Zte, Yte, n_test, L,
-                                                                 cnt.as<unsigned long long>());
-    }
-    LNE_TRY(check_launch(ctx, "score"));
-    unsigned long long h[3] = {0, 0, 0};
-    LNE_HIP(ctx, hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (h[2]) return fail(ctx, LNE_EINVAL, "score_micro_f1: %llu row indices outside [0, n)", h[2]);
-    // top-k with k = true count: FP = FN = k - TP per row
-    const double tp = (double)h[0], fp = (double)(h[1] - h[0]);
-    *f1 = (2 * tp + 2 * fp) > 0 ? 2 * tp / (2 * tp + 2 * fp) : 0.0;
-    return LNE_OK;
+    return lne_score_micro_f1_batch(ctx, X, 1, n, d, labels, n_labels, train, n_train, test,
+                                    n_test, epochs, lr, l2, f1);
 }
 
 }  // extern "C"

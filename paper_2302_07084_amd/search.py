@@ -14,10 +14,11 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import time
 
 import numpy as np
 
-from . import (Context, embed, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
+from . import (Batch, Context, embed, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
                score_micro_f1)
 
 T_MAX = 10
@@ -32,6 +33,9 @@ class Trial:
     k: int             # propagation order, 1..20
     theta: float       # [0, 1]
     mu: float          # [0, 0.5]
+
+    def as_dict(self) -> dict:
+        return {"s": np.asarray(self.s, np.float64), "k": self.k, "theta": self.theta, "mu": self.mu}
 
     def vector(self) -> np.ndarray:
         s = np.zeros(T_MAX)
@@ -167,6 +171,14 @@ def standardize(scores) -> np.ndarray:
     return (y - y.mean()) / (sd if sd > 1e-12 else 1.0)
 
 
+def evaluate_batch(ctx: Context, task: Task, batch: Batch, trials, graph: bool = True):
+    """The batched method on a list of trials: one batch run (shared sampling
+    pass, one launch per step for all trials), then batched scoring on every
+    split; returns the micro-F1 per trial and split (trials x splits)."""
+    X, _ = batch.run([t.as_dict() for t in trials], graph=graph)
+    return np.asarray([score_micro_f1(ctx, X, task.labels, tr, te) for tr, te in task.splits]).T
+
+
 def features(task: Task, trials) -> np.ndarray:
     return np.stack([np.concatenate([t.vector(), task.stats]) for t in trials])
 
@@ -201,3 +213,106 @@ def surrogate_search(ctx, task, sur: Surrogate, budget, rng, pool: int = 4096,
         sur.fit(epochs=100)
         sur.F, sur.y = sur_F, sur_y
     return tried, scores
+
+
+def channel_distribution(trials, floor: float = 0.1) -> np.ndarray:
+    """Length distribution of the shared sampling pass for a batch of trials.
+    Trial t's channel estimate sum_r (s_r / pi_r) W_r has a variance
+    proportional to sum_r s_r^2 / pi_r; the pi minimising its sum over the
+    batch is pi_r ~ sqrt(mean_t s_tr^2).  A uniform share `floor` keeps every
+    length drawn, which bounds the variance of trials far from the batch."""
+    S = np.stack([np.asarray(t.s, np.float64) / np.sum(t.s) for t in trials])
+    pi = np.sqrt((S ** 2).mean(axis=0))
+    pi = pi / pi.sum()
+    return (1.0 - floor) * pi + floor / len(pi)
+
+
+def pretrain_pairs(ctx: Context, tasks, trials_per_graph: int, rng, max_batch: int = 32):
+    """(features, per-graph standardised score) pairs for the surrogate from
+    batched runs of random trials on each task's graph."""
+    F, y = [], []
+    for task in tasks:
+        b = None
+        trials, scores = [], []
+        while len(trials) < trials_per_graph:
+            chunk = sample_trials(rng, min(max_batch, trials_per_graph - len(trials)),
+                                  T=task.base["T"])
+            pi = channel_distribution(chunk)
+            if b is None:
+                b = Batch(ctx, task.rp, task.col, dict(task.base, s=pi),
+                          max_trials=min(max_batch, trials_per_graph))
+            else:
+                b.resample(pi)
+            scores.extend(evaluate_batch(ctx, task, b, chunk).mean(axis=1))
+            trials.extend(chunk)
+        b.close()
+        F.append(features(task, trials))
+        y.extend(standardize(scores))
+    return np.concatenate(F), np.asarray(y)
+
+
+def plain_sequential_search(ctx: Context, task: Task, trials, clock=time.perf_counter):
+    """The plain method, one trial after another (its own sampling pass per
+    trial): returns the scores (trials x splits), the time at which each
+    trial's score was known, and the embedding-only seconds."""
+    import torch
+    t0 = clock()
+    scores, stamps, embed_s = [], [], 0.0
+    for t in trials:
+        a = clock()
+        p = dict(task.base, s=t.s, T=len(t.s), cheb_k=t.k, theta=t.theta, mu=t.mu)
+        X, _ = embed(ctx, task.rp, task.col, p)
+        torch.cuda.synchronize()
+        embed_s += clock() - a
+        scores.append([score_micro_f1(ctx, X, task.labels, tr, te) for tr, te in task.splits])
+        stamps.append(clock() - t0)
+    return np.asarray(scores), stamps, embed_s
+
+
+def batched_surrogate_search(ctx: Context, task: Task, sur, budget: int, rng, per_round: int = 16,
+                             pool: int = 4096, explore: float = 0.25, graph: bool = True,
+                             clock=time.perf_counter):
+    """Batched trials proposed by the surrogate: rounds of `per_round` trials,
+    each round ranked by the surrogate (plus a random share), one shared
+    sampling pass per round with the length distribution fitted to the
+    round's trials, the round run as one batch (HIP graph replay) and scored
+    in one batched call; the surrogate is refitted on the graph's
+    standardised scores after every round.  Returns trials, scores (trials x
+    splits), the time each score was known, the embedding-only seconds and the
+    set-up seconds (the sampling pass and launch-shape tuning)."""
+    import torch
+    t0 = clock()
+    b = None
+    setup = 0.0
+    tried, scores, stamps = [], [], []
+    embed_s = 0.0
+    base_F, base_y = sur.F, sur.y
+    while len(tried) < budget:
+        n = min(per_round, budget - len(tried))
+        cand = sample_trials(rng, pool, T=task.base["T"])
+        pred = sur.predict(features(task, cand))
+        n_exp = int(round(explore * n))
+        pick = [cand[i] for i in np.argsort(-pred)[:n - n_exp]] + \
+            sample_trials(rng, n_exp, T=task.base["T"])
+        a = clock()
+        pi = channel_distribution(pick)
+        if b is None:
+            b = Batch(ctx, task.rp, task.col, dict(task.base, s=pi), max_trials=per_round)
+            setup = clock() - a
+        else:
+            b.resample(pi)
+        X, _ = b.run([t.as_dict() for t in pick], graph=graph)
+        torch.cuda.synchronize()
+        embed_s += clock() - a
+        got = np.asarray([score_micro_f1(ctx, X, task.labels, tr, te)
+                          for tr, te in task.splits]).T
+        now = clock() - t0
+        tried.extend(pick)
+        scores.extend(got)
+        stamps.extend([now] * len(pick))
+        sur.F, sur.y = base_F, base_y
+        sur.add(features(task, tried), standardize(np.asarray(scores).mean(axis=1)))
+        sur.fit(epochs=100)
+    sur.F, sur.y = base_F, base_y
+    b.close()
+    return tried, np.asarray(scores), stamps, embed_s, setup

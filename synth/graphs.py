@@ -282,7 +282,9 @@ WORKLOADS = {
                       p_out=8 / 990_000, seed=0, T=10, s="uniform",
                       M_per_Tm=50, d=256, oversample=10, q=3, cheb_k=10,
                       theta=0.5, mu=0.2, precision="bf16"),
-    "batched": dict(kind="sbm", sizes=[2_000] * 50, intra=0.5, avg_deg=30,
+    # intra-block edge share 0.3: the default parameters score a micro-F1 of
+    # about 0.46 (10% training labels), inside the unsaturated 0.4-0.8 band
+    "batched": dict(kind="sbm", sizes=[2_000] * 50, intra=0.3, avg_deg=30,
                     seed=0, T=10, s="uniform", M_per_Tm=100, d=128,
                     oversample=10, q=1, cheb_k=10, theta=0.5, mu=0.2,
                     precision="f32"),

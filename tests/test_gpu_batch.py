@@ -23,10 +23,11 @@ def procrustes_err(X, Xref):
     return float(np.linalg.norm(X @ (U @ Vt) - Xref) / np.linalg.norm(Xref))
 
 
-@pytest.mark.parametrize("C", [None, "ln"])
-def test_channel_counts_bit_exact(lne, ctx, C):
+@pytest.mark.parametrize("C,pi", [(None, None), ("ln", None), ("ln", [3, 1, 0.5, 2, 0.2, 1])])
+def test_channel_counts_bit_exact(lne, ctx, C, pi):
     for g in (gs.kite(), sbm([40, 40, 40], 0.2, 0.02, seed=4)):
-        p = gs.params(T=6, M_per_m=30, C=(math.log(g.n) if C == "ln" else None), m=g.m, seed=5)
+        p = gs.params(T=6, s=pi, M_per_m=30, C=(math.log(g.n) if C == "ln" else None), m=g.m,
+                      seed=5)
         p["M"] += 7
         rp, col = to_dev(g)
         csr, st = lne.sparsify_channels(ctx, rp, col, p)
@@ -38,9 +39,12 @@ def test_channel_counts_bit_exact(lne, ctx, C):
         assert (st["attempted"], st["accepted"]) == (att, acc)
 
 
-def test_trial_matrix_matches_oracle_mixing(lne, ctx):
+@pytest.mark.parametrize("skew", [False, True])
+def test_trial_matrix_matches_oracle_mixing(lne, ctx, skew):
     g, p = workload("tiny")
     p = dict(p, M=20 * p["T"] * g.m, precision="f32")
+    if skew:
+        p["s"] = np.linspace(1.0, 3.0, p["T"])
     rp, col = to_dev(g)
     ch, _ = lne.sparsify_channels(ctx, rp, col, p)
     R0, C0, W0, _, _ = oracle.count_csr(g, p, channels=True)
@@ -89,6 +93,17 @@ def test_batch_spmm_matches_oracle(lne, ctx):
     for t in range(3):
         ref = Ms[t] @ Xs.astype(np.float64)
         assert np.all(np.abs(Y[t] - ref) <= _spmm_bar(Ms[t], Xs.astype(np.float64)))
+    # a channel pass drawn from another length distribution: same contract
+    pi = np.array([0.05, 0.1, 0.3, 0.2, 0.1, 0.1, 0.1, 0.05])
+    B.resample(pi)
+    R1, C1, W1, _, _ = oracle.count_csr(g, dict(p, s=pi), channels=True)
+    assert B.info()["channel_nnz"] == len(C1)
+    X = rng.standard_normal((3, g.n, 36)).astype(np.float32)
+    Y = B.spmm(trials, torch.from_numpy(X).cuda()).cpu().numpy()
+    for t in range(3):
+        M = oracle.trial_matrix(g, dict(p, s=pi), R1, C1, W1, trials[t]["s"])
+        ref = M @ X[t].astype(np.float64)
+        assert np.all(np.abs(Y[t] - ref) <= _spmm_bar(M, X[t].astype(np.float64)))
     B.close()
 
 
@@ -144,6 +159,13 @@ def test_graph_replays_equal_eager_runs(lne, ctx):
         torch.cuda.synchronize()
         np.testing.assert_allclose(Xb.cpu().numpy(), eager_b.cpu().numpy(), rtol=1e-6, atol=1e-7)
     assert B.info()["graph_captures"] == 2
+    # a new channel pass drops the captured graph; the replay after it
+    # matches the eager run on the new channels
+    B.resample(np.linspace(2.0, 1.0, 10))
+    eager_c, _ = B.run(set_a)
+    Xc, _ = B.run(set_a, graph=True)
+    np.testing.assert_allclose(Xc.cpu().numpy(), eager_c.cpu().numpy(), rtol=1e-6, atol=1e-7)
+    assert B.info()["graph_captures"] == 3
     ch, _ = lne.sparsify_channels(ctx, rp, col, p)
     for t in (0, 3):
         X = _single_trial_reference(lne, ctx, rp, col, p, ch, set_a[t])
@@ -165,6 +187,20 @@ def test_all_trials_off_is_the_rsvd_embedding(lne, ctx):
         M = lne.trial_matrix(ctx, rp, col, p, ch, tr)
         _, _, _, X0 = lne.rsvd(ctx, M, dict(p, s=tr["s"]))
         assert procrustes_err(Xb[t].cpu().numpy(), X0.cpu().numpy()) < 2e-3
+
+
+def test_trial_outside_the_channel_support_is_rejected(lne, ctx):
+    g = sbm([50] * 4, 0.2, 0.02, seed=7)
+    p = dict(T=4, s=np.array([1.0, 1.0, 0.0, 1.0]), M=10 * 4 * g.m, b=1, C=math.log(g.n), d=8,
+             oversample=8, q=1, cheb_k=3, theta=0.5, mu=0.2, seed=4, precision="f32")
+    rp, col = to_dev(g)
+    B = lne.Batch(ctx, rp, col, p, max_trials=2)
+    ok = {"s": np.array([0.5, 0.5, 0.0, 0.0]), "k": 2, "theta": 0.5, "mu": 0.1}
+    bad = {"s": np.array([0.5, 0.0, 0.5, 0.0]), "k": 2, "theta": 0.5, "mu": 0.1}
+    B.run([ok])
+    with pytest.raises(lne.LneError):
+        B.run([ok, bad])
+    B.close()
 
 
 def test_tuner_cache_round_trip(lne, ctx, tmp_path, monkeypatch):

@@ -98,6 +98,55 @@ def test_scorer_matches_liblinear(lne, ctx, noise):
     assert abs(f - f_ref) <= 0.02, (f, f_ref)
 
 
+def test_batched_scorer_equals_single_calls(lne, ctx):
+    """Several embeddings scored in one call give each embedding's own score
+    (the weight-gradient row chunks differ between the calls, so logits agree
+    to rounding and micro-F1 to a few test rows); more than 64 labels take
+    the in-memory logits path."""
+    import torch
+    rng = np.random.default_rng(5)
+    for L in (12, 80):
+        n, d = 2000, 16
+        Y = np.zeros((n, L), dtype=np.uint8)
+        for i in range(n):
+            Y[i, rng.choice(L, rng.integers(1, 3), replace=False)] = 1
+        centers = rng.standard_normal((L, d))
+        Xs = np.stack([(Y @ centers + s * rng.standard_normal((n, d))).astype(np.float32)
+                       for s in (0.8, 1.5, 3.0)])
+        perm = rng.permutation(n)
+        tr = torch.from_numpy(np.sort(perm[:400])).cuda()
+        te = torch.from_numpy(np.sort(perm[400:])).cuda()
+        Yd = torch.from_numpy(Y).cuda()
+        fb = lne.score_micro_f1(ctx, torch.from_numpy(Xs).cuda(), Yd, tr, te)
+        fs = [lne.score_micro_f1(ctx, torch.from_numpy(x).cuda(), Yd, tr, te) for x in Xs]
+        assert len(fb) == 3
+        assert fb[0] > fb[1] > fb[2]
+        np.testing.assert_allclose(fb, fs, atol=3.0 / (1600 * 1.5))
+
+
+def test_search_arms_run_end_to_end(lne, ctx):
+    """Pretraining pairs from batched runs, the plain sequential arm and the
+    batched surrogate arm on a small graph: shapes, monotone clocks, scores in
+    [0, 1] and the batched arm reusing one captured graph per round shape."""
+    from paper_2302_07084_amd import search
+    rng = np.random.default_rng(3)
+    fam = [_task(lne, intra, seed=40 + i) for i, intra in enumerate((0.45, 0.55))]
+    F, y = search.pretrain_pairs(ctx, fam, 8, rng, max_batch=4)
+    assert F.shape == (16, search.IN_DIM) and y.shape == (16,)
+    sur = search.Surrogate(ctx, seed=1)
+    sur.set_scaler(F)
+    sur.add(F, y)
+    sur.fit(epochs=50)
+    task = _task(lne, 0.5, seed=50)
+    sa, ta, ea = search.plain_sequential_search(ctx, task, search.sample_trials(rng, 3))
+    assert sa.shape == (3, len(task.splits)) and np.all(np.diff(ta) > 0) and ea > 0
+    tb, sb, stb, eb, setup = search.batched_surrogate_search(ctx, task, sur, 8, rng, per_round=4)
+    assert len(tb) == 8 and sb.shape == (8, len(task.splits))
+    assert np.all(np.diff(stb) >= 0) and eb > 0 and setup > 0
+    assert np.all((sa >= 0) & (sa <= 1)) and np.all((sb >= 0) & (sb <= 1))
+    assert len(sur.y) == 16                        # refits leave the pretraining set as it was
+
+
 def test_scorer_rejects_bad_indices(lne, ctx):
     import torch
     X = torch.zeros((10, 4), device="cuda")

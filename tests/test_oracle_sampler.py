@@ -293,24 +293,30 @@ def test_row_window_and_slots_agree_with_full():
     assert ok.sum() == acc and len(ok) == att
 
 
-def test_channel_mixture_is_unbiased_for_each_trial():
-    """Batched trials share one pass with r uniform (pi_r = 1/T) and weight the
-    length-r channel by s_r / pi_r: for any s the mixture has the expectation
-    E[W] = 2^F (M/m) sum_r s_r A P^(r-1) of the trial's own sampler."""
+@pytest.mark.parametrize("pi", [[1, 1, 1], [0.2, 0.3, 0.5]])
+def test_channel_mixture_is_unbiased_for_each_trial(pi):
+    """Batched trials share one pass whose lengths are drawn from pi and
+    weight the length-r channel by s_r / pi_r: for any s the mixture has the
+    expectation E[W] = 2^F (M/m) sum_r s_r A P^(r-1) of the trial's own
+    sampler."""
     g = gs.kite()
     T = 3
-    p = gs.params(T=T, s=[1, 1, 1], M_per_m=30000, C=0.5, m=g.m, seed=21)
+    p = gs.params(T=T, s=pi, M_per_m=30000, C=0.5, m=g.m, seed=21)
+    pi = np.asarray(pi, float) / np.sum(pi)
     R, Cext, W, att, acc = oracle.count_csr(g, p, channels=True)
     rows = np.repeat(np.arange(g.n), np.diff(R))
     chan = np.zeros((T, g.n, g.n))
     np.add.at(chan, (Cext & 15, rows, Cext >> 4), W.astype(np.float64))
+    # each channel holds the samples of its length only, in proportion pi_r
+    per = np.array([chan[r].sum() for r in range(T)])
+    assert np.allclose(per / per.sum(), pi, atol=0.02)
     deg = g.degrees()
     wmax = max(round(F / min(1.0, 0.5 * (1 / deg[u] + 1 / deg[v])))
                for u in range(g.n) for v in g.col[g.rowptr[u]:g.rowptr[u + 1]])
     for s in ([0.2, 0.5, 0.3], [1.0, 0.0, 0.0], [0.0, 0.1, 0.9]):
         s = np.asarray(s)
-        mixed = np.tensordot(T * s, chan, axes=1)
+        mixed = np.tensordot(s / pi, chan, axes=1)
         exp = expected_W(g, s, p["M"])
-        var = 2 * wmax * T * max(s) * exp + 1e-9
+        var = 2 * wmax * max(s / pi) * exp + 1e-9
         z = np.abs(mixed - exp) / np.sqrt(var)
         assert z.max() < 6, (s, z.max())
