@@ -181,12 +181,12 @@ static int sample_slot(const graph_t *g, const plan_t *pl, uint64_t seed, int64_
 {
     stream_t st;
     stream_init(&st, seed, e, j);
-    uint32_t z0 = stream_next(&st);   /* coin   (Alg. 4: p ~ U[0,1])        */
-    uint32_t z1 = stream_next(&st);   /* length (Alg. 4: r ~ Multinomial)   */
+    uint32_t z0 = stream_next(&st);   /* coin: p ~ U[0,1] (Downsampled Per-Edge PathSampling) */
+    uint32_t z1 = stream_next(&st);   /* length: r ~ Multinomial(s) (same algorithm)          */
     if (!(all || (uint64_t)z0 < tau)) return 0;
     int r = 1;
     while ((uint64_t)z1 >= pl->theta[r - 1]) ++r;
-    uint32_t z2 = stream_next(&st);   /* split  (Alg. 1: s ~ U{0..r-1})     */
+    uint32_t z2 = stream_next(&st);   /* split: uniform in 0..r-1 (PathSampling)              */
     int split = (int)(z2 % (uint32_t)r);
     int32_t x = u;
     for (int i = 0; i < split; ++i) x = walk_step(g, x, stream_next(&st));

@@ -275,54 +275,6 @@ std::string tune_key(const char *op, const lne_batch *b, int k) {
     return buf;
 }
 
-int cached_variant(const std::string &key) {
-    const char *path = std::getenv("LNE_TUNE_CACHE");
-    if (!path || !*path) return -1;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return -1;
-    char line[1024];
-    int v = -1;
-    while (std::fgets(line, sizeof(line), f)) {
-        if (!std::strstr(line, key.c_str())) continue;
-        const char *q = std::strstr(line, "\"variant\": ");
-        if (q) v = std::atoi(q + 11);
-    }
-    std::fclose(f);
-    return v;
-}
-
-void store_variant(const std::string &key, int v, const std::vector<float> &ms) {
-    const char *path = std::getenv("LNE_TUNE_CACHE");
-    if (!path || !*path) return;
-    FILE *f = std::fopen(path, "a");
-    if (!f) return;
-    std::fprintf(f, "{%s, \"variant\": %d, \"ms\": [", key.c_str(), v);
-    for (size_t i = 0; i < ms.size(); ++i) std::fprintf(f, "%s%.4f", i ? ", " : "", ms[i]);
-    std::fprintf(f, "]}\n");
-    std::fclose(f);
-}
-
-template <class Run>
-lne_status time_variants(lne_ctx *ctx, int nv, Run run, int *best, std::vector<float> &ms) {
-    hipEvent_t e0, e1;
-    LNE_HIP(ctx, hipEventCreate(&e0));
-    LNE_HIP(ctx, hipEventCreate(&e1));
-    lne_status s = run(0);   // warm-up
-    ms.assign(nv, 0.f);
-    for (int v = 0; v < nv && s == LNE_OK; ++v) {
-        (void)hipEventRecord(e0, ctx->stream);
-        s = run(v);
-        (void)hipEventRecord(e1, ctx->stream);
-        if (s == LNE_OK && hipEventSynchronize(e1) != hipSuccess) s = LNE_EHIP;
-        if (s == LNE_OK) (void)hipEventElapsedTime(&ms[v], e0, e1);
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    LNE_TRY(s);
-    *best = (int)(std::min_element(ms.begin(), ms.end()) - ms.begin());
-    return LNE_OK;
-}
-
 lne_status tune(lne_batch *b) {
     lne_ctx *ctx = b->ctx;
     const int nt = std::min(2, b->max_trials);
@@ -340,27 +292,16 @@ lne_status tune(lne_batch *b) {
                                 hipMemcpyHostToDevice, ctx->stream));
     LNE_HIP(ctx, hipMemcpyAsync(b->pc(), pc.data(), sizeof(float) * pc.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
-    std::vector<float> ms;
-    const std::string ks = tune_key("spmm_chan", b, b->dp);
-    int v = cached_variant(ks);
-    if (v < 0 || v >= kSpmmChanVariants) {
-        LNE_TRY(time_variants(ctx, kSpmmChanVariants, [&](int var) {
-            return spmm_chan(ctx, &b->ext, nt, b->chan(), b->om.as<float>(), b->dp, 0,
-                             b->B.as<float>(), b->dp, ys, b->dp, var);
-        }, &v, ms));
-        store_variant(ks, v, ms);
-    }
-    b->spmm_v = v;
-    const std::string kg = tune_key("graph_spmm_batch", b, b->d8);
-    v = cached_variant(kg);
-    if (v < 0 || v >= kGspmmBatchVariants) {
-        LNE_TRY(time_variants(ctx, kGspmmBatchVariants, [&](int var) {
-            return gspmm_batch(ctx, &b->g, nt, b->d8, b->d8, xs, b->X0.as<float>(), b->P0.as<float>(),
-                               nullptr, nullptr, nullptr, b->pc(), var);
-        }, &v, ms));
-        store_variant(kg, v, ms);
-    }
-    b->gspmm_v = v;
+    LNE_TRY(pick_variant(ctx, tune_key("spmm_chan", b, b->dp), kSpmmChanVariants, [&](int var) {
+        return spmm_chan(ctx, &b->ext, nt, b->chan(), b->om.as<float>(), b->dp, 0,
+                         b->B.as<float>(), b->dp, ys, b->dp, var);
+    }, &b->spmm_v));
+    LNE_TRY(pick_variant(ctx, tune_key("graph_spmm_batch", b, b->d8), kGspmmBatchVariants,
+                         [&](int var) {
+        return gspmm_batch(ctx, &b->g, nt, b->d8, b->d8, xs, b->X0.as<float>(), b->P0.as<float>(),
+                           nullptr, nullptr, nullptr, b->pc(), var);
+    }, &b->gspmm_v));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return LNE_OK;
 }
 

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -31,6 +32,7 @@ struct lne_ctx {
     size_t arena_cap = 0, arena_used = 0, arena_need = 0;
     bool arena_on = false, arena_measure = false;
     bool capturing = false;   // no event bracketing while a graph is captured
+    std::map<std::string, int> tuned;   // launch-shape choices (pick_variant)
 };
 
 namespace lne {
@@ -80,6 +82,18 @@ struct Launch {
     ~Launch();
 };
 lne_status check_launch(lne_ctx *ctx, const char *name);
+
+// Launch-shape tuning (tune.hip).  `key` names the operation and its shape
+// (a JSON fragment "op": ..., "n": ..., ...).  The first time a key is seen,
+// every variant 0..nv-1 is run once (after one warm-up run) and timed with
+// events; the fastest is kept in the context and, when LNE_TUNE_CACHE names
+// a file, appended to it as one JSON line (later processes read it from
+// there).  During graph capture nothing is timed: a known choice or 0.
+// run(v) must leave the same result whatever v, and be repeatable.
+lne_status pick_variant(lne_ctx *ctx, const std::string &key, int nv,
+                        const std::function<lne_status(int)> &run, int *out);
+// The choice made for key so far, or dflt.
+int tuned_or(lne_ctx *ctx, const std::string &key, int dflt);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline unsigned grid_of(int64_t work, int block) {

@@ -12,8 +12,11 @@
 // the wave is split into G = 64 / L lane groups of L lanes, each lane moving
 // 16 bytes per gathered row (float4 / double2 / 8 x bf16), so a 16-byte
 // aligned gathered row of up to L * 16 bytes is one vector load per lane and G
-// nonzeros are in flight per instruction.  Groups are combined by a butterfly
-// over lane offsets L, 2L, ... before the epilogue writes the row.
+// nonzeros are in flight per instruction, U such instructions per loop step.
+// Each group accumulates its nonzeros in row order (so U, the memory-level
+// parallelism, does not change the result); groups are combined by a
+// butterfly over lane offsets L, 2L, ... before the epilogue writes the row.
+// U is picked per matrix and width by timing (pick_variant).
 #include "common.hpp"
 
 namespace lne {
@@ -52,9 +55,17 @@ __device__ __forceinline__ void store_row(OT *__restrict__ p, int c0, int k, con
         if (c0 + i < k) p[i] = (OT)v[i];
 }
 
-// L = lanes per gathered row (power of two, <= 64); VT value type (void for
-// the graph kernel); XT operand type; OT output type.
-template <int L, class VT, class XT, class OT>
+// Loads of the streamed sparse structure, optionally marked non-temporal so
+// that the stream does not displace gathered rows from the caches.
+template <bool NT, class T> __device__ __forceinline__ T stream_load(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// L = lanes per gathered row (power of two, <= 64); U = loop steps in
+// flight; NT = non-temporal structure loads; VT value type; XT operand type;
+// OT output type.
+template <int L, int U, bool NT, class VT, class XT, class OT>
 __global__ void __launch_bounds__(256)
 k_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
        const VT *__restrict__ val, int64_t n_rows, const XT *__restrict__ X, int64_t ldx,
@@ -74,35 +85,36 @@ k_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
         for (int i = 0; i < N; ++i) acc[i] = 0;
         for (int64_t b0 = beg; b0 < end; b0 += 64) {
             const int64_t idx = b0 + lane;
-            const int32_t cj = idx < end ? col[idx] : 0;
-            const AT vj = idx < end ? (AT)val[idx] : (AT)0;
+            const int32_t cj = idx < end ? stream_load<NT>(col + idx) : 0;
+            const AT vj = idx < end ? (AT)stream_load<NT>(val + idx) : (AT)0;
             const int cnt = (int)min((int64_t)64, end - b0);
             // the trip count is the same for every lane, so every shuffle
             // reads from lanes that are active
-            for (int t0 = 0; t0 < cnt; t0 += 4 * G) {
-                const int t[4] = {t0 + grp, t0 + grp + G, t0 + grp + 2 * G, t0 + grp + 3 * G};
-                int32_t j[4];
-                AT v[4];
+            for (int t0 = 0; t0 < cnt; t0 += U * G) {
+                int32_t j[U];
+                AT v[U];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    j[q] = __shfl(cj, t[q] & 63);
-                    v[q] = __shfl(vj, t[q] & 63);
+                for (int q = 0; q < U; ++q) {
+                    // every lane shuffles (a shuffle under a lane-dependent
+                    // condition could read a lane that is switched off)
+                    const int t = t0 + grp + q * G;
+                    j[q] = __shfl(cj, t & 63);
+                    const AT vq = __shfl(vj, t & 63);
+                    v[q] = t < cnt ? vq : (AT)0;
                 }
-                AT x[4][N];
+                AT x[U][N];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (t[q] < cnt && c0 < k)
+                for (int q = 0; q < U; ++q) {
+                    if (t0 + grp + q * G < cnt && c0 < k)
                         load_row<XT, AT, N>(X + (int64_t)j[q] * ldx + c0, c0, k, x[q]);
                     else
 #pragma unroll
                         for (int i = 0; i < N; ++i) x[q][i] = 0;
                 }
 #pragma unroll
-                for (int i = 0; i < N; ++i)
-                    acc[i] += (t[0] < cnt ? v[0] * x[0][i] : (AT)0) +
-                              (t[1] < cnt ? v[1] * x[1][i] : (AT)0) +
-                              (t[2] < cnt ? v[2] * x[2][i] : (AT)0) +
-                              (t[3] < cnt ? v[3] * x[3][i] : (AT)0);
+                for (int q = 0; q < U; ++q)
+#pragma unroll
+                    for (int i = 0; i < N; ++i) acc[i] += v[q] * x[q][i];
             }
         }
 #pragma unroll
@@ -113,7 +125,7 @@ k_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     }
 }
 
-template <int L, class T>
+template <int L, int U, bool NT, class T>
 __global__ void __launch_bounds__(256)
 k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n_rows,
              const T *__restrict__ Z, int64_t ld, int k, T *__restrict__ out, T a, T b,
@@ -134,24 +146,25 @@ k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, in
         for (int i = 0; i < N; ++i) acc[i] = 0;
         for (int64_t b0 = beg; b0 < end; b0 += 64) {
             const int64_t idx = b0 + lane;
-            const int32_t cj = idx < end ? col[idx] : 0;
+            const int32_t cj = idx < end ? stream_load<NT>(col + idx) : 0;
             const int cnt = (int)min((int64_t)64, end - b0);
-            for (int t0 = 0; t0 < cnt; t0 += 4 * G) {
-                const int t[4] = {t0 + grp, t0 + grp + G, t0 + grp + 2 * G, t0 + grp + 3 * G};
-                int32_t j[4];
+            for (int t0 = 0; t0 < cnt; t0 += U * G) {
+                int32_t j[U];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) j[q] = __shfl(cj, t[q] & 63);
-                T x[4][N];
+                for (int q = 0; q < U; ++q) j[q] = __shfl(cj, (t0 + grp + q * G) & 63);
+                T x[U][N];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (t[q] < cnt && c0 < k)
+                for (int q = 0; q < U; ++q) {
+                    if (t0 + grp + q * G < cnt && c0 < k)
                         load_row<T, T, N>(Z + (int64_t)j[q] * ld + c0, c0, k, x[q]);
                     else
 #pragma unroll
                         for (int i = 0; i < N; ++i) x[q][i] = 0;
                 }
 #pragma unroll
-                for (int i = 0; i < N; ++i) acc[i] += (x[0][i] + x[1][i]) + (x[2][i] + x[3][i]);
+                for (int q = 0; q < U; ++q)
+#pragma unroll
+                    for (int i = 0; i < N; ++i) acc[i] += x[q][i];
             }
         }
 #pragma unroll
@@ -203,6 +216,9 @@ __global__ void k_axpby(const T *__restrict__ x, const T *__restrict__ y, T *__r
     out[o] = a * x[o] + b * y[o];
 }
 
+// launch shapes: unroll depth 4 or 8, structure loads normal or non-temporal
+constexpr int kSpmmVariants = 4;
+
 int lanes_for(int k, int N) {
     const int need = (k + N - 1) / N;
     int L = 1;
@@ -210,54 +226,97 @@ int lanes_for(int k, int N) {
     return L;
 }
 
+template <int L, class VT, class XT, class OT>
+void spmm_launch(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y, int64_t ldy,
+                 int k, int variant) {
+    const unsigned grid = grid_of(A->n_rows * 64, 256);
+    const VT *val = (const VT *)A->val;
+    Launch Lc(ctx, "spmm");
+#define LNE_SV(UU, NTT)                                                                       \
+    k_spmm<L, UU, NTT, VT, XT, OT><<<grid, 256, 0, ctx->stream>>>(A->row_ptr, A->col, val,     \
+                                                                  A->n_rows, X, ldx, Y, ldy, k)
+    switch (variant) {
+        case 1: LNE_SV(8, false); break;
+        case 2: LNE_SV(4, true); break;
+        case 3: LNE_SV(8, true); break;
+        default: LNE_SV(4, false); break;
+    }
+#undef LNE_SV
+}
+
 template <class VT, class XT, class OT>
 lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y,
-                  int64_t ldy, int k) {
+                  int64_t ldy, int k, int dtype) {
     const int N = Vec<XT>::N;
     const bool aligned = ((uintptr_t)X % 16 == 0) && (ldx % N == 0);
-    const unsigned grid = grid_of(A->n_rows * 64, 256);
     const int L = lanes_for(k, N);
-    const VT *val = (const VT *)A->val;
     if (!aligned) return fail(ctx, LNE_EINVAL, "spmm: X must be 16-byte aligned with ld %% %d == 0", N);
-    Launch Lc(ctx, "spmm");
-#define LNE_SPMM_CASE(LL)                                                                  \
-    case LL:                                                                               \
-        k_spmm<LL, VT, XT, OT><<<grid, 256, 0, ctx->stream>>>(A->row_ptr, A->col, val,    \
-                                                              A->n_rows, X, ldx, Y, ldy,   \
-                                                              k);                          \
-        break;
-    switch (L) {
-        LNE_SPMM_CASE(1) LNE_SPMM_CASE(2) LNE_SPMM_CASE(4) LNE_SPMM_CASE(8)
-        LNE_SPMM_CASE(16) LNE_SPMM_CASE(32) LNE_SPMM_CASE(64)
-        default: break;
+    auto run = [&](int v) -> lne_status {
+        switch (L) {
+            case 1: spmm_launch<1, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+            case 2: spmm_launch<2, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+            case 4: spmm_launch<4, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+            case 8: spmm_launch<8, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+            case 16: spmm_launch<16, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+            case 32: spmm_launch<32, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+            default: spmm_launch<64, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
+        }
+        return check_launch(ctx, "spmm");
+    };
+    int v = 0;
+    char key[160];
+    snprintf(key, sizeof(key), "\"op\": \"spmm\", \"n\": %lld, \"nnz\": %lld, \"k\": %d, \"dtype\": %d",
+             (long long)A->n_rows, (long long)A->nnz, k, dtype);
+    LNE_TRY(pick_variant(ctx, key, kSpmmVariants, run, &v));
+    return run(v);
+}
+
+template <int L, class T>
+void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k,
+                  double a, double b, const T *E1, double c1, const T *E2, double c2, T *acc,
+                  double cacc, int variant) {
+    const unsigned grid = grid_of(g->n * 64, 256);
+    Launch Lc(ctx, "graph_spmm");
+#define LNE_GS(UU, NTT)                                                                       \
+    k_graph_spmm<L, UU, NTT, T><<<grid, 256, 0, ctx->stream>>>(g->row_ptr, g->col, g->n, Z, ld, \
+                                                               k, out, (T)a, (T)b, E1, (T)c1,   \
+                                                               E2, (T)c2, acc, (T)cacc)
+    switch (variant) {
+        case 1: LNE_GS(8, false); break;
+        case 2: LNE_GS(4, true); break;
+        case 3: LNE_GS(8, true); break;
+        default: LNE_GS(4, false); break;
     }
-#undef LNE_SPMM_CASE
-    return LNE_OK;
+#undef LNE_GS
 }
 
 template <class T>
 lne_status gspmm_t(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k,
                    double a, double b, const T *E1, double c1, const T *E2, double c2,
-                   T *acc, double cacc) {
+                   T *acc, double cacc, int dtype) {
     const int N = Vec<T>::N;
     if ((uintptr_t)Z % 16 || (uintptr_t)out % 16 || ld % N)
         return fail(ctx, LNE_EINVAL, "graph_spmm: operands must be 16-byte aligned");
-    const unsigned grid = grid_of(g->n * 64, 256);
     const int L = lanes_for(k, N);
-    Launch Lc(ctx, "graph_spmm");
-#define LNE_GSPMM_CASE(LL)                                                                   \
-    case LL:                                                                                 \
-        k_graph_spmm<LL, T><<<grid, 256, 0, ctx->stream>>>(g->row_ptr, g->col, g->n, Z, ld, \
-                                                           k, out, (T)a, (T)b, E1, (T)c1,   \
-                                                           E2, (T)c2, acc, (T)cacc);        \
-        break;
-    switch (L) {
-        LNE_GSPMM_CASE(1) LNE_GSPMM_CASE(2) LNE_GSPMM_CASE(4) LNE_GSPMM_CASE(8)
-        LNE_GSPMM_CASE(16) LNE_GSPMM_CASE(32) LNE_GSPMM_CASE(64)
-        default: break;
-    }
-#undef LNE_GSPMM_CASE
-    return LNE_OK;
+    auto run = [&](int v) -> lne_status {
+        switch (L) {
+#define LNE_GC(LL)                                                                          \
+    case LL: gspmm_launch<LL, T>(ctx, g, Z, out, ld, k, a, b, E1, c1, E2, c2, acc, cacc, v); break;
+            LNE_GC(1) LNE_GC(2) LNE_GC(4) LNE_GC(8) LNE_GC(16) LNE_GC(32)
+            default: gspmm_launch<64, T>(ctx, g, Z, out, ld, k, a, b, E1, c1, E2, c2, acc, cacc, v);
+#undef LNE_GC
+        }
+        return check_launch(ctx, "graph_spmm");
+    };
+    int v = 0;
+    char key[160];
+    snprintf(key, sizeof(key), "\"op\": \"graph_spmm\", \"n\": %lld, \"nnz\": %lld, \"k\": %d, \"dtype\": %d",
+             (long long)g->n, (long long)g->n_arcs, k, dtype);
+    // the tuning runs write `out` and add to `acc`: tune only calls without an
+    // accumulator, whose output is recomputed by the final run
+    if (!acc) LNE_TRY(pick_variant(ctx, key, kSpmmVariants, run, &v));
+    else v = tuned_or(ctx, key, 0);
+    return run(v);
 }
 
 }  // namespace
@@ -267,18 +326,19 @@ lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void
     lne_status s;
     if (dtype == LNE_F64) {
         if (A->val_type != LNE_F64) return fail(ctx, LNE_EINVAL, "spmm: F64 needs F64 values");
-        s = spmm_t<double, double, double>(ctx, A, (const double *)X, ldx, (double *)Y, ldy, k);
+        s = spmm_t<double, double, double>(ctx, A, (const double *)X, ldx, (double *)Y, ldy, k,
+                                           dtype);
     } else if (dtype == LNE_F32) {
         if (A->val_type != LNE_F32) return fail(ctx, LNE_EINVAL, "spmm: F32 needs F32 values");
-        s = spmm_t<float, float, float>(ctx, A, (const float *)X, ldx, (float *)Y, ldy, k);
+        s = spmm_t<float, float, float>(ctx, A, (const float *)X, ldx, (float *)Y, ldy, k, dtype);
     } else if (dtype == LNE_BF16) {
         if (A->val_type != LNE_F32) return fail(ctx, LNE_EINVAL, "spmm: BF16 needs F32 values");
-        s = spmm_t<float, __bf16, __bf16>(ctx, A, (const __bf16 *)X, ldx, (__bf16 *)Y, ldy, k);
+        s = spmm_t<float, __bf16, __bf16>(ctx, A, (const __bf16 *)X, ldx, (__bf16 *)Y, ldy, k,
+                                          dtype);
     } else {
         return fail(ctx, LNE_EINVAL, "spmm: bad dtype");
     }
-    LNE_TRY(s);
-    return check_launch(ctx, "spmm");
+    return s;
 }
 
 lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out, int64_t ld,
@@ -287,14 +347,15 @@ lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out
     lne_status s;
     if (dtype == LNE_F64)
         s = gspmm_t<double>(ctx, g, (const double *)Z, (double *)out, ld, k, a, b,
-                            (const double *)E1, c1, (const double *)E2, c2, (double *)acc, cacc);
+                            (const double *)E1, c1, (const double *)E2, c2, (double *)acc, cacc,
+                            dtype);
     else if (dtype == LNE_F32)
         s = gspmm_t<float>(ctx, g, (const float *)Z, (float *)out, ld, k, a, b,
-                           (const float *)E1, c1, (const float *)E2, c2, (float *)acc, cacc);
+                           (const float *)E1, c1, (const float *)E2, c2, (float *)acc, cacc,
+                           dtype);
     else
         return fail(ctx, LNE_EINVAL, "graph_spmm: bad dtype");
-    LNE_TRY(s);
-    return check_launch(ctx, "graph_spmm");
+    return s;
 }
 
 lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,

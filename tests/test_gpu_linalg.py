@@ -120,6 +120,41 @@ def test_spmm_vs_scipy(lne, ctx, tiny, prec):
         assert np.all(np.abs(Y - ref) <= 4 * np.sqrt(A.getnnz(1).max()) * u * scale + 1e-300)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spmm_launch_shapes_give_identical_results(lne, ctx, tiny, tmp_path, monkeypatch, prec):
+    """Every unroll depth the tuner may pick computes the same bits: each lane
+    group accumulates its nonzeros in row order whatever the depth.  A fresh
+    context reads the choice from the tuning cache file."""
+    import torch
+    g, p, rp, col, st = tiny
+    pp = dict(p, precision=prec)
+    counts, _ = lne.sparsify(ctx, rp, col, pp)
+    M = lne.trunc_log(ctx, rp, col, pp, counts)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    code = 0 if prec == "f64" else 1
+    outs = []
+    for v in range(4):
+        for k in (8, 136):
+            path = tmp_path / f"tune_{v}_{k}.jsonl"
+            key = f'"op": "spmm", "n": {g.n}, "nnz": {M.nnz}, "k": {k}, "dtype": {code}'
+            gkey = f'"op": "graph_spmm", "n": {g.n}, "nnz": {g.n_arcs}, "k": {k}, "dtype": {code}'
+            path.write_text(f'{{{key}, "variant": {v}, "ms": []}}\n'
+                            f'{{{gkey}, "variant": {v}, "ms": []}}\n')
+            monkeypatch.setenv("LNE_TUNE_CACHE", str(path))
+            c2 = lne.Context()
+            X = torch.from_numpy(np.random.default_rng(k).standard_normal((g.n, k))).to(tdt).cuda()
+            Y = lne.spmm(c2, M, X)
+            Z = lne.propagate(c2, rp, col, dict(pp, flags=lne.FLAG_NO_FINAL_EIGSVD, d=k), X)
+            outs.append((k, Y.cpu().numpy(), Z.cpu().numpy()))
+            c2.close()
+            assert path.read_text().count("\n") == 2          # nothing re-tuned
+    for k in (8, 136):
+        same = [o for o in outs if o[0] == k]
+        for o in same[1:]:
+            np.testing.assert_array_equal(o[1], same[0][1])
+            np.testing.assert_array_equal(o[2], same[0][2])
+
+
 def test_rsvd_matches_oracle_f64(lne, ctx, tiny):
     g, p, rp, col, st = tiny
     counts, _ = lne.sparsify(ctx, rp, col, p)
