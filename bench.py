@@ -47,7 +47,37 @@ def kernel_bytes(name, ctx_info):
         return P * (8 + 4) * 2 + (P // 4096 + 1) * 256 * 12
     if name == "radix_hist":
         return P * 8
+    if name == "reduce_trunc_log":
+        # (key, weight) per item read, (column, value) per distinct pair
+        # written, row offsets
+        return P * 12 + ctx_info["nnz_counts"] * (4 + es) + 8 * (n + 1)
     return None
+
+
+# Counter summary of the dominant kernels (profiles/): FETCH_SIZE and
+# WRITE_SIZE per launch and the calibration factors of a plain copy.
+COUNTERS = os.path.join(ROOT, "profiles", "counters_large.json")
+KERNEL_SOURCE = {"spmm": "k_spmm.hip", "graph_spmm": "k_spmm.hip",
+                 "radix_scatter": "k_sort.hip", "radix_hist": "k_sort.hip",
+                 "reduce_trunc_log": "k_sort.hip"}
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of `name` from the committed counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            summ = json.load(f)
+        ent = summ["kernels"][name]
+        src = os.path.join(ROOT, "paper_2302_07084_amd", "csrc", ent["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != ent["source_sha256"]:
+                return None
+        return (ent["fetch_kib_per_launch"] * summ["fetch_factor"] +
+                ent["write_kib_per_launch"] * summ["write_factor"]) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -130,10 +160,10 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.1f} ms/step")
 
     names = ["validate_graph", "row_up", "fill_edges", "sample_count", "sample_emit", "scan",
-             "radix_hist", "radix_scatter", "heads", "reduce", "rowptr_tail",
-             "trunc_log_count", "trunc_log_fill", "gaussian", "spmm", "gram", "gram_reduce",
-             "chol_inv", "project", "sym_eig", "eig_weights", "w_to_bf16", "graph_spmm",
-             "dense_scale", "axpby"]
+             "radix_hist", "radix_scatter", "heads", "reduce", "reduce_trunc_log", "drop_zeros",
+             "rowptr_tail", "concat_rows", "trunc_log_count", "trunc_log_fill", "gaussian",
+             "spmm", "gram", "gram_reduce", "chol_inv", "project", "sym_eig", "eig_weights",
+             "w_to_bf16", "graph_spmm", "dense_scale", "axpby"]
     prof = {}
     for nm in names:
         ms, cnt = ctx.prof_get(nm)
@@ -145,7 +175,7 @@ def main():
     kp = p["d"] + p["oversample"]
     es = 8 if p["precision"] == "f64" else 4
     info = dict(n=g.n, nnz_M=stats["nnz_log"], kp=kp, arcs=g.n_arcs, d=p["d"],
-                pairs=2 * stats["accepted"], es=es)
+                pairs=2 * stats["accepted"], es=es, nnz_counts=stats["nnz_counts"])
     dominant = max(prof, key=lambda k: prof[k]["ms_per_step"])
     rl_name = dominant if kernel_bytes(dominant, info) is not None else "spmm"
     nbytes = kernel_bytes(rl_name, info)
@@ -176,7 +206,8 @@ def main():
                    "oversample": p["oversample"], "q": p["q"], "precision": p["precision"],
                    "parallelism": "single GPU"},
         "roofline": {"kernel": rl_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(rl_name),
                      "bytes_per_launch": nbytes, "avg_launch_ms": prof[rl_name]["avg_ms"]},
         "stats": stats,
         "sampler_edges_per_s": stats["accepted"] / (sampler_ms * 1e-3) if sampler_ms else None,

@@ -330,7 +330,8 @@ lne_status lne_batch_spmm(lne_batch *b, const lne_trial *trials, int32_t n_trial
  * Host only.  Errors: EINVAL (b NULL). */
 lne_status lne_batch_info(const lne_batch *b, int32_t *spmm_variant, int32_t *gspmm_variant,
                           int64_t *channel_nnz, int32_t *captures);
-/* Waits for the context's stream and releases the batch. */
+/* Waits for the context's stream and releases the batch (before the context
+ * it was created on is destroyed). */
 void lne_batch_destroy(lne_batch *b);
 
 /* One-shot batch: lne_batch_create, one eager lne_batch_run, lne_batch_destroy.

@@ -19,7 +19,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 # the sampler takes its coin thresholds and weights as separate IEEE ops
 PER_FILE = {"k_sample.hip": ["-ffp-contract=off"],
-            "k_trunclog.hip": ["-ffp-contract=off"]}
+            "k_trunclog.hip": ["-ffp-contract=off"],
+            "k_sort.hip": ["-ffp-contract=off"]}
 
 
 def sources():

@@ -245,10 +245,19 @@ static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int6
     return LNE_OK;
 }
 
+// With a TruncLogFuse the aggregation writes Eq. (1)'s matrix directly.
+struct TruncLogFuse {
+    TLConst c;
+    int32_t val_type;
+    uint64_t kept = 0;     // nonzero entries over all blocks so far
+};
+
 // Aggregates the pair entries of rows [lo, hi) (already counted into S.wo)
-// into a count CSR block with hi - lo rows.
+// into a count CSR block with hi - lo rows (or, with tl, the truncated-log
+// block with explicit zeros for dropped pairs).
 static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
-                                  int64_t hi, uint64_t entries, lne_csr *out) {
+                                  int64_t hi, uint64_t entries, lne_csr *out,
+                                  TruncLogFuse *tl = nullptr) {
     const int64_t P = (int64_t)entries;
     Buf k0(ctx), v0(ctx), k1(ctx), v1(ctx);
     LNE_TRY(alloc(ctx, k0, sizeof(uint64_t) * (size_t)(P > 0 ? P : 1)));
@@ -269,6 +278,13 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
     }
     const uint64_t *keys = which ? k1.as<uint64_t>() : k0.as<uint64_t>();
     const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
+    if (tl) {
+        uint64_t kept = 0;
+        LNE_TRY(reduce_to_matrix(ctx, keys, vals, P, hi - lo, S.pl.colbits, g, lo, tl->c,
+                                 tl->val_type, out, &kept));
+        tl->kept += kept;
+        return LNE_OK;
+    }
     LNE_TRY(reduce_to_csr(ctx, keys, vals, P, hi - lo, S.pl.colbits + S.pl.cbits, out));
     out->n_cols = g->n << S.pl.cbits;
     return LNE_OK;
@@ -282,7 +298,8 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
 // and keeping the entries whose row falls inside it.
 template <class Sink>
 static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
-                                lne_stats *st, Sink &&sink, bool channels = false) {
+                                lne_stats *st, Sink &&sink, bool channels = false,
+                                TruncLogFuse *tl = nullptr) {
     Sampler S;
     LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
     // one pass shared by trials with different s: the length r is kept in
@@ -306,11 +323,15 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
     if (total == 0 || range_bytes(total) <= budget) {
         lne_csr blk;
         std::memset(&blk, 0, sizeof(blk));
-        if (total == 0) {
+        if (total == 0 && tl) {
+            uint64_t kept = 0;
+            LNE_TRY(reduce_to_matrix(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits, g, 0, tl->c,
+                                     tl->val_type, &blk, &kept));
+        } else if (total == 0) {
             LNE_TRY(reduce_to_csr(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits + S.pl.cbits, &blk));
             blk.n_cols = g->n << S.pl.cbits;
         } else {
-            LNE_TRY(aggregate_range(ctx, g, S, 0, g->n, total, &blk));
+            LNE_TRY(aggregate_range(ctx, g, S, 0, g->n, total, &blk, tl));
         }
         if (st) st->nnz_counts = (uint64_t)blk.nnz;
         return sink(blk, (int64_t)0);
@@ -348,7 +369,7 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
         }
         lne_csr blk;
         std::memset(&blk, 0, sizeof(blk));
-        LNE_TRY(aggregate_range(ctx, g, S, rg.first, rg.second, entries, &blk));
+        LNE_TRY(aggregate_range(ctx, g, S, rg.first, rg.second, entries, &blk, tl));
         if (st) st->nnz_counts += (uint64_t)blk.nnz;
         LNE_TRY(sink(blk, rg.first));
     }
@@ -795,29 +816,35 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
     if (!X) return fail(ctx, LNE_EINVAL, "embed: X is NULL");
     if (st) std::memset(st, 0, sizeof(*st));
-    // each count block goes through trunc_log as soon as it exists, so only
-    // one block of counts is alive at a time
-    const int32_t vt = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    // the aggregation writes Eq. (1)'s matrix directly (no count CSR); a
+    // block keeps its dropped pairs as explicit zeros unless they are more
+    // than 1/32 of its entries, in which case it is compacted
+    TruncLogFuse tl;
+    tl.c = tl_const(g, p);
+    tl.val_type = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
     std::vector<lne_csr> mblocks;
-    auto sink = [&](lne_csr &blk, int64_t row_lo) -> lne_status {
-        lne_csr mb;
-        std::memset(&mb, 0, sizeof(mb));
-        lne_status r = trunc_log_csr(ctx, g, p, &blk, row_lo, vt, &mb);
-        lne_csr_free(ctx, &blk);
-        if (r == LNE_OK) mblocks.push_back(mb);
-        return r;
+    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
+        mblocks.push_back(blk);
+        return LNE_OK;
     };
     lne_csr M;
     std::memset(&M, 0, sizeof(M));
     LNE_TRY(validate_graph_device(ctx, g));
-    lne_status s = sparsify_impl(ctx, g, p, st, sink);
+    lne_status s = sparsify_impl(ctx, g, p, st, sink, false, &tl);
+    if (s == LNE_OK) {
+        int64_t stored = 0;
+        for (auto &b : mblocks) stored += b.nnz;
+        if ((uint64_t)stored - tl.kept > (uint64_t)stored / 32)
+            for (auto &b : mblocks)
+                if (s == LNE_OK) s = drop_zeros(ctx, &b);
+    }
     if (s == LNE_OK) s = concat_rows(ctx, mblocks, g->n, &M);
     for (auto &b : mblocks) lne_csr_free(ctx, &b);
     if (s != LNE_OK) {
         lne_csr_free(ctx, &M);
         return s;
     }
-    if (st) st->nnz_log = (uint64_t)M.nnz;
+    if (st) st->nnz_log = tl.kept;
     const int32_t out_t = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
     Buf X0(ctx);
     s = alloc(ctx, X0, dtype_size(out_t) * (size_t)g->n * p->d);

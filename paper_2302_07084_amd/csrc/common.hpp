@@ -162,6 +162,42 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1,
 lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                          int64_t n_items, int64_t n_rows, int colbits, lne_csr *out);
 
+// ---- Eq. (1) constants ------------------------------------------------------
+// x_ab = vol^2 / (2 b M) * (W_ab / 2^16) / (d_a d_b), kept iff x_ab > 1; the
+// keep decision compares W vol^2 with (2 b M 2^16) d_a d_b as exact 128-bit
+// products (vol < 2^32 and 2 b M < 2^40 are validated on the host).
+struct TLConst {
+    uint64_t vol2;     // vol^2
+    uint64_t K;        // 2 b M 2^16
+    double scale;      // vol^2 / (2 b M) / 2^16
+};
+inline TLConst tl_const(const lne_graph *g, const lne_params *p) {
+    TLConst c;
+    const uint64_t vol = (uint64_t)g->n_arcs;
+    c.vol2 = vol * vol;
+    c.K = (2ull * (uint64_t)p->b * p->M) << 16;
+    c.scale = ((double)vol * (double)vol) / (2.0 * (double)p->b * (double)p->M) / 65536.0;
+    return c;
+}
+__device__ __forceinline__ bool tl_keep(const TLConst &c, uint64_t W, uint64_t da, uint64_t db) {
+    const uint64_t dd = da * db;
+    const uint64_t lh = __umul64hi(W, c.vol2), ll = W * c.vol2;
+    const uint64_t rh = __umul64hi(c.K, dd), rl = c.K * dd;
+    return lh > rh || (lh == rh && ll > rl);
+}
+
+// Sorted (key, val) -> the truncated-log matrix directly (the count CSR is
+// never stored): every distinct pair's weights are summed by the lane that
+// holds its first item, its Eq. (1) entry is ln x if kept, else an explicit
+// zero.  Rows are [row_lo, row_lo + n_rows) of the graph.  *kept (host) = the
+// number of nonzero entries.  val_type LNE_F64 or LNE_F32.
+lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
+                            int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
+                            int64_t row_lo, const TLConst &c, int32_t val_type, lne_csr *out,
+                            uint64_t *kept);
+// Removes explicit zeros from an F32/F64 CSR (row block), in place of *m.
+lne_status drop_zeros(lne_ctx *ctx, lne_csr *m);
+
 // ---- trunc_log (k_trunclog.hip) ---------------------------------------------
 // counts covers the rows [row_lo, row_lo + counts->n_rows) of the graph.
 lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,

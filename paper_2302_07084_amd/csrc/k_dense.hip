@@ -379,16 +379,26 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
 
 // ---------------------------------------------------------------- Jacobi eig
 // Two-sided cyclic Jacobi with the round-robin (circle) ordering: every round
-// rotates kk/2 disjoint pairs at once, so a sweep is kk - 1 rounds.
+// rotates kk/2 disjoint pairs at once, so a sweep is kk - 1 rounds.  IN_LDS:
+// the working copy of A lives in the workgroup's LDS (k^2 doubles of dynamic
+// shared memory), the eigenvector accumulator in global memory.
+template <bool IN_LDS>
 __global__ void __launch_bounds__(kSolveThreads)
-k_sym_eig(double *__restrict__ A, int k, double *__restrict__ Vw, double *__restrict__ V,
+k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__restrict__ V,
           double *__restrict__ lam) {
+    extern __shared__ double lds_a[];
     {
         const int64_t b = blockIdx.x;
-        A += b * k * k;
+        Ag += b * k * k;
         Vw += b * k * k;
         V += b * k * k;
         lam += b * k;
+    }
+    double *__restrict__ A = Ag;
+    if constexpr (IN_LDS) {
+        for (int64_t i = threadIdx.x; i < (int64_t)k * k; i += kSolveThreads) lds_a[i] = Ag[i];
+        A = lds_a;
+        __syncthreads();
     }
     __shared__ double cs[160], sn[160];
     __shared__ int pp[160], qq[160];
@@ -639,9 +649,31 @@ lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, i
     if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above 288", k);
     Buf vw(ctx);
     LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)nb * k * k));
-    {
+    // the LDS variant when k^2 doubles fit next to the kernel's static arrays
+    static int lds_limit = -1;
+    if (lds_limit < 0) {
+        int dev = 0, bytes = 0;
+        lds_limit = 0;
+        int base = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&base, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            hipDeviceGetAttribute(&bytes, hipDeviceAttributeSharedMemPerBlockOptin, dev) ==
+                hipSuccess &&
+            (bytes = bytes > base ? bytes : base) > 8192 &&
+            hipFuncSetAttribute((const void *)k_sym_eig<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes - 8192) ==
+                hipSuccess)
+            lds_limit = bytes - 8192;
+        (void)hipGetLastError();
+    }
+    const size_t need = sizeof(double) * (size_t)k * k;
+    if (need <= (size_t)lds_limit) {
         Launch L(ctx, "sym_eig");
-        k_sym_eig<<<nb, kSolveThreads, 0, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
+        k_sym_eig<true><<<nb, kSolveThreads, need, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
+    } else {
+        Launch L(ctx, "sym_eig");
+        k_sym_eig<false><<<nb, kSolveThreads, 0, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
     }
     return check_launch(ctx, "sym_eig");
 }

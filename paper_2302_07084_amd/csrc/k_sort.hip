@@ -217,6 +217,84 @@ __global__ void __launch_bounds__(kT) k_reduce(const uint64_t *__restrict__ keys
     }
 }
 
+// Segmented sum fused with Eq. (1): a wave sums each run of equal keys with
+// a segmented scan; the lane holding a run's last item in the wave where the
+// run starts owns it (if the run goes on past the wave, that lane adds the
+// rest from memory) and writes the column and ln x (kept) or 0 (dropped).
+// Row offsets as in k_reduce.  Each distinct pair is written by exactly one
+// lane with an integer sum, so the result does not depend on the launch shape.
+template <class VT>
+__global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ keys,
+                                                  const uint32_t *__restrict__ vals, int64_t n,
+                                                  const uint64_t *__restrict__ head_off,
+                                                  int colbits, const int64_t *__restrict__ grp,
+                                                  int64_t row_lo, TLConst c,
+                                                  int32_t *__restrict__ col, VT *__restrict__ val,
+                                                  int64_t *__restrict__ rowptr,
+                                                  unsigned long long *__restrict__ kept) {
+    __shared__ uint32_t wh[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const uint64_t colmask = (1ull << colbits) - 1;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint64_t running = head_off[blockIdx.x];
+    uint32_t my_kept = 0;
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = base + it * kT + tid;
+        const bool valid = i < n;
+        uint64_t key = 0, prev = 0, v = 0;
+        bool head = false;
+        if (valid) {
+            key = keys[i];
+            v = vals[i];
+            prev = i > 0 ? keys[i - 1] : ~0ull;
+            head = (i == 0) || key != prev;
+        }
+        const uint64_t hm = __ballot(head);
+        if (lane == 0) wh[wv] = (uint32_t)__popcll(hm);
+        __syncthreads();
+        uint64_t before = running;
+        uint64_t itot = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wv) before += wh[w];
+            itot += wh[w];
+        }
+        __syncthreads();
+        running += itot;
+        const uint64_t u = before + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t ov = __shfl_up(v, off, 64);
+            const uint64_t ou = __shfl_up(u, off, 64);
+            if (lane >= off && ou == u) v += ov;
+        }
+        const uint64_t nu = __shfl_down(u, 1, 64);
+        if (!valid) continue;
+        if (head) {
+            const int64_t row = (int64_t)(key >> colbits);
+            const int64_t prow = i == 0 ? -1 : (int64_t)(prev >> colbits);
+            for (int64_t r = prow + 1; r <= row; ++r) rowptr[r] = (int64_t)u;
+        }
+        const bool started_here = (hm & (lt | (1ull << lane))) != 0;
+        const bool last_in_wave = lane == 63 || i + 1 >= n || nu != u;
+        if (!(started_here && last_in_wave)) continue;
+        uint64_t W = v;
+        if (lane == 63)
+            for (int64_t j = i + 1; j < n && keys[j] == key; ++j) W += vals[j];
+        const int32_t b = (int32_t)(key & colmask);
+        const int64_t row = (int64_t)(key >> colbits);
+        const uint64_t da = (uint64_t)(grp[row_lo + row + 1] - grp[row_lo + row]);
+        const uint64_t db = (uint64_t)(grp[b + 1] - grp[b]);
+        const bool k = tl_keep(c, W, da, db);
+        col[u] = b;
+        val[u] = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
+        my_kept += k ? 1u : 0u;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) my_kept += __shfl_xor(my_kept, off, 64);
+    if (lane == 0 && my_kept) atomicAdd(kept, (unsigned long long)my_kept);
+}
+
 __global__ void k_rowptr_tail(const uint64_t *__restrict__ keys, int64_t n_items,
                               int colbits, const uint64_t *__restrict__ nnz_p,
                               int64_t n_rows, int64_t *__restrict__ rowptr) {
@@ -303,6 +381,65 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
     out->col = (int32_t *)cc.detach();
     out->val = ww.detach();
     out->val_type = LNE_U64;
+    return LNE_OK;
+}
+
+lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
+                            int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
+                            int64_t row_lo, const TLConst &c, int32_t val_type, lne_csr *out,
+                            uint64_t *kept) {
+    if (val_type != LNE_F32 && val_type != LNE_F64)
+        return fail(ctx, LNE_EINVAL, "reduce_to_matrix: F32 or F64 values");
+    const int64_t ntiles = ceil_div(n_items > 0 ? n_items : 1, kTile);
+    Buf th(ctx), hoff(ctx), kc(ctx);
+    LNE_TRY(alloc(ctx, th, sizeof(uint32_t) * (size_t)ntiles));
+    LNE_TRY(alloc(ctx, hoff, sizeof(uint64_t) * (size_t)(ntiles + 1)));
+    LNE_TRY(alloc(ctx, kc, sizeof(unsigned long long)));
+    LNE_HIP(ctx, hipMemsetAsync(kc.p, 0, sizeof(unsigned long long), ctx->stream));
+    {
+        Launch L(ctx, "heads");
+        k_heads<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(keys, n_items, th.as<uint32_t>());
+    }
+    LNE_TRY(check_launch(ctx, "heads"));
+    LNE_TRY(scan_u32(ctx, th.as<uint32_t>(), hoff.as<uint64_t>(), ntiles));
+    uint64_t nnz = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(&nnz, hoff.as<uint64_t>() + ntiles, sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    Buf rp(ctx), cc(ctx), vv(ctx);
+    LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)(n_rows + 1)));
+    LNE_TRY(alloc(ctx, cc, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+    LNE_TRY(alloc(ctx, vv, dtype_size(val_type) * (size_t)(nnz > 0 ? nnz : 1)));
+    if (n_items > 0) {
+        Launch L(ctx, "reduce_trunc_log");
+        if (val_type == LNE_F64)
+            k_reduce_tl<double><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
+                keys, vals, n_items, hoff.as<uint64_t>(), colbits, g->row_ptr, row_lo, c,
+                cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(),
+                kc.as<unsigned long long>());
+        else
+            k_reduce_tl<float><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
+                keys, vals, n_items, hoff.as<uint64_t>(), colbits, g->row_ptr, row_lo, c,
+                cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), kc.as<unsigned long long>());
+    }
+    LNE_TRY(check_launch(ctx, "reduce_trunc_log"));
+    {
+        Launch L(ctx, "rowptr_tail");
+        k_rowptr_tail<<<grid_of(n_rows + 1, 256), 256, 0, ctx->stream>>>(
+            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>());
+    }
+    LNE_TRY(check_launch(ctx, "rowptr_tail"));
+    unsigned long long k = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(&k, kc.p, sizeof(k), hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *kept = (uint64_t)k;
+    out->n_rows = n_rows;
+    out->n_cols = g->n;
+    out->nnz = (int64_t)nnz;
+    out->row_ptr = (int64_t *)rp.detach();
+    out->col = (int32_t *)cc.detach();
+    out->val = vv.detach();
+    out->val_type = val_type;
     return LNE_OK;
 }
 

@@ -11,18 +11,9 @@ namespace lne {
 
 namespace {
 
-struct TLConst {
-    uint64_t vol2;     // vol^2
-    uint64_t K;        // 2 b M 2^16
-    double scale;      // vol^2 / (2 b M) / 2^16
-};
-
 __device__ __forceinline__ bool keep_entry(const TLConst &c, uint64_t W, uint64_t da,
                                            uint64_t db) {
-    const uint64_t dd = da * db;
-    const uint64_t lh = __umul64hi(W, c.vol2), ll = W * c.vol2;
-    const uint64_t rh = __umul64hi(c.K, dd), rl = c.K * dd;
-    return lh > rh || (lh == rh && ll > rl);
+    return tl_keep(c, W, da, db);
 }
 
 __global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t row_lo, int64_t n,
@@ -71,6 +62,43 @@ __global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t ro
             const double x = (double)w * c.scale / ((double)da * (double)db);
             ocol[o] = b;
             oval[o] = (VT)log(x);
+        }
+        pos += __popcll(mask);
+    }
+}
+
+// Nonzero count per row (one wave per row) and the compacting copy.
+template <class VT>
+__global__ void k_nz_count(int64_t n, const int64_t *__restrict__ rp, const VT *__restrict__ v,
+                           uint32_t *__restrict__ cnt) {
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    uint32_t c = 0;
+    for (int64_t i = rp[a] + lane; i < rp[a + 1]; i += 64) c += v[i] != (VT)0 ? 1u : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) cnt[a] = c;
+}
+
+template <class VT>
+__global__ void k_nz_fill(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                          const VT *__restrict__ v, const int64_t *__restrict__ orp,
+                          int32_t *__restrict__ ocol, VT *__restrict__ ov) {
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n) return;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int64_t pos = orp[a];
+    const int64_t beg = rp[a], end = rp[a + 1];
+    for (int64_t i0 = beg; i0 < end; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const bool k = i < end && v[i] != (VT)0;
+        const uint64_t mask = __ballot(k);
+        if (k) {
+            const int64_t o = pos + __popcll(mask & lt);
+            ocol[o] = col[i];
+            ov[o] = v[i];
         }
         pos += __popcll(mask);
     }
@@ -136,14 +164,64 @@ lne_status concat_rows(lne_ctx *ctx, std::vector<lne_csr> &blocks, int64_t n_row
     return LNE_OK;
 }
 
+lne_status drop_zeros(lne_ctx *ctx, lne_csr *m) {
+    if (m->val_type != LNE_F32 && m->val_type != LNE_F64)
+        return fail(ctx, LNE_EINVAL, "drop_zeros: F32 or F64 values expected");
+    const int64_t n = m->n_rows;
+    const bool f64 = m->val_type == LNE_F64;
+    Buf cnt(ctx), rp(ctx);
+    LNE_TRY(alloc(ctx, cnt, sizeof(uint32_t) * (size_t)(n + 1)));
+    LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)(n + 1)));
+    const unsigned grid = grid_of(n * 64, 256);
+    if (n > 0) {
+        Launch L(ctx, "drop_zeros");
+        if (f64)
+            k_nz_count<double><<<grid, 256, 0, ctx->stream>>>(n, m->row_ptr, (const double *)m->val,
+                                                              cnt.as<uint32_t>());
+        else
+            k_nz_count<float><<<grid, 256, 0, ctx->stream>>>(n, m->row_ptr, (const float *)m->val,
+                                                             cnt.as<uint32_t>());
+    }
+    LNE_TRY(check_launch(ctx, "drop_zeros"));
+    LNE_TRY(scan_u32(ctx, cnt.as<uint32_t>(), rp.as<uint64_t>(), n));
+    uint64_t nnz = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(&nnz, rp.as<int64_t>() + n, sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    Buf cc(ctx), vv(ctx);
+    LNE_TRY(alloc(ctx, cc, sizeof(int32_t) * (size_t)(nnz ? nnz : 1)));
+    LNE_TRY(alloc(ctx, vv, dtype_size(m->val_type) * (size_t)(nnz ? nnz : 1)));
+    if (n > 0) {
+        Launch L(ctx, "drop_zeros");
+        if (f64)
+            k_nz_fill<double><<<grid, 256, 0, ctx->stream>>>(n, m->row_ptr, m->col,
+                                                             (const double *)m->val,
+                                                             rp.as<int64_t>(), cc.as<int32_t>(),
+                                                             vv.as<double>());
+        else
+            k_nz_fill<float><<<grid, 256, 0, ctx->stream>>>(n, m->row_ptr, m->col,
+                                                            (const float *)m->val,
+                                                            rp.as<int64_t>(), cc.as<int32_t>(),
+                                                            vv.as<float>());
+    }
+    LNE_TRY(check_launch(ctx, "drop_zeros"));
+    const int32_t vt = m->val_type;
+    const int64_t ncols = m->n_cols;
+    lne_csr_free(ctx, m);
+    m->n_rows = n;
+    m->n_cols = ncols;
+    m->nnz = (int64_t)nnz;
+    m->row_ptr = (int64_t *)rp.detach();
+    m->col = (int32_t *)cc.detach();
+    m->val = vv.detach();
+    m->val_type = vt;
+    return LNE_OK;
+}
+
 lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                          const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out) {
     const int64_t n = counts->n_rows;
-    TLConst c;
-    const uint64_t vol = (uint64_t)g->n_arcs;
-    c.vol2 = vol * vol;
-    c.K = (2ull * (uint64_t)p->b * p->M) << 16;
-    c.scale = ((double)vol * (double)vol) / (2.0 * (double)p->b * (double)p->M) / 65536.0;
+    const TLConst c = tl_const(g, p);
 
     Buf kept(ctx), rp(ctx);
     LNE_TRY(alloc(ctx, kept, sizeof(uint32_t) * (size_t)(n + 1)));

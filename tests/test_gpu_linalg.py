@@ -204,3 +204,21 @@ def test_embed_tiny_matches_oracle(lne, ctx, tiny):
     assert stats["nnz_log"] == st["M"].nnz
     assert principal_angle(X, st["X"]) < 1e-8
     assert procrustes_err(X, st["X"]) < 1e-8
+
+
+def test_embed_keeps_few_dropped_pairs_as_explicit_zeros(lne, ctx):
+    """With few pairs dropped by Eq. (1)'s truncation the embedding path keeps
+    them as explicit zeros instead of compacting; the embedding and the kept
+    count still match the oracle."""
+    g, p = workload("tiny")
+    p = dict(p, M=3 * p["T"] * g.m, seed=11)
+    R, C, W, _, _ = oracle.count_csr(g, p)
+    keep, _ = oracle.trunc_log(g, p, R, C, W)
+    dropped = len(keep) - int(keep.sum())
+    assert 0 < dropped < len(keep) / 32
+    rp, col = to_dev(g)
+    ref = oracle.embed(g, p, return_stages=True)
+    X, stats = lne.embed(ctx, rp, col, p)
+    assert stats["nnz_log"] == ref["M"].nnz == int(keep.sum())
+    assert stats["nnz_counts"] == len(keep)
+    assert procrustes_err(X.cpu().numpy(), ref["X"]) < 1e-8
