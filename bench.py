@@ -160,7 +160,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.1f} ms/step")
 
     names = ["validate_graph", "row_up", "fill_edges", "sample_count", "sample_emit", "scan",
-             "radix_hist", "radix_scatter", "heads", "reduce", "reduce_trunc_log", "drop_zeros",
+             "radix_hist", "radix_scatter", "heads", "reduce", "degrees", "reduce_trunc_log", "drop_zeros",
              "rowptr_tail", "concat_rows", "trunc_log_count", "trunc_log_fill", "gaussian",
              "spmm", "gram", "gram_reduce", "chol_inv", "project", "sym_eig", "eig_weights",
              "w_to_bf16", "graph_spmm", "dense_scale", "axpby"]

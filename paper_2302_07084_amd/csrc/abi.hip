@@ -249,7 +249,8 @@ static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int6
 struct TruncLogFuse {
     TLConst c;
     int32_t val_type;
-    uint64_t kept = 0;     // nonzero entries over all blocks so far
+    const uint32_t *deg = nullptr;   // vertex degrees (vertex_degrees)
+    uint64_t kept = 0;               // nonzero entries over all blocks so far
 };
 
 // Aggregates the pair entries of rows [lo, hi) (already counted into S.wo)
@@ -280,8 +281,8 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
     const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
     if (tl) {
         uint64_t kept = 0;
-        LNE_TRY(reduce_to_matrix(ctx, keys, vals, P, hi - lo, S.pl.colbits, g, lo, tl->c,
-                                 tl->val_type, out, &kept));
+        LNE_TRY(reduce_to_matrix(ctx, keys, vals, P, hi - lo, S.pl.colbits, g, tl->deg, lo,
+                                 tl->c, tl->val_type, out, &kept));
         tl->kept += kept;
         return LNE_OK;
     }
@@ -325,8 +326,8 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
         std::memset(&blk, 0, sizeof(blk));
         if (total == 0 && tl) {
             uint64_t kept = 0;
-            LNE_TRY(reduce_to_matrix(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits, g, 0, tl->c,
-                                     tl->val_type, &blk, &kept));
+            LNE_TRY(reduce_to_matrix(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits, g, tl->deg, 0,
+                                     tl->c, tl->val_type, &blk, &kept));
         } else if (total == 0) {
             LNE_TRY(reduce_to_csr(ctx, nullptr, nullptr, 0, g->n, S.pl.colbits + S.pl.cbits, &blk));
             blk.n_cols = g->n << S.pl.cbits;
@@ -822,6 +823,10 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     TruncLogFuse tl;
     tl.c = tl_const(g, p);
     tl.val_type = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    Buf deg(ctx);
+    LNE_TRY(alloc(ctx, deg, sizeof(uint32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+    LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>()));
+    tl.deg = deg.as<uint32_t>();
     std::vector<lne_csr> mblocks;
     auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
         mblocks.push_back(blk);

@@ -189,12 +189,16 @@ __device__ __forceinline__ bool tl_keep(const TLConst &c, uint64_t W, uint64_t d
 // Sorted (key, val) -> the truncated-log matrix directly (the count CSR is
 // never stored): every distinct pair's weights are summed by the lane that
 // holds its first item, its Eq. (1) entry is ln x if kept, else an explicit
-// zero.  Rows are [row_lo, row_lo + n_rows) of the graph.  *kept (host) = the
+// zero.  Rows are [row_lo, row_lo + n_rows) of the graph, deg its degrees
+// (vertex_degrees).  *kept (host) = the
 // number of nonzero entries.  val_type LNE_F64 or LNE_F32.
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                             int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
-                            int64_t row_lo, const TLConst &c, int32_t val_type, lne_csr *out,
-                            uint64_t *kept);
+                            const uint32_t *deg, int64_t row_lo, const TLConst &c,
+                            int32_t val_type, lne_csr *out, uint64_t *kept);
+// deg[i] = degree of vertex i (uint32, n entries): the compact degree table
+// the fused reduction gathers from.
+lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg);
 // Removes explicit zeros from an F32/F64 CSR (row block), in place of *m.
 lne_status drop_zeros(lne_ctx *ctx, lne_csr *m);
 

@@ -76,17 +76,23 @@ __global__ void __launch_bounds__(kT) k_scatter(const uint64_t *__restrict__ kin
     __syncthreads();
 
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // all of this thread's items are loaded before the ranking starts, so
+    // the tile's loads are in flight together
+    uint64_t keys_r[kIt];
+    uint32_t vals_r[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = base + it * kT + tid;
+        keys_r[it] = i < n ? kin[i] : 0ull;
+        vals_r[it] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
     for (int it = 0; it < kIt; ++it) {
         const int64_t i = base + it * kT + tid;
         const bool valid = i < n;
-        uint64_t key = 0;
-        uint32_t val = 0;
-        uint32_t d = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-            d = (uint32_t)(key >> shift) & 255u;
-        }
+        const uint64_t key = keys_r[it];
+        const uint32_t val = vals_r[it];
+        const uint32_t d = valid ? (uint32_t)(key >> shift) & 255u : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -227,7 +233,7 @@ template <class VT>
 __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ keys,
                                                   const uint32_t *__restrict__ vals, int64_t n,
                                                   const uint64_t *__restrict__ head_off,
-                                                  int colbits, const int64_t *__restrict__ grp,
+                                                  int colbits, const uint32_t *__restrict__ deg,
                                                   int64_t row_lo, TLConst c,
                                                   int32_t *__restrict__ col, VT *__restrict__ val,
                                                   int64_t *__restrict__ rowptr,
@@ -283,8 +289,8 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
             for (int64_t j = i + 1; j < n && keys[j] == key; ++j) W += vals[j];
         const int32_t b = (int32_t)(key & colmask);
         const int64_t row = (int64_t)(key >> colbits);
-        const uint64_t da = (uint64_t)(grp[row_lo + row + 1] - grp[row_lo + row]);
-        const uint64_t db = (uint64_t)(grp[b + 1] - grp[b]);
+        const uint64_t da = deg[row_lo + row];
+        const uint64_t db = deg[b];
         const bool k = tl_keep(c, W, da, db);
         col[u] = b;
         val[u] = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
@@ -293,6 +299,11 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_kept += __shfl_xor(my_kept, off, 64);
     if (lane == 0 && my_kept) atomicAdd(kept, (unsigned long long)my_kept);
+}
+
+__global__ void k_degrees(const int64_t *__restrict__ rp, int64_t n, uint32_t *__restrict__ deg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) deg[i] = (uint32_t)(rp[i + 1] - rp[i]);
 }
 
 __global__ void k_rowptr_tail(const uint64_t *__restrict__ keys, int64_t n_items,
@@ -384,10 +395,18 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
     return LNE_OK;
 }
 
+lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg) {
+    if (g->n > 0) {
+        Launch L(ctx, "degrees");
+        k_degrees<<<grid_of(g->n, 256), 256, 0, ctx->stream>>>(g->row_ptr, g->n, deg);
+    }
+    return check_launch(ctx, "degrees");
+}
+
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                             int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
-                            int64_t row_lo, const TLConst &c, int32_t val_type, lne_csr *out,
-                            uint64_t *kept) {
+                            const uint32_t *deg, int64_t row_lo, const TLConst &c,
+                            int32_t val_type, lne_csr *out, uint64_t *kept) {
     if (val_type != LNE_F32 && val_type != LNE_F64)
         return fail(ctx, LNE_EINVAL, "reduce_to_matrix: F32 or F64 values");
     const int64_t ntiles = ceil_div(n_items > 0 ? n_items : 1, kTile);
@@ -414,12 +433,12 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
         Launch L(ctx, "reduce_trunc_log");
         if (val_type == LNE_F64)
             k_reduce_tl<double><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
-                keys, vals, n_items, hoff.as<uint64_t>(), colbits, g->row_ptr, row_lo, c,
+                keys, vals, n_items, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
                 cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(),
                 kc.as<unsigned long long>());
         else
             k_reduce_tl<float><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
-                keys, vals, n_items, hoff.as<uint64_t>(), colbits, g->row_ptr, row_lo, c,
+                keys, vals, n_items, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
                 cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), kc.as<unsigned long long>());
     }
     LNE_TRY(check_launch(ctx, "reduce_trunc_log"));
