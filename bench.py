@@ -159,7 +159,7 @@ def main():
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.1f} ms/step")
 
-    names = ["validate_graph", "row_up", "fill_edges", "sample_count", "sample_emit", "scan",
+    names = ["validate_graph", "row_up", "fill_edges", "sample_count", "fold_stats", "sample_emit", "scan",
              "radix_hist", "radix_scatter", "heads", "reduce", "degrees", "reduce_trunc_log", "drop_zeros",
              "rowptr_tail", "concat_rows", "trunc_log_count", "trunc_log_fill", "gaussian",
              "spmm", "gram", "gram_reduce", "chol_inv", "project", "sym_eig", "eig_weights",

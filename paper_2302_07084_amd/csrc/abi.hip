@@ -223,10 +223,9 @@ static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int6
     Buf scal(ctx);
     LNE_TRY(alloc(ctx, scal, 16));
     LNE_HIP(ctx, hipMemsetAsync(scal.p, 0, 16, ctx->stream));
-    unsigned long long *att_d = stats ? scal.as<unsigned long long>() : nullptr;
-    uint32_t *maxw_d = stats ? reinterpret_cast<uint32_t *>(scal.as<char>() + 8) : nullptr;
     LNE_TRY(launch_sample_count(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), S.m, lo, hi,
-                                S.wc.as<uint32_t>(), S.nw, att_d, maxw_d));
+                                S.wc.as<uint32_t>(), S.nw,
+                                stats ? scal.as<unsigned long long>() : nullptr));
     LNE_TRY(scan_u32(ctx, S.wc.as<uint32_t>(), S.wo.as<uint64_t>(), S.nw));
     uint64_t host[3] = {0, 0, 0};
     LNE_HIP(ctx, hipMemcpyAsync(&host[0], S.wo.as<uint64_t>() + S.nw, 8, hipMemcpyDeviceToHost,

@@ -137,12 +137,14 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
                                uint8_t *r);
 // Per-wave pair-entry counts (count pass) and pair emission (emit pass) for
-// the rows [row_lo, row_hi); keys are relative to row_lo.  attempted and
-// max_w may be NULL.
+// the rows [row_lo, row_hi); keys are relative to row_lo.  stats (may be
+// NULL, device, 2 x uint64): [0] = attempted sample slots, [1] = the largest
+// per-sample fixed-point weight of an edge with an accepted sample
+// (saturated at 2^32 - 1).
 lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                                int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,
-                               unsigned long long *attempted, uint32_t *max_w);
+                               unsigned long long *stats);
 lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                               const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                               int64_t row_hi, const uint64_t *wave_off, uint64_t *keys,

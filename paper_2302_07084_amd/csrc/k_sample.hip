@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kBlock)
 k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
                int64_t row_lo, int64_t row_hi, uint32_t *__restrict__ wave_cnt,
-               unsigned long long *__restrict__ attempted, uint32_t *__restrict__ max_w) {
+               unsigned long long *__restrict__ att_part, uint32_t *__restrict__ wmax_part) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t e = t / pl.chunks;
     const int64_t c = t - e * pl.chunks;
@@ -203,10 +203,57 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
         const uint64_t o = __shfl_xor(wmax, off, 64);
         wmax = o > wmax ? o : wmax;
     }
-    if ((threadIdx.x & 63) == 0) {
-        wave_cnt[t >> 6] = cnt;
-        if (attempted && att) atomicAdd(attempted, (unsigned long long)att);
-        if (max_w && wmax) atomicMax(max_w, wmax > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wmax);
+    if ((threadIdx.x & 63) == 0) wave_cnt[t >> 6] = cnt;
+    // per-block partial statistics (one writer per block, folded afterwards:
+    // a device-wide atomic per wave would serialise millions of updates)
+    if (att_part) {
+        __shared__ unsigned long long s_att[kBlock / 64];
+        __shared__ uint64_t s_max[kBlock / 64];
+        if ((threadIdx.x & 63) == 0) {
+            s_att[threadIdx.x >> 6] = att;
+            s_max[threadIdx.x >> 6] = wmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long a = 0;
+            uint64_t w = 0;
+            for (int i = 0; i < kBlock / 64; ++i) {
+                a += s_att[i];
+                w = s_max[i] > w ? s_max[i] : w;
+            }
+            att_part[blockIdx.x] = a;
+            wmax_part[blockIdx.x] = w > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)w;
+        }
+    }
+}
+
+// out[0] = sum of att_part, out[1] (as uint32) = max of wmax_part; one block.
+__global__ void __launch_bounds__(1024)
+k_fold_stats(const unsigned long long *__restrict__ att_part,
+             const uint32_t *__restrict__ wmax_part, int64_t n,
+             unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long sa[1024];
+    __shared__ uint32_t sm[1024];
+    unsigned long long a = 0;
+    uint32_t w = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        a += att_part[i];
+        w = wmax_part[i] > w ? wmax_part[i] : w;
+    }
+    sa[threadIdx.x] = a;
+    sm[threadIdx.x] = w;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sm[threadIdx.x] = sm[threadIdx.x + o] > sm[threadIdx.x] ? sm[threadIdx.x + o]
+                                                                    : sm[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sa[0];
+        out[1] = sm[0];
     }
 }
 
@@ -399,20 +446,33 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
 lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                                int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,
-                               unsigned long long *attempted, uint32_t *max_w) {
+                               unsigned long long *stats) {
     const int64_t threads = sample_threads(pl, m);
     if (threads / 64 != n_waves) return fail(ctx, LNE_EINVAL, "sampler wave count mismatch");
     const bool filter = !(row_lo <= 0 && row_hi >= g->n);
+    const int64_t nblocks = threads / kBlock;
+    Buf ap(ctx), wp(ctx);
+    if (stats) {
+        LNE_TRY(alloc(ctx, ap, sizeof(unsigned long long) * (size_t)(nblocks > 0 ? nblocks : 1)));
+        LNE_TRY(alloc(ctx, wp, sizeof(uint32_t) * (size_t)(nblocks > 0 ? nblocks : 1)));
+    }
+    unsigned long long *att_part = stats ? ap.as<unsigned long long>() : nullptr;
+    uint32_t *wmax_part = stats ? wp.as<uint32_t>() : nullptr;
     {
         Launch L(ctx, filter ? "sample_count_range" : "sample_count");
         if (filter)
-            k_sample_count<true><<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
-                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, attempted, max_w);
+            k_sample_count<true><<<(unsigned)nblocks, kBlock, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part);
         else
-            k_sample_count<false><<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
-                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, attempted, max_w);
+            k_sample_count<false><<<(unsigned)nblocks, kBlock, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part);
     }
-    return check_launch(ctx, "sample_count");
+    LNE_TRY(check_launch(ctx, "sample_count"));
+    if (stats) {
+        Launch L(ctx, "fold_stats");
+        k_fold_stats<<<1, 1024, 0, ctx->stream>>>(att_part, wmax_part, nblocks, stats);
+    }
+    return check_launch(ctx, "fold_stats");
 }
 
 lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
