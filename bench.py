@@ -88,10 +88,11 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--report", choices=["precision", "automl"], default=None,
+    ap.add_argument("--report", choices=["precision", "automl", "mfma"], default=None,
                     help="precision: the FP32 and BF16-MFMA paths against the FP64 path; "
                          "automl: trials/s and time to an equal score of the plain "
-                         "sequential search and the batched surrogate search")
+                         "sequential search and the batched surrogate search; mfma: "
+                         "achieved matrix-core rate of the dense rSVD steps")
     ap.add_argument("--automl-trials", type=int, default=64)
     ap.add_argument("--pretrain-trials", type=int, default=64,
                     help="surrogate pretraining trials per family graph (8 graphs)")
@@ -111,6 +112,9 @@ def main():
 
     if args.report == "precision":
         precision_report(args.workload if args.workload != "large" else "precision")
+        return
+    if args.report == "mfma":
+        mfma_report()
         return
     if args.report == "automl":
         automl_report(args.workload if args.workload != "large" else "batched",
@@ -299,6 +303,57 @@ def precision_report(name):
     out["results"]["f64"] = {"seconds": {"sparsify_trunc_log": ref["t_sparsify"],
                                          "rsvd": ref["t_rsvd"], "propagate": ref["t_propagate"]},
                              "nnz": ref["nnz"], "stats": ref["stats"]}
+    print(json.dumps(out), flush=True)
+
+
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6, "bf16": 2500.0}   # FP32 data runs on FP64 MFMA
+
+
+def mfma_report():
+    """Achieved matrix-core rate of the dense steps of the fast randomized SVD
+    (Gram Y^T Y and projection Y W on MFMA) at the shapes of the large
+    workload (n = 1e7, k' = 138, FP32 data on FP64 MFMA) and of the precision
+    workload (n = 1e6, k' = 266, FP32 and BF16), from HIP-event times of the
+    kernels inside eigSVD (one Gram, one k' x k' eigen-solve, one projection
+    U = Y V S^-1)."""
+    import torch
+
+    import paper_2302_07084_amd as lne
+
+    ctx = lne.Context()
+    out = {"report": "mfma", "peak_tflops": MFMA_PEAK_TFLOPS, "cases": []}
+    for dt, n, k in (("f32", 10_000_000, 138), ("f32", 1_000_000, 266), ("bf16", 1_000_000, 266),
+                     ("f64", 1_000_000, 266)):
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
+        ld = (k + 7) // 8 * 8
+        Y = torch.zeros((n, ld), dtype=tdt, device="cuda")
+        Y[:, :k] = torch.randn((n, k), dtype=torch.float32, device="cuda").to(tdt)
+        Yk = Y[:, :k]
+        lne.eigsvd(ctx, Yk)                  # warm-up
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        ctx.prof_reset()
+        reps = 3
+        for _ in range(reps):
+            lne.eigsvd(ctx, Yk)
+        torch.cuda.synchronize()
+        gms, gcnt = ctx.prof_get("gram")
+        pms, pcnt = ctx.prof_get("project")
+        ctx.prof_enable(False)
+        # useful flops: Gram n k (k + 1) (upper triangle), projection 2 n k k
+        gflop = n * k * (k + 1) * gcnt
+        pflop = 2 * n * k * k * pcnt
+        peak = MFMA_PEAK_TFLOPS[dt]
+        case = {"dtype": dt, "n": n, "k": k, "gram_launches": gcnt, "project_launches": pcnt,
+                "gram_tflops": gflop / (gms * 1e-3) / 1e12, "project_tflops": pflop / (pms * 1e-3) / 1e12,
+                "gram_avg_ms": gms / gcnt, "project_avg_ms": pms / pcnt}
+        case["gram_frac_peak"] = case["gram_tflops"] / peak
+        case["project_frac_peak"] = case["project_tflops"] / peak
+        out["cases"].append(case)
+        log(f"mfma {dt} n={n} k={k}: gram {case['gram_tflops']:.1f} TFLOP/s, "
+            f"project {case['project_tflops']:.1f} TFLOP/s (peak {peak})")
+        del Y, Yk
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
