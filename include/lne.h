@@ -177,6 +177,17 @@ lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *
 lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                         lne_csr *out, lne_stats *st);
 
+/* Rows [row_lo, row_hi) of the count matrix of lne_sparsify: every sample of
+ * every edge is drawn and walked, and only the pair entries whose row falls in
+ * the window are aggregated (the unit of work of the row-range passes, and of
+ * a row-partitioned sparsifier).  out: (row_hi - row_lo) x n count CSR, row 0
+ * = vertex row_lo.  Bit-identical to the same rows of lne_sparsify.
+ * Synchronises the stream.  st: attempted and accepted over all edges,
+ * nnz_counts of the window.  Errors: as lne_sparsify; EINVAL on an empty or
+ * out-of-range window. */
+lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            int64_t row_lo, int64_t row_hi, lne_csr *out, lne_stats *st);
+
 /* Truncated logarithm of Eq. (1) on the count matrix:
  *   x_ab = vol^2 / (2 b M) * (W_ab / 2^16) / (d_a d_b)
  * kept iff x_ab > 1 (decided exactly in 128-bit integers), value ln x_ab as

@@ -45,6 +45,9 @@ def lib():
         L.ora_count_rows.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64, i64,
                                      i32, i32, P, P, P, P, P, P]
         L.ora_count_rows.restype = i32
+        L.ora_count_rows_list.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, P, i64,
+                                          i32, P, P, P, P, P, P]
+        L.ora_count_rows_list.restype = i32
         L.ora_free.argtypes = [P]
         L.ora_trunc_log.argtypes = [i64, i64, P, P, P, P, u64, u64, u64, P, P]
         _LIB = L
@@ -167,6 +170,85 @@ def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
     return R, Cc, W, att.value, acc.value
 
 
+def edge_ids(g):
+    """Edge id of every arc: the arcs (u, v) with u < v numbered in CSR order;
+    arc (v, u) gets the id of its mirror.  Returns an int64 array of 2m."""
+    rp, col = _graph_arrays(g)
+    n = g.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    up = col > rows
+    ids = np.full(len(col), -1, np.int64)
+    ids[up] = np.arange(int(up.sum()), dtype=np.int64)
+    # the mirror of arc (u, v), u > v, sits in row v at column u; the keys
+    # row * n + col are ascending over the whole CSR
+    lo = np.flatnonzero(~up)
+    key = rows * n + col.astype(np.int64)
+    pos = np.searchsorted(key, col[lo].astype(np.int64) * n + rows[lo])
+    ids[lo] = ids[pos]
+    return ids
+
+
+def edge_ids_of(g, arcs):
+    """Edge ids of the arcs at CSR positions `arcs` (see edge_ids), from one
+    pass over the graph for the per-row counts of arcs (u, v) with u < v."""
+    rp, col = _graph_arrays(g)
+    n = g.n
+    arcs = np.asarray(arcs, np.int64)
+    rows_all = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    up = (col > rows_all).astype(np.int64)
+    del rows_all
+    cum = np.concatenate([[0], np.cumsum(up)])        # upper arcs before each position
+    first_upper = rp[1:] - (cum[rp[1:]] - cum[rp[:-1]])
+    upper_before = cum[rp[:-1]]
+    a_row = np.searchsorted(rp, arcs, side="right") - 1
+    a_col = col[arcs].astype(np.int64)
+    out = np.empty(len(arcs), np.int64)
+    fwd = a_col > a_row
+    out[fwd] = upper_before[a_row[fwd]] + (arcs[fwd] - first_upper[a_row[fwd]])
+    bwd = ~fwd
+    # mirror (x, b) of arc (b, x), x < b: its position inside row x
+    x, b = a_col[bwd], a_row[bwd]
+    pos = np.array([rp[xx] + np.searchsorted(col[rp[xx]:rp[xx + 1]], bb)
+                    for xx, bb in zip(x, b)], dtype=np.int64)
+    out[bwd] = upper_before[x] + (pos - first_upper[x])
+    return out
+
+
+def count_csr_edges(g, params, row_lo: int, row_hi: int, edges, nthreads: int | None = None):
+    """count_csr restricted to the samples of the listed edges (distinct edge
+    ids): the rows [row_lo, row_hi) of the count matrix are exact whenever the
+    list holds every edge whose samples can reach those rows."""
+    rp, col = _graph_arrays(g)
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    s = _s_array(params)
+    C, no_ds = _coin_args(params)
+    el = np.ascontiguousarray(np.unique(np.asarray(edges, np.int64)))
+    prp, pcol, pw = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    nnz, att, acc = ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().ora_count_rows_list(g.n, _p(rp), _p(col), params["T"], _p(s), int(params["M"]),
+                                   C, no_ds, int(params["seed"]), row_lo, row_hi, _p(el), len(el),
+                                   nthreads, ctypes.byref(prp), ctypes.byref(pcol),
+                                   ctypes.byref(pw), ctypes.byref(nnz), ctypes.byref(att),
+                                   ctypes.byref(acc))
+    if rc == -1:
+        raise MemoryError("oracle aggregation ran out of memory")
+    if rc == -2:
+        raise OverflowError("weight sum exceeds uint64")
+    if rc == -3:
+        raise ValueError("edge id out of range")
+    rows = row_hi - row_lo
+    k = nnz.value
+    R = np.ctypeslib.as_array(ctypes.cast(prp, ctypes.POINTER(ctypes.c_int64)), (rows + 1,)).copy()
+    Cc = (np.ctypeslib.as_array(ctypes.cast(pcol, ctypes.POINTER(ctypes.c_int32)), (k,)).copy()
+          if k else np.zeros(0, np.int32))
+    W = (np.ctypeslib.as_array(ctypes.cast(pw, ctypes.POINTER(ctypes.c_uint64)), (k,)).copy()
+         if k else np.zeros(0, np.uint64))
+    for ptr in (prp, pcol, pw):
+        lib().ora_free(ptr)
+    return R, Cc, W
+
+
 def trunc_log(g, params, rowptr, col, W, row_lo: int = 0):
     """Eq. (1): x = vol^2/(2bM) * (W/2^F) / (d_a d_b); keep x > 1 (exact
     integer test), value log x.  Returns (keep mask, values)."""
@@ -237,14 +319,16 @@ def netmf_sparse(g, params, nthreads=None):
 # --------------------------------------------------------------------------
 # Randomized SVD (section 4.2)
 # --------------------------------------------------------------------------
-def gaussian_omega(n: int, k: int, seed: int) -> np.ndarray:
-    """Omega = randn(n, k) (Algorithm "Fast Randomized SVD", first step).
-    Entry (i, c) is Box-Muller on the first two words of
-    Philox(counter = (i_lo, i_hi, c // 2, TAG_OMEGA)): with u1 = (z0+.5)/2^32,
-    u2 = (z1+.5)/2^32, radius sqrt(-2 ln u1), even c takes the cosine and odd c
-    the sine of 2 pi u2."""
+def gaussian_omega(n: int, k: int, seed: int, rows=None) -> np.ndarray:
+    """Omega = randn(n, k) (Algorithm "Fast Randomized SVD", first step), or
+    only its rows `rows`.  Entry (i, c) is Box-Muller on the first two words
+    of Philox(counter = (i_lo, i_hi, c // 2, TAG_OMEGA)): with u1 =
+    (z0+.5)/2^32, u2 = (z1+.5)/2^32, radius sqrt(-2 ln u1), even c takes the
+    cosine and odd c the sine of 2 pi u2."""
     half = (k + 1) // 2
-    i = np.repeat(np.arange(n, dtype=np.uint64), half)
+    ids = np.arange(n, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
+    n = len(ids)
+    i = np.repeat(ids, half)
     c = np.tile(np.arange(half, dtype=np.uint64), n)
     ctr = np.stack([(i & 0xFFFFFFFF).astype(np.uint32), (i >> 32).astype(np.uint32),
                     c.astype(np.uint32), np.full(n * half, TAG_OMEGA, np.uint32)], axis=1)

@@ -257,6 +257,7 @@ typedef struct { int32_t a, b; uint64_t w; } trip_t;
 typedef struct {
     const graph_t *g; const plan_t *pl; uint64_t seed; double C; int no_ds; int channels;
     const int32_t *eu, *ev;
+    const int64_t *elist;      /* NULL: edges e0..e1-1; else elist[e0..e1-1] */
     int64_t e0, e1, row_lo, row_hi;
     trip_t *buf; int64_t len, cap;
     uint64_t accepted, attempted;
@@ -280,7 +281,8 @@ static void *job_run(void *arg)
 {
     job_t *jb = arg;
     const graph_t *g = jb->g;
-    for (int64_t e = jb->e0; e < jb->e1 && !jb->fail; ++e) {
+    for (int64_t l = jb->e0; l < jb->e1 && !jb->fail; ++l) {
+        const int64_t e = jb->elist ? jb->elist[l] : l;
         int32_t u = jb->eu[e], v = jb->ev[e];
         int all; uint64_t tau, w;
         edge_coin(jb->C, jb->no_ds, g->rowptr[u + 1] - g->rowptr[u],
@@ -313,22 +315,13 @@ static int trip_cmp(const void *x, const void *y)
     return 0;
 }
 
-/*
- * Count CSR of the rows [row_lo, row_hi) from the samples of the edges
- * [e_begin, e_end) (e_end < 0: all edges): *o_rowptr has row_hi-row_lo+1
- * entries starting at 0, *o_col / *o_w have *o_nnz entries.  Buffers are
- * malloc'ed here and released with ora_free.  Also reports the number of
- * attempted and accepted samples of those edges.  With channels != 0 the
- * length r (drawn from s as always) is kept in the column: entry
- * (a, (b << 4) | (r - 1)).  Returns 0, or -1 on
- * allocation failure, -2 on a weight-sum overflow.
- */
-int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
-                   const double *s, uint64_t M, double C, int no_ds, uint64_t seed,
-                   int64_t row_lo, int64_t row_hi, int64_t e_begin, int64_t e_end, int channels,
-                   int nthreads,
-                   int64_t **o_rowptr, int32_t **o_col, uint64_t **o_w, int64_t *o_nnz,
-                   uint64_t *o_attempted, uint64_t *o_accepted)
+/* Shared body of ora_count_rows and ora_count_rows_list (below). */
+static int count_rows_impl(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
+                           const double *s, uint64_t M, double C, int no_ds, uint64_t seed,
+                           int64_t row_lo, int64_t row_hi, int64_t e_begin, int64_t e_end,
+                           const int64_t *elist, int64_t n_list, int channels, int nthreads,
+                           int64_t **o_rowptr, int32_t **o_col, uint64_t **o_w, int64_t *o_nnz,
+                           uint64_t *o_attempted, uint64_t *o_accepted)
 {
     graph_t g = {n, rowptr, col};
     int64_t m = edge_list(&g, NULL, NULL);
@@ -342,6 +335,12 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
     if (e_end < 0 || e_end > m) e_end = m;
     if (e_begin < 0) e_begin = 0;
     if (e_begin > e_end) e_begin = e_end;
+    if (elist) {
+        for (int64_t l = 0; l < n_list; ++l)
+            if (elist[l] < 0 || elist[l] >= m) { free(eu); free(ev); return -3; }
+        e_begin = 0;
+        e_end = n_list;
+    }
     job_t *jobs = calloc((size_t)nthreads, sizeof(job_t));
     pthread_t *th = calloc((size_t)nthreads, sizeof(pthread_t));
     for (int t = 0; t < nthreads; ++t) {
@@ -349,6 +348,7 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
         jb->g = &g; jb->pl = &pl; jb->seed = seed; jb->C = C; jb->no_ds = no_ds;
         jb->channels = channels;
         jb->eu = eu; jb->ev = ev;
+        jb->elist = elist;
         jb->e0 = e_begin + (e_end - e_begin) * t / nthreads;
         jb->e1 = e_begin + (e_end - e_begin) * (t + 1) / nthreads;
         jb->row_lo = row_lo; jb->row_hi = row_hi;
@@ -403,6 +403,42 @@ int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
     free(all);
     *o_rowptr = rp; *o_col = cc; *o_w = ww; *o_nnz = nnz;
     return rc;
+}
+
+/*
+ * Count CSR of the rows [row_lo, row_hi) from the samples of the edges
+ * [e_begin, e_end) (e_end < 0: all edges): *o_rowptr has row_hi-row_lo+1
+ * entries starting at 0, *o_col / *o_w have *o_nnz entries.  Buffers are
+ * malloc'ed here and released with ora_free.  Also reports the number of
+ * attempted and accepted samples of those edges.  With channels != 0 the
+ * length r (drawn from s as always) is kept in the column: entry
+ * (a, (b << 4) | (r - 1)).  Returns 0, or -1 on allocation failure, -2 on a
+ * weight-sum overflow.
+ */
+int ora_count_rows(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
+                   const double *s, uint64_t M, double C, int no_ds, uint64_t seed,
+                   int64_t row_lo, int64_t row_hi, int64_t e_begin, int64_t e_end, int channels,
+                   int nthreads,
+                   int64_t **o_rowptr, int32_t **o_col, uint64_t **o_w, int64_t *o_nnz,
+                   uint64_t *o_attempted, uint64_t *o_accepted)
+{
+    return count_rows_impl(n, rowptr, col, T, s, M, C, no_ds, seed, row_lo, row_hi, e_begin,
+                           e_end, NULL, 0, channels, nthreads, o_rowptr, o_col, o_w, o_nnz,
+                           o_attempted, o_accepted);
+}
+
+/* The same from the samples of the listed edges elist[0..n_list) only (edge
+ * ids as in the CSR order of u < v arcs; each listed once).  Returns -3 on an
+ * id outside [0, m). */
+int ora_count_rows_list(int64_t n, const int64_t *rowptr, const int32_t *col, int T,
+                        const double *s, uint64_t M, double C, int no_ds, uint64_t seed,
+                        int64_t row_lo, int64_t row_hi, const int64_t *elist, int64_t n_list,
+                        int nthreads, int64_t **o_rowptr, int32_t **o_col, uint64_t **o_w,
+                        int64_t *o_nnz, uint64_t *o_attempted, uint64_t *o_accepted)
+{
+    return count_rows_impl(n, rowptr, col, T, s, M, C, no_ds, seed, row_lo, row_hi, 0, -1,
+                           elist, n_list, 0, nthreads, o_rowptr, o_col, o_w, o_nnz,
+                           o_attempted, o_accepted);
 }
 
 void ora_free(void *p) { free(p); }

@@ -103,6 +103,7 @@ SIGNATURES = [
     ("lne_sparsify_channels", _I32, [_P, _P, _P, _P, _P]),
     ("lne_trial_matrix", _I32, [_P, _P, _P, _P, _P, _P]),
     ("lne_embed_batch", _I32, [_P, _P, _P, _P, _I32, _P, _P]),
+    ("lne_sparsify_rows", _I32, [_P, _P, _P, _I64, _I64, _P, _P]),
     ("lne_batch_create", _I32, [_P, _P, _P, _I32, _P, _P]),
     ("lne_batch_run", _I32, [_P, _P, _I32, _I32, _P, _P]),
     ("lne_batch_info", _I32, [_P, _P, _P, _P, _P]),
@@ -372,6 +373,17 @@ def sparsify(ctx: Context, rowptr, col, params: dict):
     st = Stats()
     ctx.check(ctx.L.lne_sparsify(ctx.h, ctypes.byref(g), ctypes.byref(p), ctypes.byref(out.s),
                                  ctypes.byref(st)), "sparsify")
+    return out, st.as_dict()
+
+
+def sparsify_rows(ctx: Context, rowptr, col, params: dict, row_lo: int, row_hi: int):
+    """Rows [row_lo, row_hi) of the count matrix (all samples walked)."""
+    g = graph_struct(rowptr, col)
+    p = make_params(params)
+    out = Csr(ctx)
+    st = Stats()
+    ctx.check(ctx.L.lne_sparsify_rows(ctx.h, ctypes.byref(g), ctypes.byref(p), row_lo, row_hi,
+                                      ctypes.byref(out.s), ctypes.byref(st)), "sparsify_rows")
     return out, st.as_dict()
 
 

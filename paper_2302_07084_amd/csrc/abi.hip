@@ -707,6 +707,44 @@ lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p, l
     return s;
 }
 
+lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            int64_t row_lo, int64_t row_hi, lne_csr *out, lne_stats *st) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    if (!out) return fail(ctx, LNE_EINVAL, "sparsify_rows: out is NULL");
+    if (row_lo < 0 || row_hi > g->n || row_lo >= row_hi)
+        return fail(ctx, LNE_EINVAL, "sparsify_rows: rows [%lld, %lld) outside [0, %lld)",
+                    (long long)row_lo, (long long)row_hi, (long long)g->n);
+    std::memset(out, 0, sizeof(*out));
+    if (st) std::memset(st, 0, sizeof(*st));
+    LNE_TRY(validate_graph_device(ctx, g));
+    Sampler S;
+    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
+    S.m = g->n_arcs / 2;
+    uint64_t total = 0, entries = 0;
+    if (S.m > 0 && S.pl.S > 0) {
+        LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m));
+        S.nw = sample_threads(S.pl, S.m) / 64;
+        LNE_TRY(alloc(ctx, S.wc, sizeof(uint32_t) * (size_t)S.nw));
+        LNE_TRY(alloc(ctx, S.wo, sizeof(uint64_t) * (size_t)(S.nw + 1)));
+        LNE_TRY(count_range(ctx, g, S, 0, g->n, &total, true));
+        LNE_TRY(count_range(ctx, g, S, row_lo, row_hi, &entries, false));
+    }
+    if (st) {
+        st->attempted = S.attempted;
+        st->accepted = S.accepted;
+    }
+    if (entries == 0) {
+        LNE_TRY(reduce_to_csr(ctx, nullptr, nullptr, 0, row_hi - row_lo, S.pl.colbits, out));
+        out->n_cols = g->n;
+    } else {
+        LNE_TRY(aggregate_range(ctx, g, S, row_lo, row_hi, entries, out));
+    }
+    if (st) st->nnz_counts = (uint64_t)out->nnz;
+    return LNE_OK;
+}
+
 lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                          const lne_csr *counts, lne_csr *out) {
     if (!ctx) return LNE_EINVAL;

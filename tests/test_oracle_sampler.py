@@ -320,3 +320,29 @@ def test_channel_mixture_is_unbiased_for_each_trial(pi):
         var = 2 * wmax * max(s / pi) * exp + 1e-9
         z = np.abs(mixed - exp) / np.sqrt(var)
         assert z.max() < 6, (s, z.max())
+
+
+def test_edge_subset_reproduces_row_windows():
+    """With walk lengths r <= 2 the rows of a window only receive samples of
+    edges incident to the window's closed neighbourhood: the oracle run on
+    those edges alone gives the window's rows exactly (the device's
+    full-size parity checks rely on this)."""
+    from synth import workload
+    g, p = workload("tiny")
+    p = dict(p, T=5, s=np.array([0.3, 0.7, 0.0, 0.0, 0.0]), M=40 * 5 * g.m, seed=9)
+    ids = oracle.edge_ids(g)
+    assert np.all(np.bincount(ids) == 2) and ids.max() == g.m - 1
+    for lo, hi in ((0, 3), (500, 507), (g.n - 4, g.n)):
+        nb = set(range(lo, hi))
+        for a in range(lo, hi):
+            nb.update(g.col[g.rowptr[a]:g.rowptr[a + 1]].tolist())
+        arcs = np.concatenate([np.arange(g.rowptr[b], g.rowptr[b + 1]) for b in sorted(nb)])
+        sel = oracle.edge_ids_of(g, arcs)
+        np.testing.assert_array_equal(sel, ids[arcs])
+        R0, C0, W0, _, _ = oracle.count_csr(g, p, row_lo=lo, row_hi=hi)
+        R1, C1, W1 = oracle.count_csr_edges(g, p, lo, hi, sel)
+        np.testing.assert_array_equal(R0, R1)
+        np.testing.assert_array_equal(C0, C1)
+        np.testing.assert_array_equal(W0, W1)
+    Om = oracle.gaussian_omega(g.n, 9, 5)
+    np.testing.assert_array_equal(oracle.gaussian_omega(g.n, 9, 5, rows=[3, 0, 999]), Om[[3, 0, 999]])
