@@ -269,10 +269,7 @@ int fill_table(lne_batch *b, const lne_trial *tr, int ntr) {
 
 // ---- launch-shape tuning -----------------------------------------------------
 std::string tune_key(const char *op, const lne_batch *b, int k) {
-    char buf[256];
-    snprintf(buf, sizeof(buf), "\"op\": \"%s\", \"n\": %lld, \"nnz\": %lld, \"k\": %d", op,
-             (long long)b->n, (long long)(op[0] == 's' ? b->ext.nnz : b->g.n_arcs), k);
-    return buf;
+    return shape_key(op, b->n, op[0] == 's' ? b->ext.nnz : b->g.n_arcs, k, LNE_F32);
 }
 
 lne_status tune(lne_batch *b) {

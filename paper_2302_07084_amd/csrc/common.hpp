@@ -94,6 +94,10 @@ lne_status pick_variant(lne_ctx *ctx, const std::string &key, int nv,
                         const std::function<lne_status(int)> &run, int *out);
 // The choice made for key so far, or dflt.
 int tuned_or(lne_ctx *ctx, const std::string &key, int dflt);
+// Key of an SpMM-like shape: the operation, rows, a size class of the
+// nonzero count (quarter octaves, so that matrices of one graph that differ a
+// little in nnz share their choice), width and element type.
+std::string shape_key(const char *op, int64_t n, int64_t nnz, int k, int dtype);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline unsigned grid_of(int64_t work, int block) {

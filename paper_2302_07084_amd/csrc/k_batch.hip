@@ -110,11 +110,12 @@ __global__ void k_norm_chan(const int64_t *__restrict__ rp, const int32_t *__res
 }
 
 // Y_t = M_t X_t for trials t = 0..ntr-1 with M_t generated on the fly from
-// the normalised channel CSR: for every (row a, column b) structure entry --
-// a run of channel entries with the same b, ascending r -- the head lane of
-// the run sums x = sum_r coef_t[r] w_r with coef_t[r] = s_t[r] / pi_r (FP64,
-// so the x > 1 decision is taken in FP64) and forms the truncated logarithm
-// ln x (FP32; 0 if x <= 1).  The nonzero values of a
+// the normalised channel CSR: every (row a, column b) structure entry is a
+// run of channel entries with the same b (ascending r); a segmented scan over
+// the wave sums x = sum_r coef_t[r] w_r with coef_t[r] = s_t[r] / pi_r (FP64,
+// so the x > 1 decision is taken in FP64; a run crossing a 64-entry chunk
+// carries its partial sum), and the lane holding the run's last entry forms
+// the truncated logarithm ln x (FP32; 0 if x <= 1).  The nonzero values of a
 // 64-entry chunk are compacted to the low lanes with one ds_permute, then the
 // wave gathers the X rows of those entries, U rows in flight per lane, lane l
 // holding columns 4l..4l+3 (k <= 256, k % 4 == 0, padding columns of X zero).
@@ -145,25 +146,46 @@ k_spmm_chan(const int64_t *__restrict__ rp, const int32_t *__restrict__ ecol,
     coef += 16 * t;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t beg = rp[row], end = rp[row + 1];
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);   // lanes 0..lane
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int32_t prev_b = -1;     // base column of the entry before the chunk
+    double carry = 0.0;      // partial sum of the run that reaches into the chunk
+    // the next chunk's structure is loaded while the current one is gathered
+    int32_t ec_next = beg + lane < end ? ecol[beg + lane] : -16;
+    double w_next = beg + lane < end ? wn[beg + lane] : 0.0;
     for (int64_t b0 = beg; b0 < end; b0 += 64) {
         const int64_t i = b0 + lane;
         const bool valid = i < end;
-        const int32_t ec = valid ? ecol[i] : -16;
-        int32_t pe = __shfl_up(ec, 1, 64);
-        if (lane == 0) pe = b0 > beg ? ecol[b0 - 1] : -16;
+        const int32_t ec = ec_next;
+        const double wv = w_next;
+        ec_next = i + 64 < end ? ecol[i + 64] : -16;
+        w_next = i + 64 < end ? wn[i + 64] : 0.0;
         const int32_t jb = ec >> 4;
-        const bool head = valid && (pe >> 4) != jb;
-        float v = 0.f;
-        if (head) {
-            double sum = 0.0;
-            for (int64_t j = i; j < end; ++j) {
-                const int32_t e = ecol[j];
-                if ((e >> 4) != jb) break;
-                sum += coef[e & 15] * wn[j];
-            }
-            v = sum > 1.0 ? logf((float)sum) : 0.f;
+        const double cw = valid ? coef[ec & 15] * wv : 0.0;
+        const int32_t up_b = __shfl_up(jb, 1, 64);
+        const bool head = valid && (lane == 0 ? prev_b : up_b) != jb;
+        const uint64_t hm = __ballot(head);
+        // segmented inclusive scan: a lane adds the partial of lane - off when
+        // no run starts in (lane - off, lane]; a run holds at most one entry
+        // per length (<= 16), so four doubling steps cover it
+        double sum = cw;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const double o = __shfl_up(sum, off, 64);
+            const int src = lane - off;
+            const uint64_t below = src < 0 ? 0ull : (src == 63 ? ~0ull : ((2ull << src) - 1));
+            if (src >= 0 && (hm & upto & ~below) == 0) sum += o;
         }
+        if (valid && (hm & upto) == 0) sum += carry;    // the run carried into the chunk
+        const int32_t dn_b = __shfl_down(jb, 1, 64);
+        const int32_t first_next = __shfl(ec_next, 0, 64) >> 4;
+        int32_t nb = dn_b;
+        if (lane == 63) nb = b0 + 64 < end ? first_next : -2;
+        const bool last = valid && (i + 1 >= end || nb != jb);
+        float v = 0.f;
+        if (last) v = sum > 1.0 ? logf((float)sum) : 0.f;
+        carry = __shfl(sum, 63, 64);
+        prev_b = __shfl(jb, 63, 64);
         const bool take = v != 0.f;
         const uint64_t mask = __ballot(take);
         const int cnt = __popcll(mask);

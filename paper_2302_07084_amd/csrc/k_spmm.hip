@@ -264,9 +264,7 @@ lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *
         return check_launch(ctx, "spmm");
     };
     int v = 0;
-    char key[160];
-    snprintf(key, sizeof(key), "\"op\": \"spmm\", \"n\": %lld, \"nnz\": %lld, \"k\": %d, \"dtype\": %d",
-             (long long)A->n_rows, (long long)A->nnz, k, dtype);
+    const std::string key = shape_key("spmm", A->n_rows, A->nnz, k, dtype);
     LNE_TRY(pick_variant(ctx, key, kSpmmVariants, run, &v));
     return run(v);
 }
@@ -309,9 +307,7 @@ lne_status gspmm_t(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t
         return check_launch(ctx, "graph_spmm");
     };
     int v = 0;
-    char key[160];
-    snprintf(key, sizeof(key), "\"op\": \"graph_spmm\", \"n\": %lld, \"nnz\": %lld, \"k\": %d, \"dtype\": %d",
-             (long long)g->n, (long long)g->n_arcs, k, dtype);
+    const std::string key = shape_key("graph_spmm", g->n, g->n_arcs, k, dtype);
     // the tuning runs write `out` and add to `acc`: tune only calls without an
     // accumulator, whose output is recomputed by the final run
     if (!acc) LNE_TRY(pick_variant(ctx, key, kSpmmVariants, run, &v));

@@ -2,6 +2,7 @@
 // the first time a shape is seen, keep the fastest per context, optionally in
 // a JSON-lines file shared between processes (LNE_TUNE_CACHE).
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -42,6 +43,14 @@ void file_store(const std::string &key, int v, const std::vector<float> &ms) {
 }
 
 }  // namespace
+
+std::string shape_key(const char *op, int64_t n, int64_t nnz, int k, int dtype) {
+    const int cls = nnz > 0 ? (int)std::floor(4.0 * std::log2((double)nnz)) : -1;
+    char buf[192];
+    snprintf(buf, sizeof(buf), "\"op\": \"%s\", \"n\": %lld, \"nnz_class\": %d, \"k\": %d, "
+             "\"dtype\": %d", op, (long long)n, cls, k, dtype);
+    return buf;
+}
 
 int tuned_or(lne_ctx *ctx, const std::string &key, int dflt) {
     auto it = ctx->tuned.find(key);

@@ -217,7 +217,7 @@ def test_tuner_cache_round_trip(lne, ctx, tmp_path, monkeypatch):
     assert {x["op"] for x in lines} == {"spmm_chan", "graph_spmm_batch"}
     sp = [x for x in lines if x["op"] == "spmm_chan"][0]
     assert sp["variant"] == i1["spmm_variant"] and len(sp["ms"]) == 6
-    assert sp["nnz"] == i1["channel_nnz"]
+    assert sp["nnz_class"] == math.floor(4 * math.log2(i1["channel_nnz"]))
     B2 = lne.Batch(ctx, rp, col, p, max_trials=2)
     assert B2.info()["spmm_variant"] == i1["spmm_variant"]
     assert len(path.read_text().splitlines()) == 2          # read, not re-tuned

@@ -136,8 +136,10 @@ def test_spmm_launch_shapes_give_identical_results(lne, ctx, tiny, tmp_path, mon
     for v in range(4):
         for k in (8, 136):
             path = tmp_path / f"tune_{v}_{k}.jsonl"
-            key = f'"op": "spmm", "n": {g.n}, "nnz": {M.nnz}, "k": {k}, "dtype": {code}'
-            gkey = f'"op": "graph_spmm", "n": {g.n}, "nnz": {g.n_arcs}, "k": {k}, "dtype": {code}'
+            key = (f'"op": "spmm", "n": {g.n}, "nnz_class": {math.floor(4 * math.log2(M.nnz))}, '
+                   f'"k": {k}, "dtype": {code}')
+            gkey = (f'"op": "graph_spmm", "n": {g.n}, "nnz_class": '
+                    f'{math.floor(4 * math.log2(g.n_arcs))}, "k": {k}, "dtype": {code}')
             path.write_text(f'{{{key}, "variant": {v}, "ms": []}}\n'
                             f'{{{gkey}, "variant": {v}, "ms": []}}\n')
             monkeypatch.setenv("LNE_TUNE_CACHE", str(path))
