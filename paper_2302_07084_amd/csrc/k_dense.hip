@@ -89,16 +89,37 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
 // ---------------------------------------------------------------- Gram BF16
 constexpr int kTS = 40;   // LDS row stride (bf16) of the transposed tile: 80 B
 
+constexpr int kBR = 64;            // rows per BF16 Gram tile (two MFMA k-steps)
+constexpr int kTS2 = kBR + 8;      // LDS row stride (bf16) of the transposed tile: 144 B
+
+// Loads 8 consecutive bf16 of row `row` from column c (zero beyond k or r_end).
+__device__ __forceinline__ v8bf load8(const __bf16 *__restrict__ Y, int64_t ld, int64_t row,
+                                      int64_t r_end, int c, int k, bool vec) {
+    v8bf v;
+    if (row < r_end && vec && c + 8 <= k) {
+        v = *reinterpret_cast<const v8bf *>(Y + row * ld + c);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            v[i] = (row < r_end && c + i < k) ? Y[row * ld + c + i] : (__bf16)0.0f;
+    }
+    return v;
+}
+
+// BF16 Gram: 64-row tiles read with 16-byte loads (consecutive lanes take
+// consecutive rows of one 8-column chunk, so the transposed LDS writes do not
+// conflict), two 16 x 16 x 32 MFMA steps per tile and output tile.  vec: rows
+// are 16-byte aligned (ld % 8 == 0, aligned base).
 template <int MAXT>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
             int64_t rows_per_wg, double *__restrict__ part, const int32_t *__restrict__ skip,
-            int64_t ys) {
+            int64_t ys, int vec) {
     Y += (int64_t)blockIdx.y * ys;
     part += (int64_t)blockIdx.y * gridDim.x * KP * KP;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ __attribute__((aligned(16))) __bf16 tt[288 * kTS];   // KP x kTS, transposed
+    __shared__ __attribute__((aligned(16))) __bf16 tt[288 * kTS2];   // KP x kTS2, transposed
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
     int TI[MAXT], TJ[MAXT];
@@ -112,19 +133,26 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
     const int64_t r_end = min(n, r_begin + rows_per_wg);
     const int kr = lane >> 4, kc = lane & 15;
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += 32) {
-        for (int idx = tid; idx < 32 * KP; idx += kGramThreads) {
-            const int rr = idx / KP, c = idx - rr * KP;
-            const int64_t row = r0 + rr;
-            tt[c * kTS + rr] = (row < r_end && c < k) ? Y[row * ld + c] : (__bf16)0.0f;
+    const int nch = KP / 8;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kBR) {
+        for (int idx = tid; idx < nch * kBR; idx += kGramThreads) {
+            const int rr = idx % kBR, c = (idx / kBR) * 8;
+            const v8bf v = load8(Y, ld, r0 + rr, r_end, c, k, vec != 0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) tt[(c + i) * kTS2 + rr] = v[i];
         }
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < MAXT; ++s) {
-            if (TI[s] >= 0) {
-                const v8bf a = *reinterpret_cast<const v8bf *>(tt + (16 * TI[s] + kc) * kTS + 8 * kr);
-                const v8bf b = *reinterpret_cast<const v8bf *>(tt + (16 * TJ[s] + kc) * kTS + 8 * kr);
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
+        for (int ks = 0; ks < kBR; ks += 32) {
+#pragma unroll
+            for (int s = 0; s < MAXT; ++s) {
+                if (TI[s] >= 0) {
+                    const v8bf a =
+                        *reinterpret_cast<const v8bf *>(tt + (16 * TI[s] + kc) * kTS2 + ks + 8 * kr);
+                    const v8bf b =
+                        *reinterpret_cast<const v8bf *>(tt + (16 * TJ[s] + kc) * kTS2 + ks + 8 * kr);
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -218,39 +246,45 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
     }
 }
 
+// BF16 projection: each lane reads its A operand (8 consecutive k of one
+// row) straight from memory with one 16-byte load; the 32-k slice of W^T is
+// staged in LDS per step.
 template <class OT, int MAXJ>
 __global__ void __launch_bounds__(kProjThreads)
 k_proj_bf16(const __bf16 *__restrict__ Y, int64_t ldy, int64_t n, int kin,
             const __bf16 *__restrict__ Wt, int ldw, int kout, OT *__restrict__ out,
-            int64_t ldo, const int32_t *__restrict__ skip, int64_t ys, int64_t os) {
+            int64_t ldo, const int32_t *__restrict__ skip, int64_t ys, int64_t os, int vec) {
     Y += (int64_t)blockIdx.y * ys;
     Wt += (int64_t)blockIdx.y * kout * ldw;
     out += (int64_t)blockIdx.y * os;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ __attribute__((aligned(16))) __bf16 As[kProjRows * kTS];
     __shared__ __attribute__((aligned(16))) __bf16 Ws[16 * MAXJ * kTS];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int ntout = (kout + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
     const int kr = lane >> 4, kc = lane & 15;
+    const int64_t arow = r0 + 16 * w + kc;
     v4f acc[MAXJ];
 #pragma unroll
     for (int J = 0; J < MAXJ; ++J) acc[J] = (v4f){0, 0, 0, 0};
     for (int k0 = 0; k0 < kin; k0 += 32) {
-        for (int idx = tid; idx < kProjRows * 32; idx += kProjThreads) {
-            const int rr = idx >> 5, cc = idx & 31;
-            const int64_t row = r0 + rr;
-            const int kcol = k0 + cc;
-            As[rr * kTS + cc] = (row < n && kcol < kin) ? Y[row * ldy + kcol] : (__bf16)0.0f;
-        }
-        for (int idx = tid; idx < 16 * MAXJ * 32; idx += kProjThreads) {
-            const int c = idx >> 5, cc = idx & 31;
-            const int kcol = k0 + cc;
-            Ws[c * kTS + cc] = (c < kout && kcol < kin) ? Wt[(int64_t)c * ldw + kcol] : (__bf16)0.0f;
+        const v8bf a = load8(Y, ldy, arow, n, k0 + 8 * kr, kin, vec != 0);
+        for (int idx = tid; idx < 16 * MAXJ * 4; idx += kProjThreads) {
+            const int c = idx >> 2, c8 = (idx & 3) * 8;
+            const int kcol = k0 + c8;
+            v8bf v;
+            if (c < kout && kcol + 8 <= kin) {
+                v = *reinterpret_cast<const v8bf *>(Wt + (int64_t)c * ldw + kcol);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    v[i] = (c < kout && kcol + i < kin) ? Wt[(int64_t)c * ldw + kcol + i]
+                                                        : (__bf16)0.0f;
+            }
+            *reinterpret_cast<v8bf *>(Ws + c * kTS + c8) = v;
         }
         __syncthreads();
-        const v8bf a = *reinterpret_cast<const v8bf *>(As + (16 * w + kc) * kTS + 8 * kr);
 #pragma unroll
         for (int J = 0; J < MAXJ; ++J) {
             if (J < ntout) {
@@ -538,12 +572,13 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     Buf part(ctx);
     LNE_TRY(alloc(ctx, part, sizeof(double) * (size_t)nb * nwg * KP * KP));
     const dim3 grid((unsigned)nwg, (unsigned)nb);
+    const int vec = ((uintptr_t)Y % 16 == 0 && ld % 8 == 0 && ys % 8 == 0) ? 1 : 0;
     {
         Launch L(ctx, "gram");
         if (dtype == LNE_BF16) {
 #define LNE_GB(MT)                                                                       \
     k_gram_bf16<MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
-        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys)
+        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys, vec)
             if (per_wave <= 1) LNE_GB(1);
             else if (per_wave <= 6) LNE_GB(6);
             else if (per_wave <= 12) LNE_GB(12);
@@ -586,6 +621,7 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
     const int ntout = (kout + 15) / 16;
     if (y_t == LNE_BF16) {
         const int ldw = ((kin + 31) / 32) * 32;
+        const int vec = ((uintptr_t)Y % 16 == 0 && ldy % 8 == 0 && ys % 8 == 0) ? 1 : 0;
         Buf wt(ctx);
         LNE_TRY(alloc(ctx, wt, sizeof(__bf16) * (size_t)nb * kout * ldw));
         {
@@ -597,7 +633,8 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
         Launch L(ctx, "project");
 #define LNE_PB(OT, MJ)                                                                     \
     k_proj_bf16<OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                           \
-        (const __bf16 *)Y, ldy, n, kin, wt.as<__bf16>(), ldw, kout, (OT *)out, ldo, skip, ys, os)
+        (const __bf16 *)Y, ldy, n, kin, wt.as<__bf16>(), ldw, kout, (OT *)out, ldo, skip, ys, os, \
+        vec)
         if (out_t == LNE_BF16) {
             if (ntout <= 3) LNE_PB(__bf16, 3);
             else if (ntout <= 9) LNE_PB(__bf16, 9);
