@@ -188,33 +188,54 @@ constexpr int kProjThreads = 512;
 constexpr int kKC = 16;           // K chunk (FP64 path)
 constexpr int kAS = kKC + 1;      // padded LDS row stride (doubles)
 
+// Four consecutive elements of row `row` from column c as doubles (zero
+// beyond k or n); vec: 16-byte (FP32) or 2 x 16-byte (FP64) loads allowed.
+template <class YT>
+__device__ __forceinline__ void load4d(const YT *__restrict__ Y, int64_t ld, int64_t row,
+                                       int64_t n, int c, int k, bool vec, double out[4]) {
+    if (row < n && vec && c + 4 <= k) {
+        if constexpr (sizeof(YT) == 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(Y + row * ld + c);
+            out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+        } else {
+            const double2 v0 = *reinterpret_cast<const double2 *>(Y + row * ld + c);
+            const double2 v1 = *reinterpret_cast<const double2 *>(Y + row * ld + c + 2);
+            out[0] = v0.x; out[1] = v0.y; out[2] = v1.x; out[3] = v1.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            out[i] = (row < n && c + i < k) ? to_d(Y[row * ld + c + i]) : 0.0;
+    }
+}
+
+// FP64-MFMA projection out = Y W.  Each 16 x 16 x 4 step sums over four k;
+// lane group kr takes k = k0 + 4 kr + t in step t, so a lane's A operands for
+// a 16-wide k chunk are four consecutive elements of its row, read with one
+// vector load; the chunk of W is staged in LDS.
 template <class YT, class OT, int MAXJ>
 __global__ void __launch_bounds__(kProjThreads)
 k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
          const double *__restrict__ W, int kout, OT *__restrict__ out, int64_t ldo,
-         const int32_t *__restrict__ skip, int64_t ys, int64_t ws, int64_t os) {
+         const int32_t *__restrict__ skip, int64_t ys, int64_t ws, int64_t os, int vec) {
     Y += (int64_t)blockIdx.y * ys;
     W += (int64_t)blockIdx.y * ws;
     out += (int64_t)blockIdx.y * os;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ double As[kProjRows * kAS];
     __shared__ double Ws[kKC * 16 * MAXJ];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int KPo = 16 * MAXJ;
     const int ntout = (kout + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
     const int kr = lane >> 4, kc = lane & 15;
+    const int64_t arow = r0 + 16 * w + kc;
     v4d acc[MAXJ];
 #pragma unroll
     for (int J = 0; J < MAXJ; ++J) acc[J] = (v4d){0, 0, 0, 0};
     for (int k0 = 0; k0 < kin; k0 += kKC) {
-        for (int idx = tid; idx < kProjRows * kKC; idx += kProjThreads) {
-            const int rr = idx / kKC, cc = idx - rr * kKC;
-            const int64_t row = r0 + rr;
-            const int kcol = k0 + cc;
-            As[rr * kAS + cc] = (row < n && kcol < kin) ? to_d(Y[row * ldy + kcol]) : 0.0;
-        }
+        double a4[4];
+        load4d<YT>(Y, ldy, arow, n, k0 + 4 * kr, kin, vec != 0, a4);
         for (int idx = tid; idx < kKC * KPo; idx += kProjThreads) {
             const int rr = idx / KPo, c = idx - rr * KPo;
             const int krow = k0 + rr;
@@ -222,13 +243,12 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kKC; kk += 4) {
-            const double a = As[(16 * w + kc) * kAS + kk + kr];
+        for (int t = 0; t < 4; ++t) {
 #pragma unroll
             for (int J = 0; J < MAXJ; ++J) {
                 if (J < ntout) {
-                    const double b = Ws[(kk + kr) * KPo + 16 * J + kc];
-                    acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[J], 0, 0, 0);
+                    const double b = Ws[(4 * kr + t) * KPo + 16 * J + kc];
+                    acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[t], b, acc[J], 0, 0, 0);
                 }
             }
         }
@@ -648,10 +668,12 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
         }
 #undef LNE_PB
     } else {
+        const int vmul = y_t == LNE_F64 ? 2 : 4;
+        const int vec = ((uintptr_t)Y % 16 == 0 && ldy % vmul == 0 && ys % vmul == 0) ? 1 : 0;
         Launch L(ctx, "project");
 #define LNE_P64(YT, OT, MJ)                                                                \
     k_proj64<YT, OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                          \
-        (const YT *)Y, ldy, n, kin, W, kout, (OT *)out, ldo, skip, ys, ws, os)
+        (const YT *)Y, ldy, n, kin, W, kout, (OT *)out, ldo, skip, ys, ws, os, vec)
 #define LNE_P64J(YT, OT)                                                                   \
     do {                                                                                   \
         if (ntout <= 3) LNE_P64(YT, OT, 3);                                                \
