@@ -8,13 +8,20 @@
 //
 // Both are gather-bound: every nonzero pulls one k-wide row of the dense
 // operand.  One wave owns one output row.  Its 64 lanes read the row's column
-// ids and values in coalesced batches of 64 and broadcast them lane to lane;
-// the wave is split into G = 64 / L lane groups of L lanes, each lane moving
-// 16 bytes per gathered row (float4 / double2 / 8 x bf16), so a 16-byte
-// aligned gathered row of up to L * 16 bytes is one vector load per lane and G
-// nonzeros are in flight per instruction, U such instructions per loop step.
-// Each group accumulates its nonzeros in row order (so U, the memory-level
-// parallelism, does not change the result); groups are combined by a
+// ids and values in coalesced batches of 64 and broadcast them lane to lane.
+// The k columns are split into a main part, k_main = a multiple of L * N
+// columns with L the largest power of two (<= 64) such that L * N <= k, and a
+// tail of the remaining k - k_main < L * N columns.  Each lane moves one
+// 16-byte vector (N = 4 floats, 2 doubles or 8 bf16) per gathered row: the
+// main part runs G = 64 / L nonzeros per load instruction on L lanes each,
+// the tail (at most 16 columns, 32 for BF16) runs 16 nonzeros per
+// instruction on 4 lanes each (8 nonzeros on 8 lanes for FP64), so no lane sits idle for most of a wide row (k = 138 floats would
+// otherwise take one 64-lane load per nonzero with 29 lanes idle).  Tails
+// wider than 4 vectors are handled by a second launch on the tail columns.
+// Every load is a whole 16-byte vector inside the row's ld span: columns from
+// k up to the next multiple of N are read and their sums discarded.
+// Each lane group accumulates its nonzeros in row order (so U, the number of
+// loads in flight, does not change the result); groups are combined by a
 // butterfly over lane offsets L, 2L, ... before the epilogue writes the row.
 // U is picked per matrix and width by timing (pick_variant).
 #include "common.hpp"
@@ -28,24 +35,14 @@ template <> struct Vec<double> { static constexpr int N = 2; using A = double; }
 template <> struct Vec<float> { static constexpr int N = 4; using A = float; };
 template <> struct Vec<__bf16> { static constexpr int N = 8; using A = float; };
 
-template <class T> __device__ __forceinline__ float to_f(T x) { return (float)x; }
-
+// one 16-byte vector of N elements, widened to the accumulation type
 template <class XT, class AT, int N>
-__device__ __forceinline__ void load_row(const XT *__restrict__ p, int c0, int k, AT v[N]) {
-    if (c0 + N <= k) {
-        if constexpr (sizeof(XT) * N == 16) {
-            const uint4 raw = *reinterpret_cast<const uint4 *>(p);
-            const XT *e = reinterpret_cast<const XT *>(&raw);
+__device__ __forceinline__ void load_vec(const XT *__restrict__ p, AT v[N]) {
+    static_assert(sizeof(XT) * N == 16, "16-byte vectors");
+    const uint4 raw = *reinterpret_cast<const uint4 *>(p);
+    const XT *e = reinterpret_cast<const XT *>(&raw);
 #pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = (AT)e[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = (AT)p[i];
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = (c0 + i < k) ? (AT)p[i] : (AT)0;
-    }
+    for (int i = 0; i < N; ++i) v[i] = (AT)e[i];
 }
 
 template <class OT, class AT, int N>
@@ -62,137 +59,179 @@ template <bool NT, class T> __device__ __forceinline__ T stream_load(const T *p)
     else return *p;
 }
 
-// L = lanes per gathered row (power of two, <= 64); U = loop steps in
-// flight; NT = non-temporal structure loads; VT value type; XT operand type;
-// OT output type.
-template <int L, int U, bool NT, class VT, class XT, class OT>
+// One batch of up to 64 nonzeros held one per lane (column cj, value vj):
+// lane group grp (L lanes) adds v_t X[j_t, c0 : c0 + N) for its nonzeros t =
+// grp, grp + G, ... in order.  `on` switches the lane's loads off (tail lanes
+// past k); every lane takes part in the shuffles.
+template <int L, int U, bool VALS, class XT, class AT>
+__device__ __forceinline__ void gather_batch(const XT *__restrict__ X, int64_t ldx, int c0,
+                                             bool on, int32_t cj, AT vj, int cnt, int grp,
+                                             AT acc[Vec<XT>::N]) {
+    constexpr int N = Vec<XT>::N;
+    constexpr int G = 64 / L;
+    for (int t0 = 0; t0 < cnt; t0 += U * G) {
+        int32_t j[U];
+        AT v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int t = t0 + grp + q * G;
+            j[q] = __shfl(cj, t & 63);
+            if constexpr (VALS) {
+                const AT vq = __shfl(vj, t & 63);
+                v[q] = t < cnt ? vq : (AT)0;
+            }
+        }
+        AT x[U][N];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (on && t0 + grp + q * G < cnt)
+                load_vec<XT, AT, N>(X + (int64_t)j[q] * ldx + c0, x[q]);
+            else
+#pragma unroll
+                for (int i = 0; i < N; ++i) x[q][i] = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if constexpr (VALS) acc[i] += v[q] * x[q][i];
+                else acc[i] += x[q][i];
+            }
+    }
+}
+
+template <int L, class AT, int N> __device__ __forceinline__ void fold_groups(AT acc[N]) {
+#pragma unroll
+    for (int off = L; off < 64; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+}
+
+// lanes per gathered tail row: 16 columns for FP32 and FP64, 32 for BF16
+__host__ __device__ constexpr int tail_lanes(int N) { return N == 2 ? 8 : 4; }
+
+// L = lanes per gathered main-part vector row (power of two, <= 64); TL = the
+// tail is present (tail_lanes(N) lanes per nonzero); U = loop steps in flight;
+// NT = non-temporal structure loads; VT value type; XT operand type; OT
+// output type.  Columns [0, k_main) are the main part, [k_main, k) the tail.
+template <int L, bool TL, int U, bool NT, class VT, class XT, class OT>
 __global__ void __launch_bounds__(256)
 k_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
        const VT *__restrict__ val, int64_t n_rows, const XT *__restrict__ X, int64_t ldx,
-       OT *__restrict__ Y, int64_t ldy, int k) {
+       OT *__restrict__ Y, int64_t ldy, int k_main, int k) {
     constexpr int N = Vec<XT>::N;
     using AT = typename Vec<XT>::A;
-    constexpr int G = 64 / L;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= n_rows) return;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, lc = lane % L;
+    constexpr int TLn = tail_lanes(N);
+    const int grpt = lane / TLn, lct = lane % TLn;
+    const int ct = k_main + lct * N;
     const int64_t beg = rp[row], end = rp[row + 1];
-    for (int cb = 0; cb < k; cb += L * N) {
+    for (int cb = 0;; cb += L * N) {
+        const bool main = cb < k_main;
+        const bool tail = TL && cb + L * N >= k_main;   // with the last main chunk
         const int c0 = cb + lc * N;
-        AT acc[N];
+        AT acc[N], acct[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] = 0;
+        for (int i = 0; i < N; ++i) acc[i] = acct[i] = 0;
         for (int64_t b0 = beg; b0 < end; b0 += 64) {
             const int64_t idx = b0 + lane;
             const int32_t cj = idx < end ? stream_load<NT>(col + idx) : 0;
             const AT vj = idx < end ? (AT)stream_load<NT>(val + idx) : (AT)0;
             const int cnt = (int)min((int64_t)64, end - b0);
-            // the trip count is the same for every lane, so every shuffle
-            // reads from lanes that are active
-            for (int t0 = 0; t0 < cnt; t0 += U * G) {
-                int32_t j[U];
-                AT v[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    // every lane shuffles (a shuffle under a lane-dependent
-                    // condition could read a lane that is switched off)
-                    const int t = t0 + grp + q * G;
-                    j[q] = __shfl(cj, t & 63);
-                    const AT vq = __shfl(vj, t & 63);
-                    v[q] = t < cnt ? vq : (AT)0;
-                }
-                AT x[U][N];
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    if (t0 + grp + q * G < cnt && c0 < k)
-                        load_row<XT, AT, N>(X + (int64_t)j[q] * ldx + c0, c0, k, x[q]);
-                    else
-#pragma unroll
-                        for (int i = 0; i < N; ++i) x[q][i] = 0;
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q)
-#pragma unroll
-                    for (int i = 0; i < N; ++i) acc[i] += v[q] * x[q][i];
-            }
+            if (main) gather_batch<L, U, true, XT, AT>(X, ldx, c0, true, cj, vj, cnt, grp, acc);
+            if (tail)
+                gather_batch<TLn, U, true, XT, AT>(X, ldx, ct, ct < k, cj, vj, cnt, grpt,
+                                                          acct);
         }
-#pragma unroll
-        for (int off = L; off < 64; off <<= 1)
-#pragma unroll
-            for (int i = 0; i < N; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
-        if (grp == 0 && c0 < k) store_row<OT, AT, N>(Y + row * ldy + c0, c0, k, acc);
+        if (main) {
+            fold_groups<L, AT, N>(acc);
+            if (grp == 0) store_row<OT, AT, N>(Y + row * ldy + c0, c0, k, acc);
+        }
+        if (tail) {
+            fold_groups<TLn, AT, N>(acct);
+            if (grpt == 0 && ct < k) store_row<OT, AT, N>(Y + row * ldy + ct, ct, k, acct);
+        }
+        if (cb + L * N >= k_main) break;
     }
 }
 
-template <int L, int U, bool NT, class T>
+// out = a z + b (inv acc) + c1 e1 + c2 e2 at columns [c0, c0 + N) of a row;
+// accum += cacc out when accum is given.
+template <class T, int N>
+__device__ __forceinline__ void graph_epilogue(int64_t o, int c0, int k, const T acc[N], T inv,
+                                               const T *__restrict__ Z, T *__restrict__ out, T a,
+                                               T b, const T *__restrict__ E1, T c1,
+                                               const T *__restrict__ E2, T c2,
+                                               T *__restrict__ accum, T cacc) {
+    T z[N], e1[N], e2[N];
+    load_vec<T, T, N>(Z + o, z);
+    if (E1) load_vec<T, T, N>(E1 + o, e1);
+    if (E2) load_vec<T, T, N>(E2 + o, e2);
+    T r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        r[i] = a * z[i] + b * (inv * acc[i]);
+        if (E1) r[i] += c1 * e1[i];
+        if (E2) r[i] += c2 * e2[i];
+    }
+    store_row<T, T, N>(out + o, c0, k, r);
+    if (accum) {
+        T s[N];
+        load_vec<T, T, N>(accum + o, s);
+#pragma unroll
+        for (int i = 0; i < N; ++i) s[i] += cacc * r[i];
+        store_row<T, T, N>(accum + o, c0, k, s);
+    }
+}
+
+template <int L, bool TL, int U, bool NT, class T>
 __global__ void __launch_bounds__(256)
 k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n_rows,
-             const T *__restrict__ Z, int64_t ld, int k, T *__restrict__ out, T a, T b,
-             const T *__restrict__ E1, T c1, const T *__restrict__ E2, T c2,
+             const T *__restrict__ Z, int64_t ld, int k_main, int k, T *__restrict__ out, T a,
+             T b, const T *__restrict__ E1, T c1, const T *__restrict__ E2, T c2,
              T *__restrict__ accum, T cacc) {
     constexpr int N = Vec<T>::N;
-    constexpr int G = 64 / L;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= n_rows) return;
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, lc = lane % L;
+    constexpr int TLn = tail_lanes(N);
+    const int grpt = lane / TLn, lct = lane % TLn;
+    const int ct = k_main + lct * N;
     const int64_t beg = rp[row], end = rp[row + 1];
     const T inv = end > beg ? (T)1 / (T)(end - beg) : (T)0;
-    for (int cb = 0; cb < k; cb += L * N) {
+    for (int cb = 0;; cb += L * N) {
+        const bool main = cb < k_main;
+        const bool tail = TL && cb + L * N >= k_main;
         const int c0 = cb + lc * N;
-        T acc[N];
+        T acc[N], acct[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] = 0;
+        for (int i = 0; i < N; ++i) acc[i] = acct[i] = 0;
         for (int64_t b0 = beg; b0 < end; b0 += 64) {
             const int64_t idx = b0 + lane;
             const int32_t cj = idx < end ? stream_load<NT>(col + idx) : 0;
             const int cnt = (int)min((int64_t)64, end - b0);
-            for (int t0 = 0; t0 < cnt; t0 += U * G) {
-                int32_t j[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) j[q] = __shfl(cj, (t0 + grp + q * G) & 63);
-                T x[U][N];
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    if (t0 + grp + q * G < cnt && c0 < k)
-                        load_row<T, T, N>(Z + (int64_t)j[q] * ld + c0, c0, k, x[q]);
-                    else
-#pragma unroll
-                        for (int i = 0; i < N; ++i) x[q][i] = 0;
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q)
-#pragma unroll
-                    for (int i = 0; i < N; ++i) acc[i] += x[q][i];
-            }
+            if (main) gather_batch<L, U, false, T, T>(Z, ld, c0, true, cj, (T)0, cnt, grp, acc);
+            if (tail)
+                gather_batch<TLn, U, false, T, T>(Z, ld, ct, ct < k, cj, (T)0, cnt, grpt,
+                                                         acct);
         }
-#pragma unroll
-        for (int off = L; off < 64; off <<= 1)
-#pragma unroll
-            for (int i = 0; i < N; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
-        if (grp == 0 && c0 < k) {
-            T z[N], e1[N], e2[N];
-            const int64_t o = row * ld + c0;
-            load_row<T, T, N>(Z + o, c0, k, z);
-            if (E1) load_row<T, T, N>(E1 + o, c0, k, e1);
-            if (E2) load_row<T, T, N>(E2 + o, c0, k, e2);
-            T r[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                r[i] = a * z[i] + b * (inv * acc[i]);
-                if (E1) r[i] += c1 * e1[i];
-                if (E2) r[i] += c2 * e2[i];
-            }
-            store_row<T, T, N>(out + o, c0, k, r);
-            if (accum) {
-                T s[N];
-                load_row<T, T, N>(accum + o, c0, k, s);
-#pragma unroll
-                for (int i = 0; i < N; ++i) s[i] += cacc * r[i];
-                store_row<T, T, N>(accum + o, c0, k, s);
-            }
+        if (main) {
+            fold_groups<L, T, N>(acc);
+            if (grp == 0)
+                graph_epilogue<T, N>(row * ld + c0, c0, k, acc, inv, Z, out, a, b, E1, c1, E2, c2,
+                                     accum, cacc);
         }
+        if (tail) {
+            fold_groups<TLn, T, N>(acct);
+            if (grpt == 0 && ct < k)
+                graph_epilogue<T, N>(row * ld + ct, ct, k, acct, inv, Z, out, a, b, E1, c1, E2,
+                                     c2, accum, cacc);
+        }
+        if (cb + L * N >= k_main) break;
     }
 }
 
@@ -219,22 +258,44 @@ __global__ void k_axpby(const T *__restrict__ x, const T *__restrict__ y, T *__r
 // launch shapes: unroll depth 4 or 8, structure loads normal or non-temporal
 constexpr int kSpmmVariants = 4;
 
-int lanes_for(int k, int N) {
-    const int need = (k + N - 1) / N;
+// Column split of a k-wide operand with N-element vectors: L lanes per
+// main-part vector row, main part [0, k_main), tail [k_main, k).
+struct ColSplit {
+    int L, k_main, tail;
+};
+
+ColSplit split_cols(int k, int N) {
+    if (k < N) return {1, 0, k};
     int L = 1;
-    while (L < need && L < 64) L <<= 1;
-    return L;
+    while (L < 64 && 2 * L * N <= k) L <<= 1;
+    const int k_main = k - k % (L * N);
+    return {L, k_main, k - k_main};
 }
 
-template <int L, class VT, class XT, class OT>
+// Runs fn(L-tag, tail-flag, k_main, k_launch) for each launch covering the
+// columns [0, k) (one launch unless the tail is wider than tail_lanes vectors,
+// whose columns then take launches of their own) with the operand pointers
+// advanced by col0 columns.
+template <class F> void for_each_launch(int k, int N, F &&fn) {
+    int col0 = 0;
+    while (col0 < k) {
+        const ColSplit s = split_cols(k - col0, N);
+        const bool fuse = s.tail > 0 && s.tail <= tail_lanes(N) * N;
+        const int kk = (fuse || s.tail == 0) ? k - col0 : s.k_main;
+        fn(col0, s.L, fuse, s.k_main, kk);
+        col0 += kk;
+    }
+}
+
+template <int L, bool TL, class VT, class XT, class OT>
 void spmm_launch(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y, int64_t ldy,
-                 int k, int variant) {
+                 int k_main, int k, int variant) {
     const unsigned grid = grid_of(A->n_rows * 64, 256);
     const VT *val = (const VT *)A->val;
     Launch Lc(ctx, "spmm");
-#define LNE_SV(UU, NTT)                                                                       \
-    k_spmm<L, UU, NTT, VT, XT, OT><<<grid, 256, 0, ctx->stream>>>(A->row_ptr, A->col, val,     \
-                                                                  A->n_rows, X, ldx, Y, ldy, k)
+#define LNE_SV(UU, NTT)                                                                    \
+    k_spmm<L, TL, UU, NTT, VT, XT, OT><<<grid, 256, 0, ctx->stream>>>(                    \
+        A->row_ptr, A->col, val, A->n_rows, X, ldx, Y, ldy, k_main, k)
     switch (variant) {
         case 1: LNE_SV(8, false); break;
         case 2: LNE_SV(4, true); break;
@@ -244,23 +305,29 @@ void spmm_launch(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y
 #undef LNE_SV
 }
 
+template <bool TL, class VT, class XT, class OT>
+void spmm_launch_l(int L, lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y,
+                   int64_t ldy, int k_main, int k, int v) {
+    switch (L) {
+#define LNE_SL(LL)                                                                          \
+    case LL: spmm_launch<LL, TL, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k_main, k, v); break;
+        LNE_SL(1) LNE_SL(2) LNE_SL(4) LNE_SL(8) LNE_SL(16) LNE_SL(32)
+        default: spmm_launch<64, TL, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k_main, k, v);
+#undef LNE_SL
+    }
+}
+
 template <class VT, class XT, class OT>
 lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *Y,
                   int64_t ldy, int k, int dtype) {
     const int N = Vec<XT>::N;
     const bool aligned = ((uintptr_t)X % 16 == 0) && (ldx % N == 0);
-    const int L = lanes_for(k, N);
     if (!aligned) return fail(ctx, LNE_EINVAL, "spmm: X must be 16-byte aligned with ld %% %d == 0", N);
     auto run = [&](int v) -> lne_status {
-        switch (L) {
-            case 1: spmm_launch<1, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-            case 2: spmm_launch<2, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-            case 4: spmm_launch<4, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-            case 8: spmm_launch<8, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-            case 16: spmm_launch<16, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-            case 32: spmm_launch<32, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-            default: spmm_launch<64, VT, XT, OT>(ctx, A, X, ldx, Y, ldy, k, v); break;
-        }
+        for_each_launch(k, N, [&](int c0, int L, bool tl, int k_main, int kk) {
+            if (tl) spmm_launch_l<true, VT, XT, OT>(L, ctx, A, X + c0, ldx, Y + c0, ldy, k_main, kk, v);
+            else spmm_launch_l<false, VT, XT, OT>(L, ctx, A, X + c0, ldx, Y + c0, ldy, k_main, kk, v);
+        });
         return check_launch(ctx, "spmm");
     };
     int v = 0;
@@ -269,16 +336,16 @@ lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *
     return run(v);
 }
 
-template <int L, class T>
-void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k,
-                  double a, double b, const T *E1, double c1, const T *E2, double c2, T *acc,
-                  double cacc, int variant) {
+template <int L, bool TL, class T>
+void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k_main,
+                  int k, double a, double b, const T *E1, double c1, const T *E2, double c2,
+                  T *acc, double cacc, int variant) {
     const unsigned grid = grid_of(g->n * 64, 256);
     Launch Lc(ctx, "graph_spmm");
-#define LNE_GS(UU, NTT)                                                                       \
-    k_graph_spmm<L, UU, NTT, T><<<grid, 256, 0, ctx->stream>>>(g->row_ptr, g->col, g->n, Z, ld, \
-                                                               k, out, (T)a, (T)b, E1, (T)c1,   \
-                                                               E2, (T)c2, acc, (T)cacc)
+#define LNE_GS(UU, NTT)                                                                    \
+    k_graph_spmm<L, TL, UU, NTT, T><<<grid, 256, 0, ctx->stream>>>(                       \
+        g->row_ptr, g->col, g->n, Z, ld, k_main, k, out, (T)a, (T)b, E1, (T)c1, E2, (T)c2,  \
+        acc, (T)cacc)
     switch (variant) {
         case 1: LNE_GS(8, false); break;
         case 2: LNE_GS(4, true); break;
@@ -288,22 +355,43 @@ void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t 
 #undef LNE_GS
 }
 
+template <bool TL, class T>
+void gspmm_launch_l(int L, lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld,
+                    int k_main, int k, double a, double b, const T *E1, double c1, const T *E2,
+                    double c2, T *acc, double cacc, int v) {
+    switch (L) {
+#define LNE_GL(LL)                                                                            \
+    case LL:                                                                                  \
+        gspmm_launch<LL, TL, T>(ctx, g, Z, out, ld, k_main, k, a, b, E1, c1, E2, c2, acc, cacc, \
+                                v);                                                           \
+        break;
+        LNE_GL(1) LNE_GL(2) LNE_GL(4) LNE_GL(8) LNE_GL(16) LNE_GL(32)
+        default:
+            gspmm_launch<64, TL, T>(ctx, g, Z, out, ld, k_main, k, a, b, E1, c1, E2, c2, acc,
+                                    cacc, v);
+#undef LNE_GL
+    }
+}
+
 template <class T>
 lne_status gspmm_t(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k,
                    double a, double b, const T *E1, double c1, const T *E2, double c2,
                    T *acc, double cacc, int dtype) {
     const int N = Vec<T>::N;
-    if ((uintptr_t)Z % 16 || (uintptr_t)out % 16 || ld % N)
-        return fail(ctx, LNE_EINVAL, "graph_spmm: operands must be 16-byte aligned");
-    const int L = lanes_for(k, N);
+    for (const T *q : {Z, (const T *)out, E1, E2, (const T *)acc})
+        if ((uintptr_t)q % 16)
+            return fail(ctx, LNE_EINVAL, "graph_spmm: operands must be 16-byte aligned");
+    if (ld % N) return fail(ctx, LNE_EINVAL, "graph_spmm: ld must be a multiple of %d", N);
+    auto at = [](auto *p, int c0) { return p ? p + c0 : p; };
     auto run = [&](int v) -> lne_status {
-        switch (L) {
-#define LNE_GC(LL)                                                                          \
-    case LL: gspmm_launch<LL, T>(ctx, g, Z, out, ld, k, a, b, E1, c1, E2, c2, acc, cacc, v); break;
-            LNE_GC(1) LNE_GC(2) LNE_GC(4) LNE_GC(8) LNE_GC(16) LNE_GC(32)
-            default: gspmm_launch<64, T>(ctx, g, Z, out, ld, k, a, b, E1, c1, E2, c2, acc, cacc, v);
-#undef LNE_GC
-        }
+        for_each_launch(k, N, [&](int c0, int L, bool tl, int k_main, int kk) {
+            if (tl)
+                gspmm_launch_l<true, T>(L, ctx, g, Z + c0, out + c0, ld, k_main, kk, a, b,
+                                        at(E1, c0), c1, at(E2, c0), c2, at(acc, c0), cacc, v);
+            else
+                gspmm_launch_l<false, T>(L, ctx, g, Z + c0, out + c0, ld, k_main, kk, a, b,
+                                         at(E1, c0), c1, at(E2, c0), c2, at(acc, c0), cacc, v);
+        });
         return check_launch(ctx, "graph_spmm");
     };
     int v = 0;

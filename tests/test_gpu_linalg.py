@@ -106,7 +106,9 @@ def test_spmm_vs_scipy(lne, ctx, tiny, prec):
     M = lne.trunc_log(ctx, rp, col, pp, counts)
     R, C, V = (x.cpu() for x in M.to_torch())
     A = sp.csr_matrix((V.double().numpy(), C.numpy(), R.numpy()), shape=(g.n, g.n))
-    for k in (1, 8, 42, 138):
+    # widths with no tail, a fused tail, k below one vector and tails that
+    # take a launch of their own
+    for k in (1, 3, 8, 42, 138, 200, 300):
         rng = np.random.default_rng(k)
         X = rng.standard_normal((g.n, k))
         tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
@@ -182,6 +184,22 @@ def test_propagate_filter_matches_oracle(lne, ctx, tiny, k, theta, mu):
     Xsp = lne.propagate(ctx, rp, col, pp, torch.from_numpy(X0).cuda()).cpu().numpy()
     ref = oracle.propagate(g, X0, k, theta, mu)
     assert np.max(np.abs(Xsp - ref)) <= 1e-12 * np.max(np.abs(X0)) * (2 * k + 1)
+
+
+@pytest.mark.parametrize("d", [3, 42, 138, 200])
+def test_propagate_filter_widths(lne, ctx, tiny, d):
+    """Operand widths with a fused tail, a tail of its own launch and one
+    below a single vector give the oracle's filter."""
+    import torch
+    g, p, rp, col, st = tiny
+    X0 = np.random.default_rng(d).standard_normal((g.n, d))
+    pp = dict(p, d=d, cheb_k=4, theta=0.7, mu=0.1, flags=lne.FLAG_NO_FINAL_EIGSVD)
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        X0d = torch.from_numpy(X0).to(tdt).cuda()
+        Xsp = lne.propagate(ctx, rp, col, dict(pp, precision=prec), X0d).double().cpu().numpy()
+        ref = oracle.propagate(g, X0d.double().cpu().numpy(), 4, 0.7, 0.1)
+        assert np.max(np.abs(Xsp - ref)) <= tol * np.max(np.abs(X0)) * 9
 
 
 def test_propagate_final_embedding(lne, ctx, tiny):
