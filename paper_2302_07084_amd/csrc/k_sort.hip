@@ -6,8 +6,10 @@
 //
 // Radix pass (8-bit digit): per-tile digit histograms (digit-major table),
 // one device-wide scan of the table, then a scatter in which every tile ranks
-// its items stably (wave ballots per digit bit + per-wave digit counts in LDS),
-// stages them in LDS in digit order and writes each digit run contiguously.
+// its items stably (each wave ranks a contiguous quarter of the tile with
+// ballots per digit bit and its own digit counters in LDS; a block-wide
+// prefix then orders the waves), stages them in LDS in digit order and writes
+// each digit run contiguously.
 #include "common.hpp"
 
 namespace lne {
@@ -35,28 +37,81 @@ __global__ void __launch_bounds__(kT) k_hist(const uint64_t *__restrict__ keys, 
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Tile of a scatter block.  Workgroups are dispatched to the 8 XCDs round
+// robin, so block b runs on XCD b % 8; giving each XCD a contiguous range of
+// tiles puts neighbouring tiles, whose runs of one digit meet inside a cache
+// line, in the same L2, where their partial lines merge before write-back.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
+    const int64_t q = ntiles >> 3, r = ntiles & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+constexpr int kWaveItems = kIt * 64;   // contiguous items ranked by one wave
+
 __global__ void __launch_bounds__(kT) k_scatter(const uint64_t *__restrict__ kin,
                                                 const uint32_t *__restrict__ vin, int64_t n,
                                                 int shift, int64_t ntiles,
-                                                const uint32_t *__restrict__ hist,
                                                 const uint64_t *__restrict__ offs,
                                                 uint64_t *__restrict__ kout,
                                                 uint32_t *__restrict__ vout) {
     __shared__ uint64_t skey[kTile];
     __shared__ uint32_t sval[kTile];
-    __shared__ uint32_t whist[kWaves][256];
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kWaves][256];   // per-wave digit counts, then offsets
     __shared__ uint32_t tpre[256];
     __shared__ uint64_t gbase[256];
     __shared__ uint32_t wtot[kWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
     const int64_t base = tile * kTile;
+    const int64_t wbase = base + (int64_t)wv * kWaveItems;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    gbase[tid] = offs[(int64_t)tid * ntiles + tile];
 
-    // exclusive prefix of this tile's digit counts
+    // all of this thread's items are loaded before the ranking starts, so
+    // the tile's loads are in flight together
+    uint64_t keys_r[kIt];
+    uint32_t vals_r[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t i = wbase + it * 64 + lane;
+        keys_r[it] = i < n ? kin[i] : 0ull;
+        vals_r[it] = i < n ? vin[i] : 0u;
+    }
+    __syncthreads();
+
+    // stable rank of each item among the wave's items of its digit: lanes
+    // with equal digits are found by one ballot per digit bit; the lowest
+    // such lane advances the wave's running count of that digit (one writer
+    // per digit and step, read back by the whole wave at the next step)
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t pos_r[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const bool valid = wbase + it * 64 + lane < n;
+        const uint32_t d = (uint32_t)(keys_r[it] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const uint32_t before = wcnt[wv][d];
+        pos_r[it] = before + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) wcnt[wv][d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // thread tid = digit: the tile's exclusive digit prefix and each wave's
+    // offset inside the digit's run
     {
-        const uint32_t c = hist[(int64_t)tid * ntiles + tile];
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) c += wcnt[w][tid];
         uint32_t inc = c;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -65,62 +120,27 @@ __global__ void __launch_bounds__(kT) k_scatter(const uint64_t *__restrict__ kin
         }
         if (lane == 63) wtot[wv] = inc;
         __syncthreads();
-        uint32_t before = 0;
-        for (int i = 0; i < wv; ++i) before += wtot[i];
-        tpre[tid] = before + inc - c;
-        gbase[tid] = offs[(int64_t)tid * ntiles + tile];
-        run[tid] = 0;
+        uint32_t run = inc - c;
+        for (int i = 0; i < wv; ++i) run += wtot[i];
+        tpre[tid] = run;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) whist[w][tid] = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t t = wcnt[w][tid];
+            wcnt[w][tid] = run;
+            run += t;
+        }
     }
     __syncthreads();
-
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // all of this thread's items are loaded before the ranking starts, so
-    // the tile's loads are in flight together
-    uint64_t keys_r[kIt];
-    uint32_t vals_r[kIt];
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
-        const int64_t i = base + it * kT + tid;
-        keys_r[it] = i < n ? kin[i] : 0ull;
-        vals_r[it] = i < n ? vin[i] : 0u;
+        if (wbase + it * 64 + lane < n) {
+            const uint32_t d = (uint32_t)(keys_r[it] >> shift) & 255u;
+            const uint32_t lp = wcnt[wv][d] + pos_r[it];
+            skey[lp] = keys_r[it];
+            sval[lp] = vals_r[it];
+        }
     }
-#pragma unroll
-    for (int it = 0; it < kIt; ++it) {
-        const int64_t i = base + it * kT + tid;
-        const bool valid = i < n;
-        const uint64_t key = keys_r[it];
-        const uint32_t val = vals_r[it];
-        const uint32_t d = valid ? (uint32_t)(key >> shift) & 255u : 0u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bal = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bal : ~bal;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) whist[wv][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int w = 0; w < wv; ++w) pos += whist[w][d];
-            const uint32_t lp = tpre[d] + pos;
-            skey[lp] = key;
-            sval[lp] = val;
-        }
-        __syncthreads();
-        {
-            uint32_t add = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                add += whist[w][tid];
-                whist[w][tid] = 0;
-            }
-            run[tid] += add;
-        }
-        __syncthreads();
-    }
+    __syncthreads();
 
     const int64_t cnt = min((int64_t)kTile, n - base);
     for (int64_t p = tid; p < cnt; p += kT) {
@@ -339,8 +359,8 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
         {
             Launch L(ctx, "radix_scatter");
             k_scatter<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
-                ks[cur], vs[cur], n, shift, ntiles, hist.as<uint32_t>(), offs.as<uint64_t>(),
-                ks[cur ^ 1], vs[cur ^ 1]);
+                ks[cur], vs[cur], n, shift, ntiles, offs.as<uint64_t>(), ks[cur ^ 1],
+                vs[cur ^ 1]);
         }
         LNE_TRY(check_launch(ctx, "radix_scatter"));
         cur ^= 1;
