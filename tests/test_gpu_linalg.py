@@ -242,3 +242,24 @@ def test_embed_keeps_few_dropped_pairs_as_explicit_zeros(lne, ctx):
     assert stats["nnz_log"] == ref["M"].nnz == int(keep.sum())
     assert stats["nnz_counts"] == len(keep)
     assert procrustes_err(X.cpu().numpy(), ref["X"]) < 1e-8
+
+
+def test_embed_hub_above_16_bit_degree(lne, ctx):
+    """A hub of degree above 65535 (degree products past 2^32 in Eq. (1)'s
+    keep test): the pairs and the kept count match the oracle exactly."""
+    from synth.graphs import Graph, _csr_from_pairs
+    n = 70001
+    leaves = np.arange(1, n, dtype=np.int64)
+    a = np.concatenate([np.zeros(n - 1, np.int64), leaves[:-1]])    # star + path
+    b = np.concatenate([leaves, leaves[1:]])
+    rowptr, col = _csr_from_pairs(a, b, n, "cpu")
+    g = Graph(n, rowptr, col, None, "star-path")
+    assert g.degrees().max() > 65535
+    _, p = workload("tiny")
+    p = dict(p, M=p["T"] * g.m, seed=5, d=8, oversample=4)
+    R, C, W, _, _ = oracle.count_csr(g, p)
+    keep, _ = oracle.trunc_log(g, p, R, C, W)
+    rp, cold = to_dev(g)
+    _, stats = lne.embed(ctx, rp, cold, p)
+    assert stats["nnz_counts"] == len(keep)
+    assert stats["nnz_log"] == int(keep.sum())
