@@ -21,29 +21,31 @@ constexpr int kIt = 16;              // items per thread
 constexpr int kTile = kT * kIt;      // items per tile
 constexpr int kWaves = kT / 64;
 
+// Tile of a histogram or scatter block.  Workgroups are dispatched to the 8
+// XCDs round robin, so block b runs on XCD b % 8; giving each XCD a
+// contiguous range of tiles puts neighbouring tiles, whose runs of one digit
+// (and whose entries of the digit-major count table) meet inside a cache
+// line, in the same L2, where their partial lines merge before write-back.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
+    const int64_t q = ntiles >> 3, r = ntiles & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
 __global__ void __launch_bounds__(kT) k_hist(const uint64_t *__restrict__ keys, int64_t n,
                                              int shift, int64_t ntiles,
                                              uint32_t *__restrict__ hist) {
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+    const int64_t base = tile * kTile;
 #pragma unroll 4
     for (int it = 0; it < kIt; ++it) {
         const int64_t i = base + it * kT + threadIdx.x;
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
-}
-
-// Tile of a scatter block.  Workgroups are dispatched to the 8 XCDs round
-// robin, so block b runs on XCD b % 8; giving each XCD a contiguous range of
-// tiles puts neighbouring tiles, whose runs of one digit meet inside a cache
-// line, in the same L2, where their partial lines merge before write-back.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
-    const int64_t q = ntiles >> 3, r = ntiles & 7, x = b & 7, i = b >> 3;
-    return x * q + min(x, r) + i;
+    hist[(int64_t)threadIdx.x * ntiles + tile] = cnt[threadIdx.x];
 }
 
 constexpr int kWaveItems = kIt * 64;   // contiguous items ranked by one wave
