@@ -428,7 +428,13 @@ static lne_status eig_of_gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_
     return sym_eig(ctx, G.as<double>(), k, V.as<double>(), lam.as<double>());
 }
 
-static int64_t round8(int64_t x) { return (x + 7) / 8 * 8; }
+// Row stride of the dense n x k blocks: whole 128-byte cache lines, so a
+// gathered row touches ceil(k e / 128) lines wherever it starts (a stride of
+// k rounded to 8 elements lets rows straddle one more line).
+static int64_t line_ld(int64_t k, size_t es) {
+    const int64_t q = (int64_t)(128 / es);
+    return (k + q - 1) / q * q;
+}
 
 static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U,
                             double *sigma, void *V, void *X0, lne_stats *st) {
@@ -436,8 +442,8 @@ static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p,
     const int32_t kp = p->d + p->oversample, d = p->d;
     const int32_t dt = p->precision;
     const int32_t out_t = dt == LNE_F64 ? LNE_F64 : LNE_F32;
-    const int64_t ld = round8(kp);
     const size_t es = dtype_size(dt);
+    const int64_t ld = line_ld(kp, es);
     Buf A(ctx), B(ctx);
     LNE_TRY(alloc(ctx, A, es * (size_t)n * ld));
     LNE_TRY(alloc(ctx, B, es * (size_t)n * ld));
@@ -496,7 +502,7 @@ static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_par
                                     ctx->stream));
         return LNE_OK;
     }
-    const int64_t ld = round8(d);
+    const int64_t ld = line_ld(d, es);
     const int K = p->cheb_k;
     const double th = p->theta, mu = p->mu;
     std::vector<double> c(K + 1);
