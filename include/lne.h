@@ -405,6 +405,23 @@ lne_status lne_score_micro_f1_batch(lne_ctx *ctx, const float *X, int32_t n_tria
                                     int64_t n_test, int32_t epochs, float lr, float l2,
                                     double *f1);
 
+/* Link-prediction evaluation (the protocol of the very-large-graph runs in
+ * the experiments section): each held-out edge i = (pos[2i], pos[2i+1]) =
+ * (u, v) is ranked against its K corrupted edges (u, neg[i K + j]) by the
+ * inner product of embedding rows, accumulated in FP64.  above[i] = number of
+ * corrupted edges scoring strictly above (u, v), ties[i] = number scoring
+ * equal; rank = 1 + above.  metrics (device, 4 doubles) = mean rank, mean
+ * reciprocal rank, HITS@hits_k (share of ranks <= hits_k) and AUC (mean of
+ * (K - above - ties / 2) / K).  X: device n x d rows (ldx, F32 or F64,
+ * 16-byte aligned); pos: device h x 2 int32; neg: device h x K int32; above,
+ * ties: device h uint32 each, or NULL.  Vertex ids outside [0, n) are not
+ * read: EINVAL after the launch.  Synchronises the stream.
+ * Errors: EINVAL, ENOMEM. */
+lne_status lne_link_rank(lne_ctx *ctx, const void *X, int64_t n, int32_t d, int64_t ldx,
+                         int32_t dtype, const int32_t *pos, int64_t h, const int32_t *neg,
+                         int32_t K, int32_t hits_k, uint32_t *above, uint32_t *ties,
+                         double *metrics);
+
 #ifdef __cplusplus
 }
 #endif

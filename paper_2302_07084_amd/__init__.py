@@ -120,6 +120,8 @@ SIGNATURES = [
                                   ctypes.c_float, ctypes.c_float, _P]),
     ("lne_score_micro_f1_batch", _I32, [_P, _P, _I32, _I64, _I32, _P, _I32, _P, _I64, _P, _I64,
                                         _I32, ctypes.c_float, ctypes.c_float, _P]),
+    ("lne_link_rank", _I32, [_P, _P, _I64, _I32, _I64, _I32, _P, _I64, _P, _I32, _I32, _P, _P,
+                             _P]),
 ]
 
 _lib = None
@@ -645,3 +647,25 @@ def score_micro_f1(ctx: Context, X, labels, train, test, epochs=300, lr=0.05, l2
                                              tr.data_ptr(), len(tr), te.data_ptr(), len(te),
                                              epochs, lr, l2, f1), "score_micro_f1")
     return f1[0] if single else list(f1)
+
+
+def link_rank(ctx: Context, X, pos, neg, hits_k: int = 10):
+    """Link-prediction ranks of held-out edges pos (h x 2) against corrupted
+    edges (u, neg[i, j]) (neg: h x K) by embedding inner products.  Returns
+    (metrics dict: mean_rank, mrr, hits, auc; above; ties), the last two as
+    device uint32 tensors (per edge: corrupted edges scoring above / equal)."""
+    import torch
+    assert X.dim() == 2 and X.stride(1) == 1 and X.dtype in (torch.float32, torch.float64)
+    p = pos.to(torch.int32).contiguous()
+    q = neg.to(torch.int32).contiguous()
+    h, K = q.shape
+    assert p.shape == (h, 2)
+    above = torch.empty(h, dtype=torch.int32, device=X.device)
+    ties = torch.empty(h, dtype=torch.int32, device=X.device)
+    m = torch.empty(4, dtype=torch.float64, device=X.device)
+    ctx.check(ctx.L.lne_link_rank(ctx.h, X.data_ptr(), X.shape[0], X.shape[1], X.stride(0),
+                                  _code_of(X), p.data_ptr(), h, q.data_ptr(), K, hits_k,
+                                  above.data_ptr(), ties.data_ptr(), m.data_ptr()), "link_rank")
+    mv = m.cpu().tolist()
+    return (dict(mean_rank=mv[0], mrr=mv[1], hits=mv[2], auc=mv[3]), above, ties)
+

@@ -6,6 +6,7 @@ factorisation or propagation.  Every function is a pure function of its seed.
 """
 from .graphs import (Graph, sbm, chung_lu, workload, dirichlet_s,
                      trial_vectors, WORKLOADS)
+from .links import holdout_edges, corrupt_destinations
 
 __all__ = ["Graph", "sbm", "chung_lu", "workload", "dirichlet_s",
-           "trial_vectors", "WORKLOADS"]
+           "trial_vectors", "WORKLOADS", "holdout_edges", "corrupt_destinations"]
