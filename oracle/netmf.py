@@ -39,17 +39,17 @@ def lib():
         i64, u64, i32, f64 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_double
         L.ora_philox.argtypes = [u64, P, i64, P]
         L.ora_plan.argtypes = [i32, P, u64, i64, P, P, P]
-        L.ora_sample_slots.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64,
+        L.ora_sample_slots.argtypes = [i64, P, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64,
                                        P, P, P, P, P, P, P]
         L.ora_sample_slots.restype = i64
-        L.ora_count_rows.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64, i64,
-                                     i32, i32, P, P, P, P, P, P]
+        L.ora_count_rows.argtypes = [i64, P, P, P, i32, P, u64, f64, i32, u64, i64, i64, i64,
+                                     i64, i32, i32, P, P, P, P, P, P]
         L.ora_count_rows.restype = i32
-        L.ora_count_rows_list.argtypes = [i64, P, P, i32, P, u64, f64, i32, u64, i64, i64, P, i64,
-                                          i32, P, P, P, P, P, P]
+        L.ora_count_rows_list.argtypes = [i64, P, P, P, i32, P, u64, f64, i32, u64, i64, i64, P,
+                                          i64, i32, P, P, P, P, P, P]
         L.ora_count_rows_list.restype = i32
         L.ora_free.argtypes = [P]
-        L.ora_trunc_log.argtypes = [i64, i64, P, P, P, P, u64, u64, u64, P, P]
+        L.ora_trunc_log.argtypes = [i64, i64, P, P, P, P, u64, u64, u64, u64, P, P]
         _LIB = L
     return _LIB
 
@@ -61,6 +61,41 @@ def _p(a: np.ndarray):
 def _graph_arrays(g):
     return (np.ascontiguousarray(g.rowptr, dtype=np.int64),
             np.ascontiguousarray(g.col, dtype=np.int32))
+
+
+def _weights(g):
+    """Arc weights as a C pointer argument (None: unweighted graph) and the
+    array that keeps it alive."""
+    w = getattr(g, "weight", None)
+    if w is None:
+        return None, None
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    return _p(w), w
+
+
+def degrees(g) -> np.ndarray:
+    """d_u = sum_v A_uv (int64): the arc count on an unweighted graph."""
+    w = getattr(g, "weight", None)
+    if w is None:
+        return np.diff(np.asarray(g.rowptr, dtype=np.int64))
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    return np.bincount(rows, weights=np.asarray(w, np.float64), minlength=g.n).astype(np.int64)
+
+
+def volume(g) -> int:
+    """vol(G) = sum_u d_u."""
+    return int(degrees(g).sum())
+
+
+def _rc_check(rc):
+    if rc == -1:
+        raise MemoryError("oracle aggregation ran out of memory")
+    if rc == -2:
+        raise OverflowError("weight sum exceeds uint64")
+    if rc == -3:
+        raise ValueError("edge id out of range")
+    if rc == -4:
+        raise ValueError("zero weight or weighted degree >= 2^32")
 
 
 def _s_array(params):
@@ -105,6 +140,7 @@ def sample_slots(g, params, e_begin: int = 0, e_end: int | None = None):
     """Every sample slot (e, j) of edges [e_begin, e_end): accepted flag, r,
     endpoints (u', v') and fixed-point weight (0 if rejected)."""
     rp, col = _graph_arrays(g)
+    wp, _keep = _weights(g)
     m = g.m
     if e_end is None:
         e_end = m
@@ -116,11 +152,13 @@ def sample_slots(g, params, e_begin: int = 0, e_end: int | None = None):
                    acc=np.empty(cap, np.uint8), r=np.empty(cap, np.uint8),
                    a=np.empty(cap, np.int32), b=np.empty(cap, np.int32),
                    w=np.empty(cap, np.uint64))
-        k = lib().ora_sample_slots(g.n, _p(rp), _p(col), params["T"], _p(s),
+        k = lib().ora_sample_slots(g.n, _p(rp), _p(col), wp, params["T"], _p(s),
                                    int(params["M"]), C, no_ds, int(params["seed"]),
                                    e_begin, e_end, cap, _p(out["e"]), _p(out["j"]),
                                    _p(out["acc"]), _p(out["r"]), _p(out["a"]),
                                    _p(out["b"]), _p(out["w"]))
+        if k == -(1 << 63):
+            _rc_check(-4)
         if k >= 0:
             return {key: v[:k] for key, v in out.items()}
         cap = -k
@@ -137,6 +175,7 @@ def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
     pairs are summed exactly in uint64 (section 5.2, sparse parallel hashing;
     here a sort of the sample triples)."""
     rp, col = _graph_arrays(g)
+    wp, _keep = _weights(g)
     if row_hi is None:
         row_hi = g.n
     if nthreads is None:
@@ -149,15 +188,12 @@ def count_csr(g, params, row_lo: int = 0, row_hi: int | None = None,
     nnz = ctypes.c_int64()
     att = ctypes.c_uint64()
     acc = ctypes.c_uint64()
-    rc = lib().ora_count_rows(g.n, _p(rp), _p(col), params["T"], _p(s), int(params["M"]),
+    rc = lib().ora_count_rows(g.n, _p(rp), _p(col), wp, params["T"], _p(s), int(params["M"]),
                               C, no_ds, int(params["seed"]), row_lo, row_hi, e_begin, e_end,
                               1 if channels else 0, nthreads,
                               ctypes.byref(prp), ctypes.byref(pcol), ctypes.byref(pw),
                               ctypes.byref(nnz), ctypes.byref(att), ctypes.byref(acc))
-    if rc == -1:
-        raise MemoryError("oracle aggregation ran out of memory")
-    if rc == -2:
-        raise OverflowError("weight sum exceeds uint64")
+    _rc_check(rc)
     rows = row_hi - row_lo
     k = nnz.value
     R = np.ctypeslib.as_array(ctypes.cast(prp, ctypes.POINTER(ctypes.c_int64)), (rows + 1,)).copy()
@@ -219,6 +255,7 @@ def count_csr_edges(g, params, row_lo: int, row_hi: int, edges, nthreads: int | 
     ids): the rows [row_lo, row_hi) of the count matrix are exact whenever the
     list holds every edge whose samples can reach those rows."""
     rp, col = _graph_arrays(g)
+    wp, _keep = _weights(g)
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
     s = _s_array(params)
@@ -226,17 +263,12 @@ def count_csr_edges(g, params, row_lo: int, row_hi: int, edges, nthreads: int | 
     el = np.ascontiguousarray(np.unique(np.asarray(edges, np.int64)))
     prp, pcol, pw = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
     nnz, att, acc = ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_uint64()
-    rc = lib().ora_count_rows_list(g.n, _p(rp), _p(col), params["T"], _p(s), int(params["M"]),
+    rc = lib().ora_count_rows_list(g.n, _p(rp), _p(col), wp, params["T"], _p(s), int(params["M"]),
                                    C, no_ds, int(params["seed"]), row_lo, row_hi, _p(el), len(el),
                                    nthreads, ctypes.byref(prp), ctypes.byref(pcol),
                                    ctypes.byref(pw), ctypes.byref(nnz), ctypes.byref(att),
                                    ctypes.byref(acc))
-    if rc == -1:
-        raise MemoryError("oracle aggregation ran out of memory")
-    if rc == -2:
-        raise OverflowError("weight sum exceeds uint64")
-    if rc == -3:
-        raise ValueError("edge id out of range")
+    _rc_check(rc)
     rows = row_hi - row_lo
     k = nnz.value
     R = np.ctypeslib.as_array(ctypes.cast(prp, ctypes.POINTER(ctypes.c_int64)), (rows + 1,)).copy()
@@ -250,9 +282,10 @@ def count_csr_edges(g, params, row_lo: int, row_hi: int, edges, nthreads: int | 
 
 
 def trunc_log(g, params, rowptr, col, W, row_lo: int = 0):
-    """Eq. (1): x = vol^2/(2bM) * (W/2^F) / (d_a d_b); keep x > 1 (exact
-    integer test), value log x.  Returns (keep mask, values)."""
-    deg = np.ascontiguousarray(g.degrees(), dtype=np.int64)
+    """Eq. (1): x = vol 2m/(2bM) * (W/2^F) / (d_a d_b) (vol = 2m unweighted:
+    vol^2/(2bM)); keep x > 1 (exact integer test), value log x.  Returns
+    (keep mask, values)."""
+    deg = np.ascontiguousarray(degrees(g), dtype=np.int64)
     rows = len(rowptr) - 1
     keep = np.zeros(len(col), np.uint8)
     val = np.zeros(len(col), np.float64)
@@ -260,7 +293,8 @@ def trunc_log(g, params, rowptr, col, W, row_lo: int = 0):
     col = np.ascontiguousarray(col, dtype=np.int32)
     W = np.ascontiguousarray(W, dtype=np.uint64)
     lib().ora_trunc_log(rows, row_lo, _p(deg), _p(rowptr), _p(col), _p(W),
-                        g.n_arcs, int(params["b"]), int(params["M"]), _p(keep), _p(val))
+                        volume(g), g.n_arcs, int(params["b"]), int(params["M"]), _p(keep),
+                        _p(val))
     return keep.astype(bool), val
 
 
@@ -299,8 +333,9 @@ def trial_matrix(g, params, R, Cext, W, s):
     np.add.at(mixed, grp, coef[r] * W.astype(np.float64))
     a = uniq // g.n
     b = uniq % g.n
-    deg = g.degrees().astype(np.float64)
-    vol = float(g.n_arcs)
+    assert getattr(g, "weight", None) is None, "channel trials: unweighted graphs"
+    deg = degrees(g).astype(np.float64)
+    vol = float(volume(g))
     x = vol * vol / (2.0 * params["b"] * params["M"]) / 65536.0 * mixed / (deg[a] * deg[b])
     val = np.where(x > 1.0, np.log(np.where(x > 1.0, x, 1.0)), 0.0)
     rp = np.zeros(g.n + 1, np.int64)
@@ -402,9 +437,16 @@ def cheb_coeffs(theta: float, k: int) -> np.ndarray:
     return c
 
 
+def _adjacency(g):
+    """A as a scipy CSR: arc weights, or ones on an unweighted graph."""
+    w = getattr(g, "weight", None)
+    data = np.ones(g.n_arcs) if w is None else np.asarray(w, np.float64)
+    return sp.csr_matrix((data, g.col, g.rowptr), shape=(g.n, g.n))
+
+
 def _walk_matrix(g):
-    deg = g.degrees().astype(np.float64)
-    A = sp.csr_matrix((np.ones(g.n_arcs), g.col, g.rowptr), shape=(g.n, g.n))
+    deg = degrees(g).astype(np.float64)
+    A = _adjacency(g)
     inv = np.where(deg > 0, 1.0 / np.where(deg > 0, deg, 1.0), 0.0)
     return sp.diags(inv) @ A
 
@@ -438,8 +480,8 @@ def propagate_dense(g, X0: np.ndarray, k: int, theta: float, mu: float,
     symmetric N = D^-1/2 A D^-1/2: L = D^-1/2 (I - N) D^1/2, so a polynomial
     p(L) = D^-1/2 V p(1 - Lambda) V^T D^1/2.  ``exact`` uses the filter
     g itself instead of its degree-k expansion.  Small graphs only."""
-    deg = g.degrees().astype(np.float64)
-    A = sp.csr_matrix((np.ones(g.n_arcs), g.col, g.rowptr), shape=(g.n, g.n)).toarray()
+    deg = degrees(g).astype(np.float64)
+    A = _adjacency(g).toarray()
     dm = np.where(deg > 0, deg ** -0.5, 0.0)
     N = dm[:, None] * A * dm[None, :]
     lam_n, V = np.linalg.eigh(N)

@@ -30,6 +30,7 @@ class Graph:
     col: np.ndarray               # int32, 2m
     labels: Optional[np.ndarray] = None   # bool n x L (multi-hot) or None
     name: str = ""
+    weight: Optional[np.ndarray] = None   # uint32 per arc (symmetric) or None
 
     @property
     def n_arcs(self) -> int:

@@ -49,3 +49,22 @@ def params(T=3, s=None, M_per_m=10, C=None, seed=1, m=1, **kw):
              q=1, cheb_k=5, theta=0.5, mu=0.2, precision="f64")
     p.update(kw)
     return p
+
+
+def with_weights(g, seed, wmax=9):
+    """g with symmetric positive integer arc weights drawn from 1..wmax."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    lo = np.minimum(rows, g.col)
+    hi = np.maximum(rows, g.col)
+    key = lo.astype(np.int64) * g.n + hi
+    uniq, inv = np.unique(key, return_inverse=True)
+    w = rng.integers(1, wmax + 1, size=len(uniq)).astype(np.uint32)[inv]
+    return Graph(g.n, g.rowptr, g.col, g.labels, g.name + "-w", w)
+
+
+def dense_wadj(g):
+    A = np.zeros((g.n, g.n))
+    r = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    A[r, g.col] = 1.0 if g.weight is None else g.weight.astype(np.float64)
+    return A
