@@ -60,15 +60,24 @@ typedef void (*lne_free_fn)(void *ptr, void *user);
 
 typedef struct lne_ctx lne_ctx;
 
-/* Undirected, unweighted, simple input graph in symmetric CSR form: row i
- * lists the neighbours of vertex i in ascending order, no self-loops, no
- * duplicates, and j is in row i iff i is in row j (checked only where cheap).
- * Isolated vertices are allowed. */
+/* Undirected, simple input graph in symmetric CSR form: row i lists the
+ * neighbours of vertex i in ascending order, no self-loops, no duplicates,
+ * and j is in row i iff i is in row j (checked only where cheap).  Isolated
+ * vertices are allowed.  weight: NULL for an unweighted graph, else one
+ * positive integer weight A_ij per arc (A_ij = A_ji); then degrees are
+ * d_i = sum_j A_ij, vol = sum_i d_i, degree sampling uses
+ * p_e = min(1, C A_uv (1/d_u + 1/d_v)), walk steps pick neighbour j of i
+ * with probability A_ij / d_i, and an accepted sample weighs
+ * (r / sum over its path's r edges of 1/A) / p_e (NetSMF's path estimator);
+ * Eq. (1)'s factor vol^2 / (2 b M) becomes vol 2m / (2 b M), and propagation
+ * uses the weighted D^-1 A.  Weighted degrees and vol must stay below 2^32.
+ * The batched-trials entry points take unweighted graphs only. */
 typedef struct {
     int64_t n;                 /* vertices                                   */
-    int64_t n_arcs;            /* 2m = vol(G), must be < 2^32                */
+    int64_t n_arcs;            /* 2m, must be < 2^32 (= vol(G) unweighted)   */
     const int64_t *row_ptr;    /* device, n + 1 entries, row_ptr[0] = 0      */
     const int32_t *col;        /* device, n_arcs entries                     */
+    const uint32_t *weight;    /* device, n_arcs entries, or NULL            */
 } lne_graph;
 
 /* Hyperparameters (notation table of the paper; s_r of Eq. (1)). */

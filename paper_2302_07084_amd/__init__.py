@@ -31,7 +31,8 @@ class LneError(RuntimeError):
 
 class Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
-                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -269,8 +270,9 @@ class Context:
         self.check(self.L.lne_prof_reset(self.h), "prof_reset")
 
 
-def graph_struct(rowptr, col):
-    """lne_graph over device tensors (int64 row offsets, int32 columns)."""
+def graph_struct(rowptr, col, weight=None):
+    """lne_graph over device tensors (int64 row offsets, int32 columns and,
+    for a weighted graph, int32 positive arc weights read as uint32)."""
     import torch
     assert rowptr.is_cuda and col.is_cuda
     assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
@@ -280,6 +282,11 @@ def graph_struct(rowptr, col):
     g.n_arcs = col.numel()
     g.row_ptr = rowptr.data_ptr()
     g.col = col.data_ptr() if col.numel() else None
+    g.weight = None
+    if weight is not None:
+        assert weight.is_cuda and weight.is_contiguous() and weight.numel() == col.numel()
+        assert weight.dtype in (torch.int32, torch.uint32)
+        g.weight = weight.data_ptr() if weight.numel() else None
     return g
 
 
@@ -350,9 +357,9 @@ def sampler_plan(params: dict, n_arcs: int):
     return int(base.value), int(thr.value), np.array(theta[:p.T], dtype=np.uint64)
 
 
-def sample_slots(ctx: Context, rowptr, col, params: dict, e_begin: int, e_end: int):
+def sample_slots(ctx: Context, rowptr, col, params: dict, e_begin: int, e_end: int, weight=None):
     import torch
-    g = graph_struct(rowptr, col)
+    g = graph_struct(rowptr, col, weight)
     p = make_params(params)
     S = int(ctx.L.lne_slots_per_edge(ctypes.byref(p), g.n_arcs))
     cnt = max((e_end - e_begin) * S, 1)
@@ -368,8 +375,8 @@ def sample_slots(ctx: Context, rowptr, col, params: dict, e_begin: int, e_end: i
     return dict(S=S, a=a[:k], b=b[:k], w=w[:k], r=r[:k])
 
 
-def sparsify(ctx: Context, rowptr, col, params: dict):
-    g = graph_struct(rowptr, col)
+def sparsify(ctx: Context, rowptr, col, params: dict, weight=None):
+    g = graph_struct(rowptr, col, weight)
     p = make_params(params)
     out = Csr(ctx)
     st = Stats()
@@ -378,9 +385,9 @@ def sparsify(ctx: Context, rowptr, col, params: dict):
     return out, st.as_dict()
 
 
-def sparsify_rows(ctx: Context, rowptr, col, params: dict, row_lo: int, row_hi: int):
+def sparsify_rows(ctx: Context, rowptr, col, params: dict, row_lo: int, row_hi: int, weight=None):
     """Rows [row_lo, row_hi) of the count matrix (all samples walked)."""
-    g = graph_struct(rowptr, col)
+    g = graph_struct(rowptr, col, weight)
     p = make_params(params)
     out = Csr(ctx)
     st = Stats()
@@ -389,8 +396,8 @@ def sparsify_rows(ctx: Context, rowptr, col, params: dict, row_lo: int, row_hi: 
     return out, st.as_dict()
 
 
-def trunc_log(ctx: Context, rowptr, col, params: dict, counts: Csr):
-    g = graph_struct(rowptr, col)
+def trunc_log(ctx: Context, rowptr, col, params: dict, counts: Csr, weight=None):
+    g = graph_struct(rowptr, col, weight)
     p = make_params(params)
     out = Csr(ctx)
     ctx.check(ctx.L.lne_trunc_log(ctx.h, ctypes.byref(g), ctypes.byref(p), ctypes.byref(counts.s),
@@ -441,9 +448,9 @@ def rsvd(ctx: Context, M: Csr, params: dict):
     return U, S, V, X0
 
 
-def propagate(ctx: Context, rowptr, col, params: dict, X0):
+def propagate(ctx: Context, rowptr, col, params: dict, X0, weight=None):
     import torch
-    g = graph_struct(rowptr, col)
+    g = graph_struct(rowptr, col, weight)
     p = make_params(params)
     X = torch.empty_like(X0)
     ctx.check(ctx.L.lne_propagate(ctx.h, ctypes.byref(g), ctypes.byref(p), X0.data_ptr(),
@@ -451,9 +458,9 @@ def propagate(ctx: Context, rowptr, col, params: dict, X0):
     return X
 
 
-def embed(ctx: Context, rowptr, col, params: dict, out=None):
+def embed(ctx: Context, rowptr, col, params: dict, out=None, weight=None):
     import torch
-    g = graph_struct(rowptr, col)
+    g = graph_struct(rowptr, col, weight)
     p = make_params(params)
     dt = torch.float64 if p.precision == F64 else torch.float32
     X = out if out is not None else torch.empty((g.n, p.d), dtype=dt, device=ctx.device)

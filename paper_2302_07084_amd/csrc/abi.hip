@@ -139,6 +139,10 @@ static void host_plan(const lne_params *p, int64_t n, int64_t n_arcs, SamplePlan
     const int64_t m = n_arcs / 2;
     pl.seed = p->seed;
     pl.T = p->T;
+    pl.wt = nullptr;
+    pl.cw = nullptr;
+    pl.ea = nullptr;
+    pl.hmax = 1.0;
     if (m > 0) {
         pl.base = p->M / (uint64_t)m;
         const uint64_t rem = p->M % (uint64_t)m;
@@ -213,10 +217,26 @@ static double range_bytes(uint64_t entries) { return 36.0 * (double)entries; }
 
 struct Sampler {
     SamplePlan pl;
-    Buf eu, ev, wc, wo;
+    Buf eu, ev, wc, wo, ea, cw;
     int64_t m = 0, nw = 0;
     uint64_t attempted = 0, accepted = 0;
 };
+
+// Edge list of the sampler and, on a weighted graph, its weight tables: the
+// prefix sums of the arc weights, each edge's weight and the bound T max A of
+// the path factor (the count pass checks that weights stay below 2^32 with it).
+static lne_status sampler_edges(lne_ctx *ctx, const lne_graph *g, Sampler &S) {
+    LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m, g->weight ? &S.ea : nullptr));
+    if (!g->weight) return LNE_OK;
+    uint64_t vol = 0;
+    uint32_t amax = 1;
+    LNE_TRY(weight_info(ctx, g, S.cw, &vol, &amax));
+    S.pl.wt = g->weight;
+    S.pl.cw = S.cw.as<uint64_t>();
+    S.pl.ea = S.ea.as<uint32_t>();
+    S.pl.hmax = (double)S.pl.T * (double)amax;
+    return LNE_OK;
+}
 
 static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
                               int64_t hi, uint64_t *entries, bool stats) {
@@ -305,10 +325,12 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
     // one pass shared by trials with different s: the length r is kept in
     // the key (column b << 4 | r - 1)
     if (channels) S.pl.cbits = 4;
+    if (channels && g->weight)
+        return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     S.m = g->n_arcs / 2;
     uint64_t total = 0;
     if (S.m > 0 && S.pl.S > 0) {
-        LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m));
+        LNE_TRY(sampler_edges(ctx, g, S));
         S.nw = sample_threads(S.pl, S.m) / 64;
         LNE_TRY(alloc(ctx, S.wc, sizeof(uint32_t) * (size_t)S.nw));
         LNE_TRY(alloc(ctx, S.wo, sizeof(uint64_t) * (size_t)(S.nw + 1)));
@@ -686,12 +708,12 @@ lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *
         return fail(ctx, LNE_EINVAL, "sample_slots: NULL output");
     if (e_end == e_begin) return LNE_OK;
     LNE_TRY(validate_graph_device(ctx, g));
-    SamplePlan pl;
-    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, pl));
-    Buf eu(ctx), ev(ctx);
-    LNE_TRY(build_edges(ctx, g, eu, ev, m));
-    return launch_sample_slots(ctx, g, pl, eu.as<int32_t>(), ev.as<int32_t>(), e_begin, e_end,
-                               a, b, w, r);
+    Sampler S;
+    LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
+    S.m = m;
+    LNE_TRY(sampler_edges(ctx, g, S));
+    return launch_sample_slots(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), e_begin,
+                               e_end, a, b, w, r);
 }
 
 lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
@@ -730,7 +752,7 @@ lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *g, const lne_params 
     S.m = g->n_arcs / 2;
     uint64_t total = 0, entries = 0;
     if (S.m > 0 && S.pl.S > 0) {
-        LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m));
+        LNE_TRY(sampler_edges(ctx, g, S));
         S.nw = sample_threads(S.pl, S.m) / 64;
         LNE_TRY(alloc(ctx, S.wc, sizeof(uint32_t) * (size_t)S.nw));
         LNE_TRY(alloc(ctx, S.wo, sizeof(uint64_t) * (size_t)(S.nw + 1)));
@@ -864,11 +886,17 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     // block keeps its dropped pairs as explicit zeros unless they are more
     // than 1/32 of its entries, in which case it is compacted
     TruncLogFuse tl;
-    tl.c = tl_const(g, p);
+    uint64_t vol = (uint64_t)g->n_arcs;
+    Buf cw(ctx);
+    if (g->weight) {
+        uint32_t amax = 1;
+        LNE_TRY(weight_info(ctx, g, cw, &vol, &amax));
+    }
+    tl.c = tl_const(vol, (uint64_t)g->n_arcs, p);
     tl.val_type = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
     Buf deg(ctx);
     LNE_TRY(alloc(ctx, deg, sizeof(uint32_t) * (size_t)(g->n > 0 ? g->n : 1)));
-    LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>()));
+    LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>(), g->weight ? cw.as<uint64_t>() : nullptr));
     tl.deg = deg.as<uint32_t>();
     std::vector<lne_csr> mblocks;
     auto sink = [&](lne_csr &blk, int64_t) -> lne_status {

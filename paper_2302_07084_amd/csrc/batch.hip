@@ -339,6 +339,8 @@ extern "C" {
 
 lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                                  lne_csr *out, lne_stats *st) {
+    if (ctx && g && g->weight)
+        return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
     if (!out) return fail(ctx, LNE_EINVAL, "sparsify_channels: out is NULL");
     LNE_TRY(validate_graph(ctx, g));
@@ -350,6 +352,8 @@ lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_par
 
 lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                             const lne_csr *channels, const lne_trial *trial, lne_csr *out) {
+    if (ctx && g && g->weight)
+        return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
     LNE_TRY(validate_graph(ctx, g));
     LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
@@ -385,6 +389,8 @@ lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *
 
 lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                             int32_t max_trials, lne_batch **out, lne_stats *st) {
+    if (ctx && g && g->weight)
+        return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
     if (!out) return fail(ctx, LNE_EINVAL, "batch_create: out is NULL");
     *out = nullptr;
@@ -601,6 +607,8 @@ void lne_batch_destroy(lne_batch *b) {
 
 lne_status lne_embed_batch(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                            const lne_trial *trials, int32_t n_trials, float *X, lne_stats *st) {
+    if (ctx && g && g->weight)
+        return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
     if (!trials || !X) return fail(ctx, LNE_EINVAL, "embed_batch: NULL trials or X");
     if (n_trials < 1 || n_trials > 256)

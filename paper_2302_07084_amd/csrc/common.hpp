@@ -127,6 +127,11 @@ struct SamplePlan {
     int32_t colbits;      // bits of a column id in the packed key
     int32_t cbits;        // channel bits below the column (0, or 4 when the
                           // length r is kept: key column = col << 4 | r - 1)
+    // weighted graphs (all null on an unweighted one)
+    const uint32_t *wt;   // arc weights A
+    const uint64_t *cw;   // cw[k] = sum of wt[0..k), n_arcs + 1 entries
+    const uint32_t *ea;   // weight of edge e (u < v arcs in CSR order)
+    double hmax;          // bound of the path factor r / sum 1/A: T max A (1 unweighted)
 };
 
 lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
@@ -134,8 +139,14 @@ lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arc
 
 // Device-side structural check of the input CSR; synchronises the stream.
 lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g);
-// Edge list (u < v arcs in CSR order): eu, ev of m entries.
-lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m);
+// Edge list (u < v arcs in CSR order): eu, ev of m entries; with ea, the
+// edges' weights too (weighted graphs).
+lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m,
+                       Buf *ea = nullptr);
+// Weighted graph: cw (n_arcs + 1 prefix sums of the weights), vol = sum of
+// weights, amax = largest weight; EINVAL on a zero weight, EUNSUPPORTED when a
+// weighted degree or vol reaches 2^32.  Synchronises the stream.
+lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol, uint32_t *amax);
 lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t e_begin,
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
@@ -172,17 +183,19 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
 // x_ab = vol^2 / (2 b M) * (W_ab / 2^16) / (d_a d_b), kept iff x_ab > 1; the
 // keep decision compares W vol^2 with (2 b M 2^16) d_a d_b as exact 128-bit
 // products (vol < 2^32 and 2 b M < 2^40 are validated on the host).
+// On a weighted graph (edges still sampled uniformly) the factor vol^2 is
+// vol 2m: x_ab = vol 2m / (2 b M) (W_ab / 2^16) / (d_a d_b) with weighted
+// degrees and vol; both factors are the arc count 2m on an unweighted graph.
 struct TLConst {
-    uint64_t vol2;     // vol^2
+    uint64_t vol2;     // vol 2m (vol^2 unweighted)
     uint64_t K;        // 2 b M 2^16
-    double scale;      // vol^2 / (2 b M) / 2^16
+    double scale;      // vol 2m / (2 b M) / 2^16
 };
-inline TLConst tl_const(const lne_graph *g, const lne_params *p) {
+inline TLConst tl_const(uint64_t vol, uint64_t arcs, const lne_params *p) {
     TLConst c;
-    const uint64_t vol = (uint64_t)g->n_arcs;
-    c.vol2 = vol * vol;
+    c.vol2 = vol * arcs;
     c.K = (2ull * (uint64_t)p->b * p->M) << 16;
-    c.scale = ((double)vol * (double)vol) / (2.0 * (double)p->b * (double)p->M) / 65536.0;
+    c.scale = ((double)vol * (double)arcs) / (2.0 * (double)p->b * (double)p->M) / 65536.0;
     return c;
 }
 __device__ __forceinline__ bool tl_keep(const TLConst &c, uint64_t W, uint64_t da, uint64_t db) {
@@ -203,8 +216,9 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
                             int32_t val_type, lne_csr *out, uint64_t *kept);
 // deg[i] = degree of vertex i (uint32, n entries): the compact degree table
-// the fused reduction gathers from.
-lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg);
+// the fused reduction gathers from; with cw (weight_info) the weighted degree.
+lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg,
+                          const uint64_t *cw = nullptr);
 // Removes explicit zeros from an F32/F64 CSR (row block), in place of *m.
 lne_status drop_zeros(lne_ctx *ctx, lne_csr *m);
 

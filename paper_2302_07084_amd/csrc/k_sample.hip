@@ -19,6 +19,13 @@
 // so the pair array is compact and in a fixed order without global atomics.
 // Compiled with -ffp-contract=off: the coin thresholds and fixed-point
 // weights are IEEE double operations taken one at a time.
+//
+// Weighted graphs (positive integer weights A): p_e = min(1, C A_uv (1/d_u +
+// 1/d_v)) with weighted degrees; a walk step from x takes t = z mod d_x and
+// the neighbour whose slice of the row's cumulative weights holds t (binary
+// search in the prefix sums cw); an accepted sample weighs h / p_e with
+// h = r / sum_j 1/A_j over its path's edges (the centre edge, the steps from
+// u, then the steps from v), NetSMF's path estimator, 1 on unweighted graphs.
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -31,18 +38,42 @@ constexpr int kBlock = 256;
 struct Coin {
     bool all;        // p_e >= 1 (or downsampling off): every slot accepted
     uint64_t tau;    // accept iff word < tau
-    uint64_t w;      // fixed-point weight rint(2^16 / p_e)
+    double p;        // p_e (1 when all)
+    uint64_t w;      // fixed-point weight rint(2^16 hmax / p_e): the weight of
+                     // every sample on an unweighted graph, a bound otherwise
 };
 
-__device__ __forceinline__ Coin edge_coin(const SamplePlan &pl, int64_t du, int64_t dv) {
+// Fixed-point weight of an accepted sample with path factor h.
+__device__ __forceinline__ uint64_t sample_weight(double h, bool all, double p) {
+    return all ? (uint64_t)rint(65536.0 * h) : (uint64_t)rint(65536.0 * h / p);
+}
+
+__device__ __forceinline__ Coin edge_coin(const SamplePlan &pl, uint32_t A, uint64_t du,
+                                          uint64_t dv) {
     Coin c;
-    if (pl.no_ds) { c.all = true; c.tau = 0; c.w = 65536ull; return c; }
-    const double p = pl.C * (1.0 / (double)du + 1.0 / (double)dv);
-    if (p >= 1.0) { c.all = true; c.tau = 0; c.w = 65536ull; return c; }
+    c.p = 1.0;
+    if (pl.no_ds) { c.all = true; c.tau = 0; c.w = sample_weight(pl.hmax, true, 1.0); return c; }
+    const double p = (pl.C * (double)A) * (1.0 / (double)du + 1.0 / (double)dv);
+    if (p >= 1.0) { c.all = true; c.tau = 0; c.w = sample_weight(pl.hmax, true, 1.0); return c; }
     c.all = false;
     c.tau = (uint64_t)floor(p * 4294967296.0);
-    c.w = (uint64_t)rint(65536.0 / p);
+    c.p = p;
+    c.w = sample_weight(pl.hmax, false, p);
     return c;
+}
+
+// degree of x: arcs, or the weight sum of its row
+template <bool W>
+__device__ __forceinline__ uint64_t vdeg(const SamplePlan &pl, const int64_t *__restrict__ rp,
+                                         int64_t x) {
+    if constexpr (W) return pl.cw[rp[x + 1]] - pl.cw[rp[x]];
+    else return (uint64_t)(rp[x + 1] - rp[x]);
+}
+
+template <bool W>
+__device__ __forceinline__ Coin coin_of(const SamplePlan &pl, const int64_t *__restrict__ rp,
+                                        int64_t e, int32_t u, int32_t v) {
+    return edge_coin(pl, W ? pl.ea[e] : 1u, vdeg<W>(pl, rp, u), vdeg<W>(pl, rp, v));
 }
 
 __device__ __forceinline__ uint64_t draw_ne(const SamplePlan &pl, int64_t e) {
@@ -69,25 +100,47 @@ __device__ __forceinline__ int draw_r(const SamplePlan &pl, uint32_t z) {
     return r;
 }
 
-__device__ __forceinline__ int32_t walk_step(const int64_t *__restrict__ rp,
+// One walk step from x with word z; on a weighted graph inv += 1 / A of the
+// arc taken.
+template <bool W>
+__device__ __forceinline__ int32_t walk_step(const SamplePlan &pl, const int64_t *__restrict__ rp,
                                              const int32_t *__restrict__ col, int32_t x,
-                                             uint32_t z) {
-    const int64_t beg = rp[x];
-    const uint32_t deg = (uint32_t)(rp[x + 1] - beg);
-    return deg ? col[beg + (int64_t)(z % deg)] : x;   // a sink (asymmetric input) holds
+                                             uint32_t z, double &inv) {
+    const int64_t beg = rp[x], end = rp[x + 1];
+    if constexpr (!W) {
+        const uint32_t deg = (uint32_t)(end - beg);
+        return deg ? col[beg + (int64_t)(z % deg)] : x;   // a sink (asymmetric input) holds
+    } else {
+        const uint64_t base = pl.cw[beg];
+        const uint32_t deg = (uint32_t)(pl.cw[end] - base);   // < 2^32 (validated)
+        if (deg == 0) return x;
+        const uint64_t t = base + (uint64_t)(z % deg);
+        // first arc k of the row with cw[k + 1] > t
+        int64_t lo = beg, hi = end - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (pl.cw[mid + 1] > t) hi = mid;
+            else lo = mid + 1;
+        }
+        inv += 1.0 / (double)pl.wt[lo];
+        return col[lo];
+    }
 }
 
-// Walks of an accepted slot whose first Philox block is `blk0`.
+// Walks of an accepted slot whose first Philox block is `blk0`; *h = the
+// path factor r / sum 1/A (weighted graphs; 1 otherwise).
+template <bool W>
 __device__ __forceinline__ int walk_pair(const SamplePlan &pl, const int64_t *__restrict__ rp,
                                          const int32_t *__restrict__ col, int64_t e,
                                          uint32_t j, uint4 blk0, int32_t u, int32_t v,
-                                         int32_t &a, int32_t &b) {
+                                         int32_t &a, int32_t &b, double *h = nullptr) {
     const int r = draw_r(pl, blk0.y);
     const int split = (int)(blk0.z % (uint32_t)r);
     uint4 buf = make_uint4(blk0.w, 0, 0, 0);
     int left = 1;
     uint32_t blk = 0;
     int32_t x = u, y = v;
+    double inv = W ? 1.0 / (double)pl.ea[e] : 0.0;
     // words after the first three: split steps from u, then r-1-split from v
     for (int i = 0; i < r - 1; ++i) {
         if (left == 0) {
@@ -97,11 +150,12 @@ __device__ __forceinline__ int walk_pair(const SamplePlan &pl, const int64_t *__
         const uint32_t z = buf.x;
         buf = make_uint4(buf.y, buf.z, buf.w, 0);
         --left;
-        if (i < split) x = walk_step(rp, col, x, z);
-        else y = walk_step(rp, col, y, z);
+        if (i < split) x = walk_step<W>(pl, rp, col, x, z, inv);
+        else y = walk_step<W>(pl, rp, col, y, z, inv);
     }
     a = x;
     b = y;
+    if (h) *h = W ? (double)r / inv : 1.0;
     return r;
 }
 
@@ -150,7 +204,8 @@ __global__ void k_row_up(const int64_t *__restrict__ rp, const int32_t *__restri
 __global__ void k_fill_edges(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                              int64_t n, const int64_t *__restrict__ first,
                              const uint64_t *__restrict__ eoff, int32_t *__restrict__ eu,
-                             int32_t *__restrict__ ev) {
+                             int32_t *__restrict__ ev, const uint32_t *__restrict__ wt,
+                             uint32_t *__restrict__ ea) {
     const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (u >= n) return;
@@ -159,13 +214,14 @@ __global__ void k_fill_edges(const int64_t *__restrict__ rp, const int32_t *__re
     for (int64_t k = f + lane; k < end; k += 64) {
         eu[base + (k - f)] = (int32_t)u;
         ev[base + (k - f)] = col[k];
+        if (ea) ea[base + (k - f)] = wt[k];
     }
 }
 
 // Count pass: pair entries each wave will emit.  Without a row filter every
 // accepted sample gives two entries and no walk is needed; with a filter
 // [row_lo, row_hi) the walk decides which orientations fall inside.
-template <bool FILTER>
+template <bool FILTER, bool W>
 __global__ void __launch_bounds__(kBlock)
 k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
@@ -179,7 +235,7 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
     uint64_t wmax = 0;
     if (e < m) {
         const int32_t u = eu[e], v = ev[e];
-        const Coin cn = edge_coin(pl, rp[u + 1] - rp[u], rp[v + 1] - rp[v]);
+        const Coin cn = coin_of<W>(pl, rp, e, u, v);
         const uint64_t ne = draw_ne(pl, e);
         const uint64_t j0 = (uint64_t)c * pl.J;
         const uint64_t j1 = min(j0 + (uint64_t)pl.J, ne);
@@ -191,7 +247,7 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
             ++acc;
             if (FILTER) {
                 int32_t a = u, b = v;
-                walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+                walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
                 cnt += (a >= row_lo && a < row_hi) ? 1u : 0u;
                 cnt += (b >= row_lo && b < row_hi) ? 1u : 0u;
             } else {
@@ -265,6 +321,7 @@ k_fold_stats(const unsigned long long *__restrict__ att_part,
 // Emit pass: every wave writes its entries contiguously from the scanned
 // per-wave count; the order inside a wave is (slot, lane, orientation).
 // Keys are ((row - row_lo) << colbits) | col.
+template <bool W>
 __global__ void __launch_bounds__(kBlock)
 k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
               const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
@@ -277,16 +334,16 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint64_t pos = wave_off[t >> 6];
     int32_t u = 0, v = 0;
-    Coin cn{true, 0, 0};
+    Coin cn{true, 0, 1.0, 0};
     uint64_t ne = 0;
     const uint64_t j0 = (uint64_t)c * pl.J;
     if (e < m) {
         u = eu[e];
         v = ev[e];
-        cn = edge_coin(pl, rp[u + 1] - rp[u], rp[v + 1] - rp[v]);
+        cn = coin_of<W>(pl, rp, e, u, v);
         ne = draw_ne(pl, e);
     }
-    const uint32_t w = (uint32_t)cn.w;
+    uint32_t w = (uint32_t)cn.w;
     const int kb = pl.colbits + pl.cbits;
     for (int64_t jj = 0; jj < pl.J; ++jj) {
         const uint64_t j = j0 + (uint64_t)jj;
@@ -296,7 +353,10 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
         if (e < m && j < ne) {
             const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
             if (cn.all || (uint64_t)b0.x < cn.tau) {
-                const int r = walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+                double h;
+                const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b, &h);
+                // the count pass bounded this by cn.w < 2^32
+                if (W) w = (uint32_t)sample_weight(h, cn.all, cn.p);
                 ina = a >= row_lo && a < row_hi;
                 inb = b >= row_lo && b < row_hi;
                 ch = pl.cbits ? (uint64_t)(r - 1) : 0;
@@ -320,6 +380,7 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
     }
 }
 
+template <bool W>
 __global__ void k_sample_slots(SamplePlan pl, const int64_t *__restrict__ rp,
                                const int32_t *__restrict__ col, const int32_t *__restrict__ eu,
                                const int32_t *__restrict__ ev, int64_t e_begin, int64_t count,
@@ -334,14 +395,15 @@ __global__ void k_sample_slots(SamplePlan pl, const int64_t *__restrict__ rp,
     uint64_t w = 0;
     uint8_t r = 0;
     if (j < draw_ne(pl, e)) {
-        const Coin cn = edge_coin(pl, rp[u + 1] - rp[u], rp[v + 1] - rp[v]);
+        const Coin cn = coin_of<W>(pl, rp, e, u, v);
         const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
         if (cn.all || (uint64_t)b0.x < cn.tau) {
             a = u;
             b = v;
-            walk_pair(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
+            double h;
+            walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b, &h);
             r = (uint8_t)draw_r(pl, b0.y);
-            w = cn.w;
+            w = W ? sample_weight(h, cn.all, cn.p) : cn.w;
         }
     }
     oa[s] = a;
@@ -410,8 +472,10 @@ lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g) {
     return LNE_OK;
 }
 
-lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m) {
+lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m,
+                       Buf *ea) {
     Buf nup(ctx), first(ctx), eoff(ctx);
+    if (ea) LNE_TRY(alloc(ctx, *ea, sizeof(uint32_t) * (size_t)(m > 0 ? m : 1)));
     LNE_TRY(alloc(ctx, nup, sizeof(uint32_t) * (size_t)(g->n + 1)));
     LNE_TRY(alloc(ctx, first, sizeof(int64_t) * (size_t)(g->n + 1)));
     LNE_TRY(alloc(ctx, eoff, sizeof(uint64_t) * (size_t)(g->n + 1)));
@@ -429,9 +493,56 @@ lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64
         Launch L(ctx, "fill_edges");
         k_fill_edges<<<grid_of(g->n * 64, 256), 256, 0, ctx->stream>>>(
             g->row_ptr, g->col, g->n, first.as<int64_t>(), eoff.as<uint64_t>(),
-            eu.as<int32_t>(), ev.as<int32_t>());
+            eu.as<int32_t>(), ev.as<int32_t>(), g->weight, ea ? ea->as<uint32_t>() : nullptr);
     }
     return check_launch(ctx, "fill_edges");
+}
+
+// Weighted rows: flag 1 = a zero weight, 2 = a weighted degree of 2^32 or
+// more; amax = largest weight.  16 lanes per row.
+__global__ void k_weight_check(const int64_t *__restrict__ rp, const uint32_t *__restrict__ wt,
+                               const uint64_t *__restrict__ cw, int64_t n,
+                               uint32_t *__restrict__ flags, uint32_t *__restrict__ amax) {
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kValLanes;
+    const int sub = threadIdx.x % kValLanes;
+    if (u >= n) return;
+    const int64_t b = rp[u], e = rp[u + 1];
+    uint32_t f = 0, mx = 0;
+    for (int64_t k = b + sub; k < e; k += kValLanes) {
+        const uint32_t w = wt[k];
+        if (w == 0) f |= 1;
+        mx = w > mx ? w : mx;
+    }
+    if (sub == 0 && cw[e] - cw[b] >= (1ull << 32)) f |= 2;
+    if (f) atomicOr(flags, f);
+    if (mx) atomicMax(amax, mx);
+}
+
+lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol, uint32_t *amax) {
+    LNE_TRY(alloc(ctx, cw, sizeof(uint64_t) * (size_t)(g->n_arcs + 1)));
+    LNE_TRY(scan_u32(ctx, g->weight, cw.as<uint64_t>(), g->n_arcs));
+    Buf fl(ctx);
+    LNE_TRY(alloc(ctx, fl, 2 * sizeof(uint32_t)));
+    LNE_HIP(ctx, hipMemsetAsync(fl.p, 0, 2 * sizeof(uint32_t), ctx->stream));
+    if (g->n > 0) {
+        Launch L(ctx, "weight_check");
+        k_weight_check<<<grid_of(g->n * kValLanes, 256), 256, 0, ctx->stream>>>(
+            g->row_ptr, g->weight, cw.as<uint64_t>(), g->n, fl.as<uint32_t>(),
+            fl.as<uint32_t>() + 1);
+    }
+    LNE_TRY(check_launch(ctx, "weight_check"));
+    uint32_t h[2] = {0, 0};
+    uint64_t total = 0;
+    LNE_HIP(ctx, hipMemcpyAsync(h, fl.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipMemcpyAsync(&total, cw.as<uint64_t>() + g->n_arcs, sizeof(total),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h[0] & 1) return fail(ctx, LNE_EINVAL, "graph weights must be positive");
+    if ((h[0] & 2) || total >= (1ull << 32))
+        return fail(ctx, LNE_EUNSUPPORTED, "weighted degrees and vol must be below 2^32");
+    *vol = total;
+    *amax = h[1] ? h[1] : 1;
+    return LNE_OK;
 }
 
 lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
@@ -442,8 +553,12 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
     if (count <= 0) return LNE_OK;
     {
         Launch L(ctx, "sample_slots");
-        k_sample_slots<<<grid_of(count, 256), 256, 0, ctx->stream>>>(
-            pl, g->row_ptr, g->col, eu, ev, e_begin, count, a, b, w, r);
+        if (pl.wt)
+            k_sample_slots<true><<<grid_of(count, 256), 256, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, e_begin, count, a, b, w, r);
+        else
+            k_sample_slots<false><<<grid_of(count, 256), 256, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, e_begin, count, a, b, w, r);
     }
     return check_launch(ctx, "sample_slots");
 }
@@ -465,12 +580,17 @@ lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePla
     uint32_t *wmax_part = stats ? wp.as<uint32_t>() : nullptr;
     {
         Launch L(ctx, filter ? "sample_count_range" : "sample_count");
-        if (filter)
-            k_sample_count<true><<<(unsigned)nblocks, kBlock, 0, ctx->stream>>>(
-                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part);
-        else
-            k_sample_count<false><<<(unsigned)nblocks, kBlock, 0, ctx->stream>>>(
-                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part);
+#define LNE_CNT(FF, WW)                                                                    \
+    k_sample_count<FF, WW><<<(unsigned)nblocks, kBlock, 0, ctx->stream>>>(                 \
+        pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part)
+        if (filter) {
+            if (pl.wt) LNE_CNT(true, true);
+            else LNE_CNT(true, false);
+        } else {
+            if (pl.wt) LNE_CNT(false, true);
+            else LNE_CNT(false, false);
+        }
+#undef LNE_CNT
     }
     LNE_TRY(check_launch(ctx, "sample_count"));
     if (stats) {
@@ -487,8 +607,12 @@ lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan
     const int64_t threads = sample_threads(pl, m);
     {
         Launch L(ctx, "sample_emit");
-        k_sample_emit<<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
-            pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_off, keys, vals);
+        if (pl.wt)
+            k_sample_emit<true><<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_off, keys, vals);
+        else
+            k_sample_emit<false><<<(unsigned)(threads / kBlock), kBlock, 0, ctx->stream>>>(
+                pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_off, keys, vals);
     }
     return check_launch(ctx, "sample_emit");
 }

@@ -323,9 +323,10 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
     if (lane == 0 && my_kept) atomicAdd(kept, (unsigned long long)my_kept);
 }
 
-__global__ void k_degrees(const int64_t *__restrict__ rp, int64_t n, uint32_t *__restrict__ deg) {
+__global__ void k_degrees(const int64_t *__restrict__ rp, const uint64_t *__restrict__ cw,
+                          int64_t n, uint32_t *__restrict__ deg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) deg[i] = (uint32_t)(rp[i + 1] - rp[i]);
+    if (i < n) deg[i] = cw ? (uint32_t)(cw[rp[i + 1]] - cw[rp[i]]) : (uint32_t)(rp[i + 1] - rp[i]);
 }
 
 __global__ void k_rowptr_tail(const uint64_t *__restrict__ keys, int64_t n_items,
@@ -417,10 +418,10 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
     return LNE_OK;
 }
 
-lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg) {
+lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg, const uint64_t *cw) {
     if (g->n > 0) {
         Launch L(ctx, "degrees");
-        k_degrees<<<grid_of(g->n, 256), 256, 0, ctx->stream>>>(g->row_ptr, g->n, deg);
+        k_degrees<<<grid_of(g->n, 256), 256, 0, ctx->stream>>>(g->row_ptr, cw, g->n, deg);
     }
     return check_launch(ctx, "degrees");
 }

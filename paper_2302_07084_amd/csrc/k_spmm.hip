@@ -187,9 +187,12 @@ __device__ __forceinline__ void graph_epilogue(int64_t o, int c0, int k, const T
     }
 }
 
-template <int L, bool TL, int U, bool NT, class T>
+// W: weighted graph, D^-1 A with arc weights wt and d_i = sum_j A_ij (summed
+// here from the row's weights).
+template <int L, bool TL, int U, bool NT, bool W, class T>
 __global__ void __launch_bounds__(256)
-k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n_rows,
+k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+             const uint32_t *__restrict__ wt, int64_t n_rows,
              const T *__restrict__ Z, int64_t ld, int k_main, int k, T *__restrict__ out, T a,
              T b, const T *__restrict__ E1, T c1, const T *__restrict__ E2, T c2,
              T *__restrict__ accum, T cacc) {
@@ -202,7 +205,7 @@ k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, in
     const int grpt = lane / TLn, lct = lane % TLn;
     const int ct = k_main + lct * N;
     const int64_t beg = rp[row], end = rp[row + 1];
-    const T inv = end > beg ? (T)1 / (T)(end - beg) : (T)0;
+    T inv = end > beg ? (T)1 / (T)(end - beg) : (T)0;
     for (int cb = 0;; cb += L * N) {
         const bool main = cb < k_main;
         const bool tail = TL && cb + L * N >= k_main;
@@ -210,14 +213,21 @@ k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col, in
         T acc[N], acct[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[i] = acct[i] = 0;
+        uint64_t wsum = 0;
         for (int64_t b0 = beg; b0 < end; b0 += 64) {
             const int64_t idx = b0 + lane;
             const int32_t cj = idx < end ? stream_load<NT>(col + idx) : 0;
+            const uint32_t wj = (W && idx < end) ? stream_load<NT>(wt + idx) : 0u;
+            wsum += wj;
             const int cnt = (int)min((int64_t)64, end - b0);
-            if (main) gather_batch<L, U, false, T, T>(Z, ld, c0, true, cj, (T)0, cnt, grp, acc);
+            if (main) gather_batch<L, U, W, T, T>(Z, ld, c0, true, cj, (T)wj, cnt, grp, acc);
             if (tail)
-                gather_batch<TLn, U, false, T, T>(Z, ld, ct, ct < k, cj, (T)0, cnt, grpt,
-                                                         acct);
+                gather_batch<TLn, U, W, T, T>(Z, ld, ct, ct < k, cj, (T)wj, cnt, grpt, acct);
+        }
+        if (W) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+            inv = wsum ? (T)1 / (T)wsum : (T)0;
         }
         if (main) {
             fold_groups<L, T, N>(acc);
@@ -342,16 +352,23 @@ void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t 
                   T *acc, double cacc, int variant) {
     const unsigned grid = grid_of(g->n * 64, 256);
     Launch Lc(ctx, "graph_spmm");
-#define LNE_GS(UU, NTT)                                                                    \
-    k_graph_spmm<L, TL, UU, NTT, T><<<grid, 256, 0, ctx->stream>>>(                       \
-        g->row_ptr, g->col, g->n, Z, ld, k_main, k, out, (T)a, (T)b, E1, (T)c1, E2, (T)c2,  \
-        acc, (T)cacc)
-    switch (variant) {
-        case 1: LNE_GS(8, false); break;
-        case 2: LNE_GS(4, true); break;
-        case 3: LNE_GS(8, true); break;
-        default: LNE_GS(4, false); break;
+#define LNE_GS(UU, NTT, WW)                                                                \
+    k_graph_spmm<L, TL, UU, NTT, WW, T><<<grid, 256, 0, ctx->stream>>>(                   \
+        g->row_ptr, g->col, g->weight, g->n, Z, ld, k_main, k, out, (T)a, (T)b, E1, (T)c1,  \
+        E2, (T)c2, acc, (T)cacc)
+#define LNE_GV(WW)                                                                         \
+    switch (variant) {                                                                     \
+        case 1: LNE_GS(8, false, WW); break;                                               \
+        case 2: LNE_GS(4, true, WW); break;                                                \
+        case 3: LNE_GS(8, true, WW); break;                                                \
+        default: LNE_GS(4, false, WW); break;                                              \
     }
+    if (g->weight) {
+        LNE_GV(true)
+    } else {
+        LNE_GV(false)
+    }
+#undef LNE_GV
 #undef LNE_GS
 }
 

@@ -16,17 +16,18 @@ __device__ __forceinline__ bool keep_entry(const TLConst &c, uint64_t W, uint64_
     return tl_keep(c, W, da, db);
 }
 
-__global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t row_lo, int64_t n,
+// deg: the graph's (weighted) vertex degrees (vertex_degrees)
+__global__ void k_tl_count(TLConst c, const uint32_t *__restrict__ deg, int64_t row_lo, int64_t n,
                            const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const uint64_t *__restrict__ W, uint32_t *__restrict__ kept) {
     const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (a >= n) return;
-    const uint64_t da = (uint64_t)(grp[row_lo + a + 1] - grp[row_lo + a]);
+    const uint64_t da = deg[row_lo + a];
     uint32_t cnt = 0;
     for (int64_t i = rp[a] + lane; i < rp[a + 1]; i += 64) {
         const int32_t b = col[i];
-        cnt += keep_entry(c, W[i], da, (uint64_t)(grp[b + 1] - grp[b])) ? 1u : 0u;
+        cnt += keep_entry(c, W[i], da, (uint64_t)deg[b]) ? 1u : 0u;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
@@ -34,7 +35,7 @@ __global__ void k_tl_count(TLConst c, const int64_t *__restrict__ grp, int64_t r
 }
 
 template <class VT>
-__global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t row_lo, int64_t n,
+__global__ void k_tl_fill(TLConst c, const uint32_t *__restrict__ deg, int64_t row_lo, int64_t n,
                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                           const uint64_t *__restrict__ W, const int64_t *__restrict__ orp,
                           int32_t *__restrict__ ocol, VT *__restrict__ oval) {
@@ -42,7 +43,7 @@ __global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t ro
     const int lane = threadIdx.x & 63;
     if (a >= n) return;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t da = (uint64_t)(grp[row_lo + a + 1] - grp[row_lo + a]);
+    const uint64_t da = deg[row_lo + a];
     int64_t pos = orp[a];
     const int64_t beg = rp[a], end = rp[a + 1];
     for (int64_t i0 = beg; i0 < end; i0 += 64) {
@@ -53,7 +54,7 @@ __global__ void k_tl_fill(TLConst c, const int64_t *__restrict__ grp, int64_t ro
         if (i < end) {
             b = col[i];
             w = W[i];
-            db = (uint64_t)(grp[b + 1] - grp[b]);
+            db = deg[b];
             k = keep_entry(c, w, da, db);
         }
         const uint64_t mask = __ballot(k);
@@ -221,7 +222,13 @@ lne_status drop_zeros(lne_ctx *ctx, lne_csr *m) {
 lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                          const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out) {
     const int64_t n = counts->n_rows;
-    const TLConst c = tl_const(g, p);
+    uint64_t vol = (uint64_t)g->n_arcs;
+    uint32_t amax = 1;
+    Buf cw(ctx), deg(ctx);
+    if (g->weight) LNE_TRY(weight_info(ctx, g, cw, &vol, &amax));
+    const TLConst c = tl_const(vol, (uint64_t)g->n_arcs, p);
+    LNE_TRY(alloc(ctx, deg, sizeof(uint32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+    LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>(), g->weight ? cw.as<uint64_t>() : nullptr));
 
     Buf kept(ctx), rp(ctx);
     LNE_TRY(alloc(ctx, kept, sizeof(uint32_t) * (size_t)(n + 1)));
@@ -229,7 +236,7 @@ lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
     const unsigned grid = grid_of(n * 64, 256);
     if (n > 0) {
         Launch L(ctx, "trunc_log_count");
-        k_tl_count<<<grid, 256, 0, ctx->stream>>>(c, g->row_ptr, row_lo, n, counts->row_ptr,
+        k_tl_count<<<grid, 256, 0, ctx->stream>>>(c, deg.as<uint32_t>(), row_lo, n, counts->row_ptr,
                                                   counts->col, (const uint64_t *)counts->val,
                                                   kept.as<uint32_t>());
     }
@@ -246,12 +253,12 @@ lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
         Launch L(ctx, "trunc_log_fill");
         if (val_type == LNE_F64)
             k_tl_fill<double><<<grid, 256, 0, ctx->stream>>>(
-                c, g->row_ptr, row_lo, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
-                rp.as<int64_t>(), cc.as<int32_t>(), vv.as<double>());
+                c, deg.as<uint32_t>(), row_lo, n, counts->row_ptr, counts->col,
+                (const uint64_t *)counts->val, rp.as<int64_t>(), cc.as<int32_t>(), vv.as<double>());
         else
             k_tl_fill<float><<<grid, 256, 0, ctx->stream>>>(
-                c, g->row_ptr, row_lo, n, counts->row_ptr, counts->col, (const uint64_t *)counts->val,
-                rp.as<int64_t>(), cc.as<int32_t>(), vv.as<float>());
+                c, deg.as<uint32_t>(), row_lo, n, counts->row_ptr, counts->col,
+                (const uint64_t *)counts->val, rp.as<int64_t>(), cc.as<int32_t>(), vv.as<float>());
     }
     LNE_TRY(check_launch(ctx, "trunc_log_fill"));
     out->n_rows = n;
