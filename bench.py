@@ -88,13 +88,15 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--report", choices=["precision", "automl", "mfma", "linkpred"], default=None,
+    ap.add_argument("--report", choices=["precision", "automl", "mfma", "linkpred", "weighted"],
+                    default=None,
                     help="precision: the FP32 and BF16-MFMA paths against the FP64 path; "
                          "automl: trials/s and time to an equal score of the plain "
                          "sequential search and the batched surrogate search; mfma: "
                          "achieved matrix-core rate of the dense rSVD steps; linkpred: "
                          "held-out edges ranked against corrupted ones (MR, MRR, HITS@10, "
-                         "AUC) and the ranking kernel's rate")
+                         "AUC) and the ranking kernel's rate; weighted: the embedding step on "
+                         "the workload's graph with integer weights beside the unweighted one")
     ap.add_argument("--automl-trials", type=int, default=64)
     ap.add_argument("--pretrain-trials", type=int, default=64,
                     help="surrogate pretraining trials per family graph (8 graphs)")
@@ -124,6 +126,9 @@ def main():
         return
     if args.report == "linkpred":
         linkpred_report(args.workload)
+        return
+    if args.report == "weighted":
+        weighted_report(args.workload, seconds=args.cpu_seconds)
         return
 
     if args.calib_copy_mib:
@@ -244,6 +249,54 @@ def _procrustes(X, Xref):
     import numpy as np
     U, _, Vt = np.linalg.svd(X.T @ Xref)
     return float(np.linalg.norm(X @ (U @ Vt) - Xref) / np.linalg.norm(Xref))
+
+
+def weighted_report(name, wmax=16, steps=2, seconds=15.0):
+    """The whole embedding step (sparsify, truncated log, rSVD, propagation) on
+    the workload's graph with symmetric integer weights 1..wmax (a hash of
+    each pair) beside the same step unweighted, in one process: sampled edges
+    per second, the per-kernel time of each, and the weighted oracle's sampler
+    and aggregator on a bounded block of the same edges (host cores)."""
+    import numpy as np
+    import torch
+
+    import paper_2302_07084_amd as lne
+    from synth import Graph, pair_weights, workload
+
+    g, p = workload(name, device="cuda")
+    w = pair_weights(g, wmax, seed=int(p["seed"]) + 1, device="cuda")
+    log(f"weighted: '{name}' n={g.n} m={g.m}, weights 1..{wmax}, vol {int(w.sum(dtype=np.uint64))}")
+    rp = torch.from_numpy(g.rowptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    wd = torch.from_numpy(w.astype(np.int32)).cuda()
+    ctx = lne.Context()
+    X = torch.empty((g.n, p["d"]), dtype=torch.float32, device="cuda")
+    out = {"report": "weighted", "workload": name, "n": g.n, "m": g.m, "weights": f"1..{wmax}",
+           "T": p["T"], "M": p["M"], "d": p["d"], "precision": p["precision"], "runs": {}}
+    for label, weight in (("unweighted", None), ("weighted", wd)):
+        _, st = lne.embed(ctx, rp, col, p, out=X, weight=weight)      # warm-up, tuning
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        ctx.prof_reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = lne.embed(ctx, rp, col, p, out=X, weight=weight)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ker = {}
+        for nm in ("sample_count", "sample_emit", "radix_scatter", "reduce_trunc_log", "spmm",
+                   "graph_spmm", "weight_check"):
+            ms, cnt = ctx.prof_get(nm)
+            if cnt:
+                ker[nm] = ms / steps
+        ctx.prof_enable(False)
+        out["runs"][label] = {"ms_per_step": dt * 1e3, "sampled_edges_per_s": st["accepted"] / dt,
+                              "accepted": st["accepted"], "nnz_log": st["nnz_log"],
+                              "kernels_ms_per_step": ker}
+        log(f"weighted: {label} {dt * 1e3:.1f} ms/step, {st['accepted'] / dt:.3g} sampled edges/s")
+    gw = Graph(g.n, g.rowptr, g.col, None, name + "-w", w)
+    out["cpu_baseline"] = cpu_baseline(gw, p, seconds)
+    print(json.dumps(out), flush=True)
 
 
 def linkpred_report(name, held_out=10_000, K=1000, hits_k=10, oracle_edges=500):

@@ -142,7 +142,6 @@ static void host_plan(const lne_params *p, int64_t n, int64_t n_arcs, SamplePlan
     pl.wt = nullptr;
     pl.cw = nullptr;
     pl.ea = nullptr;
-    pl.hmax = 1.0;
     if (m > 0) {
         pl.base = p->M / (uint64_t)m;
         const uint64_t rem = p->M % (uint64_t)m;
@@ -223,18 +222,15 @@ struct Sampler {
 };
 
 // Edge list of the sampler and, on a weighted graph, its weight tables: the
-// prefix sums of the arc weights, each edge's weight and the bound T max A of
-// the path factor (the count pass checks that weights stay below 2^32 with it).
+// prefix sums of the arc weights and each edge's weight.
 static lne_status sampler_edges(lne_ctx *ctx, const lne_graph *g, Sampler &S) {
     LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m, g->weight ? &S.ea : nullptr));
     if (!g->weight) return LNE_OK;
     uint64_t vol = 0;
-    uint32_t amax = 1;
-    LNE_TRY(weight_info(ctx, g, S.cw, &vol, &amax));
+    LNE_TRY(weight_info(ctx, g, S.cw, &vol));
     S.pl.wt = g->weight;
     S.pl.cw = S.cw.as<uint64_t>();
     S.pl.ea = S.ea.as<uint32_t>();
-    S.pl.hmax = (double)S.pl.T * (double)amax;
     return LNE_OK;
 }
 
@@ -888,10 +884,7 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     TruncLogFuse tl;
     uint64_t vol = (uint64_t)g->n_arcs;
     Buf cw(ctx);
-    if (g->weight) {
-        uint32_t amax = 1;
-        LNE_TRY(weight_info(ctx, g, cw, &vol, &amax));
-    }
+    if (g->weight) LNE_TRY(weight_info(ctx, g, cw, &vol));
     tl.c = tl_const(vol, (uint64_t)g->n_arcs, p);
     tl.val_type = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
     Buf deg(ctx);

@@ -131,7 +131,6 @@ struct SamplePlan {
     const uint32_t *wt;   // arc weights A
     const uint64_t *cw;   // cw[k] = sum of wt[0..k), n_arcs + 1 entries
     const uint32_t *ea;   // weight of edge e (u < v arcs in CSR order)
-    double hmax;          // bound of the path factor r / sum 1/A: T max A (1 unweighted)
 };
 
 lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
@@ -144,9 +143,9 @@ lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g);
 lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m,
                        Buf *ea = nullptr);
 // Weighted graph: cw (n_arcs + 1 prefix sums of the weights), vol = sum of
-// weights, amax = largest weight; EINVAL on a zero weight, EUNSUPPORTED when a
-// weighted degree or vol reaches 2^32.  Synchronises the stream.
-lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol, uint32_t *amax);
+// weights; EINVAL on a zero weight, EUNSUPPORTED when a weighted degree or vol
+// reaches 2^32.  Synchronises the stream.
+lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol);
 lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t e_begin,
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,

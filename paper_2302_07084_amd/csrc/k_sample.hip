@@ -39,8 +39,8 @@ struct Coin {
     bool all;        // p_e >= 1 (or downsampling off): every slot accepted
     uint64_t tau;    // accept iff word < tau
     double p;        // p_e (1 when all)
-    uint64_t w;      // fixed-point weight rint(2^16 hmax / p_e): the weight of
-                     // every sample on an unweighted graph, a bound otherwise
+    uint64_t w;      // fixed-point weight rint(2^16 / p_e) of every sample on
+                     // an unweighted graph
 };
 
 // Fixed-point weight of an accepted sample with path factor h.
@@ -52,13 +52,13 @@ __device__ __forceinline__ Coin edge_coin(const SamplePlan &pl, uint32_t A, uint
                                           uint64_t dv) {
     Coin c;
     c.p = 1.0;
-    if (pl.no_ds) { c.all = true; c.tau = 0; c.w = sample_weight(pl.hmax, true, 1.0); return c; }
+    if (pl.no_ds) { c.all = true; c.tau = 0; c.w = sample_weight(1.0, true, 1.0); return c; }
     const double p = (pl.C * (double)A) * (1.0 / (double)du + 1.0 / (double)dv);
-    if (p >= 1.0) { c.all = true; c.tau = 0; c.w = sample_weight(pl.hmax, true, 1.0); return c; }
+    if (p >= 1.0) { c.all = true; c.tau = 0; c.w = sample_weight(1.0, true, 1.0); return c; }
     c.all = false;
     c.tau = (uint64_t)floor(p * 4294967296.0);
     c.p = p;
-    c.w = sample_weight(pl.hmax, false, p);
+    c.w = sample_weight(1.0, false, p);
     return c;
 }
 
@@ -255,7 +255,10 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
             }
         }
         att = j1 > j0 ? j1 - j0 : 0;
-        wmax = acc ? cn.w : 0;
+        // weighted: r / sum_j 1/A_j <= r A_uv (the centre edge's term alone),
+        // so rint(2^16 T A_uv / p_e) bounds every sample weight of the edge
+        wmax = acc ? (W ? sample_weight((double)pl.T * (double)pl.ea[e], cn.all, cn.p) : cn.w)
+                   : 0;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -355,7 +358,7 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
             if (cn.all || (uint64_t)b0.x < cn.tau) {
                 double h;
                 const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b, &h);
-                // the count pass bounded this by cn.w < 2^32
+                // the count pass bounded this below 2^32
                 if (W) w = (uint32_t)sample_weight(h, cn.all, cn.p);
                 ina = a >= row_lo && a < row_hi;
                 inb = b >= row_lo && b < row_hi;
@@ -499,39 +502,33 @@ lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64
 }
 
 // Weighted rows: flag 1 = a zero weight, 2 = a weighted degree of 2^32 or
-// more; amax = largest weight.  16 lanes per row.
+// more.  16 lanes per row.
 __global__ void k_weight_check(const int64_t *__restrict__ rp, const uint32_t *__restrict__ wt,
                                const uint64_t *__restrict__ cw, int64_t n,
-                               uint32_t *__restrict__ flags, uint32_t *__restrict__ amax) {
+                               uint32_t *__restrict__ flags) {
     const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kValLanes;
     const int sub = threadIdx.x % kValLanes;
     if (u >= n) return;
     const int64_t b = rp[u], e = rp[u + 1];
-    uint32_t f = 0, mx = 0;
-    for (int64_t k = b + sub; k < e; k += kValLanes) {
-        const uint32_t w = wt[k];
-        if (w == 0) f |= 1;
-        mx = w > mx ? w : mx;
-    }
+    uint32_t f = 0;
+    for (int64_t k = b + sub; k < e; k += kValLanes) f |= wt[k] == 0 ? 1u : 0u;
     if (sub == 0 && cw[e] - cw[b] >= (1ull << 32)) f |= 2;
     if (f) atomicOr(flags, f);
-    if (mx) atomicMax(amax, mx);
 }
 
-lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol, uint32_t *amax) {
+lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol) {
     LNE_TRY(alloc(ctx, cw, sizeof(uint64_t) * (size_t)(g->n_arcs + 1)));
     LNE_TRY(scan_u32(ctx, g->weight, cw.as<uint64_t>(), g->n_arcs));
     Buf fl(ctx);
-    LNE_TRY(alloc(ctx, fl, 2 * sizeof(uint32_t)));
-    LNE_HIP(ctx, hipMemsetAsync(fl.p, 0, 2 * sizeof(uint32_t), ctx->stream));
+    LNE_TRY(alloc(ctx, fl, sizeof(uint32_t)));
+    LNE_HIP(ctx, hipMemsetAsync(fl.p, 0, sizeof(uint32_t), ctx->stream));
     if (g->n > 0) {
         Launch L(ctx, "weight_check");
         k_weight_check<<<grid_of(g->n * kValLanes, 256), 256, 0, ctx->stream>>>(
-            g->row_ptr, g->weight, cw.as<uint64_t>(), g->n, fl.as<uint32_t>(),
-            fl.as<uint32_t>() + 1);
+            g->row_ptr, g->weight, cw.as<uint64_t>(), g->n, fl.as<uint32_t>());
     }
     LNE_TRY(check_launch(ctx, "weight_check"));
-    uint32_t h[2] = {0, 0};
+    uint32_t h[1] = {0};
     uint64_t total = 0;
     LNE_HIP(ctx, hipMemcpyAsync(h, fl.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     LNE_HIP(ctx, hipMemcpyAsync(&total, cw.as<uint64_t>() + g->n_arcs, sizeof(total),
@@ -541,7 +538,6 @@ lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol,
     if ((h[0] & 2) || total >= (1ull << 32))
         return fail(ctx, LNE_EUNSUPPORTED, "weighted degrees and vol must be below 2^32");
     *vol = total;
-    *amax = h[1] ? h[1] : 1;
     return LNE_OK;
 }
 

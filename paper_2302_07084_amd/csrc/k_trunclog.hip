@@ -223,9 +223,8 @@ lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                          const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out) {
     const int64_t n = counts->n_rows;
     uint64_t vol = (uint64_t)g->n_arcs;
-    uint32_t amax = 1;
     Buf cw(ctx), deg(ctx);
-    if (g->weight) LNE_TRY(weight_info(ctx, g, cw, &vol, &amax));
+    if (g->weight) LNE_TRY(weight_info(ctx, g, cw, &vol));
     const TLConst c = tl_const(vol, (uint64_t)g->n_arcs, p);
     LNE_TRY(alloc(ctx, deg, sizeof(uint32_t) * (size_t)(g->n > 0 ? g->n : 1)));
     LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>(), g->weight ? cw.as<uint64_t>() : nullptr));

@@ -243,6 +243,31 @@ def chung_lu(n: int, m: int, gamma: float, seed: int, n_groups: int = 0,
     return Graph(n, rowptr, col, groups, name)
 
 
+def pair_weights(g: Graph, wmax: int, seed: int, device: str = "cpu") -> np.ndarray:
+    """Symmetric integer arc weights in 1..wmax: a hash (SplitMix64 finaliser)
+    of the seed and the unordered pair, so arcs (u, v) and (v, u) agree.
+    Returns uint32 per arc."""
+    torch = _torch()
+    n = g.n
+    rp = torch.from_numpy(np.asarray(g.rowptr, np.int64)).to(device)
+    col = torch.from_numpy(np.asarray(g.col, np.int32)).to(device)
+    rows = torch.repeat_interleave(torch.arange(n, device=device), rp[1:] - rp[:-1])
+    c = col.long()
+    key = torch.minimum(rows, c) * n + torch.maximum(rows, c)
+    del rows, c
+
+    def srl(x, k):  # logical right shift of int64 bit patterns
+        return (x >> k) & ((1 << (64 - k)) - 1)
+
+    z = key + (seed * 0x632BE59BD9B4E019 & 0x7FFFFFFFFFFFFFFF) + 0x1E3779B97F4A7C15
+    del key
+    z = (z ^ srl(z, 30)) * -4658895280553007687      # 0xBF58476D1CE4E5B9
+    z = (z ^ srl(z, 27)) * -7723592293110705685      # 0x94D049BB133111EB
+    z = z ^ srl(z, 31)
+    w = (srl(z, 1) % wmax + 1).to(torch.int32)
+    return w.cpu().numpy().astype(np.uint32)
+
+
 def dirichlet_s(T: int, seed: int) -> np.ndarray:
     """Per-length weights s_1..s_T drawn from a flat Dirichlet(1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
