@@ -54,6 +54,10 @@ typedef int32_t lne_status;
 
 /* params.flags */
 #define LNE_FLAG_NO_FINAL_EIGSVD 1u  /* lne_propagate: return the filtered matrix */
+/* lne_rsvd / lne_embed: the vanilla randomized SVD the paper improves on
+ * (section 4.2: Q spans M Omega, B = Q^T M, U = Q U_B) instead of the fast one
+ * (U = the left singular vectors of M Q); same power steps and products. */
+#define LNE_FLAG_VANILLA_RSVD 2u
 
 typedef void *(*lne_alloc_fn)(size_t bytes, void *user);
 typedef void (*lne_free_fn)(void *ptr, void *user);

@@ -22,6 +22,7 @@ import scipy.special
 from . import build as _build
 
 F_BITS = 16                 # fixed-point fraction bits of sample weights
+FLAG_VANILLA_RSVD = 2       # params["flags"] bit: the vanilla randomized SVD
 TAG_OMEGA = 3 << 24         # Philox counter tag of the Gaussian test matrix
 
 _LIB = None
@@ -423,6 +424,23 @@ def fast_rsvd(M, d: int, oversample: int, q: int, omega: np.ndarray,
     return Q[:, :d], S[:d], T @ V[:, :d]
 
 
+def vanilla_rsvd(M, d: int, oversample: int, q: int, omega: np.ndarray):
+    """The vanilla randomized SVD the paper's fast one replaces (section 4.2,
+    after Halko, Martinsson and Tropp): Q = an orthonormal basis of M Omega
+    (Householder QR), refined by q - 1 subspace iterations Q = qr(M Q); then
+    B = Q^T M and its SVD B = U_B S V_B^T give M ~ (Q U_B) S V_B^T.  Returns
+    U = Q U_B[:, :d], S[:d], V = V_B[:d]^T.  Same q convention as
+    ``fast_rsvd``: q products with M after the first."""
+    if q < 1:
+        raise ValueError("q >= 1 required")
+    Q = orth_householder(M @ omega)
+    for _ in range(q - 1):
+        Q = orth_householder(M @ Q)
+    B = (M.T @ Q).T                       # Q^T M (k' x n)
+    Ub, S, Vbt = np.linalg.svd(np.asarray(B), full_matrices=False)
+    return Q @ Ub[:, :d], S[:d], Vbt[:d].T
+
+
 # --------------------------------------------------------------------------
 # Spectral propagation (section 4.3)
 # --------------------------------------------------------------------------
@@ -525,7 +543,8 @@ def embed(g, params, nthreads=None, return_stages=False):
     Mmat = netmf_sparse(g, params, nthreads=nthreads)
     d, ov = params["d"], params["oversample"]
     omega = gaussian_omega(g.n, d + ov, params["seed"])
-    U, S, V = fast_rsvd(Mmat, d, ov, params["q"], omega)
+    rsvd = vanilla_rsvd if int(params.get("flags", 0)) & FLAG_VANILLA_RSVD else fast_rsvd
+    U, S, V = rsvd(Mmat, d, ov, params["q"], omega)
     X0 = embedding(U, S)
     k, theta, mu = params["cheb_k"], params["theta"], params["mu"]
     if k == 0 or theta < 1e-12:

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblne.so")
 
 F64, F32, BF16, U64 = 0, 1, 2, 3
 FLAG_NO_FINAL_EIGSVD = 1
+FLAG_VANILLA_RSVD = 2
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}

@@ -486,20 +486,27 @@ static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p,
     Buf W(ctx), S(ctx);
     LNE_TRY(alloc(ctx, W, sizeof(double) * (size_t)kp * d));
     LNE_TRY(alloc(ctx, S, sizeof(double) * (size_t)d));
+    // With Z = M T = Uz S Vz^T (eigenpairs of Z^T Z = Vz S^2 Vz^T): the fast
+    // randomized SVD keeps U = Z Vz S^-1, V = T Vz; the vanilla one (the
+    // randomized SVD the paper improves on: B = T^T M = Z^T, SVD of B) keeps
+    // U = T Vz, V = Z Vz S^-1.  X0 = U S^(1/2) either way.
+    const bool vanilla = (p->flags & LNE_FLAG_VANILLA_RSVD) != 0;
+    void *Ubase = vanilla ? Q : Y, *Vbase = vanilla ? Y : Q;
+    const double pu = vanilla ? 0.0 : -0.5, pv = vanilla ? -0.5 : 0.0;
     if (U) {
-        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, -0.5, W.as<double>(),
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, pu, W.as<double>(),
                             nullptr));
-        LNE_TRY(project(ctx, Y, dt, ld, n, kp, W.as<double>(), d, U, out_t, d, nullptr));
+        LNE_TRY(project(ctx, Ubase, dt, ld, n, kp, W.as<double>(), d, U, out_t, d, nullptr));
     }
     if (V) {
-        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, 0.0, W.as<double>(),
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, pv, W.as<double>(),
                             nullptr));
-        LNE_TRY(project(ctx, Q, dt, ld, n, kp, W.as<double>(), d, V, out_t, d, nullptr));
+        LNE_TRY(project(ctx, Vbase, dt, ld, n, kp, W.as<double>(), d, V, out_t, d, nullptr));
     }
     if (X0) {
-        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, -0.25,
+        LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, pu + 0.25,
                             W.as<double>(), nullptr));
-        LNE_TRY(project(ctx, Y, dt, ld, n, kp, W.as<double>(), d, X0, out_t, d, nullptr));
+        LNE_TRY(project(ctx, Ubase, dt, ld, n, kp, W.as<double>(), d, X0, out_t, d, nullptr));
     }
     LNE_TRY(eig_weights(ctx, Vk.as<double>(), lam.as<double>(), kp, d, 0.0, nullptr,
                         S.as<double>()));

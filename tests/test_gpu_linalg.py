@@ -175,6 +175,37 @@ def test_rsvd_matches_oracle_f64(lne, ctx, tiny):
     assert procrustes_err(V, st["V"]) < max(tol, 1e-9)
 
 
+@pytest.mark.parametrize("q", [1, 2])
+def test_rsvd_vanilla_matches_oracle_f64(lne, ctx, tiny, q):
+    """The vanilla randomized SVD (flag) against the oracle's HMT version:
+    U = Q U_B from the SVD of B = Q^T M."""
+    g, p, rp, col, st = tiny
+    pp = dict(p, q=q, flags=lne.FLAG_VANILLA_RSVD)
+    counts, _ = lne.sparsify(ctx, rp, col, pp)
+    M = lne.trunc_log(ctx, rp, col, pp, counts)
+    U, S, V, X0 = (x.cpu().numpy() for x in lne.rsvd(ctx, M, pp))
+    kp = p["d"] + p["oversample"]
+    omega = oracle.gaussian_omega(g.n, kp, p["seed"])
+    Uo, So, Vo = oracle.vanilla_rsvd(st["M"], p["d"], p["oversample"], q, omega)
+    gap = (So[-2] - So[-1]) / So[0]
+    tol = 100 * math.sqrt(kp) * U64 / max(gap, 1e-3)
+    np.testing.assert_allclose(S, So, rtol=10 * math.sqrt(kp) * U64 * So[0] / So.min() + 1e-12)
+    assert principal_angle(U, Uo) < max(tol, 1e-9)
+    assert procrustes_err(V, Vo) < max(tol, 1e-9)
+    assert procrustes_err(X0, Uo * np.sqrt(So)) < max(tol, 1e-9)
+    # the fast randomized SVD of the same run takes U from M Q instead
+    Uf = lne.rsvd(ctx, M, dict(p, q=q))[0].cpu().numpy()
+    assert principal_angle(Uf, U) > 10 * max(tol, 1e-9)
+
+
+def test_embed_vanilla_matches_oracle(lne, ctx, tiny):
+    g, p, rp, col, st = tiny
+    pp = dict(p, flags=lne.FLAG_VANILLA_RSVD)
+    X, _ = lne.embed(ctx, rp, col, pp)
+    ref = oracle.embed(g, pp)
+    assert procrustes_err(X.cpu().numpy(), ref) < 1e-8
+
+
 @pytest.mark.parametrize("k,theta,mu", [(10, 0.5, 0.2), (3, 1.0, 0.4), (1, 0.3, 0.0)])
 def test_propagate_filter_matches_oracle(lne, ctx, tiny, k, theta, mu):
     import torch
