@@ -301,8 +301,8 @@ def ablation_report(name, mults=(0.077, 1, 5, 10, 50, 100)):
             counts, _ = lne.sparsify(ctx, task.rp, task.col, pp)
             Mm = lne.trunc_log(ctx, task.rp, task.col, pp, counts)
             counts.free()
-            lne.rsvd(ctx, Mm, pp)
-            (_, _, _, X0), t_rsvd = sync_time(lambda: lne.rsvd(ctx, Mm, pp))
+            lne.rsvd(ctx, Mm, pp, want=("X0",))
+            (_, _, _, X0), t_rsvd = sync_time(lambda: lne.rsvd(ctx, Mm, pp, want=("X0",)))
             Mm.free()
             _, t_prop = sync_time(lambda: lne.propagate(ctx, task.rp, task.col, pp, X0))
             row = {"variant": label, "M_over_Tm": mult, "M": M, "q": q,

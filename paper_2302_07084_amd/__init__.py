@@ -434,18 +434,21 @@ def orthonormalize(ctx: Context, Y):
     return Y
 
 
-def rsvd(ctx: Context, M: Csr, params: dict):
+def rsvd(ctx: Context, M: Csr, params: dict, want=("U", "S", "V", "X0")):
+    """Fast (or, with FLAG_VANILLA_RSVD, vanilla) randomized SVD of M:
+    (U, S, V, X0); outputs not in `want` are not computed (None)."""
     import torch
     p = make_params(params)
     n, d = M.s.n_rows, p.d
     dt = torch.float64 if p.precision == F64 else torch.float32
     dev = ctx.device
-    U = torch.empty((n, d), dtype=dt, device=dev)
-    V = torch.empty((n, d), dtype=dt, device=dev)
-    X0 = torch.empty((n, d), dtype=dt, device=dev)
-    S = torch.empty(d, dtype=torch.float64, device=dev)
-    ctx.check(ctx.L.lne_rsvd(ctx.h, ctypes.byref(M.s), ctypes.byref(p), U.data_ptr(), S.data_ptr(),
-                             V.data_ptr(), X0.data_ptr()), "rsvd")
+    U = torch.empty((n, d), dtype=dt, device=dev) if "U" in want else None
+    V = torch.empty((n, d), dtype=dt, device=dev) if "V" in want else None
+    X0 = torch.empty((n, d), dtype=dt, device=dev) if "X0" in want else None
+    S = torch.empty(d, dtype=torch.float64, device=dev) if "S" in want else None
+    ptr = lambda t: t.data_ptr() if t is not None else None
+    ctx.check(ctx.L.lne_rsvd(ctx.h, ctypes.byref(M.s), ctypes.byref(p), ptr(U), ptr(S),
+                             ptr(V), ptr(X0)), "rsvd")
     return U, S, V, X0
 
 
