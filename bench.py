@@ -100,6 +100,9 @@ def main():
                          "the workload's graph with integer weights beside the unweighted one; "
                          "ablation: stage times and micro-F1 of the vanilla and fast randomized "
                          "SVD (q = 1, 2, 5) over sample sizes")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="extra LNE_FLAG_* bits for the timed step (default 0: the paper's "
+                         "method; 4 = sparse-sign test matrix, 2 = vanilla randomized SVD)")
     ap.add_argument("--automl-trials", type=int, default=64)
     ap.add_argument("--pretrain-trials", type=int, default=64,
                     help="surrogate pretraining trials per family graph (8 graphs)")
@@ -152,6 +155,8 @@ def main():
     t0 = time.time()
     log(f"generating workload '{args.workload}'")
     g, p = workload(args.workload, device="cuda")
+    if args.flags:
+        p = dict(p, flags=int(p.get("flags", 0)) | args.flags)
     log(f"graph n={g.n} m={g.m} in {time.time() - t0:.1f}s; params T={p['T']} M={p['M']} "
         f"d={p['d']} q={p['q']} precision={p['precision']}")
     rp = torch.from_numpy(g.rowptr).cuda()
@@ -182,6 +187,7 @@ def main():
     names = ["validate_graph", "row_up", "fill_edges", "sample_count", "fold_stats", "sample_emit", "scan",
              "radix_hist", "radix_scatter", "heads", "reduce", "degrees", "reduce_trunc_log", "drop_zeros",
              "rowptr_tail", "concat_rows", "trunc_log_count", "trunc_log_fill", "gaussian",
+             "sparse_omega", "spmm_sparse_omega", "weight_check",
              "spmm", "gram", "gram_reduce", "chol_inv", "project", "sym_eig", "eig_weights",
              "w_to_bf16", "graph_spmm", "dense_scale", "axpby"]
     prof = {}
@@ -224,7 +230,7 @@ def main():
                                f"M={p['M']} (4Tm), d={p['d']}, q={p['q']}, k={p['cheb_k']}",
                    "n": g.n, "m": g.m, "T": p["T"], "M": p["M"], "d": p["d"],
                    "oversample": p["oversample"], "q": p["q"], "precision": p["precision"],
-                   "parallelism": "single GPU"},
+                   "flags": int(p.get("flags", 0)), "parallelism": "single GPU"},
         "roofline": {"kernel": rl_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(rl_name),
@@ -277,7 +283,9 @@ def ablation_report(name, mults=(0.077, 1, 5, 10, 50, 100)):
     task = search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=7)
     ctx = lne.Context()
     variants = (("vanilla rSVD, q=1", 1, lne.FLAG_VANILLA_RSVD), ("fast rSVD, q=1", 1, 0),
-                ("fast rSVD, q=2", 2, 0), ("fast rSVD, q=5", 5, 0))
+                ("fast rSVD, q=2", 2, 0), ("fast rSVD, q=5", 5, 0),
+                ("fast rSVD, q=1, sparse-sign Omega", 1, lne.FLAG_SPARSE_OMEGA),
+                ("fast rSVD, q=2, sparse-sign Omega", 2, lne.FLAG_SPARSE_OMEGA))
     out = {"report": "ablation", "workload": name, "n": g.n, "m": g.m, "T": p["T"], "d": p["d"],
            "oversample": p["oversample"], "cheb_k": p["cheb_k"], "precision": p["precision"],
            "scoring": "one-vs-rest logistic regression on GPU, 10% training labels, 3 splits, "

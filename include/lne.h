@@ -58,6 +58,9 @@ typedef int32_t lne_status;
  * (section 4.2: Q spans M Omega, B = Q^T M, U = Q U_B) instead of the fast one
  * (U = the left singular vectors of M Q); same power steps and products. */
 #define LNE_FLAG_VANILLA_RSVD 2u
+/* lne_rsvd / lne_embed: a sparse-sign test matrix (lne_sparse_omega) instead
+ * of the Gaussian one; the first product gathers 16 bytes per nonzero. */
+#define LNE_FLAG_SPARSE_OMEGA 4u
 
 typedef void *(*lne_alloc_fn)(size_t bytes, void *user);
 typedef void (*lne_free_fn)(void *ptr, void *user);
@@ -154,6 +157,18 @@ lne_status lne_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr,
  * 3 << 24)): even c takes the cosine, odd c the sine.  out: device, n x k,
  * leading dimension ld, element type dtype (values computed in double and
  * rounded).  Errors: EINVAL. */
+/* Sparse-sign test matrix, the alternative Omega of the randomized SVD
+ * (LNE_FLAG_SPARSE_OMEGA): row i has 8 entries; word t (t < 8) of
+ * Philox(counter = (i_lo, i_hi, t / 4, 5 << 24)) picks column (z >> 1) mod k
+ * and sign -1 if z is odd, +1 otherwise; entries landing on one column add.
+ * out: device n x 8 int16, entry sign * (column + 1), 16-byte aligned.
+ * Errors: EINVAL (k outside 1..1024). */
+lne_status lne_sparse_omega(lne_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int16_t *out);
+/* Y = A Omega for a library CSR A and a sparse-sign Omega (lne_sparse_omega,
+ * n_cols x 8): Y device n_rows x k (ldy, dtype F64 / F32 / BF16 as in
+ * lne_spmm, accumulated in F64 / F32).  Errors: EINVAL. */
+lne_status lne_spmm_sparse_omega(lne_ctx *ctx, const lne_csr *A, const int16_t *om, void *Y,
+                                 int64_t ldy, int32_t k, int32_t dtype);
 lne_status lne_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld,
                         uint64_t seed, int32_t dtype, void *out);
 

@@ -23,6 +23,9 @@ from . import build as _build
 
 F_BITS = 16                 # fixed-point fraction bits of sample weights
 FLAG_VANILLA_RSVD = 2       # params["flags"] bit: the vanilla randomized SVD
+FLAG_SPARSE_OMEGA = 4       # params["flags"] bit: sparse-sign test matrix
+TAG_SPARSE_OMEGA = 5 << 24  # Philox counter tag of the sparse-sign test matrix
+SPARSE_OMEGA_NNZ = 8        # signed entries per row
 TAG_OMEGA = 3 << 24         # Philox counter tag of the Gaussian test matrix
 
 _LIB = None
@@ -424,6 +427,26 @@ def fast_rsvd(M, d: int, oversample: int, q: int, omega: np.ndarray,
     return Q[:, :d], S[:d], T @ V[:, :d]
 
 
+def sparse_sign_omega(n: int, k: int, seed: int, rows=None) -> np.ndarray:
+    """Sparse-sign test matrix (the alternative to randn(n, k) in the
+    randomized SVD): row i has 8 signed unit entries; word t of
+    Philox(counter = (i_lo, i_hi, t // 4, TAG_SPARSE_OMEGA)) picks column
+    (z >> 1) mod k and sign -1 for odd z, +1 otherwise; entries on one column
+    add.  Dense n x k (or only the rows `rows`)."""
+    ids = np.arange(n, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
+    n = len(ids)
+    out = np.zeros((n, k))
+    for b in range(SPARSE_OMEGA_NNZ // 4):
+        ctr = np.stack([(ids & 0xFFFFFFFF).astype(np.uint32), (ids >> 32).astype(np.uint32),
+                        np.full(n, b, np.uint32), np.full(n, TAG_SPARSE_OMEGA, np.uint32)], axis=1)
+        z = philox(seed, ctr).astype(np.uint64)
+        for t in range(4):
+            c = ((z[:, t] >> 1) % k).astype(np.int64)
+            sgn = np.where(z[:, t] & 1, -1.0, 1.0)
+            np.add.at(out, (np.arange(n), c), sgn)
+    return out
+
+
 def vanilla_rsvd(M, d: int, oversample: int, q: int, omega: np.ndarray):
     """The vanilla randomized SVD the paper's fast one replaces (section 4.2,
     after Halko, Martinsson and Tropp): Q = an orthonormal basis of M Omega
@@ -542,7 +565,9 @@ def embed(g, params, nthreads=None, return_stages=False):
     """Sparsified NetMF embedding of graph g (FP64 throughout)."""
     Mmat = netmf_sparse(g, params, nthreads=nthreads)
     d, ov = params["d"], params["oversample"]
-    omega = gaussian_omega(g.n, d + ov, params["seed"])
+    flags = int(params.get("flags", 0))
+    omega = (sparse_sign_omega if flags & FLAG_SPARSE_OMEGA else gaussian_omega)(
+        g.n, d + ov, params["seed"])
     rsvd = vanilla_rsvd if int(params.get("flags", 0)) & FLAG_VANILLA_RSVD else fast_rsvd
     U, S, V = rsvd(Mmat, d, ov, params["q"], omega)
     X0 = embedding(U, S)

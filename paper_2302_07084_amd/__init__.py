@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblne.so")
 F64, F32, BF16, U64 = 0, 1, 2, 3
 FLAG_NO_FINAL_EIGSVD = 1
 FLAG_VANILLA_RSVD = 2
+FLAG_SPARSE_OMEGA = 4
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
@@ -89,6 +90,8 @@ SIGNATURES = [
     ("lne_prof_reset", _I32, [_P]),
     ("lne_philox", _I32, [_P, _U64, _P, _I64, _P]),
     ("lne_gaussian", _I32, [_P, _I64, _I32, _I64, _U64, _I32, _P]),
+    ("lne_sparse_omega", _I32, [_P, _I64, _I32, _U64, _P]),
+    ("lne_spmm_sparse_omega", _I32, [_P, _P, _P, _P, _I64, _I32, _I32]),
     ("lne_slots_per_edge", _I64, [_P, _I64]),
     ("lne_sampler_plan", _I32, [_P, _I64, _P, _P, _P]),
     ("lne_sample_slots", _I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P]),
@@ -679,4 +682,22 @@ def link_rank(ctx: Context, X, pos, neg, hits_k: int = 10):
                                   above.data_ptr(), ties.data_ptr(), m.data_ptr()), "link_rank")
     mv = m.cpu().tolist()
     return (dict(mean_rank=mv[0], mrr=mv[1], hits=mv[2], auc=mv[3]), above, ties)
+
+
+def sparse_omega(ctx: Context, n: int, k: int, seed: int):
+    """Sparse-sign test matrix: (n, 8) int16 entries sign * (column + 1)."""
+    import torch
+    out = torch.empty((n, 8), dtype=torch.int16, device=ctx.device)
+    ctx.check(ctx.L.lne_sparse_omega(ctx.h, n, k, seed, out.data_ptr()), "sparse_omega")
+    return out
+
+
+def spmm_sparse_omega(ctx: Context, A: Csr, om, k: int, dtype=None):
+    """Y = A Omega for a sparse-sign Omega (sparse_omega)."""
+    import torch
+    dtype = dtype or (torch.float64 if A.s.val_type == F64 else torch.float32)
+    Y = torch.empty((A.s.n_rows, k), dtype=dtype, device=ctx.device)
+    ctx.check(ctx.L.lne_spmm_sparse_omega(ctx.h, ctypes.byref(A.s), om.data_ptr(), Y.data_ptr(),
+                                          Y.stride(0), k, _code_of(Y)), "spmm_sparse_omega")
+    return Y
 

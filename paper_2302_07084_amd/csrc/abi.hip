@@ -468,8 +468,15 @@ static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p,
     Flags f;
     LNE_TRY(make_flags(ctx, f));
     void *Q = A.p, *Y = B.p;
-    LNE_TRY(launch_gaussian(ctx, n, kp, ld, p->seed, dt, Q));
-    LNE_TRY(spmm(ctx, M, Q, ld, Y, ld, kp, dt));
+    if (p->flags & LNE_FLAG_SPARSE_OMEGA) {
+        Buf om(ctx);
+        LNE_TRY(alloc(ctx, om, sizeof(int16_t) * kSparseOmega * (size_t)n));
+        LNE_TRY(launch_sparse_omega(ctx, n, kp, p->seed, om.as<int16_t>()));
+        LNE_TRY(spmm_sparse_omega(ctx, M, om.as<int16_t>(), Y, ld, kp, dt));
+    } else {
+        LNE_TRY(launch_gaussian(ctx, n, kp, ld, p->seed, dt, Q));
+        LNE_TRY(spmm(ctx, M, Q, ld, Y, ld, kp, dt));
+    }
     LNE_TRY(orth_impl(ctx, Y, n, kp, ld, dt, f));
     std::swap(Q, Y);
     Buf Vk(ctx), lam(ctx);
@@ -665,6 +672,21 @@ lne_status lne_philox(lne_ctx *ctx, uint64_t seed, const uint32_t *ctr, int64_t 
     if (count < 0 || (count > 0 && (!ctr || !out)))
         return fail(ctx, LNE_EINVAL, "philox: bad arguments");
     return launch_philox(ctx, seed, ctr, count, out);
+}
+
+lne_status lne_sparse_omega(lne_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int16_t *out) {
+    if (!ctx) return LNE_EINVAL;
+    if (n < 0 || k < 1 || k > 1024 || (n > 0 && !out))
+        return fail(ctx, LNE_EINVAL, "sparse_omega: bad arguments");
+    if ((uintptr_t)out % 16) return fail(ctx, LNE_EINVAL, "sparse_omega: out must be 16-byte aligned");
+    return launch_sparse_omega(ctx, n, k, seed, out);
+}
+
+lne_status lne_spmm_sparse_omega(lne_ctx *ctx, const lne_csr *A, const int16_t *om, void *Y,
+                                 int64_t ldy, int32_t k, int32_t dtype) {
+    if (!ctx) return LNE_EINVAL;
+    if (!A || (uintptr_t)om % 16) return fail(ctx, LNE_EINVAL, "spmm_sparse_omega: bad arguments");
+    return spmm_sparse_omega(ctx, A, om, Y, ldy, k, dtype);
 }
 
 lne_status lne_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld, uint64_t seed,

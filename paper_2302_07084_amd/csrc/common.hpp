@@ -146,6 +146,15 @@ lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64
 // weights; EINVAL on a zero weight, EUNSUPPORTED when a weighted degree or vol
 // reaches 2^32.  Synchronises the stream.
 lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol);
+
+// Sparse-sign test matrix (LNE_FLAG_SPARSE_OMEGA): kSparseOmega signed
+// column entries per row, int16 sign (column + 1), one 16-byte vector per row.
+constexpr int kSparseOmega = 8;
+lne_status launch_sparse_omega(lne_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int16_t *out);
+// Y = A Omega for a sparse-sign Omega (n x k logical): the row accumulator
+// lives in LDS, each nonzero gathers one 16-byte row of Omega.
+lne_status spmm_sparse_omega(lne_ctx *ctx, const lne_csr *A, const int16_t *om, void *Y,
+                             int64_t ldy, int32_t k, int32_t dtype);
 lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t e_begin,
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,

@@ -448,7 +448,38 @@ __global__ void k_gaussian(int64_t n, int32_t k, int64_t ld, uint64_t seed, T *_
     if (c + 1 < k) out[i * ld + c + 1] = from_double<T>(rad * sin(ang));
 }
 
+// Sparse-sign test matrix: row i holds kSparseOmega entries; word t of
+// Philox(counter = (i_lo, i_hi, t / 4, 5 << 24)) gives column (z >> 1) mod k
+// and sign (z & 1 ? -1 : +1), stored as sign (column + 1) in int16.
+__global__ void k_sparse_omega(int64_t n, int32_t k, uint64_t seed, int16_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int16_t e[kSparseOmega];
+#pragma unroll
+    for (int b = 0; b < kSparseOmega / 4; ++b) {
+        const uint4 z = philox4x32_10(
+            make_uint4((uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)b, kTagSparseOmega),
+            (uint32_t)seed, (uint32_t)(seed >> 32));
+        const uint32_t w[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = (int)((w[t] >> 1) % (uint32_t)k) + 1;
+            e[4 * b + t] = (int16_t)((w[t] & 1u) ? -c : c);
+        }
+    }
+    *reinterpret_cast<uint4 *>(out + i * kSparseOmega) = *reinterpret_cast<const uint4 *>(e);
+}
+
 }  // namespace
+
+lne_status launch_sparse_omega(lne_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int16_t *out) {
+    if (n <= 0) return LNE_OK;
+    {
+        Launch L(ctx, "sparse_omega");
+        k_sparse_omega<<<grid_of(n, 256), 256, 0, ctx->stream>>>(n, k, seed, out);
+    }
+    return check_launch(ctx, "sparse_omega");
+}
 
 int64_t sample_threads(const SamplePlan &pl, int64_t m) {
     return ceil_div(m * pl.chunks, kBlock) * kBlock;

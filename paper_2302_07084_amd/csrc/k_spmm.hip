@@ -245,6 +245,42 @@ k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     }
 }
 
+// Y = A Omega with a sparse-sign Omega: one wave per row; the wave's k-wide
+// row accumulator sits in LDS, every lane takes one nonzero (column j,
+// value v) of a 64-entry batch, loads Omega's row j (kSparseOmega signed
+// columns, 16 bytes) and adds +-v to those columns with LDS atomics.
+template <class VT, class AT, class OT>
+__global__ void __launch_bounds__(256)
+k_spmm_sparse_omega(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                    const VT *__restrict__ val, int64_t n_rows, const int16_t *__restrict__ om,
+                    OT *__restrict__ Y, int64_t ldy, int k) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    AT *acc = reinterpret_cast<AT *>(lds_raw) + (threadIdx.x >> 6) * k;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int c = lane; c < k; c += 64) acc[c] = (AT)0;
+    __builtin_amdgcn_wave_barrier();
+    if (row >= n_rows) return;
+    const int64_t beg = rp[row], end = rp[row + 1];
+    for (int64_t b0 = beg; b0 < end; b0 += 64) {
+        const int64_t idx = b0 + lane;
+        if (idx < end) {
+            const int32_t j = col[idx];
+            const AT v = (AT)val[idx];
+            const uint4 raw = *reinterpret_cast<const uint4 *>(om + (int64_t)j * kSparseOmega);
+            const int16_t *e = reinterpret_cast<const int16_t *>(&raw);
+#pragma unroll
+            for (int t = 0; t < kSparseOmega; ++t) {
+                const int c = e[t] > 0 ? e[t] - 1 : -e[t] - 1;
+                if ((unsigned)c < (unsigned)k) atomicAdd(&acc[c], e[t] > 0 ? v : -v);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int c = lane; c < k; c += 64) Y[row * ldy + c] = (OT)acc[c];
+}
+
 template <class XT, class YT>
 __global__ void k_scale(const XT *__restrict__ x, int64_t ldx, YT *__restrict__ y, int64_t ldy,
                         int64_t n, int k, double alpha) {
@@ -457,6 +493,36 @@ lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out
     else
         return fail(ctx, LNE_EINVAL, "graph_spmm: bad dtype");
     return s;
+}
+
+lne_status spmm_sparse_omega(lne_ctx *ctx, const lne_csr *A, const int16_t *om, void *Y,
+                             int64_t ldy, int32_t k, int32_t dtype) {
+    if (k < 1 || k > 1024 || ldy < k || !om || !Y)
+        return fail(ctx, LNE_EINVAL, "spmm_sparse_omega: bad arguments");
+    const unsigned grid = grid_of(A->n_rows * 64, 256);
+    {
+        Launch L(ctx, "spmm_sparse_omega");
+        if (dtype == LNE_F64) {
+            if (A->val_type != LNE_F64) return fail(ctx, LNE_EINVAL, "F64 needs F64 values");
+            k_spmm_sparse_omega<double, double, double>
+                <<<grid, 256, 4 * k * sizeof(double), ctx->stream>>>(
+                    A->row_ptr, A->col, (const double *)A->val, A->n_rows, om, (double *)Y, ldy,
+                    k);
+        } else if (dtype == LNE_F32) {
+            if (A->val_type != LNE_F32) return fail(ctx, LNE_EINVAL, "F32 needs F32 values");
+            k_spmm_sparse_omega<float, float, float><<<grid, 256, 4 * k * sizeof(float),
+                                                       ctx->stream>>>(
+                A->row_ptr, A->col, (const float *)A->val, A->n_rows, om, (float *)Y, ldy, k);
+        } else if (dtype == LNE_BF16) {
+            if (A->val_type != LNE_F32) return fail(ctx, LNE_EINVAL, "BF16 needs F32 values");
+            k_spmm_sparse_omega<float, float, __bf16><<<grid, 256, 4 * k * sizeof(float),
+                                                        ctx->stream>>>(
+                A->row_ptr, A->col, (const float *)A->val, A->n_rows, om, (__bf16 *)Y, ldy, k);
+        } else {
+            return fail(ctx, LNE_EINVAL, "spmm_sparse_omega: bad dtype");
+        }
+    }
+    return check_launch(ctx, "spmm_sparse_omega");
 }
 
 lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,

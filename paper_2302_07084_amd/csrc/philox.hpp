@@ -13,6 +13,7 @@ namespace lne {
 constexpr uint32_t kTagEdgeCount = 1u << 24;  // n_e of an edge
 constexpr uint32_t kTagWalk = 2u << 24;       // words of one sample slot
 constexpr uint32_t kTagOmega = 3u << 24;      // Gaussian test matrix
+constexpr uint32_t kTagSparseOmega = 5u << 24; // sparse-sign test matrix
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll

@@ -206,6 +206,59 @@ def test_embed_vanilla_matches_oracle(lne, ctx, tiny):
     assert procrustes_err(X.cpu().numpy(), ref) < 1e-8
 
 
+def _dense_omega(om, k):
+    om = om.astype(np.int64)
+    out = np.zeros((om.shape[0], k))
+    c = np.abs(om) - 1
+    np.add.at(out, (np.repeat(np.arange(om.shape[0]), om.shape[1]), c.ravel()),
+              np.sign(om).ravel().astype(np.float64))
+    return out
+
+
+def test_sparse_omega_matches_oracle(lne, ctx):
+    for n, k, seed in ((1000, 42, 1), (5003, 138, 9)):
+        om = lne.sparse_omega(ctx, n, k, seed).cpu().numpy()
+        np.testing.assert_array_equal(_dense_omega(om, k), oracle.sparse_sign_omega(n, k, seed))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_spmm_sparse_omega_vs_scipy(lne, ctx, tiny, prec):
+    import torch
+    g, p, rp, col, st = tiny
+    pp = dict(p, precision=prec)
+    counts, _ = lne.sparsify(ctx, rp, col, pp)
+    M = lne.trunc_log(ctx, rp, col, pp, counts)
+    R, C, V = (x.cpu() for x in M.to_torch())
+    A = sp.csr_matrix((V.double().numpy(), C.numpy(), R.numpy()), shape=(g.n, g.n))
+    for k in (42, 138):
+        om = lne.sparse_omega(ctx, g.n, k, 4)
+        tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
+        Y = lne.spmm_sparse_omega(ctx, M, om, k, tdt).double().cpu().numpy()
+        O = _dense_omega(om.cpu().numpy(), k)
+        ref = A @ O
+        scale = np.abs(A) @ np.abs(O)
+        u = {"f64": U64, "f32": U32, "bf16": UBF}[prec]
+        assert np.all(np.abs(Y - ref) <= 4 * np.sqrt(A.getnnz(1).max() * 8) * u * scale + 1e-300)
+
+
+def test_rsvd_and_embed_with_sparse_omega_match_oracle(lne, ctx, tiny):
+    g, p, rp, col, st = tiny
+    pp = dict(p, flags=lne.FLAG_SPARSE_OMEGA)
+    counts, _ = lne.sparsify(ctx, rp, col, pp)
+    M = lne.trunc_log(ctx, rp, col, pp, counts)
+    U, S, V, X0 = (x.cpu().numpy() for x in lne.rsvd(ctx, M, pp))
+    kp = p["d"] + p["oversample"]
+    omega = oracle.sparse_sign_omega(g.n, kp, p["seed"])
+    Uo, So, Vo = oracle.fast_rsvd(st["M"], p["d"], p["oversample"], p["q"], omega)
+    gap = (So[-2] - So[-1]) / So[0]
+    tol = 100 * math.sqrt(kp) * U64 / max(gap, 1e-3)
+    np.testing.assert_allclose(S, So, rtol=10 * math.sqrt(kp) * U64 * So[0] / So.min() + 1e-12)
+    assert principal_angle(U, Uo) < max(tol, 1e-9)
+    assert procrustes_err(V, Vo) < max(tol, 1e-9)
+    X, _ = lne.embed(ctx, rp, col, pp)
+    assert procrustes_err(X.cpu().numpy(), oracle.embed(g, pp)) < 1e-8
+
+
 @pytest.mark.parametrize("k,theta,mu", [(10, 0.5, 0.2), (3, 1.0, 0.4), (1, 0.3, 0.0)])
 def test_propagate_filter_matches_oracle(lne, ctx, tiny, k, theta, mu):
     import torch
