@@ -436,6 +436,8 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
 // rotates kk/2 disjoint pairs at once, so a sweep is kk - 1 rounds.  IN_LDS:
 // the working copy of A lives in the workgroup's LDS (k^2 doubles of dynamic
 // shared memory), the eigenvector accumulator in global memory.
+constexpr int kB = 4;   // rotation elements per thread in flight
+
 template <bool IN_LDS>
 __global__ void __launch_bounds__(kSolveThreads)
 k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__restrict__ V,
@@ -486,37 +488,114 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__res
                 cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int64_t idx = tid; idx < (int64_t)half * k; idx += kSolveThreads) {
-                const int pr = (int)(idx / k), j = (int)(idx % k);
-                const int p = pp[pr], q = qq[pr];
-                if (q >= k || sn[pr] == 0.0) continue;
-                const double c = cs[pr], s = sn[pr];
-                const double ap = A[(int64_t)p * k + j], aq = A[(int64_t)q * k + j];
-                A[(int64_t)p * k + j] = c * ap - s * aq;
-                A[(int64_t)q * k + j] = s * ap + c * aq;
+            // rows: A <- J^T A; then columns: A <- A J, V <- V J.  32-bit
+            // index arithmetic (half k < 2^31), and each thread issues the
+            // loads of kB elements before their stores so that their
+            // latencies overlap (V lives in global memory, and so does A
+            // when it does not fit LDS)
+            const int total = half * k;
+            for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
+                double a0[kB], a1[kB];
+                int o0[kB], o1[kB];
+                bool on[kB];
+                double c[kB], s[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = b0 + u * kSolveThreads;
+                    const int pr = idx < total ? idx / k : 0, j = idx - pr * k;
+                    const int p = pp[pr], q = qq[pr];
+                    on[u] = idx < total && q < k && sn[pr] != 0.0;
+                    c[u] = cs[pr];
+                    s[u] = sn[pr];
+                    o0[u] = p * k + j;
+                    o1[u] = q * k + j;
+                    a0[u] = on[u] ? A[o0[u]] : 0.0;
+                    a1[u] = on[u] ? A[o1[u]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (on[u]) {
+                        A[o0[u]] = c[u] * a0[u] - s[u] * a1[u];
+                        A[o1[u]] = s[u] * a0[u] + c[u] * a1[u];
+                    }
             }
             __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int64_t idx = tid; idx < (int64_t)half * k; idx += kSolveThreads) {
-                const int pr = (int)(idx / k), i = (int)(idx % k);
-                const int p = pp[pr], q = qq[pr];
-                if (q >= k || sn[pr] == 0.0) continue;
-                const double c = cs[pr], s = sn[pr];
-                const double ap = A[(int64_t)i * k + p], aq = A[(int64_t)i * k + q];
-                A[(int64_t)i * k + p] = c * ap - s * aq;
-                A[(int64_t)i * k + q] = s * ap + c * aq;
-                const double vp = Vw[(int64_t)i * k + p], vq = Vw[(int64_t)i * k + q];
-                Vw[(int64_t)i * k + p] = c * vp - s * vq;
-                Vw[(int64_t)i * k + q] = s * vp + c * vq;
+            // columns: A <- A J and V <- V J, V kept transposed (row p of Vw
+            // = column p of V) so that its rotation runs along rows p, q.
+            // With A in LDS one pass does both, lanes down the columns; with
+            // A in global memory the columns of A take a pass of their own
+            // with lanes along a row i (pair index fastest), so a wave's
+            // accesses stay inside one or two rows of A.
+            if constexpr (!IN_LDS) {
+                for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
+                    double a0[kB], a1[kB];
+                    int o0[kB], o1[kB];
+                    bool on[kB];
+                    double c[kB], s[kB];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) {
+                        const int idx = b0 + u * kSolveThreads;
+                        const int i = idx < total ? idx / half : 0, pr = idx - i * half;
+                        const int p = pp[pr], q = qq[pr];
+                        on[u] = idx < total && q < k && sn[pr] != 0.0;
+                        c[u] = cs[pr];
+                        s[u] = sn[pr];
+                        o0[u] = i * k + p;
+                        o1[u] = i * k + q;
+                        a0[u] = on[u] ? A[o0[u]] : 0.0;
+                        a1[u] = on[u] ? A[o1[u]] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kB; ++u)
+                        if (on[u]) {
+                            A[o0[u]] = c[u] * a0[u] - s[u] * a1[u];
+                            A[o1[u]] = s[u] * a0[u] + c[u] * a1[u];
+                        }
+                }
+            }
+            for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
+                double a0[kB], a1[kB], v0[kB], v1[kB];
+                int o0[kB], o1[kB];
+                bool on[kB];
+                double c[kB], s[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    const int idx = b0 + u * kSolveThreads;
+                    const int pr = idx < total ? idx / k : 0, i = idx - pr * k;
+                    const int p = pp[pr], q = qq[pr];
+                    on[u] = idx < total && q < k && sn[pr] != 0.0;
+                    c[u] = cs[pr];
+                    s[u] = sn[pr];
+                    o0[u] = p * k + i;
+                    o1[u] = q * k + i;
+                    v0[u] = on[u] ? Vw[o0[u]] : 0.0;
+                    v1[u] = on[u] ? Vw[o1[u]] : 0.0;
+                    if constexpr (IN_LDS) {
+                        a0[u] = on[u] ? A[i * k + p] : 0.0;
+                        a1[u] = on[u] ? A[i * k + q] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (on[u]) {
+                        Vw[o0[u]] = c[u] * v0[u] - s[u] * v1[u];
+                        Vw[o1[u]] = s[u] * v0[u] + c[u] * v1[u];
+                        if constexpr (IN_LDS) {
+                            const int idx = b0 + u * kSolveThreads;
+                            const int pr = idx / k, i = idx - pr * k;
+                            A[i * k + pp[pr]] = c[u] * a0[u] - s[u] * a1[u];
+                            A[i * k + qq[pr]] = s[u] * a0[u] + c[u] * a1[u];
+                        }
+                    }
             }
             __syncthreads();
         }
         // convergence: off-diagonal mass relative to the diagonal
         double off = 0.0, dia = 0.0;
-        for (int64_t i = tid; i < k2; i += kSolveThreads) {
+        for (int i = tid; i < (int)k2; i += kSolveThreads) {
             const double x = A[i];
-            if (i / k == i % k) dia += x * x; else off += x * x;
+            const int r = i / k;
+            if (i - r * k == r) dia += x * x; else off += x * x;
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -542,7 +621,7 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__res
             rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
         }
         lam[rank] = li;
-        for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vw[(int64_t)row * k + i];
+        for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vw[(int64_t)i * k + row];
     }
 }
 
