@@ -115,3 +115,45 @@ def test_sampler_plan_matches_oracle(lne):
             assert lne.sampler_plan(p, 2 * m)[0:2] == oracle.plan(T, s, M, m)[0:2]
             np.testing.assert_array_equal(lne.sampler_plan(p, 2 * m)[2], oracle.plan(T, s, M, m)[2])
             assert lne.slots_per_edge(p, 2 * m) == M // m + (1 if M % m else 0)
+
+
+def test_link_rank_rejects_bad_arguments(lne):
+    L, h = _ctx(lne)
+    X, P, N, Mx = (ctypes.c_void_p(a) for a in (0x10000, 0x20000, 0x30000, 0x40000))
+    F32, F64 = lne.F32, lne.F64
+    good = dict(X=X, n=100, d=32, ldx=32, dt=F32, pos=P, h=10, neg=N, K=5, hk=10)
+    for bad in (dict(X=None), dict(n=0), dict(d=0), dict(d=4096, ldx=4096), dict(ldx=16),
+                dict(h=0), dict(K=0), dict(hk=0), dict(dt=lne.BF16), dict(pos=None),
+                dict(neg=None), dict(X=ctypes.c_void_p(0x10008)), dict(ldx=34)):
+        a = dict(good, **bad)
+        rc = L.lne_link_rank(h, a["X"], a["n"], a["d"], a["ldx"], a["dt"], a["pos"], a["h"],
+                             a["neg"], a["K"], a["hk"], None, None, Mx)
+        assert rc == -1, bad
+    L.lne_ctx_destroy(h)
+
+
+def test_sparse_omega_rejects_bad_arguments(lne):
+    L, h = _ctx(lne)
+    out = ctypes.c_void_p(0x10000)
+    for n, k, o in ((-1, 8, out), (10, 0, out), (10, 1025, out), (10, 8, None),
+                    (10, 8, ctypes.c_void_p(0x10002))):
+        assert L.lne_sparse_omega(h, n, k, 1, o) == -1, (n, k)
+    A = lne.CsrStruct()
+    A.n_rows, A.n_cols, A.nnz, A.val_type = 4, 4, 0, lne.F32
+    assert L.lne_spmm_sparse_omega(h, ctypes.byref(A), ctypes.c_void_p(0x10004),
+                                   ctypes.c_void_p(0x20000), 8, 8, lne.F32) == -1
+    assert L.lne_spmm_sparse_omega(h, ctypes.byref(A), ctypes.c_void_p(0x10000),
+                                   ctypes.c_void_p(0x20000), 8, 2000, lne.F32) == -1
+    L.lne_ctx_destroy(h)
+
+
+def test_batched_trials_reject_weighted_graphs(lne):
+    L, h = _ctx(lne)
+    g = _graph()
+    g.weight = 0x5000
+    p = lne.make_params(gs.params(T=3, m=10))
+    rc = L.lne_sparsify_channels(h, ctypes.byref(g), ctypes.byref(p), ctypes.byref(lne.CsrStruct()),
+                                 None)
+    assert rc == -5
+    assert b"unweighted" in L.lne_last_error(h)
+    L.lne_ctx_destroy(h)
