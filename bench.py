@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--report", choices=["precision", "automl", "mfma", "linkpred", "weighted",
-                                         "ablation"],
+                                         "ablation", "host"],
                     default=None,
                     help="precision: the FP32 and BF16-MFMA paths against the FP64 path; "
                          "automl: trials/s and time to an equal score of the plain "
@@ -99,7 +99,9 @@ def main():
                          "AUC) and the ranking kernel's rate; weighted: the embedding step on "
                          "the workload's graph with integer weights beside the unweighted one; "
                          "ablation: stage times and micro-F1 of the vanilla and fast randomized "
-                         "SVD (q = 1, 2, 5) over sample sizes")
+                         "SVD (q = 1, 2, 5) over sample sizes; host: the embedding step with "
+                         "the sparsifier in pinned host memory (streamed over PCIe) beside "
+                         "the in-HBM step")
     ap.add_argument("--flags", type=int, default=0,
                     help="extra LNE_FLAG_* bits for the timed step (default 0: the paper's "
                          "method; 4 = sparse-sign test matrix, 2 = vanilla randomized SVD)")
@@ -138,6 +140,9 @@ def main():
         return
     if args.report == "ablation":
         ablation_report(args.workload if args.workload != "large" else "batched")
+        return
+    if args.report == "host":
+        host_report(args.workload)
         return
 
     if args.calib_copy_mib:
@@ -368,6 +373,59 @@ def weighted_report(name, wmax=16, steps=2, seconds=15.0):
         log(f"weighted: {label} {dt * 1e3:.1f} ms/step, {st['accepted'] / dt:.3g} sampled edges/s")
     gw = Graph(g.n, g.rowptr, g.col, None, name + "-w", w)
     out["cpu_baseline"] = cpu_baseline(gw, p, seconds)
+    print(json.dumps(out), flush=True)
+
+
+def host_report(name, steps=2):
+    """The embedding step with the sparsified matrix kept in pinned host
+    memory (the path for graphs whose sparsifier exceeds HBM: its row chunks
+    stream over PCIe for each of the q + 1 products of the randomized SVD)
+    beside the same step with the matrix in HBM; both give the same
+    embedding bit for bit (checked here).  Reports ms per step, the bytes
+    moved over PCIe per step (the matrix once to the host, q + 1 times back)
+    and their rate counted over the extra time plus the in-HBM products'."""
+    import torch
+
+    import paper_2302_07084_amd as lne
+    from synth import workload
+
+    g, p = workload(name, device="cuda")
+    rp = torch.from_numpy(g.rowptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    ctx = lne.Context()
+    out = {"report": "host", "workload": name, "n": g.n, "m": g.m, "T": p["T"], "M": p["M"],
+           "d": p["d"], "q": p["q"], "precision": p["precision"], "runs": {}}
+    Xs = {}
+    for label, flags in (("hbm", 0), ("host", lne.FLAG_HOST_SPARSIFIER)):
+        pp = dict(p, flags=flags)
+        X, st = lne.embed(ctx, rp, col, pp)                 # warm-up, tuning
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        ctx.prof_reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            X, st = lne.embed(ctx, rp, col, pp, out=X)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        spmm_ms, cnt = ctx.prof_get("spmm")
+        ctx.prof_enable(False)
+        Xs[label] = X
+        out["runs"][label] = {"ms_per_step": dt * 1e3, "sampled_edges_per_s": st["accepted"] / dt,
+                              "nnz_log": st["nnz_log"], "spmm_ms_per_step": spmm_ms / steps}
+        log(f"host: {label} {dt * 1e3:.1f} ms/step (spmm {spmm_ms / steps:.1f} ms), "
+            f"nnz {st['nnz_log']}")
+    nnz = out["runs"]["host"]["nnz_log"]
+    es = 8 if p["precision"] == "f64" else 4
+    matrix = nnz * (4 + es) + 8 * (g.n + 1)
+    moved = matrix * (1 + p["q"] + 1)
+    extra = (out["runs"]["host"]["ms_per_step"] - out["runs"]["hbm"]["ms_per_step"]
+             + out["runs"]["hbm"]["spmm_ms_per_step"]) * 1e-3
+    out["matrix_bytes"] = matrix
+    out["pcie_bytes_per_step"] = moved
+    out["pcie_gb_per_s"] = moved / extra / 1e9 if extra > 0 else None
+    out["bit_identical"] = bool((Xs["host"] == Xs["hbm"]).all())
+    log(f"host: {moved / 1e9:.1f} GB over PCIe per step, {out['pcie_gb_per_s']} GB/s effective, "
+        f"identical {out['bit_identical']}")
     print(json.dumps(out), flush=True)
 
 

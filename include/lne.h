@@ -61,6 +61,11 @@ typedef int32_t lne_status;
 /* lne_rsvd / lne_embed: a sparse-sign test matrix (lne_sparse_omega) instead
  * of the Gaussian one; the first product gathers 16 bytes per nonzero. */
 #define LNE_FLAG_SPARSE_OMEGA 4u
+/* lne_embed: keep the sparsifier's row blocks in pinned host memory (for
+ * graphs whose sparsifier exceeds HBM); the products of the randomized SVD
+ * stream them over PCIe, the copy of one chunk overlapping the product with
+ * the previous one.  Results equal those of the in-HBM path. */
+#define LNE_FLAG_HOST_SPARSIFIER 8u
 
 typedef void *(*lne_alloc_fn)(size_t bytes, void *user);
 typedef void (*lne_free_fn)(void *ptr, void *user);

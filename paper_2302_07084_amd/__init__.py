@@ -20,6 +20,7 @@ F64, F32, BF16, U64 = 0, 1, 2, 3
 FLAG_NO_FINAL_EIGSVD = 1
 FLAG_VANILLA_RSVD = 2
 FLAG_SPARSE_OMEGA = 4
+FLAG_HOST_SPARSIFIER = 8
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}

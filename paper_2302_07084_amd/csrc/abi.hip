@@ -454,9 +454,188 @@ static int64_t line_ld(int64_t k, size_t es) {
     return (k + q - 1) / q * q;
 }
 
-static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U,
+// ---- sparsifier in host memory ---------------------------------------------
+// For graphs whose sparsifier exceeds HBM (LNE_FLAG_HOST_SPARSIFIER): the row
+// blocks of M live in pinned host memory in chunks of at most
+// host_chunk_nnz() entries (a longer row makes a chunk of its own), and every
+// product with M streams them: a copy stream stages chunk b + 1 while chunk b
+// is multiplied, two staging buffers ordered by events.
+// Entries per chunk: LNE_HOST_CHUNK_NNZ if set, else 2^28 (2 GB of column and
+// FP32 value, two staging copies of which sit in HBM).
+static int64_t host_chunk_nnz() {
+    const char *env = getenv("LNE_HOST_CHUNK_NNZ");
+    if (env && *env) {
+        const long long v = atoll(env);
+        if (v >= 1) return (int64_t)v;
+    }
+    return (int64_t)1 << 28;
+}
+
+struct HostChunk {
+    int64_t row_lo = 0, n_rows = 0, nnz = 0;
+    int64_t *rp = nullptr;   // pinned, n_rows + 1 entries from 0
+    int32_t *col = nullptr;  // pinned
+    void *val = nullptr;     // pinned
+};
+
+struct HostMatrix {
+    std::vector<HostChunk> chunks;
+    int64_t n = 0, rows = 0, max_rows = 0, max_nnz = 0;
+    int32_t val_type = LNE_F32;
+    HostMatrix() = default;
+    HostMatrix(const HostMatrix &) = delete;
+    HostMatrix &operator=(const HostMatrix &) = delete;
+    ~HostMatrix() {
+        for (auto &c : chunks) {
+            if (c.rp) (void)hipHostFree(c.rp);
+            if (c.col) (void)hipHostFree(c.col);
+            if (c.val) (void)hipHostFree(c.val);
+        }
+    }
+};
+
+// Moves a device row block (rows [H.rows, H.rows + blk.n_rows)) to pinned host
+// chunks and frees it.  Synchronises the stream.
+static lne_status block_to_host(lne_ctx *ctx, lne_csr &blk, HostMatrix &H) {
+    const size_t es = dtype_size(blk.val_type);
+    H.val_type = blk.val_type;
+    H.n = blk.n_cols;
+    const int64_t chunk = host_chunk_nnz();
+    std::vector<int64_t> rp((size_t)blk.n_rows + 1);
+    LNE_HIP(ctx, hipMemcpyAsync(rp.data(), blk.row_ptr, sizeof(int64_t) * rp.size(),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t r0 = 0, r1; r0 < blk.n_rows; r0 = r1) {
+        r1 = r0 + 1;
+        while (r1 < blk.n_rows && rp[r1 + 1] - rp[r0] <= chunk) ++r1;
+        HostChunk c;
+        c.row_lo = H.rows + r0;
+        c.n_rows = r1 - r0;
+        c.nnz = rp[r1] - rp[r0];
+        if (hipHostMalloc((void **)&c.rp, sizeof(int64_t) * (size_t)(c.n_rows + 1)) != hipSuccess ||
+            hipHostMalloc((void **)&c.col, sizeof(int32_t) * (size_t)(c.nnz ? c.nnz : 1)) !=
+                hipSuccess ||
+            hipHostMalloc(&c.val, es * (size_t)(c.nnz ? c.nnz : 1)) != hipSuccess) {
+            H.chunks.push_back(c);
+            return fail(ctx, LNE_ENOMEM, "host sparsifier: pinned allocation failed");
+        }
+        for (int64_t r = 0; r <= c.n_rows; ++r) c.rp[r] = rp[r0 + r] - rp[r0];
+        if (c.nnz) {
+            LNE_HIP(ctx, hipMemcpyAsync(c.col, blk.col + rp[r0], sizeof(int32_t) * c.nnz,
+                                        hipMemcpyDeviceToHost, ctx->stream));
+            LNE_HIP(ctx, hipMemcpyAsync(c.val, (const char *)blk.val + es * rp[r0], es * c.nnz,
+                                        hipMemcpyDeviceToHost, ctx->stream));
+        }
+        H.max_rows = std::max(H.max_rows, c.n_rows);
+        H.max_nnz = std::max(H.max_nnz, c.nnz);
+        H.chunks.push_back(c);
+    }
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    H.rows += blk.n_rows;
+    lne_csr_free(ctx, &blk);
+    return LNE_OK;
+}
+
+// The sparsifier of a product: a device CSR, or host chunks.
+struct MatOp {
+    const lne_csr *M = nullptr;
+    const HostMatrix *H = nullptr;
+    int64_t n = 0;
+};
+
+// Runs fn(view, row_lo) on every chunk of H staged in device memory, the copy
+// of the next chunk overlapping the work on the current one.
+template <class F>
+static lne_status stream_chunks(lne_ctx *ctx, const HostMatrix &H, F &&fn) {
+    const size_t es = dtype_size(H.val_type);
+    Buf rp[2] = {Buf(ctx), Buf(ctx)}, cc[2] = {Buf(ctx), Buf(ctx)}, vv[2] = {Buf(ctx), Buf(ctx)};
+    for (int i = 0; i < 2; ++i) {
+        LNE_TRY(alloc(ctx, rp[i], sizeof(int64_t) * (size_t)(H.max_rows + 1)));
+        LNE_TRY(alloc(ctx, cc[i], sizeof(int32_t) * (size_t)(H.max_nnz ? H.max_nnz : 1)));
+        LNE_TRY(alloc(ctx, vv[i], es * (size_t)(H.max_nnz ? H.max_nnz : 1)));
+    }
+    hipStream_t cs = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr}, ready = nullptr;
+    lne_status st = LNE_OK;
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && st == LNE_OK)
+            st = fail(ctx, LNE_EHIP, "host sparsifier: %s: %s", what, hipGetErrorString(e));
+        return e == hipSuccess;
+    };
+    if (hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "stream"))
+        for (int i = 0; i < 2; ++i)
+            if (!hip_ok(hipEventCreateWithFlags(&copied[i], hipEventDisableTiming), "event") ||
+                !hip_ok(hipEventCreateWithFlags(&used[i], hipEventDisableTiming), "event"))
+                break;
+    // a caller's stream-ordered allocator may hand out staging memory that
+    // work already queued on the context stream still reads: the copy stream
+    // starts behind that work
+    if (st == LNE_OK && hip_ok(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "event") &&
+        hip_ok(hipEventRecord(ready, ctx->stream), "record"))
+        hip_ok(hipStreamWaitEvent(cs, ready, 0), "wait");
+    for (size_t b = 0; st == LNE_OK && b < H.chunks.size(); ++b) {
+        const HostChunk &c = H.chunks[b];
+        const int sl = (int)(b & 1);
+        if (b >= 2 && !hip_ok(hipStreamWaitEvent(cs, used[sl], 0), "wait")) break;
+        if (!hip_ok(hipMemcpyAsync(rp[sl].p, c.rp, sizeof(int64_t) * (size_t)(c.n_rows + 1),
+                                   hipMemcpyHostToDevice, cs), "copy"))
+            break;
+        if (c.nnz && (!hip_ok(hipMemcpyAsync(cc[sl].p, c.col, sizeof(int32_t) * (size_t)c.nnz,
+                                             hipMemcpyHostToDevice, cs), "copy") ||
+                      !hip_ok(hipMemcpyAsync(vv[sl].p, c.val, es * (size_t)c.nnz,
+                                             hipMemcpyHostToDevice, cs), "copy")))
+            break;
+        if (!hip_ok(hipEventRecord(copied[sl], cs), "record") ||
+            !hip_ok(hipStreamWaitEvent(ctx->stream, copied[sl], 0), "wait"))
+            break;
+        lne_csr view;
+        std::memset(&view, 0, sizeof(view));
+        view.n_rows = c.n_rows;
+        view.n_cols = H.n;
+        view.nnz = c.nnz;
+        view.row_ptr = rp[sl].as<int64_t>();
+        view.col = cc[sl].as<int32_t>();
+        view.val = vv[sl].p;
+        view.val_type = H.val_type;
+        if (c.n_rows > 0) st = fn(view, c.row_lo);
+        if (st == LNE_OK) hip_ok(hipEventRecord(used[sl], ctx->stream), "record");
+    }
+    // the staging buffers are released when this returns: drain both streams
+    if (cs) {
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipStreamDestroy(cs);
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (copied[i]) (void)hipEventDestroy(copied[i]);
+        if (used[i]) (void)hipEventDestroy(used[i]);
+    }
+    if (ready) (void)hipEventDestroy(ready);
+    return st;
+}
+
+// Y = M X for a device or host sparsifier.
+static lne_status apply_M(lne_ctx *ctx, const MatOp &op, const void *X, int64_t ldx, void *Y,
+                          int64_t ldy, int32_t k, int32_t dt) {
+    if (!op.H) return spmm(ctx, op.M, X, ldx, Y, ldy, k, dt);
+    const size_t es = dtype_size(dt);
+    return stream_chunks(ctx, *op.H, [&](const lne_csr &v, int64_t lo) {
+        return spmm(ctx, &v, X, ldx, (char *)Y + es * (size_t)(lo * ldy), ldy, k, dt);
+    });
+}
+
+static lne_status apply_M_sparse_omega(lne_ctx *ctx, const MatOp &op, const int16_t *om, void *Y,
+                                       int64_t ldy, int32_t k, int32_t dt) {
+    if (!op.H) return spmm_sparse_omega(ctx, op.M, om, Y, ldy, k, dt);
+    const size_t es = dtype_size(dt);
+    return stream_chunks(ctx, *op.H, [&](const lne_csr &v, int64_t lo) {
+        return spmm_sparse_omega(ctx, &v, om, (char *)Y + es * (size_t)(lo * ldy), ldy, k, dt);
+    });
+}
+
+static lne_status rsvd_impl(lne_ctx *ctx, const MatOp &op, const lne_params *p, void *U,
                             double *sigma, void *V, void *X0, lne_stats *st) {
-    const int64_t n = M->n_rows;
+    const int64_t n = op.n;
     const int32_t kp = p->d + p->oversample, d = p->d;
     const int32_t dt = p->precision;
     const int32_t out_t = dt == LNE_F64 ? LNE_F64 : LNE_F32;
@@ -472,16 +651,16 @@ static lne_status rsvd_impl(lne_ctx *ctx, const lne_csr *M, const lne_params *p,
         Buf om(ctx);
         LNE_TRY(alloc(ctx, om, sizeof(int16_t) * kSparseOmega * (size_t)n));
         LNE_TRY(launch_sparse_omega(ctx, n, kp, p->seed, om.as<int16_t>()));
-        LNE_TRY(spmm_sparse_omega(ctx, M, om.as<int16_t>(), Y, ld, kp, dt));
+        LNE_TRY(apply_M_sparse_omega(ctx, op, om.as<int16_t>(), Y, ld, kp, dt));
     } else {
         LNE_TRY(launch_gaussian(ctx, n, kp, ld, p->seed, dt, Q));
-        LNE_TRY(spmm(ctx, M, Q, ld, Y, ld, kp, dt));
+        LNE_TRY(apply_M(ctx, op, Q, ld, Y, ld, kp, dt));
     }
     LNE_TRY(orth_impl(ctx, Y, n, kp, ld, dt, f));
     std::swap(Q, Y);
     Buf Vk(ctx), lam(ctx);
     for (int it = 1; it <= p->q; ++it) {
-        LNE_TRY(spmm(ctx, M, Q, ld, Y, ld, kp, dt));
+        LNE_TRY(apply_M(ctx, op, Q, ld, Y, ld, kp, dt));
         if (it < p->q) {
             LNE_TRY(orth_impl(ctx, Y, n, kp, ld, dt, f));
             std::swap(Q, Y);
@@ -887,7 +1066,10 @@ lne_status lne_rsvd(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U
     if (M->val_type != need)
         return fail(ctx, LNE_EINVAL, "rsvd: values must be %s for this precision",
                     need == LNE_F64 ? "F64" : "F32");
-    return rsvd_impl(ctx, M, p, U, sigma, V, X0, nullptr);
+    MatOp op;
+    op.M = M;
+    op.n = M->n_rows;
+    return rsvd_impl(ctx, op, p, U, sigma, V, X0, nullptr);
 }
 
 lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p, const void *X0,
@@ -921,22 +1103,33 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>(), g->weight ? cw.as<uint64_t>() : nullptr));
     tl.deg = deg.as<uint32_t>();
     std::vector<lne_csr> mblocks;
+    const bool host = (p->flags & LNE_FLAG_HOST_SPARSIFIER) != 0;
+    HostMatrix H;
+    uint64_t kept_before = 0;
+    // A block is compacted when more than 1/32 of its entries were dropped
+    // (the same decision with M in HBM or in host memory, so that both give
+    // the same products); in host mode it then moves to pinned host memory.
     auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
-        mblocks.push_back(blk);
+        const uint64_t kept = tl.kept - kept_before;
+        kept_before = tl.kept;
+        lne_status r = LNE_OK;
+        if ((uint64_t)blk.nnz - kept > (uint64_t)blk.nnz / 32) r = drop_zeros(ctx, &blk);
+        if (r == LNE_OK && host) r = block_to_host(ctx, blk, H);
+        if (r != LNE_OK) {
+            lne_csr_free(ctx, &blk);
+            return r;
+        }
+        if (!host) mblocks.push_back(blk);
         return LNE_OK;
     };
     lne_csr M;
     std::memset(&M, 0, sizeof(M));
     LNE_TRY(validate_graph_device(ctx, g));
     lne_status s = sparsify_impl(ctx, g, p, st, sink, false, &tl);
-    if (s == LNE_OK) {
-        int64_t stored = 0;
-        for (auto &b : mblocks) stored += b.nnz;
-        if ((uint64_t)stored - tl.kept > (uint64_t)stored / 32)
-            for (auto &b : mblocks)
-                if (s == LNE_OK) s = drop_zeros(ctx, &b);
-    }
-    if (s == LNE_OK) s = concat_rows(ctx, mblocks, g->n, &M);
+    if (s == LNE_OK && !host) s = concat_rows(ctx, mblocks, g->n, &M);
+    if (s == LNE_OK && host && H.rows != g->n)
+        s = fail(ctx, LNE_EINVAL, "host sparsifier: blocks cover %lld of %lld rows",
+                 (long long)H.rows, (long long)g->n);
     for (auto &b : mblocks) lne_csr_free(ctx, &b);
     if (s != LNE_OK) {
         lne_csr_free(ctx, &M);
@@ -946,7 +1139,11 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     const int32_t out_t = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
     Buf X0(ctx);
     s = alloc(ctx, X0, dtype_size(out_t) * (size_t)g->n * p->d);
-    if (s == LNE_OK) s = rsvd_impl(ctx, &M, p, nullptr, nullptr, nullptr, X0.p, st);
+    MatOp op;
+    op.M = host ? nullptr : &M;
+    op.H = host ? &H : nullptr;
+    op.n = g->n;
+    if (s == LNE_OK) s = rsvd_impl(ctx, op, p, nullptr, nullptr, nullptr, X0.p, st);
     lne_csr_free(ctx, &M);
     if (s != LNE_OK) return s;
     return propagate_impl(ctx, g, p, X0.p, X);
