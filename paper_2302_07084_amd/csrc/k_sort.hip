@@ -4,12 +4,13 @@
 // exact sum of its weights; here order-independent integer sums instead of a
 // lock-free hash, so the result is bit-identical for any launch shape).
 //
-// Radix pass (8-bit digit): per-tile digit histograms (digit-major table),
-// one device-wide scan of the table, then a scatter in which every tile ranks
-// its items stably (each wave ranks a contiguous quarter of the tile with
-// ballots per digit bit and its own digit counters in LDS; a block-wide
-// prefix then orders the waves), stages them in LDS in digit order and writes
-// each digit run contiguously.
+// Radix pass (8-bit digit): per-tile digit histograms (digit-major table,
+// full tiles read as 16-byte vectors), one device-wide scan of the table,
+// then a scatter in which every tile ranks its items stably (each wave ranks
+// a contiguous quarter of the tile with ballots per digit bit and its own
+// digit counters in LDS; a block-wide prefix then orders the waves), stages
+// them in LDS in digit order (keys, then values, through one buffer) and
+// writes each digit run contiguously.
 #include "common.hpp"
 
 namespace lne {
@@ -34,30 +35,48 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
 __global__ void __launch_bounds__(kT) k_hist(const uint64_t *__restrict__ keys, int64_t n,
                                              int shift, int64_t ntiles,
                                              uint32_t *__restrict__ hist) {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+    __shared__ uint32_t cnt[kWaves][256];   // per-wave counters, summed at the end
+    const int tid = threadIdx.x, wv = tid >> 6;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
     __syncthreads();
     const int64_t tile = xcd_tile(blockIdx.x, ntiles);
     const int64_t base = tile * kTile;
-#pragma unroll 4
-    for (int it = 0; it < kIt; ++it) {
-        const int64_t i = base + it * kT + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    if (base + kTile <= n) {
+        // a full tile: two keys per 16-byte load, all loads issued first
+        const uint4 *p = reinterpret_cast<const uint4 *>(keys + base);
+        uint4 v[kIt / 2];
+#pragma unroll
+        for (int j = 0; j < kIt / 2; ++j) v[j] = p[j * kT + tid];
+#pragma unroll
+        for (int j = 0; j < kIt / 2; ++j) {
+            const uint64_t k0 = (uint64_t)v[j].x | ((uint64_t)v[j].y << 32);
+            const uint64_t k1 = (uint64_t)v[j].z | ((uint64_t)v[j].w << 32);
+            atomicAdd(&cnt[wv][(k0 >> shift) & 255u], 1u);
+            atomicAdd(&cnt[wv][(k1 >> shift) & 255u], 1u);
+        }
+    } else {
+        for (int64_t i = base + tid; i < n; i += kT)
+            atomicAdd(&cnt[wv][(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * ntiles + tile] = cnt[threadIdx.x];
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += cnt[w][tid];
+    hist[(int64_t)tid * ntiles + tile] = c;
 }
 
 constexpr int kWaveItems = kIt * 64;   // contiguous items ranked by one wave
 
-__global__ void __launch_bounds__(kT) k_scatter(const uint64_t *__restrict__ kin,
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) k_scatter(const uint64_t *__restrict__ kin,
                                                 const uint32_t *__restrict__ vin, int64_t n,
                                                 int shift, int64_t ntiles,
                                                 const uint64_t *__restrict__ offs,
                                                 uint64_t *__restrict__ kout,
                                                 uint32_t *__restrict__ vout) {
-    __shared__ uint64_t skey[kTile];
-    __shared__ uint32_t sval[kTile];
+    // one staging buffer, used for the keys and then for the values, keeps
+    // the block at 40 KB of LDS: four blocks per CU
+    __shared__ uint64_t stage[kTile];
     __shared__ uint32_t wcnt[kWaves][256];   // per-wave digit counts, then offsets
     __shared__ uint32_t tpre[256];
     __shared__ uint64_t gbase[256];
@@ -137,20 +156,36 @@ __global__ void __launch_bounds__(kT) k_scatter(const uint64_t *__restrict__ kin
     for (int it = 0; it < kIt; ++it) {
         if (wbase + it * 64 + lane < n) {
             const uint32_t d = (uint32_t)(keys_r[it] >> shift) & 255u;
-            const uint32_t lp = wcnt[wv][d] + pos_r[it];
-            skey[lp] = keys_r[it];
-            sval[lp] = vals_r[it];
+            pos_r[it] += wcnt[wv][d];           // the item's place in the tile
+            stage[pos_r[it]] = keys_r[it];
         }
     }
     __syncthreads();
 
-    const int64_t cnt = min((int64_t)kTile, n - base);
-    for (int64_t p = tid; p < cnt; p += kT) {
-        const uint64_t key = skey[p];
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
-        const uint64_t g = gbase[d] + (uint64_t)(p - tpre[d]);
-        kout[g] = key;
-        vout[g] = sval[p];
+    // keys out in digit runs; each thread keeps the destinations of its
+    // places for the values
+    const int cnt = (int)min((int64_t)kTile, n - base);
+    uint64_t dst_r[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int p = it * kT + tid;
+        if (p < cnt) {
+            const uint64_t key = stage[p];
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            dst_r[it] = gbase[d] + (uint64_t)(p - (int)tpre[d]);
+            kout[dst_r[it]] = key;
+        }
+    }
+    __syncthreads();
+    uint32_t *sval = reinterpret_cast<uint32_t *>(stage);
+#pragma unroll
+    for (int it = 0; it < kIt; ++it)
+        if (wbase + it * 64 + lane < n) sval[pos_r[it]] = vals_r[it];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int p = it * kT + tid;
+        if (p < cnt) vout[dst_r[it]] = sval[p];
     }
 }
 
@@ -344,6 +379,8 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
                       int64_t n, int bits, int *which) {
     *which = 0;
     if (n <= 1) return LNE_OK;
+    if ((uintptr_t)k0 % 16 || (uintptr_t)k1 % 16)
+        return fail(ctx, LNE_EINVAL, "radix_sort: key buffers must be 16-byte aligned");
     const int64_t ntiles = ceil_div(n, kTile);
     Buf hist(ctx), offs(ctx);
     LNE_TRY(alloc(ctx, hist, sizeof(uint32_t) * (size_t)(256 * ntiles)));
