@@ -141,6 +141,7 @@ static void host_plan(const lne_params *p, int64_t n, int64_t n_arcs, SamplePlan
     pl.T = p->T;
     pl.wt = nullptr;
     pl.cw = nullptr;
+    pl.guide = nullptr;
     pl.ea = nullptr;
     if (m > 0) {
         pl.base = p->M / (uint64_t)m;
@@ -216,7 +217,7 @@ static double range_bytes(uint64_t entries) { return 36.0 * (double)entries; }
 
 struct Sampler {
     SamplePlan pl;
-    Buf eu, ev, wc, wo, ea, cw;
+    Buf eu, ev, wc, wo, ea, cw, guide;
     int64_t m = 0, nw = 0;
     uint64_t attempted = 0, accepted = 0;
 };
@@ -228,9 +229,11 @@ static lne_status sampler_edges(lne_ctx *ctx, const lne_graph *g, Sampler &S) {
     if (!g->weight) return LNE_OK;
     uint64_t vol = 0;
     LNE_TRY(weight_info(ctx, g, S.cw, &vol));
+    LNE_TRY(weight_guide(ctx, g, S.cw.as<uint64_t>(), S.guide));
     S.pl.wt = g->weight;
     S.pl.cw = S.cw.as<uint64_t>();
     S.pl.ea = S.ea.as<uint32_t>();
+    S.pl.guide = S.guide.as<uint32_t>();
     return LNE_OK;
 }
 

@@ -131,6 +131,7 @@ struct SamplePlan {
     const uint32_t *wt;   // arc weights A
     const uint64_t *cw;   // cw[k] = sum of wt[0..k), n_arcs + 1 entries
     const uint32_t *ea;   // weight of edge e (u < v arcs in CSR order)
+    const uint32_t *guide;  // guide table of each row (weight_guide)
 };
 
 lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
@@ -146,6 +147,13 @@ lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64
 // weights; EINVAL on a zero weight, EUNSUPPORTED when a weighted degree or vol
 // reaches 2^32.  Synchronises the stream.
 lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol);
+// Guide table of the weighted walk step (one uint32 per arc): for row x with
+// k arcs and weighted degree W, entry b (stored at rp[x] + b) is the local
+// index of the arc whose cumulative-weight slice holds ceil(b W / k).  A step
+// drawing t in [0, W) starts its scan at entry floor(t k / W), at or before
+// the arc that holds t, and passes about one slice on average (the guide
+// tables of Chen and Asau's cutpoint method).  cw from weight_info.
+lne_status weight_guide(lne_ctx *ctx, const lne_graph *g, const uint64_t *cw, Buf &guide);
 
 // Sparse-sign test matrix (LNE_FLAG_SPARSE_OMEGA): kSparseOmega signed
 // column entries per row, int16 sign (column + 1), one 16-byte vector per row.

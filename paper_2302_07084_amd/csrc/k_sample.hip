@@ -115,15 +115,14 @@ __device__ __forceinline__ int32_t walk_step(const SamplePlan &pl, const int64_t
         const uint32_t deg = (uint32_t)(pl.cw[end] - base);   // < 2^32 (validated)
         if (deg == 0) return x;
         const uint64_t t = base + (uint64_t)(z % deg);
-        // first arc k of the row with cw[k + 1] > t
-        int64_t lo = beg, hi = end - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (pl.cw[mid + 1] > t) hi = mid;
-            else lo = mid + 1;
-        }
-        inv += 1.0 / (double)pl.wt[lo];
-        return col[lo];
+        // the arc k of the row with cw[k] <= t < cw[k + 1]: from the guide
+        // entry of t's bucket forward
+        const uint64_t k = (uint64_t)(end - beg);
+        const uint64_t bkt = (t - base) * k / deg;
+        int64_t i = beg + (int64_t)min((uint64_t)pl.guide[beg + (int64_t)bkt], k - 1);
+        while (i < end - 1 && pl.cw[i + 1] <= t) ++i;
+        inv += 1.0 / (double)pl.wt[i];
+        return col[i];
     }
 }
 
@@ -545,6 +544,37 @@ __global__ void k_weight_check(const int64_t *__restrict__ rp, const uint32_t *_
     for (int64_t k = b + sub; k < e; k += kValLanes) f |= wt[k] == 0 ? 1u : 0u;
     if (sub == 0 && cw[e] - cw[b] >= (1ull << 32)) f |= 2;
     if (f) atomicOr(flags, f);
+}
+
+// 16 lanes per row, each lane the buckets of every 16th arc.  Bucket b's
+// value ceil(b W / k) lies in the slice [s, e) of the arcs with
+// B(s) <= b < B(e), B(s) = number of buckets whose value is below s =
+// floor((s - 1) k / W) + 1 (0 for s = 0); B(W) = k as weights are >= 1.
+__global__ void k_guide(const int64_t *__restrict__ rp, const uint64_t *__restrict__ cw,
+                        int64_t n, uint32_t *__restrict__ guide) {
+    const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kValLanes;
+    const int sub = threadIdx.x % kValLanes;
+    if (u >= n) return;
+    const int64_t b0 = rp[u], e0 = rp[u + 1];
+    const uint64_t k = (uint64_t)(e0 - b0);
+    if (k == 0) return;
+    const uint64_t base = cw[b0], W = cw[e0] - base;
+    for (int64_t i = sub; i < (int64_t)k; i += kValLanes) {
+        const uint64_t s = cw[b0 + i] - base, e = cw[b0 + i + 1] - base;
+        const uint64_t lo = s == 0 ? 0 : (s - 1) * k / W + 1;
+        const uint64_t hi = min((e - 1) * k / W + 1, k);
+        for (uint64_t b = lo; b < hi; ++b) guide[b0 + (int64_t)b] = (uint32_t)i;
+    }
+}
+
+lne_status weight_guide(lne_ctx *ctx, const lne_graph *g, const uint64_t *cw, Buf &guide) {
+    LNE_TRY(alloc(ctx, guide, sizeof(uint32_t) * (size_t)(g->n_arcs > 0 ? g->n_arcs : 1)));
+    if (g->n > 0) {
+        Launch L(ctx, "weight_guide");
+        k_guide<<<grid_of(g->n * kValLanes, 256), 256, 0, ctx->stream>>>(
+            g->row_ptr, cw, g->n, guide.as<uint32_t>());
+    }
+    return check_launch(ctx, "weight_guide");
 }
 
 lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol) {

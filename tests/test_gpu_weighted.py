@@ -53,6 +53,36 @@ def test_weighted_slots_bit_exact(lne, ctx, C):
     assert len(np.unique(ref["w"][acc])) > 3        # path-dependent weights
 
 
+def _skewed(g, seed):
+    """g with symmetric weights 2^j, j uniform in 0..20: slices of one row
+    differ by up to 2^20, so a guide bucket can hold many slices or a slice
+    many buckets."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    key = np.minimum(rows, g.col).astype(np.int64) * g.n + np.maximum(rows, g.col)
+    _, inv = np.unique(key, return_inverse=True)
+    w = (1 << rng.integers(0, 21, size=inv.max() + 1)).astype(np.uint32)[inv]
+    return type(g)(g.n, g.rowptr, g.col, g.labels, g.name + "-skew", w)
+
+
+@pytest.mark.parametrize("graph", ["star", "tiny"])
+def test_weighted_slots_skewed_weights_bit_exact(lne, ctx, graph):
+    """Walk steps by weight on rows whose slices span six orders of
+    magnitude (a 300-leaf star's hub, a planted-block graph)."""
+    g = gs.star(300) if graph == "star" else workload("tiny")[0]
+    g = _skewed(g, 9)
+    p = gs.params(T=6, s=[0.1, 0.2, 0.2, 0.2, 0.2, 0.1], M_per_m=20, C=None, m=g.m, seed=3)
+    rp, col = to_dev(g)
+    out = lne.sample_slots(ctx, rp, col, p, 0, g.m, weight=_dev_w(g))
+    S = out["S"]
+    ref = oracle.sample_slots(g, p)
+    e, j = ref["e"], ref["j"].astype(np.int64)
+    for key in ("a", "b", "r"):
+        np.testing.assert_array_equal(out[key].cpu().numpy().reshape(-1, S)[e, j], ref[key])
+    w = out["w"].cpu().numpy().view(np.uint64).reshape(-1, S)
+    np.testing.assert_array_equal(w[e, j], ref["w"])
+
+
 def test_weighted_counts_and_trunc_log(lne, ctx, wtiny):
     g, p = wtiny
     rp, col = to_dev(g)
