@@ -95,10 +95,11 @@ typedef struct {
 static void make_plan(int T, const double *s, uint64_t M, int64_t m, plan_t *pl)
 {
     pl->T = T;
-    pl->base = (uint64_t)(M / (uint64_t)m);
-    uint64_t rem = M % (uint64_t)m;
+    /* a graph without edges has no sample slots */
+    pl->base = m > 0 ? (uint64_t)(M / (uint64_t)m) : 0;
+    uint64_t rem = m > 0 ? M % (uint64_t)m : 0;
     /* frac(M/m) * 2^32 floored, exactly, in integers */
-    pl->frac_thr = (uint64_t)(((unsigned __int128)rem << 32) / (uint64_t)m);
+    pl->frac_thr = m > 0 ? (uint64_t)(((unsigned __int128)rem << 32) / (uint64_t)m) : 0;
     double total = 0.0;
     for (int t = 0; t < T; ++t) total += s[t];
     double cum = 0.0;

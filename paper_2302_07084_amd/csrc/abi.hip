@@ -1146,7 +1146,15 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     op.M = host ? nullptr : &M;
     op.H = host ? &H : nullptr;
     op.n = g->n;
-    if (s == LNE_OK) s = rsvd_impl(ctx, op, p, nullptr, nullptr, nullptr, X0.p, st);
+    // a sparsifier with no entry left is the zero matrix: every singular
+    // value is 0, so U S^1/2 = 0 whatever basis an SVD would return (the
+    // orthonormalisation of its all-zero products has no basis to find)
+    if (s == LNE_OK && tl.kept == 0) {
+        const hipError_t e = hipMemsetAsync(X0.p, 0, X0.bytes, ctx->stream);
+        if (e != hipSuccess) s = fail(ctx, LNE_EHIP, "embed: memset: %s", hipGetErrorString(e));
+    } else if (s == LNE_OK) {
+        s = rsvd_impl(ctx, op, p, nullptr, nullptr, nullptr, X0.p, st);
+    }
     lne_csr_free(ctx, &M);
     if (s != LNE_OK) return s;
     return propagate_impl(ctx, g, p, X0.p, X);

@@ -8,6 +8,7 @@ import scipy.sparse as sp
 
 import oracle
 from synth import workload
+from tests import graphs_small as gs
 from tests.conftest import to_dev
 
 pytestmark = pytest.mark.gpu
@@ -308,6 +309,28 @@ def test_embed_tiny_matches_oracle(lne, ctx, tiny):
     assert stats["nnz_log"] == st["M"].nnz
     assert principal_angle(X, st["X"]) < 1e-8
     assert procrustes_err(X, st["X"]) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_embed_degenerate_graphs_give_zero(lne, ctx, prec):
+    """No edges (no samples at all) and a sparsifier truncated to nothing
+    (K4,4 at b = 2): the zero matrix, whose embedding is exactly zero, as the
+    oracle's."""
+    g = gs.from_edges(60, [])
+    p = dict(gs.params(T=3, M_per_m=10, m=1), d=4, oversample=2, q=1, cheb_k=3, theta=0.5,
+             mu=0.2, precision=prec)
+    rp, col = to_dev(g)
+    X, st = lne.embed(ctx, rp, col, p)
+    assert st["accepted"] == 0 and st["nnz_log"] == 0
+    assert X.shape == (60, 4) and bool((X == 0).all())
+    k44 = gs.from_edges(8, [(i, j) for i in range(4) for j in range(4, 8)])
+    p = gs.params(T=1, s=[1.0], M_per_m=5, C=None, m=k44.m, b=2)
+    p.update(d=2, oversample=2, q=2, cheb_k=2, theta=0.5, mu=0.2, precision=prec)
+    rp, col = to_dev(k44)
+    X, st = lne.embed(ctx, rp, col, p)
+    assert st["accepted"] > 0 and st["nnz_log"] == 0
+    assert bool((X == 0).all())
+    assert np.all(oracle.embed(k44, p) == 0.0)
 
 
 def test_embed_keeps_few_dropped_pairs_as_explicit_zeros(lne, ctx):

@@ -166,3 +166,20 @@ def test_embed_pipeline_shapes_and_scale():
     assert sp.issparse(st["M"])
     # the sparsified matrix is symmetric
     assert abs(st["M"] - st["M"].T).max() == 0
+
+
+def test_degenerate_graphs_embed_to_zero():
+    """A graph without edges has no samples and an all-truncated sparsifier
+    (K4,4 at b = 2: every x_ab is exactly 1) is the zero matrix; its SVD has
+    only zero singular values, so the embedding U sqrt(S) and its
+    propagation are exactly zero (not NaN)."""
+    from tests import graphs_small as gs
+    g = gs.from_edges(60, [])
+    X = oracle.embed(g, dict(gs.params(T=3, M_per_m=10, m=1), d=4, oversample=2, q=1,
+                             cheb_k=3, theta=0.5, mu=0.2, precision="f64"))
+    assert X.shape == (60, 4) and np.all(X == 0.0)
+    k44 = gs.from_edges(8, [(i, j) for i in range(4) for j in range(4, 8)])
+    p = gs.params(T=1, s=[1.0], M_per_m=5, C=None, m=k44.m, b=2)
+    p.update(d=2, oversample=2, q=1, cheb_k=2, theta=0.5, mu=0.2, precision="f64")
+    st = oracle.embed(k44, p, return_stages=True)
+    assert st["M"].nnz == 0 and np.all(st["X"] == 0.0)
