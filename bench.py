@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--flags", type=int, default=0,
                     help="extra LNE_FLAG_* bits for the timed step (default 0: the paper's "
                          "method; 4 = sparse-sign test matrix, 2 = vanilla randomized SVD)")
+    ap.add_argument("--relabel", type=int, default=None,
+                    help="permute the workload's vertex ids with this seed first (the "
+                         "generators number vertices in degree order; real graphs do not)")
     ap.add_argument("--automl-trials", type=int, default=64)
     ap.add_argument("--pretrain-trials", type=int, default=64,
                     help="surrogate pretraining trials per family graph (8 graphs)")
@@ -160,6 +163,9 @@ def main():
     t0 = time.time()
     log(f"generating workload '{args.workload}'")
     g, p = workload(args.workload, device="cuda")
+    if args.relabel is not None:
+        from synth import relabel
+        g = relabel(g, args.relabel, device="cuda")
     if args.flags:
         p = dict(p, flags=int(p.get("flags", 0)) | args.flags)
     log(f"graph n={g.n} m={g.m} in {time.time() - t0:.1f}s; params T={p['T']} M={p['M']} "
@@ -235,10 +241,12 @@ def main():
                                f"M={p['M']} (4Tm), d={p['d']}, q={p['q']}, k={p['cheb_k']}",
                    "n": g.n, "m": g.m, "T": p["T"], "M": p["M"], "d": p["d"],
                    "oversample": p["oversample"], "q": p["q"], "precision": p["precision"],
-                   "flags": int(p.get("flags", 0)), "parallelism": "single GPU"},
+                   "flags": int(p.get("flags", 0)), "relabel": args.relabel,
+                   "parallelism": "single GPU"},
         "roofline": {"kernel": rl_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(rl_name),
+                     # the counters were taken on the generator's vertex order
+                     "traffic": measured_traffic(rl_name) if args.relabel is None else None,
                      "bytes_per_launch": nbytes, "avg_launch_ms": prof[rl_name]["avg_ms"]},
         "stats": stats,
         "sampler_edges_per_s": stats["accepted"] / (sampler_ms * 1e-3) if sampler_ms else None,

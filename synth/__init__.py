@@ -5,9 +5,9 @@ none of the embedding method's arithmetic: no sampling, aggregation, logarithm,
 factorisation or propagation.  Every function is a pure function of its seed.
 """
 from .graphs import (Graph, sbm, chung_lu, workload, dirichlet_s,
-                     trial_vectors, pair_weights, WORKLOADS)
+                     trial_vectors, pair_weights, relabel, WORKLOADS)
 from .links import holdout_edges, corrupt_destinations
 
 __all__ = ["Graph", "sbm", "chung_lu", "workload", "dirichlet_s",
-           "trial_vectors", "pair_weights", "WORKLOADS", "holdout_edges",
+           "trial_vectors", "pair_weights", "relabel", "WORKLOADS", "holdout_edges",
            "corrupt_destinations"]

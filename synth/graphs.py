@@ -268,6 +268,39 @@ def pair_weights(g: Graph, wmax: int, seed: int, device: str = "cpu") -> np.ndar
     return w.cpu().numpy().astype(np.uint32)
 
 
+def relabel(g: Graph, seed: int, device: str = "cpu") -> Graph:
+    """g with its vertex ids permuted by a seeded uniform permutation (rows,
+    columns, weights and labels alike; neighbour lists sorted again).  The
+    generators number vertices in a structured order (Chung-Lu: by expected
+    degree); real graphs carry arbitrary ids."""
+    torch = _torch()
+    n = g.n
+    gen = torch.Generator().manual_seed(seed)
+    perm = torch.randperm(n, generator=gen).to(device)          # new id of vertex v
+    rp = torch.from_numpy(np.asarray(g.rowptr, np.int64)).to(device)
+    rows = torch.repeat_interleave(torch.arange(n, device=device), rp[1:] - rp[:-1])
+    key = perm[rows] * n
+    del rows
+    key += perm[torch.from_numpy(np.asarray(g.col)).to(device).long()]
+    key, order = torch.sort(key)
+    new_rows = torch.div(key, n, rounding_mode="floor")
+    col = (key - new_rows * n).to(torch.int32).cpu().numpy()
+    del key
+    new_rp = np.zeros(n + 1, np.int64)
+    new_rp[1:] = torch.cumsum(torch.bincount(new_rows, minlength=n), 0).cpu().numpy()
+    del new_rows
+    weight = None
+    if g.weight is not None:
+        weight = torch.from_numpy(np.asarray(g.weight).astype(np.int64)).to(device)[order]
+        weight = weight.to(torch.int64).cpu().numpy().astype(np.uint32)
+    del order
+    labels = None
+    if g.labels is not None:
+        inv = torch.argsort(perm).cpu().numpy()                 # old id of new vertex i
+        labels = np.asarray(g.labels)[inv]
+    return Graph(n, new_rp, col, labels, g.name + f"-relabel{seed}", weight)
+
+
 def dirichlet_s(T: int, seed: int) -> np.ndarray:
     """Per-length weights s_1..s_T drawn from a flat Dirichlet(1)."""
     rng = np.random.Generator(np.random.PCG64(seed))

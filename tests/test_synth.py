@@ -60,3 +60,22 @@ def test_tiny_workload_matches_configuration():
     g, p = workload("tiny")
     assert g.n == 1000 and abs(g.m - 9675) < 6 * 90
     assert p["M"] == 100 * 10 * g.m and p["d"] == 32 and p["q"] == 1
+
+
+def test_relabel_is_an_isomorphism():
+    from synth import relabel
+    from tests import graphs_small as gs
+    g = gs.with_weights(workload("tiny")[0], 4)
+    h = relabel(g, 7)
+    assert h.n == g.n and h.n_arcs == g.n_arcs
+    # the permutation drawn from the same seed carries the weighted arcs of
+    # g exactly onto those of h
+    import torch
+    perm = torch.randperm(g.n, generator=torch.Generator().manual_seed(7)).numpy()
+    arcs = lambda gr: {(int(u), int(v), int(w)) for u in range(gr.n)
+                       for v, w in zip(gr.col[gr.rowptr[u]:gr.rowptr[u + 1]],
+                                       gr.weight[gr.rowptr[u]:gr.rowptr[u + 1]])}
+    assert {(perm[u], perm[v], w) for u, v, w in arcs(g)} == arcs(h)
+    for u in range(h.n):
+        assert np.all(np.diff(h.col[h.rowptr[u]:h.rowptr[u + 1]]) > 0)
+    assert np.array_equal(h.labels[perm], g.labels)
