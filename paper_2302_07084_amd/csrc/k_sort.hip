@@ -17,10 +17,15 @@ namespace lne {
 
 namespace {
 
-constexpr int kT = 256;              // threads per block
+constexpr int kT = 256;              // threads per block (heads, reductions)
 constexpr int kIt = 16;              // items per thread
 constexpr int kTile = kT * kIt;      // items per tile
 constexpr int kWaves = kT / 64;
+// Radix tiles are twice as large: a tile's run of one digit averages 32
+// items, so fewer of its cache lines are written in part.
+constexpr int kST = 512;             // threads per radix block
+constexpr int kSTile = kST * kIt;    // items per radix tile
+constexpr int kSWaves = kST / 64;
 
 // Tile of a histogram or scatter block.  Workgroups are dispatched to the 8
 // XCDs round robin, so block b runs on XCD b % 8; giving each XCD a
@@ -32,22 +37,21 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t ntiles) {
     return x * q + min(x, r) + i;
 }
 
-__global__ void __launch_bounds__(kT) k_hist(const uint64_t *__restrict__ keys, int64_t n,
-                                             int shift, int64_t ntiles,
-                                             uint32_t *__restrict__ hist) {
-    __shared__ uint32_t cnt[kWaves][256];   // per-wave counters, summed at the end
+__global__ void __launch_bounds__(kST) k_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                              int shift, int64_t ntiles,
+                                              uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[kSWaves][256];   // per-wave counters, summed at the end
     const int tid = threadIdx.x, wv = tid >> 6;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
+    for (int i = tid; i < kSWaves * 256; i += kST) cnt[i >> 8][i & 255] = 0;
     __syncthreads();
     const int64_t tile = xcd_tile(blockIdx.x, ntiles);
-    const int64_t base = tile * kTile;
-    if (base + kTile <= n) {
+    const int64_t base = tile * kSTile;
+    if (base + kSTile <= n) {
         // a full tile: two keys per 16-byte load, all loads issued first
         const uint4 *p = reinterpret_cast<const uint4 *>(keys + base);
         uint4 v[kIt / 2];
 #pragma unroll
-        for (int j = 0; j < kIt / 2; ++j) v[j] = p[j * kT + tid];
+        for (int j = 0; j < kIt / 2; ++j) v[j] = p[j * kST + tid];
 #pragma unroll
         for (int j = 0; j < kIt / 2; ++j) {
             const uint64_t k0 = (uint64_t)v[j].x | ((uint64_t)v[j].y << 32);
@@ -56,39 +60,38 @@ __global__ void __launch_bounds__(kT) k_hist(const uint64_t *__restrict__ keys, 
             atomicAdd(&cnt[wv][(k1 >> shift) & 255u], 1u);
         }
     } else {
-        for (int64_t i = base + tid; i < n; i += kT)
+        for (int64_t i = base + tid; i < n; i += kST)
             atomicAdd(&cnt[wv][(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    uint32_t c = 0;
+    if (tid < 256) {
+        uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) c += cnt[w][tid];
-    hist[(int64_t)tid * ntiles + tile] = c;
+        for (int w = 0; w < kSWaves; ++w) c += cnt[w][tid];
+        hist[(int64_t)tid * ntiles + tile] = c;
+    }
 }
 
 constexpr int kWaveItems = kIt * 64;   // contiguous items ranked by one wave
 
-__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) k_scatter(const uint64_t *__restrict__ kin,
-                                                const uint32_t *__restrict__ vin, int64_t n,
-                                                int shift, int64_t ntiles,
-                                                const uint64_t *__restrict__ offs,
-                                                uint64_t *__restrict__ kout,
-                                                uint32_t *__restrict__ vout) {
-    // one staging buffer, used for the keys and then for the values, keeps
-    // the block at 40 KB of LDS: four blocks per CU
-    __shared__ uint64_t stage[kTile];
-    __shared__ uint32_t wcnt[kWaves][256];   // per-wave digit counts, then offsets
+__global__ void __launch_bounds__(kST) __attribute__((amdgpu_waves_per_eu(4)))
+k_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
+          int shift, int64_t ntiles, const uint64_t *__restrict__ offs,
+          uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    // one staging buffer, used for the keys and then for the values (75 KB of
+    // LDS with the counters: two blocks, sixteen waves per CU)
+    __shared__ uint64_t stage[kSTile];
+    __shared__ uint32_t wcnt[kSWaves][256];   // per-wave digit counts, then offsets
     __shared__ uint32_t tpre[256];
     __shared__ uint64_t gbase[256];
-    __shared__ uint32_t wtot[kWaves];
+    __shared__ uint32_t wtot[4];               // digit totals of the 4 digit waves
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t tile = xcd_tile(blockIdx.x, ntiles);
-    const int64_t base = tile * kTile;
+    const int64_t base = tile * kSTile;
     const int64_t wbase = base + (int64_t)wv * kWaveItems;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-    gbase[tid] = offs[(int64_t)tid * ntiles + tile];
+    for (int i = tid; i < kSWaves * 256; i += kST) wcnt[i >> 8][i & 255] = 0;
+    if (tid < 256) gbase[tid] = offs[(int64_t)tid * ntiles + tile];
 
     // all of this thread's items are loaded before the ranking starts, so
     // the tile's loads are in flight together
@@ -127,25 +130,27 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) k_
     }
     __syncthreads();
 
-    // thread tid = digit: the tile's exclusive digit prefix and each wave's
-    // offset inside the digit's run
-    {
-        uint32_t c = 0;
+    // waves 0-3, thread tid = digit: the tile's exclusive digit prefix and
+    // each wave's offset inside the digit's run
+    uint32_t c = 0, inc = 0;
+    if (tid < 256) {
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) c += wcnt[w][tid];
-        uint32_t inc = c;
+        for (int w = 0; w < kSWaves; ++w) c += wcnt[w][tid];
+        inc = c;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(inc, off, 64);
             if (lane >= off) inc += y;
         }
         if (lane == 63) wtot[wv] = inc;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (tid < 256) {
         uint32_t run = inc - c;
         for (int i = 0; i < wv; ++i) run += wtot[i];
         tpre[tid] = run;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < kSWaves; ++w) {
             const uint32_t t = wcnt[w][tid];
             wcnt[w][tid] = run;
             run += t;
@@ -164,11 +169,11 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) k_
 
     // keys out in digit runs; each thread keeps the destinations of its
     // places for the values
-    const int cnt = (int)min((int64_t)kTile, n - base);
+    const int cnt = (int)min((int64_t)kSTile, n - base);
     uint64_t dst_r[kIt];
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
-        const int p = it * kT + tid;
+        const int p = it * kST + tid;
         if (p < cnt) {
             const uint64_t key = stage[p];
             const uint32_t d = (uint32_t)(key >> shift) & 255u;
@@ -184,7 +189,7 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4))) k_
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
-        const int p = it * kT + tid;
+        const int p = it * kST + tid;
         if (p < cnt) vout[dst_r[it]] = sval[p];
     }
 }
@@ -381,7 +386,7 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
     if (n <= 1) return LNE_OK;
     if ((uintptr_t)k0 % 16 || (uintptr_t)k1 % 16)
         return fail(ctx, LNE_EINVAL, "radix_sort: key buffers must be 16-byte aligned");
-    const int64_t ntiles = ceil_div(n, kTile);
+    const int64_t ntiles = ceil_div(n, kSTile);
     Buf hist(ctx), offs(ctx);
     LNE_TRY(alloc(ctx, hist, sizeof(uint32_t) * (size_t)(256 * ntiles)));
     LNE_TRY(alloc(ctx, offs, sizeof(uint64_t) * (size_t)(256 * ntiles + 1)));
@@ -391,14 +396,14 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
     for (int shift = 0; shift < bits; shift += 8) {
         {
             Launch L(ctx, "radix_hist");
-            k_hist<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(ks[cur], n, shift, ntiles,
-                                                             hist.as<uint32_t>());
+            k_hist<<<(unsigned)ntiles, kST, 0, ctx->stream>>>(ks[cur], n, shift, ntiles,
+                                                              hist.as<uint32_t>());
         }
         LNE_TRY(check_launch(ctx, "radix_hist"));
         LNE_TRY(scan_u32(ctx, hist.as<uint32_t>(), offs.as<uint64_t>(), 256 * ntiles));
         {
             Launch L(ctx, "radix_scatter");
-            k_scatter<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
+            k_scatter<<<(unsigned)ntiles, kST, 0, ctx->stream>>>(
                 ks[cur], vs[cur], n, shift, ntiles, offs.as<uint64_t>(), ks[cur ^ 1],
                 vs[cur ^ 1]);
         }
