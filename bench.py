@@ -198,7 +198,7 @@ def main():
     names = ["validate_graph", "row_up", "fill_edges", "sample_count", "fold_stats", "sample_emit", "scan",
              "radix_hist", "radix_scatter", "heads", "reduce", "degrees", "reduce_trunc_log", "drop_zeros",
              "rowptr_tail", "concat_rows", "trunc_log_count", "trunc_log_fill", "gaussian",
-             "sparse_omega", "spmm_sparse_omega", "weight_check",
+             "sparse_omega", "spmm_sparse_omega", "weight_check", "weight_guide",
              "spmm", "gram", "gram_reduce", "chol_inv", "project", "sym_eig", "eig_weights",
              "w_to_bf16", "graph_spmm", "dense_scale", "axpby"]
     prof = {}
@@ -370,7 +370,7 @@ def weighted_report(name, wmax=16, steps=2, seconds=15.0):
         dt = (time.perf_counter() - t0) / steps
         ker = {}
         for nm in ("sample_count", "sample_emit", "radix_scatter", "reduce_trunc_log", "spmm",
-                   "graph_spmm", "weight_check"):
+                   "graph_spmm", "weight_check", "weight_guide"):
             ms, cnt = ctx.prof_get(nm)
             if cnt:
                 ker[nm] = ms / steps
