@@ -285,13 +285,19 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
         LNE_TRY(launch_sample_emit(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), S.m, lo,
                                    hi, S.wo.as<uint64_t>(), k0.as<uint64_t>(), v0.as<uint32_t>()));
     int which = 0;
+    bool tagged = false;
     if (P > 1) {
         int rowbits = 0;
         while (((int64_t)1 << rowbits) < hi - lo) ++rowbits;
         LNE_TRY(alloc(ctx, k1, sizeof(uint64_t) * (size_t)P));
         LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)P));
+        // with the fused truncated log, the keys come out tagged with their
+        // column's degree (read while the pairs are in column order)
+        const int bits = rowbits + S.pl.colbits + S.pl.cbits;
+        tagged = tl && S.pl.cbits == 0 && radix_tag_shift(bits, S.pl.colbits) >= 0;
         LNE_TRY(radix_sort(ctx, k0.as<uint64_t>(), v0.as<uint32_t>(), k1.as<uint64_t>(),
-                           v1.as<uint32_t>(), P, rowbits + S.pl.colbits + S.pl.cbits, &which));
+                           v1.as<uint32_t>(), P, bits, &which, tagged ? tl->deg : nullptr,
+                           S.pl.colbits));
         // the other ping-pong pair is free before the CSR is allocated
         if (which) { k0.release(); v0.release(); } else { k1.release(); v1.release(); }
     }
@@ -300,7 +306,7 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
     if (tl) {
         uint64_t kept = 0;
         LNE_TRY(reduce_to_matrix(ctx, keys, vals, P, hi - lo, S.pl.colbits, g, tl->deg, lo,
-                                 tl->c, tl->val_type, out, &kept));
+                                 tl->c, tl->val_type, out, &kept, tagged));
         tl->kept += kept;
         return LNE_OK;
     }

@@ -189,8 +189,25 @@ lne_status launch_gaussian(lne_ctx *ctx, int64_t n, int32_t k, int64_t ld, uint6
 // ---- aggregation (k_sort.hip) ----------------------------------------------
 // Sorts (key, val) by the low `bits` bits of key (stable LSD radix), ping-pong
 // between the two buffer pairs; returns in *which (0 or 1) the sorted copy.
+// With tag_deg (and bits <= kTagShift) the keys come out tagged: bits 48..63
+// of each key hold deg[key & (2^colbits - 1)] of its column vertex, or
+// kTagMax when that degree is kTagMax or more.  The tag is written by the
+// first pass whose input is sorted by the column bits, so the degree reads of
+// a tile stay within a short column range (cache hits instead of random
+// gathers); equal keys stay equal and the sort bits are untouched.
+constexpr int kTagShift = 48;
+constexpr uint32_t kTagMax = 0xFFFFu;
+// Shift of the tagging pass for a sort over `bits` key bits of which the low
+// `colbits` are the column, or -1 when no pass qualifies (then no tags).
+inline int radix_tag_shift(int bits, int colbits) {
+    if (bits > kTagShift) return -1;
+    for (int shift = 0; shift < bits; shift += 8)
+        if (shift >= colbits) return shift;
+    return -1;
+}
 lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1,
-                      uint32_t *v1, int64_t n, int bits, int *which);
+                      uint32_t *v1, int64_t n, int bits, int *which,
+                      const uint32_t *tag_deg = nullptr, int colbits = 0);
 // Sorted (key, val) -> count CSR (rows, cols from the packed key).
 lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                          int64_t n_items, int64_t n_rows, int colbits, lne_csr *out);
@@ -226,11 +243,14 @@ __device__ __forceinline__ bool tl_keep(const TLConst &c, uint64_t W, uint64_t d
 // holds its first item, its Eq. (1) entry is ln x if kept, else an explicit
 // zero.  Rows are [row_lo, row_lo + n_rows) of the graph, deg its degrees
 // (vertex_degrees).  *kept (host) = the
-// number of nonzero entries.  val_type LNE_F64 or LNE_F32.
+// number of nonzero entries.  val_type LNE_F64 or LNE_F32.  tagged: the keys
+// carry radix_sort's degree tags (a tag below kTagMax is the column's degree;
+// kTagMax means look it up in deg).
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                             int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
-                            int32_t val_type, lne_csr *out, uint64_t *kept);
+                            int32_t val_type, lne_csr *out, uint64_t *kept,
+                            bool tagged = false);
 // deg[i] = degree of vertex i (uint32, n entries): the compact degree table
 // the fused reduction gathers from; with cw (weight_info) the weighted degree.
 lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg,

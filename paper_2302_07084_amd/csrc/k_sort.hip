@@ -74,10 +74,12 @@ __global__ void __launch_bounds__(kST) k_hist(const uint64_t *__restrict__ keys,
 
 constexpr int kWaveItems = kIt * 64;   // contiguous items ranked by one wave
 
+template <bool TAG>
 __global__ void __launch_bounds__(kST) __attribute__((amdgpu_waves_per_eu(4)))
 k_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, int64_t n,
           int shift, int64_t ntiles, const uint64_t *__restrict__ offs,
-          uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+          uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+          const uint32_t *__restrict__ tag_deg, uint64_t colmask) {
     // one staging buffer, used for the keys and then for the values (75 KB of
     // LDS with the counters: two blocks, sixteen waves per CU)
     __shared__ uint64_t stage[kSTile];
@@ -102,6 +104,16 @@ k_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, in
         const int64_t i = wbase + it * 64 + lane;
         keys_r[it] = i < n ? kin[i] : 0ull;
         vals_r[it] = i < n ? vin[i] : 0u;
+    }
+    if constexpr (TAG) {
+        // this pass's input is sorted by column: the tile's degree reads
+        // fall in a short range of the table
+#pragma unroll
+        for (int it = 0; it < kIt; ++it)
+            if (wbase + it * 64 + lane < n) {
+                const uint32_t d = tag_deg[keys_r[it] & colmask];
+                keys_r[it] |= (uint64_t)min(d, kTagMax) << kTagShift;
+            }
     }
     __syncthreads();
 
@@ -299,11 +311,13 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
                                                   int64_t row_lo, TLConst c,
                                                   int32_t *__restrict__ col, VT *__restrict__ val,
                                                   int64_t *__restrict__ rowptr,
-                                                  unsigned long long *__restrict__ kept) {
+                                                  uint32_t *__restrict__ block_kept,
+                                                  bool tagged) {
     __shared__ uint32_t wh[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const uint64_t colmask = (1ull << colbits) - 1;
+    const uint64_t keymask = tagged ? (1ull << kTagShift) - 1 : ~0ull;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint64_t running = head_off[blockIdx.x];
     uint32_t my_kept = 0;
@@ -339,8 +353,8 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         const uint64_t nu = __shfl_down(u, 1, 64);
         if (!valid) continue;
         if (head) {
-            const int64_t row = (int64_t)(key >> colbits);
-            const int64_t prow = i == 0 ? -1 : (int64_t)(prev >> colbits);
+            const int64_t row = (int64_t)((key & keymask) >> colbits);
+            const int64_t prow = i == 0 ? -1 : (int64_t)((prev & keymask) >> colbits);
             for (int64_t r = prow + 1; r <= row; ++r) rowptr[r] = (int64_t)u;
         }
         const bool started_here = (hm & (lt | (1ull << lane))) != 0;
@@ -350,17 +364,26 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         if (lane == 63)
             for (int64_t j = i + 1; j < n && keys[j] == key; ++j) W += vals[j];
         const int32_t b = (int32_t)(key & colmask);
-        const int64_t row = (int64_t)(key >> colbits);
+        const int64_t row = (int64_t)((key & keymask) >> colbits);
         const uint64_t da = deg[row_lo + row];
-        const uint64_t db = deg[b];
+        const uint32_t tag = tagged ? (uint32_t)(key >> kTagShift) : kTagMax;
+        const uint64_t db = tag < kTagMax ? tag : deg[b];
         const bool k = tl_keep(c, W, da, db);
         col[u] = b;
         val[u] = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
         my_kept += k ? 1u : 0u;
     }
+    // the block's count of kept entries (summed by a scan afterwards: one
+    // counter hit by every wave serialises the whole grid on it)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_kept += __shfl_xor(my_kept, off, 64);
-    if (lane == 0 && my_kept) atomicAdd(kept, (unsigned long long)my_kept);
+    if (lane == 0) wh[wv] = my_kept;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWaves; ++w) t += wh[w];
+        block_kept[blockIdx.x] = t;
+    }
 }
 
 __global__ void k_degrees(const int64_t *__restrict__ rp, const uint64_t *__restrict__ cw,
@@ -371,17 +394,19 @@ __global__ void k_degrees(const int64_t *__restrict__ rp, const uint64_t *__rest
 
 __global__ void k_rowptr_tail(const uint64_t *__restrict__ keys, int64_t n_items,
                               int colbits, const uint64_t *__restrict__ nnz_p,
-                              int64_t n_rows, int64_t *__restrict__ rowptr) {
+                              int64_t n_rows, int64_t *__restrict__ rowptr,
+                              uint64_t keymask) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > n_rows) return;
-    const int64_t last = n_items > 0 ? (int64_t)(keys[n_items - 1] >> colbits) : -1;
+    const int64_t last =
+        n_items > 0 ? (int64_t)((keys[n_items - 1] & keymask) >> colbits) : -1;
     if (r > last) rowptr[r] = (int64_t)*nnz_p;
 }
 
 }  // namespace
 
 lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
-                      int64_t n, int bits, int *which) {
+                      int64_t n, int bits, int *which, const uint32_t *tag_deg, int colbits) {
     *which = 0;
     if (n <= 1) return LNE_OK;
     if ((uintptr_t)k0 % 16 || (uintptr_t)k1 % 16)
@@ -393,6 +418,9 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
     uint64_t *ks[2] = {k0, k1};
     uint32_t *vs[2] = {v0, v1};
     int cur = 0;
+    // the tagging pass: the first whose input is sorted by the column bits
+    const int tag_shift = tag_deg ? radix_tag_shift(bits, colbits) : -1;
+    const uint64_t colmask = (1ull << colbits) - 1;
     for (int shift = 0; shift < bits; shift += 8) {
         {
             Launch L(ctx, "radix_hist");
@@ -403,9 +431,14 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
         LNE_TRY(scan_u32(ctx, hist.as<uint32_t>(), offs.as<uint64_t>(), 256 * ntiles));
         {
             Launch L(ctx, "radix_scatter");
-            k_scatter<<<(unsigned)ntiles, kST, 0, ctx->stream>>>(
-                ks[cur], vs[cur], n, shift, ntiles, offs.as<uint64_t>(), ks[cur ^ 1],
-                vs[cur ^ 1]);
+            if (shift == tag_shift)
+                k_scatter<true><<<(unsigned)ntiles, kST, 0, ctx->stream>>>(
+                    ks[cur], vs[cur], n, shift, ntiles, offs.as<uint64_t>(), ks[cur ^ 1],
+                    vs[cur ^ 1], tag_deg, colmask);
+            else
+                k_scatter<false><<<(unsigned)ntiles, kST, 0, ctx->stream>>>(
+                    ks[cur], vs[cur], n, shift, ntiles, offs.as<uint64_t>(), ks[cur ^ 1],
+                    vs[cur ^ 1], nullptr, colmask);
         }
         LNE_TRY(check_launch(ctx, "radix_scatter"));
         cur ^= 1;
@@ -447,7 +480,8 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
     {
         Launch L(ctx, "rowptr_tail");
         k_rowptr_tail<<<grid_of(n_rows + 1, 256), 256, 0, ctx->stream>>>(
-            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>());
+            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>(),
+            ~0ull);
     }
     LNE_TRY(check_launch(ctx, "rowptr_tail"));
     out->n_rows = n_rows;
@@ -471,15 +505,15 @@ lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg, const
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                             int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
-                            int32_t val_type, lne_csr *out, uint64_t *kept) {
+                            int32_t val_type, lne_csr *out, uint64_t *kept, bool tagged) {
     if (val_type != LNE_F32 && val_type != LNE_F64)
         return fail(ctx, LNE_EINVAL, "reduce_to_matrix: F32 or F64 values");
     const int64_t ntiles = ceil_div(n_items > 0 ? n_items : 1, kTile);
-    Buf th(ctx), hoff(ctx), kc(ctx);
+    Buf th(ctx), hoff(ctx), bk(ctx), bko(ctx);
     LNE_TRY(alloc(ctx, th, sizeof(uint32_t) * (size_t)ntiles));
     LNE_TRY(alloc(ctx, hoff, sizeof(uint64_t) * (size_t)(ntiles + 1)));
-    LNE_TRY(alloc(ctx, kc, sizeof(unsigned long long)));
-    LNE_HIP(ctx, hipMemsetAsync(kc.p, 0, sizeof(unsigned long long), ctx->stream));
+    LNE_TRY(alloc(ctx, bk, sizeof(uint32_t) * (size_t)ntiles));
+    LNE_TRY(alloc(ctx, bko, sizeof(uint64_t) * (size_t)(ntiles + 1)));
     {
         Launch L(ctx, "heads");
         k_heads<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(keys, n_items, th.as<uint32_t>());
@@ -499,24 +533,28 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
         if (val_type == LNE_F64)
             k_reduce_tl<double><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
                 keys, vals, n_items, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
-                cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(),
-                kc.as<unsigned long long>());
+                cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged);
         else
             k_reduce_tl<float><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
                 keys, vals, n_items, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
-                cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), kc.as<unsigned long long>());
+                cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged);
     }
     LNE_TRY(check_launch(ctx, "reduce_trunc_log"));
     {
         Launch L(ctx, "rowptr_tail");
         k_rowptr_tail<<<grid_of(n_rows + 1, 256), 256, 0, ctx->stream>>>(
-            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>());
+            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>(),
+            tagged ? (1ull << kTagShift) - 1 : ~0ull);
     }
     LNE_TRY(check_launch(ctx, "rowptr_tail"));
-    unsigned long long k = 0;
-    LNE_HIP(ctx, hipMemcpyAsync(&k, kc.p, sizeof(k), hipMemcpyDeviceToHost, ctx->stream));
-    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    *kept = (uint64_t)k;
+    uint64_t k = 0;
+    if (n_items > 0) {
+        LNE_TRY(scan_u32(ctx, bk.as<uint32_t>(), bko.as<uint64_t>(), ntiles));
+        LNE_HIP(ctx, hipMemcpyAsync(&k, bko.as<uint64_t>() + ntiles, sizeof(k),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    *kept = k;
     out->n_rows = n_rows;
     out->n_cols = g->n;
     out->nnz = (int64_t)nnz;
