@@ -229,6 +229,19 @@ lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *g, const lne_params 
 lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                          const lne_csr *counts, lne_csr *out);
 
+/* The truncated-log matrix exactly as lne_embed builds it (section 5.2's
+ * sparsifier with Eq. (1) applied while the pairs are aggregated; no count
+ * matrix is stored).  Same entries and values as lne_trunc_log of
+ * lne_sparsify, except that a row block keeps its dropped pairs as explicit
+ * zeros unless they are more than 1/32 of its entries.  out: n x n, row
+ * offsets from 0, columns ascending, values double (precision LNE_F64) or
+ * float (LNE_F32, LNE_BF16); free with lne_csr_free.  stats: attempted,
+ * accepted, nnz_log = the nonzero entries.  LNE_FLAG_HOST_SPARSIFIER is
+ * ignored (the result is in device memory).  Errors: EINVAL, ENOMEM,
+ * EUNSUPPORTED (weighted degrees or vol of 2^32 or more), EHIP. */
+lne_status lne_sparsify_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            lne_csr *out, lne_stats *st);
+
 /* Copies a library CSR into caller device buffers (row_ptr: n_rows + 1,
  * col: nnz, val: nnz elements of val_type).  Errors: EINVAL. */
 lne_status lne_csr_copy(lne_ctx *ctx, const lne_csr *m, int64_t *row_ptr,

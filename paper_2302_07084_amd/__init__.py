@@ -98,6 +98,7 @@ SIGNATURES = [
     ("lne_sample_slots", _I32, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P]),
     ("lne_sparsify", _I32, [_P, _P, _P, _P, _P]),
     ("lne_trunc_log", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_sparsify_log", _I32, [_P, _P, _P, _P, _P]),
     ("lne_csr_copy", _I32, [_P, _P, _P, _P, _P]),
     ("lne_csr_free", None, [_P, _P]),
     ("lne_spmm", _I32, [_P, _P, _P, _I64, _P, _I64, _I32, _I32]),
@@ -408,6 +409,17 @@ def trunc_log(ctx: Context, rowptr, col, params: dict, counts: Csr, weight=None)
     ctx.check(ctx.L.lne_trunc_log(ctx.h, ctypes.byref(g), ctypes.byref(p), ctypes.byref(counts.s),
                                   ctypes.byref(out.s)), "trunc_log")
     return out
+
+
+def sparsify_log(ctx: Context, rowptr, col, params: dict, weight=None):
+    """The truncated-log matrix as the embedding builds it (lne_sparsify_log)."""
+    g = graph_struct(rowptr, col, weight)
+    p = make_params(params)
+    out = Csr(ctx)
+    st = Stats()
+    ctx.check(ctx.L.lne_sparsify_log(ctx.h, ctypes.byref(g), ctypes.byref(p),
+                                     ctypes.byref(out.s), ctypes.byref(st)), "sparsify_log")
+    return out, st.as_dict()
 
 
 def spmm(ctx: Context, A: Csr, X):

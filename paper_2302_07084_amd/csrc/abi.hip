@@ -765,6 +765,57 @@ static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_par
     return project(ctx, Z, dt, ld, n, d, W.as<double>(), d, X, dt, d, nullptr);
 }
 
+// The embedding's sparsifier: the aggregation writes Eq. (1)'s matrix
+// directly (no count CSR); a row block keeps its dropped pairs as explicit
+// zeros unless they are more than 1/32 of its entries, in which case it is
+// compacted (the same decision with M in HBM or in host memory, so that both
+// give the same products).  In HBM the blocks are concatenated into *M; with
+// host they move to pinned host memory (H) as they are built.  *kept = the
+// number of nonzero entries (st->nnz_log too).
+static lne_status embed_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                               lne_stats *st, bool host, lne_csr *M, HostMatrix &H,
+                               uint64_t *kept_out) {
+    TruncLogFuse tl;
+    uint64_t vol = (uint64_t)g->n_arcs;
+    Buf cw(ctx);
+    if (g->weight) LNE_TRY(weight_info(ctx, g, cw, &vol));
+    tl.c = tl_const(vol, (uint64_t)g->n_arcs, p);
+    tl.val_type = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
+    Buf deg(ctx);
+    LNE_TRY(alloc(ctx, deg, sizeof(uint32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+    LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>(), g->weight ? cw.as<uint64_t>() : nullptr));
+    tl.deg = deg.as<uint32_t>();
+    std::vector<lne_csr> mblocks;
+    uint64_t kept_before = 0;
+    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
+        const uint64_t kept = tl.kept - kept_before;
+        kept_before = tl.kept;
+        lne_status r = LNE_OK;
+        if ((uint64_t)blk.nnz - kept > (uint64_t)blk.nnz / 32) r = drop_zeros(ctx, &blk);
+        if (r == LNE_OK && host) r = block_to_host(ctx, blk, H);
+        if (r != LNE_OK) {
+            lne_csr_free(ctx, &blk);
+            return r;
+        }
+        if (!host) mblocks.push_back(blk);
+        return LNE_OK;
+    };
+    LNE_TRY(validate_graph_device(ctx, g));
+    lne_status s = sparsify_impl(ctx, g, p, st, sink, false, &tl);
+    if (s == LNE_OK && !host) s = concat_rows(ctx, mblocks, g->n, M);
+    if (s == LNE_OK && host && H.rows != g->n)
+        s = fail(ctx, LNE_EINVAL, "host sparsifier: blocks cover %lld of %lld rows",
+                 (long long)H.rows, (long long)g->n);
+    for (auto &b : mblocks) lne_csr_free(ctx, &b);
+    if (s != LNE_OK) {
+        lne_csr_free(ctx, M);
+        return s;
+    }
+    if (st) st->nnz_log = tl.kept;
+    *kept_out = tl.kept;
+    return LNE_OK;
+}
+
 // The channel sampling pass of the batched trials: the sparsifier with the
 // walk length r kept in the key (column b << 4 | r - 1), as one CSR.
 lne_status channels_pass(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
@@ -1091,6 +1142,21 @@ lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p, 
     return propagate_impl(ctx, g, p, X0, X);
 }
 
+lne_status lne_sparsify_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+                            lne_csr *out, lne_stats *st) {
+    if (!ctx) return LNE_EINVAL;
+    if (!out) return fail(ctx, LNE_EINVAL, "sparsify_log: out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    if (p->precision < LNE_F64 || p->precision > LNE_BF16)
+        return fail(ctx, LNE_EINVAL, "precision must be LNE_F64, LNE_F32 or LNE_BF16");
+    if (st) std::memset(st, 0, sizeof(*st));
+    HostMatrix H;
+    uint64_t kept = 0;
+    return embed_matrix(ctx, g, p, st, false, out, H, &kept);
+}
+
 lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void *X,
                      lne_stats *st) {
     if (!ctx) return LNE_EINVAL;
@@ -1098,53 +1164,13 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
     if (!X) return fail(ctx, LNE_EINVAL, "embed: X is NULL");
     if (st) std::memset(st, 0, sizeof(*st));
-    // the aggregation writes Eq. (1)'s matrix directly (no count CSR); a
-    // block keeps its dropped pairs as explicit zeros unless they are more
-    // than 1/32 of its entries, in which case it is compacted
-    TruncLogFuse tl;
-    uint64_t vol = (uint64_t)g->n_arcs;
-    Buf cw(ctx);
-    if (g->weight) LNE_TRY(weight_info(ctx, g, cw, &vol));
-    tl.c = tl_const(vol, (uint64_t)g->n_arcs, p);
-    tl.val_type = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
-    Buf deg(ctx);
-    LNE_TRY(alloc(ctx, deg, sizeof(uint32_t) * (size_t)(g->n > 0 ? g->n : 1)));
-    LNE_TRY(vertex_degrees(ctx, g, deg.as<uint32_t>(), g->weight ? cw.as<uint64_t>() : nullptr));
-    tl.deg = deg.as<uint32_t>();
-    std::vector<lne_csr> mblocks;
-    const bool host = (p->flags & LNE_FLAG_HOST_SPARSIFIER) != 0;
-    HostMatrix H;
-    uint64_t kept_before = 0;
-    // A block is compacted when more than 1/32 of its entries were dropped
-    // (the same decision with M in HBM or in host memory, so that both give
-    // the same products); in host mode it then moves to pinned host memory.
-    auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
-        const uint64_t kept = tl.kept - kept_before;
-        kept_before = tl.kept;
-        lne_status r = LNE_OK;
-        if ((uint64_t)blk.nnz - kept > (uint64_t)blk.nnz / 32) r = drop_zeros(ctx, &blk);
-        if (r == LNE_OK && host) r = block_to_host(ctx, blk, H);
-        if (r != LNE_OK) {
-            lne_csr_free(ctx, &blk);
-            return r;
-        }
-        if (!host) mblocks.push_back(blk);
-        return LNE_OK;
-    };
     lne_csr M;
     std::memset(&M, 0, sizeof(M));
-    LNE_TRY(validate_graph_device(ctx, g));
-    lne_status s = sparsify_impl(ctx, g, p, st, sink, false, &tl);
-    if (s == LNE_OK && !host) s = concat_rows(ctx, mblocks, g->n, &M);
-    if (s == LNE_OK && host && H.rows != g->n)
-        s = fail(ctx, LNE_EINVAL, "host sparsifier: blocks cover %lld of %lld rows",
-                 (long long)H.rows, (long long)g->n);
-    for (auto &b : mblocks) lne_csr_free(ctx, &b);
-    if (s != LNE_OK) {
-        lne_csr_free(ctx, &M);
-        return s;
-    }
-    if (st) st->nnz_log = tl.kept;
+    const bool host = (p->flags & LNE_FLAG_HOST_SPARSIFIER) != 0;
+    HostMatrix H;
+    uint64_t kept = 0;
+    LNE_TRY(embed_matrix(ctx, g, p, st, host, &M, H, &kept));
+    lne_status s = LNE_OK;
     const int32_t out_t = p->precision == LNE_F64 ? LNE_F64 : LNE_F32;
     Buf X0(ctx);
     s = alloc(ctx, X0, dtype_size(out_t) * (size_t)g->n * p->d);
@@ -1155,7 +1181,7 @@ lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void
     // a sparsifier with no entry left is the zero matrix: every singular
     // value is 0, so U S^1/2 = 0 whatever basis an SVD would return (the
     // orthonormalisation of its all-zero products has no basis to find)
-    if (s == LNE_OK && tl.kept == 0) {
+    if (s == LNE_OK && kept == 0) {
         const hipError_t e = hipMemsetAsync(X0.p, 0, X0.bytes, ctx->stream);
         if (e != hipSuccess) s = fail(ctx, LNE_EHIP, "embed: memset: %s", hipGetErrorString(e));
     } else if (s == LNE_OK) {

@@ -59,13 +59,17 @@ def _graph(n=10, n_arcs=20):
     return g
 
 
-@pytest.mark.parametrize("field,value", [("T", 0), ("T", 17), ("b", 0), ("M", 1 << 40)])
-def test_sparsify_rejects_bad_params(lne, field, value):
+@pytest.mark.parametrize("entry", ["lne_sparsify", "lne_sparsify_log"])
+@pytest.mark.parametrize("field,value", [("T", 0), ("T", 17), ("b", 0), ("M", 1 << 40),
+                                         ("precision", 7)])
+def test_sparsify_rejects_bad_params(lne, entry, field, value):
+    if entry == "lne_sparsify" and field == "precision":
+        pytest.skip("the count matrix has no precision")
     L, h = _ctx(lne)
     p = lne.make_params(gs.params(T=3, m=10))
     setattr(p, field, value)
     out = lne.CsrStruct()
-    rc = L.lne_sparsify(h, ctypes.byref(_graph()), ctypes.byref(p), ctypes.byref(out), None)
+    rc = getattr(L, entry)(h, ctypes.byref(_graph()), ctypes.byref(p), ctypes.byref(out), None)
     assert rc == -1
     assert L.lne_last_error(h)
     L.lne_ctx_destroy(h)

@@ -82,3 +82,27 @@ def test_first_rsvd_product_rows_at_full_size(lne, ctx, large):
             ref = v @ O
             bar = 4 * math.sqrt(max(int(k.sum()), 1)) * 2.0 ** -24 * (np.abs(v) @ np.abs(O)) + 1e-30
             assert np.all(np.abs(yd[r] - ref) <= bar), (lo + r, np.max(np.abs(yd[r] - ref) / bar))
+
+
+def test_embedding_matrix_rows_at_full_size(lne, ctx, large):
+    """The matrix lne_embed factorises, built as the benchmark builds it
+    (Eq. (1) fused into the aggregation, column degrees carried in the sort
+    keys): on the windows its kept set is the oracle's and its FP32 values are
+    the oracle's FP64 ln x rounded (within one FP32 ulp)."""
+    g, p, rp, col, refs = large
+    M, st = lne.sparsify_log(ctx, rp, col, p)
+    Rd, Cd, Vd = M.to_torch()
+    for (lo, hi), (R0, C0, W0) in refs.items():
+        keep, val = oracle.trunc_log(g, p, R0, C0, W0, row_lo=lo)
+        a, b = int(Rd[lo].item()), int(Rd[hi].item())
+        R = (Rd[lo:hi + 1] - a).cpu().numpy()
+        C = Cd[a:b].cpu().numpy()
+        V = Vd[a:b].double().cpu().numpy()
+        nz = V != 0
+        rows = np.repeat(np.arange(hi - lo), np.diff(R))
+        rows0 = np.repeat(np.arange(hi - lo), np.diff(R0))
+        np.testing.assert_array_equal(rows[nz], rows0[keep])
+        np.testing.assert_array_equal(C[nz], C0[keep])
+        ref = val[keep]
+        assert np.all(np.abs(V[nz] - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-30)
+    M.free()

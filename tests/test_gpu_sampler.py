@@ -138,3 +138,59 @@ def test_row_range_passes_match_single_pass(lne, ctx, monkeypatch):
     assert st == st_ref
     X, _ = lne.embed(ctx, rp, col, p)
     assert bool((X == Xref).all())
+
+
+def _compact(R, C, V):
+    """Drop explicit zeros from a CSR (numpy)."""
+    keep = V != 0
+    rows = np.repeat(np.arange(len(R) - 1), np.diff(R))
+    R2 = np.zeros_like(R)
+    np.add.at(R2, rows[keep] + 1, 1)
+    return np.cumsum(R2), C[keep], V[keep]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("budget", [None, "0.05"])
+def test_embedding_matrix_equals_trunc_log_of_counts(lne, ctx, monkeypatch, prec, budget):
+    """The matrix the embedding factorises (Eq. (1) fused into the aggregation,
+    degrees carried in the sort keys) equals lne_trunc_log of the count matrix
+    entry for entry, explicit zeros aside; in one block and in row ranges."""
+    g, p = workload("tiny")
+    p = dict(p, precision=prec)
+    rp, col = to_dev(g)
+    if budget:
+        monkeypatch.setenv("LNE_HBM_BUDGET_GB", budget)
+    counts, st0 = lne.sparsify(ctx, rp, col, p)
+    M0 = lne.trunc_log(ctx, rp, col, p, counts)
+    R0, C0, V0 = (x.cpu().numpy() for x in M0.to_torch())
+    M1, st1 = lne.sparsify_log(ctx, rp, col, p)
+    R1, C1, V1 = _compact(*(x.cpu().numpy() for x in M1.to_torch()))
+    assert st1["nnz_log"] == M0.nnz and st1["accepted"] == st0["accepted"]
+    np.testing.assert_array_equal(R1, R0)
+    np.testing.assert_array_equal(C1, C0)
+    np.testing.assert_array_equal(V1, V0)
+
+
+def test_embedding_matrix_weighted_and_hub(lne, ctx):
+    """Weighted degrees in the keys' tags, and a hub whose degree (70,000)
+    does not fit a tag: looked up instead."""
+    from tests.test_gpu_weighted import _dev_w
+    g, p = workload("tiny")
+    gw = gs.with_weights(g, 5)
+    rp, col = to_dev(gw)
+    counts, _ = lne.sparsify(ctx, rp, col, p, weight=_dev_w(gw))
+    M0 = lne.trunc_log(ctx, rp, col, p, counts, weight=_dev_w(gw))
+    M1, _ = lne.sparsify_log(ctx, rp, col, p, weight=_dev_w(gw))
+    for a, b in zip((x.cpu().numpy() for x in M0.to_torch()),
+                    _compact(*(x.cpu().numpy() for x in M1.to_torch()))):
+        np.testing.assert_array_equal(a, b)
+    hub = gs.star(70_001)
+    ph = gs.params(T=2, s=[0.5, 0.5], M_per_m=4, C=None, m=hub.m, seed=2)
+    rp, col = to_dev(hub)
+    counts, _ = lne.sparsify(ctx, rp, col, ph)
+    M0 = lne.trunc_log(ctx, rp, col, ph, counts)
+    M1, _ = lne.sparsify_log(ctx, rp, col, ph)
+    assert M0.nnz > 0
+    for a, b in zip((x.cpu().numpy() for x in M0.to_torch()),
+                    _compact(*(x.cpu().numpy() for x in M1.to_torch()))):
+        np.testing.assert_array_equal(a, b)
