@@ -297,53 +297,87 @@ __global__ void __launch_bounds__(kT) k_reduce(const uint64_t *__restrict__ keys
     }
 }
 
-// Segmented sum fused with Eq. (1): a wave sums each run of equal keys with
-// a segmented scan; the lane holding a run's last item in the wave where the
-// run starts owns it (if the run goes on past the wave, that lane adds the
+// Segmented sum fused with Eq. (1).  Each wave owns a contiguous chunk of
+// kRChunk items and walks it 64 at a time with no block barrier (the next 64
+// items' loads are issued before the current ones are reduced); the unique
+// index of a run comes from the chunk's head offset (k_chunk_heads + scan)
+// and the wave's running head count.  A wave sums each run of equal keys
+// with a segmented scan; the lane holding a run's last item in the 64 where
+// the run starts owns it (if the run goes on past them, that lane adds the
 // rest from memory) and writes the column and ln x (kept) or 0 (dropped).
 // Row offsets as in k_reduce.  Each distinct pair is written by exactly one
 // lane with an integer sum, so the result does not depend on the launch shape.
+constexpr int kRChunk = 1024;
+
+__global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__ keys, int64_t n,
+                                                    int64_t nchunks,
+                                                    uint32_t *__restrict__ chunk_heads) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    if (w >= nchunks) return;
+    const int64_t base = w * kRChunk;
+    uint32_t c = 0;
+    for (int it = 0; it < kRChunk / 64; ++it) {
+        const int64_t i = base + it * 64 + lane;
+        if (i < n && (i == 0 || keys[i] != keys[i - 1])) ++c;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) chunk_heads[w] = c;
+}
+
 template <class VT>
 __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ keys,
                                                   const uint32_t *__restrict__ vals, int64_t n,
+                                                  int64_t nchunks,
                                                   const uint64_t *__restrict__ head_off,
                                                   int colbits, const uint32_t *__restrict__ deg,
                                                   int64_t row_lo, TLConst c,
                                                   int32_t *__restrict__ col, VT *__restrict__ val,
                                                   int64_t *__restrict__ rowptr,
-                                                  uint32_t *__restrict__ block_kept,
+                                                  uint32_t *__restrict__ chunk_kept,
                                                   bool tagged) {
-    __shared__ uint32_t wh[kWaves];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    if (w >= nchunks) return;
+    const int64_t base = w * kRChunk;
     const uint64_t colmask = (1ull << colbits) - 1;
     const uint64_t keymask = tagged ? (1ull << kTagShift) - 1 : ~0ull;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint64_t running = head_off[blockIdx.x];
+    uint64_t running = head_off[w];   // heads before these 64 items
     uint32_t my_kept = 0;
-    for (int it = 0; it < kIt; ++it) {
-        const int64_t i = base + it * kT + tid;
+    // items of the first 64 (prev = the key before each)
+    uint64_t key_n = 0, prev_n = 0, v_n = 0;
+    {
+        const int64_t i = base + lane;
+        if (i < n) {
+            key_n = keys[i];
+            v_n = vals[i];
+            prev_n = i > 0 ? keys[i - 1] : ~0ull;
+        }
+    }
+    for (int it = 0; it < kRChunk / 64; ++it) {
+        const int64_t i = base + it * 64 + lane;
+        if (base + it * 64 >= n) break;                       // wave-uniform
         const bool valid = i < n;
-        uint64_t key = 0, prev = 0, v = 0;
-        bool head = false;
-        if (valid) {
-            key = keys[i];
-            v = vals[i];
-            prev = i > 0 ? keys[i - 1] : ~0ull;
-            head = (i == 0) || key != prev;
+        const uint64_t key = key_n, prev = prev_n;
+        uint64_t v = valid ? v_n : 0;
+        // the next 64 items' loads go out before this reduction
+        const bool more = it + 1 < kRChunk / 64;
+        if (more) {
+            const int64_t j = i + 64;
+            if (j < n) {
+                key_n = keys[j];
+                v_n = vals[j];
+                prev_n = keys[j - 1];
+            }
         }
+        // the key after lane 63's item, from the prefetched registers
+        const uint64_t after = __shfl(key_n, 0, 64);
+        const bool head = valid && (i == 0 || key != prev);
         const uint64_t hm = __ballot(head);
-        if (lane == 0) wh[wv] = (uint32_t)__popcll(hm);
-        __syncthreads();
-        uint64_t before = running;
-        uint64_t itot = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            if (w < wv) before += wh[w];
-            itot += wh[w];
-        }
-        __syncthreads();
-        running += itot;
-        const uint64_t u = before + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
+        const uint64_t u = running + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
+        running += (uint64_t)__popcll(hm);
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const uint64_t ov = __shfl_up(v, off, 64);
@@ -358,10 +392,12 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
             for (int64_t r = prow + 1; r <= row; ++r) rowptr[r] = (int64_t)u;
         }
         const bool started_here = (hm & (lt | (1ull << lane))) != 0;
-        const bool last_in_wave = lane == 63 || i + 1 >= n || nu != u;
-        if (!(started_here && last_in_wave)) continue;
+        const bool last_here = lane == 63 || i + 1 >= n || nu != u;
+        if (!(started_here && last_here)) continue;
         uint64_t W = v;
-        if (lane == 63)
+        // a run that goes on past these 64 items: the rest from memory (the
+        // next key is in registers unless these are the chunk's last 64)
+        if (lane == 63 && i + 1 < n && (!more || after == key))
             for (int64_t j = i + 1; j < n && keys[j] == key; ++j) W += vals[j];
         const int32_t b = (int32_t)(key & colmask);
         const int64_t row = (int64_t)((key & keymask) >> colbits);
@@ -373,17 +409,11 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         val[u] = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
         my_kept += k ? 1u : 0u;
     }
-    // the block's count of kept entries (summed by a scan afterwards: one
+    // the chunk's count of kept entries (summed by a scan afterwards: one
     // counter hit by every wave serialises the whole grid on it)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_kept += __shfl_xor(my_kept, off, 64);
-    if (lane == 0) wh[wv] = my_kept;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < kWaves; ++w) t += wh[w];
-        block_kept[blockIdx.x] = t;
-    }
+    if (lane == 0) chunk_kept[w] = my_kept;
 }
 
 __global__ void k_degrees(const int64_t *__restrict__ rp, const uint64_t *__restrict__ cw,
@@ -508,20 +538,21 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
                             int32_t val_type, lne_csr *out, uint64_t *kept, bool tagged) {
     if (val_type != LNE_F32 && val_type != LNE_F64)
         return fail(ctx, LNE_EINVAL, "reduce_to_matrix: F32 or F64 values");
-    const int64_t ntiles = ceil_div(n_items > 0 ? n_items : 1, kTile);
+    const int64_t nchunks = ceil_div(n_items > 0 ? n_items : 1, kRChunk);
+    const unsigned nblocks = (unsigned)ceil_div(nchunks, kT / 64);
     Buf th(ctx), hoff(ctx), bk(ctx), bko(ctx);
-    LNE_TRY(alloc(ctx, th, sizeof(uint32_t) * (size_t)ntiles));
-    LNE_TRY(alloc(ctx, hoff, sizeof(uint64_t) * (size_t)(ntiles + 1)));
-    LNE_TRY(alloc(ctx, bk, sizeof(uint32_t) * (size_t)ntiles));
-    LNE_TRY(alloc(ctx, bko, sizeof(uint64_t) * (size_t)(ntiles + 1)));
+    LNE_TRY(alloc(ctx, th, sizeof(uint32_t) * (size_t)nchunks));
+    LNE_TRY(alloc(ctx, hoff, sizeof(uint64_t) * (size_t)(nchunks + 1)));
+    LNE_TRY(alloc(ctx, bk, sizeof(uint32_t) * (size_t)nchunks));
+    LNE_TRY(alloc(ctx, bko, sizeof(uint64_t) * (size_t)(nchunks + 1)));
     {
         Launch L(ctx, "heads");
-        k_heads<<<(unsigned)ntiles, kT, 0, ctx->stream>>>(keys, n_items, th.as<uint32_t>());
+        k_chunk_heads<<<nblocks, kT, 0, ctx->stream>>>(keys, n_items, nchunks, th.as<uint32_t>());
     }
     LNE_TRY(check_launch(ctx, "heads"));
-    LNE_TRY(scan_u32(ctx, th.as<uint32_t>(), hoff.as<uint64_t>(), ntiles));
+    LNE_TRY(scan_u32(ctx, th.as<uint32_t>(), hoff.as<uint64_t>(), nchunks));
     uint64_t nnz = 0;
-    LNE_HIP(ctx, hipMemcpyAsync(&nnz, hoff.as<uint64_t>() + ntiles, sizeof(uint64_t),
+    LNE_HIP(ctx, hipMemcpyAsync(&nnz, hoff.as<uint64_t>() + nchunks, sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, ctx->stream));
     LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     Buf rp(ctx), cc(ctx), vv(ctx);
@@ -531,26 +562,26 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
     if (n_items > 0) {
         Launch L(ctx, "reduce_trunc_log");
         if (val_type == LNE_F64)
-            k_reduce_tl<double><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
-                keys, vals, n_items, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
+            k_reduce_tl<double><<<nblocks, kT, 0, ctx->stream>>>(
+                keys, vals, n_items, nchunks, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
                 cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged);
         else
-            k_reduce_tl<float><<<(unsigned)ntiles, kT, 0, ctx->stream>>>(
-                keys, vals, n_items, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
+            k_reduce_tl<float><<<nblocks, kT, 0, ctx->stream>>>(
+                keys, vals, n_items, nchunks, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
                 cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged);
     }
     LNE_TRY(check_launch(ctx, "reduce_trunc_log"));
     {
         Launch L(ctx, "rowptr_tail");
         k_rowptr_tail<<<grid_of(n_rows + 1, 256), 256, 0, ctx->stream>>>(
-            keys, n_items, colbits, hoff.as<uint64_t>() + ntiles, n_rows, rp.as<int64_t>(),
+            keys, n_items, colbits, hoff.as<uint64_t>() + nchunks, n_rows, rp.as<int64_t>(),
             tagged ? (1ull << kTagShift) - 1 : ~0ull);
     }
     LNE_TRY(check_launch(ctx, "rowptr_tail"));
     uint64_t k = 0;
     if (n_items > 0) {
-        LNE_TRY(scan_u32(ctx, bk.as<uint32_t>(), bko.as<uint64_t>(), ntiles));
-        LNE_HIP(ctx, hipMemcpyAsync(&k, bko.as<uint64_t>() + ntiles, sizeof(k),
+        LNE_TRY(scan_u32(ctx, bk.as<uint32_t>(), bko.as<uint64_t>(), nchunks));
+        LNE_HIP(ctx, hipMemcpyAsync(&k, bko.as<uint64_t>() + nchunks, sizeof(k),
                                     hipMemcpyDeviceToHost, ctx->stream));
         LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
