@@ -25,7 +25,7 @@ def _same(lne, ctx, rp, col, p, weight=None):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("chunk", ["5000", "1000000000"])
+@pytest.mark.parametrize("chunk", ["100", "5000", "1000000000"])   # 100: most rows alone
 def test_host_sparsifier_bit_identical(lne, ctx, monkeypatch, prec, chunk):
     print("host sparsifier: tiny", prec, "chunk", chunk, flush=True)
     g, p = workload("tiny")

@@ -47,7 +47,9 @@ def _rand_y(n, k, seed, cond=1e3):
     return (Q1 * np.logspace(0, -math.log10(cond), k)) @ Q2
 
 
-@pytest.mark.parametrize("k", [5, 42, 138, 272])
+# 139 and 140: the last width whose Gram fits the eigensolver's LDS variant
+# and the first that takes the global-memory one; 288: the widest accepted
+@pytest.mark.parametrize("k", [5, 42, 138, 139, 140, 272, 288])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_eigsvd_vs_lapack(lne, ctx, k, dtype):
     import torch
