@@ -4,13 +4,15 @@
 // exact sum of its weights; here order-independent integer sums instead of a
 // lock-free hash, so the result is bit-identical for any launch shape).
 //
-// Radix pass (8-bit digit): per-tile digit histograms (digit-major table,
-// full tiles read as 16-byte vectors), one device-wide scan of the table,
-// then a scatter in which every tile ranks its items stably (each wave ranks
-// a contiguous quarter of the tile with ballots per digit bit and its own
-// digit counters in LDS; a block-wide prefix then orders the waves), stages
-// them in LDS in digit order (keys, then values, through one buffer) and
-// writes each digit run contiguously.
+// Radix pass (8-bit digit, 8192-item tiles): per-tile digit histograms
+// (digit-major table, full tiles read as 16-byte vectors), one device-wide
+// scan of the table, then a scatter in which every tile ranks its items
+// stably (each of its 8 waves ranks a contiguous eighth of the tile with
+// ballots per digit bit and its own digit counters in LDS; a block-wide
+// prefix then orders the waves), stages them in LDS in digit order (keys,
+// then values, through one buffer) and writes each digit run contiguously.
+// For the embedding's fused reduction, the first pass whose input is in
+// column order also writes each column's degree into the keys' spare bits.
 #include "common.hpp"
 
 namespace lne {
