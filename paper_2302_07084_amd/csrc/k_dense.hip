@@ -435,7 +435,8 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
 // Two-sided cyclic Jacobi with the round-robin (circle) ordering: every round
 // rotates kk/2 disjoint pairs at once, so a sweep is kk - 1 rounds.  IN_LDS:
 // the working copy of A lives in the workgroup's LDS (k^2 doubles of dynamic
-// shared memory), the eigenvector accumulator in global memory.
+// shared memory) and a round updates it in one pass of 2 x 2 blocks (two
+// block barriers per round); the eigenvector accumulator is in global memory.
 constexpr int kB = 4;   // rotation elements per thread in flight
 
 template <bool IN_LDS>
@@ -488,12 +489,49 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__res
                 cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
             }
             __syncthreads();
+            const int total = half * k;
+            if constexpr (IN_LDS) {
+                // A <- J^T A J in one pass: a thread takes the 2 x 2 block of
+                // rows (p_a, q_a) and columns (p_b, q_b) of two pairs, rotates
+                // its rows by pair a, then its columns by pair b (the same
+                // products as a row pass followed by a column pass); an
+                // index equal to k is the padding of an odd k
+                const int nblk = half * half;
+                for (int bi = tid; bi < nblk; bi += kSolveThreads) {
+                    const int a = bi / half, b = bi - a * half;
+                    const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+                    const bool ra = qa < k, rb = qb < k;
+                    const double x00 = A[pa * k + pb];
+                    const double x01 = rb ? A[pa * k + qb] : 0.0;
+                    const double x10 = ra ? A[qa * k + pb] : 0.0;
+                    const double x11 = ra && rb ? A[qa * k + qb] : 0.0;
+                    double y0 = x00, y1 = x10, z0 = x01, z1 = x11;
+                    if (ra && sn[a] != 0.0) {
+                        const double c = cs[a], s = sn[a];
+                        y0 = c * x00 - s * x10;
+                        y1 = s * x00 + c * x10;
+                        z0 = c * x01 - s * x11;
+                        z1 = s * x01 + c * x11;
+                    }
+                    double o00 = y0, o01 = z0, o10 = y1, o11 = z1;
+                    if (rb && sn[b] != 0.0) {
+                        const double c = cs[b], s = sn[b];
+                        o00 = c * y0 - s * z0;
+                        o01 = s * y0 + c * z0;
+                        o10 = c * y1 - s * z1;
+                        o11 = s * y1 + c * z1;
+                    }
+                    A[pa * k + pb] = o00;
+                    if (rb) A[pa * k + qb] = o01;
+                    if (ra) A[qa * k + pb] = o10;
+                    if (ra && rb) A[qa * k + qb] = o11;
+                }
+            } else {
             // rows: A <- J^T A; then columns: A <- A J, V <- V J.  32-bit
             // index arithmetic (half k < 2^31), and each thread issues the
             // loads of kB elements before their stores so that their
             // latencies overlap (V lives in global memory, and so does A
             // when it does not fit LDS)
-            const int total = half * k;
             for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
                 double a0[kB], a1[kB];
                 int o0[kB], o1[kB];
@@ -519,13 +557,14 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__res
                         A[o1[u]] = s[u] * a0[u] + c[u] * a1[u];
                     }
             }
-            __syncthreads();
-            // columns: A <- A J and V <- V J, V kept transposed (row p of Vw
-            // = column p of V) so that its rotation runs along rows p, q.
-            // With A in LDS one pass does both, lanes down the columns; with
-            // A in global memory the columns of A take a pass of their own
-            // with lanes along a row i (pair index fastest), so a wave's
-            // accesses stay inside one or two rows of A.
+                __syncthreads();
+            }
+            // columns: A <- A J (A in global memory; the LDS variant did its
+            // columns with its rows) and V <- V J, V kept transposed (row p of
+            // Vw = column p of V) so that its rotation runs along rows p, q.
+            // The columns of a global A take a pass with lanes along a row i
+            // (pair index fastest), so a wave's accesses stay inside one or
+            // two rows of A.
             if constexpr (!IN_LDS) {
                 for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
                     double a0[kB], a1[kB];
@@ -554,7 +593,7 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__res
                 }
             }
             for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
-                double a0[kB], a1[kB], v0[kB], v1[kB];
+                double v0[kB], v1[kB];
                 int o0[kB], o1[kB];
                 bool on[kB];
                 double c[kB], s[kB];
@@ -570,22 +609,12 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__res
                     o1[u] = q * k + i;
                     v0[u] = on[u] ? Vw[o0[u]] : 0.0;
                     v1[u] = on[u] ? Vw[o1[u]] : 0.0;
-                    if constexpr (IN_LDS) {
-                        a0[u] = on[u] ? A[i * k + p] : 0.0;
-                        a1[u] = on[u] ? A[i * k + q] : 0.0;
-                    }
                 }
 #pragma unroll
                 for (int u = 0; u < kB; ++u)
                     if (on[u]) {
                         Vw[o0[u]] = c[u] * v0[u] - s[u] * v1[u];
                         Vw[o1[u]] = s[u] * v0[u] + c[u] * v1[u];
-                        if constexpr (IN_LDS) {
-                            const int idx = b0 + u * kSolveThreads;
-                            const int pr = idx / k, i = idx - pr * k;
-                            A[i * k + pp[pr]] = c[u] * a0[u] - s[u] * a1[u];
-                            A[i * k + qq[pr]] = s[u] * a0[u] + c[u] * a1[u];
-                        }
                     }
             }
             __syncthreads();
