@@ -223,34 +223,62 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
     out += (int64_t)blockIdx.y * os;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ double Ws[kKC * 16 * MAXJ];
+    // two W chunks in LDS: chunk i + 1 is loaded into registers before the
+    // matrix-core steps of chunk i and stored to the other buffer after them,
+    // so one block barrier per chunk separates the two
+    constexpr int KPo = 16 * MAXJ;
+    constexpr int kWn = (kKC * KPo + kProjThreads - 1) / kProjThreads;
+    __shared__ double Ws[2][kKC * KPo];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int KPo = 16 * MAXJ;
     const int ntout = (kout + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
     const int kr = lane >> 4, kc = lane & 15;
     const int64_t arow = r0 + 16 * w + kc;
+    auto wload = [&](int k0, double wr[kWn]) {
+#pragma unroll
+        for (int u = 0; u < kWn; ++u) {
+            const int idx = tid + u * kProjThreads;
+            const int rr = idx / KPo, c = idx - rr * KPo;
+            const int krow = k0 + rr;
+            wr[u] = (idx < kKC * KPo && krow < kin && c < kout) ? W[(int64_t)krow * kout + c] : 0.0;
+        }
+    };
+    auto wstore = [&](int buf, const double wr[kWn]) {
+#pragma unroll
+        for (int u = 0; u < kWn; ++u) {
+            const int idx = tid + u * kProjThreads;
+            if (idx < kKC * KPo) Ws[buf][idx] = wr[u];
+        }
+    };
     v4d acc[MAXJ];
 #pragma unroll
     for (int J = 0; J < MAXJ; ++J) acc[J] = (v4d){0, 0, 0, 0};
-    for (int k0 = 0; k0 < kin; k0 += kKC) {
-        double a4[4];
-        load4d<YT>(Y, ldy, arow, n, k0 + 4 * kr, kin, vec != 0, a4);
-        for (int idx = tid; idx < kKC * KPo; idx += kProjThreads) {
-            const int rr = idx / KPo, c = idx - rr * KPo;
-            const int krow = k0 + rr;
-            Ws[idx] = (krow < kin && c < kout) ? W[(int64_t)krow * kout + c] : 0.0;
+    double wr[kWn], a4[4];
+    wload(0, wr);
+    load4d<YT>(Y, ldy, arow, n, 4 * kr, kin, vec != 0, a4);
+    wstore(0, wr);
+    __syncthreads();
+    for (int k0 = 0, cur = 0; k0 < kin; k0 += kKC, cur ^= 1) {
+        const bool more = k0 + kKC < kin;
+        double a4n[4];
+        if (more) {
+            wload(k0 + kKC, wr);
+            load4d<YT>(Y, ldy, arow, n, k0 + kKC + 4 * kr, kin, vec != 0, a4n);
         }
-        __syncthreads();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
 #pragma unroll
             for (int J = 0; J < MAXJ; ++J) {
                 if (J < ntout) {
-                    const double b = Ws[(4 * kr + t) * KPo + 16 * J + kc];
+                    const double b = Ws[cur][(4 * kr + t) * KPo + 16 * J + kc];
                     acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[t], b, acc[J], 0, 0, 0);
                 }
             }
+        }
+        if (more) {
+            wstore(cur ^ 1, wr);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a4[i] = a4n[i];
         }
         __syncthreads();
     }
