@@ -63,8 +63,10 @@ typedef int32_t lne_status;
 #define LNE_FLAG_SPARSE_OMEGA 4u
 /* lne_embed: keep the sparsifier's row blocks in pinned host memory (for
  * graphs whose sparsifier exceeds HBM); the products of the randomized SVD
- * stream them over PCIe, the copy of one chunk overlapping the product with
- * the previous one.  Results equal those of the in-HBM path. */
+ * stream them over PCIe in chunks of at most env LNE_HOST_CHUNK_NNZ entries
+ * (default 2^28; a longer row is a chunk of its own), the copy of one chunk
+ * overlapping the product with the previous one.  Results equal those of the
+ * in-HBM path. */
 #define LNE_FLAG_HOST_SPARSIFIER 8u
 
 typedef void *(*lne_alloc_fn)(size_t bytes, void *user);
@@ -205,7 +207,10 @@ lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *
  * sums the fixed-point weights of equal pairs, each sample counted in both
  * orientations.  out receives the symmetric count CSR (val_type LNE_U64, units
  * of 2^-16).  Synchronises the stream (twice: to size the pair buffer and the
- * CSR).  st may be NULL.  Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED (a
+ * CSR).  When the pair buffers (36 bytes per pair entry) would exceed the
+ * budget (env LNE_HBM_BUDGET_GB, default 70% of device memory) the rows are
+ * aggregated in ranges, each walking every sample again; the result is the
+ * same.  st may be NULL.  Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED (a
  * per-sample weight above 2^32 - 1 or more than 2^31 vertices). */
 lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                         lne_csr *out, lne_stats *st);
