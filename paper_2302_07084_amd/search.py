@@ -6,8 +6,8 @@ mu) with FLAML against the downstream score.  Here a small MLP, trained on
 method, ranks candidate trials; the plain method (lne_embed followed by
 lne_score_micro_f1, both on the GPU) scores every trial that is actually
 proposed, so the surrogate only decides the order in which trials are tried
-and the plain method stays the judge and the fallback (a random proposal
-stream).  This module only orchestrates: the embedding, the scorer and the
+and the plain method's score decides, with random proposals as the fallback
+(a share of every round).  This module only orchestrates: the embedding, the scorer and the
 network's forward, backward and Adam steps are library kernels.
 """
 from __future__ import annotations
