@@ -8,17 +8,18 @@
  * 5.2, Algorithm "Downsampled Per-Edge PathSampling" and Algorithm
  * "PathSampling"; Eq. (1)):
  *
- *   for every undirected edge e = (u, v), u < v, in CSR order:
- *     n_e = floor(M/m) + Bernoulli(frac(M/m))
- *     p_e = min(1, C (1/d_u + 1/d_v))                  (degree sampling, 4.1)
- *     repeat n_e times:
- *       coin with P(heads) = p_e; r ~ Multinomial(s_1..s_T)
- *       if heads: split ~ U{0..r-1}; u' = walk u for split steps,
- *                 v' = walk v for r-1-split steps; add (u', v') with weight
- *                 1/p_e to the sparsifier
- *   aggregate equal pairs by summing weights; then
- *   x_ab = vol 2m/(2 b M) * W_ab / (d_a d_b) and keep log x_ab when x_ab > 1
- *   (vol = 2m on an unweighted graph).
+ * The sparsifier is a sum of path samples drawn edge by edge.  Each undirected
+ * edge (u < v, numbered in CSR order) receives M/m samples on average: the
+ * integer part always, the fractional part as one extra sample with that
+ * probability.  A sample survives a degree-based coin whose success
+ * probability p_e is C (1/d_u + 1/d_v) capped at one (section 4.1), and picks
+ * a path length r from the normalised weights s.  A surviving sample places
+ * the edge at a uniformly chosen position of a length-r path, extends the
+ * path by uniform random-walk steps on both sides, and contributes the
+ * inverse of its survival probability to the pair of path endpoints, in both
+ * orientations.  Equal endpoint pairs are summed into counts W_ab, which Eq.
+ * (1) turns into x_ab = vol 2m/(2 b M) W_ab/(d_a d_b) (vol = 2m without
+ * weights); the matrix keeps ln x_ab wherever x_ab exceeds one.
  *
  * Weighted graphs (positive integer weights A_uv, symmetric): d_u = sum_v
  * A_uv, vol = sum_u d_u, p_e = min(1, C A_uv (1/d_u + 1/d_v)) (section 5.2,
