@@ -30,17 +30,22 @@ def log(msg):
 
 
 def kernel_bytes(name, ctx_info):
-    """Algorithmic HBM bytes of one launch of `name` (per-unit figure x units)."""
+    """Algorithmic HBM bytes of one launch of `name` (per-unit figure x units).
+
+    Both sparse x dense products use the gather model: row offsets, 8 bytes
+    of structure per nonzero, one gathered k-wide dense row per nonzero and
+    two n x k dense streams (operand in, product out),
+        B_gather = 8 (n + 1) + 8 nnz + e k nnz + 2 e n k,
+    with e the element size: the rSVD product at k = k' over the nonzeros of
+    the sparsified matrix, the propagation product at k = d over the graph's
+    arcs.  The epilogue streams the recurrence adds to some propagation
+    launches are not counted here (`graph_spmm_streams` reports them)."""
     n, nnz_M, kp, arcs, d, P = (ctx_info[k] for k in ("n", "nnz_M", "kp", "arcs", "d", "pairs"))
     es = ctx_info["es"]
     if name == "spmm":
-        # row offsets, (col, val) per nonzero, one gathered k'-row per nonzero,
-        # one written k'-row per output row
-        return 8 * (n + 1) + nnz_M * (4 + 4 + es * kp) + es * n * kp
+        return 8 * (n + 1) + 8 * nnz_M + es * kp * nnz_M + 2 * es * n * kp
     if name == "graph_spmm":
-        # offsets, col per arc, one gathered d-row per arc, own row + output
-        # row + up to two epilogue rows and the accumulator (read + write)
-        return 8 * (n + 1) + arcs * (4 + es * d) + es * n * d * 6
+        return 8 * (n + 1) + 8 * arcs + es * d * arcs + 2 * es * n * d
     if name == "radix_scatter":
         # read and write (key, weight) per item, plus the per-tile digit counts
         # and offsets
@@ -54,12 +59,171 @@ def kernel_bytes(name, ctx_info):
     return None
 
 
+def graph_spmm_streams(K):
+    """Dense n x d streams the Chebyshev recurrence of order K moves per
+    propagation, launch by launch.  Every term runs Z = B T (T in, Z out: 2
+    streams) and then the term's update with the accumulator (Z, the two
+    earlier terms and the accumulator in, the new term and the accumulator
+    out: 6; the first term has one earlier term: 5); the final D^-1 A
+    product adds 2.  Returns (launches, streams)."""
+    if K <= 0:
+        return 0, 0
+    return 2 * K + 1, 2 + 5 + 8 * (K - 1) + 2
+
+
 # Counter summary of the dominant kernels (profiles/): FETCH_SIZE and
 # WRITE_SIZE per launch and the calibration factors of a plain copy.
 COUNTERS = os.path.join(ROOT, "profiles", "counters_large.json")
 KERNEL_SOURCE = {"spmm": "k_spmm.hip", "graph_spmm": "k_spmm.hip",
                  "radix_scatter": "k_sort.hip", "radix_hist": "k_sort.hip",
                  "reduce_trunc_log": "k_sort.hip"}
+
+
+# Library kernels by the name bench.py and the counter summary use: a pattern
+# on the (demangled) kernel name and the source file that defines it.
+KERNEL_CLASSES = {
+    "spmm": (r"\bk_spmm<", "k_spmm.hip"),
+    "graph_spmm": (r"\bk_graph_spmm<", "k_spmm.hip"),
+    "radix_scatter": (r"\bk_scatter\b", "k_sort.hip"),
+    "radix_hist": (r"\bk_hist\b", "k_sort.hip"),
+    "reduce_trunc_log": (r"\bk_reduce_tl\b", "k_sort.hip"),
+    "bucket_scatter": (r"\bk_bucket_scatter\b", "k_bucket.hip"),
+    "bucket_reduce": (r"\bk_bucket_reduce\b", "k_bucket.hip"),
+}
+
+
+def _rocprof_files(root, suffix):
+    out = []
+    for d, _, files in os.walk(root):
+        out += [os.path.join(d, f) for f in files if f.endswith(suffix)]
+    return sorted(out)
+
+
+def _col(row, *names):
+    """Value of the first of `names` present in a csv row (case-insensitive)."""
+    low = {k.lower(): v for k, v in row.items() if k}
+    for nm in names:
+        if nm.lower() in low:
+            return low[nm.lower()]
+    raise KeyError(names)
+
+
+def _short_name(name):
+    """Kernel name without namespaces, return type and argument list."""
+    import re
+    name = re.sub(r"^void\s+", "", name).replace("(anonymous namespace)::", "")
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    name = name[:cut]
+    return re.sub(r"^(?:\w+::)+", "", name)
+
+
+def summarize_kernel_trace(root, steps, title, command):
+    """Markdown table of a `rocprofv3 --kernel-trace --stats` run: calls,
+    average and per-step milliseconds and share of every kernel, from its
+    kernel_stats.csv (or, without one, from the kernel trace itself)."""
+    import csv
+    rows = {}
+    stats = _rocprof_files(root, "kernel_stats.csv")
+    if stats:
+        for path in stats:
+            with open(path, newline="") as f:
+                for r in csv.DictReader(f):
+                    nm = _short_name(_col(r, "Name", "Kernel_Name", "KernelName"))
+                    calls = int(float(_col(r, "Calls")))
+                    tot = float(_col(r, "TotalDurationNs", "Total_Duration_Ns"))
+                    c0, t0 = rows.get(nm, (0, 0.0))
+                    rows[nm] = (c0 + calls, t0 + tot)
+    else:
+        for path in _rocprof_files(root, "kernel_trace.csv"):
+            with open(path, newline="") as f:
+                for r in csv.DictReader(f):
+                    nm = _short_name(_col(r, "Kernel_Name", "KernelName", "Name"))
+                    dt = float(_col(r, "End_Timestamp")) - float(_col(r, "Start_Timestamp"))
+                    c0, t0 = rows.get(nm, (0, 0.0))
+                    rows[nm] = (c0 + 1, t0 + dt)
+    if not rows:
+        raise SystemExit(f"no kernel_stats.csv or kernel_trace.csv under {root}")
+    total = sum(t for _, t in rows.values())
+    lines = [f"# {title}", "", f"Command (from the repository root, `TMPDIR=/tmp`): `{command}`",
+             "", f"Per-step figures divide the totals by {steps} (the embedding steps the "
+             "profiled command ran, warm-up included).", "",
+             "| kernel | calls | avg ms | ms per step | share |", "|---|---|---|---|---|"]
+    for nm, (calls, tot) in sorted(rows.items(), key=lambda kv: -kv[1][1]):
+        if tot / total < 0.001:
+            continue
+        lines.append(f"| `{nm[:90]}` | {calls} | {tot / calls / 1e6:.3f} | "
+                     f"{tot / steps / 1e6:.1f} | {100 * tot / total:.1f}% |")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_counters(fetch_root, write_root, calib_bytes, workload, commands):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the library kernels
+    from two `rocprofv3 --pmc` runs, averaged per launch of each kernel class,
+    with the calibration factors of the largest plain device copy
+    (`calib_bytes` long) that the runs made, and the sha256 of each kernel's
+    source so that a changed kernel invalidates its figures."""
+    import csv
+    import hashlib
+    import re
+
+    def per_dispatch(root, counter):
+        vals = {}
+        for path in _rocprof_files(root, "counter_collection.csv"):
+            with open(path, newline="") as f:
+                for r in csv.DictReader(f):
+                    if _col(r, "Counter_Name") != counter:
+                        continue
+                    key = (path, _col(r, "Dispatch_Id", "Correlation_Id"))
+                    nm = _col(r, "Kernel_Name", "KernelName")
+                    v = float(_col(r, "Counter_Value"))
+                    vals[key] = (nm, vals.get(key, (nm, 0.0))[1] + v)
+        return list(vals.values())
+
+    out = {"workload": workload, "commands": commands, "kernels": {}}
+    factors = {}
+    for counter, root in (("FETCH_SIZE", fetch_root), ("WRITE_SIZE", write_root)):
+        disp = per_dispatch(root, counter)
+        copies = [v for nm, v in disp if "copyBuffer" in nm]
+        if not copies:
+            raise SystemExit(f"no device copy in the {counter} run (use --calib-copy-mib)")
+        factors[counter] = calib_bytes / (max(copies) * 1024.0)
+        for cls, (pat, src) in KERNEL_CLASSES.items():
+            v = [x for nm, x in disp if re.search(pat, nm)]
+            if not v:
+                continue
+            ent = out["kernels"].setdefault(cls, {"source": src})
+            ent["launches"] = len(v)
+            ent[("fetch" if counter == "FETCH_SIZE" else "write") + "_kib_per_launch"] = \
+                sum(v) / len(v)
+    out["fetch_factor"] = factors["FETCH_SIZE"]
+    out["write_factor"] = factors["WRITE_SIZE"]
+    out["calibration"] = f"largest device copy of {calib_bytes} bytes"
+    for ent in out["kernels"].values():
+        with open(os.path.join(ROOT, "paper_2302_07084_amd", "csrc", ent["source"]), "rb") as f:
+            ent["source_sha256"] = hashlib.sha256(f.read()).hexdigest()
+    return out
+
+
+def counters_markdown(summ, title):
+    lines = [f"# {title}", "", "Commands: " + " and ".join(f"`{c}`" for c in summ["commands"]) +
+             " (one counter per run).", "",
+             f"Calibration: {summ['calibration']} -> read factor {summ['fetch_factor']:.3f}, "
+             f"write factor {summ['write_factor']:.3f}.", "",
+             "| kernel | launches | FETCH KiB/launch | WRITE KiB/launch | HBM bytes/launch "
+             "(calibrated) |", "|---|---|---|---|---|"]
+    for cls, e in summ["kernels"].items():
+        fk, wk = e.get("fetch_kib_per_launch", 0.0), e.get("write_kib_per_launch", 0.0)
+        tot = (fk * summ["fetch_factor"] + wk * summ["write_factor"]) * 1024
+        lines.append(f"| `{cls}` | {e['launches']} | {fk:,.0f} | {wk:,.0f} | {tot / 1e9:,.1f} GB |")
+    return "\n".join(lines) + "\n"
 
 
 def measured_traffic(name):
@@ -113,7 +277,42 @@ def main():
                     help="surrogate pretraining trials per family graph (8 graphs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-trace", metavar="DIR", default=None,
+                    help="print a markdown summary of a rocprofv3 --kernel-trace --stats "
+                         "output directory (no GPU work)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    default=None,
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) "
+                         "into the counter JSON that the roofline's traffic field reads "
+                         "(no GPU work; --calib-copy-mib gives the calibration copy's size)")
+    ap.add_argument("--summary-steps", type=int, default=1,
+                    help="embedding steps the profiled command ran (per-step figures)")
+    ap.add_argument("--summary-title", default="Kernel time")
+    ap.add_argument("--summary-command", action="append", default=[],
+                    help="the profiled command, recorded in the summary (repeatable)")
+    ap.add_argument("--summary-out", default=None,
+                    help="write the summary here (markdown; .json for --summarize-counters "
+                         "also writes a .md beside it)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        text = summarize_kernel_trace(args.summarize_trace, args.summary_steps,
+                                      args.summary_title, " && ".join(args.summary_command))
+        if args.summary_out:
+            with open(args.summary_out, "w") as f:
+                f.write(text)
+        print(text)
+        return
+    if args.summarize_counters:
+        summ = summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                                  args.calib_copy_mib << 20, args.workload, args.summary_command)
+        md = counters_markdown(summ, args.summary_title)
+        if args.summary_out:
+            with open(args.summary_out, "w") as f:
+                json.dump(summ, f, indent=1)
+            with open(os.path.splitext(args.summary_out)[0] + ".md", "w") as f:
+                f.write(md)
+        print(md)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -216,10 +415,35 @@ def main():
     dominant = max(prof, key=lambda k: prof[k]["ms_per_step"])
     rl_name = dominant if kernel_bytes(dominant, info) is not None else "spmm"
     nbytes = kernel_bytes(rl_name, info)
-    achieved = nbytes / (prof[rl_name]["avg_ms"] * 1e-3) / 1e9
+    # the counters were taken on the generator's vertex order
+    traffic = measured_traffic(rl_name) if args.relabel is None else None
+    # achieved rate: the algorithmic bytes, or the measured HBM bytes where
+    # the caches served part of them (min of the two), over the launch time
+    counted = min(nbytes, traffic) if traffic else nbytes
+    achieved = counted / (prof[rl_name]["avg_ms"] * 1e-3) / 1e9
     spmm_gbs = kernel_bytes("spmm", info) / (prof["spmm"]["avg_ms"] * 1e-3) / 1e9
     spmm_min = (8 * (g.n + 1) + 8 * stats["nnz_log"] + 2 * es * g.n * kp) / (prof["spmm"]["avg_ms"] * 1e-3) / 1e9
+    gsp = None
+    if "graph_spmm" in prof:
+        launches, streams = graph_spmm_streams(p["cheb_k"])
+        # the gather model plus the epilogue streams each launch really moves
+        # (on average over the propagation's launches)
+        b_streams = (kernel_bytes("graph_spmm", info) - 2 * es * g.n * p["d"]
+                     + streams / launches * es * g.n * p["d"])
+        gsp = {"bytes_gather_model": kernel_bytes("graph_spmm", info),
+               "bytes_with_epilogue_streams": b_streams,
+               "streams_per_launch": streams / launches,
+               "avg_launch_ms": prof["graph_spmm"]["avg_ms"],
+               "gbs_gather_model": kernel_bytes("graph_spmm", info) / (prof["graph_spmm"]["avg_ms"] * 1e-3) / 1e9,
+               "gbs_with_epilogue_streams": b_streams / (prof["graph_spmm"]["avg_ms"] * 1e-3) / 1e9}
     sampler_ms = sum(prof.get(k, {}).get("ms_per_step", 0.0) for k in ("sample_count", "sample_emit"))
+    # the sparsifier stage: sampling, the pair sort and the aggregation with
+    # Eq. (1) fused (the embedding builds no separate count matrix)
+    sparsifier_ms = sum(prof.get(k, {}).get("ms_per_step", 0.0) for k in (
+        "validate_graph", "row_up", "fill_edges", "sample_count", "fold_stats", "sample_emit",
+        "scan", "radix_hist", "radix_scatter", "heads", "reduce", "degrees", "reduce_trunc_log",
+        "drop_zeros", "rowptr_tail", "concat_rows", "bucket_count", "bucket_scatter",
+        "bucket_reduce"))
 
     value = stats["accepted"] / (ms_per_step * 1e-3)
     out = {
@@ -244,12 +468,17 @@ def main():
                    "flags": int(p.get("flags", 0)), "relabel": args.relabel,
                    "parallelism": "single GPU"},
         "roofline": {"kernel": rl_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     # the counters were taken on the generator's vertex order
-                     "traffic": measured_traffic(rl_name) if args.relabel is None else None,
-                     "bytes_per_launch": nbytes, "avg_launch_ms": prof[rl_name]["avg_ms"]},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": nbytes, "bytes_counted": counted,
+                     "avg_launch_ms": prof[rl_name]["avg_ms"],
+                     "model": "gather: 8(n+1) + 8 nnz + e k nnz + 2 e n k; achieved = "
+                              "min(model, traffic) / average launch time"},
+        "graph_spmm": gsp,
         "stats": stats,
         "sampler_edges_per_s": stats["accepted"] / (sampler_ms * 1e-3) if sampler_ms else None,
+        "gpu_same_scope": {"value": stats["accepted"] / (sparsifier_ms * 1e-3) if sparsifier_ms else None,
+                           "unit": "sampled edges/s (sampling + aggregation stages)",
+                           "ms_per_step": sparsifier_ms},
         "attempted_samples_per_s": stats["attempted"] / (ms_per_step * 1e-3),
         "spmm_gbs_gather_model": spmm_gbs,
         "spmm_gbs_min_model": spmm_min,
@@ -733,13 +962,42 @@ def automl_report(name, budget, pretrain_per_graph):
     print(json.dumps(out), flush=True)
 
 
+def host_cpu_info():
+    """CPU model, logical CPUs of the machine and CPUs this process may run
+    on (its affinity mask)."""
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return {"model": model, "nproc_machine": os.cpu_count(), "nproc_allowed": allowed}
+
+
 def cpu_baseline(g, p, seconds):
-    """The oracle's sampler + aggregator (plain C, all host threads) on a
+    """The oracle's sampler + aggregator (plain C, POSIX threads) on a
     contiguous block of edges from the middle of the same workload's edge list
     (the first edges all belong to the largest hub), sized to about `seconds`
-    of work."""
+    of work on all the threads it may use, then the same block on one thread.
+    Threads: the CPUs in this process's affinity mask, capped by
+    OMP_NUM_THREADS (the host's CPU share per GPU) when that is set.  Scope:
+    the sampling and aggregation stages (count CSR) only, in accepted
+    samples per second; the GPU's rate over the same stages is reported beside
+    it (`gpu_same_scope`)."""
     import oracle
-    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+    info = host_cpu_info()
+    cap = os.environ.get("OMP_NUM_THREADS")
+    threads = info["nproc_allowed"]
+    if cap and cap.isdigit() and int(cap) > 0:
+        threads = min(threads, int(cap))
     e0 = g.m // 2
     cnt = max(1000, g.m // 10000)
     while True:
@@ -747,13 +1005,23 @@ def cpu_baseline(g, p, seconds):
         t0 = time.perf_counter()
         _, _, _, att, acc = oracle.count_csr(g, p, nthreads=threads, e_begin=e0, e_end=e1)
         dt = time.perf_counter() - t0
-        log(f"cpu baseline: edges [{e0}, {e1}), {acc} accepted samples in {dt:.2f}s")
-        if dt >= seconds / 4 or e1 >= g.m:
+        log(f"cpu baseline: edges [{e0}, {e1}), {acc} accepted samples in {dt:.2f}s "
+            f"on {threads} threads")
+        if dt >= seconds * 0.6 or e1 >= g.m:
             break
-        cnt = int(cnt * max(2.0, seconds / max(dt, 1e-3) * 0.8))
-    return {"value": acc / dt, "unit": "sampled edges/s", "cores": threads, "kind": "oracle",
+        cnt = int(cnt * min(50.0, max(1.5, seconds / max(dt, 1e-3))))
+    # one thread on a block with a tenth of the work per thread
+    e1s = min(g.m, e0 + max(1000, (e1 - e0) // max(threads, 1) // 2))
+    t0 = time.perf_counter()
+    _, _, _, att1, acc1 = oracle.count_csr(g, p, nthreads=1, e_begin=e0, e_end=e1s)
+    dt1 = time.perf_counter() - t0
+    log(f"cpu baseline: one thread, edges [{e0}, {e1s}), {acc1} accepted samples in {dt1:.2f}s")
+    return {"value": acc / dt, "unit": "sampled edges/s (sampling + aggregation stages)",
+            "cores": threads, "kind": "oracle",
             "sample": f"all {att} sample slots of edges [{e0}, {e1}) of {g.m} "
-                      f"(sampled, walked and aggregated to a count CSR), {dt:.1f}s"}
+                      f"(sampled, walked and aggregated to a count CSR), {dt:.1f}s",
+            "single_thread": {"value": acc1 / dt1, "edges": [e0, e1s], "seconds": dt1},
+            "host": info}
 
 
 if __name__ == "__main__":

@@ -303,6 +303,17 @@ lne_status lne_rsvd(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U
 lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                          const void *X0, void *X);
 
+/* One product of the Chebyshev recurrence of lne_propagate (section 4.3):
+ *   out = a Z + b D^-1 A Z
+ * on the input graph (weighted: D^-1 A with the arc weights).  Z, out: device
+ * n x k, row-major with leading dimension ld (elements), F64 or F32 (dtype),
+ * 16-byte aligned, ld a multiple of the 16-byte vector (2 doubles, 4 floats);
+ * out must not alias Z.  The launch shape is the one lne_propagate uses
+ * (timed on the first call of a shape).  Errors: EINVAL (also a malformed
+ * graph, found by a device check that synchronises the stream). */
+lne_status lne_graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, int64_t ld,
+                          int32_t k, int32_t dtype, double a, double b, void *out);
+
 /* Whole path: sparsify -> trunc_log -> rSVD -> propagate.  X: device n x d
  * (F64 for LNE_F64, else F32).  Synchronises the stream (sizes).  st may be
  * NULL.  Errors: those of the stages. */

@@ -106,6 +106,8 @@ SIGNATURES = [
     ("lne_orthonormalize", _I32, [_P, _P, _I64, _I32, _I64, _I32]),
     ("lne_rsvd", _I32, [_P, _P, _P, _P, _P, _P, _P]),
     ("lne_propagate", _I32, [_P, _P, _P, _P, _P]),
+    ("lne_graph_spmm", _I32, [_P, _P, _P, _I64, _I32, _I32, ctypes.c_double, ctypes.c_double,
+                              _P]),
     ("lne_embed", _I32, [_P, _P, _P, _P, _P]),
     ("lne_sparsify_channels", _I32, [_P, _P, _P, _P, _P]),
     ("lne_trial_matrix", _I32, [_P, _P, _P, _P, _P, _P]),
@@ -476,6 +478,19 @@ def propagate(ctx: Context, rowptr, col, params: dict, X0, weight=None):
     ctx.check(ctx.L.lne_propagate(ctx.h, ctypes.byref(g), ctypes.byref(p), X0.data_ptr(),
                                   X.data_ptr()), "propagate")
     return X
+
+
+def graph_spmm(ctx: Context, rowptr, col, Z, a: float, b: float, weight=None):
+    """out = a Z + b D^-1 A Z (one product of the propagation recurrence).
+    Z: device n x k (row stride a multiple of 16 bytes), F64 or F32."""
+    import torch
+    g = graph_struct(rowptr, col, weight)
+    n, k = Z.shape
+    out = torch.empty((n, Z.stride(0)), dtype=Z.dtype, device=Z.device)[:, :k]
+    ctx.check(ctx.L.lne_graph_spmm(ctx.h, ctypes.byref(g), Z.data_ptr(), Z.stride(0), k,
+                                   _code_of(Z), ctypes.c_double(a), ctypes.c_double(b),
+                                   out.data_ptr()), "graph_spmm")
+    return out
 
 
 def embed(ctx: Context, rowptr, col, params: dict, out=None, weight=None):

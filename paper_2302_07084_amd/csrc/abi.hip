@@ -1142,6 +1142,18 @@ lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p, 
     return propagate_impl(ctx, g, p, X0, X);
 }
 
+lne_status lne_graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, int64_t ld,
+                          int32_t k, int32_t dtype, double a, double b, void *out) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    if (!Z || !out || k < 1 || ld < k || (dtype != LNE_F64 && dtype != LNE_F32))
+        return fail(ctx, LNE_EINVAL, "graph_spmm: bad arguments");
+    if (Z == out) return fail(ctx, LNE_EINVAL, "graph_spmm: out must not alias Z");
+    LNE_TRY(validate_graph_device(ctx, g));
+    return graph_spmm(ctx, g, Z, out, ld, k, dtype, a, b, nullptr, 0.0, nullptr, 0.0, nullptr,
+                      0.0);
+}
+
 lne_status lne_sparsify_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
                             lne_csr *out, lne_stats *st) {
     if (!ctx) return LNE_EINVAL;

@@ -161,3 +161,20 @@ def test_batched_trials_reject_weighted_graphs(lne):
     assert rc == -5
     assert b"unweighted" in L.lne_last_error(h)
     L.lne_ctx_destroy(h)
+
+
+def test_graph_spmm_rejects_bad_arguments(lne):
+    """Checked on the host before the device graph check runs."""
+    L, h = _ctx(lne)
+    Z, O = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    good = dict(Z=Z, ld=8, k=8, dt=lne.F32, out=O)
+    for bad in (dict(Z=None), dict(out=None), dict(k=0), dict(ld=4), dict(dt=lne.BF16),
+                dict(dt=lne.U64), dict(out=Z)):
+        a = dict(good, **bad)
+        rc = L.lne_graph_spmm(h, ctypes.byref(_graph()), a["Z"], a["ld"], a["k"], a["dt"],
+                              ctypes.c_double(1.0), ctypes.c_double(-1.0), a["out"])
+        assert rc == -1, bad
+    rc = L.lne_graph_spmm(h, ctypes.byref(_graph(0, 0)), Z, 8, 8, lne.F32, ctypes.c_double(1.0),
+                          ctypes.c_double(-1.0), O)
+    assert rc == -1
+    L.lne_ctx_destroy(h)

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from synth import sbm, trial_vectors, workload
+from tests import bars
 from tests import graphs_small as gs
 from tests.conftest import to_dev
 
@@ -128,6 +129,44 @@ def test_batched_pipeline_equals_single_trial_runs(lne, ctx):
         X = _single_trial_reference(lne, ctx, rp, col, p, ch, tr)
         err = procrustes_err(Xb[t].cpu().numpy(), X)
         assert err < 2e-3, (t, err)
+
+
+def test_batched_pipeline_matches_oracle(lne, ctx):
+    """The batched path end to end (channel pass, values generated inside the
+    batched SpMM, batched Gram / Cholesky / eigen-solve / projections,
+    batched propagation, final eigSVD) against the FP64 oracle run trial by
+    trial: its trial_matrix of the same channel pass, the fast randomized SVD
+    with the same Omega, the Chebyshev propagation and the final eigSVD
+    (sections 4.2-4.4).  Five trials, one with k = 0 and one with theta = 0
+    (propagation off).  d = 8 is the number of planted blocks, where the
+    spectrum has its gap; the bar is derived per trial from the oracle's
+    quantities (tests/bars.py)."""
+    g = sbm([100] * 8, 0.12, 0.01, seed=3)
+    d, ov = 8, 8
+    p = dict(T=10, s=np.full(10, 0.1), M=30 * 10 * g.m, b=1, C=math.log(g.n), d=d,
+             oversample=ov, q=2, cheb_k=5, theta=0.5, mu=0.2, seed=1, precision="f32")
+    rp, col = to_dev(g)
+    trials = trial_vectors(5, seed=7)
+    trials[1]["k"] = 0
+    trials[3]["theta"] = 0.0
+    Xb, st = lne.embed_batch(ctx, rp, col, p, trials)
+    Xb = Xb.double().cpu().numpy()
+    R0, C0, W0, _, _ = oracle.count_csr(g, p, channels=True)
+    kp = d + ov
+    omega = oracle.gaussian_omega(g.n, kp, p["seed"])
+    for t, tr in enumerate(trials):
+        Mt = oracle.trial_matrix(g, p, R0, C0, W0, tr["s"])
+        U, S, V = oracle.fast_rsvd(Mt, kp, 0, p["q"], omega)
+        X0 = oracle.embedding(U[:, :d], S[:d])
+        on = tr["k"] > 0 and tr["theta"] >= 1e-12
+        Xsp = oracle.propagate(g, X0, tr["k"], tr["theta"], tr["mu"]) if on else None
+        X = oracle.final_embedding(Xsp) if on else X0
+        bar = bars.embedding_bar(g, X0, Xsp, S, d, kp, tr)
+        err = procrustes_err(Xb[t], X)
+        print(f"trial {t}: k={tr['k']} theta={tr['theta']:.2f} err {err:.3e} bar {bar:.3e}",
+              flush=True)
+        assert bar < 0.5
+        assert err <= bar, (t, err, bar)
 
 
 def test_graph_replays_equal_eager_runs(lne, ctx):
