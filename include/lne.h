@@ -271,6 +271,24 @@ lne_status lne_spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx,
 lne_status lne_eigsvd(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t ld,
                       int32_t dtype, void *U, int64_t ldu, double *S, double *V);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lne_eigsvd
+ * with no allocation.  Same arguments, results and errors as lne_eigsvd.
+ * Every intermediate (the Gram's per-workgroup partial sums, the Gram, the
+ * eigen-solver's working matrix, eigenvectors, eigenvalues and the projection
+ * weights) lives in a fixed device array of LNE_EIGSVD_NOALLOC_SCRATCH bytes
+ * that the library holds on each device it runs on until the process ends;
+ * the call makes no hipMalloc, hipFree or allocator call and records no
+ * profiling events.  The Gram uses as many workgroups as the array has room
+ * for partial sums (fewer than lne_eigsvd for k > 160 or so), which changes
+ * only its summation order.  Calls on one device share the array: calls that
+ * overlap in time on one device (other streams, other threads) race; calls
+ * ordered on one stream do not.  Errors: EINVAL, EUNSUPPORTED (k > 288), EHIP
+ * (the array's device address could not be obtained). */
+#define LNE_EIGSVD_NOALLOC_SCRATCH (64u << 20)
+lne_status lne_eigsvd_noalloc(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t ld,
+                              int32_t dtype, void *U, int64_t ldu, double *S, double *V);
+
 /* Orthonormal basis of range(Y) by CholeskyQR2 with a shifted first pass on
  * breakdown (Fukaya et al.), in place; the Cholesky factorisations are FP64.
  * This replaces eigSVD as the orthonormaliser of the power iteration: both

@@ -103,6 +103,7 @@ SIGNATURES = [
     ("lne_csr_free", None, [_P, _P]),
     ("lne_spmm", _I32, [_P, _P, _P, _I64, _P, _I64, _I32, _I32]),
     ("lne_eigsvd", _I32, [_P, _P, _I64, _I32, _I64, _I32, _P, _I64, _P, _P]),
+    ("lne_eigsvd_noalloc", _I32, [_P, _P, _I64, _I32, _I64, _I32, _P, _I64, _P, _P]),
     ("lne_orthonormalize", _I32, [_P, _P, _I64, _I32, _I64, _I32]),
     ("lne_rsvd", _I32, [_P, _P, _P, _P, _P, _P, _P]),
     ("lne_propagate", _I32, [_P, _P, _P, _P, _P]),

@@ -61,7 +61,7 @@ lne_status alloc(lne_ctx *ctx, Buf &b, size_t bytes) {
 }
 
 Launch::Launch(lne_ctx *c, const char *n) : ctx(c), name(n) {
-    if (ctx->prof && !ctx->capturing) {
+    if (ctx->prof && !ctx->capturing && !ctx->no_events) {
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
         (void)hipEventRecord(a, ctx->stream);

@@ -32,6 +32,7 @@ struct lne_ctx {
     size_t arena_cap = 0, arena_used = 0, arena_need = 0;
     bool arena_on = false, arena_measure = false;
     bool capturing = false;   // no event bracketing while a graph is captured
+    bool no_events = false;   // no event bracketing (allocation-free entry points)
     std::map<std::string, int> tuned;   // launch-shape choices (pick_variant)
 };
 
@@ -290,13 +291,19 @@ lne_status dense_scale(lne_ctx *ctx, const void *x, int32_t xt, int64_t ldx, voi
 // run_next) at + kFlagStride b.
 constexpr int kFlagStride = 4;
 // G (k x k, FP64, leading dimension k) = Y^T Y.
+// part_ws (optional): caller workspace for the per-workgroup partial Grams
+// (fewer workgroups when it is small; at least nb k'^2 doubles, k' = k
+// rounded up to 16).
 lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k,
-                int64_t ld, double *G, const int32_t *skip, int32_t nb = 1, int64_t ys = 0);
+                int64_t ld, double *G, const int32_t *skip, int32_t nb = 1, int64_t ys = 0,
+                double *part_ws = nullptr, size_t part_ws_bytes = 0);
 // out (n x kout, out_t) = Y (n x kin, y_t) W (kin x kout, FP64 device, ld kout).
 lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_t n,
                    int32_t kin, const double *W, int32_t kout, void *out, int32_t out_t,
                    int64_t ldo, const int32_t *skip, int32_t nb = 1, int64_t ys = 0,
-                   int64_t ws = 0, int64_t os = 0);
+                   int64_t ws = 0, int64_t os = 0, void *wt_ws = nullptr);
+// Workspace of project's BF16 path (W transposed to BF16).
+size_t project_bf16_ws_bytes(int32_t kin, int32_t kout, int32_t nb = 1);
 // Upper Cholesky G = R^T R in place (R in upper triangle, lower zeroed) and
 // W = R^-1; on breakdown retries with a shift and sets *shifted.  mode 0:
 // plain; mode 1: the shift is always allowed.  status: 0 ok, 1 failed.
@@ -305,7 +312,8 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
                     int32_t *skip_next, int32_t nb = 1);
 // Symmetric eigen-decomposition of C (k x k, FP64): V (k x k, columns = vectors),
 // lam (k), sorted by decreasing eigenvalue.  C is overwritten.
-lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb = 1);
+lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb = 1,
+                   double *vw_ws = nullptr);
 // W (k x kout) = V[:, :kout] diag(f(lam)) with f = lam^pow (0 for
 // lam <= k eps lam_max); S (kout) = sqrt(lam) (optional).  Entries b with
 // on[b] == 0 (on may be NULL) get W = I and S = 1 instead (k == kout).

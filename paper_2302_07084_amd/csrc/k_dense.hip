@@ -713,20 +713,34 @@ __global__ void k_eig_weights(const double *__restrict__ V, const double *__rest
 }  // namespace
 
 // ---------------------------------------------------------------- host side
+size_t project_bf16_ws_bytes(int32_t kin, int32_t kout, int32_t nb) {
+    return sizeof(__bf16) * (size_t)nb * kout * (((kin + 31) / 32) * 32);
+}
+
 lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k, int64_t ld,
-                double *G, const int32_t *skip, int32_t nb, int64_t ys) {
+                double *G, const int32_t *skip, int32_t nb, int64_t ys, double *part_ws,
+                size_t part_ws_bytes) {
     const int KP = ((k + 15) / 16) * 16;
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
     const int per_wave = (ntu + 7) / 8;
     if (per_wave > 22) return fail(ctx, LNE_EUNSUPPORTED, "gram: k = %d above 288", k);
     if (nb < 1 || nb > 65535) return fail(ctx, LNE_EINVAL, "gram: batch of %d", nb);
     const int64_t blocks_rows = ceil_div(n > 0 ? n : 1, kGramRows);
-    // about 512 (256 for wide k) workgroups over the whole batch
-    const int64_t target = std::max<int64_t>(1, (KP > 160 ? 256 : 512) / nb);
+    // about 512 (256 for wide k) workgroups over the whole batch, or as many
+    // per-workgroup partial sums as a caller's workspace holds
+    int64_t target = std::max<int64_t>(1, (KP > 160 ? 256 : 512) / nb);
+    const size_t part_one = sizeof(double) * (size_t)nb * KP * KP;
+    if (part_ws) {
+        if (part_ws_bytes < part_one)
+            return fail(ctx, LNE_EUNSUPPORTED, "gram: workspace of %zu bytes below %zu",
+                        part_ws_bytes, part_one);
+        target = std::min<int64_t>(target, (int64_t)(part_ws_bytes / part_one));
+    }
     const int nwg = (int)std::min<int64_t>(blocks_rows, target);
     const int64_t rows_per_wg = ceil_div(blocks_rows, nwg) * kGramRows;
     Buf part(ctx);
-    LNE_TRY(alloc(ctx, part, sizeof(double) * (size_t)nb * nwg * KP * KP));
+    if (part_ws) part.p = part_ws, part.ctx = nullptr;   // borrowed: never released
+    else LNE_TRY(alloc(ctx, part, part_one * nwg));
     const dim3 grid((unsigned)nwg, (unsigned)nb);
     const int vec = ((uintptr_t)Y % 16 == 0 && ld % 8 == 0 && ys % 8 == 0) ? 1 : 0;
     {
@@ -770,7 +784,7 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
 lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_t n,
                    int32_t kin, const double *W, int32_t kout, void *out, int32_t out_t,
                    int64_t ldo, const int32_t *skip, int32_t nb, int64_t ys, int64_t ws,
-                   int64_t os) {
+                   int64_t os, void *wt_ws) {
     if (kout > 288 || kin > 288) return fail(ctx, LNE_EUNSUPPORTED, "project: width above 288");
     if (nb < 1 || nb > 65535) return fail(ctx, LNE_EINVAL, "project: batch of %d", nb);
     const dim3 grid(grid_of(n > 0 ? n : 1, kProjRows), (unsigned)nb);
@@ -779,7 +793,9 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
         const int ldw = ((kin + 31) / 32) * 32;
         const int vec = ((uintptr_t)Y % 16 == 0 && ldy % 8 == 0 && ys % 8 == 0) ? 1 : 0;
         Buf wt(ctx);
-        LNE_TRY(alloc(ctx, wt, sizeof(__bf16) * (size_t)nb * kout * ldw));
+        // wt_ws (if given) holds project_bf16_ws_bytes(kin, kout, nb)
+        if (wt_ws) wt.p = wt_ws, wt.ctx = nullptr;
+        else LNE_TRY(alloc(ctx, wt, project_bf16_ws_bytes(kin, kout, nb)));
         {
             Launch L(ctx, "w_to_bf16");
             k_w_to_bf16t<<<dim3(grid_of((int64_t)kin * kout, 256), (unsigned)nb), 256, 0,
@@ -840,10 +856,13 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
     return check_launch(ctx, "chol_inv");
 }
 
-lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb) {
+lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb,
+                   double *vw_ws) {
     if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above 288", k);
     Buf vw(ctx);
-    LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)nb * k * k));
+    // vw_ws (if given) holds nb k k doubles
+    if (vw_ws) vw.p = vw_ws, vw.ctx = nullptr;
+    else LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)nb * k * k));
     // the LDS variant when k^2 doubles fit next to the kernel's static arrays
     static int lds_limit = -1;
     if (lds_limit < 0) {
