@@ -411,7 +411,7 @@ def main():
     kp = p["d"] + p["oversample"]
     es = 8 if p["precision"] == "f64" else 4
     info = dict(n=g.n, nnz_M=stats["nnz_log"], kp=kp, arcs=g.n_arcs, d=p["d"],
-                pairs=2 * stats["accepted"], es=es, nnz_counts=stats["nnz_counts"])
+                pairs=stats["entries"], es=es, nnz_counts=stats["nnz_counts"])
     dominant = max(prof, key=lambda k: prof[k]["ms_per_step"])
     rl_name = dominant if kernel_bytes(dominant, info) is not None else "spmm"
     nbytes = kernel_bytes(rl_name, info)

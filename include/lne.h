@@ -127,6 +127,10 @@ typedef struct {
     uint64_t nnz_log;     /* nnz after the truncated logarithm                   */
     uint32_t shifted;     /* number of shifted Cholesky fallbacks taken          */
     uint32_t reserved;
+    uint64_t entries;     /* pair entries the aggregation sorted: two per       *
+                           * accepted sample, except that each sampler thread's  *
+                           * length-1 samples of one edge (all the pair (u, v)) *
+                           * are merged into one entry per orientation           */
 } lne_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -69,7 +69,8 @@ def make_trial(s, k, theta, mu) -> TrialStruct:
 class Stats(ctypes.Structure):
     _fields_ = [("attempted", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
                 ("nnz_counts", ctypes.c_uint64), ("nnz_log", ctypes.c_uint64),
-                ("shifted", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("shifted", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("entries", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}

@@ -240,22 +240,22 @@ static lne_status sampler_edges(lne_ctx *ctx, const lne_graph *g, Sampler &S) {
 static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
                               int64_t hi, uint64_t *entries, bool stats) {
     Buf scal(ctx);
-    LNE_TRY(alloc(ctx, scal, 16));
-    LNE_HIP(ctx, hipMemsetAsync(scal.p, 0, 16, ctx->stream));
+    LNE_TRY(alloc(ctx, scal, 24));
+    LNE_HIP(ctx, hipMemsetAsync(scal.p, 0, 24, ctx->stream));
     LNE_TRY(launch_sample_count(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), S.m, lo, hi,
                                 S.wc.as<uint32_t>(), S.nw,
                                 stats ? scal.as<unsigned long long>() : nullptr));
     LNE_TRY(scan_u32(ctx, S.wc.as<uint32_t>(), S.wo.as<uint64_t>(), S.nw));
-    uint64_t host[3] = {0, 0, 0};
+    uint64_t host[4] = {0, 0, 0, 0};
     LNE_HIP(ctx, hipMemcpyAsync(&host[0], S.wo.as<uint64_t>() + S.nw, 8, hipMemcpyDeviceToHost,
                                 ctx->stream));
     if (stats)
-        LNE_HIP(ctx, hipMemcpyAsync(&host[1], scal.p, 16, hipMemcpyDeviceToHost, ctx->stream));
+        LNE_HIP(ctx, hipMemcpyAsync(&host[1], scal.p, 24, hipMemcpyDeviceToHost, ctx->stream));
     LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *entries = host[0];
     if (stats) {
         S.attempted = host[1];
-        S.accepted = host[0] / 2;
+        S.accepted = host[3];
         const uint32_t max_w = (uint32_t)host[2];
         if (max_w == 0xFFFFFFFFu)
             return fail(ctx, LNE_EUNSUPPORTED, "a per-sample weight exceeds 2^32 - 1");
@@ -345,6 +345,7 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
         st->attempted = S.attempted;
         st->accepted = S.accepted;
         st->nnz_counts = 0;
+        st->entries = total;
     }
     const double budget = pair_budget(ctx);
     if (total == 0 || range_bytes(total) <= budget) {

@@ -169,10 +169,12 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
                                uint8_t *r);
 // Per-wave pair-entry counts (count pass) and pair emission (emit pass) for
-// the rows [row_lo, row_hi); keys are relative to row_lo.  stats (may be
-// NULL, device, 2 x uint64): [0] = attempted sample slots, [1] = the largest
+// the rows [row_lo, row_hi); keys are relative to row_lo.  A thread's
+// accepted length-1 samples (all the pair (u, v) of its edge with one weight)
+// are merged into as few entries as keep each sum below 2^32.  stats (may be
+// NULL, device, 3 x uint64): [0] = attempted sample slots, [1] = the largest
 // per-sample fixed-point weight of an edge with an accepted sample
-// (saturated at 2^32 - 1).
+// (saturated at 2^32 - 1), [2] = accepted samples.
 lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                                int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,

@@ -158,6 +158,24 @@ __device__ __forceinline__ int walk_pair(const SamplePlan &pl, const int64_t *__
     return r;
 }
 
+// Every accepted length-1 sample of edge e is the pair (u, v) itself with the
+// same weight (its path is the edge alone, h = 1 / (1 / A_uv)), so a thread
+// merges its chunk's length-1 samples into entries of up to
+// r1_group(w) samples each (the sum stays below 2^32); the walks of the
+// longer samples are emitted one by one.  Count and emit passes use the same
+// rule, so the pair stream is compact and its sums are those of the slots.
+template <bool W>
+__device__ __forceinline__ uint64_t weight_r1(const SamplePlan &pl, const Coin &cn, int64_t e) {
+    if constexpr (!W) return cn.w;
+    const double inv = 1.0 / (double)pl.ea[e];
+    return sample_weight(1.0 / inv, cn.all, cn.p);
+}
+
+__device__ __forceinline__ uint64_t r1_group(uint64_t w) {
+    const uint64_t g = w ? 0xFFFFFFFFull / w : 1;
+    return g ? g : 1;
+}
+
 // Structural check of the input CSR (bit 1: offsets, 2: column range,
 // 4: self-loop, 8: unsorted or duplicate column).  A group of 16 lanes walks
 // one row's arcs in coalesced strides, so a hub row costs its degree / 16
@@ -225,26 +243,30 @@ __global__ void __launch_bounds__(kBlock)
 k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                const int32_t *__restrict__ eu, const int32_t *__restrict__ ev, int64_t m,
                int64_t row_lo, int64_t row_hi, uint32_t *__restrict__ wave_cnt,
-               unsigned long long *__restrict__ att_part, uint32_t *__restrict__ wmax_part) {
+               unsigned long long *__restrict__ att_part, uint32_t *__restrict__ wmax_part,
+               unsigned long long *__restrict__ acc_part) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t e = t / pl.chunks;
     const int64_t c = t - e * pl.chunks;
     uint32_t cnt = 0;
     uint64_t att = 0;
     uint64_t wmax = 0;
+    uint32_t acc = 0;
     if (e < m) {
         const int32_t u = eu[e], v = ev[e];
         const Coin cn = coin_of<W>(pl, rp, e, u, v);
         const uint64_t ne = draw_ne(pl, e);
         const uint64_t j0 = (uint64_t)c * pl.J;
         const uint64_t j1 = min(j0 + (uint64_t)pl.J, ne);
-        uint32_t acc = 0;
+        uint64_t c1 = 0;   // accepted length-1 samples (merged)
         for (uint64_t j = j0; j < j1; ++j) {
             const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
             const bool ok = cn.all || (uint64_t)b0.x < cn.tau;
             if (!ok) continue;
             ++acc;
-            if (FILTER) {
+            if (draw_r(pl, b0.y) == 1) {
+                ++c1;
+            } else if (FILTER) {
                 int32_t a = u, b = v;
                 walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
                 cnt += (a >= row_lo && a < row_hi) ? 1u : 0u;
@@ -253,16 +275,26 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
                 cnt += 2;
             }
         }
+        if (c1) {
+            const uint64_t g = r1_group(weight_r1<W>(pl, cn, e));
+            const uint32_t nm = (uint32_t)((c1 + g - 1) / g);
+            const uint32_t per = FILTER ? ((u >= row_lo && u < row_hi) ? 1u : 0u) +
+                                              ((v >= row_lo && v < row_hi) ? 1u : 0u)
+                                        : 2u;
+            cnt += nm * per;
+        }
         att = j1 > j0 ? j1 - j0 : 0;
         // weighted: r / sum_j 1/A_j <= r A_uv (the centre edge's term alone),
         // so rint(2^16 T A_uv / p_e) bounds every sample weight of the edge
         wmax = acc ? (W ? sample_weight((double)pl.T * (double)pl.ea[e], cn.all, cn.p) : cn.w)
                    : 0;
     }
+    uint64_t accw = acc;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         cnt += __shfl_xor(cnt, off, 64);
         att += __shfl_xor(att, off, 64);
+        accw += __shfl_xor(accw, off, 64);
         const uint64_t o = __shfl_xor(wmax, off, 64);
         wmax = o > wmax ? o : wmax;
     }
@@ -270,45 +302,53 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
     // per-block partial statistics (one writer per block, folded afterwards:
     // a device-wide atomic per wave would serialise millions of updates)
     if (att_part) {
-        __shared__ unsigned long long s_att[kBlock / 64];
+        __shared__ unsigned long long s_att[kBlock / 64], s_acc[kBlock / 64];
         __shared__ uint64_t s_max[kBlock / 64];
         if ((threadIdx.x & 63) == 0) {
             s_att[threadIdx.x >> 6] = att;
+            s_acc[threadIdx.x >> 6] = accw;
             s_max[threadIdx.x >> 6] = wmax;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            unsigned long long a = 0;
+            unsigned long long a = 0, ac = 0;
             uint64_t w = 0;
             for (int i = 0; i < kBlock / 64; ++i) {
                 a += s_att[i];
+                ac += s_acc[i];
                 w = s_max[i] > w ? s_max[i] : w;
             }
             att_part[blockIdx.x] = a;
+            acc_part[blockIdx.x] = ac;
             wmax_part[blockIdx.x] = w > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)w;
         }
     }
 }
 
-// out[0] = sum of att_part, out[1] (as uint32) = max of wmax_part; one block.
+// out[0] = sum of att_part, out[1] (as uint32) = max of wmax_part, out[2] =
+// sum of acc_part; one block.
 __global__ void __launch_bounds__(1024)
 k_fold_stats(const unsigned long long *__restrict__ att_part,
-             const uint32_t *__restrict__ wmax_part, int64_t n,
+             const uint32_t *__restrict__ wmax_part,
+             const unsigned long long *__restrict__ acc_part, int64_t n,
              unsigned long long *__restrict__ out) {
-    __shared__ unsigned long long sa[1024];
+    __shared__ unsigned long long sa[1024], sc[1024];
     __shared__ uint32_t sm[1024];
-    unsigned long long a = 0;
+    unsigned long long a = 0, ac = 0;
     uint32_t w = 0;
     for (int64_t i = threadIdx.x; i < n; i += 1024) {
         a += att_part[i];
+        ac += acc_part[i];
         w = wmax_part[i] > w ? wmax_part[i] : w;
     }
     sa[threadIdx.x] = a;
+    sc[threadIdx.x] = ac;
     sm[threadIdx.x] = w;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             sa[threadIdx.x] += sa[threadIdx.x + o];
+            sc[threadIdx.x] += sc[threadIdx.x + o];
             sm[threadIdx.x] = sm[threadIdx.x + o] > sm[threadIdx.x] ? sm[threadIdx.x + o]
                                                                     : sm[threadIdx.x];
         }
@@ -317,6 +357,7 @@ k_fold_stats(const unsigned long long *__restrict__ att_part,
     if (threadIdx.x == 0) {
         out[0] = sa[0];
         out[1] = sm[0];
+        out[2] = sc[0];
     }
 }
 
@@ -347,6 +388,26 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
     }
     uint32_t w = (uint32_t)cn.w;
     const int kb = pl.colbits + pl.cbits;
+    uint64_t c1 = 0;   // accepted length-1 samples, emitted merged below
+    // writes the entries (a, b) and (b, a) that fall in the row range, at
+    // this lane's place in the wave's contiguous output
+    auto put = [&](bool ina, bool inb, int32_t a, int32_t b, uint64_t ch, uint32_t wv) {
+        const uint32_t cnt = (ina ? 1u : 0u) + (inb ? 1u : 0u);
+        const uint64_t m0 = __ballot(cnt & 1u), m1 = __ballot(cnt & 2u);
+        uint64_t idx = pos + (uint64_t)__popcll(m0 & lt) + 2ull * (uint64_t)__popcll(m1 & lt);
+        if (ina) {
+            keys[idx] = ((uint64_t)(uint32_t)(a - row_lo) << kb) |
+                        ((uint64_t)(uint32_t)b << pl.cbits) | ch;
+            vals[idx] = wv;
+            ++idx;
+        }
+        if (inb) {
+            keys[idx] = ((uint64_t)(uint32_t)(b - row_lo) << kb) |
+                        ((uint64_t)(uint32_t)a << pl.cbits) | ch;
+            vals[idx] = wv;
+        }
+        pos += (uint64_t)__popcll(m0) + 2ull * (uint64_t)__popcll(m1);
+    };
     for (int64_t jj = 0; jj < pl.J; ++jj) {
         const uint64_t j = j0 + (uint64_t)jj;
         bool ina = false, inb = false;
@@ -355,30 +416,40 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
         if (e < m && j < ne) {
             const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
             if (cn.all || (uint64_t)b0.x < cn.tau) {
-                double h;
-                const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b, &h);
-                // the count pass bounded this below 2^32
-                if (W) w = (uint32_t)sample_weight(h, cn.all, cn.p);
-                ina = a >= row_lo && a < row_hi;
-                inb = b >= row_lo && b < row_hi;
-                ch = pl.cbits ? (uint64_t)(r - 1) : 0;
+                if (draw_r(pl, b0.y) == 1) {
+                    ++c1;
+                } else {
+                    double h;
+                    const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b, &h);
+                    // the count pass bounded this below 2^32
+                    if (W) w = (uint32_t)sample_weight(h, cn.all, cn.p);
+                    ina = a >= row_lo && a < row_hi;
+                    inb = b >= row_lo && b < row_hi;
+                    ch = pl.cbits ? (uint64_t)(r - 1) : 0;
+                }
             }
         }
-        const uint32_t cnt = (ina ? 1u : 0u) + (inb ? 1u : 0u);
-        const uint64_t m0 = __ballot(cnt & 1u), m1 = __ballot(cnt & 2u);
-        uint64_t idx = pos + (uint64_t)__popcll(m0 & lt) + 2ull * (uint64_t)__popcll(m1 & lt);
-        if (ina) {
-            keys[idx] = ((uint64_t)(uint32_t)(a - row_lo) << kb) |
-                        ((uint64_t)(uint32_t)b << pl.cbits) | ch;
-            vals[idx] = w;
-            ++idx;
-        }
-        if (inb) {
-            keys[idx] = ((uint64_t)(uint32_t)(b - row_lo) << kb) |
-                        ((uint64_t)(uint32_t)a << pl.cbits) | ch;
-            vals[idx] = w;
-        }
-        pos += (uint64_t)__popcll(m0) + 2ull * (uint64_t)__popcll(m1);
+        put(ina, inb, a, b, ch, w);
+    }
+    // the merged length-1 samples: ceil(c1 / g) entries of up to g samples
+    uint64_t g = 1, w1 = 0;
+    uint32_t nm = 0;
+    if (c1) {
+        w1 = weight_r1<W>(pl, cn, e);
+        g = r1_group(w1);
+        nm = (uint32_t)((c1 + g - 1) / g);
+    }
+    uint32_t nmax = nm;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(nmax, off, 64);
+        nmax = o > nmax ? o : nmax;
+    }
+    for (uint32_t q = 0; q < nmax; ++q) {
+        const bool has = q < nm;
+        const uint64_t cq = has ? min(g, c1 - (uint64_t)q * g) : 0;
+        put(has && u >= row_lo && u < row_hi, has && v >= row_lo && v < row_hi, u, v, 0,
+            (uint32_t)(cq * w1));
     }
 }
 
@@ -628,18 +699,21 @@ lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePla
     if (threads / 64 != n_waves) return fail(ctx, LNE_EINVAL, "sampler wave count mismatch");
     const bool filter = !(row_lo <= 0 && row_hi >= g->n);
     const int64_t nblocks = threads / kBlock;
-    Buf ap(ctx), wp(ctx);
+    Buf ap(ctx), wp(ctx), cp(ctx);
     if (stats) {
         LNE_TRY(alloc(ctx, ap, sizeof(unsigned long long) * (size_t)(nblocks > 0 ? nblocks : 1)));
         LNE_TRY(alloc(ctx, wp, sizeof(uint32_t) * (size_t)(nblocks > 0 ? nblocks : 1)));
+        LNE_TRY(alloc(ctx, cp, sizeof(unsigned long long) * (size_t)(nblocks > 0 ? nblocks : 1)));
     }
     unsigned long long *att_part = stats ? ap.as<unsigned long long>() : nullptr;
     uint32_t *wmax_part = stats ? wp.as<uint32_t>() : nullptr;
+    unsigned long long *acc_part = stats ? cp.as<unsigned long long>() : nullptr;
     {
         Launch L(ctx, filter ? "sample_count_range" : "sample_count");
 #define LNE_CNT(FF, WW)                                                                    \
     k_sample_count<FF, WW><<<(unsigned)nblocks, kBlock, 0, ctx->stream>>>(                 \
-        pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part)
+        pl, g->row_ptr, g->col, eu, ev, m, row_lo, row_hi, wave_cnt, att_part, wmax_part,  \
+        acc_part)
         if (filter) {
             if (pl.wt) LNE_CNT(true, true);
             else LNE_CNT(true, false);
@@ -652,7 +726,8 @@ lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePla
     LNE_TRY(check_launch(ctx, "sample_count"));
     if (stats) {
         Launch L(ctx, "fold_stats");
-        k_fold_stats<<<1, 1024, 0, ctx->stream>>>(att_part, wmax_part, nblocks, stats);
+        k_fold_stats<<<1, 1024, 0, ctx->stream>>>(att_part, wmax_part, acc_part, nblocks,
+                                                   stats);
     }
     return check_launch(ctx, "fold_stats");
 }
