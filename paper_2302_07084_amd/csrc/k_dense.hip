@@ -33,15 +33,30 @@ __device__ __forceinline__ void upper_tile(int t, int nt, int &I, int &J) {
 constexpr int kGramRows = 32;
 constexpr int kGramThreads = 512;
 
-template <class YT, int MAXT>
-__global__ void __launch_bounds__(kGramThreads)
+// Widest padded k whose upper 16 x 16 tiles fit SPLIT blocks of 8 waves x
+// MAXT tiles.
+constexpr int gram_kp_max(int maxt, int split) {
+    int nt = 1;
+    while ((nt + 1) * (nt + 2) / 2 <= 8 * maxt * split) ++nt;
+    return 16 * nt;
+}
+
+// Two LDS tiles of kGramRows rows: the next tile's loads are issued into
+// registers before the matrix-core steps of the current one and stored to
+// the other buffer after them, so one block barrier per tile separates them.
+// SPLIT blocks (blockIdx.z) share a row range and take alternate groups of 8
+// output tiles, so that a wide k keeps its accumulators in registers.
+template <class YT, int MAXT, int SPLIT>
+__global__ void __launch_bounds__(kGramThreads, (MAXT <= 6 && sizeof(YT) == 4) ? 4 : 2)
 k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t rows_per_wg,
          double *__restrict__ part, const int32_t *__restrict__ skip, int64_t ys) {
     Y += (int64_t)blockIdx.y * ys;
     part += (int64_t)blockIdx.y * gridDim.x * KP * KP;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ double tile[kGramRows * 288];       // kGramRows x KP
+    constexpr int KPM = gram_kp_max(MAXT, SPLIT);
+    constexpr int kLd = (kGramRows * KPM + kGramThreads - 1) / kGramThreads;
+    __shared__ double tile[2][kGramRows * KPM];       // kGramRows x KP each
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
     int TI[MAXT], TJ[MAXT];
@@ -49,22 +64,43 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
         acc[s] = (v4d){0, 0, 0, 0};
-        const int t = w + 8 * s;
+        const int t = w + 8 * ((int)blockIdx.z + SPLIT * s);
         if (t < ntu) upper_tile(t, nt, TI[s], TJ[s]); else { TI[s] = TJ[s] = -1; }
     }
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
     const int64_t r_end = min(n, r_begin + rows_per_wg);
     const int kr = lane >> 4, kc = lane & 15;
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows) {
-        for (int idx = tid; idx < kGramRows * KP; idx += kGramThreads) {
+    const int tsz = kGramRows * KP;
+    // staged in the input type (half the registers for FP32 data)
+    auto gload = [&](int64_t r0, YT v[kLd]) {
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int idx = tid + u * kGramThreads;
             const int rr = idx / KP, c = idx - rr * KP;
             const int64_t row = r0 + rr;
-            tile[idx] = (row < r_end && c < k) ? to_d(Y[row * ld + c]) : 0.0;
+            v[u] = (idx < tsz && row < r_end && c < k) ? Y[row * ld + c] : (YT)0;
         }
-        __syncthreads();
+    };
+    auto lstore = [&](int buf, const YT v[kLd]) {
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int idx = tid + u * kGramThreads;
+            if (idx < tsz) tile[buf][idx] = to_d(v[u]);
+        }
+    };
+    YT v[kLd];
+    if (r_begin < r_end) {
+        gload(r_begin, v);
+        lstore(0, v);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows, cur ^= 1) {
+        const bool more = r0 + kGramRows < r_end;
+        if (more) gload(r0 + kGramRows, v);
 #pragma unroll
         for (int kk = 0; kk < kGramRows; kk += 4) {
-            const double *trow = tile + (kk + kr) * KP + kc;
+            const double *trow = tile[cur] + (kk + kr) * KP + kc;
 #pragma unroll
             for (int s = 0; s < MAXT; ++s) {
                 if (TI[s] >= 0) {
@@ -74,6 +110,7 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
                 }
             }
         }
+        if (more) lstore(cur ^ 1, v);
         __syncthreads();
     }
     double *P = part + (int64_t)blockIdx.x * KP * KP;
@@ -746,7 +783,7 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     {
         Launch L(ctx, "gram");
         if (dtype == LNE_BF16) {
-#define LNE_GB(MT)                                                                       \
+#define LNE_GB(MT)                                                                         \
     k_gram_bf16<MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
         (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys, vec)
             if (per_wave <= 1) LNE_GB(1);
@@ -755,19 +792,19 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
             else LNE_GB(22);
 #undef LNE_GB
         } else {
-#define LNE_G64(T, MT)                                                                   \
-    k_gram64<T, MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
+#define LNE_G64(T, MT, SP)                                                               \
+    k_gram64<T, MT, SP><<<dim3(grid.x, grid.y, SP), kGramThreads, 0, ctx->stream>>>(   \
         (const T *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys)
             if (dtype == LNE_F64) {
-                if (per_wave <= 1) LNE_G64(double, 1);
-                else if (per_wave <= 6) LNE_G64(double, 6);
-                else if (per_wave <= 12) LNE_G64(double, 12);
-                else LNE_G64(double, 22);
+                if (per_wave <= 1) LNE_G64(double, 1, 1);
+                else if (per_wave <= 6) LNE_G64(double, 6, 1);
+                else if (per_wave <= 12) LNE_G64(double, 12, 1);
+                else LNE_G64(double, 11, 2);
             } else {
-                if (per_wave <= 1) LNE_G64(float, 1);
-                else if (per_wave <= 6) LNE_G64(float, 6);
-                else if (per_wave <= 12) LNE_G64(float, 12);
-                else LNE_G64(float, 22);
+                if (per_wave <= 1) LNE_G64(float, 1, 1);
+                else if (per_wave <= 6) LNE_G64(float, 6, 1);
+                else if (per_wave <= 12) LNE_G64(float, 12, 1);
+                else LNE_G64(float, 11, 2);
             }
 #undef LNE_G64
         }
