@@ -300,16 +300,21 @@ __global__ void __launch_bounds__(kT) k_reduce(const uint64_t *__restrict__ keys
 }
 
 // Segmented sum fused with Eq. (1).  Each wave owns a contiguous chunk of
-// kRChunk items and walks it 64 at a time with no block barrier (the next 64
-// items' loads are issued before the current ones are reduced); the unique
-// index of a run comes from the chunk's head offset (k_chunk_heads + scan)
-// and the wave's running head count.  A wave sums each run of equal keys
-// with a segmented scan; the lane holding a run's last item in the 64 where
-// the run starts owns it (if the run goes on past them, that lane adds the
-// rest from memory) and writes the column and ln x (kept) or 0 (dropped).
-// Row offsets as in k_reduce.  Each distinct pair is written by exactly one
-// lane with an integer sum, so the result does not depend on the launch shape.
+// kRChunk items and walks it 64 at a time with no block barrier, the loads of
+// the next kPF groups of 64 in flight while the current one is reduced.  The
+// unique index of a run comes from the chunk's head offset (k_chunk_heads +
+// scan) and the wave's running head count.  A wave sums each run of equal
+// keys with a segmented scan and carries the open run's partial sum from one
+// group to the next; the lane holding a run's last item owns it and writes
+// the column and ln x (kept) or 0 (dropped).  A run that goes on past the
+// chunk is finished by the same wave, which reads on 64 keys at a time and
+// finds the run's end with a ballot (a lane adding a long run item by item
+// waits one memory latency per item, and a few pairs of hubs have runs of
+// thousands); the next chunk's wave skips that run.  Row offsets as in
+// k_reduce.  Each distinct pair is written by exactly one lane with an
+// integer sum, so the result does not depend on the launch shape.
 constexpr int kRChunk = 1024;
+constexpr int kPF = 4;   // groups of 64 items a reducing wave has in flight
 
 __global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__ keys, int64_t n,
                                                     int64_t nchunks,
@@ -319,9 +324,24 @@ __global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__
     if (w >= nchunks) return;
     const int64_t base = w * kRChunk;
     uint32_t c = 0;
-    for (int it = 0; it < kRChunk / 64; ++it) {
-        const int64_t i = base + it * 64 + lane;
-        if (i < n && (i == 0 || keys[i] != keys[i - 1])) ++c;
+    // kPF groups of 64 keys loaded at a time; the key before a group's lane 0
+    // is the previous group's lane 63 key
+    uint64_t prev_last = base > 0 ? keys[base - 1] : ~0ull;
+    for (int it0 = 0; it0 < kRChunk / 64; it0 += kPF) {
+        uint64_t kq[kPF];
+#pragma unroll
+        for (int g = 0; g < kPF; ++g) {
+            const int64_t i = base + (it0 + g) * 64 + lane;
+            kq[g] = i < n ? keys[i] : ~0ull;
+        }
+#pragma unroll
+        for (int g = 0; g < kPF; ++g) {
+            const int64_t i = base + (it0 + g) * 64 + lane;
+            uint64_t prev = __shfl_up(kq[g], 1, 64);
+            if (lane == 0) prev = prev_last;
+            prev_last = __shfl(kq[g], 63, 64);
+            if (i < n && (i == 0 || kq[g] != prev)) ++c;
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
@@ -343,64 +363,14 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
     const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
     if (w >= nchunks) return;
     const int64_t base = w * kRChunk;
+    const int64_t cend = min(n, base + kRChunk);          // end of this chunk
     const uint64_t colmask = (1ull << colbits) - 1;
     const uint64_t keymask = tagged ? (1ull << kTagShift) - 1 : ~0ull;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint64_t running = head_off[w];   // heads before these 64 items
+    uint64_t running = head_off[w];   // heads before the current 64 items
     uint32_t my_kept = 0;
-    // items of the first 64 (prev = the key before each)
-    uint64_t key_n = 0, prev_n = 0, v_n = 0;
-    {
-        const int64_t i = base + lane;
-        if (i < n) {
-            key_n = keys[i];
-            v_n = vals[i];
-            prev_n = i > 0 ? keys[i - 1] : ~0ull;
-        }
-    }
-    for (int it = 0; it < kRChunk / 64; ++it) {
-        const int64_t i = base + it * 64 + lane;
-        if (base + it * 64 >= n) break;                       // wave-uniform
-        const bool valid = i < n;
-        const uint64_t key = key_n, prev = prev_n;
-        uint64_t v = valid ? v_n : 0;
-        // the next 64 items' loads go out before this reduction
-        const bool more = it + 1 < kRChunk / 64;
-        if (more) {
-            const int64_t j = i + 64;
-            if (j < n) {
-                key_n = keys[j];
-                v_n = vals[j];
-                prev_n = keys[j - 1];
-            }
-        }
-        // the key after lane 63's item, from the prefetched registers
-        const uint64_t after = __shfl(key_n, 0, 64);
-        const bool head = valid && (i == 0 || key != prev);
-        const uint64_t hm = __ballot(head);
-        const uint64_t u = running + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
-        running += (uint64_t)__popcll(hm);
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t ov = __shfl_up(v, off, 64);
-            const uint64_t ou = __shfl_up(u, off, 64);
-            if (lane >= off && ou == u) v += ov;
-        }
-        const uint64_t nu = __shfl_down(u, 1, 64);
-        if (!valid) continue;
-        if (head) {
-            const int64_t row = (int64_t)((key & keymask) >> colbits);
-            const int64_t prow = i == 0 ? -1 : (int64_t)((prev & keymask) >> colbits);
-            for (int64_t r = prow + 1; r <= row; ++r) rowptr[r] = (int64_t)u;
-        }
-        const bool started_here = (hm & (lt | (1ull << lane))) != 0;
-        const bool last_here = lane == 63 || i + 1 >= n || nu != u;
-        if (!(started_here && last_here)) continue;
-        uint64_t W = v;
-        // a run that goes on past these 64 items: the rest from memory (the
-        // next key is in registers unless these are the chunk's last 64)
-        if (lane == 63 && i + 1 < n && (!more || after == key))
-            for (int64_t j = i + 1; j < n && keys[j] == key; ++j) W += vals[j];
+    // Eq. (1) for the run of `key` with weight sum W and unique index u
+    auto finish = [&](uint64_t key, uint64_t W, uint64_t u) {
         const int32_t b = (int32_t)(key & colmask);
         const int64_t row = (int64_t)((key & keymask) >> colbits);
         const uint64_t da = deg[row_lo + row];
@@ -410,6 +380,101 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         col[u] = b;
         val[u] = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
         my_kept += k ? 1u : 0u;
+    };
+    // kPF groups of 64 items in flight: group it lives in ring slot it % kPF
+    // until group it + kPF replaces it
+    uint64_t kq[kPF];
+    uint32_t vq[kPF];
+#pragma unroll
+    for (int g = 0; g < kPF; ++g) {
+        const int64_t i = base + g * 64 + lane;
+        kq[g] = i < cend ? keys[i] : ~0ull;
+        vq[g] = i < cend ? vals[i] : 0u;
+    }
+    // the key before each group's lane 0 (the last key of the group before),
+    // and the first key of the next chunk
+    uint64_t prev_last = base > 0 ? keys[base - 1] : ~0ull;
+    const uint64_t next_first = cend < n ? keys[cend] : ~0ull;
+    // the chunk's first run continues the previous chunk's last run: that
+    // wave sums it, this one skips it (until its first head)
+    bool skipping = base > 0 && __shfl(kq[0], 0, 64) == prev_last;
+    uint64_t carry = 0;               // the open run's sum in earlier groups
+    uint64_t last_key = 0;
+    bool open_end = false;            // the last group's last run goes on
+    for (int it0 = 0; it0 < kRChunk / 64; it0 += kPF) {
+#pragma unroll
+        for (int g = 0; g < kPF; ++g) {
+            const int it = it0 + g;
+            const int64_t i = base + it * 64 + lane;
+            if (base + it * 64 >= cend) break;                 // wave-uniform
+            const bool valid = i < cend;
+            const uint64_t key = kq[g];
+            uint64_t v = valid ? vq[g] : 0;
+            const bool more = it + 1 < kRChunk / 64 && base + (it + 1) * 64 < cend;
+            // the key after lane 63's item, taken before its slot is reused
+            const uint64_t after =
+                more ? __shfl(kq[(g + 1) % kPF], 0, 64) : next_first;
+            // the loads of group it + kPF go out before this reduction
+            if (it + kPF < kRChunk / 64) {
+                const int64_t j = i + 64 * kPF;
+                kq[g] = j < cend ? keys[j] : ~0ull;
+                vq[g] = j < cend ? vals[j] : 0u;
+            }
+            uint64_t prev = __shfl_up(key, 1, 64);
+            if (lane == 0) prev = prev_last;
+            prev_last = __shfl(key, 63, 64);
+            const bool head = valid && (i == 0 || key != prev);
+            const uint64_t hm = __ballot(head);
+            const uint64_t u = running + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
+            running += (uint64_t)__popcll(hm);
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint64_t ov = __shfl_up(v, off, 64);
+                const uint64_t ou = __shfl_up(u, off, 64);
+                if (lane >= off && ou == u) v += ov;
+            }
+            // lanes before the group's first head continue the open run
+            const bool first_seg = (hm & (lt | (1ull << lane))) == 0;
+            if (first_seg) v += carry;
+            uint64_t nxt = __shfl_down(key, 1, 64);
+            if (lane == 63) nxt = after;
+            const bool ends = valid && (i + 1 >= n || nxt != key);
+            // the sum so far of a run still open after lane 63's item
+            const int last = (int)min((int64_t)63, cend - 1 - (base + it * 64));
+            const uint64_t vl = __shfl(v, last, 64);
+            const bool open = __shfl((int)(valid && !ends), last, 64) != 0;
+            carry = open ? vl : 0;
+            last_key = __shfl(key, last, 64);
+            open_end = open;
+            const bool skip = skipping && first_seg;
+            if (hm) skipping = false;
+            if (head) {
+                const int64_t row = (int64_t)((key & keymask) >> colbits);
+                const int64_t prow = i == 0 ? -1 : (int64_t)((prev & keymask) >> colbits);
+                for (int64_t r = prow + 1; r <= row; ++r) rowptr[r] = (int64_t)u;
+            }
+            if (!valid || !ends || skip) continue;
+            finish(key, v, u);
+        }
+    }
+    // The run still open at the chunk's end, unless the chunk had no head
+    // (then all of it continues the previous chunk's run, which that wave
+    // finishes): read on, 64 keys at a time, until it ends.
+    if (open_end && !skipping) {
+        uint64_t W = carry;
+        for (int64_t j0 = cend; j0 < n; j0 += 64) {
+            const int64_t j = j0 + lane;
+            const uint64_t kj = j < n ? keys[j] : ~0ull;
+            const bool same = j < n && kj == last_key;
+            const uint64_t m = __ballot(same);
+            const int cnt = m == ~0ull ? 64 : __builtin_ctzll(~m);   // leading matches
+            uint64_t s2 = lane < cnt ? (uint64_t)vals[j] : 0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            W += s2;
+            if (cnt < 64) break;
+        }
+        if (lane == 0) finish(last_key, W, running - 1);
     }
     // the chunk's count of kept entries (summed by a scan afterwards: one
     // counter hit by every wave serialises the whole grid on it)
