@@ -273,6 +273,8 @@ def main():
                     help="permute the workload's vertex ids with this seed first (the "
                          "generators number vertices in degree order; real graphs do not)")
     ap.add_argument("--automl-trials", type=int, default=64)
+    ap.add_argument("--automl-seeds", type=int, default=3,
+                    help="independent repetitions of the AutoML report (95%% intervals)")
     ap.add_argument("--pretrain-trials", type=int, default=64,
                     help="surrogate pretraining trials per family graph (8 graphs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -332,7 +334,7 @@ def main():
         return
     if args.report == "automl":
         automl_report(args.workload if args.workload != "large" else "batched",
-                      args.automl_trials, args.pretrain_trials)
+                      args.automl_trials, args.pretrain_trials, args.automl_seeds)
         return
     if args.report == "linkpred":
         linkpred_report(args.workload)
@@ -865,7 +867,20 @@ def mfma_report():
     print(json.dumps(out), flush=True)
 
 
-def automl_report(name, budget, pretrain_per_graph):
+def _ci95(x):
+    """Mean and half-width of the 95% t-interval of the values x."""
+    import numpy as np
+    import scipy.stats
+    x = np.asarray([v for v in x if v is not None], dtype=float)
+    if len(x) == 0:
+        return None, None
+    if len(x) == 1:
+        return float(x[0]), None
+    return float(x.mean()), float(scipy.stats.t.ppf(0.975, len(x) - 1) * x.std(ddof=1) /
+                                  math.sqrt(len(x)))
+
+
+def automl_report(name, budget, pretrain_per_graph, seeds=3):
     """Hyperparameter search on the batched-trials workload, two arms on the
     same GPU, the same search space, scorer and splits:
       plain      one trial after another, each with its own sampling pass
@@ -874,9 +889,11 @@ def automl_report(name, budget, pretrain_per_graph):
                  batch (HIP graph replay) and scored in one call, proposed by
                  the surrogate (pretrained on a family of smaller graphs,
                  refitted after each round)
-    Reports trials/s with and without scoring and the wall time each arm
-    needs to reach the better arm's best score minus its 95% interval over
-    the scoring splits."""
+    Repeated over `seeds` seeds (pretraining trials, surrogate initialisation
+    and both arms' proposals drawn anew; the graphs stay the same).  Per seed:
+    trials/s with and without scoring and the wall time each arm needs to
+    reach the better arm's best score minus its 95% interval over the scoring
+    splits; over the seeds: means with 95% t-intervals."""
     import numpy as np
     import torch
 
@@ -894,34 +911,13 @@ def automl_report(name, budget, pretrain_per_graph):
         family.append(search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=100 + i))
     t_fam = time.perf_counter() - t0
     log(f"automl: {len(family)} family graphs in {t_fam:.1f}s")
-    t0 = time.perf_counter()
-    F, y = search.pretrain_pairs(ctx, family, pretrain_per_graph, np.random.default_rng(0))
-    t_pairs = time.perf_counter() - t0
-    sur = search.Surrogate(ctx, seed=0)
-    sur.set_scaler(F)
-    sur.add(F, y)
-    t0 = time.perf_counter()
-    loss = sur.fit(epochs=800)
-    torch.cuda.synchronize()
-    t_fit = time.perf_counter() - t0
-    log(f"automl: surrogate pretrained on {len(y)} trials ({t_pairs:.1f}s batched runs, "
-        f"{t_fit:.1f}s fit, loss {loss})")
-    del family
-
     g, p = workload(name, device="cuda")
     task = search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=0)
-    log(f"automl: target graph n={g.n} m={g.m}, budget {budget} trials per arm")
+    log(f"automl: target graph n={g.n} m={g.m}, budget {budget} trials per arm, {seeds} seeds")
     # warm both paths once so that neither arm pays first-launch costs
     w = search.sample_trials(np.random.default_rng(9), 1)
     search.plain_sequential_search(ctx, task, w)
     torch.cuda.synchronize()
-
-    trials_a = search.sample_trials(np.random.default_rng(1), budget)
-    sa, ta, ea = search.plain_sequential_search(ctx, task, trials_a)
-    log(f"automl: plain arm {ta[-1]:.1f}s, best {sa.mean(axis=1).max():.4f}")
-    tb, sb, stb, eb, setup = search.batched_surrogate_search(ctx, task, sur, budget,
-                                                             np.random.default_rng(2))
-    log(f"automl: batched arm {stb[-1]:.1f}s (set-up {setup:.1f}s), best {sb.mean(axis=1).max():.4f}")
 
     def best_ci(sc):
         m = sc.mean(axis=1)
@@ -929,36 +925,77 @@ def automl_report(name, budget, pretrain_per_graph):
         half = 1.96 * sc[i].std(ddof=1) / math.sqrt(sc.shape[1]) if sc.shape[1] > 1 else 0.0
         return float(m[i]), float(half)
 
-    ba, ca = best_ci(sa)
-    bb, cb = best_ci(sb)
-    target = (ba - ca) if ba >= bb else (bb - cb)
+    runs = []
+    for seed in range(seeds):
+        t0 = time.perf_counter()
+        F, y = search.pretrain_pairs(ctx, family, pretrain_per_graph,
+                                     np.random.default_rng(seed))
+        t_pairs = time.perf_counter() - t0
+        sur = search.Surrogate(ctx, seed=seed)
+        sur.set_scaler(F)
+        sur.add(F, y)
+        t0 = time.perf_counter()
+        loss = sur.fit(epochs=800)
+        torch.cuda.synchronize()
+        t_fit = time.perf_counter() - t0
+        log(f"automl seed {seed}: surrogate pretrained on {len(y)} trials ({t_pairs:.1f}s batched "
+            f"runs, {t_fit:.1f}s fit, loss {loss})")
+        trials_a = search.sample_trials(np.random.default_rng(1000 + seed), budget)
+        sa, ta, ea = search.plain_sequential_search(ctx, task, trials_a)
+        log(f"automl seed {seed}: plain arm {ta[-1]:.1f}s, best {sa.mean(axis=1).max():.4f}")
+        tb, sb, stb, eb, setup = search.batched_surrogate_search(
+            ctx, task, sur, budget, np.random.default_rng(2000 + seed))
+        log(f"automl seed {seed}: batched arm {stb[-1]:.1f}s (set-up {setup:.1f}s), "
+            f"best {sb.mean(axis=1).max():.4f}")
+        ba, ca = best_ci(sa)
+        bb, cb = best_ci(sb)
+        target = (ba - ca) if ba >= bb else (bb - cb)
 
-    def time_to(sc, stamps):
-        run = np.maximum.accumulate(sc.mean(axis=1))
-        hit = np.flatnonzero(run >= target)
-        return float(stamps[hit[0]]) if len(hit) else None
+        def time_to(sc, stamps):
+            run = np.maximum.accumulate(sc.mean(axis=1))
+            hit = np.flatnonzero(run >= target)
+            return float(stamps[hit[0]]) if len(hit) else None
 
-    def arm(sc, stamps, embed_s, extra):
-        return dict(extra, trials=len(stamps), seconds=float(stamps[-1]),
-                    trials_per_s=len(stamps) / float(stamps[-1]),
-                    trials_per_s_embedding_only=len(stamps) / embed_s,
-                    best_micro_f1=float(sc.mean(axis=1).max()),
-                    mean_micro_f1=float(sc.mean()), seconds_to_target=time_to(sc, stamps))
+        def arm(sc, stamps, embed_s, extra):
+            return dict(extra, trials=len(stamps), seconds=float(stamps[-1]),
+                        trials_per_s=len(stamps) / float(stamps[-1]),
+                        trials_per_s_embedding_only=len(stamps) / embed_s,
+                        best_micro_f1=float(sc.mean(axis=1).max()),
+                        mean_micro_f1=float(sc.mean()), seconds_to_target=time_to(sc, stamps))
 
+        r = {"seed": seed, "target_micro_f1": target,
+             "arms": {"plain_sequential": arm(sa, ta, ea, {"proposals": "random"}),
+                      "batched_surrogate": arm(sb, stb, eb, {"proposals": "surrogate, 25% random",
+                                                             "per_round": 16,
+                                                             "setup_seconds": setup})},
+             "surrogate_pretraining": {"graphs": 8, "trials": int(len(y)),
+                                       "batched_run_seconds": t_pairs, "fit_seconds": t_fit}}
+        a, b = r["arms"]["plain_sequential"], r["arms"]["batched_surrogate"]
+        r["speedup_trials_per_s"] = b["trials_per_s"] / a["trials_per_s"]
+        r["speedup_time_to_target"] = (a["seconds_to_target"] / b["seconds_to_target"]
+                                       if a["seconds_to_target"] and b["seconds_to_target"] else None)
+        runs.append(r)
+
+    def agg(key, arm_name=None):
+        vals = [(r["arms"][arm_name][key] if arm_name else r[key]) for r in runs]
+        m, h = _ci95(vals)
+        return {"mean": m, "ci95": h, "values": vals}
+
+    summary = {"plain_trials_per_s": agg("trials_per_s", "plain_sequential"),
+               "batched_trials_per_s": agg("trials_per_s", "batched_surrogate"),
+               "speedup_trials_per_s": agg("speedup_trials_per_s"),
+               "plain_seconds_to_target": agg("seconds_to_target", "plain_sequential"),
+               "batched_seconds_to_target": agg("seconds_to_target", "batched_surrogate"),
+               "plain_best_micro_f1": agg("best_micro_f1", "plain_sequential"),
+               "batched_best_micro_f1": agg("best_micro_f1", "batched_surrogate"),
+               "plain_reached_target": sum(r["arms"]["plain_sequential"]["seconds_to_target"]
+                                           is not None for r in runs),
+               "batched_reached_target": sum(r["arms"]["batched_surrogate"]["seconds_to_target"]
+                                             is not None for r in runs)}
     out = {"report": "automl", "workload": name, "n": g.n, "m": g.m, "T": p["T"], "M": p["M"],
-           "d": p["d"], "q": p["q"], "budget": budget, "scoring": "one-vs-rest logistic "
-           "regression on GPU, 10% training labels, 3 seeded splits, micro-F1",
-           "target_micro_f1": target,
-           "arms": {"plain_sequential": arm(sa, ta, ea, {"proposals": "random"}),
-                    "batched_surrogate": arm(sb, stb, eb, {"proposals": "surrogate, 25% random",
-                                                           "per_round": 16,
-                                                           "setup_seconds": setup})},
-           "surrogate_pretraining": {"graphs": 8, "trials": int(len(y)),
-                                     "batched_run_seconds": t_pairs, "fit_seconds": t_fit}}
-    a, b = out["arms"]["plain_sequential"], out["arms"]["batched_surrogate"]
-    out["speedup_trials_per_s"] = b["trials_per_s"] / a["trials_per_s"]
-    if a["seconds_to_target"] and b["seconds_to_target"]:
-        out["speedup_time_to_target"] = a["seconds_to_target"] / b["seconds_to_target"]
+           "d": p["d"], "q": p["q"], "budget": budget, "seeds": seeds,
+           "scoring": "one-vs-rest logistic regression on GPU, 10% training labels, 3 seeded "
+                      "splits, micro-F1", "summary": summary, "runs": runs}
     print(json.dumps(out), flush=True)
 
 
