@@ -52,6 +52,10 @@ def kernel_bytes(name, ctx_info):
         return P * (8 + 4) * 2 + (P // 4096 + 1) * 256 * 12
     if name == "radix_hist":
         return P * 8
+    if name == "sym_merge":
+        # row offsets of both triangles, the upper triangle's (col, value) and
+        # the lower's (key, value) per entry read, (col, value) written
+        return 24 * (n + 1) + ctx_info["nnz_counts"] * (8 + 12 + 8) // 2
     if name == "reduce_trunc_log":
         # (key, weight) per item read, (column, value) per distinct pair
         # written, row offsets
@@ -87,8 +91,7 @@ KERNEL_CLASSES = {
     "radix_scatter": (r"\bk_scatter\b", "k_sort.hip"),
     "radix_hist": (r"\bk_hist\b", "k_sort.hip"),
     "reduce_trunc_log": (r"\bk_reduce_tl\b", "k_sort.hip"),
-    "bucket_scatter": (r"\bk_bucket_scatter\b", "k_bucket.hip"),
-    "bucket_reduce": (r"\bk_bucket_reduce\b", "k_bucket.hip"),
+    "sym_merge": (r"\bk_sym_merge\b", "k_sort.hip"),
 }
 
 
@@ -401,7 +404,8 @@ def main():
              "rowptr_tail", "concat_rows", "trunc_log_count", "trunc_log_fill", "gaussian",
              "sparse_omega", "spmm_sparse_omega", "weight_check", "weight_guide",
              "spmm", "gram", "gram_reduce", "chol_inv", "project", "sym_eig", "eig_weights",
-             "w_to_bf16", "graph_spmm", "dense_scale", "axpby"]
+             "w_to_bf16", "graph_spmm", "dense_scale", "axpby", "sym_bounds", "sym_rowlen",
+             "sym_merge"]
     prof = {}
     for nm in names:
         ms, cnt = ctx.prof_get(nm)
@@ -444,8 +448,7 @@ def main():
     sparsifier_ms = sum(prof.get(k, {}).get("ms_per_step", 0.0) for k in (
         "validate_graph", "row_up", "fill_edges", "sample_count", "fold_stats", "sample_emit",
         "scan", "radix_hist", "radix_scatter", "heads", "reduce", "degrees", "reduce_trunc_log",
-        "drop_zeros", "rowptr_tail", "concat_rows", "bucket_count", "bucket_scatter",
-        "bucket_reduce"))
+        "drop_zeros", "rowptr_tail", "concat_rows", "sym_bounds", "sym_rowlen", "sym_merge"))
 
     value = stats["accepted"] / (ms_per_step * 1e-3)
     out = {

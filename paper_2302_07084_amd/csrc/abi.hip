@@ -315,6 +315,55 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
     return LNE_OK;
 }
 
+// The embedding's matrix in one pass from one entry per sample, (min, max) of
+// its endpoints: the upper triangle is sorted and reduced (Eq. (1) fused, a
+// diagonal sum doubled), its distinct pairs sorted again by column give the
+// lower triangle, and the two are merged into the symmetric matrix -- the
+// same entries as reducing both orientations of every sample, with half the
+// items in the six-pass sort (S.pl.upper set, entries counted that way).
+static lne_status aggregate_sym(lne_ctx *ctx, const lne_graph *g, Sampler &S, uint64_t entries,
+                                lne_csr *out, TruncLogFuse *tl) {
+    const int64_t P = (int64_t)entries;
+    const int colbits = S.pl.colbits;
+    Buf k0(ctx), v0(ctx), k1(ctx), v1(ctx);
+    LNE_TRY(alloc(ctx, k0, sizeof(uint64_t) * (size_t)(P > 0 ? P : 1)));
+    LNE_TRY(alloc(ctx, v0, sizeof(uint32_t) * (size_t)(P > 0 ? P : 1)));
+    if (P > 0)
+        LNE_TRY(launch_sample_emit(ctx, g, S.pl, S.eu.as<int32_t>(), S.ev.as<int32_t>(), S.m, 0,
+                                   g->n, S.wo.as<uint64_t>(), k0.as<uint64_t>(),
+                                   v0.as<uint32_t>()));
+    int which = 0;
+    const bool tagged = P > 1;   // the sort writes the column degree tags
+    if (P > 1) {
+        LNE_TRY(alloc(ctx, k1, sizeof(uint64_t) * (size_t)P));
+        LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)P));
+        LNE_TRY(radix_sort(ctx, k0.as<uint64_t>(), v0.as<uint32_t>(), k1.as<uint64_t>(),
+                           v1.as<uint32_t>(), P, 2 * colbits, &which, tl->deg, colbits));
+        if (which) { k0.release(); v0.release(); } else { k1.release(); v1.release(); }
+    }
+    const uint64_t *keys = which ? k1.as<uint64_t>() : k0.as<uint64_t>();
+    const uint32_t *vals = which ? v1.as<uint32_t>() : v0.as<uint32_t>();
+    lne_csr U;
+    std::memset(&U, 0, sizeof(U));
+    SymOut sym(ctx);
+    uint64_t kept_u = 0;
+    lne_status s = reduce_to_matrix(ctx, keys, vals, P, g->n, colbits, g, tl->deg, 0, tl->c,
+                                    LNE_F32, &U, &kept_u, tagged, &sym);
+    k0.release(); v0.release(); k1.release(); v1.release();
+    if (s != LNE_OK) {
+        lne_csr_free(ctx, &U);
+        return s;
+    }
+    uint64_t kept = 0;
+    s = sym_assemble(ctx, &U, sym, colbits, kept_u, out, &kept);
+    if (s != LNE_OK) {
+        lne_csr_free(ctx, &U);
+        return s;
+    }
+    tl->kept += kept;
+    return LNE_OK;
+}
+
 // Runs the sparsifier and hands each row block of the count matrix, in row
 // order, to `sink(block, row_lo)`, which takes ownership of the block.  One
 // block covers all rows unless the pair buffers would exceed the budget; then
@@ -332,6 +381,11 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
     if (channels) S.pl.cbits = 4;
     if (channels && g->weight)
         return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
+    // the embedding's FP32 matrix from the upper triangle (aggregate_sym) when
+    // the sort can carry the column degree tags
+    const bool sym = tl && !channels && tl->val_type == LNE_F32 &&
+                     radix_tag_shift(2 * S.pl.colbits, S.pl.colbits) >= 0;
+    S.pl.upper = sym ? 1 : 0;
     S.m = g->n_arcs / 2;
     uint64_t total = 0;
     if (S.m > 0 && S.pl.S > 0) {
@@ -348,6 +402,21 @@ static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_para
         st->entries = total;
     }
     const double budget = pair_budget(ctx);
+    // the upper-triangle pass needs about as much memory as the two-orientation
+    // one for half the entries
+    if (sym && total > 0 && range_bytes(2 * total) <= budget) {
+        lne_csr blk;
+        std::memset(&blk, 0, sizeof(blk));
+        LNE_TRY(aggregate_sym(ctx, g, S, total, &blk, tl));
+        if (st) st->nnz_counts = (uint64_t)blk.nnz;
+        return sink(blk, (int64_t)0);
+    }
+    if (sym && total > 0) {
+        // too large for one pass: count both orientations for the row ranges
+        S.pl.upper = 0;
+        LNE_TRY(count_range(ctx, g, S, 0, g->n, &total, false));
+        if (st) st->entries = total;
+    }
     if (total == 0 || range_bytes(total) <= budget) {
         lne_csr blk;
         std::memset(&blk, 0, sizeof(blk));

@@ -128,6 +128,9 @@ struct SamplePlan {
     int32_t colbits;      // bits of a column id in the packed key
     int32_t cbits;        // channel bits below the column (0, or 4 when the
                           // length r is kept: key column = col << 4 | r - 1)
+    int32_t upper;        // emit one entry per sample, (min, max) of its two
+                          // endpoints (the upper triangle; no row filter, no
+                          // channels), instead of both orientations
     // weighted graphs (all null on an unweighted one)
     const uint32_t *wt;   // arc weights A
     const uint64_t *cw;   // cw[k] = sum of wt[0..k), n_arcs + 1 entries
@@ -208,9 +211,11 @@ inline int radix_tag_shift(int bits, int colbits) {
         if (shift >= colbits) return shift;
     return -1;
 }
+// Stable LSD sort of (key, val) on key bits [lo_bit, bits); *which = the
+// buffer pair holding the result.
 lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1,
                       uint32_t *v1, int64_t n, int bits, int *which,
-                      const uint32_t *tag_deg = nullptr, int colbits = 0);
+                      const uint32_t *tag_deg = nullptr, int colbits = 0, int lo_bit = 0);
 // Sorted (key, val) -> count CSR (rows, cols from the packed key).
 lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                          int64_t n_items, int64_t n_rows, int colbits, lne_csr *out);
@@ -249,11 +254,27 @@ __device__ __forceinline__ bool tl_keep(const TLConst &c, uint64_t W, uint64_t d
 // number of nonzero entries.  val_type LNE_F64 or LNE_F32.  tagged: the keys
 // carry radix_sort's degree tags (a tag below kTagMax is the column's degree;
 // kTagMax means look it up in deg).
+// sym (optional, F32 only): the keys hold one entry per sample, (min, max)
+// of its endpoints (the upper triangle with the diagonal); a diagonal pair's
+// sum counts twice, and every distinct pair is also written transposed into
+// sym->keyT, sym->valT (max << colbits | min, the value's bits), allocated
+// here with out->nnz entries, for sym_assemble.
+struct SymOut {
+    Buf keyT, valT;
+    explicit SymOut(lne_ctx *ctx) : keyT(ctx), valT(ctx) {}
+};
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                             int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
                             int32_t val_type, lne_csr *out, uint64_t *kept,
-                            bool tagged = false);
+                            bool tagged = false, SymOut *sym = nullptr);
+// The symmetric matrix from its upper triangle U (reduce_to_matrix with sym,
+// all rows, F32) and the transposed pairs in sym: sorts them by (max, min)
+// and merges each row's lower part (without the diagonal) with U's row.
+// Frees U and sym's buffers; *out = the full n x n matrix, *kept = its
+// nonzero entries (kept_u = U's).
+lne_status sym_assemble(lne_ctx *ctx, lne_csr *U, SymOut &sym, int colbits, uint64_t kept_u,
+                        lne_csr *out, uint64_t *kept);
 // deg[i] = degree of vertex i (uint32, n entries): the compact degree table
 // the fused reduction gathers from; with cw (weight_info) the weighted degree.
 lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg,

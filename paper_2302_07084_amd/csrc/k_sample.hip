@@ -266,6 +266,8 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
             ++acc;
             if (draw_r(pl, b0.y) == 1) {
                 ++c1;
+            } else if (pl.upper) {
+                cnt += 1;
             } else if (FILTER) {
                 int32_t a = u, b = v;
                 walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b);
@@ -278,9 +280,10 @@ k_sample_count(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__r
         if (c1) {
             const uint64_t g = r1_group(weight_r1<W>(pl, cn, e));
             const uint32_t nm = (uint32_t)((c1 + g - 1) / g);
-            const uint32_t per = FILTER ? ((u >= row_lo && u < row_hi) ? 1u : 0u) +
-                                              ((v >= row_lo && v < row_hi) ? 1u : 0u)
-                                        : 2u;
+            const uint32_t per = pl.upper ? 1u
+                                 : FILTER ? ((u >= row_lo && u < row_hi) ? 1u : 0u) +
+                                                ((v >= row_lo && v < row_hi) ? 1u : 0u)
+                                          : 2u;
             cnt += nm * per;
         }
         att = j1 > j0 ? j1 - j0 : 0;
@@ -392,6 +395,11 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
     // writes the entries (a, b) and (b, a) that fall in the row range, at
     // this lane's place in the wave's contiguous output
     auto put = [&](bool ina, bool inb, int32_t a, int32_t b, uint64_t ch, uint32_t wv) {
+        if (pl.upper) {
+            // one entry (min, max) per sample (the rows cover all vertices)
+            if (a > b) { const int32_t x = a; a = b; b = x; }
+            inb = false;
+        }
         const uint32_t cnt = (ina ? 1u : 0u) + (inb ? 1u : 0u);
         const uint64_t m0 = __ballot(cnt & 1u), m1 = __ballot(cnt & 2u);
         uint64_t idx = pos + (uint64_t)__popcll(m0 & lt) + 2ull * (uint64_t)__popcll(m1 & lt);

@@ -358,7 +358,8 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
                                                   int32_t *__restrict__ col, VT *__restrict__ val,
                                                   int64_t *__restrict__ rowptr,
                                                   uint32_t *__restrict__ chunk_kept,
-                                                  bool tagged) {
+                                                  bool tagged, uint64_t *__restrict__ keyT,
+                                                  uint32_t *__restrict__ valT) {
     const int lane = threadIdx.x & 63;
     const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
     if (w >= nchunks) return;
@@ -369,16 +370,28 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint64_t running = head_off[w];   // heads before the current 64 items
     uint32_t my_kept = 0;
-    // Eq. (1) for the run of `key` with weight sum W and unique index u
+    // Eq. (1) for the run of `key` with weight sum W and unique index u.
+    // With keyT (the upper triangle: one entry per sample, (min, max)), a
+    // diagonal pair counts twice (its sample lands in both orientations of
+    // the symmetric matrix) and the pair is also written transposed,
+    // (max << colbits | min, value bits), for the lower triangle's sort.
     auto finish = [&](uint64_t key, uint64_t W, uint64_t u) {
         const int32_t b = (int32_t)(key & colmask);
         const int64_t row = (int64_t)((key & keymask) >> colbits);
+        if (keyT && (int64_t)b == row_lo + row) W *= 2;
         const uint64_t da = deg[row_lo + row];
         const uint32_t tag = tagged ? (uint32_t)(key >> kTagShift) : kTagMax;
         const uint64_t db = tag < kTagMax ? tag : deg[b];
         const bool k = tl_keep(c, W, da, db);
+        const VT x = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
         col[u] = b;
-        val[u] = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
+        val[u] = x;
+        if constexpr (sizeof(VT) == 4) {
+            if (keyT) {
+                keyT[u] = ((uint64_t)(uint32_t)b << colbits) | (uint64_t)(row_lo + row);
+                valT[u] = __float_as_uint((float)x);
+            }
+        }
         my_kept += k ? 1u : 0u;
     };
     // kPF groups of 64 items in flight: group it lives in ring slot it % kPF
@@ -483,6 +496,76 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
     if (lane == 0) chunk_kept[w] = my_kept;
 }
 
+// Row offsets of a stream sorted by row (key >> shift): rp[r] = the first
+// item whose row is at least r, for r up to the last row present (the rest
+// are set by k_row_bounds_tail).
+__global__ void k_row_bounds(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                             int64_t *__restrict__ rp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t row = (int64_t)(keys[i] >> shift);
+    const int64_t prow = i == 0 ? -1 : (int64_t)(keys[i - 1] >> shift);
+    for (int64_t r = prow + 1; r <= row; ++r) rp[r] = i;
+}
+
+__global__ void k_row_bounds_tail(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                  int64_t n_rows, int64_t *__restrict__ rp) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n_rows) return;
+    const int64_t last = n > 0 ? (int64_t)(keys[n - 1] >> shift) : -1;
+    if (r > last) rp[r] = n;
+}
+
+// Symmetric matrix from its upper triangle U (rows = min, with the diagonal)
+// and the transposed stream L (U's pairs sorted by (max, min)): row a is L's
+// segment of a without its last entry when that is the diagonal (a, a), then
+// U's row a.  len[a] = row a's length; dk[block] = kept diagonal entries.
+template <class VT>
+__global__ void k_sym_rowlen(const int64_t *__restrict__ rpU, const int32_t *__restrict__ colU,
+                             const VT *__restrict__ valU, const int64_t *__restrict__ rpL,
+                             int64_t n_rows, uint32_t *__restrict__ len,
+                             uint32_t *__restrict__ dk) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t kd = 0;
+    if (a < n_rows) {
+        const int64_t u0 = rpU[a], u1 = rpU[a + 1];
+        const bool diag = u1 > u0 && colU[u0] == (int32_t)a;
+        len[a] = (uint32_t)((u1 - u0) + (rpL[a + 1] - rpL[a]) - (diag ? 1 : 0));
+        kd = diag && valU[u0] != (VT)0 ? 1u : 0u;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) kd += __shfl_xor(kd, off, 64);
+    __shared__ uint32_t ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = kd;
+    __syncthreads();
+    if (threadIdx.x == 0) dk[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// One wave per row: L's entries (cols below a), then U's (cols from a).
+template <class VT>
+__global__ void k_sym_merge(const int64_t *__restrict__ rpU, const int32_t *__restrict__ colU,
+                            const VT *__restrict__ valU, const int64_t *__restrict__ rpL,
+                            const uint64_t *__restrict__ keyL, const uint32_t *__restrict__ valL,
+                            int64_t n_rows, uint64_t colmask, const uint64_t *__restrict__ rpF,
+                            int32_t *__restrict__ colF, VT *__restrict__ valF) {
+    const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (a >= n_rows) return;
+    const int64_t u0 = rpU[a], u1 = rpU[a + 1];
+    const bool diag = u1 > u0 && colU[u0] == (int32_t)a;
+    const int64_t l0 = rpL[a], l1 = rpL[a + 1] - (diag ? 1 : 0);
+    const int64_t o = (int64_t)rpF[a];
+    for (int64_t j = l0 + lane; j < l1; j += 64) {
+        colF[o + (j - l0)] = (int32_t)(keyL[j] & colmask);
+        valF[o + (j - l0)] = (VT)__uint_as_float(valL[j]);
+    }
+    const int64_t o2 = o + (l1 - l0);
+    for (int64_t j = u0 + lane; j < u1; j += 64) {
+        colF[o2 + (j - u0)] = colU[j];
+        valF[o2 + (j - u0)] = valU[j];
+    }
+}
+
 __global__ void k_degrees(const int64_t *__restrict__ rp, const uint64_t *__restrict__ cw,
                           int64_t n, uint32_t *__restrict__ deg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -503,7 +586,8 @@ __global__ void k_rowptr_tail(const uint64_t *__restrict__ keys, int64_t n_items
 }  // namespace
 
 lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
-                      int64_t n, int bits, int *which, const uint32_t *tag_deg, int colbits) {
+                      int64_t n, int bits, int *which, const uint32_t *tag_deg, int colbits,
+                      int lo_bit) {
     *which = 0;
     if (n <= 1) return LNE_OK;
     if ((uintptr_t)k0 % 16 || (uintptr_t)k1 % 16)
@@ -518,7 +602,7 @@ lne_status radix_sort(lne_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
     // the tagging pass: the first whose input is sorted by the column bits
     const int tag_shift = tag_deg ? radix_tag_shift(bits, colbits) : -1;
     const uint64_t colmask = (1ull << colbits) - 1;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = lo_bit; shift < bits; shift += 8) {
         {
             Launch L(ctx, "radix_hist");
             k_hist<<<(unsigned)ntiles, kST, 0, ctx->stream>>>(ks[cur], n, shift, ntiles,
@@ -602,9 +686,12 @@ lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg, const
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
                             int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
-                            int32_t val_type, lne_csr *out, uint64_t *kept, bool tagged) {
+                            int32_t val_type, lne_csr *out, uint64_t *kept, bool tagged,
+                            SymOut *sym) {
     if (val_type != LNE_F32 && val_type != LNE_F64)
         return fail(ctx, LNE_EINVAL, "reduce_to_matrix: F32 or F64 values");
+    if (sym && val_type != LNE_F32)
+        return fail(ctx, LNE_EINVAL, "reduce_to_matrix: the upper-triangle path takes F32");
     const int64_t nchunks = ceil_div(n_items > 0 ? n_items : 1, kRChunk);
     const unsigned nblocks = (unsigned)ceil_div(nchunks, kT / 64);
     Buf th(ctx), hoff(ctx), bk(ctx), bko(ctx);
@@ -626,16 +713,24 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
     LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)(n_rows + 1)));
     LNE_TRY(alloc(ctx, cc, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
     LNE_TRY(alloc(ctx, vv, dtype_size(val_type) * (size_t)(nnz > 0 ? nnz : 1)));
+    if (sym) {
+        LNE_TRY(alloc(ctx, sym->keyT, sizeof(uint64_t) * (size_t)(nnz > 0 ? nnz : 1)));
+        LNE_TRY(alloc(ctx, sym->valT, sizeof(uint32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+    }
+    uint64_t *kT_ = sym ? sym->keyT.as<uint64_t>() : nullptr;
+    uint32_t *vT_ = sym ? sym->valT.as<uint32_t>() : nullptr;
     if (n_items > 0) {
         Launch L(ctx, "reduce_trunc_log");
         if (val_type == LNE_F64)
             k_reduce_tl<double><<<nblocks, kT, 0, ctx->stream>>>(
                 keys, vals, n_items, nchunks, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
-                cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged);
+                cc.as<int32_t>(), vv.as<double>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged,
+                nullptr, nullptr);
         else
             k_reduce_tl<float><<<nblocks, kT, 0, ctx->stream>>>(
                 keys, vals, n_items, nchunks, hoff.as<uint64_t>(), colbits, deg, row_lo, c,
-                cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged);
+                cc.as<int32_t>(), vv.as<float>(), rp.as<int64_t>(), bk.as<uint32_t>(), tagged,
+                kT_, vT_);
     }
     LNE_TRY(check_launch(ctx, "reduce_trunc_log"));
     {
@@ -660,6 +755,80 @@ lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *
     out->col = (int32_t *)cc.detach();
     out->val = vv.detach();
     out->val_type = val_type;
+    return LNE_OK;
+}
+
+lne_status sym_assemble(lne_ctx *ctx, lne_csr *U, SymOut &sym, int colbits, uint64_t kept_u,
+                        lne_csr *out, uint64_t *kept) {
+    const int64_t n = U->n_rows, nu = U->nnz;
+    // the transposed pairs, in U's (min, max) order, sorted stably by max
+    Buf k1(ctx), v1(ctx);
+    int which = 0;
+    if (nu > 1) {
+        LNE_TRY(alloc(ctx, k1, sizeof(uint64_t) * (size_t)nu));
+        LNE_TRY(alloc(ctx, v1, sizeof(uint32_t) * (size_t)nu));
+        LNE_TRY(radix_sort(ctx, sym.keyT.as<uint64_t>(), sym.valT.as<uint32_t>(),
+                           k1.as<uint64_t>(), v1.as<uint32_t>(), nu, 2 * colbits, &which,
+                           nullptr, 0, colbits));
+    }
+    if (which) { sym.keyT.release(); sym.valT.release(); } else { k1.release(); v1.release(); }
+    const uint64_t *keyL = which ? k1.as<uint64_t>() : sym.keyT.as<uint64_t>();
+    const uint32_t *valL = which ? v1.as<uint32_t>() : sym.valT.as<uint32_t>();
+    Buf rpL(ctx), len(ctx), rpF(ctx), dk(ctx), dko(ctx);
+    LNE_TRY(alloc(ctx, rpL, sizeof(int64_t) * (size_t)(n + 1)));
+    if (nu > 0) {
+        Launch L(ctx, "sym_bounds");
+        k_row_bounds<<<grid_of(nu, 256), 256, 0, ctx->stream>>>(keyL, nu, colbits,
+                                                                 rpL.as<int64_t>());
+    }
+    LNE_TRY(check_launch(ctx, "sym_bounds"));
+    {
+        Launch L(ctx, "sym_bounds");
+        k_row_bounds_tail<<<grid_of(n + 1, 256), 256, 0, ctx->stream>>>(keyL, nu, colbits, n,
+                                                                          rpL.as<int64_t>());
+    }
+    LNE_TRY(check_launch(ctx, "sym_bounds"));
+    const int64_t nb = ceil_div(n > 0 ? n : 1, 256);
+    LNE_TRY(alloc(ctx, len, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)));
+    LNE_TRY(alloc(ctx, rpF, sizeof(uint64_t) * (size_t)(n + 1)));
+    LNE_TRY(alloc(ctx, dk, sizeof(uint32_t) * (size_t)nb));
+    LNE_TRY(alloc(ctx, dko, sizeof(uint64_t) * (size_t)(nb + 1)));
+    {
+        Launch L(ctx, "sym_rowlen");
+        k_sym_rowlen<float><<<(unsigned)nb, 256, 0, ctx->stream>>>(
+            U->row_ptr, U->col, (const float *)U->val, rpL.as<int64_t>(), n,
+            len.as<uint32_t>(), dk.as<uint32_t>());
+    }
+    LNE_TRY(check_launch(ctx, "sym_rowlen"));
+    LNE_TRY(scan_u32(ctx, len.as<uint32_t>(), rpF.as<uint64_t>(), n));
+    LNE_TRY(scan_u32(ctx, dk.as<uint32_t>(), dko.as<uint64_t>(), nb));
+    uint64_t host[2] = {0, 0};
+    LNE_HIP(ctx, hipMemcpyAsync(&host[0], rpF.as<uint64_t>() + n, 8, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    LNE_HIP(ctx, hipMemcpyAsync(&host[1], dko.as<uint64_t>() + nb, 8, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    LNE_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t nnz = (int64_t)host[0];
+    Buf cF(ctx), vF(ctx);
+    LNE_TRY(alloc(ctx, cF, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+    LNE_TRY(alloc(ctx, vF, sizeof(float) * (size_t)(nnz > 0 ? nnz : 1)));
+    if (n > 0) {
+        Launch L(ctx, "sym_merge");
+        k_sym_merge<float><<<grid_of(n * 64, 256), 256, 0, ctx->stream>>>(
+            U->row_ptr, U->col, (const float *)U->val, rpL.as<int64_t>(), keyL, valL, n,
+            (1ull << colbits) - 1, rpF.as<uint64_t>(), cF.as<int32_t>(), vF.as<float>());
+    }
+    LNE_TRY(check_launch(ctx, "sym_merge"));
+    // row offsets as int64 (the scan's uint64 offsets have the same bits)
+    out->n_rows = n;
+    out->n_cols = U->n_cols;
+    out->nnz = nnz;
+    out->row_ptr = (int64_t *)rpF.detach();
+    out->col = (int32_t *)cF.detach();
+    out->val = vF.detach();
+    out->val_type = LNE_F32;
+    *kept = 2 * kept_u - host[1];
+    lne_csr_free(ctx, U);
     return LNE_OK;
 }
 
