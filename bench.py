@@ -178,26 +178,30 @@ def summarize_counters(fetch_root, write_root, calib_bytes, workload, commands):
     import re
 
     def per_dispatch(root, counter):
+        """[(dispatch id, kernel name, counter value)] in dispatch order."""
         vals = {}
         for path in _rocprof_files(root, "counter_collection.csv"):
             with open(path, newline="") as f:
                 for r in csv.DictReader(f):
                     if _col(r, "Counter_Name") != counter:
                         continue
-                    key = (path, _col(r, "Dispatch_Id", "Correlation_Id"))
+                    did = int(float(_col(r, "Dispatch_Id", "Correlation_Id")))
+                    key = (path, did)
                     nm = _col(r, "Kernel_Name", "KernelName")
                     v = float(_col(r, "Counter_Value"))
-                    vals[key] = (nm, vals.get(key, (nm, 0.0))[1] + v)
-        return list(vals.values())
+                    vals[key] = (did, nm, vals.get(key, (did, nm, 0.0))[2] + v)
+        return sorted(vals.values())
 
     out = {"workload": workload, "commands": commands, "kernels": {}}
     factors = {}
     for counter, root in (("FETCH_SIZE", fetch_root), ("WRITE_SIZE", write_root)):
-        disp = per_dispatch(root, counter)
-        copies = [v for nm, v in disp if "copyBuffer" in nm]
-        if not copies:
-            raise SystemExit(f"no device copy in the {counter} run (use --calib-copy-mib)")
-        factors[counter] = calib_bytes / (max(copies) * 1024.0)
+        disp = [(nm, v) for _, nm, v in per_dispatch(root, counter)]
+        # the calibration: bench.py --calib-copy-mib copies the buffer three
+        # times before any other device copy of the run
+        copies = [v for nm, v in disp if "copyBuffer" in nm][:3]
+        if len(copies) < 3:
+            raise SystemExit(f"no calibration copies in the {counter} run (use --calib-copy-mib)")
+        factors[counter] = calib_bytes / (sorted(copies)[1] * 1024.0)
         for cls, (pat, src) in KERNEL_CLASSES.items():
             v = [x for nm, x in disp if re.search(pat, nm)]
             if not v:
@@ -208,7 +212,8 @@ def summarize_counters(fetch_root, write_root, calib_bytes, workload, commands):
                 sum(v) / len(v)
     out["fetch_factor"] = factors["FETCH_SIZE"]
     out["write_factor"] = factors["WRITE_SIZE"]
-    out["calibration"] = f"largest device copy of {calib_bytes} bytes"
+    out["calibration"] = (f"median of the run's first three device copies ({calib_bytes} bytes "
+                          f"each)")
     for ent in out["kernels"].values():
         with open(os.path.join(ROOT, "paper_2302_07084_amd", "csrc", ent["source"]), "rb") as f:
             ent["source_sha256"] = hashlib.sha256(f.read()).hexdigest()

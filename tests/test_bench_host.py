@@ -70,11 +70,17 @@ def test_rocprof_summaries(tmp_path):
     hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
     _write_csv(tmp_path / "f" / "h" / "1_counter_collection.csv", hdr,
                [[1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0],
+                [5, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 511.0],
+                [6, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 513.0],
+                [9, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 9999.0],
                 [2, "void k_graph_spmm<32, false, 8, true, false, float>()", "FETCH_SIZE", 100.0],
                 [3, "void k_graph_spmm<32, false, 8, true, false, float>()", "FETCH_SIZE", 300.0],
                 [4, "void k_spmm<32, true, 8, true, float, float, float>()", "FETCH_SIZE", 7.0]])
     _write_csv(tmp_path / "w" / "h" / "1_counter_collection.csv", hdr,
                [[1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0],
+                [5, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0],
+                [6, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0],
+                [9, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 4096.0],
                 [2, "void k_graph_spmm<32, false, 8, true, false, float>()", "WRITE_SIZE", 10.0],
                 [3, "void k_graph_spmm<32, false, 8, true, false, float>()", "WRITE_SIZE", 30.0]])
     summ = bench.summarize_counters(str(tmp_path / "f"), str(tmp_path / "w"), 1 << 20, "x", ["c"])
