@@ -496,226 +496,414 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
     }
 }
 
-// ---------------------------------------------------------------- Jacobi eig
-// Two-sided cyclic Jacobi with the round-robin (circle) ordering: every round
-// rotates kk/2 disjoint pairs at once, so a sweep is kk - 1 rounds.  IN_LDS:
-// the working copy of A lives in the workgroup's LDS (k^2 doubles of dynamic
-// shared memory) and a round updates it in one pass of 2 x 2 blocks (two
-// block barriers per round); the eigenvector accumulator is in global memory.
-constexpr int kB = 4;   // rotation elements per thread in flight
+// ---------------------------------------------------------------- eigen-solver
+// Symmetric eigen-decomposition of a k x k matrix by one workgroup, in three
+// phases (the textbook route: Householder reduction to tridiagonal form, the
+// implicit QL algorithm with Wilkinson's shift on the tridiagonal matrix, and
+// the reflectors applied to its eigenvectors):
+//  1. k - 2 Householder steps.  Step j reflects the entries of column j below
+//     the subdiagonal to zero: with x = A[j+1.., j], beta = -sign(x0) |x|,
+//     v = (1, x1 / (x0 - beta), ...), tau = (beta - x0) / beta, the trailing
+//     block becomes A - v w^T - w v^T with p = tau A v, w = p - (tau/2)(p.v) v.
+//     x stays in row j (which later steps never touch), so v is rebuilt from it
+//     when the reflector is applied.  The two products of the rank-2 update
+//     are rounded separately, so the block stays exactly symmetric.
+//  2. QL sweeps on (d, e) chase the shifted bulge from the bottom of the
+//     unreduced block up to its top with plane rotations.  Wave 0 computes a
+//     sweep's rotations while waves 1.. apply the previous sweep's rotations
+//     to the eigenvector rows (two rotation buffers, one block barrier per
+//     sweep); each lane of those waves owns one component of every
+//     eigenvector and carries the running value through the sweep.
+//  3. Every wave takes whole eigenvectors (in registers) and applies the
+//     reflectors k-3 .. 0 to them without block barriers, then writes them to
+//     V in order of decreasing eigenvalue.
+// IN_LDS: A (and then the reflectors) lives in LDS (k^2 doubles of dynamic
+// shared memory); otherwise it is worked on in place in global memory.  The
+// eigenvectors of the tridiagonal matrix are kept transposed in Zt (row i =
+// eigenvector i), so a rotation of eigenvectors (i, i+1) reads two rows.
+constexpr int kEigMaxLds = 144;   // largest k of the LDS variant
+constexpr int kEigMaxK = 288;
+
+// A double moved between lanes by a DPP pattern (both halves).
+template <int CTRL>
+__device__ inline double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double readlane_d(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Sum over a fully active wave, the same bits in every lane: pairs, quads,
+// half rows and rows by DPP (each step adds two equal sums in either order),
+// then the four row sums read from lanes 0, 16, 32 and 48.
+__device__ inline double wave_sum(double x) {
+    x += dpp_d<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+    x += dpp_d<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+    x += dpp_d<0x141>(x);   // row_half_mirror
+    x += dpp_d<0x140>(x);   // row_mirror
+    return (readlane_d(x, 0) + readlane_d(x, 16)) + (readlane_d(x, 32) + readlane_d(x, 48));
+}
+
+// Serial QL state of the producing wave.
+struct QlState {
+    int l = 0;      // eigenvalues 0 .. l-1 have converged
+    int iter = 0;   // sweeps spent on eigenvalue l
+};
+
+// The rotations of one QL sweep, rows m-1 up to l, from the values (d, e)
+// held when the sweep started: lane j keeps entries 64 q + j in D[q], E[q]
+// and the serial chain reads them by lane index; lane 0 stores the new d, e
+// and the rotations (rc, rs at the index of their upper row).  The matrix is
+// scaled to unit size, so f^2 + g^2 is a normal number unless both are
+// negligible (below 2^-500), which is where the sweep must deflate instead.
+// CHECK = false runs the chain with no branch on that test and returns -2 if
+// it failed anywhere (the stored values are then void); CHECK = true returns
+// the row at which it deflated, or -1 when the sweep completed.
+template <int R, bool CHECK>
+__device__ int ql_chain(const double (&D)[R], const double (&E)[R], int l, int m, double g,
+                        double dn, double dl, double *d, double *e, double *rc, double *rs,
+                        bool w0) {
+    double s = 1.0, c = 1.0, p = 0.0;
+    bool bad = false;
+    // segments of 64 rows from the bottom, each reading its own registers
+    // (q is a constant in each unrolled copy)
+#pragma unroll
+    for (int q = R - 1; q >= 0; --q) {
+        if (q > ((m - 1) >> 6) || q < (l >> 6)) continue;
+        const double Dq = D[q], Eq = E[q];
+        const int ilo = l > 64 * q ? l : 64 * q;
+        for (int i = (m - 1 < 64 * q + 63 ? m - 1 : 64 * q + 63); i >= ilo; --i) {
+            const double di = readlane_d(Dq, i - 64 * q), ei = readlane_d(Eq, i - 64 * q);
+            const double f = s * ei, b = c * ei;
+            const double x = fma(f, f, g * g);
+            if constexpr (CHECK) {
+                if (!(x >= 0x1p-1000)) {   // both vanished: deflate at i + 1
+                    if (w0) {
+                        e[i + 1] = 0.0;
+                        d[i + 1] = dn - p;
+                        e[m] = 0.0;
+                    }
+                    return i;
+                }
+            } else {
+                bad |= !(x >= 0x1p-1000);
+            }
+            // 1/sqrt(x) by the hardware estimate and two Newton steps, the
+            // last step's product folded into c, s and r
+            const double h = 0.5 * x, y0 = __builtin_amdgcn_rsq(x);
+            const double y1 = y0 * fma(-h * y0, y0, 1.5);
+            const double u2 = fma(-h * y1, y1, 1.5);
+            c = (g * y1) * u2;
+            s = (f * y1) * u2;
+            const double gp = dn - p;
+            const double r2 = fma(di - gp, s, (2.0 * b) * c);
+            p = s * r2;
+            g = fma(c, r2, -b);
+            if (w0) {
+                e[i + 1] = (x * y1) * u2;
+                d[i + 1] = gp + p;
+                rc[i] = c;
+                rs[i] = s;
+            }
+            dn = di;
+        }
+    }
+    if (!CHECK && bad) return -2;
+    if (w0) {
+        d[l] = dl - p;
+        e[l] = g;
+        e[m] = 0.0;
+    }
+    return -1;
+}
+
+// One QL sweep on (d, e) (length-k diagonal and coupling e[i] between i and
+// i+1, e[k-1] = 0), run by a whole wave computing the same values.  Returns
+// false once every eigenvalue has converged; else the sweep's rotations are
+// in rc, rs over [*lo, *hi).
+template <int R>
+__device__ bool ql_sweep(double *d, double *e, int k, QlState &st, double *rc, double *rs,
+                         int *lo, int *hi, int lane) {
+    const double eps = 2.220446049250313e-16;
+    const bool w0 = lane == 0;
+    while (st.l < k) {
+        const int l = st.l;
+        double D[R], E[R];
+        int m = k - 1;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int j = 64 * q + lane;
+            D[q] = j < k ? d[j] : 0.0;
+            E[q] = j < k ? e[j] : 0.0;
+            const double dn = j + 1 < k ? d[j + 1] : 0.0;
+            // the first coupling at or after l that is negligible
+            const bool split = j >= l && j < k - 1 && fabs(E[q]) <= eps * (fabs(D[q]) + fabs(dn));
+            const uint64_t bal = __ballot(split);
+            if (bal && m == k - 1) m = 64 * q + __builtin_ctzll(bal);
+        }
+        if (m == l) {
+            st.l = l + 1;
+            st.iter = 0;
+            continue;
+        }
+        if (st.iter++ >= 64) {   // not expected: give up on this coupling
+            if (w0) e[l] = 0.0;
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
+        const double dl = d[l], dl1 = d[l + 1], el = e[l], dm = d[m];
+        // shift: the eigenvalue of the leading 2 x 2 block nearer d[l]
+        double g = (dl1 - dl) / (2.0 * el);
+        const double r = hypot(g, 1.0);
+        g = dm - dl + el / (g + (g >= 0.0 ? r : -r));
+        int at = ql_chain<R, false>(D, E, l, m, g, dm, dl, d, e, rc, rs, w0);
+        if (at == -2) {
+            // put the sweep's starting values back, then take the checked path
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int j = 64 * q + lane;
+                if (j < k) { d[j] = D[q]; e[j] = E[q]; }
+            }
+            __builtin_amdgcn_wave_barrier();
+            at = ql_chain<R, true>(D, E, l, m, g, dm, dl, d, e, rc, rs, w0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        *lo = at >= 0 ? at + 1 : l;
+        *hi = m;
+        if (*lo < *hi) return true;
+    }
+    return false;
+}
 
 template <bool IN_LDS>
 __global__ void __launch_bounds__(kSolveThreads)
-k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Vw, double *__restrict__ V,
+k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Zt, double *__restrict__ V,
           double *__restrict__ lam) {
+    constexpr int MK = IN_LDS ? kEigMaxLds : kEigMaxK;
     extern __shared__ double lds_a[];
+    __shared__ double dg[MK], eg[MK], taus[MK];
+    __shared__ double buf[4 * MK];   // p of a Householder step, then the rotation buffers
+    __shared__ int s_lo[2], s_hi[2], s_more[2];
     {
         const int64_t b = blockIdx.x;
         Ag += b * k * k;
-        Vw += b * k * k;
+        Zt += b * k * k;
         V += b * k * k;
         lam += b * k;
     }
+    // the wave index as a scalar, so that code under `w == 0` branches as a
+    // uniform wave
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int NW = kSolveThreads / 64;
     double *__restrict__ A = Ag;
     if constexpr (IN_LDS) {
-        for (int64_t i = threadIdx.x; i < (int64_t)k * k; i += kSolveThreads) lds_a[i] = Ag[i];
+        for (int64_t i = tid; i < (int64_t)k * k; i += kSolveThreads) lds_a[i] = Ag[i];
         A = lds_a;
+    }
+    for (int64_t i = tid; i < (int64_t)k * k; i += kSolveThreads)
+        Zt[i] = (i / k == i % k) ? 1.0 : 0.0;
+    __syncthreads();
+
+    // ---- 1. Householder reduction.  Per step: every wave forms the
+    // reflector from row j; threads (row i, part q) sum parts of p = tau A v;
+    // thread i < m finishes p_i and writes v_i into row j (where phase 3
+    // reads it back, first entry 1); threads (column l, row group g) apply
+    // the rank-2 update.  Three block barriers per step.
+    constexpr int P = kSolveThreads / MK < 4 ? kSolveThreads / MK : 4;   // parts per row sum
+    constexpr int G = kSolveThreads / MK;                                 // row groups
+    double *pq = buf;   // P x MK partial sums, then p (row 0) and v (row 1)
+    for (int j = 0; j + 2 < k; ++j) {
+        const int m = k - j - 1;   // trailing indices j+1 .. k-1
+        double *x = A + (int64_t)j * k + j + 1;
+        double sg = 0.0;
+        for (int l = 1 + lane; l < m; l += 64) sg += x[l] * x[l];
+        sg = wave_sum(sg);
+        const double x0 = x[0];
+        if (tid == 0) dg[j] = A[(int64_t)j * k + j];
+        if (sg == 0.0) {   // already reduced: H = I
+            if (tid == 0) { eg[j] = x0; taus[j] = 0.0; }
+            continue;
+        }
+        const double beta = -copysign(sqrt(x0 * x0 + sg), x0);
+        const double tau = (beta - x0) / beta, sc = 1.0 / (x0 - beta);
+        if (tid == 0) { eg[j] = beta; taus[j] = tau; }
+        {
+            const int i = tid % MK, q = tid / MK, L = (m + P - 1) / P;
+            if (q < P && i < m) {
+                // A[j+1+l][j+1+i] = A[j+1+i][j+1+l]: lanes read along a row
+                const double *col = A + (int64_t)(j + 1) * k + j + 1 + i;
+                const int l1 = m < (q + 1) * L ? m : (q + 1) * L;
+                double acc0 = 0.0, acc1 = 0.0;
+                int l = q * L;
+                if (l == 0) { acc0 = col[0]; l = 1; }
+                for (; l + 1 < l1; l += 2) {
+                    acc0 += col[(int64_t)l * k] * (x[l] * sc);
+                    acc1 += col[(int64_t)(l + 1) * k] * (x[l + 1] * sc);
+                }
+                if (l < l1) acc0 += col[(int64_t)l * k] * (x[l] * sc);
+                pq[q * MK + i] = acc0 + acc1;
+            }
+        }
+        __syncthreads();
+        if (tid < m) {
+            double ps = 0.0;
+            for (int q = 0; q < P; ++q) ps += pq[q * MK + tid];
+            const double v = tid == 0 ? 1.0 : x[tid] * sc;
+            pq[tid] = tau * ps;
+            pq[MK + tid] = v;
+            x[tid] = v;
+        }
+        __syncthreads();
+        double pd = 0.0;
+        for (int l = lane; l < m; l += 64) pd += pq[l] * pq[MK + l];
+        const double K = 0.5 * tau * wave_sum(pd);
+        {
+            const int l = tid % MK, g = tid / MK;
+            if (g < G && l < m) {
+                const double vl = pq[MK + l], wl = pq[l] - K * vl;
+                double *colp = A + (int64_t)(j + 1) * k + j + 1 + l;
+#pragma unroll 4
+                for (int i = g; i < m; i += G) {
+                    const double vi = pq[MK + i], wi = pq[i] - K * vi;
+                    colp[(int64_t)i * k] -= __dadd_rn(__dmul_rn(vi, wl), __dmul_rn(wi, vl));
+                }
+            }
+        }
         __syncthreads();
     }
-    __shared__ double cs[160], sn[160];
-    __shared__ int pp[160], qq[160];
-    __shared__ double red[kSolveThreads / 64][2];
-    __shared__ int done;
-    const int tid = threadIdx.x;
-    const int kk = k + (k & 1);
-    const int half = kk / 2, m = kk - 1;
-    const int64_t k2 = (int64_t)k * k;
-    for (int64_t i = tid; i < k2; i += kSolveThreads) Vw[i] = (i / k == i % k) ? 1.0 : 0.0;
-    if (tid == 0) done = 0;
+    if (tid == 0) {
+        for (int j = (k >= 2 ? k - 2 : 0); j < k; ++j) dg[j] = A[(int64_t)j * k + j];
+        if (k >= 2) eg[k - 2] = A[(int64_t)(k - 2) * k + k - 1];
+        eg[k - 1] = 0.0;
+        s_more[0] = s_more[1] = 0;
+    }
     __syncthreads();
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        for (int r = 0; r < m; ++r) {
-            if (tid < half) {
-                int p, q;
-                if (tid == 0) { p = m; q = r; }
-                else { p = (r + tid) % m; q = (r - tid + m) % m; }
-                if (p > q) { const int x = p; p = q; q = x; }
-                double c = 1.0, s = 0.0;
-                if (q < k) {
-                    const double apq = A[(int64_t)p * k + q];
-                    if (apq != 0.0) {
-                        const double app = A[(int64_t)p * k + p], aqq = A[(int64_t)q * k + q];
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                    }
-                }
-                cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
+
+    // ---- 2. QL sweeps, rotations produced by wave 0 and applied by waves 1..
+    {
+        // rotation buffer b: cosines at buf + 2 MK b, sines MK further.  The
+        // producer scales (d, e) by a power of two to unit size (exact) and
+        // scales the eigenvalues back when done.
+        // The producer is all of wave 0 computing the same values (uniform
+        // branches), lane 0 storing them.
+        QlState st;
+        double unit = 1.0;
+        if (w == 0) {
+            double amax = 0.0;
+            for (int i = lane; i < k; i += 64) amax = fmax(amax, fmax(fabs(dg[i]), fabs(eg[i])));
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+            if (amax > 0.0 && isfinite(amax)) {
+                unit = ldexp(1.0, -ilogb(amax));
+                for (int i = lane; i < k; i += 64) { dg[i] *= unit; eg[i] *= unit; }
             }
-            __syncthreads();
-            const int total = half * k;
-            if constexpr (IN_LDS) {
-                // A <- J^T A J in one pass: a thread takes the 2 x 2 block of
-                // rows (p_a, q_a) and columns (p_b, q_b) of two pairs, rotates
-                // its rows by pair a, then its columns by pair b (the same
-                // products as a row pass followed by a column pass); an
-                // index equal to k is the padding of an odd k
-                const int nblk = half * half;
-                for (int bi = tid; bi < nblk; bi += kSolveThreads) {
-                    const int a = bi / half, b = bi - a * half;
-                    const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
-                    const bool ra = qa < k, rb = qb < k;
-                    const double x00 = A[pa * k + pb];
-                    const double x01 = rb ? A[pa * k + qb] : 0.0;
-                    const double x10 = ra ? A[qa * k + pb] : 0.0;
-                    const double x11 = ra && rb ? A[qa * k + qb] : 0.0;
-                    double y0 = x00, y1 = x10, z0 = x01, z1 = x11;
-                    if (ra && sn[a] != 0.0) {
-                        const double c = cs[a], s = sn[a];
-                        y0 = c * x00 - s * x10;
-                        y1 = s * x00 + c * x10;
-                        z0 = c * x01 - s * x11;
-                        z1 = s * x01 + c * x11;
-                    }
-                    double o00 = y0, o01 = z0, o10 = y1, o11 = z1;
-                    if (rb && sn[b] != 0.0) {
-                        const double c = cs[b], s = sn[b];
-                        o00 = c * y0 - s * z0;
-                        o01 = s * y0 + c * z0;
-                        o10 = c * y1 - s * z1;
-                        o11 = s * y1 + c * z1;
-                    }
-                    A[pa * k + pb] = o00;
-                    if (rb) A[pa * k + qb] = o01;
-                    if (ra) A[qa * k + pb] = o10;
-                    if (ra && rb) A[qa * k + qb] = o11;
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int t = 0;; ++t) {
+            const int b = t & 1;
+            if (w == 0) {
+                int lo = 0, hi = 0;
+                double *cb = buf + 2 * MK * b;
+                const bool more =
+                    ql_sweep<(MK + 63) / 64>(dg, eg, k, st, cb, cb + MK, &lo, &hi, lane);
+                if (!more)
+                    for (int i = lane; i < k; i += 64) dg[i] /= unit;
+                if (lane == 0) {
+                    s_more[b] = more ? 1 : 0;
+                    s_lo[b] = lo;
+                    s_hi[b] = hi;
                 }
-            } else {
-            // rows: A <- J^T A; then columns: A <- A J, V <- V J.  32-bit
-            // index arithmetic (half k < 2^31), and each thread issues the
-            // loads of kB elements before their stores so that their
-            // latencies overlap (V lives in global memory, and so does A
-            // when it does not fit LDS)
-            for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
-                double a0[kB], a1[kB];
-                int o0[kB], o1[kB];
-                bool on[kB];
-                double c[kB], s[kB];
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    const int idx = b0 + u * kSolveThreads;
-                    const int pr = idx < total ? idx / k : 0, j = idx - pr * k;
-                    const int p = pp[pr], q = qq[pr];
-                    on[u] = idx < total && q < k && sn[pr] != 0.0;
-                    c[u] = cs[pr];
-                    s[u] = sn[pr];
-                    o0[u] = p * k + j;
-                    o1[u] = q * k + j;
-                    a0[u] = on[u] ? A[o0[u]] : 0.0;
-                    a1[u] = on[u] ? A[o1[u]] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < kB; ++u)
-                    if (on[u]) {
-                        A[o0[u]] = c[u] * a0[u] - s[u] * a1[u];
-                        A[o1[u]] = s[u] * a0[u] + c[u] * a1[u];
-                    }
             }
-                __syncthreads();
-            }
-            // columns: A <- A J (A in global memory; the LDS variant did its
-            // columns with its rows) and V <- V J, V kept transposed (row p of
-            // Vw = column p of V) so that its rotation runs along rows p, q.
-            // The columns of a global A take a pass with lanes along a row i
-            // (pair index fastest), so a wave's accesses stay inside one or
-            // two rows of A.
-            if constexpr (!IN_LDS) {
-                for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
-                    double a0[kB], a1[kB];
-                    int o0[kB], o1[kB];
-                    bool on[kB];
-                    double c[kB], s[kB];
+            const int pb = b ^ 1;
+            const int kk = tid - 64;
+            if (t > 0 && kk >= 0 && kk < k && s_more[pb]) {
+                const int lo = s_lo[pb], hi = s_hi[pb];
+                const double *c = buf + 2 * MK * pb, *s = c + MK;
+                double carry = Zt[(int64_t)hi * k + kk];
+                // rotations hi-1 .. lo, loads of up to 32 rows issued ahead
+                for (int i0 = hi - 1; i0 >= lo; i0 -= 32) {
+                    double z[32];
+                    const int cnt = i0 - lo + 1 < 32 ? i0 - lo + 1 : 32;
 #pragma unroll
-                    for (int u = 0; u < kB; ++u) {
-                        const int idx = b0 + u * kSolveThreads;
-                        const int i = idx < total ? idx / half : 0, pr = idx - i * half;
-                        const int p = pp[pr], q = qq[pr];
-                        on[u] = idx < total && q < k && sn[pr] != 0.0;
-                        c[u] = cs[pr];
-                        s[u] = sn[pr];
-                        o0[u] = i * k + p;
-                        o1[u] = i * k + q;
-                        a0[u] = on[u] ? A[o0[u]] : 0.0;
-                        a1[u] = on[u] ? A[o1[u]] : 0.0;
-                    }
+                    for (int u = 0; u < 32; ++u)
+                        if (u < cnt) z[u] = Zt[(int64_t)(i0 - u) * k + kk];
 #pragma unroll
-                    for (int u = 0; u < kB; ++u)
-                        if (on[u]) {
-                            A[o0[u]] = c[u] * a0[u] - s[u] * a1[u];
-                            A[o1[u]] = s[u] * a0[u] + c[u] * a1[u];
+                    for (int u = 0; u < 32; ++u)
+                        if (u < cnt) {
+                            const int i = i0 - u;
+                            Zt[(int64_t)(i + 1) * k + kk] = s[i] * z[u] + c[i] * carry;
+                            carry = c[i] * z[u] - s[i] * carry;
                         }
                 }
-            }
-            for (int b0 = tid; b0 < total; b0 += kSolveThreads * kB) {
-                double v0[kB], v1[kB];
-                int o0[kB], o1[kB];
-                bool on[kB];
-                double c[kB], s[kB];
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    const int idx = b0 + u * kSolveThreads;
-                    const int pr = idx < total ? idx / k : 0, i = idx - pr * k;
-                    const int p = pp[pr], q = qq[pr];
-                    on[u] = idx < total && q < k && sn[pr] != 0.0;
-                    c[u] = cs[pr];
-                    s[u] = sn[pr];
-                    o0[u] = p * k + i;
-                    o1[u] = q * k + i;
-                    v0[u] = on[u] ? Vw[o0[u]] : 0.0;
-                    v1[u] = on[u] ? Vw[o1[u]] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < kB; ++u)
-                    if (on[u]) {
-                        Vw[o0[u]] = c[u] * v0[u] - s[u] * v1[u];
-                        Vw[o1[u]] = s[u] * v0[u] + c[u] * v1[u];
-                    }
+                Zt[(int64_t)lo * k + kk] = carry;
             }
             __syncthreads();
+            if (!s_more[b]) break;
         }
-        // convergence: off-diagonal mass relative to the diagonal
-        double off = 0.0, dia = 0.0;
-        for (int i = tid; i < (int)k2; i += kSolveThreads) {
-            const double x = A[i];
-            const int r = i / k;
-            if (i - r * k == r) dia += x * x; else off += x * x;
+    }
+
+    // ---- 3. reflectors applied to each eigenvector, then sorted output.  A
+    // wave takes three eigenvectors at a time (three independent sums per
+    // reflector); reflector j is row j of A from column j + 1 on.
+    constexpr int R = (MK + 63) / 64;
+    for (int c0 = w; c0 < k; c0 += 3 * NW) {
+        double z[3][R];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int c = c0 + r * NW;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int i = lane + 64 * q;
+                z[r][q] = c < k && i < k ? Zt[(int64_t)c * k + i] : 0.0;
+            }
+        }
+        for (int j = k - 3; j >= 0; --j) {
+            const double tau = taus[j];
+            if (tau == 0.0) continue;
+            double v[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int i = lane + 64 * q;
+                v[q] = i > j && i < k ? A[(int64_t)j * k + i] : 0.0;
+            }
+            double f[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                double dot = 0.0;
+#pragma unroll
+                for (int q = 0; q < R; ++q) dot += v[q] * z[r][q];
+                f[r] = dot;
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) f[r] = tau * wave_sum(f[r]);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int q = 0; q < R; ++q) z[r][q] -= f[r] * v[q];
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            off += __shfl_xor(off, o, 64);
-            dia += __shfl_xor(dia, o, 64);
+        for (int r = 0; r < 3; ++r) {
+            const int c = c0 + r * NW;
+            if (c >= k) break;
+            // rank by decreasing eigenvalue, ties by index
+            const double lc = dg[c];
+            int rank = 0;
+            for (int j0 = 0; j0 < k; j0 += 64) {
+                const int j = j0 + lane;
+                const bool before = j < k && (dg[j] > lc || (dg[j] == lc && j < c));
+                rank += __popcll(__ballot(before));
+            }
+            if (lane == 0) lam[rank] = lc;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int i = lane + 64 * q;
+                if (i < k) V[(int64_t)i * k + rank] = z[r][q];
+            }
         }
-        if ((tid & 63) == 0) { red[tid >> 6][0] = off; red[tid >> 6][1] = dia; }
-        __syncthreads();
-        if (tid == 0) {
-            double o = 0.0, d = 0.0;
-            for (int i = 0; i < kSolveThreads / 64; ++i) { o += red[i][0]; d += red[i][1]; }
-            done = (o <= 1e-30 * d) ? 1 : 0;
-        }
-        __syncthreads();
-        if (done) break;
-    }
-    // sort by decreasing eigenvalue (rank by counting, ties by index)
-    for (int i = tid; i < k; i += kSolveThreads) {
-        const double li = A[(int64_t)i * k + i];
-        int rank = 0;
-        for (int j = 0; j < k; ++j) {
-            const double lj = A[(int64_t)j * k + j];
-            rank += (lj > li || (lj == li && j < i)) ? 1 : 0;
-        }
-        lam[rank] = li;
-        for (int row = 0; row < k; ++row) V[(int64_t)row * k + rank] = Vw[(int64_t)i * k + row];
     }
 }
 
@@ -895,7 +1083,7 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
 
 lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb,
                    double *vw_ws) {
-    if (k > 288) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above 288", k);
+    if (k > kEigMaxK) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above %d", k, kEigMaxK);
     Buf vw(ctx);
     // vw_ws (if given) holds nb k k doubles
     if (vw_ws) vw.p = vw_ws, vw.ctx = nullptr;
@@ -906,20 +1094,22 @@ lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, i
         int dev = 0, bytes = 0;
         lds_limit = 0;
         int base = 0;
+        hipFuncAttributes fa;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&base, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
                 hipSuccess &&
             hipDeviceGetAttribute(&bytes, hipDeviceAttributeSharedMemPerBlockOptin, dev) ==
                 hipSuccess &&
-            (bytes = bytes > base ? bytes : base) > 8192 &&
+            hipFuncGetAttributes(&fa, (const void *)k_sym_eig<true>) == hipSuccess &&
+            (bytes = bytes > base ? bytes : base) > (int)fa.sharedSizeBytes &&
             hipFuncSetAttribute((const void *)k_sym_eig<true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes - 8192) ==
-                hipSuccess)
-            lds_limit = bytes - 8192;
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes - (int)fa.sharedSizeBytes) == hipSuccess)
+            lds_limit = bytes - (int)fa.sharedSizeBytes;
         (void)hipGetLastError();
     }
     const size_t need = sizeof(double) * (size_t)k * k;
-    if (need <= (size_t)lds_limit) {
+    if (k <= kEigMaxLds && need <= (size_t)lds_limit) {
         Launch L(ctx, "sym_eig");
         k_sym_eig<true><<<nb, kSolveThreads, need, ctx->stream>>>(C, k, vw.as<double>(), V, lam);
     } else {
