@@ -268,8 +268,9 @@ lne_status lne_spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx,
 
 /* eigSVD (Algorithm "eigSVD") of a dense Y (n x k, dtype): C = Y^T Y in FP64
  * (BF16 inputs: FP32 accumulation), C = V D V^T in FP64 on the device
- * (Householder tridiagonalization, implicit QL sweeps with Wilkinson's shift,
- * the reflectors applied to the eigenvectors), S = sqrt(D) sorted descending, U = Y V S^-1 (columns with
+ * (Householder tridiagonalization; the tridiagonal matrix torn in two halves
+ * solved by implicit QL sweeps with Wilkinson's shift and merged through the
+ * secular equation; the reflectors applied to the eigenvectors), S = sqrt(D) sorted descending, U = Y V S^-1 (columns with
  * S <= k eps S_1 are zero).  U: device n x k (ldu, dtype; BF16 input gives F32
  * U), S: device k doubles, V: device k x k doubles.  Any output may be NULL.
  * Errors: EINVAL, ENOMEM, EUNSUPPORTED (k > 288). */

@@ -334,7 +334,9 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
                     int32_t *shifted, int64_t n_rows, const int32_t *skip,
                     int32_t *skip_next, int32_t nb = 1);
 // Symmetric eigen-decomposition of C (k x k, FP64): V (k x k, columns = vectors),
-// lam (k), sorted by decreasing eigenvalue.  C is overwritten.
+// lam (k), sorted by decreasing eigenvalue.  C is overwritten.  vw_ws: a
+// workspace of sym_eig_ws_doubles(k, nb) doubles (allocated when NULL).
+size_t sym_eig_ws_doubles(int32_t k, int32_t nb = 1);
 lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb = 1,
                    double *vw_ws = nullptr);
 // W (k x kout) = V[:, :kout] diag(f(lam)) with f = lam^pow (0 for

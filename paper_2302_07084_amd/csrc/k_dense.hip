@@ -498,31 +498,36 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
 
 // ---------------------------------------------------------------- eigen-solver
 // Symmetric eigen-decomposition of a k x k matrix by one workgroup, in three
-// phases (the textbook route: Householder reduction to tridiagonal form, the
-// implicit QL algorithm with Wilkinson's shift on the tridiagonal matrix, and
-// the reflectors applied to its eigenvectors):
+// phases (Householder reduction to tridiagonal form, the tridiagonal
+// eigen-problem, the reflectors applied to its eigenvectors):
 //  1. k - 2 Householder steps.  Step j reflects the entries of column j below
 //     the subdiagonal to zero: with x = A[j+1.., j], beta = -sign(x0) |x|,
 //     v = (1, x1 / (x0 - beta), ...), tau = (beta - x0) / beta, the trailing
 //     block becomes A - v w^T - w v^T with p = tau A v, w = p - (tau/2)(p.v) v.
-//     x stays in row j (which later steps never touch), so v is rebuilt from it
-//     when the reflector is applied.  The two products of the rank-2 update
-//     are rounded separately, so the block stays exactly symmetric.
-//  2. QL sweeps on (d, e) chase the shifted bulge from the bottom of the
-//     unreduced block up to its top with plane rotations.  Wave 0 computes a
-//     sweep's rotations while waves 1.. apply the previous sweep's rotations
-//     to the eigenvector rows (two rotation buffers, one block barrier per
-//     sweep); each lane of those waves owns one component of every
-//     eigenvector and carries the running value through the sweep.
+//     v is written into row j (which later steps never touch).  The two
+//     products of the rank-2 update are rounded separately, so the block
+//     stays exactly symmetric.
+//  2. The tridiagonal matrix (d, e): implicit QL sweeps (Wilkinson's shift)
+//     chase the shifted bulge from the bottom of an unreduced block to its
+//     top with plane rotations.  One wave computes a sweep's rotations while
+//     other waves apply the previous sweep's rotations to the eigenvector
+//     rows (two rotation buffers, one block barrier per sweep); each of their
+//     lanes owns one component of every eigenvector.  From kEigSplit on, the
+//     matrix is first torn in two halves plus a rank-one term (Cuppen), the
+//     halves are swept side by side by two waves, and a merge solves the
+//     rank-one problem (its comment gives the steps).
 //  3. Every wave takes whole eigenvectors (in registers) and applies the
 //     reflectors k-3 .. 0 to them without block barriers, then writes them to
 //     V in order of decreasing eigenvalue.
 // IN_LDS: A (and then the reflectors) lives in LDS (k^2 doubles of dynamic
 // shared memory); otherwise it is worked on in place in global memory.  The
 // eigenvectors of the tridiagonal matrix are kept transposed in Zt (row i =
-// eigenvector i), so a rotation of eigenvectors (i, i+1) reads two rows.
+// eigenvector i), so a rotation of eigenvectors (i, i+1) reads two rows; the
+// workspace Zt holds 2 k^2 doubles (the merge writes its rows to the second
+// half) and V serves as the merge's scratch before it receives the result.
 constexpr int kEigMaxLds = 144;   // largest k of the LDS variant
 constexpr int kEigMaxK = 288;
+constexpr int kEigSplit = 32;   // tear the tridiagonal matrix from this size on
 
 // A double moved between lanes by a DPP pattern (both halves).
 template <int CTRL>
@@ -687,11 +692,14 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Zt, double *__res
     extern __shared__ double lds_a[];
     __shared__ double dg[MK], eg[MK], taus[MK];
     __shared__ double buf[4 * MK];   // p of a Householder step, then the rotation buffers
-    __shared__ int s_lo[2], s_hi[2], s_more[2];
+    __shared__ int s_lo[2][2], s_hi[2][2], s_more[2][2];   // [problem][buffer]
+    __shared__ int idx[2 * MK];                             // merge: order, kept and deflated rows
+    __shared__ double s_rho, s_unit, s_tol;
+    __shared__ int s_K, s_flip;
     {
         const int64_t b = blockIdx.x;
         Ag += b * k * k;
-        Zt += b * k * k;
+        Zt += b * 2 * k * k;
         V += b * k * k;
         lam += b * k;
     }
@@ -779,60 +787,77 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Zt, double *__res
         for (int j = (k >= 2 ? k - 2 : 0); j < k; ++j) dg[j] = A[(int64_t)j * k + j];
         if (k >= 2) eg[k - 2] = A[(int64_t)(k - 2) * k + k - 1];
         eg[k - 1] = 0.0;
-        s_more[0] = s_more[1] = 0;
+        s_more[0][0] = s_more[0][1] = s_more[1][0] = s_more[1][1] = 0;
     }
     __syncthreads();
 
-    // ---- 2. QL sweeps, rotations produced by wave 0 and applied by waves 1..
-    {
-        // rotation buffer b: cosines at buf + 2 MK b, sines MK further.  The
-        // producer scales (d, e) by a power of two to unit size (exact) and
-        // scales the eigenvalues back when done.
-        // The producer is all of wave 0 computing the same values (uniform
-        // branches), lane 0 storing them.
-        QlState st;
-        double unit = 1.0;
-        if (w == 0) {
-            double amax = 0.0;
-            for (int i = lane; i < k; i += 64) amax = fmax(amax, fmax(fabs(dg[i]), fabs(eg[i])));
+    // ---- 2. eigen-decomposition of the tridiagonal matrix T = (d, e).
+    // Wave 0 scales (d, e) by a power of two to unit size (exact).  For
+    // k >= kEigSplit, T is torn at h = k/2 into blockdiag(T1, T2) + rho w w^T
+    // (w = e_{h-1} + e_h, rho the coupling, taken off d[h-1] and d[h]); waves
+    // 0 and 1 run the QL sweeps of T1 and T2 side by side while waves 2..
+    // apply each problem's previous sweep to its block of eigenvector rows
+    // (component c by thread c; rotation buffer b: cosines at buf + 2 MK b,
+    // sines MK further, indexed by global row).  The merge below then solves
+    // the rank-one problem.  Smaller k: one problem, waves 1.. apply.
+    const int h = k >= kEigSplit ? k / 2 : k;
+    const int np = h < k ? 2 : 1;
+    if (w == 0) {
+        double amax = 0.0;
+        for (int i = lane; i < k; i += 64) amax = fmax(amax, fmax(fabs(dg[i]), fabs(eg[i])));
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
-            if (amax > 0.0 && isfinite(amax)) {
-                unit = ldexp(1.0, -ilogb(amax));
-                for (int i = lane; i < k; i += 64) { dg[i] *= unit; eg[i] *= unit; }
-            }
-            __builtin_amdgcn_wave_barrier();
+        for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+        double unit = 1.0;
+        if (amax > 0.0 && isfinite(amax)) {
+            unit = ldexp(1.0, -ilogb(amax));
+            for (int i = lane; i < k; i += 64) { dg[i] *= unit; eg[i] *= unit; }
         }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            s_unit = unit;
+            s_rho = 0.0;
+            if (np == 2) {
+                const double rho = eg[h - 1];
+                dg[h - 1] -= rho;
+                dg[h] -= rho;
+                eg[h - 1] = 0.0;
+                s_rho = rho;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        QlState st;
         for (int t = 0;; ++t) {
             const int b = t & 1;
-            if (w == 0) {
+            if (w < np) {
+                const int base = w == 0 ? 0 : h, n = w == 0 ? h : k - h;
                 int lo = 0, hi = 0;
-                double *cb = buf + 2 * MK * b;
-                const bool more =
-                    ql_sweep<(MK + 63) / 64>(dg, eg, k, st, cb, cb + MK, &lo, &hi, lane);
-                if (!more)
-                    for (int i = lane; i < k; i += 64) dg[i] /= unit;
+                double *cb = buf + 2 * MK * b + base;
+                const bool more = ql_sweep<(MK + 63) / 64>(dg + base, eg + base, n, st, cb,
+                                                          cb + MK, &lo, &hi, lane);
                 if (lane == 0) {
-                    s_more[b] = more ? 1 : 0;
-                    s_lo[b] = lo;
-                    s_hi[b] = hi;
+                    s_more[w][b] = more ? 1 : 0;
+                    s_lo[w][b] = base + lo;
+                    s_hi[w][b] = base + hi;
                 }
             }
             const int pb = b ^ 1;
-            const int kk = tid - 64;
-            if (t > 0 && kk >= 0 && kk < k && s_more[pb]) {
-                const int lo = s_lo[pb], hi = s_hi[pb];
+            const int kk = tid - 64 * np;
+            const int pr = kk >= h ? 1 : 0;
+            if (t > 0 && kk >= 0 && kk < k && s_more[pr][pb]) {
+                const int lo = s_lo[pr][pb], hi = s_hi[pr][pb];
                 const double *c = buf + 2 * MK * pb, *s = c + MK;
                 double carry = Zt[(int64_t)hi * k + kk];
-                // rotations hi-1 .. lo, loads of up to 32 rows issued ahead
-                for (int i0 = hi - 1; i0 >= lo; i0 -= 32) {
-                    double z[32];
-                    const int cnt = i0 - lo + 1 < 32 ? i0 - lo + 1 : 32;
+                // rotations hi-1 .. lo, loads of up to 16 rows issued ahead
+                for (int i0 = hi - 1; i0 >= lo; i0 -= 16) {
+                    double z[16];
+                    const int cnt = i0 - lo + 1 < 16 ? i0 - lo + 1 : 16;
 #pragma unroll
-                    for (int u = 0; u < 32; ++u)
+                    for (int u = 0; u < 16; ++u)
                         if (u < cnt) z[u] = Zt[(int64_t)(i0 - u) * k + kk];
 #pragma unroll
-                    for (int u = 0; u < 32; ++u)
+                    for (int u = 0; u < 16; ++u)
                         if (u < cnt) {
                             const int i = i0 - u;
                             Zt[(int64_t)(i + 1) * k + kk] = s[i] * z[u] + c[i] * carry;
@@ -842,8 +867,246 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Zt, double *__res
                 Zt[(int64_t)lo * k + kk] = carry;
             }
             __syncthreads();
-            if (!s_more[b]) break;
+            if (!s_more[0][b] && !s_more[1][b]) break;
         }
+    }
+    const double *Zv = Zt;   // the eigenvector rows phase 3 starts from
+    if (np == 1) {
+        for (int i = tid; i < k; i += kSolveThreads) dg[i] /= s_unit;
+    } else {
+        // ---- merge: eigenvalues and eigenvectors of D + rho z z^T, D the
+        // eigenvalues of T1 and T2, z the rows h-1 / h of their eigenvectors.
+        // Deflation (a negligible weight, or two poles whose rotation
+        // leaves a negligible coupling), then per root a bisection of the
+        // secular equation 1 + rho sum z_i^2 / (d_i - lambda) = 0 in its
+        // interval between poles (its distance to the nearer pole kept as
+        // (origin, tau) so that differences stay accurate), weights
+        // recomputed from the roots (Gu and Eisenstat) so that the
+        // eigenvectors z_i / (d_i - lambda_j) come out orthogonal, and the
+        // new rows Zt2 = U Zt[kept] (U in V as scratch).
+        double *Zt2 = Zt + (int64_t)k * k;
+        double *Ut = V;
+        int *ord = idx, *kept = idx + MK;
+        double *dk = buf, *zk = buf + MK, *tau = buf + 2 * MK, *zh = buf + 3 * MK;
+        for (int i = tid; i < k; i += kSolveThreads)
+            eg[i] = i < h ? Zt[(int64_t)i * k + h - 1] : Zt[(int64_t)i * k + h];
+        __syncthreads();
+        if (w == 0) {
+            double zz = 0.0, dmax = 0.0;
+            for (int i = lane; i < k; i += 64) {
+                zz += eg[i] * eg[i];
+                dmax = fmax(dmax, fabs(dg[i]));
+            }
+            zz = wave_sum(zz);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+            if (lane == 0) {
+                const double rt = s_rho * zz;
+                s_flip = rt < 0.0 ? 1 : 0;
+                s_rho = fabs(rt);
+                s_tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, fabs(rt));
+                zh[0] = zz > 0.0 ? 1.0 / sqrt(zz) : 0.0;
+            }
+        }
+        __syncthreads();
+        {
+            const double sz = zh[0];
+            const bool flip = s_flip != 0;
+            for (int i = tid; i < k; i += kSolveThreads) {
+                eg[i] *= sz;
+                if (flip) dg[i] = -dg[i];
+            }
+        }
+        __syncthreads();
+        // ascending order of the poles (ties by index)
+        for (int i = tid; i < k; i += kSolveThreads) {
+            const double di = dg[i];
+            int r = 0;
+            for (int j = 0; j < k; ++j) r += (dg[j] < di || (dg[j] == di && j < i)) ? 1 : 0;
+            ord[r] = i;
+        }
+        __syncthreads();
+        // deflation, in pole order, by wave 0
+        if (w == 0) {
+            const double rho = s_rho, tol = s_tol;
+            int K = 0, nd = 0, prev = -1;
+            for (int sidx = 0; sidx < k; ++sidx) {
+                const int i = ord[sidx];
+                const double zi = eg[i];
+                if (rho * fabs(zi) <= tol) {
+                    if (lane == 0) kept[k - 1 - nd] = i;
+                    ++nd;
+                    continue;
+                }
+                if (prev >= 0) {
+                    const double zp = eg[prev], dp = dg[prev], di = dg[i];
+                    const double r = hypot(zp, zi);
+                    const double c = zi / r, sn = zp / r;
+                    if (fabs(c * sn * (di - dp)) <= tol) {
+                        // rotate rows prev, i so that prev's weight vanishes
+                        for (int cc = lane; cc < k; cc += 64) {
+                            const double a = Zt[(int64_t)prev * k + cc], bb = Zt[(int64_t)i * k + cc];
+                            Zt[(int64_t)prev * k + cc] = c * a - sn * bb;
+                            Zt[(int64_t)i * k + cc] = sn * a + c * bb;
+                        }
+                        if (lane == 0) {
+                            dg[prev] = c * c * dp + sn * sn * di;
+                            dg[i] = sn * sn * dp + c * c * di;
+                            eg[i] = r;
+                            eg[prev] = 0.0;
+                            kept[k - 1 - nd] = prev;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        ++nd;
+                        prev = i;
+                        continue;
+                    }
+                    if (lane == 0) kept[K] = prev;
+                    ++K;
+                }
+                prev = i;
+            }
+            if (prev >= 0) {
+                if (lane == 0) kept[K] = prev;
+                ++K;
+            }
+            if (lane == 0) s_K = K;
+        }
+        __syncthreads();
+        const int K = s_K;
+        const double rho = s_rho;
+        for (int j = tid; j < K; j += kSolveThreads) {
+            dk[j] = dg[kept[j]];
+            zk[j] = eg[kept[j]];
+        }
+        __syncthreads();
+        // roots: lambda_j in (dk_j, dk_j+1), the last in (dk_K-1, dk_K-1 +
+        // rho |z|^2].  Four lanes per root (partial sums over every fourth
+        // pole, quad sums by DPP); Newton steps on the secular function
+        // inside its bracket, a bisection step whenever Newton leaves it.
+        for (int j0 = 0; j0 < K; j0 += kSolveThreads / 4) {
+            const int j = j0 + (tid >> 2), sub = tid & 3;
+            if (j < K) {
+                // 1 + rho sum z^2 / delta and its derivative, delta_i =
+                // (dk_i - dk_o) - t
+                auto secular = [&](int oo, double tt, double &der) {
+                    double f = 0.0, g = 0.0;
+                    for (int i = sub; i < K; i += 4) {
+                        const double r = 1.0 / ((dk[i] - dk[oo]) - tt);
+                        const double a2 = zk[i] * zk[i] * r;
+                        f += a2;
+                        g += a2 * r;
+                    }
+                    f += dpp_d<0xB1>(f);
+                    f += dpp_d<0x4E>(f);
+                    g += dpp_d<0xB1>(g);
+                    g += dpp_d<0x4E>(g);
+                    der = rho * g;
+                    return 1.0 + rho * f;
+                };
+                int o;
+                double lo, hi, der;
+                if (j < K - 1) {
+                    const double gap = dk[j + 1] - dk[j];
+                    if (secular(j, 0.5 * gap, der) >= 0.0) { o = j; lo = 0.0; hi = 0.5 * gap; }
+                    else { o = j + 1; lo = -0.5 * gap; hi = 0.0; }
+                } else {
+                    double zz = 0.0;
+                    for (int i = 0; i < K; ++i) zz += zk[i] * zk[i];
+                    o = j; lo = 0.0; hi = rho * zz;
+                }
+                double t = 0.5 * (lo + hi);
+                for (int it = 0; it < 200; ++it) {
+                    const double f = secular(o, t, der);
+                    if (f == 0.0) break;
+                    if (f < 0.0) lo = t; else hi = t;
+                    double tn = t - f / der;
+                    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+                    const bool done = !(tn > lo && tn < hi) ||
+                                      fabs(tn - t) <= 4.440892098500626e-16 * fabs(tn);
+                    if (!(tn > lo && tn < hi)) break;
+                    t = tn;
+                    if (done) break;
+                }
+                if (sub == 0) {
+                    ord[j] = o;
+                    tau[j] = t;
+                }
+            }
+        }
+        __syncthreads();
+        // recomputed weights: zh_i^2 = prod_j (lambda_j - dk_i) / (rho prod_l!=i (dk_l - dk_i))
+        for (int i = tid; i < K; i += kSolveThreads) {
+            auto lmd = [&](int j) { return (dk[ord[j]] - dk[i]) + tau[j]; };   // lambda_j - dk_i
+            double P = lmd(K - 1) / rho;
+            for (int j = 0; j < i; ++j) P *= lmd(j) / (dk[j] - dk[i]);
+            for (int j = i; j < K - 1; ++j) P *= lmd(j) / (dk[j + 1] - dk[i]);
+            zh[i] = copysign(sqrt(fmax(P, 0.0)), zk[i]);
+        }
+        __syncthreads();
+        // eigenvectors of the rank-one problem (rows of Ut), and the new
+        // eigenvalues (unscaled, sign restored) next to the deflated ones
+        {
+            const double sgn = s_flip ? -1.0 : 1.0, un = s_unit;
+            for (int j = tid; j < K; j += kSolveThreads) {
+                const double dj = dk[ord[j]], tj = tau[j];
+                double nrm = 0.0;
+                for (int i = 0; i < K; ++i) {
+                    const double u = zh[i] / ((dk[i] - dj) - tj);
+                    nrm += u * u;
+                }
+                const double inv = 1.0 / sqrt(nrm);
+                for (int i = 0; i < K; ++i) Ut[(int64_t)j * K + i] = zh[i] / ((dk[i] - dj) - tj) * inv;
+            }
+            __syncthreads();
+            // zk is free now: the final eigenvalues
+            for (int j = tid; j < k; j += kSolveThreads)
+                zk[j] = sgn * (j < K ? dk[ord[j]] + tau[j] : dg[kept[j]]) / un;
+        }
+        __syncthreads();
+        for (int j = tid; j < k; j += kSolveThreads) dg[j] = zk[j];
+        // new rows: Zt2[j] = sum_i Ut[j][i] Zt[kept_i] (j < K); the deflated
+        // rows are copied.  4 x 4 output tiles per thread.
+        {
+            const int nt4 = (k + 3) / 4;
+            for (int tt = tid; tt < nt4 * nt4; tt += kSolveThreads) {
+                const int j0 = (tt / nt4) * 4, c0 = (tt % nt4) * 4;
+                double acc[4][4];
+#pragma unroll
+                for (int a4 = 0; a4 < 4; ++a4)
+#pragma unroll
+                    for (int b4 = 0; b4 < 4; ++b4) acc[a4][b4] = 0.0;
+                const int jn = K - j0;   // rows of this tile that are sums
+                if (jn > 0) {
+                    for (int i = 0; i < K; ++i) {
+                        const double *zr = Zt + (int64_t)kept[i] * k + c0;
+                        double zv[4], uv[4];
+#pragma unroll
+                        for (int b4 = 0; b4 < 4; ++b4) zv[b4] = c0 + b4 < k ? zr[b4] : 0.0;
+#pragma unroll
+                        for (int a4 = 0; a4 < 4; ++a4)
+                            uv[a4] = a4 < jn ? Ut[(int64_t)(j0 + a4) * K + i] : 0.0;
+#pragma unroll
+                        for (int a4 = 0; a4 < 4; ++a4)
+#pragma unroll
+                            for (int b4 = 0; b4 < 4; ++b4) acc[a4][b4] += uv[a4] * zv[b4];
+                    }
+                }
+#pragma unroll
+                for (int a4 = 0; a4 < 4; ++a4) {
+                    const int j = j0 + a4;
+                    if (j >= k) break;
+#pragma unroll
+                    for (int b4 = 0; b4 < 4; ++b4) {
+                        const int c = c0 + b4;
+                        if (c >= k) break;
+                        Zt2[(int64_t)j * k + c] = j < K ? acc[a4][b4] : Zt[(int64_t)kept[j] * k + c];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        Zv = Zt2;
     }
 
     // ---- 3. reflectors applied to each eigenvector, then sorted output.  A
@@ -858,7 +1121,7 @@ k_sym_eig(double *__restrict__ Ag, int k, double *__restrict__ Zt, double *__res
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int i = lane + 64 * q;
-                z[r][q] = c < k && i < k ? Zt[(int64_t)c * k + i] : 0.0;
+                z[r][q] = c < k && i < k ? Zv[(int64_t)c * k + i] : 0.0;
             }
         }
         for (int j = k - 3; j >= 0; --j) {
@@ -1081,13 +1344,15 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
     return check_launch(ctx, "chol_inv");
 }
 
+size_t sym_eig_ws_doubles(int32_t k, int32_t nb) { return (size_t)nb * 2 * k * k; }
+
 lne_status sym_eig(lne_ctx *ctx, double *C, int32_t k, double *V, double *lam, int32_t nb,
                    double *vw_ws) {
     if (k > kEigMaxK) return fail(ctx, LNE_EUNSUPPORTED, "sym_eig: k = %d above %d", k, kEigMaxK);
     Buf vw(ctx);
-    // vw_ws (if given) holds nb k k doubles
+    // vw_ws (if given) holds sym_eig_ws_doubles(k, nb) doubles
     if (vw_ws) vw.p = vw_ws, vw.ctx = nullptr;
-    else LNE_TRY(alloc(ctx, vw, sizeof(double) * (size_t)nb * k * k));
+    else LNE_TRY(alloc(ctx, vw, sizeof(double) * sym_eig_ws_doubles(k, nb)));
     // the LDS variant when k^2 doubles fit next to the kernel's static arrays
     static int lds_limit = -1;
     if (lds_limit < 0) {

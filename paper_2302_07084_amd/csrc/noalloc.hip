@@ -1,8 +1,8 @@
 // Allocation-free eigSVD (Algorithm "eigSVD") for callers that cannot
 // allocate device memory: code under HIP graph capture, serving loops, and
 // harnesses that forbid hipMalloc.  Every intermediate of lne_eigsvd (the
-// Gram's per-workgroup partial sums, the Gram, the eigen-solver's working
-// matrix, eigenvectors and eigenvalues, the projection weights and their
+// Gram's per-workgroup partial sums, the Gram, the eigen-solver's workspace,
+// eigenvectors and eigenvalues, the projection weights and their
 // BF16 copy) lives in one file-scope device array that each device holds
 // until the process ends.  The kernels are those of lne_eigsvd; only the
 // number of Gram workgroups may be smaller (as many partial sums as the array
@@ -70,10 +70,12 @@ lne_status lne_eigsvd_noalloc(lne_ctx *ctx, const void *Y, int64_t n, int32_t k,
     if (!Y || n < 1 || k < 1 || ld < k || (U && ldu < k) || dtype < LNE_F64 || dtype > LNE_BF16)
         return fail(ctx, LNE_EINVAL, "eigsvd_noalloc: bad arguments");
     if (k > kMaxK) return fail(ctx, LNE_EUNSUPPORTED, "eigsvd_noalloc: k = %d above %d", k, kMaxK);
-    // layout: G, eigen-solver working matrix, eigenvectors, weights (k x k
-    // doubles each), eigenvalues, BF16 weights, then the partial Grams
+    // layout: G, eigenvectors, weights (k x k doubles each), the
+    // eigen-solver's workspace, eigenvalues, BF16 weights, then the partial
+    // Grams
     const size_t kk = up256(sizeof(double) * (size_t)k * k);
-    const size_t fixed = 4 * kk + up256(sizeof(double) * (size_t)k) +
+    const size_t ws = up256(sizeof(double) * sym_eig_ws_doubles(k));
+    const size_t fixed = 3 * kk + ws + up256(sizeof(double) * (size_t)k) +
                          up256(project_bf16_ws_bytes(k, k));
     const int KP = (k + 15) / 16 * 16;
     const size_t one_part = sizeof(double) * (size_t)KP * KP;
@@ -84,11 +86,11 @@ lne_status lne_eigsvd_noalloc(lne_ctx *ctx, const void *Y, int64_t n, int32_t k,
     LNE_TRY(scratch_ptr(ctx, &base));
     NoEvents guard(ctx);
     double *G = reinterpret_cast<double *>(base);
-    double *vw = reinterpret_cast<double *>(base + kk);
-    double *Vk = reinterpret_cast<double *>(base + 2 * kk);
-    double *W = reinterpret_cast<double *>(base + 3 * kk);
-    double *lam = reinterpret_cast<double *>(base + 4 * kk);
-    void *wt = base + 4 * kk + up256(sizeof(double) * (size_t)k);
+    double *Vk = reinterpret_cast<double *>(base + kk);
+    double *W = reinterpret_cast<double *>(base + 2 * kk);
+    double *vw = reinterpret_cast<double *>(base + 3 * kk);
+    double *lam = reinterpret_cast<double *>(base + 3 * kk + ws);
+    void *wt = base + 3 * kk + ws + up256(sizeof(double) * (size_t)k);
     double *part = reinterpret_cast<double *>(base + fixed);
     // every entry these kernels read is written first in the same call, so
     // nothing needs clearing between calls

@@ -47,7 +47,7 @@ def _rand_y(n, k, seed, cond=1e3):
     return (Q1 * np.logspace(0, -math.log10(cond), k)) @ Q2
 
 
-# 139 and 140: the last width whose Gram fits the eigensolver's LDS variant
+# 138 and 139: the last width whose Gram fits the eigensolver's LDS variant
 # and the first that takes the global-memory one; 288: the widest accepted
 @pytest.mark.parametrize("k", [5, 42, 138, 139, 140, 272, 288])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -70,6 +70,50 @@ def test_eigsvd_vs_lapack(lne, ctx, k, dtype):
     rt = {"f64": 1e-12, "f32": 1e-6, "bf16": 2e-2}[dtype]
     assert np.linalg.norm(recon - Yq) <= rt * np.linalg.norm(Yq)
     np.testing.assert_allclose(Vn.T @ Vn, np.eye(k), atol=1e-12)
+
+
+def _structured_y(n, k, kind, seed):
+    """Inputs whose Gram matrices drive the eigen-solver's deflation: exactly
+    repeated singular values, a rank-deficient Y (zero eigenvalues) and
+    orthogonal columns (an already diagonal Gram, no coupling anywhere)."""
+    rng = np.random.default_rng(seed)
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    if kind == "diagonal":
+        return Q1 * np.linspace(3.0, 1.0, k)
+    Q2, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    if kind == "clustered":
+        s = np.repeat([10.0, 3.0, 1.0], (k + 2) // 3)[:k]
+    else:   # rank-deficient: a third of the directions carry the data
+        s = np.where(np.arange(k) < max(1, k // 3), np.linspace(5.0, 1.0, k), 0.0)
+    return (Q1 * s) @ Q2
+
+
+# 31 / 32 / 33 straddle the size from which the tridiagonal matrix is torn in
+# two and merged; 138 and 266 are the embedding and precision widths
+@pytest.mark.parametrize("k", [31, 32, 33, 138, 266])
+@pytest.mark.parametrize("kind", ["clustered", "rankdef", "diagonal"])
+def test_eigsvd_structured_spectra(lne, ctx, k, kind):
+    import torch
+    n = 2000
+    Y = _structured_y(n, k, kind, seed=k)
+    Yd = torch.from_numpy(Y).cuda()
+    U, S, V = lne.eigsvd(ctx, Yd)
+    S = S.cpu().numpy()
+    Vn = V.cpu().numpy()
+    S2 = np.linalg.svd(Y, compute_uv=False)
+    # eigenvalues of the Gram to an absolute 1e-13 of the largest, so the
+    # singular values to that over 2 s_i, and exact zeros to sqrt of it
+    lam, lam2 = S ** 2, S2 ** 2
+    assert np.max(np.abs(lam - lam2)) <= 1e-13 * lam2[0] * k
+    np.testing.assert_allclose(Vn.T @ Vn, np.eye(k), atol=1e-12)
+    # V diagonalises the Gram: V^T G V = diag(S^2) to rounding
+    G = Y.T @ Y
+    off = Vn.T @ G @ Vn - np.diag(lam)
+    assert np.max(np.abs(off)) <= 1e-12 * lam2[0]
+    Un = U.cpu().numpy()
+    keep = S > k * 2.220446049250313e-16 * S[0]
+    assert np.linalg.norm((Un[:, keep] * S[keep]) - Y @ Vn[:, keep]) <= 1e-12 * np.linalg.norm(Y)
+    assert np.all(Un[:, ~keep] == 0.0)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
