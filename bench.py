@@ -532,8 +532,8 @@ def ablation_report(name, mults=(0.077, 1, 5, 10, 50, 100)):
     from synth import workload
 
     g, p = workload(name, device="cuda")
-    task = search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=7)
     ctx = lne.Context()
+    task = search.Task.make(ctx, g, p, train_ratio=0.1, n_splits=3, seed=7)
     variants = (("vanilla rSVD, q=1", 1, lne.FLAG_VANILLA_RSVD), ("fast rSVD, q=1", 1, 0),
                 ("fast rSVD, q=2", 2, 0), ("fast rSVD, q=5", 5, 0),
                 ("fast rSVD, q=1, sparse-sign Omega", 1, lne.FLAG_SPARSE_OMEGA),
@@ -916,11 +916,11 @@ def automl_report(name, budget, pretrain_per_graph, seeds=3):
                                                 (40, 500, 0.40), (25, 1600, 0.28), (25, 1600, 0.34),
                                                 (50, 800, 0.31), (50, 800, 0.37)]):
         g, p = workload(name, sizes=[size] * blocks, intra=intra, seed=100 + i)
-        family.append(search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=100 + i))
+        family.append(search.Task.make(ctx, g, p, train_ratio=0.1, n_splits=3, seed=100 + i))
     t_fam = time.perf_counter() - t0
     log(f"automl: {len(family)} family graphs in {t_fam:.1f}s")
     g, p = workload(name, device="cuda")
-    task = search.Task.make(g, p, train_ratio=0.1, n_splits=3, seed=0)
+    task = search.Task.make(ctx, g, p, train_ratio=0.1, n_splits=3, seed=0)
     log(f"automl: target graph n={g.n} m={g.m}, budget {budget} trials per arm, {seeds} seeds")
     # warm both paths once so that neither arm pays first-launch costs
     w = search.sample_trials(np.random.default_rng(9), 1)

@@ -277,6 +277,30 @@ lne_status lne_spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx,
 lne_status lne_eigsvd(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t ld,
                       int32_t dtype, void *U, int64_t ldu, double *S, double *V);
 
+/* ---- graph descriptors ---------------------------------------------------- */
+
+/* The eight descriptors of a graph that the hyperparameter search's surrogate
+ * reads next to the trial's parameters (section 4.4 searches trials per
+ * graph; the choice of descriptors is this library's): out[0] log n, out[1]
+ * log max(m, 1), out[2] log of the mean degree, out[3] the degree coefficient
+ * of variation (population standard deviation over mean), out[4] log of the
+ * maximum degree, out[5] the Hill tail exponent 1 + |T| / sum_{d in T}
+ * log(d / (x_min - 1/2)) with x_min = max(1, median degree) and T the degrees
+ * >= x_min, out[6] the fraction of closed wedges among `wedges` sampled ones,
+ * out[7] the spectral gap 1 - lambda_2 of D^-1/2 A D^-1/2.  Wedge t draws the
+ * Philox block of counter (t_lo, t_hi, 0, 6 << 24) under key seed, words z0..z3:
+ * its centre is candidate ((z1 << 32) | z0) mod C of the C vertices of degree
+ * >= 2 in increasing order, its ends the neighbours at positions z2 mod d and
+ * z3 mod (d - 1), the second moved past the first when not smaller.
+ * lambda_2 = 2 S_2 - 1 after `iters` steps X <- U of [U, S] = eigSVD((X + D^-1/2
+ * A D^-1/2 X) / 2), from X = the lne_gaussian block of n x min(16, n) under
+ * key seed (isolated vertices: zero rows of D^-1/2 A D^-1/2).  g: unweighted,
+ * with at least one edge.  out: host, 8 doubles.  Synchronous.
+ * Errors: EINVAL (wedges < 1, iters < 1, invalid graph), EUNSUPPORTED
+ * (weighted graph), ENOMEM, EHIP. */
+lne_status lne_graph_stats(lne_ctx *ctx, const lne_graph *g, uint64_t seed, int32_t wedges,
+                           int32_t iters, double *out);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): lne_eigsvd
  * with no allocation.  Same arguments, results and errors as lne_eigsvd.

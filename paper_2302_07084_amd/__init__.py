@@ -133,6 +133,7 @@ SIGNATURES = [
                                         _I32, ctypes.c_float, ctypes.c_float, _P]),
     ("lne_link_rank", _I32, [_P, _P, _I64, _I32, _I64, _I32, _P, _I64, _P, _I32, _I32, _P, _P,
                              _P]),
+    ("lne_graph_stats", _I32, [_P, _P, _U64, _I32, _I32, _P]),
 ]
 
 _lib = None
@@ -691,6 +692,17 @@ def score_micro_f1(ctx: Context, X, labels, train, test, epochs=300, lr=0.05, l2
                                              tr.data_ptr(), len(tr), te.data_ptr(), len(te),
                                              epochs, lr, l2, f1), "score_micro_f1")
     return f1[0] if single else list(f1)
+
+
+def graph_stats(ctx: Context, rowptr, col, seed: int = 0, wedges: int = 2000, iters: int = 200):
+    """The eight graph descriptors of lne_graph_stats (log n, log m, log mean
+    degree, degree coefficient of variation, log max degree, Hill tail
+    exponent, wedge clustering, spectral gap) as a numpy array."""
+    out = (ctypes.c_double * 8)()
+    g = graph_struct(rowptr, col)
+    ctx.check(ctx.L.lne_graph_stats(ctx.h, ctypes.byref(g), seed, wedges, iters, out),
+              "graph_stats")
+    return np.array(list(out))
 
 
 def link_rank(ctx: Context, X, pos, neg, hits_k: int = 10):

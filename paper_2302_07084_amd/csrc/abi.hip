@@ -1174,6 +1174,17 @@ lne_status lne_eigsvd(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t
     return LNE_OK;
 }
 
+lne_status lne_graph_stats(lne_ctx *ctx, const lne_graph *g, uint64_t seed, int32_t wedges,
+                           int32_t iters, double *out) {
+    if (!ctx) return LNE_EINVAL;
+    LNE_TRY(validate_graph(ctx, g));
+    if (!out || wedges < 1 || iters < 1 || g->n_arcs < 2)
+        return fail(ctx, LNE_EINVAL, "graph_stats: needs out, wedges >= 1, iters >= 1, an edge");
+    if (g->weight) return fail(ctx, LNE_EUNSUPPORTED, "graph_stats: unweighted graphs only");
+    LNE_TRY(validate_graph_device(ctx, g));
+    return graph_stats_impl(ctx, g, seed, wedges, iters, out);
+}
+
 lne_status lne_orthonormalize(lne_ctx *ctx, void *Y, int64_t n, int32_t k, int64_t ld,
                               int32_t dtype) {
     if (!ctx) return LNE_EINVAL;

@@ -333,6 +333,9 @@ size_t project_bf16_ws_bytes(int32_t kin, int32_t kout, int32_t nb = 1);
 lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *status,
                     int32_t *shifted, int64_t n_rows, const int32_t *skip,
                     int32_t *skip_next, int32_t nb = 1);
+// Graph descriptors (k_stats.hip) behind lne_graph_stats; g validated.
+lne_status graph_stats_impl(lne_ctx *ctx, const lne_graph *g, uint64_t seed, int32_t wedges,
+                            int32_t iters, double *out);
 // Symmetric eigen-decomposition of C (k x k, FP64): V (k x k, columns = vectors),
 // lam (k), sorted by decreasing eigenvalue.  C is overwritten.  vw_ws: a
 // workspace of sym_eig_ws_doubles(k, nb) doubles (allocated when NULL).

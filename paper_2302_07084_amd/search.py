@@ -18,8 +18,8 @@ import time
 
 import numpy as np
 
-from . import (Batch, Context, embed, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
-               score_micro_f1)
+from . import (Batch, Context, embed, graph_stats, mlp_adam, mlp_forward, mlp_grad, mlp_init,
+               mlp_param_count, score_micro_f1)
 
 T_MAX = 10
 N_STATS = 8
@@ -48,39 +48,6 @@ def sample_trials(rng: np.random.Generator, count: int, T: int = T_MAX):
     k ~ U{1..20}, theta ~ U[0, 1], mu ~ U[0, 0.5]."""
     return [Trial(rng.dirichlet(np.ones(T)), int(rng.integers(1, 21)), float(rng.random()),
                   float(0.5 * rng.random())) for _ in range(count)]
-
-
-def graph_stats(g, seed: int = 0) -> np.ndarray:
-    """Eight descriptors of a graph: log n, log m, log mean degree, degree
-    coefficient of variation, log max degree, tail exponent (Hill estimator
-    above the median degree), wedge-sampled clustering coefficient and the
-    spectral gap 1 - lambda_2 of D^-1/2 A D^-1/2."""
-    import scipy.sparse as sp
-    import scipy.sparse.linalg as sla
-    deg = np.diff(g.rowptr).astype(np.float64)
-    n, m = g.n, g.m
-    xmin = max(1.0, float(np.median(deg)))
-    tail = deg[deg >= xmin]
-    alpha = 1.0 + len(tail) / max(np.sum(np.log(tail / (xmin - 0.5))), 1e-9)
-    rng = np.random.default_rng(seed)
-    cand = np.flatnonzero(deg >= 2)
-    closed = 0
-    trials = 2000
-    for _ in range(trials):
-        v = cand[rng.integers(len(cand))]
-        nb = g.col[g.rowptr[v]:g.rowptr[v + 1]]
-        a, b = rng.choice(nb, 2, replace=False)
-        row = g.col[g.rowptr[a]:g.rowptr[a + 1]]
-        j = np.searchsorted(row, b)
-        closed += int(j < len(row) and row[j] == b)
-    A = sp.csr_matrix((np.ones(len(g.col)), g.col, g.rowptr), shape=(n, n))
-    dm = sp.diags(np.where(deg > 0, deg ** -0.5, 0.0))
-    N = dm @ A @ dm
-    lam = sla.eigsh(N, k=2, which="LA", return_eigenvectors=False, tol=1e-4,
-                    v0=np.ones(n) / math.sqrt(n))
-    gap = 1.0 - float(np.sort(lam)[0])
-    return np.array([math.log(n), math.log(max(m, 1)), math.log(deg.mean()),
-                     deg.std() / deg.mean(), math.log(deg.max()), alpha, closed / trials, gap])
 
 
 class Surrogate:
@@ -140,7 +107,11 @@ class Task:
     splits: list
 
     @staticmethod
-    def make(g, base: dict, train_ratio: float = 0.1, n_splits: int = 1, seed: int = 0):
+    def make(ctx: Context, g, base: dict, train_ratio: float = 0.1, n_splits: int = 1,
+             seed: int = 0):
+        """The graph on the device, its label splits, and its eight descriptors
+        (lne_graph_stats: degree moments, Hill tail exponent, wedge clustering,
+        spectral gap)."""
         import torch
         rng = np.random.default_rng(seed)
         splits = []
@@ -149,9 +120,10 @@ class Task:
             ntr = max(1, int(round(train_ratio * g.n)))
             splits.append((torch.from_numpy(np.sort(perm[:ntr]).astype(np.int32)).cuda(),
                            torch.from_numpy(np.sort(perm[ntr:]).astype(np.int32)).cuda()))
-        return Task(g, torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.col).cuda(),
-                    torch.from_numpy(g.labels.astype(np.uint8)).cuda(), dict(base),
-                    graph_stats(g, seed), splits)
+        rp = torch.from_numpy(g.rowptr).cuda()
+        col = torch.from_numpy(g.col).cuda()
+        return Task(g, rp, col, torch.from_numpy(g.labels.astype(np.uint8)).cuda(), dict(base),
+                    graph_stats(ctx, rp, col, seed), splits)
 
 
 def evaluate(ctx: Context, task: Task, trial: Trial) -> float:

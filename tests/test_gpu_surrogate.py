@@ -130,14 +130,14 @@ def test_search_arms_run_end_to_end(lne, ctx):
     [0, 1] and the batched arm reusing one captured graph per round shape."""
     from paper_2302_07084_amd import search
     rng = np.random.default_rng(3)
-    fam = [_task(lne, intra, seed=40 + i) for i, intra in enumerate((0.45, 0.55))]
+    fam = [_task(lne, ctx, intra, seed=40 + i) for i, intra in enumerate((0.45, 0.55))]
     F, y = search.pretrain_pairs(ctx, fam, 8, rng, max_batch=4)
     assert F.shape == (16, search.IN_DIM) and y.shape == (16,)
     sur = search.Surrogate(ctx, seed=1)
     sur.set_scaler(F)
     sur.add(F, y)
     sur.fit(epochs=50)
-    task = _task(lne, 0.5, seed=50)
+    task = _task(lne, ctx, 0.5, seed=50)
     sa, ta, ea = search.plain_sequential_search(ctx, task, search.sample_trials(rng, 3))
     assert sa.shape == (3, len(task.splits)) and np.all(np.diff(ta) > 0) and ea > 0
     tb, sb, stb, eb, setup = search.batched_surrogate_search(ctx, task, sur, 8, rng, per_round=4)
@@ -157,14 +157,14 @@ def test_scorer_rejects_bad_indices(lne, ctx):
                            torch.tensor([2, 3], device="cuda"))
 
 
-def _task(lne, intra, seed):
+def _task(lne, ctx, intra, seed):
     from paper_2302_07084_amd import search
     n_b, bs, deg = 10, 200, 10
     n = n_b * bs
     g = sbm([bs] * n_b, intra * deg / (bs - 1), (1 - intra) * deg / (n - bs), seed=seed)
     base = dict(T=10, M=20 * 10 * g.m, b=1, C=float(np.log(g.n)), d=32, oversample=10, q=1,
                 seed=seed, precision="f32")
-    return search.Task.make(g, base, train_ratio=0.5, seed=seed)
+    return search.Task.make(ctx, g, base, train_ratio=0.5, seed=seed)
 
 
 def test_surrogate_beats_random_proposals(lne, ctx):
@@ -181,7 +181,7 @@ def test_surrogate_beats_random_proposals(lne, ctx):
     sur = search.Surrogate(ctx, seed=0)
     F, y = [], []
     for i, intra in enumerate((0.42, 0.46, 0.5, 0.54, 0.58, 0.62)):
-        task = _task(lne, intra, seed=10 + i)
+        task = _task(lne, ctx, intra, seed=10 + i)
         trials, scores = search.random_search(ctx, task, 64, rng)
         F.append(search.features(task, trials))
         y.extend(search.standardize(scores))
@@ -191,7 +191,7 @@ def test_surrogate_beats_random_proposals(lne, ctx):
     sur.fit(epochs=800)
     gains, rhos = [], []
     for i, intra in enumerate((0.44, 0.48, 0.52, 0.56, 0.6)):
-        task = _task(lne, intra, seed=30 + i)
+        task = _task(lne, ctx, intra, seed=30 + i)
         rtrials, rscores = search.random_search(ctx, task, 32, rng)
         cand = search.sample_trials(rng, 4096)
         pred = sur.predict(search.features(task, cand))
