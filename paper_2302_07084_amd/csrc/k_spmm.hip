@@ -281,24 +281,37 @@ k_spmm_sparse_omega(const int64_t *__restrict__ rp, const int32_t *__restrict__ 
     for (int c = lane; c < k; c += 64) Y[row * ldy + c] = (OT)acc[c];
 }
 
+// Streaming element-wise kernels over n x k row blocks: each wave walks rows
+// (grid-stride), its lanes across the row's columns, so no per-element index
+// division.
 template <class XT, class YT>
 __global__ void k_scale(const XT *__restrict__ x, int64_t ldx, YT *__restrict__ y, int64_t ldy,
                         int64_t n, int k, double alpha) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * k) return;
-    const int64_t i = t / k;
-    const int c = (int)(t - i * k);
-    y[i * ldy + c] = (YT)(alpha * (double)x[i * ldx + c]);
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = w0; i < n; i += nw)
+        for (int c = lane; c < k; c += 64) y[i * ldy + c] = (YT)(alpha * (double)x[i * ldx + c]);
 }
 
 template <class T>
 __global__ void k_axpby(const T *__restrict__ x, const T *__restrict__ y, T *__restrict__ out,
                         int64_t n, int k, int64_t ld, T a, T b) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * k) return;
-    const int64_t i = t / k;
-    const int64_t o = i * ld + (t - i * k);
-    out[o] = a * x[o] + b * y[o];
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = w0; i < n; i += nw)
+        for (int c = lane; c < k; c += 64) {
+            const int64_t o = i * ld + c;
+            out[o] = a * x[o] + b * y[o];
+        }
+}
+
+// Blocks of the row-walking kernels: 4 waves each, one row per wave, at most
+// 64 blocks per CU (the loop covers the remaining rows).
+inline unsigned rows_grid(int64_t n) {
+    const int64_t blocks = ceil_div(n, 4);   // 4 waves (256 threads) per block
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 64));
 }
 
 // launch shapes: unroll depth 4 or 8, structure loads normal or non-temporal
@@ -530,7 +543,7 @@ lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t 
     if (n * k == 0) return LNE_OK;
     {
         Launch L(ctx, "axpby");
-        const unsigned grid = grid_of(n * k, 256);
+        const unsigned grid = rows_grid(n);
         if (dt == LNE_F64)
             k_axpby<double><<<grid, 256, 0, ctx->stream>>>((const double *)x, (const double *)y,
                                                            (double *)out, n, k, ld, a, b);
@@ -547,7 +560,7 @@ lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t 
 lne_status dense_scale(lne_ctx *ctx, const void *x, int32_t xt, int64_t ldx, void *y,
                        int32_t yt, int64_t ldy, int64_t n, int32_t k, double alpha) {
     if (n * k == 0) return LNE_OK;
-    const unsigned grid = grid_of(n * k, 256);
+    const unsigned grid = rows_grid(n);
     {
         Launch L(ctx, "dense_scale");
 #define LNE_SC(XT, YT)                                                                    \
