@@ -57,15 +57,22 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
     constexpr int KPM = gram_kp_max(MAXT, SPLIT);
     constexpr int kLd = (kGramRows * KPM + kGramThreads - 1) / kGramThreads;
     __shared__ double tile[2][kGramRows * KPM];       // kGramRows x KP each
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the wave index as a scalar, so that the tile indices below are too
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
+    // a block takes a contiguous run of the upper tiles in row order and each
+    // wave a contiguous part of it, so that a wave's tiles mostly share their
+    // tile row and its A fragment is read from LDS once per step
+    const int cb = (ntu + SPLIT - 1) / SPLIT, cw = (cb + 7) / 8;
+    const int t0 = (int)blockIdx.z * cb + w * cw, t1 = min(min(ntu, ((int)blockIdx.z + 1) * cb),
+                                                           t0 + cw);
     int TI[MAXT], TJ[MAXT];
     v4d acc[MAXT];
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
         acc[s] = (v4d){0, 0, 0, 0};
-        const int t = w + 8 * ((int)blockIdx.z + SPLIT * s);
-        if (t < ntu) upper_tile(t, nt, TI[s], TJ[s]); else { TI[s] = TJ[s] = -1; }
+        const int t = t0 + s;
+        if (t < t1) upper_tile(t, nt, TI[s], TJ[s]); else { TI[s] = TJ[s] = -1; }
     }
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
     const int64_t r_end = min(n, r_begin + rows_per_wg);
@@ -88,6 +95,21 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
             if (idx < tsz) tile[buf][idx] = to_d(v[u]);
         }
     };
+    auto mfma_tile = [&](int cur) {
+#pragma unroll
+        for (int kk = 0; kk < kGramRows; kk += 4) {
+            const double *trow = tile[cur] + (kk + kr) * KP + kc;
+            double a = 0.0;
+#pragma unroll
+            for (int s = 0; s < MAXT; ++s) {
+                if (TI[s] >= 0) {
+                    if (s == 0 || TI[s] != TI[s - 1]) a = trow[16 * TI[s]];
+                    const double b = trow[16 * TJ[s]];
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                }
+            }
+        }
+    };
     YT v[kLd];
     if (r_begin < r_end) {
         gload(r_begin, v);
@@ -98,18 +120,7 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
     for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows, cur ^= 1) {
         const bool more = r0 + kGramRows < r_end;
         if (more) gload(r0 + kGramRows, v);
-#pragma unroll
-        for (int kk = 0; kk < kGramRows; kk += 4) {
-            const double *trow = tile[cur] + (kk + kr) * KP + kc;
-#pragma unroll
-            for (int s = 0; s < MAXT; ++s) {
-                if (TI[s] >= 0) {
-                    const double a = trow[16 * TI[s]];
-                    const double b = trow[16 * TJ[s]];
-                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
-                }
-            }
-        }
+        mfma_tile(cur);
         if (more) lstore(cur ^ 1, v);
         __syncthreads();
     }
