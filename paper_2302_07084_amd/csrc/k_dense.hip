@@ -182,14 +182,30 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
     const int64_t r_end = min(n, r_begin + rows_per_wg);
     const int kr = lane >> 4, kc = lane & 15;
     const int nch = KP / 8;
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += kBR) {
-        for (int idx = tid; idx < nch * kBR; idx += kGramThreads) {
-            const int rr = idx % kBR, c = (idx / kBR) * 8;
-            const v8bf v = load8(Y, ld, r0 + rr, r_end, c, k, vec != 0);
+    // the next tile's 16-byte chunks are requested into registers before the
+    // matrix-core steps of the current one and written to LDS after them
+    constexpr int NP = (288 / 8 * kBR + kGramThreads - 1) / kGramThreads;
+    v8bf pv[NP];
+    auto fetch = [&](int64_t r0) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) tt[(c + i) * kTS2 + rr] = v[i];
+        for (int u = 0; u < NP; ++u) {
+            const int idx = tid + u * kGramThreads;
+            if (idx < nch * kBR) pv[u] = load8(Y, ld, r0 + idx % kBR, r_end, (idx / kBR) * 8, k, vec != 0);
+        }
+    };
+    if (r_begin < r_end) fetch(r_begin);
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kBR) {
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int idx = tid + u * kGramThreads;
+            if (idx < nch * kBR) {
+                const int rr = idx % kBR, c = (idx / kBR) * 8;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) tt[(c + i) * kTS2 + rr] = pv[u][i];
+            }
         }
         __syncthreads();
+        if (r0 + kBR < r_end) fetch(r0 + kBR);
 #pragma unroll
         for (int ks = 0; ks < kBR; ks += 32) {
 #pragma unroll
