@@ -808,7 +808,10 @@ def precision_report(name):
            "gap_at_d_prime": float(gaps[dprime - 1]), "results": {}}
     for prec, u in (("f32", 2.0 ** -24), ("bf16", 2.0 ** -8)):
         r = res[prec]
-        bar = 100 * math.sqrt(kp) * u / max(float(gaps[dprime - 1]), 1e-12)
+        # every stored n x k' block is rounded entry by entry, so the factorised products
+        # move by at most about 4 sqrt(k') u s_1: the principal angle of the top d' vectors
+        # is then at most 4 sqrt(k') u / gap (the bar of the precision tests)
+        bar = 4 * math.sqrt(kp) * u / max(float(gaps[dprime - 1]), 1e-12)
         out["results"][prec] = {
             "sigma_max_rel_err": float(np.max(np.abs(r["S"] - S) / S)),
             "U_principal_angle_top_dprime": _principal_angle(r["U"][:, :dprime], ref["U"][:, :dprime]),
