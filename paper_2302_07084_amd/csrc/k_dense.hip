@@ -55,7 +55,6 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
     constexpr int KPM = gram_kp_max(MAXT, SPLIT);
-    constexpr int kLd = (kGramRows * KPM + kGramThreads - 1) / kGramThreads;
     __shared__ double tile[2][kGramRows * KPM];       // kGramRows x KP each
     // the wave index as a scalar, so that the tile indices below are too
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -77,25 +76,30 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
     const int64_t r_end = min(n, r_begin + rows_per_wg);
     const int kr = lane >> 4, kc = lane & 15;
-    const int tsz = kGramRows * KP;
-    // staged in the input type (half the registers for FP32 data)
-    auto gload = [&](int64_t r0, YT v[kLd]) {
+    // a tile is loaded by whole rows: wave w takes rows w, w + 8, ... and its
+    // lanes the row's columns 64 apart (no index division per element)
+    constexpr int RPW = kGramRows / 8, CPR = (KPM + 63) / 64, NLD = RPW * CPR;
+    auto gload = [&](int64_t r0, YT v[NLD]) {
 #pragma unroll
-        for (int u = 0; u < kLd; ++u) {
-            const int idx = tid + u * kGramThreads;
-            const int rr = idx / KP, c = idx - rr * KP;
-            const int64_t row = r0 + rr;
-            v[u] = (idx < tsz && row < r_end && c < k) ? Y[row * ld + c] : (YT)0;
+        for (int i = 0; i < RPW; ++i) {
+            const int64_t row = r0 + w + 8 * i;
+#pragma unroll
+            for (int j = 0; j < CPR; ++j) {
+                const int c = lane + 64 * j;
+                v[i * CPR + j] = (row < r_end && c < k) ? Y[row * ld + c] : (YT)0;
+            }
         }
     };
-    auto lstore = [&](int buf, const YT v[kLd]) {
+    auto lstore = [&](int buf, const YT v[NLD]) {
 #pragma unroll
-        for (int u = 0; u < kLd; ++u) {
-            const int idx = tid + u * kGramThreads;
-            if (idx < tsz) tile[buf][idx] = to_d(v[u]);
-        }
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+            for (int j = 0; j < CPR; ++j) {
+                const int c = lane + 64 * j;
+                if (c < KP) tile[buf][(w + 8 * i) * KP + c] = to_d(v[i * CPR + j]);
+            }
     };
-    auto mfma_tile = [&](int cur) {
+auto mfma_tile = [&](int cur) {
 #pragma unroll
         for (int kk = 0; kk < kGramRows; kk += 4) {
             const double *trow = tile[cur] + (kk + kr) * KP + kc;
@@ -110,7 +114,7 @@ k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t
             }
         }
     };
-    YT v[kLd];
+    YT v[NLD];
     if (r_begin < r_end) {
         gload(r_begin, v);
         lstore(0, v);
