@@ -30,7 +30,7 @@ __device__ __forceinline__ void upper_tile(int t, int nt, int &I, int &J) {
 }
 
 // ---------------------------------------------------------------- Gram FP64
-constexpr int kGramRows = 32;
+constexpr int kGramRows = 16;
 constexpr int kGramThreads = 512;
 
 // Widest padded k whose upper 16 x 16 tiles fit SPLIT blocks of 8 waves x
@@ -44,10 +44,13 @@ constexpr int gram_kp_max(int maxt, int split) {
 // Two LDS tiles of kGramRows rows: the next tile's loads are issued into
 // registers before the matrix-core steps of the current one and stored to
 // the other buffer after them, so one block barrier per tile separates them.
-// SPLIT blocks (blockIdx.z) share a row range and take alternate groups of 8
-// output tiles, so that a wide k keeps its accumulators in registers.
+// Small tiles (16 rows) keep a block's LDS small enough for three blocks per
+// CU at k' <= 144 and two at k' <= 272, so that other blocks' matrix-core
+// steps cover each block's barrier and tile turnaround.  SPLIT blocks
+// (blockIdx.z) share a row range and split its upper output tiles, so that a
+// wide k keeps its accumulators in registers.
 template <class YT, int MAXT, int SPLIT>
-__global__ void __launch_bounds__(kGramThreads, (MAXT <= 6 && sizeof(YT) == 4) ? 4 : 2)
+__global__ void __launch_bounds__(kGramThreads, MAXT <= 6 ? 6 : 2)
 k_gram64(const YT *__restrict__ Y, int64_t n, int k, int64_t ld, int KP, int64_t rows_per_wg,
          double *__restrict__ part, const int32_t *__restrict__ skip, int64_t ys) {
     Y += (int64_t)blockIdx.y * ys;
@@ -1245,9 +1248,10 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     if (per_wave > 22) return fail(ctx, LNE_EUNSUPPORTED, "gram: k = %d above 288", k);
     if (nb < 1 || nb > 65535) return fail(ctx, LNE_EINVAL, "gram: batch of %d", nb);
     const int64_t blocks_rows = ceil_div(n > 0 ? n : 1, kGramRows);
-    // about 512 (256 for wide k) workgroups over the whole batch, or as many
-    // per-workgroup partial sums as a caller's workspace holds
-    int64_t target = std::max<int64_t>(1, (KP > 160 ? 256 : 512) / nb);
+    // about 768 (512 for wide k) workgroups over the whole batch, one round
+    // of three (two) blocks per CU, or as many per-workgroup partial sums as
+    // a caller's workspace holds
+    int64_t target = std::max<int64_t>(1, (KP > 160 ? 512 : 768) / nb);
     const size_t part_one = sizeof(double) * (size_t)nb * KP * KP;
     if (part_ws) {
         if (part_ws_bytes < part_one)
