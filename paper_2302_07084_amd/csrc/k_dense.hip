@@ -285,7 +285,7 @@ __device__ __forceinline__ void load4d(const YT *__restrict__ Y, int64_t ld, int
 // a 16-wide k chunk are four consecutive elements of its row, read with one
 // vector load; the chunk of W is staged in LDS.
 template <class YT, class OT, int MAXJ>
-__global__ void __launch_bounds__(kProjThreads)
+__global__ void __launch_bounds__(kProjThreads, MAXJ <= 3 ? 6 : 2)
 k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
          const double *__restrict__ W, int kout, OT *__restrict__ out, int64_t ldo,
          const int32_t *__restrict__ skip, int64_t ys, int64_t ws, int64_t os, int vec) {
@@ -301,7 +301,9 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
     constexpr int kWn = (kKC * KPo + kProjThreads - 1) / kProjThreads;
     __shared__ double Ws[2][kKC * KPo];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int ntout = (kout + 15) / 16;
+    // blockIdx.z takes output column tiles jz .. jz + MAXJ - 1
+    const int jz = (int)blockIdx.z * MAXJ, cz = 16 * jz;
+    const int ntout = min(MAXJ, (kout + 15) / 16 - jz);
     const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
     const int kr = lane >> 4, kc = lane & 15;
     const int64_t arow = r0 + 16 * w + kc;
@@ -311,7 +313,9 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
             const int idx = tid + u * kProjThreads;
             const int rr = idx / KPo, c = idx - rr * KPo;
             const int krow = k0 + rr;
-            wr[u] = (idx < kKC * KPo && krow < kin && c < kout) ? W[(int64_t)krow * kout + c] : 0.0;
+            wr[u] = (idx < kKC * KPo && krow < kin && cz + c < kout)
+                        ? W[(int64_t)krow * kout + cz + c]
+                        : 0.0;
         }
     };
     auto wstore = [&](int buf, const double wr[kWn]) {
@@ -356,7 +360,7 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
 #pragma unroll
     for (int J = 0; J < MAXJ; ++J) {
         if (J >= ntout) continue;
-        const int c = 16 * J + kc;
+        const int c = cz + 16 * J + kc;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t row = r0 + 16 * w + kr + 4 * i;
@@ -1346,14 +1350,18 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
         const int vmul = y_t == LNE_F64 ? 2 : 4;
         const int vec = ((uintptr_t)Y % 16 == 0 && ldy % vmul == 0 && ys % vmul == 0) ? 1 : 0;
         Launch L(ctx, "project");
+        // at most 9 output column tiles per block: a wider output is split
+        // over blockIdx.z (fewer accumulators per wave, so that two blocks
+        // share a CU and cover each other's barriers; at k' <= 144 a split
+        // costs more in repeated Y reads and spills than it gains)
 #define LNE_P64(YT, OT, MJ)                                                                \
-    k_proj64<YT, OT, MJ><<<grid, kProjThreads, 0, ctx->stream>>>(                          \
+    k_proj64<YT, OT, MJ><<<dim3(grid.x, grid.y, (unsigned)((ntout + (MJ) - 1) / (MJ))),  \
+                           kProjThreads, 0, ctx->stream>>>(                                \
         (const YT *)Y, ldy, n, kin, W, kout, (OT *)out, ldo, skip, ys, ws, os, vec)
 #define LNE_P64J(YT, OT)                                                                   \
     do {                                                                                   \
         if (ntout <= 3) LNE_P64(YT, OT, 3);                                                \
-        else if (ntout <= 9) LNE_P64(YT, OT, 9);                                           \
-        else LNE_P64(YT, OT, 18);                                                          \
+        else LNE_P64(YT, OT, 9);                                                           \
     } while (0)
         if (y_t == LNE_F64 && out_t == LNE_F64) LNE_P64J(double, double);
         else if (y_t == LNE_F32 && out_t == LNE_F32) LNE_P64J(float, float);
