@@ -163,12 +163,13 @@ __device__ __forceinline__ v8bf load8(const __bf16 *__restrict__ Y, int64_t ld, 
 
 // BF16 Gram: 64-row tiles read with 16-byte loads (consecutive lanes take
 // consecutive rows of one 8-column chunk, so the transposed LDS writes do not
-// conflict), two 16 x 16 x 32 MFMA steps per tile and output tile.  vec: rows
-// are 16-byte aligned (ld % 8 == 0, aligned base).
+// conflict), two 16 x 16 x 32 MFMA steps per tile and output tile.  The
+// per-block sums are FP32 (the accumulators' own type).  vec: rows are
+// 16-byte aligned (ld % 8 == 0, aligned base).
 template <int MAXT>
 __global__ void __launch_bounds__(kGramThreads)
 k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
-            int64_t rows_per_wg, double *__restrict__ part, const int32_t *__restrict__ skip,
+            int64_t rows_per_wg, float *__restrict__ part, const int32_t *__restrict__ skip,
             int64_t ys, int vec) {
     Y += (int64_t)blockIdx.y * ys;
     part += (int64_t)blockIdx.y * gridDim.x * KP * KP;
@@ -228,29 +229,52 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
         }
         __syncthreads();
     }
-    double *P = part + (int64_t)blockIdx.x * KP * KP;
+    float *P = part + (int64_t)blockIdx.x * KP * KP;
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
         if (TI[s] < 0) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            P[(int64_t)(16 * TI[s] + 4 * kr + i) * KP + 16 * TJ[s] + kc] = (double)acc[s][i];
+            P[(int64_t)(16 * TI[s] + 4 * kr + i) * KP + 16 * TJ[s] + kc] = acc[s][i];
     }
 }
 
-__global__ void k_gram_reduce(const double *__restrict__ part, int nwg, int KP, int k,
-                              double *__restrict__ G, const int32_t *__restrict__ skip) {
+// G = sum of the per-workgroup upper partial Grams, mirrored.  A block sums
+// 64 consecutive entries (a, b), b >= a, of one row a: its four waves take
+// the workgroups w = q mod 4, two running sums each, combined in a fixed
+// order (the result does not depend on the launch).
+constexpr int kRedThreads = 256;
+template <class PT>
+__global__ void __launch_bounds__(kRedThreads)
+k_gram_reduce(const PT *__restrict__ part, int nwg, int KP, int k, double *__restrict__ G,
+              const int32_t *__restrict__ skip) {
     part += (int64_t)blockIdx.y * nwg * KP * KP;
     G += (int64_t)blockIdx.y * k * k;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)k * k) return;
-    const int i = (int)(t / k), j = (int)(t % k);
-    const int a = min(i, j), b = max(i, j);
-    double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += part[((int64_t)w * KP + a) * KP + b];
-    G[(int64_t)i * k + j] = s;
+    const int nbc = (k + 63) / 64;
+    const int a = (int)blockIdx.x / nbc, b = ((int)blockIdx.x % nbc) * 64 + (threadIdx.x & 63);
+    const int q = threadIdx.x >> 6;
+    __shared__ double sums[4][64];
+    double s0 = 0.0, s1 = 0.0;
+    if (b >= a && b < k) {
+        const PT *pa = part + (int64_t)a * KP + b;
+        const int64_t step = (int64_t)KP * KP;
+        int w = q;
+        for (; w + 4 < nwg; w += 8) {
+            s0 += (double)pa[w * step];
+            s1 += (double)pa[(w + 4) * step];
+        }
+        if (w < nwg) s0 += (double)pa[w * step];
+    }
+    sums[q][threadIdx.x & 63] = s0 + s1;
+    __syncthreads();
+    if (q == 0 && b >= a && b < k) {
+        const int l = threadIdx.x;
+        const double g = (sums[0][l] + sums[1][l]) + (sums[2][l] + sums[3][l]);
+        G[(int64_t)a * k + b] = g;
+        G[(int64_t)b * k + a] = g;
+    }
 }
 
 // ---------------------------------------------------------------- projection
@@ -1246,6 +1270,7 @@ size_t project_bf16_ws_bytes(int32_t kin, int32_t kout, int32_t nb) {
 lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k, int64_t ld,
                 double *G, const int32_t *skip, int32_t nb, int64_t ys, double *part_ws,
                 size_t part_ws_bytes) {
+    if (k < 1) return fail(ctx, LNE_EINVAL, "gram: k = %d", k);
     const int KP = ((k + 15) / 16) * 16;
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
     const int per_wave = (ntu + 7) / 8;
@@ -1256,7 +1281,9 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     // of three (two) blocks per CU, or as many per-workgroup partial sums as
     // a caller's workspace holds
     int64_t target = std::max<int64_t>(1, (KP > 160 ? 512 : 768) / nb);
-    const size_t part_one = sizeof(double) * (size_t)nb * KP * KP;
+    // per-workgroup sums: FP32 for BF16 data (its accumulators), else FP64
+    const size_t part_es = dtype == LNE_BF16 ? sizeof(float) : sizeof(double);
+    const size_t part_one = part_es * (size_t)nb * KP * KP;
     if (part_ws) {
         if (part_ws_bytes < part_one)
             return fail(ctx, LNE_EUNSUPPORTED, "gram: workspace of %zu bytes below %zu",
@@ -1275,7 +1302,7 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
         if (dtype == LNE_BF16) {
 #define LNE_GB(MT)                                                                         \
     k_gram_bf16<MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
-        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<double>(), skip, ys, vec)
+        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<float>(), skip, ys, vec)
             if (per_wave <= 1) LNE_GB(1);
             else if (per_wave <= 6) LNE_GB(6);
             else if (per_wave <= 12) LNE_GB(12);
@@ -1302,8 +1329,13 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     LNE_TRY(check_launch(ctx, "gram"));
     {
         Launch L(ctx, "gram_reduce");
-        k_gram_reduce<<<dim3(grid_of((int64_t)k * k, 256), (unsigned)nb), 256, 0, ctx->stream>>>(
-            part.as<double>(), nwg, KP, k, G, skip);
+        const dim3 rgrid((unsigned)(k * ((k + 63) / 64)), (unsigned)nb);
+        if (dtype == LNE_BF16)
+            k_gram_reduce<float><<<rgrid, kRedThreads, 0, ctx->stream>>>(part.as<float>(), nwg, KP,
+                                                                         k, G, skip);
+        else
+            k_gram_reduce<double><<<rgrid, kRedThreads, 0, ctx->stream>>>(part.as<double>(), nwg,
+                                                                          KP, k, G, skip);
     }
     return check_launch(ctx, "gram_reduce");
 }
