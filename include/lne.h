@@ -89,9 +89,14 @@ typedef struct lne_ctx lne_ctx;
 typedef struct {
     int64_t n;                 /* vertices                                   */
     int64_t n_arcs;            /* 2m, must be < 2^32 (= vol(G) unweighted)   */
-    const int64_t *row_ptr;    /* device, n + 1 entries, row_ptr[0] = 0      */
+    const void *row_ptr;       /* device, n + 1 offsets of index_bits bits,  *
+                                * row_ptr[0] = 0                             */
     const int32_t *col;        /* device, n_arcs entries                     */
     const uint32_t *weight;    /* device, n_arcs entries, or NULL            */
+    int32_t index_bits;        /* row_ptr element width: 64 (0 reads as 64)  *
+                                * or 32 (int32 offsets, n_arcs < 2^31; the   *
+                                * library widens them into its own buffer at *
+                                * each call, after the host-side checks)     */
 } lne_graph;
 
 /* Hyperparameters (notation table of the paper; s_r of Eq. (1)). */

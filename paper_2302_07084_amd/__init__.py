@@ -35,7 +35,7 @@ class LneError(RuntimeError):
 class Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_arcs", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
-                ("weight", ctypes.c_void_p)]
+                ("weight", ctypes.c_void_p), ("index_bits", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -282,16 +282,18 @@ class Context:
 
 
 def graph_struct(rowptr, col, weight=None):
-    """lne_graph over device tensors (int64 row offsets, int32 columns and,
-    for a weighted graph, int32 positive arc weights read as uint32)."""
+    """lne_graph over device tensors (int64 or int32 row offsets, int32
+    columns and, for a weighted graph, int32 positive arc weights read as
+    uint32)."""
     import torch
     assert rowptr.is_cuda and col.is_cuda
-    assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
+    assert rowptr.dtype in (torch.int64, torch.int32) and col.dtype == torch.int32
     assert rowptr.is_contiguous() and col.is_contiguous()
     g = Graph()
     g.n = rowptr.numel() - 1
     g.n_arcs = col.numel()
     g.row_ptr = rowptr.data_ptr()
+    g.index_bits = 32 if rowptr.dtype == torch.int32 else 64
     g.col = col.data_ptr() if col.numel() else None
     g.weight = None
     if weight is not None:

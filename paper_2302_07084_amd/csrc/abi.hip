@@ -101,6 +101,40 @@ lne_status validate_graph(lne_ctx *ctx, const lne_graph *g) {
                     (long long)g->n_arcs);
     if (!g->row_ptr || (g->n_arcs > 0 && !g->col))
         return fail(ctx, LNE_EINVAL, "graph: NULL row_ptr or col");
+    if (g->index_bits != 0 && g->index_bits != 32 && g->index_bits != 64)
+        return fail(ctx, LNE_EINVAL, "graph: index_bits = %d (32 or 64)", g->index_bits);
+    if (g->index_bits == 32 && g->n_arcs >= (int64_t)1 << 31)
+        return fail(ctx, LNE_EINVAL, "graph: 32-bit offsets with n_arcs = %lld >= 2^31",
+                    (long long)g->n_arcs);
+    return LNE_OK;
+}
+
+namespace {
+__global__ void k_widen_offsets(const int32_t *__restrict__ in, int64_t *__restrict__ out,
+                                int64_t n1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n1) out[i] = (int64_t)in[i];
+}
+}  // namespace
+
+lne_status bind_graph(lne_ctx *ctx, const lne_graph *g, Buf &rp, Graph &out) {
+    out.n = g->n;
+    out.n_arcs = g->n_arcs;
+    out.col = g->col;
+    out.weight = g->weight;
+    if (g->index_bits != 32) {
+        out.row_ptr = static_cast<const int64_t *>(g->row_ptr);
+        return LNE_OK;
+    }
+    const int64_t n1 = g->n + 1;
+    LNE_TRY(alloc(ctx, rp, sizeof(int64_t) * (size_t)n1));
+    {
+        Launch L(ctx, "widen_offsets");
+        k_widen_offsets<<<grid_of(n1, 256), 256, 0, ctx->stream>>>(
+            static_cast<const int32_t *>(g->row_ptr), rp.as<int64_t>(), n1);
+    }
+    LNE_TRY(check_launch(ctx, "widen_offsets"));
+    out.row_ptr = rp.as<int64_t>();
     return LNE_OK;
 }
 
@@ -224,7 +258,7 @@ struct Sampler {
 
 // Edge list of the sampler and, on a weighted graph, its weight tables: the
 // prefix sums of the arc weights and each edge's weight.
-static lne_status sampler_edges(lne_ctx *ctx, const lne_graph *g, Sampler &S) {
+static lne_status sampler_edges(lne_ctx *ctx, const Graph *g, Sampler &S) {
     LNE_TRY(build_edges(ctx, g, S.eu, S.ev, S.m, g->weight ? &S.ea : nullptr));
     if (!g->weight) return LNE_OK;
     uint64_t vol = 0;
@@ -237,7 +271,7 @@ static lne_status sampler_edges(lne_ctx *ctx, const lne_graph *g, Sampler &S) {
     return LNE_OK;
 }
 
-static lne_status count_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
+static lne_status count_range(lne_ctx *ctx, const Graph *g, Sampler &S, int64_t lo,
                               int64_t hi, uint64_t *entries, bool stats) {
     Buf scal(ctx);
     LNE_TRY(alloc(ctx, scal, 24));
@@ -274,7 +308,7 @@ struct TruncLogFuse {
 // Aggregates the pair entries of rows [lo, hi) (already counted into S.wo)
 // into a count CSR block with hi - lo rows (or, with tl, the truncated-log
 // block with explicit zeros for dropped pairs).
-static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, int64_t lo,
+static lne_status aggregate_range(lne_ctx *ctx, const Graph *g, Sampler &S, int64_t lo,
                                   int64_t hi, uint64_t entries, lne_csr *out,
                                   TruncLogFuse *tl = nullptr) {
     const int64_t P = (int64_t)entries;
@@ -321,7 +355,7 @@ static lne_status aggregate_range(lne_ctx *ctx, const lne_graph *g, Sampler &S, 
 // lower triangle, and the two are merged into the symmetric matrix -- the
 // same entries as reducing both orientations of every sample, with half the
 // items in the six-pass sort (S.pl.upper set, entries counted that way).
-static lne_status aggregate_sym(lne_ctx *ctx, const lne_graph *g, Sampler &S, uint64_t entries,
+static lne_status aggregate_sym(lne_ctx *ctx, const Graph *g, Sampler &S, uint64_t entries,
                                 lne_csr *out, TruncLogFuse *tl) {
     const int64_t P = (int64_t)entries;
     const int colbits = S.pl.colbits;
@@ -371,7 +405,7 @@ static lne_status aggregate_sym(lne_ctx *ctx, const lne_graph *g, Sampler &S, ui
 // while a range is still too large), each range walking every sample again
 // and keeping the entries whose row falls inside it.
 template <class Sink>
-static lne_status sparsify_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+static lne_status sparsify_impl(lne_ctx *ctx, const Graph *g, const lne_params *p,
                                 lne_stats *st, Sink &&sink, bool channels = false,
                                 TruncLogFuse *tl = nullptr) {
     Sampler S;
@@ -781,7 +815,7 @@ static lne_status rsvd_impl(lne_ctx *ctx, const MatOp &op, const lne_params *p, 
     return read_flags(ctx, f, st);
 }
 
-static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+static lne_status propagate_impl(lne_ctx *ctx, const Graph *g, const lne_params *p,
                                  const void *X0, void *X) {
     const int64_t n = g->n;
     const int32_t d = p->d;
@@ -842,7 +876,7 @@ static lne_status propagate_impl(lne_ctx *ctx, const lne_graph *g, const lne_par
 // give the same products).  In HBM the blocks are concatenated into *M; with
 // host they move to pinned host memory (H) as they are built.  *kept = the
 // number of nonzero entries (st->nnz_log too).
-static lne_status embed_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+static lne_status embed_matrix(lne_ctx *ctx, const Graph *g, const lne_params *p,
                                lne_stats *st, bool host, lne_csr *M, HostMatrix &H,
                                uint64_t *kept_out) {
     TruncLogFuse tl;
@@ -888,7 +922,7 @@ static lne_status embed_matrix(lne_ctx *ctx, const lne_graph *g, const lne_param
 
 // The channel sampling pass of the batched trials: the sparsifier with the
 // walk length r kept in the key (column b << 4 | r - 1), as one CSR.
-lne_status channels_pass(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
+lne_status channels_pass(lne_ctx *ctx, const Graph *g, const lne_params *p, lne_csr *out,
                          lne_stats *st) {
     if (g->n > ((int64_t)1 << 30))
         return fail(ctx, LNE_EUNSUPPORTED, "channel sparsifier: n above 2^30");
@@ -1028,19 +1062,22 @@ lne_status lne_sampler_plan(const lne_params *p, int64_t n_arcs, uint64_t *base,
     return LNE_OK;
 }
 
-lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                             int64_t e_begin, int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
                             uint8_t *r) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
-    const int64_t m = g->n_arcs / 2;
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
+    const int64_t m = gin->n_arcs / 2;
     if (e_begin < 0 || e_end < e_begin || e_end > m)
         return fail(ctx, LNE_EINVAL, "sample_slots: edge range [%lld, %lld) outside [0, %lld)",
                     (long long)e_begin, (long long)e_end, (long long)m);
     if (e_end > e_begin && (!a || !b || !w || !r))
         return fail(ctx, LNE_EINVAL, "sample_slots: NULL output");
     if (e_end == e_begin) return LNE_OK;
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     Sampler S;
     LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
@@ -1050,13 +1087,16 @@ lne_status lne_sample_slots(lne_ctx *ctx, const lne_graph *g, const lne_params *
                                e_end, a, b, w, r);
 }
 
-lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
+lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *gin, const lne_params *p, lne_csr *out,
                         lne_stats *st) {
     if (!ctx) return LNE_EINVAL;
     if (!out) return fail(ctx, LNE_EINVAL, "sparsify: out is NULL");
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
     std::memset(out, 0, sizeof(*out));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     std::vector<lne_csr> blocks;
     auto sink = [&](lne_csr &blk, int64_t) -> lne_status {
@@ -1069,17 +1109,20 @@ lne_status lne_sparsify(lne_ctx *ctx, const lne_graph *g, const lne_params *p, l
     return s;
 }
 
-lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                             int64_t row_lo, int64_t row_hi, lne_csr *out, lne_stats *st) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
     if (!out) return fail(ctx, LNE_EINVAL, "sparsify_rows: out is NULL");
-    if (row_lo < 0 || row_hi > g->n || row_lo >= row_hi)
+    if (row_lo < 0 || row_hi > gin->n || row_lo >= row_hi)
         return fail(ctx, LNE_EINVAL, "sparsify_rows: rows [%lld, %lld) outside [0, %lld)",
-                    (long long)row_lo, (long long)row_hi, (long long)g->n);
+                    (long long)row_lo, (long long)row_hi, (long long)gin->n);
     std::memset(out, 0, sizeof(*out));
     if (st) std::memset(st, 0, sizeof(*st));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     Sampler S;
     LNE_TRY(make_plan(ctx, p, g->n, g->n_arcs, S.pl));
@@ -1107,16 +1150,19 @@ lne_status lne_sparsify_rows(lne_ctx *ctx, const lne_graph *g, const lne_params 
     return LNE_OK;
 }
 
-lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_trunc_log(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                          const lne_csr *counts, lne_csr *out) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
-    if (!counts || !out || counts->val_type != LNE_U64 || counts->n_rows != g->n)
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
+    if (!counts || !out || counts->val_type != LNE_U64 || counts->n_rows != gin->n)
         return fail(ctx, LNE_EINVAL, "trunc_log: counts must be the U64 count matrix of g");
     if (p->precision < LNE_F64 || p->precision > LNE_BF16)
         return fail(ctx, LNE_EINVAL, "trunc_log: bad precision");
     std::memset(out, 0, sizeof(*out));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     return trunc_log_csr(ctx, g, p, counts, 0, p->precision == LNE_F64 ? LNE_F64 : LNE_F32, out);
 }
 
@@ -1174,13 +1220,16 @@ lne_status lne_eigsvd(lne_ctx *ctx, const void *Y, int64_t n, int32_t k, int64_t
     return LNE_OK;
 }
 
-lne_status lne_graph_stats(lne_ctx *ctx, const lne_graph *g, uint64_t seed, int32_t wedges,
+lne_status lne_graph_stats(lne_ctx *ctx, const lne_graph *gin, uint64_t seed, int32_t wedges,
                            int32_t iters, double *out) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    if (!out || wedges < 1 || iters < 1 || g->n_arcs < 2)
+    LNE_TRY(validate_graph(ctx, gin));
+    if (!out || wedges < 1 || iters < 1 || gin->n_arcs < 2)
         return fail(ctx, LNE_EINVAL, "graph_stats: needs out, wedges >= 1, iters >= 1, an edge");
-    if (g->weight) return fail(ctx, LNE_EUNSUPPORTED, "graph_stats: unweighted graphs only");
+    if (gin->weight) return fail(ctx, LNE_EUNSUPPORTED, "graph_stats: unweighted graphs only");
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     return graph_stats_impl(ctx, g, seed, wedges, iters, out);
 }
@@ -1213,50 +1262,62 @@ lne_status lne_rsvd(lne_ctx *ctx, const lne_csr *M, const lne_params *p, void *U
     return rsvd_impl(ctx, op, p, U, sigma, V, X0, nullptr);
 }
 
-lne_status lne_propagate(lne_ctx *ctx, const lne_graph *g, const lne_params *p, const void *X0,
+lne_status lne_propagate(lne_ctx *ctx, const lne_graph *gin, const lne_params *p, const void *X0,
                          void *X) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, true));
     if (!X0 || !X) return fail(ctx, LNE_EINVAL, "propagate: NULL matrix");
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     return propagate_impl(ctx, g, p, X0, X);
 }
 
-lne_status lne_graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, int64_t ld,
+lne_status lne_graph_spmm(lne_ctx *ctx, const lne_graph *gin, const void *Z, int64_t ld,
                           int32_t k, int32_t dtype, double a, double b, void *out) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
+    LNE_TRY(validate_graph(ctx, gin));
     if (!Z || !out || k < 1 || ld < k || (dtype != LNE_F64 && dtype != LNE_F32))
         return fail(ctx, LNE_EINVAL, "graph_spmm: bad arguments");
     if (Z == out) return fail(ctx, LNE_EINVAL, "graph_spmm: out must not alias Z");
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     return graph_spmm(ctx, g, Z, out, ld, k, dtype, a, b, nullptr, 0.0, nullptr, 0.0, nullptr,
                       0.0);
 }
 
-lne_status lne_sparsify_log(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_sparsify_log(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                             lne_csr *out, lne_stats *st) {
     if (!ctx) return LNE_EINVAL;
     if (!out) return fail(ctx, LNE_EINVAL, "sparsify_log: out is NULL");
     std::memset(out, 0, sizeof(*out));
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
     if (p->precision < LNE_F64 || p->precision > LNE_BF16)
         return fail(ctx, LNE_EINVAL, "precision must be LNE_F64, LNE_F32 or LNE_BF16");
     if (st) std::memset(st, 0, sizeof(*st));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     HostMatrix H;
     uint64_t kept = 0;
     return embed_matrix(ctx, g, p, st, false, out, H, &kept);
 }
 
-lne_status lne_embed(lne_ctx *ctx, const lne_graph *g, const lne_params *p, void *X,
+lne_status lne_embed(lne_ctx *ctx, const lne_graph *gin, const lne_params *p, void *X,
                      lne_stats *st) {
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, true));
     if (!X) return fail(ctx, LNE_EINVAL, "embed: X is NULL");
     if (st) std::memset(st, 0, sizeof(*st));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     lne_csr M;
     std::memset(&M, 0, sizeof(M));
     const bool host = (p->flags & LNE_FLAG_HOST_SPARSIFIER) != 0;

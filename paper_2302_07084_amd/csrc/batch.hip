@@ -71,7 +71,7 @@ lne_status check_support(lne_ctx *ctx, const lne_trial *t, const lne_params *p) 
 }
 
 // vol^2 / (2 b M) / 2^16: Eq. (1)'s constant on fixed-point counts
-double tl_scale(const lne_graph *g, const lne_params *p) {
+double tl_scale(const Graph *g, const lne_params *p) {
     const double vol = (double)g->n_arcs;
     return vol * vol / (2.0 * (double)p->b * (double)p->M) / 65536.0;
 }
@@ -121,7 +121,8 @@ lne_status eig_project(lne_ctx *ctx, const float *Y, int64_t n, int k, int64_t l
 
 struct lne_batch {
     lne_ctx *ctx = nullptr;
-    lne_graph g{};
+    Graph g{};
+    Buf rp64;
     lne_params p{};
     int32_t max_trials = 0;
     int64_t n = 0;
@@ -337,32 +338,38 @@ struct ArenaScope {
 
 extern "C" {
 
-lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_sparsify_channels(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                                  lne_csr *out, lne_stats *st) {
-    if (ctx && g && g->weight)
+    if (ctx && gin && gin->weight)
         return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
     if (!out) return fail(ctx, LNE_EINVAL, "sparsify_channels: out is NULL");
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
     std::memset(out, 0, sizeof(*out));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
     return channels_pass(ctx, g, p, out, st);
 }
 
-lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                             const lne_csr *channels, const lne_trial *trial, lne_csr *out) {
-    if (ctx && g && g->weight)
+    if (ctx && gin && gin->weight)
         return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, false));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, false));
     if (!channels || !trial || !out || channels->val_type != LNE_U64 ||
-        channels->n_rows != g->n || channels->n_cols != (g->n << 4))
+        channels->n_rows != gin->n || channels->n_cols != (gin->n << 4))
         return fail(ctx, LNE_EINVAL, "trial_matrix: channels must come from lne_sparsify_channels");
     LNE_TRY(check_trial(ctx, trial, p->T));
     LNE_TRY(check_support(ctx, trial, p));
     std::memset(out, 0, sizeof(*out));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     lne_csr st;
     std::memset(&st, 0, sizeof(st));
     Buf chan(ctx), sdev(ctx), vals(ctx);
@@ -387,15 +394,15 @@ lne_status lne_trial_matrix(lne_ctx *ctx, const lne_graph *g, const lne_params *
     return LNE_OK;
 }
 
-lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *gin, const lne_params *p,
                             int32_t max_trials, lne_batch **out, lne_stats *st) {
-    if (ctx && g && g->weight)
+    if (ctx && gin && gin->weight)
         return fail(ctx, LNE_EUNSUPPORTED, "batched trials take unweighted graphs");
     if (!ctx) return LNE_EINVAL;
     if (!out) return fail(ctx, LNE_EINVAL, "batch_create: out is NULL");
     *out = nullptr;
-    LNE_TRY(validate_graph(ctx, g));
-    LNE_TRY(validate_params(ctx, p, g->n, g->n_arcs, true));
+    LNE_TRY(validate_graph(ctx, gin));
+    LNE_TRY(validate_params(ctx, p, gin->n, gin->n_arcs, true));
     if (max_trials < 1 || max_trials > 256)
         return fail(ctx, LNE_EUNSUPPORTED, "batch_create: max_trials = %d outside 1..256", max_trials);
     if (p->precision != LNE_F32) return fail(ctx, LNE_EINVAL, "batch_create: precision must be LNE_F32");
@@ -403,6 +410,9 @@ lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *
     if (round8(kp) > 256 || round8(p->d) > 256)
         return fail(ctx, LNE_EUNSUPPORTED, "batch_create: d + oversample above 256");
     if (st) std::memset(st, 0, sizeof(*st));
+    GraphArg ga(ctx);
+    LNE_TRY(bind_graph(ctx, gin, ga.rp, ga.g));
+    const Graph *g = &ga.g;
     LNE_TRY(validate_graph_device(ctx, g));
 
     lne_batch *b = new (std::nothrow) lne_batch();
@@ -413,6 +423,9 @@ lne_status lne_batch_create(lne_ctx *ctx, const lne_graph *g, const lne_params *
     } guard{b};
     b->ctx = ctx;
     b->g = *g;
+    b->rp64.ctx = ctx;
+    b->rp64.bytes = ga.rp.bytes;
+    b->rp64.p = ga.rp.detach();   // widened offsets (if any) live with the batch
     b->p = *p;
     b->max_trials = max_trials;
     b->n = g->n;

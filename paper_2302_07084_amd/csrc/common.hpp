@@ -55,6 +55,16 @@ lne_status fail(lne_ctx *ctx, lne_status code, const char *fmt, ...);
     } while (0)
 
 // Device scratch from the context allocator, released at scope exit.
+// The input graph as the kernels read it: 64-bit row offsets (lne_graph
+// also accepts 32-bit ones; bind_graph widens them).
+struct Graph {
+    int64_t n = 0;
+    int64_t n_arcs = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const uint32_t *weight = nullptr;
+};
+
 struct Buf {
     lne_ctx *ctx = nullptr;
     void *p = nullptr;
@@ -142,22 +152,22 @@ lne_status make_plan(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arc
                      SamplePlan &pl);
 
 // Device-side structural check of the input CSR; synchronises the stream.
-lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g);
+lne_status validate_graph_device(lne_ctx *ctx, const Graph *g);
 // Edge list (u < v arcs in CSR order): eu, ev of m entries; with ea, the
 // edges' weights too (weighted graphs).
-lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m,
+lne_status build_edges(lne_ctx *ctx, const Graph *g, Buf &eu, Buf &ev, int64_t m,
                        Buf *ea = nullptr);
 // Weighted graph: cw (n_arcs + 1 prefix sums of the weights), vol = sum of
 // weights; EINVAL on a zero weight, EUNSUPPORTED when a weighted degree or vol
 // reaches 2^32.  Synchronises the stream.
-lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol);
+lne_status weight_info(lne_ctx *ctx, const Graph *g, Buf &cw, uint64_t *vol);
 // Guide table of the weighted walk step (one uint32 per arc): for row x with
 // k arcs and weighted degree W, entry b (stored at rp[x] + b) is the local
 // index of the arc whose cumulative-weight slice holds ceil(b W / k).  A step
 // drawing t in [0, W) starts its scan at entry floor(t k / W), at or before
 // the arc that holds t, and passes about one slice on average (the guide
 // tables of Chen and Asau's cutpoint method).  cw from weight_info.
-lne_status weight_guide(lne_ctx *ctx, const lne_graph *g, const uint64_t *cw, Buf &guide);
+lne_status weight_guide(lne_ctx *ctx, const Graph *g, const uint64_t *cw, Buf &guide);
 
 // Sparse-sign test matrix (LNE_FLAG_SPARSE_OMEGA): kSparseOmega signed
 // column entries per row, int16 sign (column + 1), one 16-byte vector per row.
@@ -167,7 +177,7 @@ lne_status launch_sparse_omega(lne_ctx *ctx, int64_t n, int32_t k, uint64_t seed
 // lives in LDS, each nonzero gathers one 16-byte row of Omega.
 lne_status spmm_sparse_omega(lne_ctx *ctx, const lne_csr *A, const int16_t *om, void *Y,
                              int64_t ldy, int32_t k, int32_t dtype);
-lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+lne_status launch_sample_slots(lne_ctx *ctx, const Graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t e_begin,
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
                                uint8_t *r);
@@ -178,11 +188,11 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
 // NULL, device, 3 x uint64): [0] = attempted sample slots, [1] = the largest
 // per-sample fixed-point weight of an edge with an accepted sample
 // (saturated at 2^32 - 1), [2] = accepted samples.
-lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+lne_status launch_sample_count(lne_ctx *ctx, const Graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                                int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,
                                unsigned long long *stats);
-lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+lne_status launch_sample_emit(lne_ctx *ctx, const Graph *g, const SamplePlan &pl,
                               const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                               int64_t row_hi, const uint64_t *wave_off, uint64_t *keys,
                               uint32_t *vals);
@@ -264,7 +274,7 @@ struct SymOut {
     explicit SymOut(lne_ctx *ctx) : keyT(ctx), valT(ctx) {}
 };
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
-                            int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
+                            int64_t n_items, int64_t n_rows, int colbits, const Graph *g,
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
                             int32_t val_type, lne_csr *out, uint64_t *kept,
                             bool tagged = false, SymOut *sym = nullptr);
@@ -277,14 +287,14 @@ lne_status sym_assemble(lne_ctx *ctx, lne_csr *U, SymOut &sym, int colbits, uint
                         lne_csr *out, uint64_t *kept);
 // deg[i] = degree of vertex i (uint32, n entries): the compact degree table
 // the fused reduction gathers from; with cw (weight_info) the weighted degree.
-lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg,
+lne_status vertex_degrees(lne_ctx *ctx, const Graph *g, uint32_t *deg,
                           const uint64_t *cw = nullptr);
 // Removes explicit zeros from an F32/F64 CSR (row block), in place of *m.
 lne_status drop_zeros(lne_ctx *ctx, lne_csr *m);
 
 // ---- trunc_log (k_trunclog.hip) ---------------------------------------------
 // counts covers the rows [row_lo, row_lo + counts->n_rows) of the graph.
-lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status trunc_log_csr(lne_ctx *ctx, const Graph *g, const lne_params *p,
                          const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out);
 // Stacks row blocks (block b holds rows [lo_b, lo_b + n_rows_b), in order)
 // into one CSR of n_rows rows; the blocks are released.
@@ -296,7 +306,7 @@ lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void
                 int64_t ldy, int32_t k, int32_t dtype);
 // out = a Z + b D^-1 A Z + c1 E1 + c2 E2 ; if acc: acc += cacc * out
 // (graph adjacency without values; E1/E2/acc may be null).
-lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out,
+lne_status graph_spmm(lne_ctx *ctx, const Graph *g, const void *Z, void *out,
                       int64_t ld, int32_t k, int32_t dtype, double a, double b,
                       const void *E1, double c1, const void *E2, double c2, void *acc,
                       double cacc);
@@ -334,7 +344,7 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
                     int32_t *shifted, int64_t n_rows, const int32_t *skip,
                     int32_t *skip_next, int32_t nb = 1);
 // Graph descriptors (k_stats.hip) behind lne_graph_stats; g validated.
-lne_status graph_stats_impl(lne_ctx *ctx, const lne_graph *g, uint64_t seed, int32_t wedges,
+lne_status graph_stats_impl(lne_ctx *ctx, const Graph *g, uint64_t seed, int32_t wedges,
                             int32_t iters, double *out);
 // Symmetric eigen-decomposition of C (k x k, FP64): V (k x k, columns = vectors),
 // lam (k), sorted by decreasing eigenvalue.  C is overwritten.  vw_ws: a
@@ -355,11 +365,11 @@ lne_status eig_weights(lne_ctx *ctx, const double *V, const double *lam, int32_t
 lne_status split_channels(lne_ctx *ctx, const lne_csr *ext, int T, lne_csr *st, Buf &chan);
 // vals[entry * ntr + t]: truncated log of trial t's mixed counts (0 if
 // dropped); s_dev[16 t + r - 1] = s_t[r] / pi_r.
-lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, const uint64_t *chan,
+lne_status trial_values(lne_ctx *ctx, const Graph *g, const lne_csr *st, const uint64_t *chan,
                         int T, const double *s_dev, int ntr, double scale, float *vals);
 // Channel CSR weights in place: counts W_r -> FP64 scale W_r / (d_a d_b)
 // (val_type becomes LNE_F64).
-lne_status norm_channels(lne_ctx *ctx, lne_csr *ext, const lne_graph *g, double scale);
+lne_status norm_channels(lne_ctx *ctx, lne_csr *ext, const Graph *g, double scale);
 // Y_t (rows ldy apart, trials ys apart) = M_t X_t (ldx, xs; xs = 0 shares one
 // operand) for ntr trials, M_t generated from the normalised channel CSR
 // `ext` with coef[16 t + r - 1] = s_t[r] / pi_r; k <= 256, k % 4 == 0, X's columns
@@ -371,7 +381,7 @@ constexpr int kSpmmChanVariants = 6;
 // Propagation step for ntr trials (blocks zs apart, rows ld apart, k columns):
 // out = a Z + b D^-1 A Z + c1 E1 + c2 E2, acc += e out, coef[5 t + {a, b, c1,
 // c2, e}]; E1, E2, acc may be NULL.  variant: launch shape 0..3.
-lne_status gspmm_batch(lne_ctx *ctx, const lne_graph *g, int ntr, int k, int64_t ld, int64_t zs,
+lne_status gspmm_batch(lne_ctx *ctx, const Graph *g, int ntr, int k, int64_t ld, int64_t zs,
                        const float *Z, float *out, const float *E1, const float *E2, float *acc,
                        const float *coef, int variant);
 constexpr int kGspmmBatchVariants = 4;
@@ -382,11 +392,20 @@ lne_status scale_blocks(lne_ctx *ctx, const float *x, float *y, int64_t count, i
 lne_status fill_u32(lne_ctx *ctx, void *p, int64_t count, uint32_t v);
 double bessel_i(int n, double x);
 // The channel sampling pass (lengths kept in the columns) into one CSR.
-lne_status channels_pass(lne_ctx *ctx, const lne_graph *g, const lne_params *p, lne_csr *out,
+lne_status channels_pass(lne_ctx *ctx, const Graph *g, const lne_params *p, lne_csr *out,
                          lne_stats *st);
 
 // ---- validation (abi.hip) -------------------------------------------------------
 lne_status validate_graph(lne_ctx *ctx, const lne_graph *g);
+// g's 64-bit view (the one every kernel reads): 64-bit offsets are used in
+// place; 32-bit ones are widened into `rp` (n + 1 int64 on the context's
+// stream).  g must have passed validate_graph.
+lne_status bind_graph(lne_ctx *ctx, const lne_graph *g, Buf &rp, Graph &out);
+struct GraphArg {
+    Buf rp;    // widened offsets, when the caller's are 32-bit
+    Graph g;
+    explicit GraphArg(lne_ctx *c) : rp(c) {}
+};
 lne_status validate_params(lne_ctx *ctx, const lne_params *p, int64_t n, int64_t n_arcs,
                            bool need_linalg);
 size_t dtype_size(int32_t t);

@@ -355,7 +355,7 @@ lne_status split_channels(lne_ctx *ctx, const lne_csr *ext, int T, lne_csr *st, 
     return LNE_OK;
 }
 
-lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, const uint64_t *chan,
+lne_status trial_values(lne_ctx *ctx, const Graph *g, const lne_csr *st, const uint64_t *chan,
                         int T, const double *s_dev, int ntr, double scale, float *vals) {
     if (st->n_rows > 0) {
         Launch L(ctx, "trial_values");
@@ -365,7 +365,7 @@ lne_status trial_values(lne_ctx *ctx, const lne_graph *g, const lne_csr *st, con
     return check_launch(ctx, "trial_values");
 }
 
-lne_status norm_channels(lne_ctx *ctx, lne_csr *ext, const lne_graph *g, double scale) {
+lne_status norm_channels(lne_ctx *ctx, lne_csr *ext, const Graph *g, double scale) {
     if (ext->val_type != LNE_U64) return fail(ctx, LNE_EINVAL, "norm_channels: counts expected");
     if (ext->n_rows > 0) {
         Launch L(ctx, "norm_channels");
@@ -408,7 +408,7 @@ lne_status spmm_chan(lne_ctx *ctx, const lne_csr *ext, int ntr, const double *co
     return check_launch(ctx, "spmm_chan");
 }
 
-lne_status gspmm_batch(lne_ctx *ctx, const lne_graph *g, int ntr, int k, int64_t ld, int64_t zs,
+lne_status gspmm_batch(lne_ctx *ctx, const Graph *g, int ntr, int k, int64_t ld, int64_t zs,
                        const float *Z, float *out, const float *E1, const float *E2, float *acc,
                        const float *coef, int variant) {
     if (k % 4 || k > 256 || ld % 4 || zs % 4 || (uintptr_t)Z % 16 || (uintptr_t)out % 16)

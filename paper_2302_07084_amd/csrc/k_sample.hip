@@ -563,7 +563,7 @@ int64_t sample_threads(const SamplePlan &pl, int64_t m) {
     return ceil_div(m * pl.chunks, kBlock) * kBlock;
 }
 
-lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g) {
+lne_status validate_graph_device(lne_ctx *ctx, const Graph *g) {
     Buf fl(ctx);
     LNE_TRY(alloc(ctx, fl, sizeof(uint32_t)));
     LNE_HIP(ctx, hipMemsetAsync(fl.p, 0, sizeof(uint32_t), ctx->stream));
@@ -584,7 +584,7 @@ lne_status validate_graph_device(lne_ctx *ctx, const lne_graph *g) {
     return LNE_OK;
 }
 
-lne_status build_edges(lne_ctx *ctx, const lne_graph *g, Buf &eu, Buf &ev, int64_t m,
+lne_status build_edges(lne_ctx *ctx, const Graph *g, Buf &eu, Buf &ev, int64_t m,
                        Buf *ea) {
     Buf nup(ctx), first(ctx), eoff(ctx);
     if (ea) LNE_TRY(alloc(ctx, *ea, sizeof(uint32_t) * (size_t)(m > 0 ? m : 1)));
@@ -646,7 +646,7 @@ __global__ void k_guide(const int64_t *__restrict__ rp, const uint64_t *__restri
     }
 }
 
-lne_status weight_guide(lne_ctx *ctx, const lne_graph *g, const uint64_t *cw, Buf &guide) {
+lne_status weight_guide(lne_ctx *ctx, const Graph *g, const uint64_t *cw, Buf &guide) {
     LNE_TRY(alloc(ctx, guide, sizeof(uint32_t) * (size_t)(g->n_arcs > 0 ? g->n_arcs : 1)));
     if (g->n > 0) {
         Launch L(ctx, "weight_guide");
@@ -656,7 +656,7 @@ lne_status weight_guide(lne_ctx *ctx, const lne_graph *g, const uint64_t *cw, Bu
     return check_launch(ctx, "weight_guide");
 }
 
-lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol) {
+lne_status weight_info(lne_ctx *ctx, const Graph *g, Buf &cw, uint64_t *vol) {
     LNE_TRY(alloc(ctx, cw, sizeof(uint64_t) * (size_t)(g->n_arcs + 1)));
     LNE_TRY(scan_u32(ctx, g->weight, cw.as<uint64_t>(), g->n_arcs));
     Buf fl(ctx);
@@ -681,7 +681,7 @@ lne_status weight_info(lne_ctx *ctx, const lne_graph *g, Buf &cw, uint64_t *vol)
     return LNE_OK;
 }
 
-lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+lne_status launch_sample_slots(lne_ctx *ctx, const Graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t e_begin,
                                int64_t e_end, int32_t *a, int32_t *b, uint64_t *w,
                                uint8_t *r) {
@@ -699,7 +699,7 @@ lne_status launch_sample_slots(lne_ctx *ctx, const lne_graph *g, const SamplePla
     return check_launch(ctx, "sample_slots");
 }
 
-lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+lne_status launch_sample_count(lne_ctx *ctx, const Graph *g, const SamplePlan &pl,
                                const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                                int64_t row_hi, uint32_t *wave_cnt, int64_t n_waves,
                                unsigned long long *stats) {
@@ -740,7 +740,7 @@ lne_status launch_sample_count(lne_ctx *ctx, const lne_graph *g, const SamplePla
     return check_launch(ctx, "fold_stats");
 }
 
-lne_status launch_sample_emit(lne_ctx *ctx, const lne_graph *g, const SamplePlan &pl,
+lne_status launch_sample_emit(lne_ctx *ctx, const Graph *g, const SamplePlan &pl,
                               const int32_t *eu, const int32_t *ev, int64_t m, int64_t row_lo,
                               int64_t row_hi, const uint64_t *wave_off, uint64_t *keys,
                               uint32_t *vals) {

@@ -675,7 +675,7 @@ lne_status reduce_to_csr(lne_ctx *ctx, const uint64_t *keys, const uint32_t *val
     return LNE_OK;
 }
 
-lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg, const uint64_t *cw) {
+lne_status vertex_degrees(lne_ctx *ctx, const Graph *g, uint32_t *deg, const uint64_t *cw) {
     if (g->n > 0) {
         Launch L(ctx, "degrees");
         k_degrees<<<grid_of(g->n, 256), 256, 0, ctx->stream>>>(g->row_ptr, cw, g->n, deg);
@@ -684,7 +684,7 @@ lne_status vertex_degrees(lne_ctx *ctx, const lne_graph *g, uint32_t *deg, const
 }
 
 lne_status reduce_to_matrix(lne_ctx *ctx, const uint64_t *keys, const uint32_t *vals,
-                            int64_t n_items, int64_t n_rows, int colbits, const lne_graph *g,
+                            int64_t n_items, int64_t n_rows, int colbits, const Graph *g,
                             const uint32_t *deg, int64_t row_lo, const TLConst &c,
                             int32_t val_type, lne_csr *out, uint64_t *kept, bool tagged,
                             SymOut *sym) {

@@ -396,7 +396,7 @@ lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *
 }
 
 template <int L, bool TL, class T>
-void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k_main,
+void gspmm_launch(lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld, int k_main,
                   int k, double a, double b, const T *E1, double c1, const T *E2, double c2,
                   T *acc, double cacc, int variant) {
     const unsigned grid = grid_of(g->n * 64, 256);
@@ -422,7 +422,7 @@ void gspmm_launch(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t 
 }
 
 template <bool TL, class T>
-void gspmm_launch_l(int L, lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld,
+void gspmm_launch_l(int L, lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld,
                     int k_main, int k, double a, double b, const T *E1, double c1, const T *E2,
                     double c2, T *acc, double cacc, int v) {
     switch (L) {
@@ -440,7 +440,7 @@ void gspmm_launch_l(int L, lne_ctx *ctx, const lne_graph *g, const T *Z, T *out,
 }
 
 template <class T>
-lne_status gspmm_t(lne_ctx *ctx, const lne_graph *g, const T *Z, T *out, int64_t ld, int k,
+lne_status gspmm_t(lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld, int k,
                    double a, double b, const T *E1, double c1, const T *E2, double c2,
                    T *acc, double cacc, int dtype) {
     const int N = Vec<T>::N;
@@ -491,7 +491,7 @@ lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void
     return s;
 }
 
-lne_status graph_spmm(lne_ctx *ctx, const lne_graph *g, const void *Z, void *out, int64_t ld,
+lne_status graph_spmm(lne_ctx *ctx, const Graph *g, const void *Z, void *out, int64_t ld,
                       int32_t k, int32_t dtype, double a, double b, const void *E1, double c1,
                       const void *E2, double c2, void *acc, double cacc) {
     lne_status s;

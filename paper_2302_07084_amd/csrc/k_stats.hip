@@ -184,7 +184,7 @@ __global__ void k_half_walk(const int64_t *__restrict__ rp, const int32_t *__res
 
 }  // namespace
 
-lne_status graph_stats_impl(lne_ctx *ctx, const lne_graph *g, uint64_t seed, int32_t wedges,
+lne_status graph_stats_impl(lne_ctx *ctx, const Graph *g, uint64_t seed, int32_t wedges,
                             int32_t iters, double *out) {
     const int64_t n = g->n, arcs = g->n_arcs;
     const int64_t *rp = g->row_ptr;

@@ -219,7 +219,7 @@ lne_status drop_zeros(lne_ctx *ctx, lne_csr *m) {
     return LNE_OK;
 }
 
-lne_status trunc_log_csr(lne_ctx *ctx, const lne_graph *g, const lne_params *p,
+lne_status trunc_log_csr(lne_ctx *ctx, const Graph *g, const lne_params *p,
                          const lne_csr *counts, int64_t row_lo, int32_t val_type, lne_csr *out) {
     const int64_t n = counts->n_rows;
     uint64_t vol = (uint64_t)g->n_arcs;

@@ -94,6 +94,23 @@ def test_graph_validation(lne, n, n_arcs):
     L.lne_ctx_destroy(h)
 
 
+@pytest.mark.parametrize("bits,n_arcs", [(16, 20), (-1, 20), (128, 20), (32, 1 << 31)])
+def test_graph_index_bits_validation(lne, bits, n_arcs):
+    # offsets are 64-bit (0 reads as 64) or 32-bit; 32-bit offsets cannot
+    # address 2^31 arcs.  Rejected on the host, before any GPU work.
+    L, h = _ctx(lne)
+    p = lne.make_params(gs.params(T=2, m=10))
+    g = _graph(10, n_arcs)
+    g.index_bits = bits
+    for entry in ("lne_sparsify", "lne_sparsify_log", "lne_embed"):
+        out = lne.CsrStruct() if entry != "lne_embed" else ctypes.c_void_p(0x3000)
+        arg = ctypes.byref(out) if entry != "lne_embed" else out
+        rc = getattr(L, entry)(h, ctypes.byref(g), ctypes.byref(p), arg, None)
+        assert rc == -1, entry
+        assert b"index_bits" in L.lne_last_error(h) or b"32-bit" in L.lne_last_error(h)
+    L.lne_ctx_destroy(h)
+
+
 def test_linalg_param_validation(lne):
     L, h = _ctx(lne)
     base = gs.params(T=2, m=10, d=4, oversample=2, q=1)
