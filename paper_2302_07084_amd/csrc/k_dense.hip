@@ -395,7 +395,9 @@ k_proj64(const YT *__restrict__ Y, int64_t ldy, int64_t n, int kin,
 
 // BF16 projection: each lane reads its A operand (8 consecutive k of one
 // row) straight from memory with one 16-byte load; the 32-k slice of W^T is
-// staged in LDS per step.
+// staged in LDS, double-buffered: the next step's operand and W slice are
+// requested into registers before the current step's matrix-core steps and
+// the slice is stored to the other buffer after them, one barrier per step.
 template <class OT, int MAXJ>
 __global__ void __launch_bounds__(kProjThreads)
 k_proj_bf16(const __bf16 *__restrict__ Y, int64_t ldy, int64_t n, int kin,
@@ -406,40 +408,65 @@ k_proj_bf16(const __bf16 *__restrict__ Y, int64_t ldy, int64_t n, int kin,
     out += (int64_t)blockIdx.y * os;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ __attribute__((aligned(16))) __bf16 Ws[16 * MAXJ * kTS];
+    __shared__ __attribute__((aligned(16))) __bf16 Ws[2][16 * MAXJ * kTS];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int ntout = (kout + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * kProjRows;
     const int kr = lane >> 4, kc = lane & 15;
     const int64_t arow = r0 + 16 * w + kc;
-    v4f acc[MAXJ];
+    // a thread's share of one W slice: 16 MAXJ columns x 4 chunks of 8 k
+    constexpr int NW = (16 * MAXJ * 4 + kProjThreads - 1) / kProjThreads;
+    auto wload = [&](int k0, v8bf v[NW]) {
 #pragma unroll
-    for (int J = 0; J < MAXJ; ++J) acc[J] = (v4f){0, 0, 0, 0};
-    for (int k0 = 0; k0 < kin; k0 += 32) {
-        const v8bf a = load8(Y, ldy, arow, n, k0 + 8 * kr, kin, vec != 0);
-        for (int idx = tid; idx < 16 * MAXJ * 4; idx += kProjThreads) {
-            const int c = idx >> 2, c8 = (idx & 3) * 8;
-            const int kcol = k0 + c8;
-            v8bf v;
+        for (int u = 0; u < NW; ++u) {
+            const int idx = tid + u * kProjThreads;
+            const int c = idx >> 2, kcol = k0 + (idx & 3) * 8;
+            if (idx >= 16 * MAXJ * 4) continue;
             if (c < kout && kcol + 8 <= kin) {
-                v = *reinterpret_cast<const v8bf *>(Wt + (int64_t)c * ldw + kcol);
+                v[u] = *reinterpret_cast<const v8bf *>(Wt + (int64_t)c * ldw + kcol);
             } else {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    v[i] = (c < kout && kcol + i < kin) ? Wt[(int64_t)c * ldw + kcol + i]
-                                                        : (__bf16)0.0f;
+                    v[u][i] = (c < kout && kcol + i < kin) ? Wt[(int64_t)c * ldw + kcol + i]
+                                                           : (__bf16)0.0f;
             }
-            *reinterpret_cast<v8bf *>(Ws + c * kTS + c8) = v;
         }
-        __syncthreads();
+    };
+    auto wstore = [&](int buf, const v8bf v[NW]) {
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int idx = tid + u * kProjThreads;
+            if (idx < 16 * MAXJ * 4)
+                *reinterpret_cast<v8bf *>(Ws[buf] + (idx >> 2) * kTS + (idx & 3) * 8) = v[u];
+        }
+    };
+    v4f acc[MAXJ];
+#pragma unroll
+    for (int J = 0; J < MAXJ; ++J) acc[J] = (v4f){0, 0, 0, 0};
+    v8bf wv[NW];
+    wload(0, wv);
+    wstore(0, wv);
+    v8bf a = load8(Y, ldy, arow, n, 8 * kr, kin, vec != 0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < kin; k0 += 32, cur ^= 1) {
+        const bool more = k0 + 32 < kin;
+        v8bf an = a;
+        if (more) {
+            an = load8(Y, ldy, arow, n, k0 + 32 + 8 * kr, kin, vec != 0);
+            wload(k0 + 32, wv);
+        }
 #pragma unroll
         for (int J = 0; J < MAXJ; ++J) {
             if (J < ntout) {
-                const v8bf b = *reinterpret_cast<const v8bf *>(Ws + (16 * J + kc) * kTS + 8 * kr);
+                const v8bf b =
+                    *reinterpret_cast<const v8bf *>(Ws[cur] + (16 * J + kc) * kTS + 8 * kr);
                 acc[J] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[J], 0, 0, 0);
             }
         }
+        if (more) wstore(cur ^ 1, wv);
         __syncthreads();
+        a = an;
     }
 #pragma unroll
     for (int J = 0; J < MAXJ; ++J) {
