@@ -555,14 +555,42 @@ __global__ void k_sym_merge(const int64_t *__restrict__ rpU, const int32_t *__re
     const bool diag = u1 > u0 && colU[u0] == (int32_t)a;
     const int64_t l0 = rpL[a], l1 = rpL[a + 1] - (diag ? 1 : 0);
     const int64_t o = (int64_t)rpF[a];
-    for (int64_t j = l0 + lane; j < l1; j += 64) {
-        colF[o + (j - l0)] = (int32_t)(keyL[j] & colmask);
-        valF[o + (j - l0)] = (VT)__uint_as_float(valL[j]);
+    // four entries per lane and step, their loads issued before any store
+    constexpr int Q = 4;
+    for (int64_t j0 = l0; j0 < l1; j0 += 64 * Q) {
+        uint64_t kq[Q];
+        uint32_t vq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t j = j0 + q * 64 + lane;
+            if (j < l1) { kq[q] = keyL[j]; vq[q] = valL[j]; }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t j = j0 + q * 64 + lane;
+            if (j < l1) {
+                colF[o + (j - l0)] = (int32_t)(kq[q] & colmask);
+                valF[o + (j - l0)] = (VT)__uint_as_float(vq[q]);
+            }
+        }
     }
     const int64_t o2 = o + (l1 - l0);
-    for (int64_t j = u0 + lane; j < u1; j += 64) {
-        colF[o2 + (j - u0)] = colU[j];
-        valF[o2 + (j - u0)] = valU[j];
+    for (int64_t j0 = u0; j0 < u1; j0 += 64 * Q) {
+        int32_t cq[Q];
+        VT wq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t j = j0 + q * 64 + lane;
+            if (j < u1) { cq[q] = colU[j]; wq[q] = valU[j]; }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t j = j0 + q * 64 + lane;
+            if (j < u1) {
+                colF[o2 + (j - u0)] = cq[q];
+                valF[o2 + (j - u0)] = wq[q];
+            }
+        }
     }
 }
 
