@@ -395,19 +395,30 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         my_kept += k ? 1u : 0u;
     };
     // kPF groups of 64 items in flight: group it lives in ring slot it % kPF
-    // until group it + kPF replaces it
+    // until group it + kPF replaces it.  The slots are loaded unconditionally
+    // (indices past the chunk clamped to its last item) and masked where a
+    // group is used: a conditional load would be merged into its slot by a
+    // register copy that waits for it, and the loads would not overlap.
+    // the key before the chunk and the first key after it, loaded first and
+    // kept in scalar registers (waiting for them leaves the ring in flight)
+    const uint64_t before0 = keys[max(base - 1, (int64_t)0)];
+    const uint64_t after0 = keys[min(cend, n - 1)];
     uint64_t kq[kPF];
     uint32_t vq[kPF];
 #pragma unroll
     for (int g = 0; g < kPF; ++g) {
-        const int64_t i = base + g * 64 + lane;
-        kq[g] = i < cend ? keys[i] : ~0ull;
-        vq[g] = i < cend ? vals[i] : 0u;
+        const int64_t i = min(base + g * 64 + lane, cend - 1);
+        kq[g] = keys[i];
+        vq[g] = vals[i];
     }
+    auto uniform64 = [](uint64_t x) {
+        return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x) |
+               ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32);
+    };
     // the key before each group's lane 0 (the last key of the group before),
     // and the first key of the next chunk
-    uint64_t prev_last = base > 0 ? keys[base - 1] : ~0ull;
-    const uint64_t next_first = cend < n ? keys[cend] : ~0ull;
+    uint64_t prev_last = base > 0 ? uniform64(before0) : ~0ull;
+    const uint64_t next_first = cend < n ? uniform64(after0) : ~0ull;
     // the chunk's first run continues the previous chunk's last run: that
     // wave sums it, this one skips it (until its first head)
     bool skipping = base > 0 && __shfl(kq[0], 0, 64) == prev_last;
@@ -421,17 +432,18 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
             const int64_t i = base + it * 64 + lane;
             if (base + it * 64 >= cend) break;                 // wave-uniform
             const bool valid = i < cend;
-            const uint64_t key = kq[g];
+            const uint64_t key = valid ? kq[g] : ~0ull;
             uint64_t v = valid ? vq[g] : 0;
             const bool more = it + 1 < kRChunk / 64 && base + (it + 1) * 64 < cend;
             // the key after lane 63's item, taken before its slot is reused
             const uint64_t after =
                 more ? __shfl(kq[(g + 1) % kPF], 0, 64) : next_first;
-            // the loads of group it + kPF go out before this reduction
-            if (it + kPF < kRChunk / 64) {
-                const int64_t j = i + 64 * kPF;
-                kq[g] = j < cend ? keys[j] : ~0ull;
-                vq[g] = j < cend ? vals[j] : 0u;
+            // the loads of group it + kPF go out before this reduction (past
+            // the chunk they re-read its last item: no branch around them)
+            {
+                const int64_t j = min(i + 64 * kPF, cend - 1);
+                kq[g] = keys[j];
+                vq[g] = vals[j];
             }
             uint64_t prev = __shfl_up(key, 1, 64);
             if (lane == 0) prev = prev_last;
