@@ -34,6 +34,7 @@ namespace lne {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kWalkQ = 2;   // slots whose walks one lane advances together (emit pass)
 
 struct Coin {
     bool all;        // p_e >= 1 (or downsampling off): every slot accepted
@@ -416,28 +417,116 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
         }
         pos += (uint64_t)__popcll(m0) + 2ull * (uint64_t)__popcll(m1);
     };
-    for (int64_t jj = 0; jj < pl.J; ++jj) {
-        const uint64_t j = j0 + (uint64_t)jj;
-        bool ina = false, inb = false;
-        int32_t a = u, b = v;
-        uint64_t ch = 0;
-        if (e < m && j < ne) {
-            const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
-            if (cn.all || (uint64_t)b0.x < cn.tau) {
-                if (draw_r(pl, b0.y) == 1) {
-                    ++c1;
-                } else {
-                    double h;
-                    const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b, &h);
-                    // the count pass bounded this below 2^32
-                    if (W) w = (uint32_t)sample_weight(h, cn.all, cn.p);
-                    ina = a >= row_lo && a < row_hi;
-                    inb = b >= row_lo && b < row_hi;
-                    ch = pl.cbits ? (uint64_t)(r - 1) : 0;
+    if constexpr (!W) {
+        // kWalkQ slots at a time: their walks advance together, so each lane
+        // has kWalkQ chains of dependent loads (row offsets, then the column)
+        // in flight instead of one; the entries still go out in slot order.
+        // A slot without a step to take loads from u (cached) and keeps its
+        // vertex, so the loads carry no branch.
+        for (int64_t jj = 0; jj < pl.J; jj += kWalkQ) {
+            int32_t x[kWalkQ], y[kWalkQ];
+            int r[kWalkQ], split[kWalkQ], steps[kWalkQ], left[kWalkQ];
+            uint4 buf[kWalkQ];
+            uint32_t blk[kWalkQ];
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) {
+                x[q] = u; y[q] = v; r[q] = 1; split[q] = 0; steps[q] = 0; left[q] = 1;
+                buf[q] = make_uint4(0, 0, 0, 0); blk[q] = 0;
+            }
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) {
+                const uint64_t j = j0 + (uint64_t)(jj + q);
+                if (e < m && jj + q < pl.J && j < ne) {
+                    const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
+                    if (cn.all || (uint64_t)b0.x < cn.tau) {
+                        r[q] = draw_r(pl, b0.y);
+                        if (r[q] == 1) {
+                            ++c1;
+                        } else {
+                            split[q] = (int)(b0.z % (uint32_t)r[q]);
+                            steps[q] = r[q] - 1;
+                            buf[q] = make_uint4(b0.w, 0, 0, 0);
+                        }
+                    }
                 }
             }
+            int nsteps = 0;
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) nsteps = max(nsteps, steps[q]);
+            for (int i = 0; i < nsteps; ++i) {
+                int32_t cur[kWalkQ];
+                uint32_t z[kWalkQ];
+                bool act[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    act[q] = i < steps[q];
+                    if (act[q] && left[q] == 0) {
+                        buf[q] = slot_block(pl, e, (uint32_t)(j0 + (uint64_t)(jj + q)), ++blk[q]);
+                        left[q] = 4;
+                    }
+                    z[q] = buf[q].x;
+                    if (act[q]) {
+                        buf[q] = make_uint4(buf[q].y, buf[q].z, buf[q].w, 0);
+                        --left[q];
+                    }
+                    cur[q] = act[q] ? (i < split[q] ? x[q] : y[q]) : u;
+                }
+                int64_t beg[kWalkQ], end[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) { beg[q] = rp[cur[q]]; end[q] = rp[cur[q] + 1]; }
+                int32_t nb[kWalkQ];
+                uint32_t deg[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    deg[q] = (uint32_t)(end[q] - beg[q]);
+                    const int64_t at = beg[q] + (int64_t)(deg[q] ? z[q] % deg[q] : 0u);
+                    nb[q] = col[min(at, 2 * m - 1)];
+                }
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    // a sink (asymmetric input) holds
+                    const int32_t nx = deg[q] ? nb[q] : cur[q];
+                    if (act[q]) {
+                        if (i < split[q]) x[q] = nx;
+                        else y[q] = nx;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) {
+                if (jj + q >= pl.J) break;                              // uniform
+                const bool walked = steps[q] > 0;
+                const bool ina = walked && x[q] >= row_lo && x[q] < row_hi;
+                const bool inb = walked && y[q] >= row_lo && y[q] < row_hi;
+                const uint64_t ch = pl.cbits && walked ? (uint64_t)(r[q] - 1) : 0;
+                put(ina, inb, walked ? x[q] : u, walked ? y[q] : v, ch, w);
+            }
         }
-        put(ina, inb, a, b, ch, w);
+    } else {
+        for (int64_t jj = 0; jj < pl.J; ++jj) {
+            const uint64_t j = j0 + (uint64_t)jj;
+            bool ina = false, inb = false;
+            int32_t a = u, b = v;
+            uint64_t ch = 0;
+            if (e < m && j < ne) {
+                const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
+                if (cn.all || (uint64_t)b0.x < cn.tau) {
+                    if (draw_r(pl, b0.y) == 1) {
+                        ++c1;
+                    } else {
+                        double h;
+                        const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b,
+                                                   &h);
+                        // the count pass bounded this below 2^32
+                        w = (uint32_t)sample_weight(h, cn.all, cn.p);
+                        ina = a >= row_lo && a < row_hi;
+                        inb = b >= row_lo && b < row_hi;
+                        ch = pl.cbits ? (uint64_t)(r - 1) : 0;
+                    }
+                }
+            }
+            put(ina, inb, a, b, ch, w);
+        }
     }
     // the merged length-1 samples: ceil(c1 / g) entries of up to g samples
     uint64_t g = 1, w1 = 0;
