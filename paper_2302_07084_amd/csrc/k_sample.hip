@@ -96,8 +96,10 @@ __device__ __forceinline__ uint4 slot_block(const SamplePlan &pl, int64_t e, uin
 __device__ __forceinline__ int draw_r(const SamplePlan &pl, uint32_t z) {
     int r = 1;
 #pragma unroll
-    for (int t = 0; t < 15; ++t)
-        r += (t < pl.T - 1 && (uint64_t)z >= pl.theta[t]) ? 1 : 0;
+    for (int t = 0; t < 15; ++t) {
+        if (t >= pl.T - 1) break;                   // uniform: T - 1 thresholds
+        r += (uint64_t)z >= pl.theta[t] ? 1 : 0;
+    }
     return r;
 }
 
