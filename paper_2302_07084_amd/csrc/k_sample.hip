@@ -612,9 +612,11 @@ __global__ void k_gaussian(int64_t n, int32_t k, int64_t ld, uint64_t seed, T *_
     const double u2 = ((double)z.y + 0.5) * 2.3283064365386963e-10;
     const double rad = sqrt(-2.0 * log(u1));
     const double ang = 2.0 * 3.141592653589793 * u2;
+    double sn, cs;
+    sincos(ang, &sn, &cs);   // one argument reduction for both
     const int64_t c = 2 * (int64_t)h;
-    out[i * ld + c] = from_double<T>(rad * cos(ang));
-    if (c + 1 < k) out[i * ld + c + 1] = from_double<T>(rad * sin(ang));
+    out[i * ld + c] = from_double<T>(rad * cs);
+    if (c + 1 < k) out[i * ld + c + 1] = from_double<T>(rad * sn);
 }
 
 // Sparse-sign test matrix: row i holds kSparseOmega entries; word t of
