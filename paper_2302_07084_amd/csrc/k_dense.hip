@@ -493,10 +493,13 @@ __global__ void k_w_to_bf16t(const double *__restrict__ W, int kin, int kout,
 // ---------------------------------------------------------------- Cholesky
 constexpr int kSolveThreads = 1024;
 
-// Right-looking upper Cholesky of A (k x k, in place).  Returns false on a
-// pivot that is not positive relative to the original diagonal.
+// Right-looking upper Cholesky of A (k x k, in place; LDS or global).
+// Returns false on a pivot that is not positive relative to the original
+// diagonal.  The trailing update takes rows by wave and columns by lane.
 __device__ bool chol_upper(double *A, int k, const double *diag0) {
     __shared__ int bad;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NW = kSolveThreads / 64;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     for (int j = 0; j < k; ++j) {
@@ -512,20 +515,29 @@ __device__ bool chol_upper(double *A, int k, const double *diag0) {
         for (int c = j + 1 + threadIdx.x; c < k; c += kSolveThreads) A[(int64_t)j * k + c] /= r;
         if (threadIdx.x == 0) A[(int64_t)j * k + j] = r;
         __syncthreads();
-        const int m = k - j - 1;
-        for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += kSolveThreads) {
-            const int i = j + 1 + (int)(idx / m), c = j + 1 + (int)(idx % m);
-            if (c >= i) A[(int64_t)i * k + c] -= A[(int64_t)j * k + i] * A[(int64_t)j * k + c];
+        for (int i = j + 1 + wv; i < k; i += NW) {
+            const double aji = A[(int64_t)j * k + i];
+            for (int c = i + lane; c < k; c += 64)
+                A[(int64_t)i * k + c] -= aji * A[(int64_t)j * k + c];
         }
         __syncthreads();
     }
     return bad == 0;
 }
 
+// Cholesky of the Gram G = R^T R (a shifted retry if a pivot fails) and W =
+// R^-1.  IN_LDS: the k x k matrix is factored in LDS (k <= kCholMaxLds), then
+// W is formed there row by row while R is read from G.  The inverse takes
+// the rows from the bottom up, all columns of a row at once; each entry is
+// the sum over j ascending of R[i][j] W[j][c], as a column-by-column
+// back-substitution forms it.
+constexpr int kCholMaxLds = 140;
+template <bool IN_LDS>
 __global__ void __launch_bounds__(kSolveThreads)
 k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__restrict__ diag0,
            int32_t *__restrict__ status, int32_t *__restrict__ shifted, int64_t n_rows,
            const int32_t *__restrict__ skip, int32_t *__restrict__ run_next) {
+    extern __shared__ double lds_m[];
     {
         const int64_t b = blockIdx.x;
         G += b * k * k;
@@ -542,10 +554,14 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
     }
     const int64_t kk = (int64_t)k * k;
     __shared__ double trace;
-    for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads) W[i] = G[i];
+    double *A = IN_LDS ? lds_m : G;
+    for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads) {
+        W[i] = G[i];
+        if (IN_LDS) A[i] = G[i];
+    }
     for (int i = threadIdx.x; i < k; i += kSolveThreads) diag0[i] = G[(int64_t)i * k + i];
     __syncthreads();
-    bool ok = chol_upper(G, k, diag0);
+    bool ok = chol_upper(A, k, diag0);
     bool sh = false;
     if (!ok) {
         // shifted retry: G + sigma I, sigma = 11 (n k + k (k + 1)) u trace(G)
@@ -558,11 +574,11 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
         const double sigma = 11.0 * ((double)n_rows * k + (double)k * (k + 1)) *
                              1.1102230246251565e-16 * trace;
         for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads)
-            G[i] = W[i] + ((i / k == i % k) ? sigma : 0.0);
+            A[i] = W[i] + ((i / k == i % k) ? sigma : 0.0);
         __syncthreads();
         for (int i = threadIdx.x; i < k; i += kSolveThreads) diag0[i] = 0.0;
         __syncthreads();
-        ok = chol_upper(G, k, diag0);
+        ok = chol_upper(A, k, diag0);
         sh = true;
     }
     if (threadIdx.x == 0) {
@@ -570,19 +586,47 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
         if (sh) atomicAdd(shifted, 1);
         if (run_next) *run_next = sh ? 1 : 0;
     }
-    // lower triangle of R is zero; W = R^-1 (upper), one thread per column
+    // R (upper; its lower triangle zero) to G
     for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads)
-        if (i / k > i % k) G[i] = 0.0;
+        G[i] = (i / k > i % k) ? 0.0 : A[i];
     __syncthreads();
-    for (int c = threadIdx.x; c < k; c += kSolveThreads) {
-        for (int i = c + 1; i < k; ++i) W[(int64_t)i * k + c] = 0.0;
-        W[(int64_t)c * k + c] = ok ? 1.0 / G[(int64_t)c * k + c] : 0.0;
-        for (int i = c - 1; i >= 0; --i) {
-            double s = 0.0;
-            for (int j = i + 1; j <= c; ++j) s += G[(int64_t)i * k + j] * W[(int64_t)j * k + c];
-            W[(int64_t)i * k + c] = ok ? -s / G[(int64_t)i * k + i] : 0.0;
+    // W = R^-1 (upper), in LDS for the LDS variant (A is free now); row i of
+    // R is staged in LDS for its step
+    __shared__ double rrow[288];   // the widest k accepted
+    double *Wm = IN_LDS ? lds_m : W;
+    for (int i = k - 1; i >= 0; --i) {
+        for (int j = i + threadIdx.x; j < k; j += kSolveThreads) rrow[j] = G[(int64_t)i * k + j];
+        __syncthreads();
+        const double rii = rrow[i];
+        for (int c = threadIdx.x; c < k; c += kSolveThreads) {
+            double x;
+            if (c < i) {
+                x = 0.0;
+            } else if (c == i) {
+                x = ok ? 1.0 / rii : 0.0;
+            } else {
+                // the products' operands four at a time (loads ahead of the
+                // still sequential sum)
+                double s = 0.0;
+                int j = i + 1;
+                for (; j + 3 <= c; j += 4) {
+                    const double r0 = rrow[j], r1 = rrow[j + 1], r2 = rrow[j + 2], r3 = rrow[j + 3];
+                    const double w0 = Wm[(int64_t)j * k + c], w1 = Wm[(int64_t)(j + 1) * k + c];
+                    const double w2 = Wm[(int64_t)(j + 2) * k + c], w3 = Wm[(int64_t)(j + 3) * k + c];
+                    s += r0 * w0;
+                    s += r1 * w1;
+                    s += r2 * w2;
+                    s += r3 * w3;
+                }
+                for (; j <= c; ++j) s += rrow[j] * Wm[(int64_t)j * k + c];
+                x = ok ? -s / rii : 0.0;
+            }
+            Wm[(int64_t)i * k + c] = x;
         }
+        __syncthreads();
     }
+    if constexpr (IN_LDS)
+        for (int64_t i = threadIdx.x; i < kk; i += kSolveThreads) W[i] = Wm[i];
 }
 
 // ---------------------------------------------------------------- eigen-solver
@@ -1438,10 +1482,34 @@ lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *stat
                     int32_t nb) {
     Buf diag(ctx);
     LNE_TRY(alloc(ctx, diag, sizeof(double) * (size_t)nb * k));
+    // the LDS variant when k^2 doubles fit beside the kernel's static arrays
+    static int lds_limit = -1;
+    if (lds_limit < 0) {
+        int dev = 0, bytes = 0, base = 0;
+        lds_limit = 0;
+        hipFuncAttributes fa;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&base, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            hipDeviceGetAttribute(&bytes, hipDeviceAttributeSharedMemPerBlockOptin, dev) ==
+                hipSuccess &&
+            hipFuncGetAttributes(&fa, (const void *)k_chol_inv<true>) == hipSuccess &&
+            (bytes = bytes > base ? bytes : base) > (int)fa.sharedSizeBytes &&
+            hipFuncSetAttribute((const void *)k_chol_inv<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes - (int)fa.sharedSizeBytes) == hipSuccess)
+            lds_limit = bytes - (int)fa.sharedSizeBytes;
+        (void)hipGetLastError();
+    }
+    const size_t need = sizeof(double) * (size_t)k * k;
     {
         Launch L(ctx, "chol_inv");
-        k_chol_inv<<<nb, kSolveThreads, 0, ctx->stream>>>(G, k, W, diag.as<double>(), status,
-                                                         shifted, n_rows, skip, skip_next);
+        if (k <= kCholMaxLds && need <= (size_t)lds_limit)
+            k_chol_inv<true><<<nb, kSolveThreads, need, ctx->stream>>>(
+                G, k, W, diag.as<double>(), status, shifted, n_rows, skip, skip_next);
+        else
+            k_chol_inv<false><<<nb, kSolveThreads, 0, ctx->stream>>>(
+                G, k, W, diag.as<double>(), status, shifted, n_rows, skip, skip_next);
     }
     return check_launch(ctx, "chol_inv");
 }
