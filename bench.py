@@ -16,6 +16,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -830,6 +831,30 @@ def precision_report(name):
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6, "bf16": 2500.0}   # FP32 data runs on FP64 MFMA
 
 
+def mfma_ceiling():
+    """Runs tests/probe/mfma_ceiling (built by __graft_entry__.build()): the
+    rate of register-only back-to-back MFMAs at 1 to 8 waves per SIMD, the
+    most a kernel made of the same instruction can reach on this chip.
+    Returns its JSON with the best rate per instruction, or None if the probe
+    is not built."""
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "probe",
+                       "mfma_ceiling")
+    if not os.path.exists(exe):
+        log("mfma ceiling probe not built; reporting against the published peaks only")
+        return None
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        raise RuntimeError(f"mfma_ceiling failed ({r.returncode}): {r.stderr.strip()}")
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    best = {}
+    for x in res["results"]:
+        best[x["mfma"]] = max(best.get(x["mfma"], 0.0), x["tflops"])
+    res["max_tflops"] = best
+    log("mfma ceiling (register-only, best over waves per SIMD): " +
+        ", ".join(f"{k} {v:.1f} TFLOP/s" for k, v in best.items()))
+    return res
+
+
 def mfma_report():
     """Achieved matrix-core rate of the dense steps of the fast randomized SVD
     (Gram Y^T Y and projection Y W on MFMA) at the shapes of the large
@@ -837,12 +862,15 @@ def mfma_report():
     workload (n = 1e6, k' = 266, FP32 and BF16), from HIP-event times of the
     kernels inside eigSVD (one Gram, one k' x k' eigen-solve, one projection
     U = Y V S^-1)."""
+    ceiling = mfma_ceiling()     # a child process, before this one touches the GPU
     import torch
 
     import paper_2302_07084_amd as lne
 
     ctx = lne.Context()
     out = {"report": "mfma", "peak_tflops": MFMA_PEAK_TFLOPS, "cases": []}
+    if ceiling:
+        out["ceiling"] = ceiling
     for dt, n, k in (("f32", 10_000_000, 138), ("f32", 1_000_000, 266), ("bf16", 1_000_000, 266),
                      ("f64", 1_000_000, 266)):
         tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dt]
@@ -870,6 +898,11 @@ def mfma_report():
                 "gram_avg_ms": gms / gcnt, "project_avg_ms": pms / pcnt}
         case["gram_frac_peak"] = case["gram_tflops"] / peak
         case["project_frac_peak"] = case["project_tflops"] / peak
+        top = (ceiling or {}).get("max_tflops", {}).get(
+            "bf16_16x16x32" if dt == "bf16" else "f64_16x16x4")
+        if top:
+            case["gram_frac_ceiling"] = case["gram_tflops"] / top
+            case["project_frac_ceiling"] = case["project_tflops"] / top
         out["cases"].append(case)
         log(f"mfma {dt} n={n} k={k}: gram {case['gram_tflops']:.1f} TFLOP/s, "
             f"project {case['project_tflops']:.1f} TFLOP/s (peak {peak})")
