@@ -492,6 +492,7 @@ __global__ void k_w_to_bf16t(const double *__restrict__ W, int kin, int kout,
 
 // ---------------------------------------------------------------- Cholesky
 constexpr int kSolveThreads = 1024;
+constexpr int kEigMaxK = 288;   // widest k of the Cholesky and eigen-solver kernels
 
 // Right-looking upper Cholesky of A (k x k, in place; LDS or global).
 // Returns false on a pivot that is not positive relative to the original
@@ -592,7 +593,7 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
     __syncthreads();
     // W = R^-1 (upper), in LDS for the LDS variant (A is free now); row i of
     // R is staged in LDS for its step
-    __shared__ double rrow[288];   // the widest k accepted
+    __shared__ double rrow[kEigMaxK];   // the widest k accepted
     double *Wm = IN_LDS ? lds_m : W;
     for (int i = k - 1; i >= 0; --i) {
         for (int j = i + threadIdx.x; j < k; j += kSolveThreads) rrow[j] = G[(int64_t)i * k + j];
@@ -659,7 +660,6 @@ k_chol_inv(double *__restrict__ G, int k, double *__restrict__ W, double *__rest
 // workspace Zt holds 2 k^2 doubles (the merge writes its rows to the second
 // half) and V serves as the merge's scratch before it receives the result.
 constexpr int kEigMaxLds = 144;   // largest k of the LDS variant
-constexpr int kEigMaxK = 288;
 constexpr int kEigSplit = 32;   // tear the tridiagonal matrix from this size on
 
 // A double moved between lanes by a DPP pattern (both halves).
@@ -1480,6 +1480,7 @@ lne_status project(lne_ctx *ctx, const void *Y, int32_t y_t, int64_t ldy, int64_
 lne_status chol_inv(lne_ctx *ctx, double *G, int32_t k, double *W, int32_t *status,
                     int32_t *shifted, int64_t n_rows, const int32_t *skip, int32_t *skip_next,
                     int32_t nb) {
+    if (k < 1 || k > kEigMaxK) return fail(ctx, LNE_EUNSUPPORTED, "chol_inv: k = %d", k);
     Buf diag(ctx);
     LNE_TRY(alloc(ctx, diag, sizeof(double) * (size_t)nb * k));
     // the LDS variant when k^2 doubles fit beside the kernel's static arrays

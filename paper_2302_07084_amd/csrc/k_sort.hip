@@ -312,9 +312,18 @@ __global__ void __launch_bounds__(kT) k_reduce(const uint64_t *__restrict__ keys
 // waits one memory latency per item, and a few pairs of hubs have runs of
 // thousands); the next chunk's wave skips that run.  Row offsets as in
 // k_reduce.  Each distinct pair is written by exactly one lane with an
-// integer sum, so the result does not depend on the launch shape.
+// integer sum, so the result does not depend on the launch shape.  The
+// cross-lane steps are DPP moves and lane reads (no LDS round trips), the
+// keys at uniform places scalar loads, and the row degrees come from an LDS
+// window filled once per chunk: a vector load whose value is needed at once
+// would make the wave wait for every load issued before it, the prefetched
+// groups included.
 constexpr int kRChunk = 1024;
 constexpr int kPF = 4;   // groups of 64 items a reducing wave has in flight
+// Rows whose degrees a reducing wave keeps in LDS: those from its chunk's
+// first row on (a chunk spans more only across empty rows; the rest are read
+// from memory).
+constexpr int kDegWin = 1024;
 
 __global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__ keys, int64_t n,
                                                     int64_t nchunks,
@@ -348,6 +357,50 @@ __global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__
     if (lane == 0) chunk_heads[w] = c;
 }
 
+// Cross-lane moves without the LDS crossbar (gfx9 DPP): a lane with no
+// source lane under the control keeps `old`.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint32_t dpp32(uint32_t old, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t old, uint64_t src) {
+    return (uint64_t)dpp32<CTRL>((uint32_t)old, (uint32_t)src) |
+           ((uint64_t)dpp32<CTRL>((uint32_t)(old >> 32), (uint32_t)(src >> 32)) << 32);
+}
+constexpr int kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;   // whole-wave shift by one lane
+constexpr int kDppRowShr = 0x110;                           // + n: shift by n in a row of 16
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l) << 32);
+}
+
+// One step of a segmented inclusive sum: add the partial sum of the source
+// lane when it belongs to the same segment (seg ids rise along the lanes, so
+// equal ids mean every lane between is in the segment too).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(uint64_t &v, uint32_t seg) {
+    const uint32_t s2 = dpp32<CTRL, ROWS>(~0u, seg);
+    const uint64_t v2 = (uint64_t)dpp32<CTRL, ROWS>(0u, (uint32_t)v) |
+                        ((uint64_t)dpp32<CTRL, ROWS>(0u, (uint32_t)(v >> 32)) << 32);
+    if (s2 == seg) v += v2;
+}
+
+// Segmented inclusive sum over the wave: shifts by 1, 2, 4, 8 inside each row
+// of 16 lanes, then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31
+// into rows 2 and 3.
+__device__ __forceinline__ uint64_t seg_scan64(uint64_t v, uint32_t seg) {
+    seg_step<kDppRowShr + 1, 0xf>(v, seg);
+    seg_step<kDppRowShr + 2, 0xf>(v, seg);
+    seg_step<kDppRowShr + 4, 0xf>(v, seg);
+    seg_step<kDppRowShr + 8, 0xf>(v, seg);
+    seg_step<kDppRowBcast15, 0xa>(v, seg);
+    seg_step<kDppRowBcast31, 0xc>(v, seg);
+    return v;
+}
+
 template <class VT>
 __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ keys,
                                                   const uint32_t *__restrict__ vals, int64_t n,
@@ -360,8 +413,13 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
                                                   uint32_t *__restrict__ chunk_kept,
                                                   bool tagged, uint64_t *__restrict__ keyT,
                                                   uint32_t *__restrict__ valT) {
+    __shared__ uint32_t dwin[kT / 64][kDegWin];   // per wave: deg of rows rfirst, rfirst + 1, ...
+    __shared__ uint32_t dmiss[kT / 64][2][64];      // per lane: a row's, a column's degree
     const int lane = threadIdx.x & 63;
-    const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    // the wave's chunk as scalars: the keys at uniform places are then scalar
+    // loads, waited for apart from the vector loads in flight
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * (kT / 64) + wv;
     if (w >= nchunks) return;
     const int64_t base = w * kRChunk;
     const int64_t cend = min(n, base + kRChunk);          // end of this chunk
@@ -370,6 +428,7 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint64_t running = head_off[w];   // heads before the current 64 items
     uint32_t my_kept = 0;
+    int64_t rfirst = 0;               // first row of the chunk (of the degree window)
     // Eq. (1) for the run of `key` with weight sum W and unique index u.
     // With keyT (the upper triangle: one entry per sample, (min, max)), a
     // diagonal pair counts twice (its sample lands in both orientations of
@@ -379,9 +438,15 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         const int32_t b = (int32_t)(key & colmask);
         const int64_t row = (int64_t)((key & keymask) >> colbits);
         if (keyT && (int64_t)b == row_lo + row) W *= 2;
-        const uint64_t da = deg[row_lo + row];
+        // degrees from LDS: a row past the window, or a column whose tag
+        // is saturated, is read from memory into the lane's LDS slot first,
+        // inside the branch, so that the usual path waits for no vector load
+        const int64_t rr = row - rfirst;
         const uint32_t tag = tagged ? (uint32_t)(key >> kTagShift) : kTagMax;
-        const uint64_t db = tag < kTagMax ? tag : deg[b];
+        if (rr >= kDegWin) dmiss[wv][0][lane] = deg[row_lo + row];
+        if (tag >= kTagMax) dmiss[wv][1][lane] = deg[b];
+        const uint64_t da = rr < kDegWin ? dwin[wv][rr] : dmiss[wv][0][lane];
+        const uint64_t db = tag < kTagMax ? tag : dmiss[wv][1][lane];
         const bool k = tl_keep(c, W, da, db);
         const VT x = k ? (VT)log((double)W * c.scale / ((double)da * (double)db)) : (VT)0;
         col[u] = b;
@@ -401,8 +466,6 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
     // register copy that waits for it, and the loads would not overlap.
     // the key before the chunk and the first key after it, loaded first and
     // kept in scalar registers (waiting for them leaves the ring in flight)
-    const uint64_t before0 = keys[max(base - 1, (int64_t)0)];
-    const uint64_t after0 = keys[min(cend, n - 1)];
     uint64_t kq[kPF];
     uint32_t vq[kPF];
 #pragma unroll
@@ -411,17 +474,28 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
         kq[g] = keys[i];
         vq[g] = vals[i];
     }
-    auto uniform64 = [](uint64_t x) {
-        return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x) |
-               ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32);
-    };
+    // scalar loads: the key before the chunk, its first and last keys and the
+    // first key after it
+    const uint64_t before0 = keys[max(base - 1, (int64_t)0)];
+    const uint64_t first0 = keys[base];
+    const uint64_t last0 = keys[cend - 1];
+    const uint64_t after0 = keys[min(cend, n - 1)];
+    // the degrees of the chunk's rows into the wave's LDS window (a run
+    // going on past the chunk keeps the last key's row); the vector loads
+    // in flight are the ones the first groups need first anyway
+    rfirst = (int64_t)((first0 & keymask) >> colbits);
+    {
+        const int64_t span = (int64_t)((last0 & keymask) >> colbits) - rfirst + 1;
+        const int nwin = (int)min(span, (int64_t)kDegWin);
+        for (int j = lane; j < nwin; j += 64) dwin[wv][j] = deg[row_lo + rfirst + j];
+    }
     // the key before each group's lane 0 (the last key of the group before),
     // and the first key of the next chunk
-    uint64_t prev_last = base > 0 ? uniform64(before0) : ~0ull;
-    const uint64_t next_first = cend < n ? uniform64(after0) : ~0ull;
+    uint64_t prev_last = base > 0 ? before0 : ~0ull;
+    const uint64_t next_first = cend < n ? after0 : ~0ull;
     // the chunk's first run continues the previous chunk's last run: that
     // wave sums it, this one skips it (until its first head)
-    bool skipping = base > 0 && __shfl(kq[0], 0, 64) == prev_last;
+    bool skipping = base > 0 && first0 == prev_last;
     uint64_t carry = 0;               // the open run's sum in earlier groups
     uint64_t last_key = 0;
     bool open_end = false;            // the last group's last run goes on
@@ -435,9 +509,8 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
             const uint64_t key = valid ? kq[g] : ~0ull;
             uint64_t v = valid ? vq[g] : 0;
             const bool more = it + 1 < kRChunk / 64 && base + (it + 1) * 64 < cend;
-            // the key after lane 63's item, taken before its slot is reused
-            const uint64_t after =
-                more ? __shfl(kq[(g + 1) % kPF], 0, 64) : next_first;
+            // the key after lane 63's item (a scalar load)
+            const uint64_t after = more ? keys[base + (it + 1) * 64] : next_first;
             // the loads of group it + kPF go out before this reduction (past
             // the chunk they re-read its last item: no branch around them)
             {
@@ -445,31 +518,26 @@ __global__ void __launch_bounds__(kT) k_reduce_tl(const uint64_t *__restrict__ k
                 kq[g] = keys[j];
                 vq[g] = vals[j];
             }
-            uint64_t prev = __shfl_up(key, 1, 64);
-            if (lane == 0) prev = prev_last;
-            prev_last = __shfl(key, 63, 64);
+            const uint64_t prev = dpp64<kDppWaveShr1>(prev_last, key);   // lane 0: prev_last
+            prev_last = readlane64(key, 63);
             const bool head = valid && (i == 0 || key != prev);
             const uint64_t hm = __ballot(head);
-            const uint64_t u = running + (uint64_t)__popcll(hm & (lt | (1ull << lane))) - 1;
+            // the lane's run within the group: heads up to and including it
+            const uint32_t seg = (uint32_t)__popcll(hm & (lt | (1ull << lane)));
+            const uint64_t u = running + (uint64_t)seg - 1;
             running += (uint64_t)__popcll(hm);
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint64_t ov = __shfl_up(v, off, 64);
-                const uint64_t ou = __shfl_up(u, off, 64);
-                if (lane >= off && ou == u) v += ov;
-            }
+            v = seg_scan64(v, seg);
             // lanes before the group's first head continue the open run
-            const bool first_seg = (hm & (lt | (1ull << lane))) == 0;
+            const bool first_seg = seg == 0;
             if (first_seg) v += carry;
-            uint64_t nxt = __shfl_down(key, 1, 64);
-            if (lane == 63) nxt = after;
+            const uint64_t nxt = dpp64<kDppWaveShl1>(after, key);         // lane 63: after
             const bool ends = valid && (i + 1 >= n || nxt != key);
             // the sum so far of a run still open after lane 63's item
             const int last = (int)min((int64_t)63, cend - 1 - (base + it * 64));
-            const uint64_t vl = __shfl(v, last, 64);
-            const bool open = __shfl((int)(valid && !ends), last, 64) != 0;
+            const uint64_t vl = readlane64(v, last);
+            const bool open = __builtin_amdgcn_readlane((int)(valid && !ends), last) != 0;
             carry = open ? vl : 0;
-            last_key = __shfl(key, last, 64);
+            last_key = readlane64(key, last);
             open_end = open;
             const bool skip = skipping && first_seg;
             if (hm) skipping = false;
