@@ -325,38 +325,6 @@ constexpr int kPF = 4;   // groups of 64 items a reducing wave has in flight
 // from memory).
 constexpr int kDegWin = 1024;
 
-__global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__ keys, int64_t n,
-                                                    int64_t nchunks,
-                                                    uint32_t *__restrict__ chunk_heads) {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
-    if (w >= nchunks) return;
-    const int64_t base = w * kRChunk;
-    uint32_t c = 0;
-    // kPF groups of 64 keys loaded at a time; the key before a group's lane 0
-    // is the previous group's lane 63 key
-    uint64_t prev_last = base > 0 ? keys[base - 1] : ~0ull;
-    for (int it0 = 0; it0 < kRChunk / 64; it0 += kPF) {
-        uint64_t kq[kPF];
-#pragma unroll
-        for (int g = 0; g < kPF; ++g) {
-            const int64_t i = base + (it0 + g) * 64 + lane;
-            kq[g] = i < n ? keys[i] : ~0ull;
-        }
-#pragma unroll
-        for (int g = 0; g < kPF; ++g) {
-            const int64_t i = base + (it0 + g) * 64 + lane;
-            uint64_t prev = __shfl_up(kq[g], 1, 64);
-            if (lane == 0) prev = prev_last;
-            prev_last = __shfl(kq[g], 63, 64);
-            if (i < n && (i == 0 || kq[g] != prev)) ++c;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if (lane == 0) chunk_heads[w] = c;
-}
-
 // Cross-lane moves without the LDS crossbar (gfx9 DPP): a lane with no
 // source lane under the control keeps `old`.
 template <int CTRL, int ROWS = 0xf>
@@ -399,6 +367,37 @@ __device__ __forceinline__ uint64_t seg_scan64(uint64_t v, uint32_t seg) {
     seg_step<kDppRowBcast15, 0xa>(v, seg);
     seg_step<kDppRowBcast31, 0xc>(v, seg);
     return v;
+}
+
+__global__ void __launch_bounds__(kT) k_chunk_heads(const uint64_t *__restrict__ keys, int64_t n,
+                                                    int64_t nchunks,
+                                                    uint32_t *__restrict__ chunk_heads) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    if (w >= nchunks) return;
+    const int64_t base = w * kRChunk;
+    uint32_t c = 0;
+    // kPF groups of 64 keys loaded at a time; the key before a group's lane 0
+    // is the previous group's lane 63 key
+    uint64_t prev_last = base > 0 ? keys[base - 1] : ~0ull;
+    for (int it0 = 0; it0 < kRChunk / 64; it0 += kPF) {
+        uint64_t kq[kPF];
+#pragma unroll
+        for (int g = 0; g < kPF; ++g) {
+            const int64_t i = base + (it0 + g) * 64 + lane;
+            kq[g] = i < n ? keys[i] : ~0ull;
+        }
+#pragma unroll
+        for (int g = 0; g < kPF; ++g) {
+            const int64_t i = base + (it0 + g) * 64 + lane;
+            const uint64_t prev = dpp64<kDppWaveShr1>(prev_last, kq[g]);   // lane 0: prev_last
+            prev_last = readlane64(kq[g], 63);
+            if (i < n && (i == 0 || kq[g] != prev)) ++c;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) chunk_heads[w] = c;
 }
 
 template <class VT>
