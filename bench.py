@@ -93,6 +93,8 @@ KERNEL_CLASSES = {
     "radix_hist": (r"\bk_hist\b", "k_sort.hip"),
     "reduce_trunc_log": (r"\bk_reduce_tl\b", "k_sort.hip"),
     "sym_merge": (r"\bk_sym_merge\b", "k_sort.hip"),
+    "sample_count": (r"\bk_sample_count<", "k_sample.hip"),
+    "sample_emit": (r"\bk_sample_emit<", "k_sample.hip"),
 }
 
 
