@@ -10,6 +10,8 @@
 // l / 16] and B[k-block l / 16][l % 16].  Accumulator value i of lane l is
 // column l % 16 of the output tile, row 4 (l / 16) + i for the FP32/BF16
 // forms but row l / 16 + 4 i for the FP64 form (checked by a lane probe).
+#include <mutex>
+
 #include "common.hpp"
 
 namespace lne {
@@ -144,8 +146,10 @@ auto mfma_tile = [&](int cur) {
 // ---------------------------------------------------------------- Gram BF16
 constexpr int kTS = 40;   // LDS row stride (bf16) of the transposed tile: 80 B
 
-constexpr int kBR = 64;            // rows per BF16 Gram tile (two MFMA k-steps)
-constexpr int kTS2 = kBR + 8;      // LDS row stride (bf16) of the transposed tile: 144 B
+constexpr int kBR = 128;           // rows per BF16 Gram tile (four MFMA k-steps)
+constexpr int kTS2 = kBR + 8;      // LDS row stride (bf16) of the transposed tile: 272 B
+constexpr int kGBThreads = 1024;   // BF16 Gram block: sixteen waves
+constexpr int kGBWaves = kGBThreads / 64;
 
 // Loads 8 consecutive bf16 of row `row` from column c (zero beyond k or r_end).
 __device__ __forceinline__ v8bf load8(const __bf16 *__restrict__ Y, int64_t ld, int64_t row,
@@ -161,13 +165,16 @@ __device__ __forceinline__ v8bf load8(const __bf16 *__restrict__ Y, int64_t ld, 
     return v;
 }
 
-// BF16 Gram: 64-row tiles read with 16-byte loads (consecutive lanes take
+// BF16 Gram: 128-row tiles read with 16-byte loads (consecutive lanes take
 // consecutive rows of one 8-column chunk, so the transposed LDS writes do not
-// conflict), two 16 x 16 x 32 MFMA steps per tile and output tile.  The
-// per-block sums are FP32 (the accumulators' own type).  vec: rows are
-// 16-byte aligned (ld % 8 == 0, aligned base).
+// conflict), four 16 x 16 x 32 MFMA steps per tile and output tile.  Sixteen
+// waves share a block, so each holds few output tiles and one block per CU
+// has a whole 128-row tile (68 KB at k' = 266) of loads in flight; the
+// transposed tile lives in dynamic LDS (KP x kTS2 bf16).  The per-block sums
+// are FP32 (the accumulators' own type).  vec: rows are 16-byte aligned
+// (ld % 8 == 0, aligned base).
 template <int MAXT>
-__global__ void __launch_bounds__(kGramThreads)
+__global__ void __launch_bounds__(kGBThreads)
 k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
             int64_t rows_per_wg, float *__restrict__ part, const int32_t *__restrict__ skip,
             int64_t ys, int vec) {
@@ -175,15 +182,16 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
     part += (int64_t)blockIdx.y * gridDim.x * KP * KP;
     if (skip) skip += kFlagStride * blockIdx.y;
     if (skip && *skip == 0) return;
-    __shared__ __attribute__((aligned(16))) __bf16 tt[288 * kTS2];   // KP x kTS2, transposed
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    extern __shared__ __attribute__((aligned(16))) __bf16 tt[];   // KP x kTS2, transposed
+    // the wave index as a scalar, so that the tile indices below are too
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nt = KP / 16, ntu = nt * (nt + 1) / 2;
     int TI[MAXT], TJ[MAXT];
     v4f acc[MAXT];
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
         acc[s] = (v4f){0, 0, 0, 0};
-        const int t = w + 8 * s;
+        const int t = w + kGBWaves * s;
         if (t < ntu) upper_tile(t, nt, TI[s], TJ[s]); else { TI[s] = TJ[s] = -1; }
     }
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
@@ -192,12 +200,12 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
     const int nch = KP / 8;
     // the next tile's 16-byte chunks are requested into registers before the
     // matrix-core steps of the current one and written to LDS after them
-    constexpr int NP = (288 / 8 * kBR + kGramThreads - 1) / kGramThreads;
+    constexpr int NP = (288 / 8 * kBR + kGBThreads - 1) / kGBThreads;
     v8bf pv[NP];
     auto fetch = [&](int64_t r0) {
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
-            const int idx = tid + u * kGramThreads;
+            const int idx = tid + u * kGBThreads;
             if (idx < nch * kBR) pv[u] = load8(Y, ld, r0 + idx % kBR, r_end, (idx / kBR) * 8, k, vec != 0);
         }
     };
@@ -205,7 +213,7 @@ k_gram_bf16(const __bf16 *__restrict__ Y, int64_t n, int k, int64_t ld, int KP,
     for (int64_t r0 = r_begin; r0 < r_end; r0 += kBR) {
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
-            const int idx = tid + u * kGramThreads;
+            const int idx = tid + u * kGBThreads;
             if (idx < nch * kBR) {
                 const int rr = idx % kBR, c = (idx / kBR) * 8;
 #pragma unroll
@@ -1334,6 +1342,24 @@ __global__ void k_eig_weights(const double *__restrict__ V, const double *__rest
 }  // namespace
 
 // ---------------------------------------------------------------- host side
+// Lets `fn` use `bytes` of dynamic LDS (above the default 64 KB), once per
+// kernel; fails when the device offers less.
+static lne_status lds_opt_in(lne_ctx *ctx, const void *fn, size_t bytes) {
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find(fn);
+    if (it != done.end() && it->second >= bytes) return LNE_OK;
+    if (bytes > 64 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, LNE_EUNSUPPORTED, "%zu bytes of LDS per block are not available", bytes);
+    }
+    done[fn] = bytes;
+    return LNE_OK;
+}
+
 size_t project_bf16_ws_bytes(int32_t kin, int32_t kout, int32_t nb) {
     return sizeof(__bf16) * (size_t)nb * kout * (((kin + 31) / 32) * 32);
 }
@@ -1347,11 +1373,14 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     const int per_wave = (ntu + 7) / 8;
     if (per_wave > 22) return fail(ctx, LNE_EUNSUPPORTED, "gram: k = %d above 288", k);
     if (nb < 1 || nb > 65535) return fail(ctx, LNE_EINVAL, "gram: batch of %d", nb);
-    const int64_t blocks_rows = ceil_div(n > 0 ? n : 1, kGramRows);
-    // about 768 (512 for wide k) workgroups over the whole batch, one round
-    // of three (two) blocks per CU, or as many per-workgroup partial sums as
-    // a caller's workspace holds
-    int64_t target = std::max<int64_t>(1, (KP > 160 ? 512 : 768) / nb);
+    // BF16: row ranges in whole 128-row tiles, one sixteen-wave block per CU
+    const bool bf = dtype == LNE_BF16;
+    const int rows_unit = bf ? kBR : kGramRows;
+    const int64_t blocks_rows = ceil_div(n > 0 ? n : 1, rows_unit);
+    // about 768 (512 for wide k, 256 for BF16) workgroups over the whole
+    // batch, one round of three (two, one) blocks per CU, or as many
+    // per-workgroup partial sums as a caller's workspace holds
+    int64_t target = std::max<int64_t>(1, (bf ? 256 : KP > 160 ? 512 : 768) / nb);
     // per-workgroup sums: FP32 for BF16 data (its accumulators), else FP64
     const size_t part_es = dtype == LNE_BF16 ? sizeof(float) : sizeof(double);
     const size_t part_one = part_es * (size_t)nb * KP * KP;
@@ -1362,7 +1391,7 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
         target = std::min<int64_t>(target, (int64_t)(part_ws_bytes / part_one));
     }
     const int nwg = (int)std::min<int64_t>(blocks_rows, target);
-    const int64_t rows_per_wg = ceil_div(blocks_rows, nwg) * kGramRows;
+    const int64_t rows_per_wg = ceil_div(blocks_rows, nwg) * rows_unit;
     Buf part(ctx);
     if (part_ws) part.p = part_ws, part.ctx = nullptr;   // borrowed: never released
     else LNE_TRY(alloc(ctx, part, part_one * nwg));
@@ -1370,14 +1399,19 @@ lne_status gram(lne_ctx *ctx, const void *Y, int32_t dtype, int64_t n, int32_t k
     const int vec = ((uintptr_t)Y % 16 == 0 && ld % 8 == 0 && ys % 8 == 0) ? 1 : 0;
     {
         Launch L(ctx, "gram");
-        if (dtype == LNE_BF16) {
+        if (bf) {
+            const int bpw = (ntu + kGBWaves - 1) / kGBWaves;
+            const size_t lds = sizeof(__bf16) * (size_t)KP * kTS2;
 #define LNE_GB(MT)                                                                         \
-    k_gram_bf16<MT><<<grid, kGramThreads, 0, ctx->stream>>>(                           \
-        (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<float>(), skip, ys, vec)
-            if (per_wave <= 1) LNE_GB(1);
-            else if (per_wave <= 6) LNE_GB(6);
-            else if (per_wave <= 12) LNE_GB(12);
-            else LNE_GB(22);
+    do {                                                                                   \
+        LNE_TRY(lds_opt_in(ctx, (const void *)k_gram_bf16<MT>, lds));                      \
+        k_gram_bf16<MT><<<grid, kGBThreads, lds, ctx->stream>>>(                           \
+            (const __bf16 *)Y, n, k, ld, KP, rows_per_wg, part.as<float>(), skip, ys, vec); \
+    } while (0)
+            if (bpw <= 1) LNE_GB(1);
+            else if (bpw <= 6) LNE_GB(6);
+            else if (bpw <= 10) LNE_GB(10);
+            else LNE_GB(12);
 #undef LNE_GB
         } else {
 #define LNE_G64(T, MT, SP)                                                               \
