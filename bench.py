@@ -69,11 +69,12 @@ def graph_spmm_streams(K):
     propagation, launch by launch.  Every term runs Z = B T (T in, Z out: 2
     streams) and then the term's update with the accumulator (Z, the two
     earlier terms and the accumulator in, the new term and the accumulator
-    out: 6; the first term has one earlier term: 5); the final D^-1 A
-    product adds 2.  Returns (launches, streams)."""
+    out: 6; the first term has one earlier term and starts the accumulator
+    without reading it: 4); the final D^-1 A product adds 2.  Returns
+    (launches, streams)."""
     if K <= 0:
         return 0, 0
-    return 2 * K + 1, 2 + 5 + 8 * (K - 1) + 2
+    return 2 * K + 1, 2 + 4 + 8 * (K - 1) + 2
 
 
 # Counter summary of the dominant kernels (profiles/): FETCH_SIZE and

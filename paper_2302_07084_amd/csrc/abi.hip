@@ -835,37 +835,32 @@ static lne_status propagate_impl(lne_ctx *ctx, const Graph *g, const lne_params 
     Buf b0(ctx), b1(ctx), b2(ctx), bz(ctx), bc(ctx);
     for (Buf *b : {&b0, &b1, &b2, &bz, &bc}) LNE_TRY(alloc(ctx, *b, es * (size_t)n * ld));
     // X0 already in the padded layout (ld == d, 16-byte aligned) serves as T0
-    // itself (read only; the first rotation hands its slot to b0), and as the
-    // X0 of the last step, instead of being copied twice
+    // itself (read only; the first rotation hands its slot to b0) instead of
+    // being copied
     const bool direct = ld == d && (uintptr_t)X0 % 16 == 0;
     void *x0 = const_cast<void *>(X0);
     void *T0 = direct ? x0 : b0.p, *T1 = b1.p, *T2 = b2.p, *Z = bz.p, *conv = bc.p;
     if (!direct) LNE_TRY(dense_scale(ctx, X0, dt, d, T0, dt, ld, n, d, 1.0));
-    LNE_TRY(dense_scale(ctx, T0, dt, ld, conv, dt, ld, n, d, c[0]));
+    // conv holds X0 - sum_i c_i T_i, the operand of the final product: it
+    // starts as (1 - c_0) T0 (T0 = X0) in the pass that makes T1, and every
+    // term is subtracted in the pass that makes it
     // T1 = (B^2 / 2 - I) T0 with B = L - mu I = (1 - mu) I - D^-1 A
     LNE_TRY(graph_spmm(ctx, g, T0, Z, ld, d, dt, 1.0 - mu, -1.0, nullptr, 0, nullptr, 0,
                        nullptr, 0));
     LNE_TRY(graph_spmm(ctx, g, Z, T1, ld, d, dt, 0.5 * (1.0 - mu), -0.5, T0, -1.0, nullptr, 0,
-                       conv, c[1]));
+                       conv, -c[1], true, 1.0 - c[0]));
     for (int i = 2; i <= K; ++i) {
         // T_i = B^2 T_{i-1} - 2 T_{i-1} - T_{i-2}
         LNE_TRY(graph_spmm(ctx, g, T1, Z, ld, d, dt, 1.0 - mu, -1.0, nullptr, 0, nullptr, 0,
                            nullptr, 0));
         LNE_TRY(graph_spmm(ctx, g, Z, T2, ld, d, dt, 1.0 - mu, -1.0, T1, -2.0, T0, -1.0, conv,
-                           c[i]));
+                           -c[i]));
         void *t = T0;
         T0 = T1;
         T1 = T2;
         T2 = t == x0 ? b0.p : t;   // X0 is never written
     }
-    // X_sp = D^-1 A (X0 - conv)
-    if (direct) {
-        LNE_TRY(axpby(ctx, X0, conv, conv, n, d, ld, dt, 1.0, -1.0));
-    } else {
-        void *tmp = T2;   // holds neither of the last two terms
-        LNE_TRY(dense_scale(ctx, X0, dt, d, tmp, dt, ld, n, d, 1.0));
-        LNE_TRY(axpby(ctx, tmp, conv, conv, n, d, ld, dt, 1.0, -1.0));
-    }
+    // X_sp = D^-1 A (X0 - sum_i c_i T_i)
     LNE_TRY(graph_spmm(ctx, g, conv, Z, ld, d, dt, 0.0, 1.0, nullptr, 0, nullptr, 0, nullptr, 0));
     if (p->flags & LNE_FLAG_NO_FINAL_EIGSVD)
         return dense_scale(ctx, Z, dt, ld, X, dt, d, n, d, 1.0);

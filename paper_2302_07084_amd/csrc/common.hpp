@@ -304,12 +304,13 @@ lne_status concat_rows(lne_ctx *ctx, std::vector<lne_csr> &blocks, int64_t n_row
 // ---- SpMM (k_spmm.hip) -------------------------------------------------------
 lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void *Y,
                 int64_t ldy, int32_t k, int32_t dtype);
-// out = a Z + b D^-1 A Z + c1 E1 + c2 E2 ; if acc: acc += cacc * out
+// out = a Z + b D^-1 A Z + c1 E1 + c2 E2 ; if acc: acc += cacc * out, or
+// with acc_init acc = cinit * E1 + cacc * out (acc not read; E1 needed)
 // (graph adjacency without values; E1/E2/acc may be null).
 lne_status graph_spmm(lne_ctx *ctx, const Graph *g, const void *Z, void *out,
                       int64_t ld, int32_t k, int32_t dtype, double a, double b,
                       const void *E1, double c1, const void *E2, double c2, void *acc,
-                      double cacc);
+                      double cacc, bool acc_init = false, double cinit = 0.0);
 // out = a x + b y over n rows of k columns (rows ld apart), dt F64 or F32.
 lne_status axpby(lne_ctx *ctx, const void *x, const void *y, void *out, int64_t n, int32_t k,
                  int64_t ld, int32_t dt, double a, double b);

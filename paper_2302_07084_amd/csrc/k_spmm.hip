@@ -159,13 +159,15 @@ k_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
 }
 
 // out = a z + b (inv acc) + c1 e1 + c2 e2 at columns [c0, c0 + N) of a row;
-// accum += cacc out when accum is given.
+// accum += cacc out when accum is given, or with ainit accum = cinit e1 +
+// cacc out (accum not read: the first term of a sum started in the same pass).
 template <class T, int N>
 __device__ __forceinline__ void graph_epilogue(int64_t o, int c0, int k, const T acc[N], T inv,
                                                const T *__restrict__ Z, T *__restrict__ out, T a,
                                                T b, const T *__restrict__ E1, T c1,
                                                const T *__restrict__ E2, T c2,
-                                               T *__restrict__ accum, T cacc) {
+                                               T *__restrict__ accum, T cacc, int ainit,
+                                               T cinit) {
     T z[N], e1[N], e2[N];
     load_vec<T, T, N>(Z + o, z);
     if (E1) load_vec<T, T, N>(E1 + o, e1);
@@ -180,7 +182,12 @@ __device__ __forceinline__ void graph_epilogue(int64_t o, int c0, int k, const T
     store_row<T, T, N>(out + o, c0, k, r);
     if (accum) {
         T s[N];
-        load_vec<T, T, N>(accum + o, s);
+        if (ainit) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) s[i] = cinit * e1[i];
+        } else {
+            load_vec<T, T, N>(accum + o, s);
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) s[i] += cacc * r[i];
         store_row<T, T, N>(accum + o, c0, k, s);
@@ -195,7 +202,7 @@ k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
              const uint32_t *__restrict__ wt, int64_t n_rows,
              const T *__restrict__ Z, int64_t ld, int k_main, int k, T *__restrict__ out, T a,
              T b, const T *__restrict__ E1, T c1, const T *__restrict__ E2, T c2,
-             T *__restrict__ accum, T cacc) {
+             T *__restrict__ accum, T cacc, int ainit, T cinit) {
     constexpr int N = Vec<T>::N;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= n_rows) return;
@@ -233,13 +240,13 @@ k_graph_spmm(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
             fold_groups<L, T, N>(acc);
             if (grp == 0)
                 graph_epilogue<T, N>(row * ld + c0, c0, k, acc, inv, Z, out, a, b, E1, c1, E2, c2,
-                                     accum, cacc);
+                                     accum, cacc, ainit, cinit);
         }
         if (tail) {
             fold_groups<TLn, T, N>(acct);
             if (grpt == 0 && ct < k)
                 graph_epilogue<T, N>(row * ld + ct, ct, k, acct, inv, Z, out, a, b, E1, c1, E2,
-                                     c2, accum, cacc);
+                                     c2, accum, cacc, ainit, cinit);
         }
         if (cb + L * N >= k_main) break;
     }
@@ -398,13 +405,13 @@ lne_status spmm_t(lne_ctx *ctx, const lne_csr *A, const XT *X, int64_t ldx, OT *
 template <int L, bool TL, class T>
 void gspmm_launch(lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld, int k_main,
                   int k, double a, double b, const T *E1, double c1, const T *E2, double c2,
-                  T *acc, double cacc, int variant) {
+                  T *acc, double cacc, int ainit, double cinit, int variant) {
     const unsigned grid = grid_of(g->n * 64, 256);
     Launch Lc(ctx, "graph_spmm");
 #define LNE_GS(UU, NTT, WW)                                                                \
     k_graph_spmm<L, TL, UU, NTT, WW, T><<<grid, 256, 0, ctx->stream>>>(                   \
         g->row_ptr, g->col, g->weight, g->n, Z, ld, k_main, k, out, (T)a, (T)b, E1, (T)c1,  \
-        E2, (T)c2, acc, (T)cacc)
+        E2, (T)c2, acc, (T)cacc, ainit, (T)cinit)
 #define LNE_GV(WW)                                                                         \
     switch (variant) {                                                                     \
         case 1: LNE_GS(8, false, WW); break;                                               \
@@ -424,17 +431,17 @@ void gspmm_launch(lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld, 
 template <bool TL, class T>
 void gspmm_launch_l(int L, lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld,
                     int k_main, int k, double a, double b, const T *E1, double c1, const T *E2,
-                    double c2, T *acc, double cacc, int v) {
+                    double c2, T *acc, double cacc, int ainit, double cinit, int v) {
     switch (L) {
 #define LNE_GL(LL)                                                                            \
     case LL:                                                                                  \
         gspmm_launch<LL, TL, T>(ctx, g, Z, out, ld, k_main, k, a, b, E1, c1, E2, c2, acc, cacc, \
-                                v);                                                           \
+                                ainit, cinit, v);                                             \
         break;
         LNE_GL(1) LNE_GL(2) LNE_GL(4) LNE_GL(8) LNE_GL(16) LNE_GL(32)
         default:
             gspmm_launch<64, TL, T>(ctx, g, Z, out, ld, k_main, k, a, b, E1, c1, E2, c2, acc,
-                                    cacc, v);
+                                    cacc, ainit, cinit, v);
 #undef LNE_GL
     }
 }
@@ -442,7 +449,7 @@ void gspmm_launch_l(int L, lne_ctx *ctx, const Graph *g, const T *Z, T *out, int
 template <class T>
 lne_status gspmm_t(lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld, int k,
                    double a, double b, const T *E1, double c1, const T *E2, double c2,
-                   T *acc, double cacc, int dtype) {
+                   T *acc, double cacc, int ainit, double cinit, int dtype) {
     const int N = Vec<T>::N;
     for (const T *q : {Z, (const T *)out, E1, E2, (const T *)acc})
         if ((uintptr_t)q % 16)
@@ -453,10 +460,12 @@ lne_status gspmm_t(lne_ctx *ctx, const Graph *g, const T *Z, T *out, int64_t ld,
         for_each_launch(k, N, [&](int c0, int L, bool tl, int k_main, int kk) {
             if (tl)
                 gspmm_launch_l<true, T>(L, ctx, g, Z + c0, out + c0, ld, k_main, kk, a, b,
-                                        at(E1, c0), c1, at(E2, c0), c2, at(acc, c0), cacc, v);
+                                        at(E1, c0), c1, at(E2, c0), c2, at(acc, c0), cacc, ainit,
+                                        cinit, v);
             else
                 gspmm_launch_l<false, T>(L, ctx, g, Z + c0, out + c0, ld, k_main, kk, a, b,
-                                         at(E1, c0), c1, at(E2, c0), c2, at(acc, c0), cacc, v);
+                                         at(E1, c0), c1, at(E2, c0), c2, at(acc, c0), cacc, ainit,
+                                         cinit, v);
         });
         return check_launch(ctx, "graph_spmm");
     };
@@ -493,16 +502,19 @@ lne_status spmm(lne_ctx *ctx, const lne_csr *A, const void *X, int64_t ldx, void
 
 lne_status graph_spmm(lne_ctx *ctx, const Graph *g, const void *Z, void *out, int64_t ld,
                       int32_t k, int32_t dtype, double a, double b, const void *E1, double c1,
-                      const void *E2, double c2, void *acc, double cacc) {
+                      const void *E2, double c2, void *acc, double cacc, bool acc_init,
+                      double cinit) {
+    if (acc_init && (!acc || !E1))
+        return fail(ctx, LNE_EINVAL, "graph_spmm: starting acc from E1 needs both");
     lne_status s;
     if (dtype == LNE_F64)
         s = gspmm_t<double>(ctx, g, (const double *)Z, (double *)out, ld, k, a, b,
                             (const double *)E1, c1, (const double *)E2, c2, (double *)acc, cacc,
-                            dtype);
+                            acc_init ? 1 : 0, cinit, dtype);
     else if (dtype == LNE_F32)
         s = gspmm_t<float>(ctx, g, (const float *)Z, (float *)out, ld, k, a, b,
                            (const float *)E1, c1, (const float *)E2, c2, (float *)acc, cacc,
-                           dtype);
+                           acc_init ? 1 : 0, cinit, dtype);
     else
         return fail(ctx, LNE_EINVAL, "graph_spmm: bad dtype");
     return s;
