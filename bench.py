@@ -265,7 +265,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--report", choices=["precision", "automl", "mfma", "linkpred", "weighted",
-                                         "ablation", "host"],
+                                         "ablation", "host", "hbm"],
                     default=None,
                     help="precision: the FP32 and BF16-MFMA paths against the FP64 path; "
                          "automl: trials/s and time to an equal score of the plain "
@@ -277,7 +277,9 @@ def main():
                          "ablation: stage times and micro-F1 of the vanilla and fast randomized "
                          "SVD (q = 1, 2, 5) over sample sizes; host: the embedding step with "
                          "the sparsifier in pinned host memory (streamed over PCIe) beside "
-                         "the in-HBM step")
+                         "the in-HBM step; hbm: the rates of plain device copies, fills and "
+                         "sums of 4 GiB (the practical streaming ceiling beside the 8 TB/s "
+                         "peak)")
     ap.add_argument("--flags", type=int, default=0,
                     help="extra LNE_FLAG_* bits for the timed step (default 0: the paper's "
                          "method; 4 = sparse-sign test matrix, 2 = vanilla randomized SVD)")
@@ -356,6 +358,9 @@ def main():
         return
     if args.report == "ablation":
         ablation_report(args.workload if args.workload != "large" else "batched")
+        return
+    if args.report == "hbm":
+        hbm_report()
         return
     if args.report == "host":
         host_report(args.workload)
@@ -832,6 +837,37 @@ def precision_report(name):
 
 
 MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6, "bf16": 2500.0}   # FP32 data runs on FP64 MFMA
+
+
+def hbm_report():
+    """Practical streaming rates of this GPU's HBM: torch's device copy (read
+    + write), fill (write) and sum (read) of 4 GiB, best of five HIP-event
+    timed runs each.  Context for the roofline fractions, which divide by the
+    published 8 TB/s."""
+    import torch
+
+    n = 1 << 30   # float32 elements: 4 GiB
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    a.uniform_()
+    b = torch.empty_like(a)
+    out = {"report": "hbm", "bytes": 4 * n, "peak_GBps": HBM_PEAK_GBS, "cases": []}
+    for name, fn, nbytes in (("copy (read + write)", lambda: b.copy_(a), 8 * n),
+                             ("fill (write)", lambda: b.fill_(1.0), 4 * n),
+                             ("sum (read)", lambda: a.sum(), 4 * n)):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        gbps = nbytes / (best * 1e-3) / 1e9
+        out["cases"].append({"op": name, "ms": best, "GBps": gbps, "of_peak": gbps / HBM_PEAK_GBS})
+        log(f"hbm {name}: {best:.3f} ms, {gbps:.0f} GB/s")
+    print(json.dumps(out), flush=True)
 
 
 def mfma_ceiling():
