@@ -631,11 +631,64 @@ __global__ void k_sym_merge(const int64_t *__restrict__ rpU, const int32_t *__re
     const int lane = threadIdx.x & 63;
     if (a >= n_rows) return;
     const int64_t u0 = rpU[a], u1 = rpU[a + 1];
-    const bool diag = u1 > u0 && colU[u0] == (int32_t)a;
-    const int64_t l0 = rpL[a], l1 = rpL[a + 1] - (diag ? 1 : 0);
+    const int64_t l0 = rpL[a], l1r = rpL[a + 1];
     const int64_t o = (int64_t)rpF[a];
     // four entries per lane and step, their loads issued before any store
     constexpr int Q = 4;
+    if (l1r - l0 <= 64 * Q && u1 - u0 <= 64 * Q) {
+        // a short row (the usual case): both parts' loads go out together
+        // (clamped to the part, so that none is predicated), then the diagonal
+        // test reads U's first column from them, then every store
+        uint64_t kq[Q];
+        uint32_t vq[Q];
+        int32_t cq[Q];
+        VT wq[Q];
+        if (l1r > l0) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t j = min(l0 + q * 64 + lane, l1r - 1);
+                kq[q] = keyL[j];
+                vq[q] = valL[j];
+            }
+        }
+        if (u1 > u0) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t j = min(u0 + q * 64 + lane, u1 - 1);
+                cq[q] = colU[j];
+                wq[q] = valU[j];
+            }
+        }
+        // keep the loads above every store (the compiler would otherwise sink
+        // each part's loads to the stores that use them)
+        __asm__ volatile("" ::: "memory");
+        const bool diag = u1 > u0 && __builtin_amdgcn_readfirstlane(cq[0]) == (int32_t)a;
+        const int64_t l1 = l1r - (diag ? 1 : 0);
+        if (l1r > l0) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t j = l0 + q * 64 + lane;
+                if (j < l1) {
+                    colF[o + (j - l0)] = (int32_t)(kq[q] & colmask);
+                    valF[o + (j - l0)] = (VT)__uint_as_float(vq[q]);
+                }
+            }
+        }
+        if (u1 > u0) {
+            const int64_t o2 = o + (l1 - l0);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t j = u0 + q * 64 + lane;
+                if (j < u1) {
+                    colF[o2 + (j - u0)] = cq[q];
+                    valF[o2 + (j - u0)] = wq[q];
+                }
+            }
+        }
+        return;
+    }
+    const bool diag = u1 > u0 && colU[u0] == (int32_t)a;
+    const int64_t l1 = l1r - (diag ? 1 : 0);
     for (int64_t j0 = l0; j0 < l1; j0 += 64 * Q) {
         uint64_t kq[Q];
         uint32_t vq[Q];
