@@ -505,29 +505,116 @@ k_sample_emit(SamplePlan pl, const int64_t *__restrict__ rp, const int32_t *__re
             }
         }
     } else {
-        for (int64_t jj = 0; jj < pl.J; ++jj) {
-            const uint64_t j = j0 + (uint64_t)jj;
-            bool ina = false, inb = false;
-            int32_t a = u, b = v;
-            uint64_t ch = 0;
-            if (e < m && j < ne) {
-                const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
-                if (cn.all || (uint64_t)b0.x < cn.tau) {
-                    if (draw_r(pl, b0.y) == 1) {
-                        ++c1;
-                    } else {
-                        double h;
-                        const int r = walk_pair<W>(pl, rp, col, e, (uint32_t)j, b0, u, v, a, b,
-                                                   &h);
-                        // the count pass bounded this below 2^32
-                        w = (uint32_t)sample_weight(h, cn.all, cn.p);
-                        ina = a >= row_lo && a < row_hi;
-                        inb = b >= row_lo && b < row_hi;
-                        ch = pl.cbits ? (uint64_t)(r - 1) : 0;
+        // the weighted walk, kWalkQ slots at a time as above: each level of a
+        // step's dependent loads (row bounds, cumulative weights at them, the
+        // guide entry, the arc's weight and column) is requested for every
+        // slot before the next level; each slot keeps its own path factor
+        const double inv0 = e < m ? 1.0 / (double)pl.ea[e] : 1.0;
+        for (int64_t jj = 0; jj < pl.J; jj += kWalkQ) {
+            int32_t x[kWalkQ], y[kWalkQ];
+            int r[kWalkQ], split[kWalkQ], steps[kWalkQ], left[kWalkQ];
+            uint4 buf[kWalkQ];
+            uint32_t blk[kWalkQ];
+            double inv[kWalkQ];
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) {
+                x[q] = u; y[q] = v; r[q] = 1; split[q] = 0; steps[q] = 0; left[q] = 1;
+                buf[q] = make_uint4(0, 0, 0, 0); blk[q] = 0; inv[q] = inv0;
+            }
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) {
+                const uint64_t j = j0 + (uint64_t)(jj + q);
+                if (e < m && jj + q < pl.J && j < ne) {
+                    const uint4 b0 = slot_block(pl, e, (uint32_t)j, 0);
+                    if (cn.all || (uint64_t)b0.x < cn.tau) {
+                        r[q] = draw_r(pl, b0.y);
+                        if (r[q] == 1) {
+                            ++c1;
+                        } else {
+                            split[q] = (int)(b0.z % (uint32_t)r[q]);
+                            steps[q] = r[q] - 1;
+                            buf[q] = make_uint4(b0.w, 0, 0, 0);
+                        }
                     }
                 }
             }
-            put(ina, inb, a, b, ch, w);
+            int nsteps = 0;
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) nsteps = max(nsteps, steps[q]);
+            for (int i = 0; i < nsteps; ++i) {
+                int32_t cur[kWalkQ];
+                uint32_t z[kWalkQ];
+                bool act[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    act[q] = i < steps[q];
+                    if (act[q] && left[q] == 0) {
+                        buf[q] = slot_block(pl, e, (uint32_t)(j0 + (uint64_t)(jj + q)), ++blk[q]);
+                        left[q] = 4;
+                    }
+                    z[q] = buf[q].x;
+                    if (act[q]) {
+                        buf[q] = make_uint4(buf[q].y, buf[q].z, buf[q].w, 0);
+                        --left[q];
+                    }
+                    cur[q] = act[q] ? (i < split[q] ? x[q] : y[q]) : u;
+                }
+                int64_t beg[kWalkQ], end[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) { beg[q] = rp[cur[q]]; end[q] = rp[cur[q] + 1]; }
+                uint64_t base[kWalkQ], top[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) { base[q] = pl.cw[beg[q]]; top[q] = pl.cw[end[q]]; }
+                // the arc k of the row with cw[k] <= t < cw[k + 1]: from the
+                // guide entry of t's bucket forward (as in walk_step)
+                uint32_t deg[kWalkQ];
+                uint64_t tt[kWalkQ];
+                int64_t ai[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    deg[q] = (uint32_t)(top[q] - base[q]);   // < 2^32 (validated)
+                    const uint64_t k = (uint64_t)(end[q] - beg[q]);
+                    tt[q] = base[q] + (uint64_t)(deg[q] ? z[q] % deg[q] : 0u);
+                    const uint64_t bkt = deg[q] ? (tt[q] - base[q]) * k / deg[q] : 0;
+                    ai[q] = deg[q] ? beg[q] + (int64_t)min((uint64_t)pl.guide[beg[q] + (int64_t)bkt],
+                                                           k - 1)
+                                   : beg[q];
+                }
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q)
+                    if (act[q] && deg[q])
+                        while (ai[q] < end[q] - 1 && pl.cw[ai[q] + 1] <= tt[q]) ++ai[q];
+                uint32_t wa[kWalkQ];
+                int32_t nb[kWalkQ];
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    const int64_t at = min(ai[q], 2 * m - 1);
+                    wa[q] = pl.wt[at];
+                    nb[q] = col[at];
+                }
+#pragma unroll
+                for (int q = 0; q < kWalkQ; ++q) {
+                    if (act[q] && deg[q]) {
+                        inv[q] += 1.0 / (double)wa[q];
+                        if (i < split[q]) x[q] = nb[q];
+                        else y[q] = nb[q];
+                    }
+                    // a sink (asymmetric input) holds
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kWalkQ; ++q) {
+                if (jj + q >= pl.J) break;                              // uniform
+                const bool walked = steps[q] > 0;
+                const bool ina = walked && x[q] >= row_lo && x[q] < row_hi;
+                const bool inb = walked && y[q] >= row_lo && y[q] < row_hi;
+                const uint64_t ch = pl.cbits && walked ? (uint64_t)(r[q] - 1) : 0;
+                // the path factor r / sum 1/A; the count pass bounded the
+                // weight below 2^32
+                const uint32_t wq =
+                    walked ? (uint32_t)sample_weight((double)r[q] / inv[q], cn.all, cn.p) : w;
+                put(ina, inb, walked ? x[q] : u, walked ? y[q] : v, ch, wq);
+            }
         }
     }
     // the merged length-1 samples: ceil(c1 / g) entries of up to g samples
